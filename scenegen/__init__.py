@@ -1,0 +1,343 @@
+"""Seeded synthetic workloads for the triangulation ray walk.
+
+This module only *produces inputs*: scenes of non-crossing line segments inside a bounding square,
+their constrained Delaunay triangulation (plus an optional flip-annealed low-weight variant) and
+rays with a known start triangle. It serves both the checker under ``oracle/`` and the walk
+library, and contains none of the walk's arithmetic. The heavy lifting is C++ in ``csrc/``
+(``libscenegen.so``, built by :func:`build`).
+
+Workloads (paper: the "lines" scenes of Sec. 4.3 and the ray experiment of Sec. 5.4):
+
+* ``tiny``   unit square + 64 segments, lengths U[0.02, 0.1]; 65,536 rays.
+* ``grid``   256 x 256 lattice of unit segments trimmed to [0.1, 0.9], rotated 30 degrees about the
+             centre; CDT and a flip-annealed triangulation; 2^22 rays.
+* ``large``  10^6 segments, midpoints U[0,1000]^2, lengths log-U[0.01, 1]; box [-1,1001]^2; 2^26 rays.
+* ``batch``  256 scenes as ``large`` with log-U[100, 10^5] segments and log-U[1024, 2^20] rays.
+* ``serve``  64 resident scenes with log-U[10^3, 5*10^5] segments.
+
+Conventions: vertices 0..3 are the box corners (counter-clockwise from the lower left); segment k
+joins vertices 4+2k and 5+2k and is primitive k; the box sides bottom, right, top, left are
+primitives S..S+3. Triangle arrays follow the walk library's descriptor: ``tri_v[t, i]`` counter-
+clockwise, edge i opposite vertex i, ``tri_nbr[t, i]`` the triangle across edge i (-1 on the hull)
+and ``tri_prim[t, i]`` the primitive of a constrained edge (-1 otherwise).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libscenegen.so")
+_lib = None
+
+
+def build() -> str:
+    """Compile libscenegen.so with g++ (host code only)."""
+    src = os.path.join(_HERE, "csrc", "scenegen.cpp")
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+           "-o", _LIB_PATH + ".tmp", src]
+    subprocess.check_call(cmd)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: run __graft_entry__.build() first")
+        lib = ctypes.CDLL(_LIB_PATH)
+        P, I64, U64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double
+        lib.sg_last_error.restype = ctypes.c_char_p
+        lib.sg_random_segments.argtypes = [U64, I64, D, D, D, D, ctypes.c_int, D, D, P, I64]
+        lib.sg_random_segments.restype = I64
+        lib.sg_build_cdt.argtypes = [P, I64, P, P, I64, I32]
+        lib.sg_build_cdt.restype = P
+        lib.sg_mesh_from_arrays.argtypes = [P, I64, I64, P, P, P]
+        lib.sg_mesh_from_arrays.restype = P
+        lib.sg_mesh_ntri.argtypes = [P]
+        lib.sg_mesh_ntri.restype = I64
+        lib.sg_mesh_copy.argtypes = [P, P, P, P]
+        lib.sg_mesh_weight.argtypes = [P]
+        lib.sg_mesh_weight.restype = D
+        lib.sg_mesh_anneal.argtypes = [P, U64, I64, D, D, P]
+        lib.sg_mesh_anneal.restype = ctypes.c_int
+        lib.sg_mesh_greedy.argtypes = [P]
+        lib.sg_mesh_locate.argtypes = [P, I64, P, P]
+        lib.sg_mesh_locate.restype = ctypes.c_int
+        lib.sg_mesh_free.argtypes = [P]
+        lib.sg_sample_rays.argtypes = [P, I64, P, U64, I64, P, P, P, ctypes.c_int]
+        lib.sg_orient_batch.argtypes = [I64, P, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _err(msg):
+    raise RuntimeError(f"{msg}: {_L().sg_last_error().decode()}")
+
+
+# Per-purpose seed tags: every draw stream is derived from (seed, tag), so the scene, the rays
+# and any later stream of the same workload never share random numbers.
+TAG_SCENE, TAG_RAYS, TAG_ANNEAL, TAG_CHOICE = 1, 2, 3, 4
+
+
+def subseed(seed: int, tag: int, index: int = 0) -> int:
+    return (int(seed) * 1_000_003 + tag * 7919 + index * 104_729) & ((1 << 64) - 1)
+
+
+@dataclass
+class Scene:
+    """A scene and its triangulation (all host numpy arrays)."""
+
+    xy: np.ndarray          # (V,2) float64
+    prims: np.ndarray       # (P,4) float64: ax, ay, bx, by
+    seg_v: np.ndarray       # (S,2) int32 vertex ids of segment k (primitive k)
+    box: tuple              # (lo, hi) of the bounding square
+    tri_v: np.ndarray = None
+    tri_nbr: np.ndarray = None
+    tri_prim: np.ndarray = None
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_vertices(self):
+        return int(self.xy.shape[0])
+
+    @property
+    def n_triangles(self):
+        return int(self.tri_v.shape[0])
+
+    @property
+    def n_prims(self):
+        return int(self.prims.shape[0])
+
+    def copy_with(self, tri_v, tri_nbr, tri_prim, name=None):
+        return Scene(self.xy, self.prims, self.seg_v, self.box, tri_v, tri_nbr, tri_prim,
+                     name or self.name, dict(self.meta))
+
+
+def scene_from_segments(seg: np.ndarray, lo: float, hi: float, name: str = "") -> Scene:
+    """Vertices, primitives and segment ids for segments seg (S,4) inside the square [lo,hi]^2."""
+    seg = np.ascontiguousarray(seg, dtype=np.float64).reshape(-1, 4)
+    S = seg.shape[0]
+    corners = np.array([[lo, lo], [hi, lo], [hi, hi], [lo, hi]], dtype=np.float64)
+    xy = np.concatenate([corners, seg.reshape(-1, 2)], axis=0)
+    seg_v = (4 + np.arange(2 * S, dtype=np.int32)).reshape(S, 2)
+    sides = np.array([[lo, lo, hi, lo], [hi, lo, hi, hi], [hi, hi, lo, hi], [lo, hi, lo, lo]],
+                     dtype=np.float64)
+    prims = np.concatenate([seg, sides], axis=0)
+    return Scene(np.ascontiguousarray(xy), np.ascontiguousarray(prims), seg_v, (lo, hi), name=name)
+
+
+def random_segments(seed, n, mid_lo, mid_hi, len_lo, len_hi, log_len, box_lo, box_hi,
+                    max_draws=None) -> np.ndarray:
+    out = np.empty((n, 4), dtype=np.float64)
+    max_draws = max_draws or max(1000, 100 * n)
+    m = _L().sg_random_segments(int(seed) & ((1 << 64) - 1), n, mid_lo, mid_hi, len_lo, len_hi,
+                                int(log_len), box_lo, box_hi, _ptr(out), max_draws)
+    if m < 0:
+        _err("segment sampling failed")
+    if m < n:
+        raise RuntimeError(f"segment sampling placed only {m} of {n} segments")
+    return out
+
+
+def triangulate(sc: Scene) -> Scene:
+    """Constrained Delaunay triangulation of the scene (fills tri_v / tri_nbr / tri_prim)."""
+    L = _L()
+    S = sc.seg_v.shape[0]
+    segp = np.arange(S, dtype=np.int32)
+    h = L.sg_build_cdt(_ptr(sc.xy), sc.xy.shape[0], _ptr(sc.seg_v), _ptr(segp), S, S)
+    if not h:
+        _err("triangulation failed")
+    try:
+        T = L.sg_mesh_ntri(h)
+        tv = np.empty((T, 3), np.int32)
+        tn = np.empty((T, 3), np.int32)
+        tp = np.empty((T, 3), np.int32)
+        L.sg_mesh_copy(h, _ptr(tv), _ptr(tn), _ptr(tp))
+    finally:
+        L.sg_mesh_free(h)
+    sc.tri_v, sc.tri_nbr, sc.tri_prim = tv, tn, tp
+    return sc
+
+
+def _mesh(sc: Scene):
+    return _L().sg_mesh_from_arrays(_ptr(sc.xy), sc.xy.shape[0], sc.n_triangles, _ptr(sc.tri_v),
+                                    _ptr(sc.tri_nbr), _ptr(sc.tri_prim))
+
+
+def weight(sc: Scene) -> float:
+    """Total edge length of the triangulation (the paper's weight)."""
+    h = _mesh(sc)
+    try:
+        return float(_L().sg_mesh_weight(h))
+    finally:
+        _L().sg_mesh_free(h)
+
+
+def anneal_flips(sc: Scene, seed: int, moves_per_edge: float = 6.0, t0_rel: float = 0.02,
+                 t1_rel: float = 1e-4) -> tuple:
+    """Flip-only simulated annealing of the triangulation, then greedy flips.
+
+    Temperatures are relative to the box side (the paper normalises scenes to the unit square).
+    Returns (annealed Scene, stats dict). If annealing ends heavier than greedy flipping of the
+    input alone, the greedy result is returned instead, so the weight never exceeds the input's.
+    """
+    L = _L()
+    side = sc.box[1] - sc.box[0]
+    n_edges = (3 * sc.n_triangles) // 2
+    n_moves = int(moves_per_edge * n_edges)
+    out = np.zeros(5, np.float64)
+    h = _mesh(sc)
+    try:
+        if L.sg_mesh_anneal(h, subseed(seed, TAG_ANNEAL), n_moves, t0_rel * side, t1_rel * side,
+                            _ptr(out)) != 0:
+            _err("annealing failed")
+        T = L.sg_mesh_ntri(h)
+        tv, tn, tp = (np.empty((T, 3), np.int32) for _ in range(3))
+        L.sg_mesh_copy(h, _ptr(tv), _ptr(tn), _ptr(tp))
+    finally:
+        L.sg_mesh_free(h)
+    stats = dict(w_start=out[0], w_end=out[1], proposals=out[2], accepted=out[3], flips=out[4])
+    res = sc.copy_with(tv, tn, tp, name=sc.name + "/annealed")
+    h = _mesh(sc)
+    try:
+        L.sg_mesh_greedy(h)
+        w_greedy = float(L.sg_mesh_weight(h))
+        if w_greedy < stats["w_end"]:
+            T = L.sg_mesh_ntri(h)
+            tv, tn, tp = (np.empty((T, 3), np.int32) for _ in range(3))
+            L.sg_mesh_copy(h, _ptr(tv), _ptr(tn), _ptr(tp))
+            res = sc.copy_with(tv, tn, tp, name=sc.name + "/greedy")
+            stats["w_end"] = w_greedy
+            stats["fallback"] = "greedy"
+    finally:
+        L.sg_mesh_free(h)
+    return res, stats
+
+
+def locate(sc: Scene, pts: np.ndarray) -> np.ndarray:
+    """Triangle strictly containing each point, -1 if on an edge, vertex or outside."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    out = np.empty(pts.shape[0], np.int32)
+    h = _mesh(sc)
+    try:
+        if _L().sg_mesh_locate(h, pts.shape[0], _ptr(pts), _ptr(out)) != 0:
+            _err("point location failed")
+    finally:
+        _L().sg_mesh_free(h)
+    return out
+
+
+@dataclass
+class Rays:
+    o: np.ndarray       # (N,2) float64 origins
+    d: np.ndarray       # (N,2) float64 directions (cos, sin), not renormalised
+    start: np.ndarray   # (N,) int32 start triangle (origin strictly inside)
+
+    @property
+    def n(self):
+        return int(self.start.shape[0])
+
+    def slice(self, a, b):
+        return Rays(self.o[a:b], self.d[a:b], self.start[a:b])
+
+    def take(self, idx):
+        return Rays(np.ascontiguousarray(self.o[idx]), np.ascontiguousarray(self.d[idx]),
+                    np.ascontiguousarray(self.start[idx]))
+
+
+def sample_rays(sc: Scene, n: int, seed: int, threads: int = 0) -> Rays:
+    """Area-weighted start triangle, origin uniform inside it (strictly), angle U[0, 2pi)."""
+    o = np.empty((n, 2), np.float64)
+    d = np.empty((n, 2), np.float64)
+    st = np.empty(n, np.int32)
+    _L().sg_sample_rays(_ptr(sc.xy), sc.n_triangles, _ptr(sc.tri_v), subseed(seed, TAG_RAYS), n,
+                        _ptr(o), _ptr(d), _ptr(st), int(threads))
+    return Rays(o, d, st)
+
+
+def exact_orient(abc: np.ndarray) -> np.ndarray:
+    abc = np.ascontiguousarray(abc, dtype=np.float64).reshape(-1, 6)
+    out = np.empty(abc.shape[0], np.int32)
+    _L().sg_orient_batch(abc.shape[0], _ptr(abc), _ptr(out))
+    return out
+
+
+# ----------------------------------------------------------------------------- workloads
+def _rot30(p, c):
+    cs, sn = math.cos(math.radians(30.0)), math.sin(math.radians(30.0))
+    x, y = p[..., 0] - c, p[..., 1] - c
+    return np.stack([c + cs * x - sn * y, c + sn * x + cs * y], axis=-1)
+
+
+def grid_segments(n: int = 256, trim: float = 0.1) -> tuple:
+    """Unit segments between 4-neighbours of the n x n lattice, trimmed to [trim, 1-trim] of
+    their span and rotated 30 degrees about the lattice centre. Horizontal segments first (row
+    by row), then vertical ones (column by column). Returns (segments (S,4), box lo, box hi)."""
+    i = np.arange(n - 1, dtype=np.float64)
+    j = np.arange(n, dtype=np.float64)
+    J, I = np.meshgrid(j, i, indexing="ij")           # horizontal: row j, column i
+    h = np.stack([I + trim, J, I + 1 - trim, J], axis=-1).reshape(-1, 4)
+    I2, J2 = np.meshgrid(j, i, indexing="ij")          # vertical: column I2, row J2
+    v = np.stack([I2, J2 + trim, I2, J2 + 1 - trim], axis=-1).reshape(-1, 4)
+    seg = np.concatenate([h, v], axis=0)
+    c = (n - 1) / 2.0
+    a = _rot30(seg[:, 0:2], c)
+    b = _rot30(seg[:, 2:4], c)
+    seg = np.concatenate([a, b], axis=1)
+    half = 0.5 * (n - 1) * (math.cos(math.radians(30)) + math.sin(math.radians(30))) + 1.0
+    return np.ascontiguousarray(seg), c - half, c + half
+
+
+WORKLOADS = {
+    "tiny": dict(kind="random", n_seg=64, mid=(0.0, 1.0), length=(0.02, 0.1), log_len=False,
+                 box=(0.0, 1.0), rays=65536),
+    "grid": dict(kind="grid", n=256, rays=1 << 22),
+    "large": dict(kind="random", n_seg=1_000_000, mid=(0.0, 1000.0), length=(0.01, 1.0),
+                  log_len=True, box=(-1.0, 1001.0), rays=1 << 26),
+    "batch": dict(kind="multi", n_scenes=256, n_seg=(100, 100_000), rays=(1024, 1 << 20),
+                  mid=(0.0, 1000.0), length=(0.01, 1.0), box=(-1.0, 1001.0)),
+    "serve": dict(kind="multi", n_scenes=64, n_seg=(1000, 500_000), rays=(256, 262_144),
+                  mid=(0.0, 1000.0), length=(0.01, 1.0), box=(-1.0, 1001.0)),
+}
+
+
+def log_uniform_int(u: np.ndarray, lo: float, hi: float) -> np.ndarray:
+    """round(exp(U[ln lo, ln hi])) for uniforms u in [0,1)."""
+    return np.rint(np.exp(math.log(lo) + (math.log(hi) - math.log(lo)) * u)).astype(np.int64)
+
+
+def make_scene(name: str, seed: int = 0, n_seg: int | None = None, index: int = 0) -> Scene:
+    """Build the scene of a workload (without rays) and its CDT."""
+    w = WORKLOADS[name]
+    if w["kind"] == "grid":
+        seg, lo, hi = grid_segments(w["n"])
+        sc = scene_from_segments(seg, lo, hi, name=name)
+    else:
+        n = int(n_seg if n_seg is not None else w["n_seg"])
+        seg = random_segments(subseed(seed, TAG_SCENE, index), n, w["mid"][0], w["mid"][1],
+                              w["length"][0], w["length"][1], w.get("log_len", True),
+                              w["box"][0], w["box"][1])
+        sc = scene_from_segments(seg, w["box"][0], w["box"][1], name=f"{name}[{index}]")
+    return triangulate(sc)
+
+
+def multi_sizes(name: str, seed: int = 0) -> tuple:
+    """Segment and ray counts of the scenes of a multi-scene workload (log-uniform draws)."""
+    w = WORKLOADS[name]
+    rng = np.random.default_rng(np.random.SeedSequence([seed, TAG_CHOICE]))
+    u = rng.random((w["n_scenes"], 2))
+    segs = log_uniform_int(u[:, 0], *w["n_seg"])
+    rays = log_uniform_int(u[:, 1], *w["rays"])
+    return segs, rays

@@ -1,0 +1,248 @@
+"""Pins for the checker's walk (paper Sec. 5.1) against things other than itself.
+
+* a hand-derived closed-form fixture (unit square split by its diagonal);
+* the textbook distance to a square and the diagonal test on random rays;
+* brute force over every edge and over every primitive (the definition of the result), on the
+  whole tiny workload and on scenes built to hit every degenerate case exactly: rays through
+  vertices, along edges and through box corners;
+* Cauchy-Crofton: the mean number of interior edges crossed by isotropic lines equals
+  2 * (interior edge length) / (box perimeter) (the weight/cost relation of Sec. 1.4);
+* invariance of hit and distance across two triangulations of one scene.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+import scenegen as sg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tri(sc):
+    return oracle.Triangulation.of(sc)
+
+
+def test_golden_unit_square():
+    g = json.load(open(os.path.join(GOLDEN, "unit_square_diagonal.json")))
+    tri = oracle.Triangulation(g["xy"], g["tri_v"], g["tri_nbr"], g["tri_prim"], g["prims"])
+    assert oracle.validate(tri, delaunay=True) == ""
+    o = np.array([r["o"] for r in g["rays"]], float)
+    d = np.array([r["d"] for r in g["rays"]], float)
+    s = np.array([r["start"] for r in g["rays"]], np.int32)
+    prim, t, steps = oracle.walk(tri, o, d, s)
+    assert prim.tolist() == [r["prim"] for r in g["rays"]]
+    assert t.tolist() == [r["t"] for r in g["rays"]]
+    assert steps.tolist() == [r["steps"] for r in g["rays"]]
+
+
+def _square():
+    g = json.load(open(os.path.join(GOLDEN, "unit_square_diagonal.json")))
+    return g, oracle.Triangulation(g["xy"], g["tri_v"], g["tri_nbr"], g["tri_prim"], g["prims"])
+
+
+def test_square_closed_form_random_rays():
+    g, tri = _square()
+    rng = np.random.default_rng(5)
+    n = 20000
+    o = rng.uniform(0, 1, (n, 2))
+    o = o[o[:, 0] != o[:, 1]]
+    th = rng.uniform(0, 2 * np.pi, o.shape[0])
+    d = np.stack([np.cos(th), np.sin(th)], 1)
+    start = (o[:, 1] > o[:, 0]).astype(np.int32)  # above the diagonal: triangle 1
+    prim, t, steps = oracle.walk(tri, o, d, start)
+    # textbook: distance to each side along d, the smallest positive one wins
+    with np.errstate(divide="ignore"):
+        tx = np.where(d[:, 0] > 0, (1 - o[:, 0]) / d[:, 0], -o[:, 0] / d[:, 0])
+        ty = np.where(d[:, 1] > 0, (1 - o[:, 1]) / d[:, 1], -o[:, 1] / d[:, 1])
+    side = np.where(tx < ty, np.where(d[:, 0] > 0, 1, 3), np.where(d[:, 1] > 0, 2, 0))
+    tt = np.minimum(tx, ty)
+    assert (prim == side).all()
+    np.testing.assert_allclose(t, tt, rtol=1e-13)
+    # the exit point lies on the other triangle's sides iff the diagonal was crossed
+    x = o + tt[:, None] * d
+    other = np.where(start == 0, x[:, 1] > x[:, 0], x[:, 1] < x[:, 0])
+    assert (steps == 1 + other).all()
+
+
+def test_tiny_walk_equals_brute_force(tiny_scene, tiny_rays):
+    tri = _tri(tiny_scene)
+    r = tiny_rays
+    p, t, s = oracle.walk(tri, r.o, r.d, r.start)
+    assert (p >= 0).all() and (s >= 1).all()
+    pb, tb, sb, status = oracle.brute_edges(tri, r.o, r.d)
+    assert status == 0
+    assert (p == pb).all() and (s == sb).all()
+    assert np.array_equal(t, tb)
+    pp, tp, status = oracle.brute_prims(tiny_scene.prims, r.o, r.d)
+    assert status == 0 and (pp == p).all() and np.array_equal(tp, t)
+
+
+def _integer_scene(rng, n_seg, size=16):
+    segs = []
+    while len(segs) < n_seg:
+        a = rng.integers(1, size, 2)
+        b = a + rng.integers(-3, 4, 2)
+        if (b <= 0).any() or (b >= size).any() or (a == b).all():
+            continue
+        s = np.concatenate([a, b]).astype(float)
+        if all(not _touch(s, q) for q in segs):
+            segs.append(s)
+    return sg.triangulate(sg.scene_from_segments(np.array(segs), 0.0, float(size)))
+
+
+def _touch(s, q):
+    # integer data: exact signs in binary64
+    def o(a, b, c):
+        return np.sign((b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]))
+    A, B, C, D = s[:2], s[2:], q[:2], q[2:]
+    o1, o2, o3, o4 = o(A, B, C), o(A, B, D), o(C, D, A), o(C, D, B)
+    if o1 * o2 > 0 or o3 * o4 > 0:
+        return False
+    if o1 == 0 and o2 == 0:
+        k = 0 if abs(B[0] - A[0]) >= abs(B[1] - A[1]) else 1
+        return not (max(A[k], B[k]) < min(C[k], D[k]) or max(C[k], D[k]) < min(A[k], B[k]))
+    return True
+
+
+def _degenerate_rays(sc, rng, n):
+    """Dyadic origins strictly inside a triangle, aimed exactly at vertices, along edge lines
+    and at the box corners."""
+    V = sc.xy
+    o_list, d_list = [], []
+    T = sc.n_triangles
+    while len(o_list) < n:
+        kind = rng.integers(0, 3)
+        if kind == 2:  # along the line of an edge, from outside the edge
+            t = rng.integers(0, T)
+            i = rng.integers(0, 3)
+            p, q = V[sc.tri_v[t, (i + 1) % 3]], V[sc.tri_v[t, (i + 2) % 3]]
+            lam = rng.choice([-0.5, -0.25, 1.25, 1.5, 2.0])
+            o = p + lam * (q - p)
+            d = (q - p) * rng.choice([-1.0, 1.0])
+        else:
+            o = rng.integers(0, 64, 2) / 4.0 + 0.125
+            tgt = V[rng.integers(0, 4)] if kind == 1 else V[rng.integers(0, V.shape[0])]
+            d = tgt - o
+        if (d == 0).all():
+            continue
+        o_list.append(o)
+        d_list.append(d)
+    o = np.array(o_list)
+    d = np.array(d_list)
+    start = sg.locate(sc, o)
+    keep = start >= 0
+    return o[keep], d[keep], start[keep]
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(0, 2**31 - 1))
+def test_degenerate_rays_walk_equals_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    sc = _integer_scene(rng, int(rng.integers(3, 14)))
+    tri = _tri(sc)
+    assert oracle.validate(tri, delaunay=True) == ""
+    o, d, start = _degenerate_rays(sc, rng, 200)
+    assert o.shape[0] > 20
+    # the cases are really degenerate: some vertex lies exactly on many rays
+    zero = sum(oracle.side_sign(o[k], d[k], v) == 0 for k in range(10) for v in sc.xy)
+    assert zero >= 10
+    p, t, s = oracle.walk(tri, o, d, start)
+    assert (p >= 0).all()
+    pb, tb, sb, status = oracle.brute_edges(tri, o, d)
+    assert status == 0
+    assert (p == pb).all() and (s == sb).all() and np.array_equal(t, tb)
+    pp, tp, status = oracle.brute_prims(sc.prims, o, d)
+    assert (pp == p).all() and np.array_equal(tp, t)
+
+
+def _crofton_lines(lo, hi, n, rng):
+    """Lines from the motion-invariant measure that hit the box, and a point uniform on each
+    chord. Returns (origin, direction, chord length)."""
+    c = 0.5 * (lo + hi)
+    R = (hi - lo) * math.sqrt(0.5)
+    o_all, d_all, L_all = [], [], []
+    while sum(x.shape[0] for x in o_all) < n:
+        m = 2 * n
+        th = rng.uniform(0, np.pi, m)
+        p = rng.uniform(-R, R, m)
+        d = np.stack([np.cos(th), np.sin(th)], 1)
+        nrm = np.stack([-np.sin(th), np.cos(th)], 1)
+        foot = c + p[:, None] * nrm
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t1 = (lo - foot) / d
+            t2 = (hi - foot) / d
+        tmin = np.nanmax(np.minimum(t1, t2), axis=1)
+        tmax = np.nanmin(np.maximum(t1, t2), axis=1)
+        ok = tmax > tmin
+        u = rng.uniform(0, 1, m)
+        s = tmin + u * (tmax - tmin)
+        o = foot + s[:, None] * d
+        o_all.append(o[ok])
+        d_all.append(d[ok])
+        L_all.append((tmax - tmin)[ok])
+    return (np.concatenate(o_all)[:n], np.concatenate(d_all)[:n], np.concatenate(L_all)[:n])
+
+
+def _crofton_check(sc, n_lines, seed):
+    rng = np.random.default_rng(seed)
+    lo, hi = sc.box
+    # interior constraints removed: a ray then crosses the whole chord; box sides stay primitives
+    hull = sc.tri_nbr < 0
+    prim = np.where(hull, sc.tri_prim, -1).astype(np.int32)
+    tri = oracle.Triangulation(sc.xy, sc.tri_v, sc.tri_nbr, prim, sc.prims)
+    o, d, chord = _crofton_lines(lo, hi, n_lines, rng)
+    start = sg.locate(sc, o)
+    keep = start >= 0
+    o, d, chord, start = o[keep], d[keep], chord[keep], start[keep]
+    pf, tf, sf = oracle.walk(tri, o, d, start)
+    pbk, tbk, sbk = oracle.walk(tri, o, -d, start)
+    assert (pf >= 0).all() and (pbk >= 0).all()
+    ncross = (sf + sbk - 2).astype(np.float64)
+    # interior edge length
+    e = []
+    for i in range(3):
+        a = sc.xy[sc.tri_v[:, (i + 1) % 3]]
+        b = sc.xy[sc.tri_v[:, (i + 2) % 3]]
+        inner = (sc.tri_nbr[:, i] >= 0) & (sc.tri_nbr[:, i] > np.arange(sc.n_triangles))
+        e.append(np.hypot(*(b - a).T)[inner])
+    L_int = float(np.concatenate(e).sum())
+    expect = 2.0 * L_int / (4.0 * (hi - lo))
+    mean = ncross.mean()
+    se = ncross.std(ddof=1) / math.sqrt(ncross.size)
+    np.testing.assert_allclose(tf + tbk, chord, rtol=1e-12, atol=1e-13 * (hi - lo))
+    return mean, se, expect
+
+
+def test_crofton_unit_square():
+    g, _ = _square()
+    sc = sg.Scene(np.array(g["xy"], float), np.array(g["prims"], float), np.zeros((0, 2), np.int32),
+                  (0.0, 1.0), np.array(g["tri_v"], np.int32), np.array(g["tri_nbr"], np.int32),
+                  np.array(g["tri_prim"], np.int32))
+    mean, se, expect = _crofton_check(sc, 1 << 18, 11)
+    assert abs(expect - g["crofton_mean_interior_crossings"]) < 1e-15
+    assert abs(mean - expect) < 5 * se, (mean, se, expect)
+
+
+def test_crofton_tiny(tiny_scene):
+    mean, se, expect = _crofton_check(tiny_scene, 1 << 20, 12)
+    assert abs(mean - expect) < 5 * se, (mean, se, expect)
+    assert se < 0.01 * expect  # the statistic is sharp enough to catch a dropped edge class
+
+
+def test_invariance_cdt_vs_annealed(tiny_scene, tiny_rays):
+    an, stats = sg.anneal_flips(tiny_scene, seed=0)
+    assert stats["w_end"] <= stats["w_start"]
+    tri_a = _tri(an)
+    assert oracle.validate(tri_a) == ""
+    r = tiny_rays
+    start = sg.locate(an, r.o)
+    keep = start >= 0
+    p1, t1, s1 = oracle.walk(_tri(tiny_scene), r.o[keep], r.d[keep], r.start[keep])
+    p2, t2, s2 = oracle.walk(tri_a, r.o[keep], r.d[keep], start[keep])
+    assert (p1 == p2).all() and np.array_equal(t1, t2)
+    assert (s1 != s2).any()
