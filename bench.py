@@ -1,0 +1,178 @@
+"""Benchmark: stackless triangulation walk on one MI355X.
+
+Workload: the large clutter scene (10^6 non-crossing segments, midpoints U[0,1000]^2, lengths
+log-U[0.01, 1], box [-1,1001]^2, constrained Delaunay triangulation with 4,000,002 triangles) and
+2^26 isotropic rays with known start triangles, synthetic and seeded. One step = one trace of all
+rays (the whole walk: first triangle, steps, hit distance), inputs resident in HBM.
+
+Prints one JSON line: rays/s of the binary32-filtered walk (value), steps/s, the binary64 walk's
+rays/s on the same inputs, the roofline of the walk kernel (HIP events on its stream), and the
+checker's throughput on the host cores for a bounded sample of the same rays.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+BYTES_PER_STEP = 16          # opposite-vertex id + binary32 xy + exit word
+BYTES_PER_RAY = 100          # ray in (36) + result out (16) + first-triangle vertices + primitive
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large", choices=["large", "grid", "tiny"])
+    ap.add_argument("--rays", type=int, default=0, help="override the ray count")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the checker leg")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune", default="", help="wg,tile,waves_per_cu,refill_min")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the walk shards by "
+                                   "replicating the scene and splitting rays (see DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2112_05570_amd as ccsp
+    import scenegen as sg
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    sc = sg.make_scene(args.workload, seed=0)
+    n = args.rays or sg.WORKLOADS[args.workload]["rays"]
+    rays = sg.sample_rays(sc, n, seed=0)
+    log(f"[bench] {args.workload}: {sc.n_prims} prims, {sc.n_triangles} triangles, {n} rays "
+        f"built in {time.time() - t0:.1f}s")
+    o = torch.from_numpy(rays.o).to(dev)
+    d = torch.from_numpy(rays.d).to(dev)
+    st = torch.from_numpy(rays.start).to(dev)
+    scene = ccsp.Scene.from_arrays(sc)
+    tune = None
+    if args.tune:
+        tune = ccsp.TuneParams(*[int(x) for x in args.tune.split(",")])
+    out32 = ccsp.Result(torch.empty(n, dtype=torch.int32, device=dev),
+                        torch.empty(n, dtype=torch.float64, device=dev),
+                        torch.empty(n, dtype=torch.int32, device=dev))
+    out64 = ccsp.Result(torch.empty_like(out32.hit_prim), torch.empty_like(out32.hit_t),
+                        torch.empty_like(out32.steps))
+    stream = torch.cuda.current_stream()
+
+    def timed(prec, out, k, w):
+        for _ in range(w):
+            ccsp.trace(scene, o, d, st, precision=prec, out=out, tune=tune, stream=stream)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(k)]
+        t = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            ccsp.trace(scene, o, d, st, precision=prec, out=out, tune=tune, stream=stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        kern = [a.elapsed_time(b) / 1e3 for a, b in evs]
+        return wall, kern
+
+    wall32, k32 = timed("fp32", out32, args.steps, args.warmup)
+    log(f"[bench] fp32 walk: {args.steps} steps in {wall32:.3f}s")
+    wall64, k64 = timed("fp64", out64, max(1, args.steps // 2), 1)
+    log(f"[bench] fp64 walk: {len(k64)} steps in {wall64:.3f}s")
+
+    # diagnostics outside the timed region
+    steps_total = int(out32.steps.sum(dtype=torch.int64).item())
+    same = bool(torch.equal(out32.hit_prim, out64.hit_prim) and torch.equal(out32.steps, out64.steps)
+                and torch.equal(out32.hit_t, out64.hit_t))
+    ccsp.read_counters(reset=True)
+    ccsp.trace(scene, o, d, st, precision="fp32", out=out64, count=True, tune=tune)
+    c_steps, c_fb32, c_fb64, c_rays = ccsp.read_counters(reset=True)
+    hp = out32.hit_prim
+    n_bad = int((hp < 0).sum().item())
+
+    ms = wall32 / args.steps * 1e3
+    rays_s = n * args.steps / wall32
+    kern_avg = float(np.mean(k32))
+    alg_bytes = BYTES_PER_STEP * steps_total + BYTES_PER_RAY * n
+    achieved = alg_bytes / kern_avg / 1e9
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_leg(sc, rays, args.cpu_seconds)
+
+    line = {
+        "metric": "rays/s and traversal steps/s on 1 MI355X (FP32+filter vs FP64); p99 latency",
+        "value": rays_s,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {sc.n_prims - 4} segments + 4 box sides, "
+                        f"{sc.n_triangles} CDT triangles, {n} isotropic rays, seed 0",
+            "rays": n, "triangles": sc.n_triangles, "primitives": sc.n_prims,
+            "precision": "fp32 filtered, fp64 exact fallback",
+        },
+        "steps_per_s": steps_total * args.steps / wall32,
+        "mean_steps_per_ray": steps_total / n,
+        "fp64": {"rays_per_s": n * len(k64) / wall64, "ms_per_step": wall64 / len(k64) * 1e3,
+                 "steps_per_s": steps_total * len(k64) / wall64},
+        "fp32_equals_fp64": same,
+        "fallback": {"fp32_to_fp64_per_step": c_fb32 / max(1, c_steps),
+                     "fp64_to_exact_per_step": c_fb64 / max(1, c_steps)},
+        "rays_not_hit": n_bad,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel_ms": kern_avg * 1e3,
+                     "bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    scene.free()
+
+
+def cpu_leg(sc, rays, budget_s):
+    """The checker's walk, as it stands, on the host cores: a bounded prefix of the same rays."""
+    import numpy as np
+
+    import oracle
+
+    tri = oracle.Triangulation.of(sc)
+    threads = oracle.num_threads()
+    m = 4096
+    t = time.perf_counter()
+    oracle.walk(tri, rays.o[:m], rays.d[:m], rays.start[:m], threads)
+    dt = max(time.perf_counter() - t, 1e-3)
+    m = int(min(rays.n, max(m, m * budget_s / dt)))
+    t = time.perf_counter()
+    _, _, s = oracle.walk(tri, rays.o[:m], rays.d[:m], rays.start[:m], threads)
+    dt = time.perf_counter() - t
+    log(f"[bench] checker walk: {m} rays on {threads} threads in {dt:.1f}s")
+    return {"value": m / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {m} of the same rays (exact integer-arithmetic checker walk, "
+                      f"OpenMP over rays)",
+            "steps_per_s": float(np.sum(s, dtype=np.int64)) / dt}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * ccsp_walk: stackless ray traversal of a 2D constrained triangulation on AMD Instinct MI355X.
+ *
+ * The operation (Frederickx & Dutre, arXiv 2112.05570, Sec. 5.1 "Ray Traversal", and the
+ * operation count of Sec. 5.4): a ray R(s) = o + s*d starts inside a known triangle. In each
+ * visited triangle one decision is taken: the edge the ray leaves through. If that edge is part
+ * of the scene geometry (a constrained edge) the walk stops with a hit; if no triangle lies across
+ * it the ray has left the triangulation (no hit); otherwise the walk continues in the neighbour.
+ * Per ray the library returns
+ *   hit_prim  the primitive id of the constrained edge hit (>= 0), or a status below 0,
+ *   hit_t     the hit parameter t with R(t) on the primitive, computed from the primitive's own
+ *             segment (a,b) as ((ax-ox)*ey - (ay-oy)*ex) / (dx*ey - dy*ex), e = b - a, in IEEE
+ *             binary64 in exactly this order without fused operations (so t does not depend on the
+ *             triangulation, nor on where a primitive is split into several edges),
+ *   steps     the number of triangles visited, start and hit triangle included (Sec. 5.4).
+ *
+ * Decisions are exact: vertex v is LEFT of the ray iff dx*(vy-oy) - dy*(vx-ox) >= 0 evaluated
+ * exactly on the binary64 inputs (zero counts as LEFT: the ray is shifted infinitesimally to its
+ * right, a consistent symbolic perturbation). Sec. 5.1 requires consistent decisions to avoid
+ * loops and missing exit edges; exactness makes hit_prim and steps independent of the precision
+ * mode. In TRACE_FP32_FILTERED mode the sign is first taken from single-precision coordinates
+ * and accepted only when a forward error bound proves it; otherwise the binary64 filter and, if
+ * needed, an exact expansion decide. Both modes give identical hit_prim, hit_t and steps.
+ *
+ * Conventions
+ *   Triangle t has counter-clockwise vertices tri_v[3t+0..2]; its edge i joins tri_v[3t+(i+1)%3]
+ *   and tri_v[3t+(i+2)%3] and lies opposite tri_v[3t+i]. tri_nbr[3t+i] is the triangle across
+ *   edge i (-1 on the hull). tri_prim[3t+i] is the primitive id of a constrained edge i, -1 for an
+ *   unconstrained one. A primitive may be split over several collinear constrained edges.
+ *
+ * Errors: every call returns CCSP_OK (0) or a negative code; last_error() then describes the
+ * failure (thread-local, valid until the next call on the same thread). Per-ray outcomes are
+ * data: hit_prim >= 0 hit; CCSP_RAY_MISS (-1) left through an unconstrained hull edge, hit_t=+inf;
+ * CCSP_RAY_GUARD (-2) more steps than triangles (impossible with exact decisions, kept as a
+ * guard); CCSP_RAY_BAD (-3) start_tri out of range or the origin is not strictly inside it (then
+ * steps = 0). A ray whose origin is not strictly inside start_tri is a precondition violation;
+ * without CCSP_TRACE_VALIDATE it may also end as a hit or miss along a wrong path, but never reads
+ * out of bounds.
+ *
+ * Streams: every stream argument is a hipStream_t (NULL = the default stream). Calls are
+ * asynchronous on that stream unless stated; results are valid once the stream has reached the
+ * point of the call. A loaded triangulation is read-only, so traces on different streams may run
+ * concurrently.
+ */
+#ifndef CCSP_WALK_H
+#define CCSP_WALK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CCSP_OK = 0,
+  CCSP_E_ARG = -1,               /* a null pointer, negative size, misaligned buffer, bad mode */
+  CCSP_E_BAD_TRIANGULATION = -2, /* the descriptor fails validation (see load_triangulation) */
+  CCSP_E_OOM = -3,               /* device or pinned host allocation failed */
+  CCSP_E_HIP = -4,               /* a HIP runtime call failed */
+  CCSP_E_BAD_RAY = -5            /* CCSP_TRACE_VALIDATE found a ray violating its precondition */
+};
+
+enum {
+  CCSP_RAY_MISS = -1,
+  CCSP_RAY_GUARD = -2,
+  CCSP_RAY_BAD = -3
+};
+
+/* precision: one mode, optionally OR-ed with flags */
+enum {
+  CCSP_TRACE_FP64 = 0,          /* binary64 coordinates, binary64 filter, exact fallback */
+  CCSP_TRACE_FP32_FILTERED = 1, /* binary32 coordinates + error-bound filter, then as FP64 */
+  CCSP_TRACE_MODE_MASK = 0xff,
+  CCSP_TRACE_VALIDATE = 1 << 8, /* check every ray's precondition exactly; synchronises the
+                                   stream and returns CCSP_E_BAD_RAY if any ray fails it */
+  CCSP_TRACE_COUNT = 1 << 9     /* accumulate the counters read by read_counters() */
+};
+
+typedef struct Triangulation Triangulation; /* opaque; owns its device memory */
+
+/* Host description of a triangulation; everything is copied at load. */
+typedef struct {
+  int64_t n_vertices;
+  const double *xy;        /* 2*n_vertices: x0,y0,x1,y1,... (binary64 is authoritative) */
+  int64_t n_triangles;     /* < 2^29 */
+  const int32_t *tri_v;    /* 3*n_triangles */
+  const int32_t *tri_nbr;  /* 3*n_triangles */
+  const int32_t *tri_prim; /* 3*n_triangles */
+  int64_t n_prims;
+  const double *prim_seg;  /* 4*n_prims: ax,ay,bx,by (t is computed from these) */
+} TriangulationDesc;
+
+/* Tuning of the persistent walk (NULL = library defaults). Zero fields take the default. */
+typedef struct {
+  int32_t wg_size;       /* threads per workgroup: 64, 128, 256, 512 */
+  int32_t tile_rays;     /* rays staged per wave in LDS per claim: 64..512, multiple of 64 */
+  int32_t waves_per_cu;  /* persistent waves resident per compute unit (grid size) */
+  int32_t refill_min;    /* refill a wave once at least this many of its 64 lanes are idle */
+  int32_t reserved[4];
+} TuneParams;
+
+/*
+ * load_triangulation: validate desc, pack it for the walk and copy it to the current device.
+ * Validation (exact): vertex ids in range, every triangle strictly counter-clockwise, coordinates
+ * finite with magnitude < 2^64, neighbours in range and symmetric with the shared edge reversed,
+ * the same primitive on both sides of an edge, primitive ids in range, every constrained edge
+ * collinear with its primitive, V - E + T = 1 over the referenced vertices. Failure returns
+ * CCSP_E_BAD_TRIANGULATION and names the first offending triangle. On success *out owns the
+ * device copy until free_triangulation. Host pointers are not retained. Synchronises `stream`.
+ */
+int load_triangulation(const TriangulationDesc *desc, void *stream, Triangulation **out);
+
+/*
+ * trace_rays: walk n rays through one triangulation. All array arguments are DEVICE pointers
+ * owned by the caller: o_xy and d_xy hold n interleaved (x,y) binary64 pairs (16-byte aligned),
+ * start_tri n triangle ids; the outputs hit_prim, hit_t (8-byte aligned) and steps receive n
+ * values each. d must be nonzero and the origin strictly inside start_tri. No allocation; the
+ * call is asynchronous on `stream` (except with CCSP_TRACE_VALIDATE).
+ */
+int trace_rays(const Triangulation *tri, const double *o_xy, const double *d_xy,
+               const int32_t *start_tri, int64_t n, int precision, int32_t *hit_prim,
+               double *hit_t, int32_t *steps, void *stream);
+
+/* trace_rays with explicit tuning of the persistent launch (tune may be NULL). */
+int trace_rays_tuned(const Triangulation *tri, const double *o_xy, const double *d_xy,
+                     const int32_t *start_tri, int64_t n, int precision, int32_t *hit_prim,
+                     double *hit_t, int32_t *steps, const TuneParams *tune, void *stream);
+
+/* One batch item: a triangulation and its rays (device pointers, as in trace_rays). */
+typedef struct {
+  const Triangulation *scene;
+  const double *o_xy;
+  const double *d_xy;
+  const int32_t *start_tri;
+  int64_t n;
+  int32_t *hit_prim;
+  double *hit_t;
+  int32_t *steps;
+} TraceItem;
+
+/*
+ * trace_batch: walk the rays of n_items items (possibly different triangulations of uneven
+ * sizes) in one persistent launch. `items` is a HOST array, read during the call. Results equal
+ * those of one trace_rays per item. The item table is uploaded from library-owned pinned memory
+ * reserved at the first call (no allocation afterwards unless n_items exceeds every earlier
+ * call's). With tune->reserved[0] = 1 the upload and launch are replayed from a cached HIP graph.
+ */
+int trace_batch(const TraceItem *items, int32_t n_items, int precision, const TuneParams *tune,
+                void *stream);
+
+/* free_triangulation: release the device copy (synchronises the device first). NULL is a no-op. */
+void free_triangulation(Triangulation *tri);
+
+/* last_error: description of the last failure on this thread ("" if none). */
+const char *last_error(void);
+
+/*
+ * read_counters: out[0] steps walked, out[1] binary32 decisions deferred to binary64,
+ * out[2] binary64 decisions deferred to the exact expansion, out[3] rays traced, accumulated
+ * over every trace made with CCSP_TRACE_COUNT on the current device since the last reset.
+ * Synchronises the device. reset != 0 clears them after reading.
+ */
+int read_counters(uint64_t out[4], int reset);
+
+/* triangulation_info: out[0] triangles, out[1] vertices, out[2] primitives, out[3] device bytes. */
+int triangulation_info(const Triangulation *tri, int64_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCSP_WALK_H */

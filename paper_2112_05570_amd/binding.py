@@ -1,0 +1,141 @@
+"""ctypes binding of libccsp_walk.so (include/ccsp_walk.h), same names as the C ABI.
+
+Argument marshalling only: every step of the walk runs in the library's HIP kernels. Device
+buffers are passed as raw pointers (torch tensors on the GPU via ``data_ptr()``), streams as
+``hipStream_t`` handles (``torch.cuda.current_stream().cuda_stream``). The module raises at import
+if the library is missing; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccsp_walk.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(the walk has no non-HIP implementation)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+CCSP_OK = 0
+CCSP_E_ARG = -1
+CCSP_E_BAD_TRIANGULATION = -2
+CCSP_E_OOM = -3
+CCSP_E_HIP = -4
+CCSP_E_BAD_RAY = -5
+CCSP_RAY_MISS = -1
+CCSP_RAY_GUARD = -2
+CCSP_RAY_BAD = -3
+CCSP_TRACE_FP64 = 0
+CCSP_TRACE_FP32_FILTERED = 1
+CCSP_TRACE_VALIDATE = 1 << 8
+CCSP_TRACE_COUNT = 1 << 9
+
+EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch",
+           "free_triangulation", "last_error", "read_counters", "triangulation_info")
+
+
+class TriangulationDesc(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("xy", ctypes.c_void_p),
+                ("n_triangles", ctypes.c_int64), ("tri_v", ctypes.c_void_p),
+                ("tri_nbr", ctypes.c_void_p), ("tri_prim", ctypes.c_void_p),
+                ("n_prims", ctypes.c_int64), ("prim_seg", ctypes.c_void_p)]
+
+
+class TuneParams(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("tile_rays", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("refill_min", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class TraceItem(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("o_xy", ctypes.c_void_p), ("d_xy", ctypes.c_void_p),
+                ("start_tri", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("hit_prim", ctypes.c_void_p), ("hit_t", ctypes.c_void_p),
+                ("steps", ctypes.c_void_p)]
+
+
+_P, _I, _I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+_lib.load_triangulation.argtypes = [ctypes.POINTER(TriangulationDesc), _P, ctypes.POINTER(_P)]
+_lib.load_triangulation.restype = _I
+_lib.trace_rays.argtypes = [_P, _P, _P, _P, _I64, _I, _P, _P, _P, _P]
+_lib.trace_rays.restype = _I
+_lib.trace_rays_tuned.argtypes = [_P, _P, _P, _P, _I64, _I, _P, _P, _P,
+                                  ctypes.POINTER(TuneParams), _P]
+_lib.trace_rays_tuned.restype = _I
+_lib.trace_batch.argtypes = [ctypes.POINTER(TraceItem), ctypes.c_int32, _I,
+                             ctypes.POINTER(TuneParams), _P]
+_lib.trace_batch.restype = _I
+_lib.free_triangulation.argtypes = [_P]
+_lib.free_triangulation.restype = None
+_lib.last_error.argtypes = []
+_lib.last_error.restype = ctypes.c_char_p
+_lib.read_counters.argtypes = [ctypes.POINTER(ctypes.c_uint64 * 4), _I]
+_lib.read_counters.restype = _I
+_lib.triangulation_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64 * 4)]
+_lib.triangulation_info.restype = _I
+
+
+class CcspError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ccsp error {code}: {msg}")
+        self.code = code
+
+
+def last_error() -> str:
+    return _lib.last_error().decode()
+
+
+def _check(rc):
+    if rc != CCSP_OK:
+        raise CcspError(rc, last_error())
+    return rc
+
+
+def load_triangulation(desc: TriangulationDesc, stream: int = 0) -> int:
+    h = _P()
+    _check(_lib.load_triangulation(ctypes.byref(desc), _P(stream), ctypes.byref(h)))
+    return h.value
+
+
+def trace_rays(tri: int, o_xy: int, d_xy: int, start_tri: int, n: int, precision: int,
+               hit_prim: int, hit_t: int, steps: int, stream: int = 0) -> None:
+    _check(_lib.trace_rays(_P(tri), _P(o_xy), _P(d_xy), _P(start_tri), n, precision, _P(hit_prim),
+                           _P(hit_t), _P(steps), _P(stream)))
+
+
+def trace_rays_tuned(tri: int, o_xy: int, d_xy: int, start_tri: int, n: int, precision: int,
+                     hit_prim: int, hit_t: int, steps: int, tune: TuneParams | None,
+                     stream: int = 0) -> None:
+    _check(_lib.trace_rays_tuned(_P(tri), _P(o_xy), _P(d_xy), _P(start_tri), n, precision,
+                                 _P(hit_prim), _P(hit_t), _P(steps),
+                                 ctypes.byref(tune) if tune is not None else None, _P(stream)))
+
+
+def trace_batch(items, precision: int, tune: TuneParams | None = None, stream: int = 0) -> None:
+    arr = (TraceItem * len(items))(*items)
+    _check(_lib.trace_batch(arr, len(items), precision,
+                            ctypes.byref(tune) if tune is not None else None, _P(stream)))
+
+
+def free_triangulation(tri: int) -> None:
+    _lib.free_triangulation(_P(tri))
+
+
+def read_counters(reset: bool = False) -> list:
+    out = (ctypes.c_uint64 * 4)()
+    _check(_lib.read_counters(ctypes.byref(out), int(reset)))
+    return list(out)
+
+
+def triangulation_info(tri: int) -> list:
+    out = (ctypes.c_int64 * 4)()
+    _check(_lib.triangulation_info(_P(tri), ctypes.byref(out)))
+    return list(out)
+
+
+def raw_call(name: str, *args):
+    """Direct access to an exported symbol (for tests of argument handling)."""
+    return getattr(_lib, name)(*args)

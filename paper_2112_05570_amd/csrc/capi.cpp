@@ -1,0 +1,520 @@
+// C ABI of the triangulation walk: load (validate, pack, upload), trace, batch, counters.
+//
+// Packing for the walk (paper Sec. 5.1 needs, per visited triangle, the exit decision and the
+// neighbour across the chosen edge): every (triangle, edge) slot stores the exit word and the one
+// vertex the next step tests, so a step is a single dependent 16-byte (binary32) or 32-byte
+// (binary64) load. Memory is traded for latency: a 4M-triangle scene takes ~0.7 GB of HBM.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ccsp_walk.h"
+#include "exact.hpp"
+#include "walk.hpp"
+
+using namespace ccsp;
+
+struct Triangulation {
+  int device = 0;
+  void* mem = nullptr;
+  size_t bytes = 0;
+  SceneDev dev{};
+  int64_t nv = 0, nt = 0, np = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(CCSP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+  const int hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int nth = n < 65536 ? 1 : hw;
+  if (nth == 1) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nth - 1) / nth;
+  for (int k = 0; k < nth; ++k) {
+    const int64_t a = k * chunk, b = std::min(n, a + chunk);
+    if (a < b) th.emplace_back([&f, a, b] { f(a, b); });
+  }
+  for (auto& t : th) t.join();
+}
+
+// host orientation: binary64 filter (Shewchuk's bound (3+16u)u for this evaluation), then exact
+int orient_host(const double* a, const double* b, const double* c) {
+  const double l = (b[0] - a[0]) * (c[1] - a[1]);
+  const double r = (b[1] - a[1]) * (c[0] - a[0]);
+  const double det = l - r, sum = std::fabs(l) + std::fabs(r);
+  if (std::fabs(det) > 0x1p-51 * sum && sum > 0x1p-900) return det > 0 ? 1 : -1;
+  return orient_exact(a[0], a[1], b[0], b[1], c[0], c[1]);
+}
+
+struct DeviceState {
+  bool init = false;
+  int cus = 0;
+  Workspace ws{};
+  std::atomic<unsigned> next_counter{0};
+  // trace_batch staging
+  std::mutex mu;
+  BatchItem* items_dev = nullptr;
+  BatchItem* items_host = nullptr;  // pinned
+  int items_cap = 0;
+  hipEvent_t staging_free = nullptr;
+  std::unordered_map<uint64_t, hipGraphExec_t> graphs;
+};
+
+std::mutex g_dev_mu;
+DeviceState g_dev[64];
+
+int device_state(DeviceState** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(CCSP_E_HIP, "device index %d unsupported", dev);
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  DeviceState& s = g_dev[dev];
+  if (!s.init) {
+    e = hipDeviceGetAttribute(&s.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    void* p = nullptr;
+    const size_t bytes = sizeof(unsigned long long) * (kCounterSlots + 4) + 256;
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(CCSP_E_OOM, "workspace allocation failed: %s", hipGetErrorString(e));
+    e = hipMemset(p, 0, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset");
+    s.ws.counters = static_cast<unsigned long long*>(p);
+    s.ws.stats = s.ws.counters + kCounterSlots;
+    s.ws.errflag = reinterpret_cast<int*>(s.ws.stats + 4);
+    e = hipEventCreateWithFlags(&s.staging_free, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    s.init = true;
+  }
+  *out = &s;
+  return CCSP_OK;
+}
+
+LaunchCfg make_cfg(const DeviceState& ds, int mode, const TuneParams* tp) {
+  LaunchCfg c{};
+  c.wg = (tp && tp->wg_size) ? tp->wg_size : 256;
+  c.tile = (tp && tp->tile_rays) ? tp->tile_rays : (mode == 1 ? 64 : 64);
+  const int wpcu = (tp && tp->waves_per_cu) ? tp->waves_per_cu : 32;
+  c.refill_min = (tp && tp->refill_min) ? tp->refill_min : 16;
+  c.grid = std::max(1, ds.cus * wpcu / (c.wg / 64));
+  return c;
+}
+
+int check_cfg(const LaunchCfg& c) {
+  if (c.wg < 64 || c.wg > 512 || c.wg % 64) return fail(CCSP_E_ARG, "wg_size %d must be 64..512, multiple of 64", c.wg);
+  if (c.tile != 64 && c.tile != 128 && c.tile != 256) return fail(CCSP_E_ARG, "tile_rays %d must be 64, 128 or 256", c.tile);
+  if (c.refill_min < 1 || c.refill_min > 64) return fail(CCSP_E_ARG, "refill_min %d must be 1..64", c.refill_min);
+  return CCSP_OK;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* last_error(void) { return g_err.c_str(); }
+
+int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulation** out) {
+  g_err.clear();
+  if (!desc || !out) return fail(CCSP_E_ARG, "null descriptor or output pointer");
+  *out = nullptr;
+  const int64_t V = desc->n_vertices, T = desc->n_triangles, P = desc->n_prims;
+  if (V < 3 || V > INT32_MAX) return fail(CCSP_E_ARG, "n_vertices %lld out of range", (long long)V);
+  if (T < 1 || T >= (int64_t(1) << 29)) return fail(CCSP_E_ARG, "n_triangles %lld out of range [1, 2^29)", (long long)T);
+  if (P < 0 || P > INT32_MAX - 3) return fail(CCSP_E_ARG, "n_prims %lld out of range", (long long)P);
+  if (!desc->xy || !desc->tri_v || !desc->tri_nbr || !desc->tri_prim || (P > 0 && !desc->prim_seg))
+    return fail(CCSP_E_ARG, "null array in descriptor");
+  const double* xy = desc->xy;
+  const int32_t *tv = desc->tri_v, *tn = desc->tri_nbr, *tp = desc->tri_prim;
+  const double* ps = desc->prim_seg;
+
+  // ---- validation (first failure per worker, reported in triangle order)
+  const double kMax = 0x1p64;
+  for (int64_t i = 0; i < 2 * V; ++i)
+    if (!std::isfinite(xy[i]) || std::fabs(xy[i]) >= kMax)
+      return fail(CCSP_E_BAD_TRIANGULATION, "vertex %lld: coordinate not finite or |x| >= 2^64", (long long)(i / 2));
+  for (int64_t i = 0; i < 4 * P; ++i)
+    if (!std::isfinite(ps[i]) || std::fabs(ps[i]) >= kMax)
+      return fail(CCSP_E_BAD_TRIANGULATION, "primitive %lld: coordinate not finite or |x| >= 2^64", (long long)(i / 4));
+  std::vector<int64_t> bad(64, INT64_MAX);
+  std::vector<std::string> why(64);
+  std::atomic<int> slot{0};
+  std::vector<uint8_t> used(V, 0);
+  std::atomic<int64_t> n_hull{0};
+  parallel_for(T, [&](int64_t a, int64_t b) {
+    const int me = slot.fetch_add(1);
+    int64_t hull = 0;
+    auto note = [&](int64_t t, const char* w) {
+      if (t < bad[me]) { bad[me] = t; why[me] = w; }
+    };
+    for (int64_t t = a; t < b && bad[me] == INT64_MAX; ++t) {
+      const int32_t* v = tv + 3 * t;
+      bool ids_ok = true;
+      for (int i = 0; i < 3; ++i)
+        if (v[i] < 0 || v[i] >= V) ids_ok = false;
+      if (!ids_ok) { note(t, "vertex id out of range"); break; }
+      for (int i = 0; i < 3; ++i) used[v[i]] = 1;  // benign race: every writer stores 1
+      if (orient_host(xy + 2 * (int64_t)v[0], xy + 2 * (int64_t)v[1], xy + 2 * (int64_t)v[2]) <= 0) {
+        note(t, "triangle is not strictly counter-clockwise");
+        break;
+      }
+      for (int i = 0; i < 3; ++i) {
+        const int32_t n = tn[3 * t + i], pr = tp[3 * t + i];
+        if (pr < -1 || pr >= P) { note(t, "primitive id out of range"); break; }
+        const int32_t p = v[(i + 1) % 3], q = v[(i + 2) % 3];
+        if (pr >= 0) {
+          const double* s = ps + 4 * (int64_t)pr;
+          if (orient_host(s, s + 2, xy + 2 * (int64_t)p) != 0 || orient_host(s, s + 2, xy + 2 * (int64_t)q) != 0) {
+            note(t, "constrained edge is not collinear with its primitive");
+            break;
+          }
+        }
+        if (n == -1) { ++hull; continue; }
+        if (n < 0 || n >= T) { note(t, "neighbour out of range"); break; }
+        int back = -1, hits = 0;
+        for (int j = 0; j < 3; ++j)
+          if (tn[3 * (int64_t)n + j] == t) { back = j; ++hits; }
+        if (hits != 1) { note(t, "adjacency is not symmetric"); break; }
+        const int32_t* w = tv + 3 * (int64_t)n;
+        if (w[(back + 1) % 3] != q || w[(back + 2) % 3] != p) { note(t, "shared edge does not match its neighbour"); break; }
+        if (tp[3 * (int64_t)n + back] != pr) { note(t, "primitive differs across a shared edge"); break; }
+      }
+    }
+    n_hull += hull;
+  });
+  int64_t first = INT64_MAX;
+  std::string reason;
+  for (int k = 0; k < 64; ++k)
+    if (bad[k] < first) { first = bad[k]; reason = why[k]; }
+  if (first != INT64_MAX)
+    return fail(CCSP_E_BAD_TRIANGULATION, "triangle %lld: %s", (long long)first, reason.c_str());
+  int64_t vused = 0;
+  for (int64_t i = 0; i < V; ++i) vused += used[i];
+  const int64_t E = (3 * T + n_hull.load()) / 2;
+  if (vused - E + T != 1)
+    return fail(CCSP_E_BAD_TRIANGULATION, "Euler characteristic V - E + T = %lld, expected 1 (one disk)",
+                (long long)(vused - E + T));
+
+  // ---- packing
+  double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+  for (int64_t i = 0; i < V; ++i)
+    for (int k = 0; k < 2; ++k) {
+      lo[k] = std::min(lo[k], xy[2 * i + k]);
+      hi[k] = std::max(hi[k], xy[2 * i + k]);
+    }
+  const double org[2] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1])};
+  auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t off_s32 = 0;
+  const size_t off_s64 = align(off_s32 + sizeof(Slot32) * 3 * T);
+  const size_t off_txy = align(off_s64 + sizeof(Slot64) * 3 * T);
+  const size_t off_tv = align(off_txy + sizeof(TriXY32) * T);
+  const size_t off_v = align(off_tv + sizeof(int4) * T);
+  const size_t off_p = align(off_v + sizeof(double2) * V);
+  const size_t total = align(off_p + sizeof(double4) * std::max<int64_t>(P, 1));
+  std::vector<unsigned char> host(total, 0);
+  auto* s32 = reinterpret_cast<Slot32*>(host.data() + off_s32);
+  auto* s64 = reinterpret_cast<Slot64*>(host.data() + off_s64);
+  auto* txy = reinterpret_cast<TriXY32*>(host.data() + off_txy);
+  auto* t4 = reinterpret_cast<int4*>(host.data() + off_tv);
+  std::memcpy(host.data() + off_v, xy, sizeof(double) * 2 * V);
+  if (P > 0) std::memcpy(host.data() + off_p, ps, sizeof(double) * 4 * P);
+  parallel_for(T, [&](int64_t a, int64_t b) {
+    for (int64_t t = a; t < b; ++t) {
+      const int32_t* v = tv + 3 * t;
+      t4[t] = make_int4(v[0], v[1], v[2], 0);
+      for (int i = 0; i < 3; ++i) {
+        txy[t].x[i] = (float)(xy[2 * (int64_t)v[i]] - org[0]);
+        txy[t].y[i] = (float)(xy[2 * (int64_t)v[i] + 1] - org[1]);
+      }
+      for (int i = 0; i < 3; ++i) {
+        const int64_t k = 3 * t + i;
+        const int32_t n = tn[k], pr = tp[k];
+        int32_t word, vid = 0;
+        if (pr >= 0) {
+          word = -(pr + 2);
+        } else if (n < 0) {
+          word = -1;
+        } else {
+          int back = 0;
+          for (int j = 0; j < 3; ++j)
+            if (tn[3 * (int64_t)n + j] == t) back = j;
+          word = (n << 2) | back;
+          vid = tv[3 * (int64_t)n + back];
+        }
+        const double vx = xy[2 * (int64_t)vid], vy = xy[2 * (int64_t)vid + 1];
+        s32[k].word = word;
+        s32[k].vid = vid;
+        s32[k].x = word >= 0 ? (float)(vx - org[0]) : 0.0f;
+        s32[k].y = word >= 0 ? (float)(vy - org[1]) : 0.0f;
+        s64[k].word = word;
+        s64[k].vid = vid;
+        s64[k].x = word >= 0 ? vx : 0.0;
+        s64[k].y = word >= 0 ? vy : 0.0;
+      }
+    }
+  });
+
+  // ---- upload
+  DeviceState* ds = nullptr;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  auto* tri = new Triangulation;
+  (void)hipGetDevice(&tri->device);
+  hipError_t e = hipMalloc(&tri->mem, total);
+  if (e != hipSuccess) {
+    delete tri;
+    return fail(CCSP_E_OOM, "device allocation of %zu bytes failed: %s", total, hipGetErrorString(e));
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  e = hipMemcpyAsync(tri->mem, host.data(), total, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    (void)hipFree(tri->mem);
+    delete tri;
+    return hip_fail(e, "upload");
+  }
+  auto* base = static_cast<unsigned char*>(tri->mem);
+  tri->bytes = total;
+  tri->nv = V;
+  tri->nt = T;
+  tri->np = P;
+  tri->dev.slot32 = reinterpret_cast<const Slot32*>(base + off_s32);
+  tri->dev.slot64 = reinterpret_cast<const Slot64*>(base + off_s64);
+  tri->dev.trixy = reinterpret_cast<const TriXY32*>(base + off_txy);
+  tri->dev.triv = reinterpret_cast<const int4*>(base + off_tv);
+  tri->dev.v64 = reinterpret_cast<const double2*>(base + off_v);
+  tri->dev.prim = reinterpret_cast<const double4*>(base + off_p);
+  tri->dev.org_x = org[0];
+  tri->dev.org_y = org[1];
+  tri->dev.ntri = (int32_t)T;
+  *out = tri;
+  return CCSP_OK;
+}
+
+void free_triangulation(Triangulation* tri) {
+  if (!tri) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(tri->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(tri->mem);
+  (void)hipSetDevice(cur);
+  delete tri;
+}
+
+int triangulation_info(const Triangulation* tri, int64_t out[4]) {
+  if (!tri || !out) return fail(CCSP_E_ARG, "null argument");
+  out[0] = tri->nt;
+  out[1] = tri->nv;
+  out[2] = tri->np;
+  out[3] = (int64_t)tri->bytes;
+  return CCSP_OK;
+}
+
+static int check_rays(const double* o, const double* d, const int32_t* s, int64_t n, int32_t* hp,
+                      double* ht, int32_t* st) {
+  if (n < 0) return fail(CCSP_E_ARG, "negative ray count");
+  if (n == 0) return CCSP_OK;
+  if (!o || !d || !s || !hp || !ht || !st) return fail(CCSP_E_ARG, "null ray or output pointer");
+  if (!aligned(o, 16) || !aligned(d, 16)) return fail(CCSP_E_ARG, "o_xy and d_xy must be 16-byte aligned");
+  if (!aligned(ht, 8) || !aligned(s, 4) || !aligned(hp, 4) || !aligned(st, 4))
+    return fail(CCSP_E_ARG, "misaligned output or start_tri");
+  return CCSP_OK;
+}
+
+int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double* d_xy,
+                     const int32_t* start_tri, int64_t n, int precision, int32_t* hit_prim,
+                     double* hit_t, int32_t* steps, const TuneParams* tune, void* stream) {
+  g_err.clear();
+  if (!tri) return fail(CCSP_E_ARG, "null triangulation");
+  const int mode = precision & CCSP_TRACE_MODE_MASK;
+  if (mode != CCSP_TRACE_FP64 && mode != CCSP_TRACE_FP32_FILTERED)
+    return fail(CCSP_E_ARG, "unknown precision mode %d", mode);
+  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_VALIDATE | CCSP_TRACE_COUNT))
+    return fail(CCSP_E_ARG, "unknown precision flags 0x%x", precision);
+  int rc = check_rays(o_xy, d_xy, start_tri, n, hit_prim, hit_t, steps);
+  if (rc || n == 0) return rc;
+  DeviceState* ds = nullptr;
+  rc = device_state(&ds);
+  if (rc) return rc;
+  const LaunchCfg cfg = make_cfg(*ds, mode, tune);
+  rc = check_cfg(cfg);
+  if (rc) return rc;
+  const bool validate = precision & CCSP_TRACE_VALIDATE;
+  const bool count = precision & CCSP_TRACE_COUNT;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  RaysDev io{reinterpret_cast<const double2*>(o_xy), reinterpret_cast<const double2*>(d_xy),
+             start_tri, hit_prim, hit_t, steps, n};
+  unsigned long long* counter = ds->ws.counters + (ds->next_counter.fetch_add(1) % kCounterSlots);
+  hipError_t e;
+  if (validate) {
+    e = hipMemsetAsync(ds->ws.errflag, 0, sizeof(int), st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+  }
+  e = launch_walk(tri->dev, io, mode, count, validate, cfg, counter, ds->ws, st);
+  if (e != hipSuccess) return hip_fail(e, "walk launch");
+  if (validate) {
+    int flag = 0;
+    e = hipMemcpyAsync(&flag, ds->ws.errflag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "validation read-back");
+    if (flag) return fail(CCSP_E_BAD_RAY, "a ray's origin is not strictly inside its start triangle, its start "
+                                          "triangle is out of range, or its direction is zero or not finite");
+  }
+  return CCSP_OK;
+}
+
+int trace_rays(const Triangulation* tri, const double* o_xy, const double* d_xy,
+               const int32_t* start_tri, int64_t n, int precision, int32_t* hit_prim,
+               double* hit_t, int32_t* steps, void* stream) {
+  return trace_rays_tuned(tri, o_xy, d_xy, start_tri, n, precision, hit_prim, hit_t, steps, nullptr,
+                          stream);
+}
+
+int trace_batch(const TraceItem* items, int32_t n_items, int precision, const TuneParams* tune,
+                void* stream) {
+  g_err.clear();
+  if (n_items < 0 || (n_items > 0 && !items)) return fail(CCSP_E_ARG, "bad item array");
+  const int mode = precision & CCSP_TRACE_MODE_MASK;
+  if (mode != CCSP_TRACE_FP64 && mode != CCSP_TRACE_FP32_FILTERED)
+    return fail(CCSP_E_ARG, "unknown precision mode %d", mode);
+  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_COUNT))
+    return fail(CCSP_E_ARG, "unsupported precision flags 0x%x for trace_batch", precision);
+  DeviceState* ds = nullptr;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  const LaunchCfg cfg = make_cfg(*ds, mode, tune);
+  rc = check_cfg(cfg);
+  if (rc) return rc;
+  const bool use_graph = tune && tune->reserved[0] == 1;
+  int64_t tiles = 0;
+  for (int i = 0; i < n_items; ++i) {
+    const TraceItem& it = items[i];
+    if (!it.scene) return fail(CCSP_E_ARG, "item %d: null scene", i);
+    rc = check_rays(it.o_xy, it.d_xy, it.start_tri, it.n, it.hit_prim, it.hit_t, it.steps);
+    if (rc) return fail(rc, "item %d: %s", i, g_err.c_str());
+    tiles += (it.n + cfg.tile - 1) / cfg.tile;
+  }
+  if (tiles == 0) return CCSP_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(ds->mu);
+  hipError_t e;
+  if (n_items > ds->items_cap) {  // grow the staging buffers (first call or a larger batch)
+    if (ds->items_dev) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(ds->items_dev);
+      (void)hipHostFree(ds->items_host);
+      for (auto& kv : ds->graphs) (void)hipGraphExecDestroy(kv.second);
+      ds->graphs.clear();
+    }
+    int cap = 256;
+    while (cap < n_items) cap *= 2;
+    e = hipMalloc(&ds->items_dev, sizeof(BatchItem) * cap);
+    if (e != hipSuccess) return fail(CCSP_E_OOM, "item table allocation failed");
+    e = hipHostMalloc(&ds->items_host, sizeof(BatchItem) * cap, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(CCSP_E_OOM, "pinned item table allocation failed");
+    ds->items_cap = cap;
+  }
+  // the pinned table may still be read by the previous batch's upload
+  e = hipEventSynchronize(ds->staging_free);
+  if (e != hipSuccess) return hip_fail(e, "staging wait");
+  int64_t tb = 0;
+  for (int i = 0; i < n_items; ++i) {
+    const TraceItem& it = items[i];
+    BatchItem& b = ds->items_host[i];
+    b.scene = it.scene->dev;
+    b.rays = RaysDev{reinterpret_cast<const double2*>(it.o_xy), reinterpret_cast<const double2*>(it.d_xy),
+                     it.start_tri, it.hit_prim, it.hit_t, it.steps, it.n};
+    b.tile_begin = tb;
+    tb += (it.n + cfg.tile - 1) / cfg.tile;
+  }
+  unsigned long long* counter = ds->ws.counters + (ds->next_counter.fetch_add(1) % kCounterSlots);
+  const bool count = precision & CCSP_TRACE_COUNT;
+  if (!use_graph) {
+    e = hipMemcpyAsync(ds->items_dev, ds->items_host, sizeof(BatchItem) * n_items, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "item table upload");
+    e = hipEventRecord(ds->staging_free, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    e = launch_walk_batch(ds->items_dev, n_items, tiles, mode, count, cfg, counter, ds->ws, st);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return CCSP_OK;
+  }
+  // Graph path: (upload, reset, walk) captured once per (n_items, tiles, mode, count, cfg,
+  // counter) and replayed; the upload node reads the pinned table at replay time.
+  const uint64_t key = ((uint64_t)n_items << 40) ^ ((uint64_t)tiles << 8) ^ ((uint64_t)mode << 4) ^
+                       ((uint64_t)count << 3) ^ ((uint64_t)cfg.tile << 50) ^ ((uint64_t)cfg.wg << 56) ^
+                       ((uint64_t)cfg.refill_min << 20) ^ ((uint64_t)cfg.grid << 28);
+  counter = ds->ws.counters + kCounterSlots - 1;  // graphs use the reserved last counter slot
+  auto itg = ds->graphs.find(key);
+  if (itg == ds->graphs.end()) {
+    hipStream_t cap_stream;
+    e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t e1 = hipMemcpyAsync(ds->items_dev, ds->items_host, sizeof(BatchItem) * n_items,
+                                   hipMemcpyHostToDevice, cap_stream);
+    hipError_t e2 = launch_walk_batch(ds->items_dev, n_items, tiles, mode, count, cfg, counter, ds->ws, cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap_stream, &g);
+    (void)hipStreamDestroy(cap_stream);
+    if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) return hip_fail(e != hipSuccess ? e : (e1 != hipSuccess ? e1 : e2), "graph capture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    itg = ds->graphs.emplace(key, ge).first;
+  }
+  e = hipGraphLaunch(itg->second, st);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  e = hipEventRecord(ds->staging_free, st);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return CCSP_OK;
+}
+
+int read_counters(uint64_t out[4], int reset) {
+  if (!out) return fail(CCSP_E_ARG, "null output");
+  DeviceState* ds = nullptr;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(out, ds->ws.stats, sizeof(uint64_t) * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && reset) e = hipMemset(ds->ws.stats, 0, sizeof(uint64_t) * 4);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "read_counters");
+  return CCSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Device layout of a packed triangulation and the launch interface of the walk kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ccsp {
+
+// Exit-edge word stored per (triangle, edge) slot:
+//   >= 0 : (neighbour << 2) | back, where `back` is the edge of the neighbour that leads back;
+//   -1   : unconstrained hull edge (the ray leaves the triangulation);
+//   <= -2: constrained edge of primitive (-word - 2).
+// Each slot also stores the vertex across the edge (the neighbour's vertex opposite `back`),
+// which is exactly the one vertex the next step needs: one dependent load per step.
+struct alignas(16) Slot32 {  // binary32 walk: 16 B per slot
+  int32_t word;
+  float x, y;                 // across vertex, relative to the scene origin, rounded to binary32
+  int32_t vid;                // its vertex id (for the binary64 fallback)
+};
+struct alignas(32) Slot64 {  // binary64 walk: 32 B per slot
+  double x, y;                // across vertex (binary64, absolute)
+  int32_t word;
+  int32_t vid;
+  int32_t pad[2];
+};
+struct alignas(32) TriXY32 {  // own vertices of a triangle in binary32 (first step only)
+  float x[3], y[3];
+  float pad[2];
+};
+
+struct SceneDev {
+  const Slot32* slot32;  // 3T
+  const Slot64* slot64;  // 3T
+  const TriXY32* trixy;  // T
+  const int4* triv;      // T: v0, v1, v2, 0
+  const double2* v64;    // V
+  const double4* prim;   // P: ax, ay, bx, by
+  double org_x, org_y;   // origin of the binary32 coordinates
+  int32_t ntri;
+  int32_t pad;
+};
+
+struct RaysDev {
+  const double2* o;
+  const double2* d;
+  const int32_t* start;
+  int32_t* prim;
+  double* t;
+  int32_t* steps;
+  int64_t n;
+};
+
+// One item of a batched launch: the scene, its rays and where its tiles start in the
+// concatenated tile sequence.
+struct BatchItem {
+  SceneDev scene;
+  RaysDev rays;
+  int64_t tile_begin;
+};
+
+struct LaunchCfg {
+  int wg;          // threads per workgroup (multiple of 64)
+  int tile;        // rays per wave tile (multiple of 64)
+  int grid;        // workgroups
+  int refill_min;  // idle lanes that trigger a refill
+};
+
+// Per-device scratch used by the walk: tile counters and the diagnostic counters.
+struct Workspace {
+  unsigned long long* counters;  // ring of kCounterSlots tile counters
+  unsigned long long* stats;     // 4 diagnostic counters
+  int* errflag;                  // set by validating launches
+};
+constexpr int kCounterSlots = 4096;
+
+hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
+                       const LaunchCfg& cfg, unsigned long long* counter, const Workspace& ws,
+                       hipStream_t stream);
+
+hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t total_tiles,
+                             int mode, bool count, const LaunchCfg& cfg,
+                             unsigned long long* counter, const Workspace& ws, hipStream_t stream);
+
+size_t walk_lds_bytes(int mode, const LaunchCfg& cfg);
+
+}  // namespace ccsp

@@ -1,0 +1,491 @@
+// Persistent stackless triangulation walk for gfx950 (CDNA4, wave64).
+//
+// Paper: Sec. 5.1 (the walk: find the exit edge, stop on scene geometry or at the hull, else
+// continue in the neighbour) and Sec. 5.4 (one operation per visited triangle: choosing the exit
+// edge; two candidates once the entry edge is known, three in the first triangle).
+//
+// Mapping to the hardware:
+//  * The walk is a chain of dependent gathers with a few flops each, bound by memory latency and
+//    gather bandwidth, not by MFMA or the ALUs. One step is one 16-byte load: the slot of the exit
+//    edge holds the neighbour, the entry edge there and the one vertex the next decision needs.
+//  * Waves are persistent. Each wave claims tiles of TPL*64 rays from a global counter, stages
+//    them in its own LDS region (origin, direction and the first exit slot, computed while the
+//    tile is loaded), and refills idle lanes from LDS as soon as `refill_min` of its 64 lanes have
+//    finished, so that divergent ray lengths do not idle the SIMD.
+//  * Decisions: the sign of D(v) = dx*(vy-oy) - dy*(vx-ox), zero counting as LEFT. In binary32 mode
+//    the sign is taken from binary32 coordinates when a forward error bound proves it, otherwise
+//    from the binary64 filter, otherwise from an exact expansion; all three agree with the exact
+//    sign whenever they decide, so both modes give identical results.
+//
+// All code here is compiled with -ffp-contract=off: the filters' bounds and the hit distance
+// formula assume every operation is rounded separately.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "exact.hpp"
+#include "walk.hpp"
+
+namespace ccsp {
+
+// ------------------------------------------------------------------------------ decisions
+
+// binary32 filter. Inputs: origin and across vertex relative to the scene origin and rounded to
+// binary32 (relative error <= 2^-24 each, plus 2^-53 from the binary64 subtraction), direction
+// rounded to binary32. The rounded evaluation differs from the exact D by at most
+// u*|D~| + 4.02u*M, u = 2^-24, M = |dx|(|cy|+|oy|) + |dy|(|cx|+|ox|) (absolute magnitudes: input
+// rounding is relative to the coordinates, not to their differences). The threshold 6u*M~ + 2^-100
+// covers this with margin, also for subnormal intermediates. Returns +-1 if certain, 0 if not.
+struct Ray32 {
+  float ox, oy, dx, dy;
+};
+
+__device__ __forceinline__ int side32(const Ray32& r, float cx, float cy) {
+  const float a = cy - r.oy;
+  const float b = cx - r.ox;
+  const float D = r.dx * a - r.dy * b;
+  const float M = fabsf(r.dx) * (fabsf(cy) + fabsf(r.oy)) + fabsf(r.dy) * (fabsf(cx) + fabsf(r.ox));
+  if (fabsf(D) > 0x1.8p-22f * M + 0x1p-100f) return D > 0.0f ? 1 : -1;
+  return 0;
+}
+
+// Exact decision, kept out of line so that its expansion registers do not count against the
+// occupancy of the hot loop.
+__device__ __attribute__((noinline)) int side_exact_call(double ox, double oy, double dx, double dy,
+                                                         double vx, double vy) {
+  return side_exact(ox, oy, dx, dy, vx, vy);
+}
+
+template <bool COUNT>
+__device__ __forceinline__ bool left64(double ox, double oy, double dx, double dy, double vx,
+                                       double vy, unsigned& n_exact) {
+  bool certain;
+  int s = side_fp64_filtered(ox, oy, dx, dy, vx, vy, certain);
+  if (!certain) {
+    if (COUNT) ++n_exact;
+    s = side_exact_call(ox, oy, dx, dy, vx, vy);
+  }
+  return s >= 0;
+}
+
+struct Counters {
+  unsigned steps = 0, fb32 = 0, fb64 = 0, rays = 0;
+};
+
+// binary32 decision deferred to binary64: the ray is re-read from its (caller-owned) arrays.
+template <bool COUNT>
+__device__ __attribute__((noinline)) bool left_deferred(const double2* o_arr, const double2* d_arr,
+                                                        int64_t ray, const double2* v64, int vid,
+                                                        unsigned* n_exact) {
+  const double2 o = o_arr[ray], d = d_arr[ray], v = v64[vid];
+  unsigned n = 0;
+  const bool l = left64<COUNT>(o.x, o.y, d.x, d.y, v.x, v.y, n);
+  if (COUNT) *n_exact += n;
+  return l;
+}
+
+__device__ __attribute__((noinline)) bool validate_ray(const SceneDev& sc, double2 o, double2 d,
+                                                       int st) {
+  const int4 tv = sc.triv[st];
+  const double2 v[3] = {sc.v64[tv.x], sc.v64[tv.y], sc.v64[tv.z]};
+  bool ok = isfinite(d.x) && isfinite(d.y) && (d.x != 0.0 || d.y != 0.0) && isfinite(o.x) &&
+            isfinite(o.y);
+  for (int i = 0; i < 3; ++i) {
+    const double2 a = v[(i + 1) % 3], b = v[(i + 2) % 3];
+    ok = ok && orient_exact(a.x, a.y, b.x, b.y, o.x, o.y) > 0;
+  }
+  return ok;
+}
+
+// Exit slot of the start triangle (3*st + edge), or -1 if st is out of range, no edge qualifies
+// or (VALIDATE) the origin is not strictly inside / the direction is zero or not finite.
+// The exit edge i is the one whose first endpoint is RIGHT of the ray and second LEFT.
+template <bool COUNT>
+__device__ __forceinline__ int first_exit32(const SceneDev& sc, const RaysDev& io, int64_t ray,
+                                            const Ray32& r, int st, Counters& c) {
+  const float4* p = reinterpret_cast<const float4*>(sc.trixy + st);
+  const float4 a = p[0], b = p[1];
+  int s0 = side32(r, a.x, a.w), s1 = side32(r, a.y, b.x), s2 = side32(r, a.z, b.y);
+  if ((s0 == 0) | (s1 == 0) | (s2 == 0)) {
+    const int4 tv = sc.triv[st];
+    if (s0 == 0) { if (COUNT) ++c.fb32; s0 = left_deferred<COUNT>(io.o, io.d, ray, sc.v64, tv.x, &c.fb64) ? 1 : -1; }
+    if (s1 == 0) { if (COUNT) ++c.fb32; s1 = left_deferred<COUNT>(io.o, io.d, ray, sc.v64, tv.y, &c.fb64) ? 1 : -1; }
+    if (s2 == 0) { if (COUNT) ++c.fb32; s2 = left_deferred<COUNT>(io.o, io.d, ray, sc.v64, tv.z, &c.fb64) ? 1 : -1; }
+  }
+  const bool L0 = s0 > 0, L1 = s1 > 0, L2 = s2 > 0;
+  const int e = (!L1 && L2) ? 0 : ((!L2 && L0) ? 1 : ((!L0 && L1) ? 2 : -1));
+  return e < 0 ? -1 : 3 * st + e;
+}
+
+template <bool COUNT>
+__device__ __forceinline__ int first_exit64(const SceneDev& sc, double2 o, double2 d, int st,
+                                            Counters& c) {
+  const int4 tv = sc.triv[st];
+  const double2 v0 = sc.v64[tv.x], v1 = sc.v64[tv.y], v2 = sc.v64[tv.z];
+  const bool L0 = left64<COUNT>(o.x, o.y, d.x, d.y, v0.x, v0.y, c.fb64);
+  const bool L1 = left64<COUNT>(o.x, o.y, d.x, d.y, v1.x, v1.y, c.fb64);
+  const bool L2 = left64<COUNT>(o.x, o.y, d.x, d.y, v2.x, v2.y, c.fb64);
+  const int e = (!L1 && L2) ? 0 : ((!L2 && L0) ? 1 : ((!L0 && L1) ? 2 : -1));
+  return e < 0 ? -1 : 3 * st + e;
+}
+
+__device__ __forceinline__ double hit_t(const double4 g, double ox, double oy, double dx,
+                                        double dy) {
+  const double ex = g.z - g.x;
+  const double ey = g.w - g.y;
+  const double num = (g.x - ox) * ey - (g.y - oy) * ex;
+  const double den = dx * ey - dy * ex;
+  return num / den;
+}
+
+// ------------------------------------------------------------------------------ persistent walk
+
+__device__ __forceinline__ int lane_rank(unsigned long long mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__device__ __forceinline__ long long bcast64(unsigned long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+  // A wave's LDS operations execute in order; this only stops the compiler from moving the
+  // reads of a freshly written tile above the writes.
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Per-wave LDS tile. binary32 mode: the rounded ray (float4) and the first exit slot, 20 B/ray;
+// binary64 mode: the ray (2 x double2) and the first exit slot, 36 B/ray.
+template <int MODE, int TILE>
+struct Tile {
+  static constexpr int kBytes = MODE == 1 ? 20 * TILE : 36 * TILE;
+  float4* r32;
+  double2* o;
+  double2* d;
+  int* s0;
+  __device__ explicit Tile(unsigned char* base) {
+    if (MODE == 1) {
+      r32 = reinterpret_cast<float4*>(base);
+      o = d = nullptr;
+      s0 = reinterpret_cast<int*>(base + 16 * TILE);
+    } else {
+      r32 = nullptr;
+      o = reinterpret_cast<double2*>(base);
+      d = reinterpret_cast<double2*>(base + 16 * TILE);
+      s0 = reinterpret_cast<int*>(base + 32 * TILE);
+    }
+  }
+};
+
+// Load rays [base, base+len) of `io` into the tile and compute their first exit slots.
+template <int MODE, int TPL, bool COUNT, bool VALIDATE>
+__device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, int len,
+                          const Tile<MODE, TPL * 64>& tl, int lane, Counters& c, int* errflag) {
+  // phase 1: all loads of the tile in flight together, rays rounded on arrival
+  int st[TPL];
+  float4 r[TPL];
+  double2 o[TPL], d[TPL];
+#pragma unroll
+  for (int q = 0; q < TPL; ++q) {
+    const int k = lane + 64 * q;
+    st[q] = -1;
+    if (k < len) {
+      o[q] = io.o[base + k];
+      d[q] = io.d[base + k];
+      st[q] = io.start[base + k];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TPL; ++q) {
+    const int k = lane + 64 * q;
+    if (k < len) {
+      if (MODE == 1) {
+        r[q] = make_float4((float)(o[q].x - sc.org_x), (float)(o[q].y - sc.org_y), (float)d[q].x,
+                           (float)d[q].y);
+        tl.r32[k] = r[q];
+      } else {
+        tl.o[k] = o[q];
+        tl.d[k] = d[q];
+      }
+      if (VALIDATE && (st[q] < 0 || st[q] >= sc.ntri || !validate_ray(sc, o[q], d[q], st[q]))) {
+        atomicOr(errflag, 1);
+        st[q] = -1;
+      }
+      if (st[q] >= sc.ntri) st[q] = -1;
+    }
+  }
+  // phase 2: first triangle of each ray
+#pragma unroll
+  for (int q = 0; q < TPL; ++q) {
+    const int k = lane + 64 * q;
+    if (k < len) {
+      int s0 = -1;
+      if (st[q] >= 0) {
+        if (MODE == 1) {
+          const Ray32 rr{r[q].x, r[q].y, r[q].z, r[q].w};
+          s0 = first_exit32<COUNT>(sc, io, base + k, rr, st[q], c);
+        } else {
+          s0 = first_exit64<COUNT>(sc, o[q], d[q], st[q], c);
+        }
+      }
+      tl.s0[k] = s0;
+    }
+  }
+  wave_lds_fence();
+}
+
+// Scene access in a batched launch.
+struct ItemRef {
+  const BatchItem* items;
+  int n_items;
+  const int64_t* lds_tile_begin;  // tile_begin of the first n_lds items, staged in LDS
+  int n_lds;
+};
+
+template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH>
+__global__ void __launch_bounds__(512)
+walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_tiles,
+                unsigned long long* __restrict__ counter, int refill_min,
+                unsigned long long* __restrict__ stats, int* __restrict__ errflag) {
+  constexpr int TILE = TPL * 64;
+  extern __shared__ unsigned char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  unsigned char* tile_mem = lds;
+  if (BATCH) {
+    // stage the items' first tiles in LDS for the tile -> item search
+    int64_t* tb = reinterpret_cast<int64_t*>(lds);
+    for (int i = threadIdx.x; i < batch.n_lds; i += blockDim.x) tb[i] = batch.items[i].tile_begin;
+    __syncthreads();
+    batch.lds_tile_begin = tb;
+    tile_mem = lds + (size_t)((batch.n_lds + 1) & ~1) * 8;
+  }
+  const Tile<MODE, TILE> tl(tile_mem + (size_t)wave * Tile<MODE, TILE>::kBytes);
+
+  Counters c;
+  // lane state
+  bool act = false;
+  Ray32 r32{0, 0, 0, 0};             // binary32 mode
+  double ox = 0, oy = 0, dx = 0, dy = 0;  // binary64 mode
+  int s = 0, steps = 0;
+  int64_t ray = 0;
+  int item = 0;
+  // per-lane scene in a batch, kernel argument otherwise
+  const Slot32* slot32 = sc_arg.slot32;
+  const Slot64* slot64 = sc_arg.slot64;
+  int ntri = sc_arg.ntri;
+
+  // wave-uniform tile state
+  int64_t tbase = 0;
+  int tlen = 0, thead = 0, titem = 0;
+  bool drained = false;
+
+  for (;;) {
+    const unsigned long long idle = __ballot(!act);
+    const int nidle = __popcll(idle);
+    if (drained && nidle == 64) break;
+    if (!drained && nidle >= refill_min) {
+      const int rank = lane_rank(idle);
+      int served = 0;
+      while (served < nidle) {
+        if (thead == tlen) {
+          unsigned long long b = 0;
+          if (lane == 0) b = atomicAdd(counter, BATCH ? 1ull : (unsigned long long)TILE);
+          const long long claim = bcast64(b);
+          if (BATCH) {
+            if (claim >= total_tiles) {
+              drained = true;
+              break;
+            }
+            // item owning tile `claim`: the last item whose tile_begin <= claim
+            int lo = 0, hi = batch.n_items - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              const int64_t tbm = mid < batch.n_lds ? batch.lds_tile_begin[mid]
+                                                    : batch.items[mid].tile_begin;
+              if (tbm <= claim) lo = mid;
+              else hi = mid - 1;
+            }
+            titem = __builtin_amdgcn_readfirstlane(lo);
+            const BatchItem& it = batch.items[titem];
+            tbase = (claim - it.tile_begin) * TILE;
+            tlen = (int)min((int64_t)TILE, it.rays.n - tbase);
+            thead = 0;
+            fill_tile<MODE, TPL, COUNT, false>(it.scene, it.rays, tbase, tlen, tl, lane, c, errflag);
+          } else {
+            if (claim >= io_arg.n) {
+              drained = true;
+              break;
+            }
+            tbase = claim;
+            tlen = (int)min((int64_t)TILE, io_arg.n - tbase);
+            thead = 0;
+            fill_tile<MODE, TPL, COUNT, VALIDATE>(sc_arg, io_arg, tbase, tlen, tl, lane, c, errflag);
+          }
+        }
+        const int take = min(nidle - served, tlen - thead);
+        if (!act && rank >= served && rank < served + take) {
+          const int k = thead + (rank - served);
+          if (MODE == 1) {
+            const float4 q = tl.r32[k];
+            r32 = Ray32{q.x, q.y, q.z, q.w};
+          } else {
+            const double2 o = tl.o[k], d = tl.d[k];
+            ox = o.x; oy = o.y; dx = d.x; dy = d.y;
+          }
+          s = tl.s0[k];
+          ray = tbase + k;
+          steps = 1;
+          act = true;
+          if (BATCH) {
+            item = titem;
+            const SceneDev& sc = batch.items[item].scene;
+            slot32 = sc.slot32;
+            slot64 = sc.slot64;
+            ntri = sc.ntri;
+          }
+          if (s < 0) {  // bad ray: out-of-range start, no exit edge, or failed validation
+            const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
+            io.prim[ray] = -3;
+            io.t[ray] = INFINITY;
+            io.steps[ray] = 0;
+            act = false;
+          }
+        }
+        served += take;
+        thead += take;
+      }
+    }
+    if (act) {
+      int word;
+      bool left = false;
+      if (MODE == 1) {
+        const int4 q = *reinterpret_cast<const int4*>(slot32 + s);
+        word = q.x;
+        if (word >= 0) {
+          const int sg = side32(r32, __int_as_float(q.y), __int_as_float(q.z));
+          if (sg != 0) {
+            left = sg > 0;
+          } else {
+            if (COUNT) ++c.fb32;
+            const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
+            const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
+            left = left_deferred<COUNT>(io.o, io.d, ray, v64, q.w, &c.fb64);
+          }
+        }
+      } else {
+        const double2 xy = *reinterpret_cast<const double2*>(slot64 + s);
+        word = *reinterpret_cast<const int*>(&slot64[s].word);
+        if (word >= 0) left = left64<COUNT>(ox, oy, dx, dy, xy.x, xy.y, c.fb64);
+      }
+      if (word >= 0 && steps < ntri) {
+        ++steps;
+        int e = (word & 3) + (left ? 1 : 2);
+        e = e >= 3 ? e - 3 : e;
+        s = 3 * (word >> 2) + e;
+      } else {
+        // terminate: constrained edge (hit), hull edge (miss) or the step guard
+        const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
+        int p;
+        double t = INFINITY;
+        if (word >= 0) {
+          p = -2;
+        } else if (word == -1) {
+          p = -1;
+        } else {
+          p = -word - 2;
+          const double4* prim = BATCH ? batch.items[item].scene.prim : sc_arg.prim;
+          const double4 g = prim[p];
+          if (MODE == 1) {
+            const double2 o = io.o[ray], d = io.d[ray];
+            t = hit_t(g, o.x, o.y, d.x, d.y);
+          } else {
+            t = hit_t(g, ox, oy, dx, dy);
+          }
+        }
+        io.prim[ray] = p;
+        io.t[ray] = t;
+        io.steps[ray] = steps;
+        if (COUNT) {
+          c.steps += steps;
+          ++c.rays;
+        }
+        act = false;
+      }
+    }
+  }
+  if (COUNT) {
+    if (c.steps) atomicAdd(&stats[0], (unsigned long long)c.steps);
+    if (c.fb32) atomicAdd(&stats[1], (unsigned long long)c.fb32);
+    if (c.fb64) atomicAdd(&stats[2], (unsigned long long)c.fb64);
+    if (c.rays) atomicAdd(&stats[3], (unsigned long long)c.rays);
+  }
+}
+
+__global__ void reset_counter(unsigned long long* counter) { *counter = 0ull; }
+
+// ------------------------------------------------------------------------------ launchers
+
+size_t walk_lds_bytes(int mode, const LaunchCfg& cfg) {
+  return (size_t)(cfg.wg / 64) * cfg.tile * (mode == 1 ? 20 : 36);
+}
+
+template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH>
+static hipError_t go(const SceneDev& sc, const RaysDev& io, ItemRef br, int64_t total_tiles,
+                     const LaunchCfg& cfg, size_t lds, unsigned long long* counter,
+                     const Workspace& ws, hipStream_t stream) {
+  hipLaunchKernelGGL((walk_persistent<MODE, TPL, COUNT, VALIDATE, BATCH>), dim3(cfg.grid),
+                     dim3(cfg.wg), lds, stream, sc, io, br, total_tiles, counter, cfg.refill_min,
+                     ws.stats, ws.errflag);
+  return hipGetLastError();
+}
+
+template <int MODE, bool COUNT, bool VALIDATE, bool BATCH>
+static hipError_t pick_tile(const SceneDev& sc, const RaysDev& io, ItemRef br, int64_t total_tiles,
+                            const LaunchCfg& cfg, size_t lds, unsigned long long* counter,
+                            const Workspace& ws, hipStream_t stream) {
+  switch (cfg.tile) {
+    case 64: return go<MODE, 1, COUNT, VALIDATE, BATCH>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
+    case 128: return go<MODE, 2, COUNT, VALIDATE, BATCH>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
+    case 256: return go<MODE, 4, COUNT, VALIDATE, BATCH>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
+                       const LaunchCfg& cfg, unsigned long long* counter, const Workspace& ws,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, stream, counter);
+  const size_t lds = walk_lds_bytes(mode, cfg);
+  const ItemRef none{nullptr, 0, nullptr, 0};
+#define CCSP_CASE(M, C, V) \
+  if (mode == M && count == C && validate == V) \
+    return pick_tile<M, C, V, false>(sc, io, none, 0, cfg, lds, counter, ws, stream);
+  CCSP_CASE(0, false, false) CCSP_CASE(0, true, false) CCSP_CASE(0, false, true) CCSP_CASE(0, true, true)
+  CCSP_CASE(1, false, false) CCSP_CASE(1, true, false) CCSP_CASE(1, false, true) CCSP_CASE(1, true, true)
+#undef CCSP_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t total_tiles,
+                             int mode, bool count, const LaunchCfg& cfg,
+                             unsigned long long* counter, const Workspace& ws, hipStream_t stream) {
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, stream, counter);
+  const int n_lds = n_items < 1024 ? n_items : 1024;
+  const size_t lds = walk_lds_bytes(mode, cfg) + (size_t)((n_lds + 1) & ~1) * 8;
+  const ItemRef br{items_dev, n_items, nullptr, n_lds};
+  const SceneDev nosc{};
+  const RaysDev noio{};
+  if (mode == 0 && !count) return pick_tile<0, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
+  if (mode == 0 && count) return pick_tile<0, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
+  if (mode == 1 && !count) return pick_tile<1, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
+  if (mode == 1 && count) return pick_tile<1, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ccsp

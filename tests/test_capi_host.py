@@ -1,0 +1,121 @@
+"""The C ABI library on the CPU: it loads, exports every declared symbol, and rejects bad
+arguments and malformed triangulations in host code before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2112_05570_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_match_header():
+    hdr = open(os.path.join(ROOT, "include", "ccsp_walk.h")).read()
+    declared = set(re.findall(r"^(?:int|void|const char \*)\s*\*?\s*(\w+)\(", hdr, re.M))
+    assert declared == set(B.EXPORTS), declared ^ set(B.EXPORTS)
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _desc(sc, **over):
+    arrs = dict(xy=np.ascontiguousarray(sc.xy), tri_v=sc.tri_v.copy(), tri_nbr=sc.tri_nbr.copy(),
+                tri_prim=sc.tri_prim.copy(), prims=np.ascontiguousarray(sc.prims))
+    arrs.update(over)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
+    d = B.TriangulationDesc(arrs["xy"].shape[0], p(arrs["xy"]), arrs["tri_v"].shape[0],
+                            p(arrs["tri_v"]), p(arrs["tri_nbr"]), p(arrs["tri_prim"]),
+                            arrs["prims"].shape[0], p(arrs["prims"]))
+    return d, arrs
+
+
+def _load_code(desc):
+    h = ctypes.c_void_p()
+    return B.raw_call("load_triangulation", ctypes.byref(desc), None, ctypes.byref(h))
+
+
+@pytest.mark.parametrize("what,needle", [
+    ("cw", "counter-clockwise"),
+    ("nbr_range", "neighbour out of range"),
+    ("asym", "symmetric|does not match"),
+    ("prim_mismatch", "primitive differs"),
+    ("prim_range", "primitive id out of range"),
+    ("not_collinear", "collinear"),
+    ("nan", "not finite"),
+    ("euler", "Euler"),
+    ("vid", "vertex id"),
+])
+def test_load_rejects_malformed(tiny_scene, what, needle):
+    sc = tiny_scene
+    tv, tn, tp, xy = sc.tri_v.copy(), sc.tri_nbr.copy(), sc.tri_prim.copy(), sc.xy.copy()
+    t = int(np.nonzero((tn >= 0).all(1) & (tp < 0).all(1))[0][0])
+    if what == "cw":
+        tv[t, [1, 2]] = tv[t, [2, 1]]
+    elif what == "nbr_range":
+        tn[t, 0] = 10**6
+    elif what == "asym":
+        tn[t, 0] = tn[t, 1]
+    elif what == "prim_mismatch":
+        # drop the constraint on one side of an interior constrained edge
+        tc, ic = map(int, np.argwhere((tp >= 0) & (tn >= 0))[0])
+        tp[tc, ic] = -1
+    elif what == "prim_range":
+        tp[t, 0] = 10**6
+    elif what == "not_collinear":
+        # mark an interior edge as constrained on both sides, but with a primitive it is not on
+        n = tn[t, 0]
+        back = int(np.nonzero(tn[n] == t)[0][0])
+        tp[t, 0] = 0
+        tp[n, back] = 0
+    elif what == "nan":
+        xy[7, 0] = np.nan
+    elif what == "euler":
+        n = tn[t, 0]
+        back = int(np.nonzero(tn[n] == t)[0][0])
+        tn[t, 0] = -1
+        tn[n, back] = -1
+    elif what == "vid":
+        tv[t, 0] = -5
+    desc, keep = _desc(sc, tri_v=tv, tri_nbr=tn, tri_prim=tp, xy=xy)
+    rc = _load_code(desc)
+    assert rc in (B.CCSP_E_BAD_TRIANGULATION, B.CCSP_E_ARG), rc
+    assert re.search(needle, B.last_error()), B.last_error()
+
+
+def test_load_rejects_sizes():
+    d = B.TriangulationDesc(2, None, 1, None, None, None, 0, None)
+    assert _load_code(d) == B.CCSP_E_ARG
+    d = B.TriangulationDesc(10, None, 1 << 29, None, None, None, 0, None)
+    assert _load_code(d) == B.CCSP_E_ARG
+    assert B.raw_call("load_triangulation", None, None, None) == B.CCSP_E_ARG
+
+
+def test_trace_argument_errors():
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: argument checks come first
+    z = ctypes.c_void_p(0)
+    al = ctypes.c_void_p(0x10000)
+    # null scene
+    assert B.raw_call("trace_rays", z, al, al, al, ctypes.c_int64(5), 1, al, al, al, z) == B.CCSP_E_ARG
+    # unknown mode and flags
+    assert B.raw_call("trace_rays", fake, al, al, al, ctypes.c_int64(5), 7, al, al, al, z) == B.CCSP_E_ARG
+    assert B.raw_call("trace_rays", fake, al, al, al, ctypes.c_int64(5), 1 | (1 << 12), al, al, al, z) == B.CCSP_E_ARG
+    # negative count, null and misaligned buffers
+    assert B.raw_call("trace_rays", fake, al, al, al, ctypes.c_int64(-1), 1, al, al, al, z) == B.CCSP_E_ARG
+    assert B.raw_call("trace_rays", fake, z, al, al, ctypes.c_int64(5), 1, al, al, al, z) == B.CCSP_E_ARG
+    mis = ctypes.c_void_p(0x10008)
+    assert B.raw_call("trace_rays", fake, mis, al, al, ctypes.c_int64(5), 1, al, al, al, z) == B.CCSP_E_ARG
+    assert "aligned" in B.last_error()
+    # an empty trace is a no-op
+    assert B.raw_call("trace_rays", fake, z, z, z, ctypes.c_int64(0), 1, z, z, z, z) == B.CCSP_OK
+
+
+def test_trace_batch_argument_errors():
+    assert B.raw_call("trace_batch", None, 3, 1, None, None) == B.CCSP_E_ARG
+    assert B.raw_call("trace_batch", None, -1, 1, None, None) == B.CCSP_E_ARG
+    item = B.TraceItem(None, 0x10000, 0x10000, 0x10000, 4, 0x10000, 0x10000, 0x10000)
+    arr = (B.TraceItem * 1)(item)
+    assert B.raw_call("trace_batch", arr, 1, 1, None, None) in (B.CCSP_E_ARG, B.CCSP_E_HIP)
+    assert B.raw_call("trace_batch", arr, 1, 1 | B.CCSP_TRACE_VALIDATE, None, None) == B.CCSP_E_ARG

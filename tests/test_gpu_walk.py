@@ -1,0 +1,246 @@
+"""GPU parity of the HIP walk against the checker (runs on an MI355X).
+
+hit_prim and steps must match bit for bit; hit_t is computed by the same fixed binary64 formula on
+both sides, so it is compared bit for bit as well (stricter than the 1e-12 / 1e-5 relative
+tolerances stated for the two precision modes). Both precision modes must give identical results.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ccsp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_05570_amd as m
+    return m
+
+
+DEV = "cuda:0"
+
+
+def _dev(r):
+    return (torch.from_numpy(np.ascontiguousarray(r.o)).to(DEV),
+            torch.from_numpy(np.ascontiguousarray(r.d)).to(DEV),
+            torch.from_numpy(np.ascontiguousarray(r.start)).to(DEV))
+
+
+def _host(res):
+    torch.cuda.synchronize()
+    return res.hit_prim.cpu().numpy(), res.hit_t.cpu().numpy(), res.steps.cpu().numpy()
+
+
+def _assert_same(got, ref, what=""):
+    p, t, s = got
+    rp, rt, rs = ref
+    bad = np.nonzero((p != rp) | (s != rs) | ~((t == rt) | (np.isinf(t) & np.isinf(rt))))[0]
+    assert bad.size == 0, (f"{what}: {bad.size} rays differ, first {bad[:5]}: "
+                           f"gpu {p[bad[:5]]}, {s[bad[:5]]}, {t[bad[:5]]} vs "
+                           f"ref {rp[bad[:5]]}, {rs[bad[:5]]}, {rt[bad[:5]]}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tiny_all_rays(ccsp, tiny_scene, tiny_rays, prec):
+    ref = oracle.walk(oracle.Triangulation.of(tiny_scene), tiny_rays.o, tiny_rays.d, tiny_rays.start)
+    with ccsp.Scene.from_arrays(tiny_scene) as scene:
+        got = _host(ccsp.trace(scene, *_dev(tiny_rays), precision=prec))
+    _assert_same(got, ref, prec)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 127, 4099])
+@pytest.mark.parametrize("tune", [(64, 64, 32, 1), (256, 128, 32, 16), (512, 256, 16, 64), (128, 64, 8, 32)])
+def test_ragged_and_launch_shapes(ccsp, tiny_scene, tiny_rays, n, tune):
+    r = tiny_rays.slice(0, n)
+    ref = oracle.walk(oracle.Triangulation.of(tiny_scene), r.o, r.d, r.start)
+    tp = ccsp.TuneParams(*tune)
+    with ccsp.Scene.from_arrays(tiny_scene) as scene:
+        for prec in ("fp32", "fp64"):
+            got = _host(ccsp.trace(scene, *_dev(r), precision=prec, tune=tp))
+            _assert_same(got, ref, f"{prec} n={n} tune={tune}")
+
+
+def test_empty_trace_is_noop(ccsp, tiny_scene):
+    e = torch.empty((0, 2), dtype=torch.float64, device=DEV)
+    s = torch.empty((0,), dtype=torch.int32, device=DEV)
+    with ccsp.Scene.from_arrays(tiny_scene) as scene:
+        res = ccsp.trace(scene, e, e, s)
+        torch.cuda.synchronize()
+    assert res.hit_prim.numel() == 0
+
+
+def test_bad_start_and_validation(ccsp, tiny_scene, tiny_rays):
+    r = tiny_rays.slice(0, 300)
+    start = r.start.copy()
+    start[5] = -1
+    start[17] = tiny_scene.n_triangles
+    start[31] = 2**31 - 1
+    with ccsp.Scene.from_arrays(tiny_scene) as scene:
+        o, d, _ = _dev(r)
+        st = torch.from_numpy(start).to(DEV)
+        for prec in ("fp32", "fp64"):
+            p, t, s = _host(ccsp.trace(scene, o, d, st, precision=prec))
+            assert (p[[5, 17, 31]] == ccsp.CCSP_RAY_BAD).all() and (s[[5, 17, 31]] == 0).all()
+            assert np.isinf(t[[5, 17, 31]]).all()
+            ok = np.ones(300, bool)
+            ok[[5, 17, 31]] = False
+            assert (p[ok] >= 0).all()
+        with pytest.raises(ccsp.CcspError) as ei:
+            ccsp.trace(scene, o, d, st, validate=True)
+        assert ei.value.code == ccsp.binding.CCSP_E_BAD_RAY
+        # a valid start triangle that does not contain the origin is caught too
+        wrong = torch.from_numpy(np.roll(r.start, 1)).to(DEV)
+        with pytest.raises(ccsp.CcspError):
+            ccsp.trace(scene, o, d, wrong, validate=True, precision="fp64")
+        # and valid rays pass validation with the same results
+        ref = oracle.walk(oracle.Triangulation.of(tiny_scene), r.o, r.d, r.start)
+        got = _host(ccsp.trace(scene, *_dev(r), validate=True))
+        _assert_same(got, ref, "validated")
+
+
+def _integer_scene(seed):
+    from helpers import degenerate_rays, integer_scene
+    rng = np.random.default_rng(seed)
+    sc = integer_scene(rng, 12)
+    o, d, start = degenerate_rays(sc, rng, 3000)
+    return sc, sg.Rays(o, d, start.astype(np.int32))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_degenerate_rays(ccsp, seed):
+    sc, r = _integer_scene(seed)
+    ref = oracle.walk(oracle.Triangulation.of(sc), r.o, r.d, r.start)
+    assert (ref[0] >= 0).all()
+    with ccsp.Scene.from_arrays(sc) as scene:
+        for prec in ("fp32", "fp64"):
+            ccsp.read_counters(reset=True)
+            got = _host(ccsp.trace(scene, *_dev(r), precision=prec, count=True))
+            _assert_same(got, ref, f"degenerate {prec}")
+            steps, fb32, fb64, rays = ccsp.read_counters(reset=True)
+            assert rays == r.n and steps == int(ref[2].sum())
+            assert fb64 > 0  # exact ties really reached the exact expansion
+
+
+@pytest.fixture(scope="module")
+def grid_pair():
+    sc = sg.make_scene("grid")
+    an, _ = sg.anneal_flips(sc, seed=0)
+    rays = sg.sample_rays(sc, sg.WORKLOADS["grid"]["rays"], seed=0)
+    start_an = sg.locate(an, rays.o)
+    keep = start_an >= 0
+    rays = rays.take(np.nonzero(keep)[0])
+    return sc, an, rays, start_an[keep].astype(np.int32)
+
+
+def test_grid_cdt_and_annealed(ccsp, grid_pair):
+    sc, an, rays, start_an = grid_pair
+    ra = sg.Rays(rays.o, rays.d, start_an)
+    ref_c = oracle.walk(oracle.Triangulation.of(sc), rays.o, rays.d, rays.start)
+    ref_a = oracle.walk(oracle.Triangulation.of(an), ra.o, ra.d, ra.start)
+    # the hit and its distance do not depend on the triangulation; the step count does
+    assert np.array_equal(ref_c[0], ref_a[0]) and np.array_equal(ref_c[1], ref_a[1])
+    assert ref_a[2].mean() < ref_c[2].mean()
+    for tri, r, ref in ((sc, rays, ref_c), (an, ra, ref_a)):
+        with ccsp.Scene.from_arrays(tri) as scene:
+            for prec in ("fp32", "fp64"):
+                _assert_same(_host(ccsp.trace(scene, *_dev(r), precision=prec)), ref, f"grid {prec}")
+
+
+def test_large_bench_configuration_sampled(ccsp):
+    """The 1M-segment scene and all 2^26 rays in the default launch: every ray checked for
+    agreement between the two modes and for valid outputs, a sample against the checker."""
+    sc = sg.make_scene("large")
+    rays = sg.sample_rays(sc, sg.WORKLOADS["large"]["rays"], seed=0)
+    idx = np.random.default_rng(7).choice(rays.n, 50_000, replace=False)
+    idx = np.concatenate([idx, np.arange(rays.n - 1000, rays.n)])  # and the ragged end
+    sub = rays.take(idx)
+    ref = oracle.walk(oracle.Triangulation.of(sc), sub.o, sub.d, sub.start)
+    with ccsp.Scene.from_arrays(sc) as scene:
+        o, d, st = _dev(rays)
+        del rays
+        r32 = ccsp.trace(scene, o, d, st, precision="fp32")
+        p32, t32, s32 = _host(r32)
+        _assert_same((p32[idx], t32[idx], s32[idx]), ref, "large fp32 sample")
+        assert (p32 >= 0).all() and (s32 >= 1).all() and np.isfinite(t32).all() and (t32 > 0).all()
+        del r32
+        r64 = ccsp.trace(scene, o, d, st, precision="fp64")
+        p64, t64, s64 = _host(r64)
+        assert np.array_equal(p32, p64) and np.array_equal(s32, s64) and np.array_equal(t32, t64)
+
+
+def _batch_scenes(k=6, max_seg=20000):
+    segs, nrays = sg.multi_sizes("batch", seed=0)
+    out = []
+    for i in range(k):
+        ns = int(min(segs[i], max_seg))
+        sc = sg.make_scene("batch", seed=0, n_seg=ns, index=i)
+        r = sg.sample_rays(sc, int(min(nrays[i], 100_000)) + 17 * i, seed=i + 1)
+        out.append((sc, r))
+    return out
+
+
+def test_batch_equals_single_and_graph_replays(ccsp):
+    data = _batch_scenes()
+    scenes = [ccsp.Scene.from_arrays(sc) for sc, _ in data]
+    try:
+        devr = [_dev(r) for _, r in data]
+        refs = []
+        for scene, (o, d, st) in zip(scenes, devr):
+            refs.append(_host(ccsp.trace(scene, o, d, st)))
+        # oracle on a sample of each item
+        for (sc, r), ref in zip(data, refs):
+            idx = np.arange(0, r.n, 97)
+            rr = oracle.walk(oracle.Triangulation.of(sc), r.o[idx], r.d[idx], r.start[idx])
+            _assert_same((ref[0][idx], ref[1][idx], ref[2][idx]), rr, "single vs checker")
+        for prec in ("fp32", "fp64"):
+            jobs = [(scene, *x) for scene, x in zip(scenes, devr)]
+            res = ccsp.trace_batch(jobs, precision=prec)
+            for k, rs in enumerate(res):
+                _assert_same(_host(rs), refs[k], f"batch {prec} item {k}")
+        # graph path: replay with changing item order and contents; every replay is checked
+        for rep in range(4):
+            order = np.random.default_rng(rep).permutation(len(scenes))
+            jobs = [(scenes[k], *devr[k]) for k in order]
+            res = ccsp.trace_batch(jobs, precision="fp32", graph=True)
+            torch.cuda.synchronize()
+            for k, rs in zip(order, res):
+                _assert_same(_host(rs), refs[k], f"graph replay {rep} item {k}")
+            # eager work between replays
+            _assert_same(_host(ccsp.trace(scenes[0], *devr[0])), refs[0], "eager between replays")
+    finally:
+        for s in scenes:
+            s.free()
+
+
+def test_batch_with_empty_and_tiny_items(ccsp, tiny_scene, tiny_rays):
+    with ccsp.Scene.from_arrays(tiny_scene) as scene:
+        parts = [tiny_rays.slice(0, 0), tiny_rays.slice(0, 1), tiny_rays.slice(1, 130),
+                 tiny_rays.slice(130, 130), tiny_rays.slice(130, 5000)]
+        jobs = [(scene, *_dev(p)) for p in parts]
+        res = ccsp.trace_batch(jobs, precision="fp64")
+        for p, rs in zip(parts, res):
+            ref = oracle.walk(oracle.Triangulation.of(tiny_scene), p.o, p.d, p.start)
+            _assert_same(_host(rs), ref, f"batch part n={p.n}")
+
+
+def test_concurrent_streams(ccsp, tiny_scene, tiny_rays):
+    ref = oracle.walk(oracle.Triangulation.of(tiny_scene), tiny_rays.o, tiny_rays.d, tiny_rays.start)
+    with ccsp.Scene.from_arrays(tiny_scene) as scene:
+        o, d, st = _dev(tiny_rays)
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s1):
+            a = ccsp.trace(scene, o, d, st, stream=s1)
+        with torch.cuda.stream(s2):
+            b = ccsp.trace(scene, o, d, st, stream=s2, precision="fp64")
+        torch.cuda.synchronize()
+        _assert_same(_host(a), ref, "stream 1")
+        _assert_same(_host(b), ref, "stream 2")
