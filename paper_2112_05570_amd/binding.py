@@ -13,6 +13,11 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libccsp_walk.so")
 
+# The library must bind to the HIP runtime that owns the caller's device memory and streams.
+# PyTorch ships its own libamdhip64; loading it first makes the dynamic linker resolve the
+# library's libamdhip64.so.7 dependency to that already-loaded runtime instead of a second copy.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                       "(the walk has no non-HIP implementation)")
