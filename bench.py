@@ -37,7 +37,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the checker leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune", default="", help="wg,tile,waves_per_cu,refill_min")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (for scaling HBM "
+                         "counters of a profiler run)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -151,6 +157,19 @@ def main():
     scene.free()
 
 
+def copy_calibration(mib):
+    """A plain copy of known size: the profiler's FETCH_SIZE / WRITE_SIZE for it give the
+    counters' scale (bytes counted per byte moved)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+
+
 def cpu_leg(sc, rays, budget_s):
     """The checker's walk, as it stands, on the host cores: a bounded prefix of the same rays."""
     import numpy as np
@@ -159,10 +178,14 @@ def cpu_leg(sc, rays, budget_s):
 
     tri = oracle.Triangulation.of(sc)
     threads = oracle.num_threads()
-    m = 4096
-    t = time.perf_counter()
-    oracle.walk(tri, rays.o[:m], rays.d[:m], rays.start[:m], threads)
-    dt = max(time.perf_counter() - t, 1e-3)
+    m = 1 << 14
+    while True:  # calibrate on growing prefixes until a run takes at least a second
+        t = time.perf_counter()
+        oracle.walk(tri, rays.o[:m], rays.d[:m], rays.start[:m], threads)
+        dt = time.perf_counter() - t
+        if dt >= 1.0 or m >= rays.n:
+            break
+        m = min(rays.n, m * 4)
     m = int(min(rays.n, max(m, m * budget_s / dt)))
     t = time.perf_counter()
     _, _, s = oracle.walk(tri, rays.o[:m], rays.d[:m], rays.start[:m], threads)

@@ -125,8 +125,8 @@ LaunchCfg make_cfg(const DeviceState& ds, int mode, const TuneParams* tp) {
   LaunchCfg c{};
   c.wg = (tp && tp->wg_size) ? tp->wg_size : 256;
   c.tile = (tp && tp->tile_rays) ? tp->tile_rays : (mode == 1 ? 64 : 64);
-  const int wpcu = (tp && tp->waves_per_cu) ? tp->waves_per_cu : 32;
-  c.refill_min = (tp && tp->refill_min) ? tp->refill_min : 16;
+  const int wpcu = (tp && tp->waves_per_cu) ? tp->waves_per_cu : 16;
+  c.refill_min = (tp && tp->refill_min) ? tp->refill_min : 32;
   c.grid = std::max(1, ds.cus * wpcu / (c.wg / 64));
   return c;
 }

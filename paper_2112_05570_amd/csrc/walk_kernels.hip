@@ -366,9 +366,12 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
       bool left = false;
       if (MODE == 1) {
         const int4 q = *reinterpret_cast<const int4*>(slot32 + s);
+        // Keep the slot one 16-byte load: without this the compiler loads the exit word alone,
+        // branches on it and only then loads the vertex, a second dependent round trip per step.
+        __asm__ volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
         word = q.x;
+        const int sg = side32(r32, __int_as_float(q.y), __int_as_float(q.z));
         if (word >= 0) {
-          const int sg = side32(r32, __int_as_float(q.y), __int_as_float(q.z));
           if (sg != 0) {
             left = sg > 0;
           } else {
@@ -380,7 +383,9 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         }
       } else {
         const double2 xy = *reinterpret_cast<const double2*>(slot64 + s);
-        word = *reinterpret_cast<const int*>(&slot64[s].word);
+        const int wd = *reinterpret_cast<const int*>(&slot64[s].word);
+        __asm__ volatile("" ::"v"(xy.x), "v"(xy.y), "v"(wd));
+        word = wd;
         if (word >= 0) left = left64<COUNT>(ox, oy, dx, dy, xy.x, xy.y, c.fb64);
       }
       if (word >= 0 && steps < ntri) {
