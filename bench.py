@@ -99,6 +99,16 @@ def main():
     log(f"[bench] fp32 walk: {args.steps} steps in {wall32:.3f}s")
     wall64, k64 = timed("fp64", out64, max(1, args.steps // 2), 1)
     log(f"[bench] fp64 walk: {len(k64)} steps in {wall64:.3f}s")
+    # the same walk without ray binning (rays walked in input order), for comparison
+    for _ in range(1):
+        ccsp.trace(scene, o, d, st, precision="fp32", out=out64, tune=tune, input_order=True)
+    torch.cuda.synchronize()
+    t_io = time.perf_counter()
+    k_io = max(1, args.steps // 2)
+    for _ in range(k_io):
+        ccsp.trace(scene, o, d, st, precision="fp32", out=out64, tune=tune, input_order=True)
+    torch.cuda.synchronize()
+    ms_io = (time.perf_counter() - t_io) / k_io * 1e3
 
     # diagnostics outside the timed region
     steps_total = int(out32.steps.sum(dtype=torch.int64).item())
@@ -143,6 +153,7 @@ def main():
         "mean_steps_per_ray": steps_total / n,
         "fp64": {"rays_per_s": n * len(k64) / wall64, "ms_per_step": wall64 / len(k64) * 1e3,
                  "steps_per_s": steps_total * len(k64) / wall64},
+        "fp32_input_order_ms_per_step": ms_io,
         "fp32_equals_fp64": same,
         "fallback": {"fp32_to_fp64_per_step": c_fb32 / max(1, c_steps),
                      "fp64_to_exact_per_step": c_fb64 / max(1, c_steps)},

@@ -73,7 +73,9 @@ enum {
   CCSP_TRACE_MODE_MASK = 0xff,
   CCSP_TRACE_VALIDATE = 1 << 8, /* check every ray's precondition exactly; synchronises the
                                    stream and returns CCSP_E_BAD_RAY if any ray fails it */
-  CCSP_TRACE_COUNT = 1 << 9     /* accumulate the counters read by read_counters() */
+  CCSP_TRACE_COUNT = 1 << 9,    /* accumulate the counters read by read_counters() */
+  CCSP_TRACE_INPUT_ORDER = 1 << 10 /* walk rays in input order; by default a trace of at least
+                                      65,536 rays first bins them by start triangle (see below) */
 };
 
 typedef struct Triangulation Triangulation; /* opaque; owns its device memory */
@@ -114,8 +116,13 @@ int load_triangulation(const TriangulationDesc *desc, void *stream, Triangulatio
  * trace_rays: walk n rays through one triangulation. All array arguments are DEVICE pointers
  * owned by the caller: o_xy and d_xy hold n interleaved (x,y) binary64 pairs (16-byte aligned),
  * start_tri n triangle ids; the outputs hit_prim, hit_t (8-byte aligned) and steps receive n
- * values each. d must be nonzero and the origin strictly inside start_tri. No allocation; the
- * call is asynchronous on `stream` (except with CCSP_TRACE_VALIDATE).
+ * values each. d must be nonzero and the origin strictly inside start_tri. The call is
+ * asynchronous on `stream` (except with CCSP_TRACE_VALIDATE).
+ * Ray binning: unless CCSP_TRACE_INPUT_ORDER is set, n >= 65,536 rays are first sorted by a
+ * spatial key of their start triangle (the result does not depend on it; only the order in which
+ * rays are walked, hence cache reuse, does). It uses per-device scratch of about 16 bytes per ray,
+ * allocated on the first trace larger than any before unless reserve_workspace() reserved it;
+ * binned traces on different streams of one device are serialised on the device.
  */
 int trace_rays(const Triangulation *tri, const double *o_xy, const double *d_xy,
                const int32_t *start_tri, int64_t n, int precision, int32_t *hit_prim,
@@ -147,6 +154,10 @@ typedef struct {
  */
 int trace_batch(const TraceItem *items, int32_t n_items, int precision, const TuneParams *tune,
                 void *stream);
+
+/* reserve_workspace: reserve the ray binning scratch for traces of up to max_rays rays on the
+ * current device, so that later traces allocate nothing. */
+int reserve_workspace(int64_t max_rays);
 
 /* free_triangulation: release the device copy (synchronises the device first). NULL is a no-op. */
 void free_triangulation(Triangulation *tri);

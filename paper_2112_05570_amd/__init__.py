@@ -13,8 +13,8 @@ import numpy as np
 
 from . import binding as B
 from .binding import (CCSP_RAY_BAD, CCSP_RAY_GUARD, CCSP_RAY_MISS, CCSP_TRACE_COUNT,
-                      CCSP_TRACE_FP32_FILTERED, CCSP_TRACE_FP64, CCSP_TRACE_VALIDATE, CcspError,
-                      TuneParams)
+                      CCSP_TRACE_FP32_FILTERED, CCSP_TRACE_FP64, CCSP_TRACE_INPUT_ORDER,
+                      CCSP_TRACE_VALIDATE, CcspError, TuneParams, reserve_workspace)
 
 PRECISION = {"fp64": CCSP_TRACE_FP64, "fp32": CCSP_TRACE_FP32_FILTERED}
 
@@ -98,11 +98,14 @@ def _check_rays(o, d, start):
 
 
 def trace(scene: Scene, o, d, start, precision="fp32", out: Result | None = None, stream=None,
-          tune: TuneParams | None = None, validate=False, count=False) -> Result:
-    """Walk rays (o, d: (n,2) float64; start: (n,) int32 CUDA tensors). Asynchronous."""
+          tune: TuneParams | None = None, validate=False, count=False,
+          input_order=False) -> Result:
+    """Walk rays (o, d: (n,2) float64; start: (n,) int32 CUDA tensors). Asynchronous.
+    input_order=True walks the rays in the given order instead of binning them spatially."""
     n = _check_rays(o, d, start)
     res = _outputs(n, o.device, out)
-    mode = _mode(precision) | (CCSP_TRACE_VALIDATE if validate else 0) | (CCSP_TRACE_COUNT if count else 0)
+    mode = (_mode(precision) | (CCSP_TRACE_VALIDATE if validate else 0)
+            | (CCSP_TRACE_COUNT if count else 0) | (CCSP_TRACE_INPUT_ORDER if input_order else 0))
     B.trace_rays_tuned(scene.handle, o.data_ptr(), d.data_ptr(), start.data_ptr(), n, mode,
                        res.hit_prim.data_ptr(), res.hit_t.data_ptr(), res.steps.data_ptr(), tune,
                        _stream(stream))

@@ -37,9 +37,11 @@ CCSP_TRACE_FP64 = 0
 CCSP_TRACE_FP32_FILTERED = 1
 CCSP_TRACE_VALIDATE = 1 << 8
 CCSP_TRACE_COUNT = 1 << 9
+CCSP_TRACE_INPUT_ORDER = 1 << 10
 
 EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch",
-           "free_triangulation", "last_error", "read_counters", "triangulation_info")
+           "free_triangulation", "last_error", "read_counters", "triangulation_info",
+           "reserve_workspace")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -81,6 +83,8 @@ _lib.read_counters.argtypes = [ctypes.POINTER(ctypes.c_uint64 * 4), _I]
 _lib.read_counters.restype = _I
 _lib.triangulation_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64 * 4)]
 _lib.triangulation_info.restype = _I
+_lib.reserve_workspace.argtypes = [_I64]
+_lib.reserve_workspace.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -139,6 +143,10 @@ def triangulation_info(tri: int) -> list:
     out = (ctypes.c_int64 * 4)()
     _check(_lib.triangulation_info(_P(tri), ctypes.byref(out)))
     return list(out)
+
+
+def reserve_workspace(max_rays: int) -> None:
+    _check(_lib.reserve_workspace(max_rays))
 
 
 def raw_call(name: str, *args):

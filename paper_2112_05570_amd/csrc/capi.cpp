@@ -77,6 +77,25 @@ int orient_host(const double* a, const double* b, const double* c) {
   return orient_exact(a[0], a[1], b[0], b[1], c[0], c[1]);
 }
 
+// Position of (x, y) along the Hilbert curve of a 2^16 x 2^16 grid.
+uint32_t hilbert16(uint32_t x, uint32_t y) {
+  uint32_t d = 0;
+  for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+    d += s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = 0xffffu - x;
+        y = 0xffffu - y;
+      }
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
+}
+
 struct DeviceState {
   bool init = false;
   int cus = 0;
@@ -89,6 +108,12 @@ struct DeviceState {
   int items_cap = 0;
   hipEvent_t staging_free = nullptr;
   std::unordered_map<uint64_t, hipGraphExec_t> graphs;
+  // ray binning scratch, shared by the traces on this device
+  std::mutex bin_mu;
+  void* bin_ws = nullptr;
+  size_t bin_ws_bytes = 0;
+  hipEvent_t bin_free = nullptr;
+  hipStream_t bin_last_stream = nullptr;
 };
 
 std::mutex g_dev_mu;
@@ -114,10 +139,32 @@ int device_state(DeviceState** out) {
     s.ws.stats = s.ws.counters + kCounterSlots;
     s.ws.errflag = reinterpret_cast<int*>(s.ws.stats + 4);
     e = hipEventCreateWithFlags(&s.staging_free, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.bin_free, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     s.init = true;
   }
   *out = &s;
+  return CCSP_OK;
+}
+
+constexpr int64_t kBinMinRays = 1 << 16;
+
+// Grow the per-device ray binning scratch to hold n rays (allocates only when n exceeds every
+// earlier size; reserve_workspace() does it ahead of time). Caller holds ds->bin_mu.
+int grow_bin_workspace(DeviceState* ds, int64_t n) {
+  const size_t need = bin_workspace_bytes(n);
+  if (need <= ds->bin_ws_bytes) return CCSP_OK;
+  hipError_t e;
+  if (ds->bin_ws) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    (void)hipFree(ds->bin_ws);
+    ds->bin_ws = nullptr;
+    ds->bin_ws_bytes = 0;
+  }
+  e = hipMalloc(&ds->bin_ws, need);
+  if (e != hipSuccess) return fail(CCSP_E_OOM, "ray binning scratch of %zu bytes: %s", need, hipGetErrorString(e));
+  ds->bin_ws_bytes = need;
   return CCSP_OK;
 }
 
@@ -227,7 +274,9 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
     return fail(CCSP_E_BAD_TRIANGULATION, "Euler characteristic V - E + T = %lld, expected 1 (one disk)",
                 (long long)(vused - E + T));
 
-  // ---- packing
+  // ---- packing. Internal triangle order: Hilbert order of the centroids, so that ids close
+  // together are triangles close together (neighbouring steps share cache lines and pages, and
+  // an id range is a compact region for ray binning).
   double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
   for (int64_t i = 0; i < V; ++i)
     for (int k = 0; k < 2; ++k) {
@@ -235,6 +284,45 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
       hi[k] = std::max(hi[k], xy[2 * i + k]);
     }
   const double org[2] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1])};
+  std::vector<uint64_t> hkey(T);
+  {
+    const double span = std::max(hi[0] - lo[0], hi[1] - lo[1]);
+    const double sc = span > 0 ? 65535.0 / span : 0.0;
+    parallel_for(T, [&](int64_t a, int64_t b) {
+      for (int64_t t = a; t < b; ++t) {
+        double cx = 0, cy = 0;
+        for (int i = 0; i < 3; ++i) {
+          cx += xy[2 * (int64_t)tv[3 * t + i]];
+          cy += xy[2 * (int64_t)tv[3 * t + i] + 1];
+        }
+        const uint32_t gx = (uint32_t)std::min(65535.0, std::max(0.0, (cx / 3.0 - lo[0]) * sc));
+        const uint32_t gy = (uint32_t)std::min(65535.0, std::max(0.0, (cy / 3.0 - lo[1]) * sc));
+        hkey[t] = ((uint64_t)hilbert16(gx, gy) << 32) | (uint64_t)t;
+      }
+    });
+    std::sort(hkey.begin(), hkey.end());
+  }
+  std::vector<int32_t> new_of(T);
+  for (int64_t r = 0; r < T; ++r) new_of[(int64_t)(hkey[r] & 0xffffffffu)] = (int32_t)r;
+  // primitives in the order their edges are met along the triangle order, so that the record a
+  // hit reads is near the records of nearby hits
+  std::vector<int32_t> prim_new(P, -1), prim_old;
+  prim_old.reserve(P);
+  for (int64_t r = 0; r < T; ++r) {
+    const int64_t t = (int64_t)(hkey[r] & 0xffffffffu);
+    for (int i = 0; i < 3; ++i) {
+      const int32_t pr = tp[3 * t + i];
+      if (pr >= 0 && prim_new[pr] < 0) {
+        prim_new[pr] = (int32_t)prim_old.size();
+        prim_old.push_back(pr);
+      }
+    }
+  }
+  for (int64_t k = 0; k < P; ++k)
+    if (prim_new[k] < 0) {
+      prim_new[k] = (int32_t)prim_old.size();
+      prim_old.push_back((int32_t)k);
+    }
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t off_s32 = 0;
   const size_t off_s64 = align(off_s32 + sizeof(Slot32) * 3 * T);
@@ -242,35 +330,46 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   const size_t off_tv = align(off_txy + sizeof(TriXY32) * T);
   const size_t off_v = align(off_tv + sizeof(int4) * T);
   const size_t off_p = align(off_v + sizeof(double2) * V);
-  const size_t total = align(off_p + sizeof(double4) * std::max<int64_t>(P, 1));
+  const size_t off_perm = align(off_p + sizeof(PrimRec) * std::max<int64_t>(P, 1));
+  const size_t total = align(off_perm + sizeof(int32_t) * T);
   std::vector<unsigned char> host(total, 0);
   auto* s32 = reinterpret_cast<Slot32*>(host.data() + off_s32);
   auto* s64 = reinterpret_cast<Slot64*>(host.data() + off_s64);
   auto* txy = reinterpret_cast<TriXY32*>(host.data() + off_txy);
   auto* t4 = reinterpret_cast<int4*>(host.data() + off_tv);
   std::memcpy(host.data() + off_v, xy, sizeof(double) * 2 * V);
-  if (P > 0) std::memcpy(host.data() + off_p, ps, sizeof(double) * 4 * P);
+  auto* prec = reinterpret_cast<PrimRec*>(host.data() + off_p);
+  for (int64_t k = 0; k < P; ++k) {
+    const int32_t old = prim_old[k];
+    prec[k].ax = ps[4 * (int64_t)old];
+    prec[k].ay = ps[4 * (int64_t)old + 1];
+    prec[k].bx = ps[4 * (int64_t)old + 2];
+    prec[k].by = ps[4 * (int64_t)old + 3];
+    prec[k].id = old;
+  }
+  std::memcpy(host.data() + off_perm, new_of.data(), sizeof(int32_t) * T);
   parallel_for(T, [&](int64_t a, int64_t b) {
-    for (int64_t t = a; t < b; ++t) {
+    for (int64_t nt = a; nt < b; ++nt) {
+      const int64_t t = (int64_t)(hkey[nt] & 0xffffffffu);  // caller's id of internal triangle nt
       const int32_t* v = tv + 3 * t;
-      t4[t] = make_int4(v[0], v[1], v[2], 0);
+      t4[nt] = make_int4(v[0], v[1], v[2], 0);
       for (int i = 0; i < 3; ++i) {
-        txy[t].x[i] = (float)(xy[2 * (int64_t)v[i]] - org[0]);
-        txy[t].y[i] = (float)(xy[2 * (int64_t)v[i] + 1] - org[1]);
+        txy[nt].x[i] = (float)(xy[2 * (int64_t)v[i]] - org[0]);
+        txy[nt].y[i] = (float)(xy[2 * (int64_t)v[i] + 1] - org[1]);
       }
       for (int i = 0; i < 3; ++i) {
-        const int64_t k = 3 * t + i;
-        const int32_t n = tn[k], pr = tp[k];
+        const int64_t k = 3 * nt + i;
+        const int32_t n = tn[3 * t + i], pr = tp[3 * t + i];
         int32_t word, vid = 0;
         if (pr >= 0) {
-          word = -(pr + 2);
+          word = -(prim_new[pr] + 2);
         } else if (n < 0) {
           word = -1;
         } else {
           int back = 0;
           for (int j = 0; j < 3; ++j)
             if (tn[3 * (int64_t)n + j] == t) back = j;
-          word = (n << 2) | back;
+          word = (new_of[n] << 2) | back;
           vid = tv[3 * (int64_t)n + back];
         }
         const double vx = xy[2 * (int64_t)vid], vy = xy[2 * (int64_t)vid + 1];
@@ -315,7 +414,8 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   tri->dev.trixy = reinterpret_cast<const TriXY32*>(base + off_txy);
   tri->dev.triv = reinterpret_cast<const int4*>(base + off_tv);
   tri->dev.v64 = reinterpret_cast<const double2*>(base + off_v);
-  tri->dev.prim = reinterpret_cast<const double4*>(base + off_p);
+  tri->dev.prim = reinterpret_cast<const PrimRec*>(base + off_p);
+  tri->dev.perm = reinterpret_cast<const int32_t*>(base + off_perm);
   tri->dev.org_x = org[0];
   tri->dev.org_y = org[1];
   tri->dev.ntri = (int32_t)T;
@@ -362,7 +462,7 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
   const int mode = precision & CCSP_TRACE_MODE_MASK;
   if (mode != CCSP_TRACE_FP64 && mode != CCSP_TRACE_FP32_FILTERED)
     return fail(CCSP_E_ARG, "unknown precision mode %d", mode);
-  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_VALIDATE | CCSP_TRACE_COUNT))
+  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_VALIDATE | CCSP_TRACE_COUNT | CCSP_TRACE_INPUT_ORDER))
     return fail(CCSP_E_ARG, "unknown precision flags 0x%x", precision);
   int rc = check_rays(o_xy, d_xy, start_tri, n, hit_prim, hit_t, steps);
   if (rc || n == 0) return rc;
@@ -376,15 +476,36 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
   const bool count = precision & CCSP_TRACE_COUNT;
   hipStream_t st = static_cast<hipStream_t>(stream);
   RaysDev io{reinterpret_cast<const double2*>(o_xy), reinterpret_cast<const double2*>(d_xy),
-             start_tri, hit_prim, hit_t, steps, n};
+             start_tri, hit_prim, hit_t, steps, n, nullptr};
   unsigned long long* counter = ds->ws.counters + (ds->next_counter.fetch_add(1) % kCounterSlots);
   hipError_t e;
+  const bool bin = !(precision & CCSP_TRACE_INPUT_ORDER) && n >= kBinMinRays && n < INT32_MAX;
+  std::unique_lock<std::mutex> bin_lock(ds->bin_mu, std::defer_lock);
+  if (bin) {
+    bin_lock.lock();
+    rc = grow_bin_workspace(ds, n);
+    if (rc) return rc;
+    // the shared scratch may still be in use by a trace on another stream
+    if (ds->bin_last_stream != st) {
+      e = hipStreamWaitEvent(st, ds->bin_free, 0);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    }
+    e = launch_bin_rays(tri->dev, start_tri, n, ds->bin_ws, ds->bin_ws_bytes, &io.order,
+                        &io.order_start, st);
+    if (e != hipSuccess) return hip_fail(e, "ray binning");
+  }
   if (validate) {
     e = hipMemsetAsync(ds->ws.errflag, 0, sizeof(int), st);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
   }
   e = launch_walk(tri->dev, io, mode, count, validate, cfg, counter, ds->ws, st);
   if (e != hipSuccess) return hip_fail(e, "walk launch");
+  if (bin) {
+    e = hipEventRecord(ds->bin_free, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ds->bin_last_stream = st;
+    bin_lock.unlock();
+  }
   if (validate) {
     int flag = 0;
     e = hipMemcpyAsync(&flag, ds->ws.errflag, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -502,6 +623,16 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
   e = hipEventRecord(ds->staging_free, st);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   return CCSP_OK;
+}
+
+int reserve_workspace(int64_t max_rays) {
+  g_err.clear();
+  if (max_rays < 0 || max_rays >= INT32_MAX) return fail(CCSP_E_ARG, "max_rays out of range");
+  DeviceState* ds = nullptr;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ds->bin_mu);
+  return grow_bin_workspace(ds, max_rays);
 }
 
 int read_counters(uint64_t out[4], int reset) {

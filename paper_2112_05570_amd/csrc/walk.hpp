@@ -28,13 +28,21 @@ struct alignas(32) TriXY32 {  // own vertices of a triangle in binary32 (first s
   float pad[2];
 };
 
+// A primitive in internal order: its segment (t is computed from it) and the caller's id.
+struct alignas(16) PrimRec {
+  double ax, ay, bx, by;
+  int32_t id;
+  int32_t pad[3];
+};
+
 struct SceneDev {
   const Slot32* slot32;  // 3T
   const Slot64* slot64;  // 3T
   const TriXY32* trixy;  // T
   const int4* triv;      // T: v0, v1, v2, 0
   const double2* v64;    // V
-  const double4* prim;   // P: ax, ay, bx, by
+  const PrimRec* prim;   // P, internal order (first met along the Hilbert order of triangles)
+  const int32_t* perm;   // T: caller's triangle id -> internal (Hilbert-ordered) id
   double org_x, org_y;   // origin of the binary32 coordinates
   int32_t ntri;
   int32_t pad;
@@ -48,6 +56,8 @@ struct RaysDev {
   double* t;
   int32_t* steps;
   int64_t n;
+  const int32_t* order;        // optional processing order (a permutation of 0..n-1), or null
+  const int32_t* order_start;  // with `order`: internal start triangle of each ray in that order
 };
 
 // One item of a batched launch: the scene, its rays and where its tiles start in the
@@ -72,6 +82,13 @@ struct Workspace {
   int* errflag;                  // set by validating launches
 };
 constexpr int kCounterSlots = 4096;
+
+// Spatial binning of rays: order[] = ray indices sorted by the internal (Hilbert-ordered) id of
+// their start triangle, which order_start[] holds. Needs bin_workspace_bytes(n) of scratch.
+size_t bin_workspace_bytes(int64_t n);
+hipError_t launch_bin_rays(const SceneDev& sc, const int32_t* start, int64_t n, void* workspace,
+                           size_t ws_bytes, const int32_t** order_out,
+                           const int32_t** order_start_out, hipStream_t stream);
 
 hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
                        const LaunchCfg& cfg, unsigned long long* counter, const Workspace& ws,

@@ -73,12 +73,11 @@ struct Counters {
   unsigned steps = 0, fb32 = 0, fb64 = 0, rays = 0;
 };
 
-// binary32 decision deferred to binary64: the ray is re-read from its (caller-owned) arrays.
+// binary32 decision deferred to binary64 (out of line: rare).
 template <bool COUNT>
-__device__ __attribute__((noinline)) bool left_deferred(const double2* o_arr, const double2* d_arr,
-                                                        int64_t ray, const double2* v64, int vid,
-                                                        unsigned* n_exact) {
-  const double2 o = o_arr[ray], d = d_arr[ray], v = v64[vid];
+__device__ __attribute__((noinline)) bool left_deferred(double2 o, double2 d, const double2* v64,
+                                                        int vid, unsigned* n_exact) {
+  const double2 v = v64[vid];
   unsigned n = 0;
   const bool l = left64<COUNT>(o.x, o.y, d.x, d.y, v.x, v.y, n);
   if (COUNT) *n_exact += n;
@@ -102,16 +101,16 @@ __device__ __attribute__((noinline)) bool validate_ray(const SceneDev& sc, doubl
 // or (VALIDATE) the origin is not strictly inside / the direction is zero or not finite.
 // The exit edge i is the one whose first endpoint is RIGHT of the ray and second LEFT.
 template <bool COUNT>
-__device__ __forceinline__ int first_exit32(const SceneDev& sc, const RaysDev& io, int64_t ray,
+__device__ __forceinline__ int first_exit32(const SceneDev& sc, double2 o, double2 d,
                                             const Ray32& r, int st, Counters& c) {
   const float4* p = reinterpret_cast<const float4*>(sc.trixy + st);
   const float4 a = p[0], b = p[1];
   int s0 = side32(r, a.x, a.w), s1 = side32(r, a.y, b.x), s2 = side32(r, a.z, b.y);
   if ((s0 == 0) | (s1 == 0) | (s2 == 0)) {
     const int4 tv = sc.triv[st];
-    if (s0 == 0) { if (COUNT) ++c.fb32; s0 = left_deferred<COUNT>(io.o, io.d, ray, sc.v64, tv.x, &c.fb64) ? 1 : -1; }
-    if (s1 == 0) { if (COUNT) ++c.fb32; s1 = left_deferred<COUNT>(io.o, io.d, ray, sc.v64, tv.y, &c.fb64) ? 1 : -1; }
-    if (s2 == 0) { if (COUNT) ++c.fb32; s2 = left_deferred<COUNT>(io.o, io.d, ray, sc.v64, tv.z, &c.fb64) ? 1 : -1; }
+    if (s0 == 0) { if (COUNT) ++c.fb32; s0 = left_deferred<COUNT>(o, d, sc.v64, tv.x, &c.fb64) ? 1 : -1; }
+    if (s1 == 0) { if (COUNT) ++c.fb32; s1 = left_deferred<COUNT>(o, d, sc.v64, tv.y, &c.fb64) ? 1 : -1; }
+    if (s2 == 0) { if (COUNT) ++c.fb32; s2 = left_deferred<COUNT>(o, d, sc.v64, tv.z, &c.fb64) ? 1 : -1; }
   }
   const bool L0 = s0 > 0, L1 = s1 > 0, L2 = s2 > 0;
   const int e = (!L1 && L2) ? 0 : ((!L2 && L0) ? 1 : ((!L0 && L1) ? 2 : -1));
@@ -159,64 +158,63 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Per-wave LDS tile. binary32 mode: the rounded ray (float4) and the first exit slot, 20 B/ray;
-// binary64 mode: the ray (2 x double2) and the first exit slot, 36 B/ray.
-template <int MODE, int TILE>
+// Per-wave LDS tile: the ray (2 x double2), its first exit slot and its index, 40 B/ray.
+template <int TILE>
 struct Tile {
-  static constexpr int kBytes = MODE == 1 ? 20 * TILE : 36 * TILE;
-  float4* r32;
+  static constexpr int kBytes = 40 * TILE;
   double2* o;
   double2* d;
   int* s0;
-  __device__ explicit Tile(unsigned char* base) {
-    if (MODE == 1) {
-      r32 = reinterpret_cast<float4*>(base);
-      o = d = nullptr;
-      s0 = reinterpret_cast<int*>(base + 16 * TILE);
-    } else {
-      r32 = nullptr;
-      o = reinterpret_cast<double2*>(base);
-      d = reinterpret_cast<double2*>(base + 16 * TILE);
-      s0 = reinterpret_cast<int*>(base + 32 * TILE);
-    }
-  }
+  int* idx;
+  __device__ explicit Tile(unsigned char* base)
+      : o(reinterpret_cast<double2*>(base)),
+        d(reinterpret_cast<double2*>(base + 16 * TILE)),
+        s0(reinterpret_cast<int*>(base + 32 * TILE)),
+        idx(reinterpret_cast<int*>(base + 36 * TILE)) {}
 };
 
 // Load rays [base, base+len) of `io` into the tile and compute their first exit slots.
 template <int MODE, int TPL, bool COUNT, bool VALIDATE>
 __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, int len,
-                          const Tile<MODE, TPL * 64>& tl, int lane, Counters& c, int* errflag) {
-  // phase 1: all loads of the tile in flight together, rays rounded on arrival
+                          const Tile<TPL * 64>& tl, int lane, Counters& c, int* errflag) {
+  // phase 1: all loads of the tile in flight together
   int st[TPL];
-  float4 r[TPL];
+  int64_t ri[TPL];
   double2 o[TPL], d[TPL];
 #pragma unroll
   for (int q = 0; q < TPL; ++q) {
     const int k = lane + 64 * q;
     st[q] = -1;
+    ri[q] = base + k;
     if (k < len) {
-      o[q] = io.o[base + k];
-      d[q] = io.d[base + k];
-      st[q] = io.start[base + k];
+      if (io.order) {
+        // binned: the sort's keys are the internal start ids already
+        ri[q] = io.order[base + k];
+        st[q] = io.order_start[base + k];
+      } else {
+        st[q] = io.start[ri[q]];
+      }
+      o[q] = io.o[ri[q]];
+      d[q] = io.d[ri[q]];
     }
   }
 #pragma unroll
   for (int q = 0; q < TPL; ++q) {
     const int k = lane + 64 * q;
     if (k < len) {
-      if (MODE == 1) {
-        r[q] = make_float4((float)(o[q].x - sc.org_x), (float)(o[q].y - sc.org_y), (float)d[q].x,
-                           (float)d[q].y);
-        tl.r32[k] = r[q];
+      if (io.order) {
+        if (st[q] >= sc.ntri) st[q] = -1;
       } else {
-        tl.o[k] = o[q];
-        tl.d[k] = d[q];
+        // the caller's triangle id -> internal (Hilbert-ordered) id
+        st[q] = (st[q] >= 0 && st[q] < sc.ntri) ? sc.perm[st[q]] : -1;
       }
-      if (VALIDATE && (st[q] < 0 || st[q] >= sc.ntri || !validate_ray(sc, o[q], d[q], st[q]))) {
+      tl.o[k] = o[q];
+      tl.d[k] = d[q];
+      tl.idx[k] = (int)ri[q];
+      if (VALIDATE && (st[q] < 0 || !validate_ray(sc, o[q], d[q], st[q]))) {
         atomicOr(errflag, 1);
         st[q] = -1;
       }
-      if (st[q] >= sc.ntri) st[q] = -1;
     }
   }
   // phase 2: first triangle of each ray
@@ -227,8 +225,9 @@ __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, i
       int s0 = -1;
       if (st[q] >= 0) {
         if (MODE == 1) {
-          const Ray32 rr{r[q].x, r[q].y, r[q].z, r[q].w};
-          s0 = first_exit32<COUNT>(sc, io, base + k, rr, st[q], c);
+          const Ray32 rr{(float)(o[q].x - sc.org_x), (float)(o[q].y - sc.org_y), (float)d[q].x,
+                         (float)d[q].y};
+          s0 = first_exit32<COUNT>(sc, o[q], d[q], rr, st[q], c);
         } else {
           s0 = first_exit64<COUNT>(sc, o[q], d[q], st[q], c);
         }
@@ -265,7 +264,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
     batch.lds_tile_begin = tb;
     tile_mem = lds + (size_t)((batch.n_lds + 1) & ~1) * 8;
   }
-  const Tile<MODE, TILE> tl(tile_mem + (size_t)wave * Tile<MODE, TILE>::kBytes);
+  const Tile<TILE> tl(tile_mem + (size_t)wave * Tile<TILE>::kBytes);
 
   Counters c;
   // lane state
@@ -284,6 +283,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   int64_t tbase = 0;
   int tlen = 0, thead = 0, titem = 0;
   bool drained = false;
+  bool io_order = io_arg.order != nullptr;
 
   for (;;) {
     const unsigned long long idle = __ballot(!act);
@@ -316,6 +316,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             tbase = (claim - it.tile_begin) * TILE;
             tlen = (int)min((int64_t)TILE, it.rays.n - tbase);
             thead = 0;
+            io_order = it.rays.order != nullptr;
             fill_tile<MODE, TPL, COUNT, false>(it.scene, it.rays, tbase, tlen, tl, lane, c, errflag);
           } else {
             if (claim >= io_arg.n) {
@@ -331,24 +332,25 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         const int take = min(nidle - served, tlen - thead);
         if (!act && rank >= served && rank < served + take) {
           const int k = thead + (rank - served);
-          if (MODE == 1) {
-            const float4 q = tl.r32[k];
-            r32 = Ray32{q.x, q.y, q.z, q.w};
-          } else {
+          {
             const double2 o = tl.o[k], d = tl.d[k];
             ox = o.x; oy = o.y; dx = d.x; dy = d.y;
           }
           s = tl.s0[k];
-          ray = tbase + k;
+          ray = io_order ? (int64_t)tl.idx[k] : tbase + k;
           steps = 1;
           act = true;
+          double org_x = sc_arg.org_x, org_y = sc_arg.org_y;
           if (BATCH) {
             item = titem;
             const SceneDev& sc = batch.items[item].scene;
             slot32 = sc.slot32;
             slot64 = sc.slot64;
             ntri = sc.ntri;
+            org_x = sc.org_x;
+            org_y = sc.org_y;
           }
+          if (MODE == 1) r32 = Ray32{(float)(ox - org_x), (float)(oy - org_y), (float)dx, (float)dy};
           if (s < 0) {  // bad ray: out-of-range start, no exit edge, or failed validation
             const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
             io.prim[ray] = -3;
@@ -376,9 +378,8 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             left = sg > 0;
           } else {
             if (COUNT) ++c.fb32;
-            const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
             const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
-            left = left_deferred<COUNT>(io.o, io.d, ray, v64, q.w, &c.fb64);
+            left = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64, q.w, &c.fb64);
           }
         }
       } else {
@@ -403,15 +404,12 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         } else if (word == -1) {
           p = -1;
         } else {
-          p = -word - 2;
-          const double4* prim = BATCH ? batch.items[item].scene.prim : sc_arg.prim;
-          const double4 g = prim[p];
-          if (MODE == 1) {
-            const double2 o = io.o[ray], d = io.d[ray];
-            t = hit_t(g, o.x, o.y, d.x, d.y);
-          } else {
-            t = hit_t(g, ox, oy, dx, dy);
-          }
+          const PrimRec* prim = BATCH ? batch.items[item].scene.prim : sc_arg.prim;
+          const PrimRec& g = prim[-word - 2];
+          const double2 a = *reinterpret_cast<const double2*>(&g.ax);
+          const double2 b = *reinterpret_cast<const double2*>(&g.bx);
+          p = g.id;
+          t = hit_t(make_double4(a.x, a.y, b.x, b.y), ox, oy, dx, dy);
         }
         io.prim[ray] = p;
         io.t[ray] = t;
@@ -437,7 +435,8 @@ __global__ void reset_counter(unsigned long long* counter) { *counter = 0ull; }
 // ------------------------------------------------------------------------------ launchers
 
 size_t walk_lds_bytes(int mode, const LaunchCfg& cfg) {
-  return (size_t)(cfg.wg / 64) * cfg.tile * (mode == 1 ? 20 : 36);
+  (void)mode;
+  return (size_t)(cfg.wg / 64) * cfg.tile * 40;
 }
 
 template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH>

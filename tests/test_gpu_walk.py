@@ -154,6 +154,30 @@ def test_grid_cdt_and_annealed(ccsp, grid_pair):
                 _assert_same(_host(ccsp.trace(scene, *_dev(r), precision=prec)), ref, f"grid {prec}")
 
 
+@pytest.mark.parametrize("n", [65535, 65536, 200_003])
+def test_binned_equals_input_order(ccsp, grid_pair, n):
+    sc, _, rays, _ = grid_pair
+    r = rays.slice(0, n)
+    with ccsp.Scene.from_arrays(sc) as scene:
+        o, d, st = _dev(r)
+        for prec in ("fp32", "fp64"):
+            a = _host(ccsp.trace(scene, o, d, st, precision=prec))
+            b = _host(ccsp.trace(scene, o, d, st, precision=prec, input_order=True))
+            _assert_same(a, b, f"binned vs input order {prec} n={n}")
+        idx = np.arange(0, n, 37)
+        ref = oracle.walk(oracle.Triangulation.of(sc), r.o[idx], r.d[idx], r.start[idx])
+        _assert_same((a[0][idx], a[1][idx], a[2][idx]), ref, "binned vs checker")
+
+
+def test_reserve_workspace_then_trace(ccsp, tiny_scene, tiny_rays):
+    ccsp.reserve_workspace(1 << 17)
+    ref = oracle.walk(oracle.Triangulation.of(tiny_scene), tiny_rays.o, tiny_rays.d, tiny_rays.start)
+    with ccsp.Scene.from_arrays(tiny_scene) as scene:
+        _assert_same(_host(ccsp.trace(scene, *_dev(tiny_rays))), ref, "after reserve")
+    with pytest.raises(ccsp.CcspError):
+        ccsp.reserve_workspace(-1)
+
+
 def test_large_bench_configuration_sampled(ccsp):
     """The 1M-segment scene and all 2^26 rays in the default launch: every ray checked for
     agreement between the two modes and for valid outputs, a sample against the checker."""
@@ -174,6 +198,10 @@ def test_large_bench_configuration_sampled(ccsp):
         r64 = ccsp.trace(scene, o, d, st, precision="fp64")
         p64, t64, s64 = _host(r64)
         assert np.array_equal(p32, p64) and np.array_equal(s32, s64) and np.array_equal(t32, t64)
+        del r64
+        ri = ccsp.trace(scene, o, d, st, precision="fp32", input_order=True)
+        pi, ti, si = _host(ri)
+        assert np.array_equal(p32, pi) and np.array_equal(s32, si) and np.array_equal(t32, ti)
 
 
 def _batch_scenes(k=6, max_seg=20000):
@@ -234,7 +262,7 @@ def test_batch_with_empty_and_tiny_items(ccsp, tiny_scene, tiny_rays):
 def test_concurrent_streams(ccsp, tiny_scene, tiny_rays):
     ref = oracle.walk(oracle.Triangulation.of(tiny_scene), tiny_rays.o, tiny_rays.d, tiny_rays.start)
     with ccsp.Scene.from_arrays(tiny_scene) as scene:
-        o, d, st = _dev(tiny_rays)
+        o, d, st = _dev(tiny_rays)  # 65,536 rays: both traces are binned, sharing the scratch
         s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
         torch.cuda.synchronize()
         with torch.cuda.stream(s1):
