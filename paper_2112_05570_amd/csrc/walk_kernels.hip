@@ -267,10 +267,11 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   const Tile<TILE> tl(tile_mem + (size_t)wave * Tile<TILE>::kBytes);
 
   Counters c;
-  // lane state
-  bool act = false;
-  Ray32 r32{0, 0, 0, 0};             // binary32 mode
-  double ox = 0, oy = 0, dx = 0, dy = 0;  // binary64 mode
+  // lane state: IDLE (no ray), WALK (s is the exit slot to load), FIN (hit primitive p to load)
+  enum : int { IDLE = 0, WALK = 1, FIN = 2 };
+  int state = IDLE;
+  Ray32 r32{0, 0, 0, 0};                  // binary32 mode
+  double ox = 0, oy = 0, dx = 0, dy = 0;  // the ray in binary64
   int s = 0, steps = 0;
   int64_t ray = 0;
   int item = 0;
@@ -286,7 +287,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   bool io_order = io_arg.order != nullptr;
 
   for (;;) {
-    const unsigned long long idle = __ballot(!act);
+    const unsigned long long idle = __ballot(state == IDLE);
     const int nidle = __popcll(idle);
     if (drained && nidle == 64) break;
     if (!drained && nidle >= refill_min) {
@@ -330,7 +331,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
           }
         }
         const int take = min(nidle - served, tlen - thead);
-        if (!act && rank >= served && rank < served + take) {
+        if (state == IDLE && rank >= served && rank < served + take) {
           const int k = thead + (rank - served);
           {
             const double2 o = tl.o[k], d = tl.d[k];
@@ -339,7 +340,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
           s = tl.s0[k];
           ray = io_order ? (int64_t)tl.idx[k] : tbase + k;
           steps = 1;
-          act = true;
+          state = WALK;
           double org_x = sc_arg.org_x, org_y = sc_arg.org_y;
           if (BATCH) {
             item = titem;
@@ -356,24 +357,45 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             io.prim[ray] = -3;
             io.t[ray] = INFINITY;
             io.steps[ray] = 0;
-            act = false;
+            state = IDLE;
           }
         }
         served += take;
         thead += take;
       }
     }
-    if (act) {
-      int word;
-      bool left = false;
+    // Issue this iteration's loads before using any: a walking lane loads its exit slot, a
+    // finishing lane its hit primitive, so both share one memory round trip.
+    const int st_now = state;
+    int4 q = make_int4(0, 0, 0, 0);
+    double2 xy64 = make_double2(0.0, 0.0);
+    double2 ga = make_double2(0.0, 0.0), gb = make_double2(0.0, 0.0);
+    int gid = 0;
+    if (st_now == WALK) {
       if (MODE == 1) {
-        const int4 q = *reinterpret_cast<const int4*>(slot32 + s);
+        q = *reinterpret_cast<const int4*>(slot32 + s);
         // Keep the slot one 16-byte load: without this the compiler loads the exit word alone,
-        // branches on it and only then loads the vertex, a second dependent round trip per step.
+        // branches on it and only then loads the vertex, a second dependent round trip.
         __asm__ volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
-        word = q.x;
-        const int sg = side32(r32, __int_as_float(q.y), __int_as_float(q.z));
-        if (word >= 0) {
+      } else {
+        xy64 = *reinterpret_cast<const double2*>(slot64 + s);
+        q.x = *reinterpret_cast<const int*>(&slot64[s].word);
+        __asm__ volatile("" ::"v"(xy64.x), "v"(xy64.y), "v"(q.x));
+      }
+    } else if (st_now == FIN) {
+      const PrimRec* prim = BATCH ? batch.items[item].scene.prim : sc_arg.prim;
+      const PrimRec* g = prim + s;
+      ga = *reinterpret_cast<const double2*>(&g->ax);
+      gb = *reinterpret_cast<const double2*>(&g->bx);
+      gid = g->id;
+      __asm__ volatile("" ::"v"(ga.x), "v"(ga.y), "v"(gb.x), "v"(gb.y), "v"(gid));
+    }
+    if (st_now == WALK) {
+      const int word = q.x;
+      bool left = false;
+      if (word >= 0) {
+        if (MODE == 1) {
+          const int sg = side32(r32, __int_as_float(q.y), __int_as_float(q.z));
           if (sg != 0) {
             left = sg > 0;
           } else {
@@ -381,45 +403,40 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
             left = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64, q.w, &c.fb64);
           }
+        } else {
+          left = left64<COUNT>(ox, oy, dx, dy, xy64.x, xy64.y, c.fb64);
         }
-      } else {
-        const double2 xy = *reinterpret_cast<const double2*>(slot64 + s);
-        const int wd = *reinterpret_cast<const int*>(&slot64[s].word);
-        __asm__ volatile("" ::"v"(xy.x), "v"(xy.y), "v"(wd));
-        word = wd;
-        if (word >= 0) left = left64<COUNT>(ox, oy, dx, dy, xy.x, xy.y, c.fb64);
       }
       if (word >= 0 && steps < ntri) {
         ++steps;
         int e = (word & 3) + (left ? 1 : 2);
         e = e >= 3 ? e - 3 : e;
         s = 3 * (word >> 2) + e;
+      } else if (word <= -2) {
+        s = -word - 2;  // constrained edge: hit; its primitive is loaded next iteration
+        state = FIN;
       } else {
-        // terminate: constrained edge (hit), hull edge (miss) or the step guard
+        // hull edge (miss) or the step guard
         const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
-        int p;
-        double t = INFINITY;
-        if (word >= 0) {
-          p = -2;
-        } else if (word == -1) {
-          p = -1;
-        } else {
-          const PrimRec* prim = BATCH ? batch.items[item].scene.prim : sc_arg.prim;
-          const PrimRec& g = prim[-word - 2];
-          const double2 a = *reinterpret_cast<const double2*>(&g.ax);
-          const double2 b = *reinterpret_cast<const double2*>(&g.bx);
-          p = g.id;
-          t = hit_t(make_double4(a.x, a.y, b.x, b.y), ox, oy, dx, dy);
-        }
-        io.prim[ray] = p;
-        io.t[ray] = t;
+        io.prim[ray] = word >= 0 ? -2 : -1;
+        io.t[ray] = INFINITY;
         io.steps[ray] = steps;
         if (COUNT) {
           c.steps += steps;
           ++c.rays;
         }
-        act = false;
+        state = IDLE;
       }
+    } else if (st_now == FIN) {
+      const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
+      io.prim[ray] = gid;
+      io.t[ray] = hit_t(make_double4(ga.x, ga.y, gb.x, gb.y), ox, oy, dx, dy);
+      io.steps[ray] = steps;
+      if (COUNT) {
+        c.steps += steps;
+        ++c.rays;
+      }
+      state = IDLE;
     }
   }
   if (COUNT) {
