@@ -176,6 +176,18 @@ int read_counters(uint64_t out[4], int reset);
 /* triangulation_info: out[0] triangles, out[1] vertices, out[2] primitives, out[3] device bytes. */
 int triangulation_info(const Triangulation *tri, int64_t out[4]);
 
+/*
+ * gather_roofline: a measurement, not part of the walk. Chases a buffer of working_set_bytes
+ * (rounded down to a power of two of 16-byte records, each pointing to a pseudo-random next one)
+ * with waves_per_cu waves of 64 lanes per compute unit, each lane doing steps_per_lane dependent
+ * 16-byte loads, and stores the sustained loads per second in *out_loads_per_s. This is the
+ * memory pattern of one walk step, so the walk's steps per second over this rate (at a matching
+ * working set) is its fraction of the gather roofline. Allocates and frees its own buffer and
+ * synchronises `stream`.
+ */
+int gather_roofline(int64_t working_set_bytes, int32_t waves_per_cu, int64_t steps_per_lane,
+                    double *out_loads_per_s, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,7 +41,7 @@ CCSP_TRACE_INPUT_ORDER = 1 << 10
 
 EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch",
            "free_triangulation", "last_error", "read_counters", "triangulation_info",
-           "reserve_workspace")
+           "reserve_workspace", "gather_roofline")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -85,6 +85,8 @@ _lib.triangulation_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64 * 4)]
 _lib.triangulation_info.restype = _I
 _lib.reserve_workspace.argtypes = [_I64]
 _lib.reserve_workspace.restype = _I
+_lib.gather_roofline.argtypes = [_I64, ctypes.c_int32, _I64, ctypes.POINTER(ctypes.c_double), _P]
+_lib.gather_roofline.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -147,6 +149,14 @@ def triangulation_info(tri: int) -> list:
 
 def reserve_workspace(max_rays: int) -> None:
     _check(_lib.reserve_workspace(max_rays))
+
+
+def gather_roofline(working_set_bytes: int, waves_per_cu: int = 16, steps_per_lane: int = 4096,
+                    stream: int = 0) -> float:
+    out = ctypes.c_double()
+    _check(_lib.gather_roofline(working_set_bytes, waves_per_cu, steps_per_lane, ctypes.byref(out),
+                                _P(stream)))
+    return out.value
 
 
 def raw_call(name: str, *args):

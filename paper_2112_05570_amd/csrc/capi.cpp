@@ -149,6 +149,13 @@ int device_state(DeviceState** out) {
 
 constexpr int64_t kBinMinRays = 1 << 16;
 
+// Tile counters of the next launch: a ring of kCounterSlots / kClaimChunks groups (the last group
+// is reserved for captured graphs), so that launches in flight on different streams never share.
+unsigned long long* next_counters(DeviceState* ds) {
+  const unsigned groups = kCounterSlots / kClaimChunks - 1;
+  return ds->ws.counters + (size_t)(ds->next_counter.fetch_add(1) % groups) * kClaimChunks;
+}
+
 // Grow the per-device ray binning scratch to hold n rays (allocates only when n exceeds every
 // earlier size; reserve_workspace() does it ahead of time). Caller holds ds->bin_mu.
 int grow_bin_workspace(DeviceState* ds, int64_t n) {
@@ -175,6 +182,7 @@ LaunchCfg make_cfg(const DeviceState& ds, int mode, const TuneParams* tp) {
   const int wpcu = (tp && tp->waves_per_cu) ? tp->waves_per_cu : 16;
   c.refill_min = (tp && tp->refill_min) ? tp->refill_min : 32;
   c.grid = std::max(1, ds.cus * wpcu / (c.wg / 64));
+  c.chunks = (tp && tp->reserved[1] == 1) ? 1 : kClaimChunks;
   return c;
 }
 
@@ -418,6 +426,10 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   tri->dev.perm = reinterpret_cast<const int32_t*>(base + off_perm);
   tri->dev.org_x = org[0];
   tri->dev.org_y = org[1];
+  tri->dev.box_x0 = lo[0];
+  tri->dev.box_y0 = lo[1];
+  tri->dev.box_x1 = hi[0];
+  tri->dev.box_y1 = hi[1];
   tri->dev.ntri = (int32_t)T;
   *out = tri;
   return CCSP_OK;
@@ -477,7 +489,7 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
   hipStream_t st = static_cast<hipStream_t>(stream);
   RaysDev io{reinterpret_cast<const double2*>(o_xy), reinterpret_cast<const double2*>(d_xy),
              start_tri, hit_prim, hit_t, steps, n, nullptr};
-  unsigned long long* counter = ds->ws.counters + (ds->next_counter.fetch_add(1) % kCounterSlots);
+  unsigned long long* counter = next_counters(ds);
   hipError_t e;
   const bool bin = !(precision & CCSP_TRACE_INPUT_ORDER) && n >= kBinMinRays && n < INT32_MAX;
   std::unique_lock<std::mutex> bin_lock(ds->bin_mu, std::defer_lock);
@@ -490,8 +502,10 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
       e = hipStreamWaitEvent(st, ds->bin_free, 0);
       if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     }
-    e = launch_bin_rays(tri->dev, start_tri, n, ds->bin_ws, ds->bin_ws_bytes, &io.order,
-                        &io.order_start, st);
+    RaysDev binned{};
+    e = launch_bin_rays(tri->dev, io, (tune && tune->reserved[2] == 1) ? kKeyCoherent : kKeyStart,
+                        ds->bin_ws, ds->bin_ws_bytes, &binned, st);
+    io = binned;
     if (e != hipSuccess) return hip_fail(e, "ray binning");
   }
   if (validate) {
@@ -581,7 +595,7 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
     b.tile_begin = tb;
     tb += (it.n + cfg.tile - 1) / cfg.tile;
   }
-  unsigned long long* counter = ds->ws.counters + (ds->next_counter.fetch_add(1) % kCounterSlots);
+  unsigned long long* counter = next_counters(ds);
   const bool count = precision & CCSP_TRACE_COUNT;
   if (!use_graph) {
     e = hipMemcpyAsync(ds->items_dev, ds->items_host, sizeof(BatchItem) * n_items, hipMemcpyHostToDevice, st);
@@ -597,7 +611,7 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
   const uint64_t key = ((uint64_t)n_items << 40) ^ ((uint64_t)tiles << 8) ^ ((uint64_t)mode << 4) ^
                        ((uint64_t)count << 3) ^ ((uint64_t)cfg.tile << 50) ^ ((uint64_t)cfg.wg << 56) ^
                        ((uint64_t)cfg.refill_min << 20) ^ ((uint64_t)cfg.grid << 28);
-  counter = ds->ws.counters + kCounterSlots - 1;  // graphs use the reserved last counter slot
+  counter = ds->ws.counters + kCounterSlots - kClaimChunks;  // graphs use the reserved last slot
   auto itg = ds->graphs.find(key);
   if (itg == ds->graphs.end()) {
     hipStream_t cap_stream;

@@ -44,10 +44,13 @@ struct SceneDev {
   const PrimRec* prim;   // P, internal order (first met along the Hilbert order of triangles)
   const int32_t* perm;   // T: caller's triangle id -> internal (Hilbert-ordered) id
   double org_x, org_y;   // origin of the binary32 coordinates
+  double box_x0, box_y0, box_x1, box_y1;  // bounding box of the vertices
   int32_t ntri;
   int32_t pad;
 };
 
+// Rays in the caller's order. When `order` is set, the ray walked at position k is order[k]
+// (a permutation of 0..n-1 produced by binning); otherwise it is k.
 struct RaysDev {
   const double2* o;
   const double2* d;
@@ -56,8 +59,8 @@ struct RaysDev {
   double* t;
   int32_t* steps;
   int64_t n;
-  const int32_t* order;        // optional processing order (a permutation of 0..n-1), or null
-  const int32_t* order_start;  // with `order`: internal start triangle of each ray in that order
+  const int32_t* order;
+  const int32_t* order_start;  // optional: internal start triangle of the ray at position k
 };
 
 // One item of a batched launch: the scene, its rays and where its tiles start in the
@@ -73,6 +76,7 @@ struct LaunchCfg {
   int tile;        // rays per wave tile (multiple of 64)
   int grid;        // workgroups
   int refill_min;  // idle lanes that trigger a refill
+  int chunks;      // the tile sequence is split into this many chunks, one per XCD (1 or 8)
 };
 
 // Per-device scratch used by the walk: tile counters and the diagnostic counters.
@@ -82,13 +86,14 @@ struct Workspace {
   int* errflag;                  // set by validating launches
 };
 constexpr int kCounterSlots = 4096;
+constexpr int kClaimChunks = 8;  // tile counters per launch (one per XCD)
 
-// Spatial binning of rays: order[] = ray indices sorted by the internal (Hilbert-ordered) id of
-// their start triangle, which order_start[] holds. Needs bin_workspace_bytes(n) of scratch.
+// Binning: *out = `in` with out->order set to a cache-friendly walking order (see bin.hip for
+// the two keys). Needs bin_workspace_bytes(n) of scratch.
+enum { kKeyStart = 0, kKeyCoherent = 1 };
 size_t bin_workspace_bytes(int64_t n);
-hipError_t launch_bin_rays(const SceneDev& sc, const int32_t* start, int64_t n, void* workspace,
-                           size_t ws_bytes, const int32_t** order_out,
-                           const int32_t** order_start_out, hipStream_t stream);
+hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int key_kind, void* workspace,
+                           size_t ws_bytes, RaysDev* out, hipStream_t stream);
 
 hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
                        const LaunchCfg& cfg, unsigned long long* counter, const Workspace& ws,

@@ -187,23 +187,18 @@ __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, i
     st[q] = -1;
     ri[q] = base + k;
     if (k < len) {
-      if (io.order) {
-        // binned: the sort's keys are the internal start ids already
-        ri[q] = io.order[base + k];
-        st[q] = io.order_start[base + k];
-      } else {
-        st[q] = io.start[ri[q]];
-      }
+      if (io.order) ri[q] = io.order[base + k];
       o[q] = io.o[ri[q]];
       d[q] = io.d[ri[q]];
+      st[q] = io.order_start ? io.order_start[base + k] : io.start[ri[q]];
     }
   }
 #pragma unroll
   for (int q = 0; q < TPL; ++q) {
     const int k = lane + 64 * q;
     if (k < len) {
-      if (io.order) {
-        if (st[q] >= sc.ntri) st[q] = -1;
+      if (io.order_start) {
+        if (st[q] >= sc.ntri) st[q] = -1;  // already internal (the binning sort's keys)
       } else {
         // the caller's triangle id -> internal (Hilbert-ordered) id
         st[q] = (st[q] >= 0 && st[q] < sc.ntri) ? sc.perm[st[q]] : -1;
@@ -246,10 +241,29 @@ struct ItemRef {
   int n_lds;
 };
 
+// Claim the next tile of [0, total): the sequence is split into `chunks` contiguous chunks with a
+// counter each; a workgroup starts in chunk blockIdx.x % chunks (workgroups are dispatched to the
+// XCDs round-robin, so with 8 chunks each XCD walks its own part of the binned rays and keeps its
+// own region of the scene in its L2) and moves on to the next chunk once one is exhausted.
+// Returns -1 when every chunk is exhausted. Wave-uniform.
+__device__ __forceinline__ long long claim_tile(unsigned long long* counter, int chunks,
+                                                long long total, int& cur, int& tried, int lane) {
+  while (tried < chunks) {
+    const long long c0 = total * cur / chunks, c1 = total * (cur + 1) / chunks;
+    unsigned long long b = 0;
+    if (lane == 0) b = atomicAdd(counter + cur, 1ull);
+    const long long t = c0 + bcast64(b);
+    if (t < c1) return t;
+    cur = cur + 1 == chunks ? 0 : cur + 1;
+    ++tried;
+  }
+  return -1;
+}
+
 template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH>
 __global__ void __launch_bounds__(512)
 walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_tiles,
-                unsigned long long* __restrict__ counter, int refill_min,
+                unsigned long long* __restrict__ counter, int refill_min, int chunks,
                 unsigned long long* __restrict__ stats, int* __restrict__ errflag) {
   constexpr int TILE = TPL * 64;
   extern __shared__ unsigned char lds[];
@@ -285,6 +299,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   int tlen = 0, thead = 0, titem = 0;
   bool drained = false;
   bool io_order = io_arg.order != nullptr;
+  int chunk_cur = (int)(blockIdx.x % (unsigned)chunks), chunk_tried = 0;
 
   for (;;) {
     const unsigned long long idle = __ballot(state == IDLE);
@@ -295,14 +310,12 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
       int served = 0;
       while (served < nidle) {
         if (thead == tlen) {
-          unsigned long long b = 0;
-          if (lane == 0) b = atomicAdd(counter, BATCH ? 1ull : (unsigned long long)TILE);
-          const long long claim = bcast64(b);
+          const long long claim = claim_tile(counter, chunks, total_tiles, chunk_cur, chunk_tried, lane);
+          if (claim < 0) {
+            drained = true;
+            break;
+          }
           if (BATCH) {
-            if (claim >= total_tiles) {
-              drained = true;
-              break;
-            }
             // item owning tile `claim`: the last item whose tile_begin <= claim
             int lo = 0, hi = batch.n_items - 1;
             while (lo < hi) {
@@ -320,11 +333,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             io_order = it.rays.order != nullptr;
             fill_tile<MODE, TPL, COUNT, false>(it.scene, it.rays, tbase, tlen, tl, lane, c, errflag);
           } else {
-            if (claim >= io_arg.n) {
-              drained = true;
-              break;
-            }
-            tbase = claim;
+            tbase = claim * TILE;
             tlen = (int)min((int64_t)TILE, io_arg.n - tbase);
             thead = 0;
             fill_tile<MODE, TPL, COUNT, VALIDATE>(sc_arg, io_arg, tbase, tlen, tl, lane, c, errflag);
@@ -447,7 +456,9 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   }
 }
 
-__global__ void reset_counter(unsigned long long* counter) { *counter = 0ull; }
+__global__ void reset_counters(unsigned long long* counter) {
+  if (threadIdx.x < kClaimChunks) counter[threadIdx.x] = 0ull;
+}
 
 // ------------------------------------------------------------------------------ launchers
 
@@ -462,7 +473,7 @@ static hipError_t go(const SceneDev& sc, const RaysDev& io, ItemRef br, int64_t 
                      const Workspace& ws, hipStream_t stream) {
   hipLaunchKernelGGL((walk_persistent<MODE, TPL, COUNT, VALIDATE, BATCH>), dim3(cfg.grid),
                      dim3(cfg.wg), lds, stream, sc, io, br, total_tiles, counter, cfg.refill_min,
-                     ws.stats, ws.errflag);
+                     cfg.chunks, ws.stats, ws.errflag);
   return hipGetLastError();
 }
 
@@ -481,12 +492,13 @@ static hipError_t pick_tile(const SceneDev& sc, const RaysDev& io, ItemRef br, i
 hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
                        const LaunchCfg& cfg, unsigned long long* counter, const Workspace& ws,
                        hipStream_t stream) {
-  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, stream, counter);
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counter);
   const size_t lds = walk_lds_bytes(mode, cfg);
   const ItemRef none{nullptr, 0, nullptr, 0};
+  const int64_t tiles = (io.n + cfg.tile - 1) / cfg.tile;
 #define CCSP_CASE(M, C, V) \
   if (mode == M && count == C && validate == V) \
-    return pick_tile<M, C, V, false>(sc, io, none, 0, cfg, lds, counter, ws, stream);
+    return pick_tile<M, C, V, false>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
   CCSP_CASE(0, false, false) CCSP_CASE(0, true, false) CCSP_CASE(0, false, true) CCSP_CASE(0, true, true)
   CCSP_CASE(1, false, false) CCSP_CASE(1, true, false) CCSP_CASE(1, false, true) CCSP_CASE(1, true, true)
 #undef CCSP_CASE
@@ -496,7 +508,7 @@ hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool cou
 hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t total_tiles,
                              int mode, bool count, const LaunchCfg& cfg,
                              unsigned long long* counter, const Workspace& ws, hipStream_t stream) {
-  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, stream, counter);
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counter);
   const int n_lds = n_items < 1024 ? n_items : 1024;
   const size_t lds = walk_lds_bytes(mode, cfg) + (size_t)((n_lds + 1) & ~1) * 8;
   const ItemRef br{items_dev, n_items, nullptr, n_lds};
