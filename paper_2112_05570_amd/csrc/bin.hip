@@ -1,19 +1,21 @@
 // Binning of rays before the walk, for cache reuse.
 //
 // Rays arrive in any order; walked in that order, the lanes resident on the GPU touch triangles
-// all over the scene and nearly every step misses the caches. The rays are therefore walked in
-// the order of a key, by a radix sort of (key, index) pairs; the walk reads each ray through the
-// sorted index. Two keys:
-//  * kKeyStart (default): the internal id of the start triangle. Triangles are numbered along a
-//    Hilbert curve, so consecutive rays start close together and an L2-sized region of the scene
-//    is in use at any moment. The sorted keys double as the rays' internal start ids.
-//  * kKeyCoherent: [ Hilbert cell of the origin on a G x G grid | direction sector (16) |
-//    sub-cell (4x4) ], G chosen for about a thousand rays per cell, so that the lanes of a wave
-//    also share a direction. Needs no gather, but the walk then maps start ids itself.
+// all over the scene and nearly every step misses the caches (the walk then runs at the random
+// gather rate of a scene-sized working set). Binning puts rays that start close together next to
+// each other, so that the rays in flight on one XCD start in one compact region whose triangles
+// (stored in Hilbert order) fit its L2.
+//
+// Default (kBinBuckets): one counting-sort pass into kBuckets buckets = cells of a 16 x 16 grid
+// over the scene numbered along a Hilbert curve. A counting kernel histograms the buckets per
+// chunk of rays, a scan turns the counts into destinations, and a scatter kernel stages each
+// chunk in LDS sorted by bucket and writes it out as 48-byte records (origin, direction, internal
+// start triangle, caller's index) in runs, so that both its reads and writes are coalesced and
+// the walk then reads its rays contiguously, with no gather through a permutation.
+// Alternative (kBinRadix): a radix sort of (internal start triangle, index) pairs; the walk then
+// gathers each ray through the sorted index.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
-
-#include <cmath>
 
 #include "walk.hpp"
 
@@ -21,12 +23,20 @@ namespace ccsp {
 
 namespace {
 
-constexpr int kSectorBits = 4;
-constexpr int kSubBits = 2;  // sub-cell grid 2^kSubBits x 2^kSubBits inside a cell
+constexpr int kGridBits = 4;
+constexpr int kBuckets = 1 << (2 * kGridBits);
+constexpr int kChunk = 1024;  // rays per scatter workgroup (LDS staging: 48 KiB)
+constexpr int kThreads = 256;
+constexpr int kPerThread = kChunk / kThreads;
 
-__device__ __forceinline__ uint32_t hilbert(uint32_t x, uint32_t y, int bits) {
-  const uint32_t n = 1u << bits;
+struct BinGeom {
+  double x0, y0, sx, sy;  // cell = floor((p - p0) * s), clamped to the grid
+};
+
+__device__ __forceinline__ uint32_t hilbert_cell(uint32_t x, uint32_t y) {
+  constexpr uint32_t n = 1u << kGridBits;
   uint32_t d = 0;
+#pragma unroll
   for (uint32_t s = n >> 1; s > 0; s >>= 1) {
     const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
     d += s * s * ((3u * rx) ^ ry);
@@ -43,27 +53,93 @@ __device__ __forceinline__ uint32_t hilbert(uint32_t x, uint32_t y, int bits) {
   return d;
 }
 
-struct KeyGeom {
-  double x0, y0, sx, sy;  // fine grid coordinate = (p - p0) * s, in [0, 2^(bits+kSubBits))
-  int bits;               // log2 of the cell grid size G
-};
-
-__global__ void ray_keys(const double2* __restrict__ o, const double2* __restrict__ d, int64_t n,
-                         KeyGeom g, uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double2 oi = o[i], di = d[i];
-  const double hi = (double)((1u << (g.bits + kSubBits)) - 1);
+__device__ __forceinline__ uint32_t bucket_of(const double2 o, const BinGeom& g) {
+  constexpr double hi = (double)((1 << kGridBits) - 1);
   // NaN coordinates compare false and land in cell 0; the walk itself deals with such rays.
-  const uint32_t fx = (uint32_t)fmin(fmax((oi.x - g.x0) * g.sx, 0.0), hi);
-  const uint32_t fy = (uint32_t)fmin(fmax((oi.y - g.y0) * g.sy, 0.0), hi);
-  const uint32_t cell = hilbert(fx >> kSubBits, fy >> kSubBits, g.bits);
-  const uint32_t sub = hilbert(fx & ((1u << kSubBits) - 1), fy & ((1u << kSubBits) - 1), kSubBits);
-  const float a = atan2f((float)di.y, (float)di.x);  // (-pi, pi]
-  uint32_t sector = (uint32_t)((a + 3.14159265f) * (float)(1 << kSectorBits) / 6.2831854f);
-  sector = min(sector, (1u << kSectorBits) - 1);
-  key[i] = (((cell << kSectorBits) | sector) << (2 * kSubBits)) | sub;
-  idx[i] = (int32_t)i;
+  const double fx = fmin(fmax((o.x - g.x0) * g.sx, 0.0), hi);
+  const double fy = fmin(fmax((o.y - g.y0) * g.sy, 0.0), hi);
+  return hilbert_cell((uint32_t)fx, (uint32_t)fy);
+}
+
+__global__ void __launch_bounds__(kThreads)
+bucket_count(const double2* __restrict__ o, int64_t n, BinGeom g, uint32_t* __restrict__ H,
+             int nchunks) {
+  __shared__ uint32_t h[kBuckets];
+  for (int b = threadIdx.x; b < kBuckets; b += kThreads) h[b] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int64_t i = base + threadIdx.x + q * kThreads;
+    if (i < n) atomicAdd(&h[bucket_of(o[i], g)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBuckets; b += kThreads) H[(size_t)b * nchunks + blockIdx.x] = h[b];
+}
+
+__global__ void __launch_bounds__(kThreads)
+bucket_scatter(const double2* __restrict__ o, const double2* __restrict__ d,
+               const int32_t* __restrict__ start, const int32_t* __restrict__ perm,
+               int32_t ntri, int64_t n, BinGeom g, const uint32_t* __restrict__ Hoff,
+               int nchunks, RayRec* __restrict__ out) {
+  __shared__ uint32_t off[kBuckets], cnt[kBuckets], pre[kBuckets];
+  __shared__ RayRec stage[kChunk];
+  __shared__ uint16_t stage_bucket[kChunk];
+  for (int b = threadIdx.x; b < kBuckets; b += kThreads) {
+    off[b] = Hoff[(size_t)b * nchunks + blockIdx.x];
+    cnt[b] = 0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  const int len = (int)min((int64_t)kChunk, n - base);
+  RayRec r[kPerThread];
+  uint32_t bk[kPerThread], rank[kPerThread];
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int j = threadIdx.x + q * kThreads;
+    if (j < len) {
+      const int64_t i = base + j;
+      r[q].o = o[i];
+      r[q].d = d[i];
+      const int32_t s = start[i];
+      r[q].start = (s >= 0 && s < ntri) ? perm[s] : -1;  // internal id, -1 if out of range
+      r[q].idx = (int32_t)i;
+      r[q].pad[0] = r[q].pad[1] = 0;
+      bk[q] = bucket_of(r[q].o, g);
+      rank[q] = atomicAdd(&cnt[bk[q]], 1u);
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the chunk's bucket counts (kBuckets == kThreads: one bucket per thread)
+  {
+    const int b = threadIdx.x;
+    const uint32_t v = cnt[b];
+    pre[b] = v;
+    __syncthreads();
+    for (int s = 1; s < kBuckets; s <<= 1) {
+      const uint32_t add = b >= s ? pre[b - s] : 0u;
+      __syncthreads();
+      pre[b] += add;
+      __syncthreads();
+    }
+    pre[b] -= v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int j = threadIdx.x + q * kThreads;
+    if (j < len) {
+      const uint32_t p = pre[bk[q]] + rank[q];
+      stage[p] = r[q];
+      stage_bucket[p] = (uint16_t)bk[q];
+    }
+  }
+  __syncthreads();
+  // consecutive staged records of one bucket go to consecutive destinations
+  for (int j = threadIdx.x; j < len; j += kThreads) {
+    const uint32_t b = stage_bucket[j];
+    out[off[b] + (j - pre[b])] = stage[j];
+  }
 }
 
 __global__ void start_keys(const int32_t* __restrict__ start, const int32_t* __restrict__ perm,
@@ -84,13 +160,14 @@ int bits_for(int64_t v) {  // smallest b with v < 2^b
   return b;
 }
 
-int grid_bits(int64_t n) {  // about 1024 rays per cell, cells from 16 x 16 to 4096 x 4096
-  int b = 4;
-  while (b < 12 && (int64_t(1) << (2 * (b + 1))) * 1024 <= n) ++b;
-  return b;
-}
+int n_chunks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
 
-int key_bits(int64_t n) { return 2 * grid_bits(n) + kSectorBits + 2 * kSubBits; }
+size_t scan_temp_bytes(size_t items) {
+  size_t temp = 0;
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, temp, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                         (int)items);
+  return temp;
+}
 
 size_t sort_temp_bytes(int64_t n) {
   size_t temp = 0;
@@ -102,48 +179,70 @@ size_t sort_temp_bytes(int64_t n) {
 
 }  // namespace
 
+static_assert(kBuckets == kThreads, "the chunk scan assigns one bucket per thread");
+static_assert(sizeof(RayRec) == 48, "ray record layout");
+
 size_t bin_workspace_bytes(int64_t n) {
-  return 4 * align256(sizeof(uint32_t) * (size_t)n) + align256(sort_temp_bytes(n));
+  const size_t items = (size_t)kBuckets * n_chunks(n);
+  const size_t bucket = align256(sizeof(RayRec) * (size_t)n) + 2 * align256(sizeof(uint32_t) * items) +
+                        align256(scan_temp_bytes(items));
+  const size_t radix = 4 * align256(sizeof(uint32_t) * (size_t)n) + align256(sort_temp_bytes(n));
+  return bucket > radix ? bucket : radix;
 }
 
-hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int key_kind, void* workspace,
+hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void* workspace,
                            size_t ws_bytes, RaysDev* out, hipStream_t stream) {
   const int64_t n = in.n;
   if (n <= 0 || n >= INT32_MAX || bin_workspace_bytes(n) > ws_bytes) return hipErrorInvalidValue;
   auto* p = static_cast<unsigned char*>(workspace);
-  const size_t a = align256(sizeof(uint32_t) * (size_t)n);
-  uint32_t* k0 = reinterpret_cast<uint32_t*>(p);
-  uint32_t* k1 = reinterpret_cast<uint32_t*>(p + a);
-  int32_t* v0 = reinterpret_cast<int32_t*>(p + 2 * a);
-  int32_t* v1 = reinterpret_cast<int32_t*>(p + 3 * a);
-  void* temp = p + 4 * a;
-  size_t temp_bytes = ws_bytes - 4 * a;
-  KeyGeom g;
-  g.bits = grid_bits(n);
-  const double fine = (double)(1u << (g.bits + kSubBits));
+  *out = in;
+  hipError_t e;
+  if (kind == kBinRadix) {
+    const size_t a = align256(sizeof(uint32_t) * (size_t)n);
+    uint32_t* k0 = reinterpret_cast<uint32_t*>(p);
+    uint32_t* k1 = reinterpret_cast<uint32_t*>(p + a);
+    int32_t* v0 = reinterpret_cast<int32_t*>(p + 2 * a);
+    int32_t* v1 = reinterpret_cast<int32_t*>(p + 3 * a);
+    size_t temp_bytes = ws_bytes - 4 * a;
+    const int bs = 256;
+    hipLaunchKernelGGL(start_keys, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, stream,
+                       in.start, sc.perm, sc.ntri, n, k0, v0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipcub::DoubleBuffer<uint32_t> keys(k0, k1);
+    hipcub::DoubleBuffer<int32_t> vals(v0, v1);
+    e = hipcub::DeviceRadixSort::SortPairs(p + 4 * a, temp_bytes, keys, vals, (int)n, 0,
+                                           bits_for(sc.ntri), stream);
+    if (e != hipSuccess) return e;
+    out->order = vals.Current();
+    out->order_start = reinterpret_cast<const int32_t*>(keys.Current());
+    return hipSuccess;
+  }
+  const int nch = n_chunks(n);
+  const size_t items = (size_t)kBuckets * nch;
+  RayRec* recs = reinterpret_cast<RayRec*>(p);
+  p += align256(sizeof(RayRec) * (size_t)n);
+  uint32_t* H = reinterpret_cast<uint32_t*>(p);
+  p += align256(sizeof(uint32_t) * items);
+  uint32_t* Hoff = reinterpret_cast<uint32_t*>(p);
+  p += align256(sizeof(uint32_t) * items);
+  size_t temp_bytes = align256(scan_temp_bytes(items));
+  BinGeom g;
+  const double cells = (double)(1 << kGridBits);
   g.x0 = sc.box_x0;
   g.y0 = sc.box_y0;
-  g.sx = sc.box_x1 > sc.box_x0 ? fine / (sc.box_x1 - sc.box_x0) : 0.0;
-  g.sy = sc.box_y1 > sc.box_y0 ? fine / (sc.box_y1 - sc.box_y0) : 0.0;
-  const int bs = 256;
-  const dim3 grid((unsigned)((n + bs - 1) / bs));
-  int end_bit;
-  if (key_kind == kKeyCoherent) {
-    hipLaunchKernelGGL(ray_keys, grid, dim3(bs), 0, stream, in.o, in.d, n, g, k0, v0);
-    end_bit = key_bits(n);
-  } else {
-    hipLaunchKernelGGL(start_keys, grid, dim3(bs), 0, stream, in.start, sc.perm, sc.ntri, n, k0, v0);
-    end_bit = bits_for(sc.ntri);
-  }
-  hipError_t e = hipGetLastError();
+  g.sx = sc.box_x1 > sc.box_x0 ? cells / (sc.box_x1 - sc.box_x0) : 0.0;
+  g.sy = sc.box_y1 > sc.box_y0 ? cells / (sc.box_y1 - sc.box_y0) : 0.0;
+  hipLaunchKernelGGL(bucket_count, dim3(nch), dim3(kThreads), 0, stream, in.o, n, g, H, nch);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipcub::DoubleBuffer<uint32_t> keys(k0, k1);
-  hipcub::DoubleBuffer<int32_t> vals(v0, v1);
-  e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, vals, (int)n, 0, end_bit, stream);
+  e = hipcub::DeviceScan::ExclusiveSum(p, temp_bytes, H, Hoff, (int)items, stream);
   if (e != hipSuccess) return e;
-  *out = in;
-  out->order = vals.Current();
-  out->order_start = key_kind == kKeyCoherent ? nullptr : reinterpret_cast<const int32_t*>(keys.Current());
+  hipLaunchKernelGGL(bucket_scatter, dim3(nch), dim3(kThreads), 0, stream, in.o, in.d, in.start,
+                     sc.perm, sc.ntri, n, g, Hoff, nch, recs);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  out->recs = recs;
   return hipSuccess;
 }
 

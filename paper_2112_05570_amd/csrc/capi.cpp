@@ -503,7 +503,7 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
       if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     }
     RaysDev binned{};
-    e = launch_bin_rays(tri->dev, io, (tune && tune->reserved[2] == 1) ? kKeyCoherent : kKeyStart,
+    e = launch_bin_rays(tri->dev, io, (tune && tune->reserved[2] == kBinRadix) ? kBinRadix : kBinBuckets,
                         ds->bin_ws, ds->bin_ws_bytes, &binned, st);
     io = binned;
     if (e != hipSuccess) return hip_fail(e, "ray binning");

@@ -49,8 +49,19 @@ struct SceneDev {
   int32_t pad;
 };
 
-// Rays in the caller's order. When `order` is set, the ray walked at position k is order[k]
-// (a permutation of 0..n-1 produced by binning); otherwise it is k.
+// A binned ray: origin, direction, internal start triangle (-1 if out of range) and the caller's
+// index of the ray.
+struct alignas(16) RayRec {
+  double2 o;
+  double2 d;
+  int32_t start;
+  int32_t idx;
+  int32_t pad[2];
+};
+
+// Rays in the caller's order. When `recs` is set, the ray walked at position k is recs[k] (binned
+// copies); else when `order` is set it is ray order[k] (a permutation of 0..n-1), with internal
+// start triangle order_start[k] if that is set too; otherwise it is ray k.
 struct RaysDev {
   const double2* o;
   const double2* d;
@@ -60,7 +71,8 @@ struct RaysDev {
   int32_t* steps;
   int64_t n;
   const int32_t* order;
-  const int32_t* order_start;  // optional: internal start triangle of the ray at position k
+  const int32_t* order_start;
+  const RayRec* recs;
 };
 
 // One item of a batched launch: the scene, its rays and where its tiles start in the
@@ -90,9 +102,9 @@ constexpr int kClaimChunks = 8;  // tile counters per launch (one per XCD)
 
 // Binning: *out = `in` with out->order set to a cache-friendly walking order (see bin.hip for
 // the two keys). Needs bin_workspace_bytes(n) of scratch.
-enum { kKeyStart = 0, kKeyCoherent = 1 };
+enum { kBinBuckets = 0, kBinRadix = 2 };
 size_t bin_workspace_bytes(int64_t n);
-hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int key_kind, void* workspace,
+hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void* workspace,
                            size_t ws_bytes, RaysDev* out, hipStream_t stream);
 
 hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,

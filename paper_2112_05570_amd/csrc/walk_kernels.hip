@@ -181,24 +181,34 @@ __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, i
   int st[TPL];
   int64_t ri[TPL];
   double2 o[TPL], d[TPL];
+  const bool internal = io.recs != nullptr || io.order_start != nullptr;
 #pragma unroll
   for (int q = 0; q < TPL; ++q) {
     const int k = lane + 64 * q;
     st[q] = -1;
     ri[q] = base + k;
     if (k < len) {
-      if (io.order) ri[q] = io.order[base + k];
-      o[q] = io.o[ri[q]];
-      d[q] = io.d[ri[q]];
-      st[q] = io.order_start ? io.order_start[base + k] : io.start[ri[q]];
+      if (io.recs) {  // binned copies, read contiguously
+        const RayRec* r = io.recs + base + k;
+        o[q] = r->o;
+        d[q] = r->d;
+        const int2 si = *reinterpret_cast<const int2*>(&r->start);
+        st[q] = si.x;
+        ri[q] = si.y;
+      } else {
+        if (io.order) ri[q] = io.order[base + k];
+        o[q] = io.o[ri[q]];
+        d[q] = io.d[ri[q]];
+        st[q] = io.order_start ? io.order_start[base + k] : io.start[ri[q]];
+      }
     }
   }
 #pragma unroll
   for (int q = 0; q < TPL; ++q) {
     const int k = lane + 64 * q;
     if (k < len) {
-      if (io.order_start) {
-        if (st[q] >= sc.ntri) st[q] = -1;  // already internal (the binning sort's keys)
+      if (internal) {
+        if (st[q] >= sc.ntri) st[q] = -1;  // already an internal id (binning mapped it)
       } else {
         // the caller's triangle id -> internal (Hilbert-ordered) id
         st[q] = (st[q] >= 0 && st[q] < sc.ntri) ? sc.perm[st[q]] : -1;
@@ -298,7 +308,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   int64_t tbase = 0;
   int tlen = 0, thead = 0, titem = 0;
   bool drained = false;
-  bool io_order = io_arg.order != nullptr;
+  bool io_order = io_arg.order != nullptr || io_arg.recs != nullptr;
   int chunk_cur = (int)(blockIdx.x % (unsigned)chunks), chunk_tried = 0;
 
   for (;;) {
@@ -330,7 +340,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             tbase = (claim - it.tile_begin) * TILE;
             tlen = (int)min((int64_t)TILE, it.rays.n - tbase);
             thead = 0;
-            io_order = it.rays.order != nullptr;
+            io_order = it.rays.order != nullptr || it.rays.recs != nullptr;
             fill_tile<MODE, TPL, COUNT, false>(it.scene, it.rays, tbase, tlen, tl, lane, c, errflag);
           } else {
             tbase = claim * TILE;
