@@ -118,11 +118,12 @@ int load_triangulation(const TriangulationDesc *desc, void *stream, Triangulatio
  * start_tri n triangle ids; the outputs hit_prim, hit_t (8-byte aligned) and steps receive n
  * values each. d must be nonzero and the origin strictly inside start_tri. The call is
  * asynchronous on `stream` (except with CCSP_TRACE_VALIDATE).
- * Ray binning: unless CCSP_TRACE_INPUT_ORDER is set, n >= 65,536 rays are first sorted by a
- * spatial key of their start triangle (the result does not depend on it; only the order in which
- * rays are walked, hence cache reuse, does). It uses per-device scratch of about 16 bytes per ray,
- * allocated on the first trace larger than any before unless reserve_workspace() reserved it;
- * binned traces on different streams of one device are serialised on the device.
+ * Ray binning: unless CCSP_TRACE_INPUT_ORDER is set, a trace of n >= 65,536 rays through a
+ * triangulation of at least 262,144 triangles first groups the rays by the cell of their origin
+ * (the results do not depend on it; only the order in which rays are walked, hence cache reuse,
+ * does). It uses per-device scratch of about 48 bytes per ray, allocated on the first binned
+ * trace larger than any before unless reserve_workspace() reserved it; binned traces on
+ * different streams of one device are serialised on the device.
  */
 int trace_rays(const Triangulation *tri, const double *o_xy, const double *d_xy,
                const int32_t *start_tri, int64_t n, int precision, int32_t *hit_prim,

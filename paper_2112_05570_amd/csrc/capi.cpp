@@ -147,7 +147,9 @@ int device_state(DeviceState** out) {
   return CCSP_OK;
 }
 
+// Binning pays only when the scene does not fit the caches anyway and there are enough rays.
 constexpr int64_t kBinMinRays = 1 << 16;
+constexpr int64_t kBinMinTriangles = 1 << 18;
 
 // Tile counters of the next launch: a ring of kCounterSlots / kClaimChunks groups (the last group
 // is reserved for captured graphs), so that launches in flight on different streams never share.
@@ -179,10 +181,11 @@ LaunchCfg make_cfg(const DeviceState& ds, int mode, const TuneParams* tp) {
   LaunchCfg c{};
   c.wg = (tp && tp->wg_size) ? tp->wg_size : 256;
   c.tile = (tp && tp->tile_rays) ? tp->tile_rays : (mode == 1 ? 64 : 64);
-  const int wpcu = (tp && tp->waves_per_cu) ? tp->waves_per_cu : 16;
-  c.refill_min = (tp && tp->refill_min) ? tp->refill_min : 32;
+  const int wpcu = (tp && tp->waves_per_cu) ? tp->waves_per_cu : 24;
+  c.refill_min = (tp && tp->refill_min) ? tp->refill_min : 16;
   c.grid = std::max(1, ds.cus * wpcu / (c.wg / 64));
   c.chunks = (tp && tp->reserved[1] == 1) ? 1 : kClaimChunks;
+  c.group = (tp && tp->reserved[3] > 0) ? tp->reserved[3] : 4;
   return c;
 }
 
@@ -190,6 +193,7 @@ int check_cfg(const LaunchCfg& c) {
   if (c.wg < 64 || c.wg > 512 || c.wg % 64) return fail(CCSP_E_ARG, "wg_size %d must be 64..512, multiple of 64", c.wg);
   if (c.tile != 64 && c.tile != 128 && c.tile != 256) return fail(CCSP_E_ARG, "tile_rays %d must be 64, 128 or 256", c.tile);
   if (c.refill_min < 1 || c.refill_min > 64) return fail(CCSP_E_ARG, "refill_min %d must be 1..64", c.refill_min);
+  if (c.group < 1 || c.group > 4096) return fail(CCSP_E_ARG, "tile group %d must be 1..4096", c.group);
   return CCSP_OK;
 }
 
@@ -335,7 +339,8 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   const size_t off_s32 = 0;
   const size_t off_s64 = align(off_s32 + sizeof(Slot32) * 3 * T);
   const size_t off_txy = align(off_s64 + sizeof(Slot64) * 3 * T);
-  const size_t off_tv = align(off_txy + sizeof(TriXY32) * T);
+  const size_t off_txy64 = align(off_txy + sizeof(TriXY32) * T);
+  const size_t off_tv = align(off_txy64 + sizeof(TriXY64) * T);
   const size_t off_v = align(off_tv + sizeof(int4) * T);
   const size_t off_p = align(off_v + sizeof(double2) * V);
   const size_t off_perm = align(off_p + sizeof(PrimRec) * std::max<int64_t>(P, 1));
@@ -344,6 +349,7 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   auto* s32 = reinterpret_cast<Slot32*>(host.data() + off_s32);
   auto* s64 = reinterpret_cast<Slot64*>(host.data() + off_s64);
   auto* txy = reinterpret_cast<TriXY32*>(host.data() + off_txy);
+  auto* txy64 = reinterpret_cast<TriXY64*>(host.data() + off_txy64);
   auto* t4 = reinterpret_cast<int4*>(host.data() + off_tv);
   std::memcpy(host.data() + off_v, xy, sizeof(double) * 2 * V);
   auto* prec = reinterpret_cast<PrimRec*>(host.data() + off_p);
@@ -365,6 +371,12 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
         txy[nt].x[i] = (float)(xy[2 * (int64_t)v[i]] - org[0]);
         txy[nt].y[i] = (float)(xy[2 * (int64_t)v[i] + 1] - org[1]);
       }
+      txy64[nt].x0 = xy[2 * (int64_t)v[0]];
+      txy64[nt].y0 = xy[2 * (int64_t)v[0] + 1];
+      txy64[nt].x1 = xy[2 * (int64_t)v[1]];
+      txy64[nt].y1 = xy[2 * (int64_t)v[1] + 1];
+      txy64[nt].x2 = xy[2 * (int64_t)v[2]];
+      txy64[nt].y2 = xy[2 * (int64_t)v[2] + 1];
       for (int i = 0; i < 3; ++i) {
         const int64_t k = 3 * nt + i;
         const int32_t n = tn[3 * t + i], pr = tp[3 * t + i];
@@ -420,6 +432,7 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   tri->dev.slot32 = reinterpret_cast<const Slot32*>(base + off_s32);
   tri->dev.slot64 = reinterpret_cast<const Slot64*>(base + off_s64);
   tri->dev.trixy = reinterpret_cast<const TriXY32*>(base + off_txy);
+  tri->dev.trixy64 = reinterpret_cast<const TriXY64*>(base + off_txy64);
   tri->dev.triv = reinterpret_cast<const int4*>(base + off_tv);
   tri->dev.v64 = reinterpret_cast<const double2*>(base + off_v);
   tri->dev.prim = reinterpret_cast<const PrimRec*>(base + off_p);
@@ -491,7 +504,8 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
              start_tri, hit_prim, hit_t, steps, n, nullptr};
   unsigned long long* counter = next_counters(ds);
   hipError_t e;
-  const bool bin = !(precision & CCSP_TRACE_INPUT_ORDER) && n >= kBinMinRays && n < INT32_MAX;
+  const bool bin = !(precision & CCSP_TRACE_INPUT_ORDER) && n >= kBinMinRays && n < INT32_MAX &&
+                   tri->nt >= kBinMinTriangles;
   std::unique_lock<std::mutex> bin_lock(ds->bin_mu, std::defer_lock);
   if (bin) {
     bin_lock.lock();

@@ -35,10 +35,16 @@ struct alignas(16) PrimRec {
   int32_t pad[3];
 };
 
+struct alignas(64) TriXY64 {  // own vertices in binary64 (first step of the binary64 walk)
+  double x0, y0, x1, y1, x2, y2;
+  double pad[2];
+};
+
 struct SceneDev {
-  const Slot32* slot32;  // 3T
-  const Slot64* slot64;  // 3T
-  const TriXY32* trixy;  // T
+  const Slot32* slot32;    // 3T
+  const Slot64* slot64;    // 3T
+  const TriXY32* trixy;    // T
+  const TriXY64* trixy64;  // T
   const int4* triv;      // T: v0, v1, v2, 0
   const double2* v64;    // V
   const PrimRec* prim;   // P, internal order (first met along the Hilbert order of triangles)
@@ -89,6 +95,7 @@ struct LaunchCfg {
   int grid;        // workgroups
   int refill_min;  // idle lanes that trigger a refill
   int chunks;      // the tile sequence is split into this many chunks, one per XCD (1 or 8)
+  int group;       // tiles claimed per atomic
 };
 
 // Per-device scratch used by the walk: tile counters and the diagnostic counters.

@@ -97,38 +97,6 @@ __device__ __attribute__((noinline)) bool validate_ray(const SceneDev& sc, doubl
   return ok;
 }
 
-// Exit slot of the start triangle (3*st + edge), or -1 if st is out of range, no edge qualifies
-// or (VALIDATE) the origin is not strictly inside / the direction is zero or not finite.
-// The exit edge i is the one whose first endpoint is RIGHT of the ray and second LEFT.
-template <bool COUNT>
-__device__ __forceinline__ int first_exit32(const SceneDev& sc, double2 o, double2 d,
-                                            const Ray32& r, int st, Counters& c) {
-  const float4* p = reinterpret_cast<const float4*>(sc.trixy + st);
-  const float4 a = p[0], b = p[1];
-  int s0 = side32(r, a.x, a.w), s1 = side32(r, a.y, b.x), s2 = side32(r, a.z, b.y);
-  if ((s0 == 0) | (s1 == 0) | (s2 == 0)) {
-    const int4 tv = sc.triv[st];
-    if (s0 == 0) { if (COUNT) ++c.fb32; s0 = left_deferred<COUNT>(o, d, sc.v64, tv.x, &c.fb64) ? 1 : -1; }
-    if (s1 == 0) { if (COUNT) ++c.fb32; s1 = left_deferred<COUNT>(o, d, sc.v64, tv.y, &c.fb64) ? 1 : -1; }
-    if (s2 == 0) { if (COUNT) ++c.fb32; s2 = left_deferred<COUNT>(o, d, sc.v64, tv.z, &c.fb64) ? 1 : -1; }
-  }
-  const bool L0 = s0 > 0, L1 = s1 > 0, L2 = s2 > 0;
-  const int e = (!L1 && L2) ? 0 : ((!L2 && L0) ? 1 : ((!L0 && L1) ? 2 : -1));
-  return e < 0 ? -1 : 3 * st + e;
-}
-
-template <bool COUNT>
-__device__ __forceinline__ int first_exit64(const SceneDev& sc, double2 o, double2 d, int st,
-                                            Counters& c) {
-  const int4 tv = sc.triv[st];
-  const double2 v0 = sc.v64[tv.x], v1 = sc.v64[tv.y], v2 = sc.v64[tv.z];
-  const bool L0 = left64<COUNT>(o.x, o.y, d.x, d.y, v0.x, v0.y, c.fb64);
-  const bool L1 = left64<COUNT>(o.x, o.y, d.x, d.y, v1.x, v1.y, c.fb64);
-  const bool L2 = left64<COUNT>(o.x, o.y, d.x, d.y, v2.x, v2.y, c.fb64);
-  const int e = (!L1 && L2) ? 0 : ((!L2 && L0) ? 1 : ((!L0 && L1) ? 2 : -1));
-  return e < 0 ? -1 : 3 * st + e;
-}
-
 __device__ __forceinline__ double hit_t(const double4 g, double ox, double oy, double dx,
                                         double dy) {
   const double ex = g.z - g.x;
@@ -136,6 +104,14 @@ __device__ __forceinline__ double hit_t(const double4 g, double ox, double oy, d
   const double num = (g.x - ox) * ey - (g.y - oy) * ex;
   const double den = dx * ey - dy * ex;
   return num / den;
+}
+
+__device__ __forceinline__ double lohi(int lo, int hi) { return __hiloint2double(hi, lo); }
+
+// The exit edge i of the first triangle is the one whose first endpoint is RIGHT of the ray and
+// whose second is LEFT (three candidates: nothing is known about the entry).
+__device__ __forceinline__ int first_edge(bool L0, bool L1, bool L2) {
+  return (!L1 && L2) ? 0 : ((!L2 && L0) ? 1 : ((!L0 && L1) ? 2 : -1));
 }
 
 // ------------------------------------------------------------------------------ persistent walk
@@ -158,26 +134,26 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Per-wave LDS tile: the ray (2 x double2), its first exit slot and its index, 40 B/ray.
+// Per-wave LDS tile: the ray (2 x double2), its internal start triangle and its index, 40 B/ray.
 template <int TILE>
 struct Tile {
   static constexpr int kBytes = 40 * TILE;
   double2* o;
   double2* d;
-  int* s0;
+  int* st;
   int* idx;
   __device__ explicit Tile(unsigned char* base)
       : o(reinterpret_cast<double2*>(base)),
         d(reinterpret_cast<double2*>(base + 16 * TILE)),
-        s0(reinterpret_cast<int*>(base + 32 * TILE)),
+        st(reinterpret_cast<int*>(base + 32 * TILE)),
         idx(reinterpret_cast<int*>(base + 36 * TILE)) {}
 };
 
-// Load rays [base, base+len) of `io` into the tile and compute their first exit slots.
-template <int MODE, int TPL, bool COUNT, bool VALIDATE>
+// Load rays [base, base+len) of `io` into the tile: one round of loads (plus the id map for rays
+// that were not binned). Their first triangle is handled by the walk loop itself.
+template <int TPL, bool VALIDATE>
 __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, int len,
-                          const Tile<TPL * 64>& tl, int lane, Counters& c, int* errflag) {
-  // phase 1: all loads of the tile in flight together
+                          const Tile<TPL * 64>& tl, int lane, int* errflag) {
   int st[TPL];
   int64_t ri[TPL];
   double2 o[TPL], d[TPL];
@@ -213,31 +189,14 @@ __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, i
         // the caller's triangle id -> internal (Hilbert-ordered) id
         st[q] = (st[q] >= 0 && st[q] < sc.ntri) ? sc.perm[st[q]] : -1;
       }
-      tl.o[k] = o[q];
-      tl.d[k] = d[q];
-      tl.idx[k] = (int)ri[q];
       if (VALIDATE && (st[q] < 0 || !validate_ray(sc, o[q], d[q], st[q]))) {
         atomicOr(errflag, 1);
         st[q] = -1;
       }
-    }
-  }
-  // phase 2: first triangle of each ray
-#pragma unroll
-  for (int q = 0; q < TPL; ++q) {
-    const int k = lane + 64 * q;
-    if (k < len) {
-      int s0 = -1;
-      if (st[q] >= 0) {
-        if (MODE == 1) {
-          const Ray32 rr{(float)(o[q].x - sc.org_x), (float)(o[q].y - sc.org_y), (float)d[q].x,
-                         (float)d[q].y};
-          s0 = first_exit32<COUNT>(sc, o[q], d[q], rr, st[q], c);
-        } else {
-          s0 = first_exit64<COUNT>(sc, o[q], d[q], st[q], c);
-        }
-      }
-      tl.s0[k] = s0;
+      tl.o[k] = o[q];
+      tl.d[k] = d[q];
+      tl.st[k] = st[q];
+      tl.idx[k] = (int)ri[q];
     }
   }
   wave_lds_fence();
@@ -270,10 +229,16 @@ __device__ __forceinline__ long long claim_tile(unsigned long long* counter, int
   return -1;
 }
 
+// Each lane is a small state machine that issues exactly one round of loads per iteration:
+//   FIRST: the own vertices of the start triangle (then three decisions, Sec. 5.4's first step),
+//   WALK:  the slot of the exit edge (then one decision: the vertex across the entry edge),
+//   FIN:   the hit primitive's record (then the hit distance and the results),
+// so lanes in different states share one memory round trip, and a refilled lane starts walking
+// in the next iteration without a separate gather phase.
 template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH>
 __global__ void __launch_bounds__(512)
 walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_tiles,
-                unsigned long long* __restrict__ counter, int refill_min, int chunks,
+                unsigned long long* __restrict__ counter, int refill_min, int chunks, int group,
                 unsigned long long* __restrict__ stats, int* __restrict__ errflag) {
   constexpr int TILE = TPL * 64;
   extern __shared__ unsigned char lds[];
@@ -291,12 +256,11 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   const Tile<TILE> tl(tile_mem + (size_t)wave * Tile<TILE>::kBytes);
 
   Counters c;
-  // lane state: IDLE (no ray), WALK (s is the exit slot to load), FIN (hit primitive p to load)
-  enum : int { IDLE = 0, WALK = 1, FIN = 2 };
+  enum : int { IDLE = 0, FIRST = 1, WALK = 2, FIN = 3 };
   int state = IDLE;
   Ray32 r32{0, 0, 0, 0};                  // binary32 mode
   double ox = 0, oy = 0, dx = 0, dy = 0;  // the ray in binary64
-  int s = 0, steps = 0;
+  int s = 0, steps = 0;                   // s: start triangle (FIRST), exit slot (WALK), prim (FIN)
   int64_t ray = 0;
   int item = 0;
   // per-lane scene in a batch, kernel argument otherwise
@@ -310,6 +274,10 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   bool drained = false;
   bool io_order = io_arg.order != nullptr || io_arg.recs != nullptr;
   int chunk_cur = (int)(blockIdx.x % (unsigned)chunks), chunk_tried = 0;
+  // tiles are claimed `group` at a time (one global atomic per group): same-address atomics
+  // from thousands of waves serialise, and one per tile would stall every refill
+  const long long total_groups = (total_tiles + group - 1) / group;
+  long long grp_next = 0, grp_end = 0;
 
   for (;;) {
     const unsigned long long idle = __ballot(state == IDLE);
@@ -320,11 +288,16 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
       int served = 0;
       while (served < nidle) {
         if (thead == tlen) {
-          const long long claim = claim_tile(counter, chunks, total_tiles, chunk_cur, chunk_tried, lane);
-          if (claim < 0) {
-            drained = true;
-            break;
+          if (grp_next == grp_end) {
+            const long long g = claim_tile(counter, chunks, total_groups, chunk_cur, chunk_tried, lane);
+            if (g < 0) {
+              drained = true;
+              break;
+            }
+            grp_next = g * group;
+            grp_end = min(grp_next + group, (long long)total_tiles);
           }
+          const long long claim = grp_next++;
           if (BATCH) {
             // item owning tile `claim`: the last item whose tile_begin <= claim
             int lo = 0, hi = batch.n_items - 1;
@@ -341,12 +314,12 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             tlen = (int)min((int64_t)TILE, it.rays.n - tbase);
             thead = 0;
             io_order = it.rays.order != nullptr || it.rays.recs != nullptr;
-            fill_tile<MODE, TPL, COUNT, false>(it.scene, it.rays, tbase, tlen, tl, lane, c, errflag);
+            fill_tile<TPL, false>(it.scene, it.rays, tbase, tlen, tl, lane, errflag);
           } else {
             tbase = claim * TILE;
             tlen = (int)min((int64_t)TILE, io_arg.n - tbase);
             thead = 0;
-            fill_tile<MODE, TPL, COUNT, VALIDATE>(sc_arg, io_arg, tbase, tlen, tl, lane, c, errflag);
+            fill_tile<TPL, VALIDATE>(sc_arg, io_arg, tbase, tlen, tl, lane, errflag);
           }
         }
         const int take = min(nidle - served, tlen - thead);
@@ -356,10 +329,10 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             const double2 o = tl.o[k], d = tl.d[k];
             ox = o.x; oy = o.y; dx = d.x; dy = d.y;
           }
-          s = tl.s0[k];
+          s = tl.st[k];
           ray = io_order ? (int64_t)tl.idx[k] : tbase + k;
           steps = 1;
-          state = WALK;
+          state = FIRST;
           double org_x = sc_arg.org_x, org_y = sc_arg.org_y;
           if (BATCH) {
             item = titem;
@@ -371,7 +344,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             org_y = sc.org_y;
           }
           if (MODE == 1) r32 = Ray32{(float)(ox - org_x), (float)(oy - org_y), (float)dx, (float)dy};
-          if (s < 0) {  // bad ray: out-of-range start, no exit edge, or failed validation
+          if (s < 0) {  // bad ray: out-of-range start or failed validation
             const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
             io.prim[ray] = -3;
             io.t[ray] = INFINITY;
@@ -383,48 +356,56 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         thead += take;
       }
     }
-    // Issue this iteration's loads before using any: a walking lane loads its exit slot, a
-    // finishing lane its hit primitive, so both share one memory round trip.
+    // ---- issue: one round of loads for every busy lane, whatever its state
     const int st_now = state;
-    int4 q = make_int4(0, 0, 0, 0);
-    double2 xy64 = make_double2(0.0, 0.0);
-    double2 ga = make_double2(0.0, 0.0), gb = make_double2(0.0, 0.0);
-    int gid = 0;
+    int4 R0 = make_int4(0, 0, 0, 0), R1 = R0, R2 = R0;
     if (st_now == WALK) {
       if (MODE == 1) {
-        q = *reinterpret_cast<const int4*>(slot32 + s);
-        // Keep the slot one 16-byte load: without this the compiler loads the exit word alone,
-        // branches on it and only then loads the vertex, a second dependent round trip.
-        __asm__ volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
+        R0 = *reinterpret_cast<const int4*>(slot32 + s);
       } else {
-        xy64 = *reinterpret_cast<const double2*>(slot64 + s);
-        q.x = *reinterpret_cast<const int*>(&slot64[s].word);
-        __asm__ volatile("" ::"v"(xy64.x), "v"(xy64.y), "v"(q.x));
+        const int4* p = reinterpret_cast<const int4*>(slot64 + s);
+        R0 = p[0];
+        R1 = p[1];
+      }
+    } else if (st_now == FIRST) {
+      if (MODE == 1) {
+        const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.trixy : sc_arg.trixy) + s);
+        R0 = p[0];
+        R1 = p[1];
+      } else {
+        const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.trixy64 : sc_arg.trixy64) + s);
+        R0 = p[0];
+        R1 = p[1];
+        R2 = p[2];
       }
     } else if (st_now == FIN) {
-      const PrimRec* prim = BATCH ? batch.items[item].scene.prim : sc_arg.prim;
-      const PrimRec* g = prim + s;
-      ga = *reinterpret_cast<const double2*>(&g->ax);
-      gb = *reinterpret_cast<const double2*>(&g->bx);
-      gid = g->id;
-      __asm__ volatile("" ::"v"(ga.x), "v"(ga.y), "v"(gb.x), "v"(gb.y), "v"(gid));
+      const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.prim : sc_arg.prim) + s);
+      R0 = p[0];
+      R1 = p[1];
+      R2 = p[2];
     }
+    // every load above is issued before any result is used (and none is split per field)
+    __asm__ volatile("" ::"v"(R0.x), "v"(R0.y), "v"(R0.z), "v"(R0.w), "v"(R1.x), "v"(R1.y),
+                     "v"(R1.z), "v"(R1.w), "v"(R2.x), "v"(R2.y), "v"(R2.z), "v"(R2.w));
+    // ---- process
     if (st_now == WALK) {
-      const int word = q.x;
+      int word;
       bool left = false;
-      if (word >= 0) {
-        if (MODE == 1) {
-          const int sg = side32(r32, __int_as_float(q.y), __int_as_float(q.z));
+      if (MODE == 1) {
+        word = R0.x;
+        const int sg = side32(r32, __int_as_float(R0.y), __int_as_float(R0.z));
+        if (word >= 0) {
           if (sg != 0) {
             left = sg > 0;
           } else {
             if (COUNT) ++c.fb32;
             const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
-            left = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64, q.w, &c.fb64);
+            left = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64, R0.w, &c.fb64);
           }
-        } else {
-          left = left64<COUNT>(ox, oy, dx, dy, xy64.x, xy64.y, c.fb64);
         }
+      } else {
+        word = R1.x;
+        if (word >= 0) left = left64<COUNT>(ox, oy, dx, dy, lohi(R0.x, R0.y), lohi(R0.z, R0.w), c.fb64);
       }
       if (word >= 0 && steps < ntri) {
         ++steps;
@@ -446,11 +427,51 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         }
         state = IDLE;
       }
+    } else if (st_now == FIRST) {
+      bool L0, L1, L2;
+      if (MODE == 1) {
+        // TriXY32: x0 x1 x2 y0 | y1 y2 - -
+        int s0 = side32(r32, __int_as_float(R0.x), __int_as_float(R0.w));
+        int s1 = side32(r32, __int_as_float(R0.y), __int_as_float(R1.x));
+        int s2 = side32(r32, __int_as_float(R0.z), __int_as_float(R1.y));
+        if ((s0 == 0) | (s1 == 0) | (s2 == 0)) {
+          const SceneDev& sc = BATCH ? batch.items[item].scene : sc_arg;
+          const int4 tv = sc.triv[s];
+          const double2 o = make_double2(ox, oy), d = make_double2(dx, dy);
+          if (s0 == 0) { if (COUNT) ++c.fb32; s0 = left_deferred<COUNT>(o, d, sc.v64, tv.x, &c.fb64) ? 1 : -1; }
+          if (s1 == 0) { if (COUNT) ++c.fb32; s1 = left_deferred<COUNT>(o, d, sc.v64, tv.y, &c.fb64) ? 1 : -1; }
+          if (s2 == 0) { if (COUNT) ++c.fb32; s2 = left_deferred<COUNT>(o, d, sc.v64, tv.z, &c.fb64) ? 1 : -1; }
+        }
+        L0 = s0 > 0;
+        L1 = s1 > 0;
+        L2 = s2 > 0;
+      } else {
+        // TriXY64: x0 y0 | x1 y1 | x2 y2
+        L0 = left64<COUNT>(ox, oy, dx, dy, lohi(R0.x, R0.y), lohi(R0.z, R0.w), c.fb64);
+        L1 = left64<COUNT>(ox, oy, dx, dy, lohi(R1.x, R1.y), lohi(R1.z, R1.w), c.fb64);
+        L2 = left64<COUNT>(ox, oy, dx, dy, lohi(R2.x, R2.y), lohi(R2.z, R2.w), c.fb64);
+      }
+      const int e = first_edge(L0, L1, L2);
+      if (e >= 0) {
+        s = 3 * s + e;
+        state = WALK;
+      } else {  // no exit edge: the origin is not inside the start triangle
+        const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
+        io.prim[ray] = -3;
+        io.t[ray] = INFINITY;
+        io.steps[ray] = 0;
+        state = IDLE;
+      }
     } else if (st_now == FIN) {
+      // Results go to the caller's (random, once binned) positions with non-temporal stores:
+      // they are never read again here, so they should not displace the scene in the L2.
       const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
-      io.prim[ray] = gid;
-      io.t[ray] = hit_t(make_double4(ga.x, ga.y, gb.x, gb.y), ox, oy, dx, dy);
-      io.steps[ray] = steps;
+      __builtin_nontemporal_store(R2.x, io.prim + ray);
+      __builtin_nontemporal_store(hit_t(make_double4(lohi(R0.x, R0.y), lohi(R0.z, R0.w),
+                                                     lohi(R1.x, R1.y), lohi(R1.z, R1.w)),
+                                        ox, oy, dx, dy),
+                                  io.t + ray);
+      __builtin_nontemporal_store(steps, io.steps + ray);
       if (COUNT) {
         c.steps += steps;
         ++c.rays;
@@ -483,7 +504,7 @@ static hipError_t go(const SceneDev& sc, const RaysDev& io, ItemRef br, int64_t 
                      const Workspace& ws, hipStream_t stream) {
   hipLaunchKernelGGL((walk_persistent<MODE, TPL, COUNT, VALIDATE, BATCH>), dim3(cfg.grid),
                      dim3(cfg.wg), lds, stream, sc, io, br, total_tiles, counter, cfg.refill_min,
-                     cfg.chunks, ws.stats, ws.errflag);
+                     cfg.chunks, cfg.group, ws.stats, ws.errflag);
   return hipGetLastError();
 }
 

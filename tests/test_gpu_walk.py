@@ -259,6 +259,26 @@ def test_batch_with_empty_and_tiny_items(ccsp, tiny_scene, tiny_rays):
             _assert_same(_host(rs), ref, f"batch part n={p.n}")
 
 
+def test_binned_traces_on_two_streams(ccsp, grid_pair):
+    """Binned traces share the per-device scratch; traces on two streams must still be right."""
+    sc, _, rays, _ = grid_pair
+    r1, r2 = rays.slice(0, 300_000), rays.slice(300_000, 700_000)
+    with ccsp.Scene.from_arrays(sc) as scene:
+        d1, d2 = _dev(r1), _dev(r2)
+        ref1 = _host(ccsp.trace(scene, *d1, input_order=True))
+        ref2 = _host(ccsp.trace(scene, *d2, input_order=True))
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        torch.cuda.synchronize()
+        for _ in range(3):
+            with torch.cuda.stream(s1):
+                a = ccsp.trace(scene, *d1, stream=s1)
+            with torch.cuda.stream(s2):
+                b = ccsp.trace(scene, *d2, stream=s2, precision="fp64")
+            torch.cuda.synchronize()
+            _assert_same(_host(a), ref1, "binned stream 1")
+            _assert_same(_host(b), ref2, "binned stream 2")
+
+
 def test_concurrent_streams(ccsp, tiny_scene, tiny_rays):
     ref = oracle.walk(oracle.Triangulation.of(tiny_scene), tiny_rays.o, tiny_rays.d, tiny_rays.start)
     with ccsp.Scene.from_arrays(tiny_scene) as scene:
