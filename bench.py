@@ -6,10 +6,12 @@ log-U[0.01, 1], box [-1,1001]^2, constrained Delaunay triangulation with 4,000,0
 rays (the whole walk: first triangle, steps, hit distance), inputs resident in HBM.
 
 Prints one JSON line: rays/s of the binary32-filtered walk (value), steps/s, the binary64 walk's
-rays/s on the same inputs, the roofline of the walk kernel (HIP events on its stream), and the
-checker's throughput on the host cores for a bounded sample of the same rays.
+rays/s on the same inputs, the roofline of the walk kernel (its own duration from HIP events the
+library records on the trace's stream around it), the dependent-gather roofline measured on this
+GPU, and the checker's throughput on the host cores for a bounded sample of the same rays.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -19,8 +21,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-BYTES_PER_STEP = 16          # opposite-vertex id + binary32 xy + exit word
-BYTES_PER_RAY = 100          # ray in (36) + result out (16) + first-triangle vertices + primitive
+# Algorithmic bytes of the walk kernel: per step the exit word, the across vertex in binary32 and
+# its id; per ray its input (origin, direction, start triangle: 36), the two first-triangle
+# vertices beyond the one a step would read (16) and the parked result (8). The finishing pass
+# (primitive record, hit distance, the three outputs) is a separate kernel.
+BYTES_PER_STEP = 16
+BYTES_PER_RAY = 60
+
+# HBM traffic of one binary32 walk launch on the large workload, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE passes (profiles/walk_fp32_large_pmc.md), each scaled by what the same counter reports
+# for a plain copy of known size. Valid only for the kernel sources it was taken on.
+WALK_SOURCES = ("walk_kernels.hip", "walk.hpp", "exact.hpp")
+MEASURED_TRAFFIC = {"sources_sha256": "", "bytes_per_launch": None}
+
+
+def walk_sources_sha256():
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        with open(os.path.join(ROOT, "paper_2112_05570_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -40,9 +60,14 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling HBM "
                          "counters of a profiler run)")
+    ap.add_argument("--gather-sweep", action="store_true",
+                    help="only measure the dependent-gather roofline over a range of buffer sizes")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.gather_sweep:
+        gather_sweep()
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -83,22 +108,27 @@ def main():
         for _ in range(w):
             ccsp.trace(scene, o, d, st, precision=prec, out=out, tune=tune, stream=stream)
         torch.cuda.synchronize()
+        ccsp.read_stage_times()  # forget older records
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(k)]
         t = time.perf_counter()
         for a, b in evs:
             a.record(stream)
-            ccsp.trace(scene, o, d, st, precision=prec, out=out, tune=tune, stream=stream)
+            ccsp.trace(scene, o, d, st, precision=prec, out=out, tune=tune, stream=stream,
+                       timed=True)
             b.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
-        kern = [a.elapsed_time(b) / 1e3 for a, b in evs]
-        return wall, kern
+        trace_s = [a.elapsed_time(b) / 1e3 for a, b in evs]
+        bin_ms, walk_ms, fin_ms = ccsp.read_stage_times(k)
+        assert len(walk_ms) == k
+        return (wall, trace_s, [x / 1e3 for x in bin_ms], [x / 1e3 for x in walk_ms],
+                [x / 1e3 for x in fin_ms])
 
-    wall32, k32 = timed("fp32", out32, args.steps, args.warmup)
+    wall32, tr32, bin32, walk32, fin32 = timed("fp32", out32, args.steps, args.warmup)
     log(f"[bench] fp32 walk: {args.steps} steps in {wall32:.3f}s")
-    wall64, k64 = timed("fp64", out64, max(1, args.steps // 2), 1)
-    log(f"[bench] fp64 walk: {len(k64)} steps in {wall64:.3f}s")
+    wall64, tr64, bin64, walk64, fin64 = timed("fp64", out64, max(1, args.steps // 2), 1)
+    log(f"[bench] fp64 walk: {len(tr64)} steps in {wall64:.3f}s")
     # the same walk without ray binning (rays walked in input order), for comparison
     for _ in range(1):
         ccsp.trace(scene, o, d, st, precision="fp32", out=out64, tune=tune, input_order=True)
@@ -122,9 +152,21 @@ def main():
 
     ms = wall32 / args.steps * 1e3
     rays_s = n * args.steps / wall32
-    kern_avg = float(np.mean(k32))
+    walk_avg = float(np.mean(walk32))
     alg_bytes = BYTES_PER_STEP * steps_total + BYTES_PER_RAY * n
-    achieved = alg_bytes / kern_avg / 1e9
+    achieved = alg_bytes / walk_avg / 1e9
+    traffic = None
+    if MEASURED_TRAFFIC["sources_sha256"] == walk_sources_sha256() and args.workload == "large" \
+            and not args.rays and not args.tune:
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+
+    # dependent-gather roofline: 16-byte pointer chases over the walk's binary32 slot array size
+    # and over an L2-sized buffer (what one XCD's share of binned rays touches at a time)
+    ws_bytes = 48 * sc.n_triangles
+    from paper_2112_05570_amd import binding as B
+    g_scene = B.gather_roofline(ws_bytes, 16, 2048, stream.cuda_stream)
+    g_l2 = B.gather_roofline(2 << 20, 16, 2048, stream.cuda_stream)
+    walk_steps_s = steps_total / walk_avg
 
     cpu = None
     if not args.no_cpu:
@@ -151,17 +193,30 @@ def main():
         },
         "steps_per_s": steps_total * args.steps / wall32,
         "mean_steps_per_ray": steps_total / n,
-        "fp64": {"rays_per_s": n * len(k64) / wall64, "ms_per_step": wall64 / len(k64) * 1e3,
-                 "steps_per_s": steps_total * len(k64) / wall64},
+        "ms_per_step_median": float(np.median(tr32)) * 1e3,
+        "stages_ms": {"binning": float(np.mean(bin32)) * 1e3, "walk": walk_avg * 1e3,
+                      "walk_median": float(np.median(walk32)) * 1e3,
+                      "finish": float(np.mean(fin32)) * 1e3},
+        "fp64": {"rays_per_s": n * len(tr64) / wall64, "ms_per_step": wall64 / len(tr64) * 1e3,
+                 "steps_per_s": steps_total * len(tr64) / wall64,
+                 "stages_ms": {"binning": float(np.mean(bin64)) * 1e3,
+                               "walk": float(np.mean(walk64)) * 1e3,
+                               "finish": float(np.mean(fin64)) * 1e3}},
         "fp32_input_order_ms_per_step": ms_io,
         "fp32_equals_fp64": same,
         "fallback": {"fp32_to_fp64_per_step": c_fb32 / max(1, c_steps),
                      "fp64_to_exact_per_step": c_fb64 / max(1, c_steps)},
         "rays_not_hit": n_bad,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel_ms": kern_avg * 1e3,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "walk_persistent (binary32)", "kernel_ms": walk_avg * 1e3,
                      "bytes_per_launch": alg_bytes},
+        "gather_roofline": {
+            "walk_steps_per_s": walk_steps_s,
+            "chase_loads_per_s_scene_sized": g_scene, "scene_sized_bytes": ws_bytes,
+            "frac_scene_sized": walk_steps_s / g_scene,
+            "chase_loads_per_s_l2_sized": g_l2, "l2_sized_bytes": 2 << 20,
+            "frac_l2_sized": walk_steps_s / g_l2},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -179,6 +234,17 @@ def copy_calibration(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+
+
+def gather_sweep():
+    """Sustained 16-byte dependent loads per second of persistent pointer-chasing waves, by buffer
+    size (the memory pattern of one walk step) and resident waves per compute unit."""
+    import torch  # noqa: F401  (binds the HIP runtime first)
+    from paper_2112_05570_amd import binding as B
+    for ws in (1 << 21, 1 << 22, 1 << 23, 1 << 25, 1 << 27, 1 << 30, 1 << 32):
+        for wpc in (8, 16, 24, 32):
+            r = B.gather_roofline(ws, wpc, 2048)
+            print(json.dumps({"buffer_bytes": ws, "waves_per_cu": wpc, "loads_per_s": r}), flush=True)
 
 
 def cpu_leg(sc, rays, budget_s):

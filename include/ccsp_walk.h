@@ -74,8 +74,10 @@ enum {
   CCSP_TRACE_VALIDATE = 1 << 8, /* check every ray's precondition exactly; synchronises the
                                    stream and returns CCSP_E_BAD_RAY if any ray fails it */
   CCSP_TRACE_COUNT = 1 << 9,    /* accumulate the counters read by read_counters() */
-  CCSP_TRACE_INPUT_ORDER = 1 << 10 /* walk rays in input order; by default a trace of at least
-                                      65,536 rays first bins them by start triangle (see below) */
+  CCSP_TRACE_INPUT_ORDER = 1 << 10, /* walk rays in input order instead of binning them first
+                                       (see trace_rays) */
+  CCSP_TRACE_TIMED = 1 << 11        /* record HIP events on the stream around the stages of this
+                                       trace, for read_stage_times() */
 };
 
 typedef struct Triangulation Triangulation; /* opaque; owns its device memory */
@@ -173,6 +175,20 @@ const char *last_error(void);
  * Synchronises the device. reset != 0 clears them after reading.
  */
 int read_counters(uint64_t out[4], int reset);
+
+/*
+ * read_stage_times: stage durations of the most recent traces made with CCSP_TRACE_TIMED on the
+ * current device, oldest first, measured with HIP events on each trace's stream. bin_ms[i] runs
+ * from the start of the trace to the start of the walk kernel (the ray binning; about zero for a
+ * trace that does not bin; the item-table upload for trace_batch), walk_ms[i] covers the walk
+ * kernel alone (a whole replayed graph for trace_batch with a graph), finish_ms[i] the finishing
+ * pass that writes a single trace's results (zero for trace_batch, which finishes in the walk).
+ * The library keeps the last 256 timed traces per device; this call writes up to max_records of
+ * the most recent ones, sets *n_records to their number, and forgets all kept records. Blocks
+ * until those traces finish.
+ */
+int read_stage_times(int32_t max_records, float *bin_ms, float *walk_ms, float *finish_ms,
+                     int32_t *n_records);
 
 /* triangulation_info: out[0] triangles, out[1] vertices, out[2] primitives, out[3] device bytes. */
 int triangulation_info(const Triangulation *tri, int64_t out[4]);

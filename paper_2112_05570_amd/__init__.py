@@ -14,7 +14,8 @@ import numpy as np
 from . import binding as B
 from .binding import (CCSP_RAY_BAD, CCSP_RAY_GUARD, CCSP_RAY_MISS, CCSP_TRACE_COUNT,
                       CCSP_TRACE_FP32_FILTERED, CCSP_TRACE_FP64, CCSP_TRACE_INPUT_ORDER,
-                      CCSP_TRACE_VALIDATE, CcspError, TuneParams, reserve_workspace)
+                      CCSP_TRACE_TIMED, CCSP_TRACE_VALIDATE, CcspError, TuneParams,
+                      read_stage_times, reserve_workspace)
 
 PRECISION = {"fp64": CCSP_TRACE_FP64, "fp32": CCSP_TRACE_FP32_FILTERED}
 
@@ -99,13 +100,15 @@ def _check_rays(o, d, start):
 
 def trace(scene: Scene, o, d, start, precision="fp32", out: Result | None = None, stream=None,
           tune: TuneParams | None = None, validate=False, count=False,
-          input_order=False) -> Result:
+          input_order=False, timed=False) -> Result:
     """Walk rays (o, d: (n,2) float64; start: (n,) int32 CUDA tensors). Asynchronous.
-    input_order=True walks the rays in the given order instead of binning them spatially."""
+    input_order=True walks the rays in the given order instead of binning them spatially;
+    timed=True records the stage durations read by read_stage_times()."""
     n = _check_rays(o, d, start)
     res = _outputs(n, o.device, out)
     mode = (_mode(precision) | (CCSP_TRACE_VALIDATE if validate else 0)
-            | (CCSP_TRACE_COUNT if count else 0) | (CCSP_TRACE_INPUT_ORDER if input_order else 0))
+            | (CCSP_TRACE_COUNT if count else 0) | (CCSP_TRACE_INPUT_ORDER if input_order else 0)
+            | (CCSP_TRACE_TIMED if timed else 0))
     B.trace_rays_tuned(scene.handle, o.data_ptr(), d.data_ptr(), start.data_ptr(), n, mode,
                        res.hit_prim.data_ptr(), res.hit_t.data_ptr(), res.steps.data_ptr(), tune,
                        _stream(stream))
@@ -113,7 +116,7 @@ def trace(scene: Scene, o, d, start, precision="fp32", out: Result | None = None
 
 
 def trace_batch(jobs, precision="fp32", tune: TuneParams | None = None, stream=None,
-                graph=False, count=False):
+                graph=False, count=False, timed=False):
     """jobs: list of (Scene, o, d, start[, Result]). Returns the list of Results."""
     items, results = [], []
     for job in jobs:
@@ -128,8 +131,8 @@ def trace_batch(jobs, precision="fp32", tune: TuneParams | None = None, stream=N
         tune = tune or TuneParams()
         tune = TuneParams(tune.wg_size, tune.tile_rays, tune.waves_per_cu, tune.refill_min,
                           (ctypes.c_int32 * 4)(1, 0, 0, 0))
-    B.trace_batch(items, _mode(precision) | (CCSP_TRACE_COUNT if count else 0), tune,
-                  _stream(stream))
+    B.trace_batch(items, _mode(precision) | (CCSP_TRACE_COUNT if count else 0)
+                  | (CCSP_TRACE_TIMED if timed else 0), tune, _stream(stream))
     return results
 
 

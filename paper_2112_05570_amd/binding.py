@@ -38,10 +38,11 @@ CCSP_TRACE_FP32_FILTERED = 1
 CCSP_TRACE_VALIDATE = 1 << 8
 CCSP_TRACE_COUNT = 1 << 9
 CCSP_TRACE_INPUT_ORDER = 1 << 10
+CCSP_TRACE_TIMED = 1 << 11
 
 EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch",
            "free_triangulation", "last_error", "read_counters", "triangulation_info",
-           "reserve_workspace", "gather_roofline")
+           "reserve_workspace", "gather_roofline", "read_stage_times")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -87,6 +88,10 @@ _lib.reserve_workspace.argtypes = [_I64]
 _lib.reserve_workspace.restype = _I
 _lib.gather_roofline.argtypes = [_I64, ctypes.c_int32, _I64, ctypes.POINTER(ctypes.c_double), _P]
 _lib.gather_roofline.restype = _I
+_lib.read_stage_times.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                  ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                  ctypes.POINTER(ctypes.c_int32)]
+_lib.read_stage_times.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -139,6 +144,17 @@ def read_counters(reset: bool = False) -> list:
     out = (ctypes.c_uint64 * 4)()
     _check(_lib.read_counters(ctypes.byref(out), int(reset)))
     return list(out)
+
+
+def read_stage_times(max_records: int = 256) -> tuple:
+    """(bin_ms, walk_ms, finish_ms) lists of the most recent CCSP_TRACE_TIMED traces, oldest
+    first."""
+    b = (ctypes.c_float * max(1, max_records))()
+    w = (ctypes.c_float * max(1, max_records))()
+    f = (ctypes.c_float * max(1, max_records))()
+    n = ctypes.c_int32()
+    _check(_lib.read_stage_times(max_records, b, w, f, ctypes.byref(n)))
+    return list(b[:n.value]), list(w[:n.value]), list(f[:n.value])
 
 
 def triangulation_info(tri: int) -> list:

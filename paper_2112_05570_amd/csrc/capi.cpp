@@ -96,6 +96,13 @@ uint32_t hilbert16(uint32_t x, uint32_t y) {
   return d;
 }
 
+// Events of one timed trace: start of the trace, start and end of the walk kernel, end of the
+// trace (after the finishing pass).
+struct StageEvents {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+constexpr int kTimeSlots = 256;
+
 struct DeviceState {
   bool init = false;
   int cus = 0;
@@ -114,6 +121,10 @@ struct DeviceState {
   size_t bin_ws_bytes = 0;
   hipEvent_t bin_free = nullptr;
   hipStream_t bin_last_stream = nullptr;
+  // stage timing (CCSP_TRACE_TIMED): a ring of the last kTimeSlots timed traces
+  std::mutex time_mu;
+  std::vector<StageEvents> tev;
+  int time_next = 0, time_count = 0;
 };
 
 std::mutex g_dev_mu;
@@ -174,6 +185,29 @@ int grow_bin_workspace(DeviceState* ds, int64_t n) {
   e = hipMalloc(&ds->bin_ws, need);
   if (e != hipSuccess) return fail(CCSP_E_OOM, "ray binning scratch of %zu bytes: %s", need, hipGetErrorString(e));
   ds->bin_ws_bytes = need;
+  return CCSP_OK;
+}
+
+// The next record of the timing ring (its events are created on the first timed trace).
+int timing_slot(DeviceState* ds, StageEvents** out) {
+  std::lock_guard<std::mutex> lk(ds->time_mu);
+  if (ds->tev.empty()) {
+    std::vector<StageEvents> v(kTimeSlots);
+    for (auto& s : v)
+      for (auto& ev : s.ev) {
+        const hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+          for (auto& s2 : v)
+            for (auto& ev2 : s2.ev)
+              if (ev2) (void)hipEventDestroy(ev2);
+          return hip_fail(e, "hipEventCreate");
+        }
+      }
+    ds->tev.swap(v);
+  }
+  *out = &ds->tev[ds->time_next];
+  ds->time_next = (ds->time_next + 1) % kTimeSlots;
+  ds->time_count = std::min(ds->time_count + 1, kTimeSlots);
   return CCSP_OK;
 }
 
@@ -316,25 +350,8 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   }
   std::vector<int32_t> new_of(T);
   for (int64_t r = 0; r < T; ++r) new_of[(int64_t)(hkey[r] & 0xffffffffu)] = (int32_t)r;
-  // primitives in the order their edges are met along the triangle order, so that the record a
-  // hit reads is near the records of nearby hits
-  std::vector<int32_t> prim_new(P, -1), prim_old;
-  prim_old.reserve(P);
-  for (int64_t r = 0; r < T; ++r) {
-    const int64_t t = (int64_t)(hkey[r] & 0xffffffffu);
-    for (int i = 0; i < 3; ++i) {
-      const int32_t pr = tp[3 * t + i];
-      if (pr >= 0 && prim_new[pr] < 0) {
-        prim_new[pr] = (int32_t)prim_old.size();
-        prim_old.push_back(pr);
-      }
-    }
-  }
-  for (int64_t k = 0; k < P; ++k)
-    if (prim_new[k] < 0) {
-      prim_new[k] = (int32_t)prim_old.size();
-      prim_old.push_back((int32_t)k);
-    }
+  // primitives stay in the caller's order: a single trace reads them in input order of the rays
+  // (the finishing pass), where no renumbering would bring hits of neighbouring rays together
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t off_s32 = 0;
   const size_t off_s64 = align(off_s32 + sizeof(Slot32) * 3 * T);
@@ -352,15 +369,8 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   auto* txy64 = reinterpret_cast<TriXY64*>(host.data() + off_txy64);
   auto* t4 = reinterpret_cast<int4*>(host.data() + off_tv);
   std::memcpy(host.data() + off_v, xy, sizeof(double) * 2 * V);
-  auto* prec = reinterpret_cast<PrimRec*>(host.data() + off_p);
-  for (int64_t k = 0; k < P; ++k) {
-    const int32_t old = prim_old[k];
-    prec[k].ax = ps[4 * (int64_t)old];
-    prec[k].ay = ps[4 * (int64_t)old + 1];
-    prec[k].bx = ps[4 * (int64_t)old + 2];
-    prec[k].by = ps[4 * (int64_t)old + 3];
-    prec[k].id = old;
-  }
+  static_assert(sizeof(PrimRec) == 4 * sizeof(double), "primitive record = its segment");
+  if (P > 0) std::memcpy(host.data() + off_p, ps, sizeof(PrimRec) * P);
   std::memcpy(host.data() + off_perm, new_of.data(), sizeof(int32_t) * T);
   parallel_for(T, [&](int64_t a, int64_t b) {
     for (int64_t nt = a; nt < b; ++nt) {
@@ -382,7 +392,7 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
         const int32_t n = tn[3 * t + i], pr = tp[3 * t + i];
         int32_t word, vid = 0;
         if (pr >= 0) {
-          word = -(prim_new[pr] + 2);
+          word = -(pr + 2);
         } else if (n < 0) {
           word = -1;
         } else {
@@ -487,7 +497,8 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
   const int mode = precision & CCSP_TRACE_MODE_MASK;
   if (mode != CCSP_TRACE_FP64 && mode != CCSP_TRACE_FP32_FILTERED)
     return fail(CCSP_E_ARG, "unknown precision mode %d", mode);
-  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_VALIDATE | CCSP_TRACE_COUNT | CCSP_TRACE_INPUT_ORDER))
+  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_VALIDATE | CCSP_TRACE_COUNT | CCSP_TRACE_INPUT_ORDER |
+                    CCSP_TRACE_TIMED))
     return fail(CCSP_E_ARG, "unknown precision flags 0x%x", precision);
   int rc = check_rays(o_xy, d_xy, start_tri, n, hit_prim, hit_t, steps);
   if (rc || n == 0) return rc;
@@ -504,6 +515,13 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
              start_tri, hit_prim, hit_t, steps, n, nullptr};
   unsigned long long* counter = next_counters(ds);
   hipError_t e;
+  StageEvents* tev = nullptr;
+  if (precision & CCSP_TRACE_TIMED) {
+    rc = timing_slot(ds, &tev);
+    if (rc) return rc;
+    e = hipEventRecord(tev->ev[0], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  }
   const bool bin = !(precision & CCSP_TRACE_INPUT_ORDER) && n >= kBinMinRays && n < INT32_MAX &&
                    tri->nt >= kBinMinTriangles;
   std::unique_lock<std::mutex> bin_lock(ds->bin_mu, std::defer_lock);
@@ -526,8 +544,13 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
     e = hipMemsetAsync(ds->ws.errflag, 0, sizeof(int), st);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
   }
-  e = launch_walk(tri->dev, io, mode, count, validate, cfg, counter, ds->ws, st);
+  e = launch_walk(tri->dev, io, mode, count, validate, cfg, counter, ds->ws, st,
+                  tev ? tev->ev[1] : nullptr, tev ? tev->ev[2] : nullptr);
   if (e != hipSuccess) return hip_fail(e, "walk launch");
+  if (tev) {
+    e = hipEventRecord(tev->ev[3], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  }
   if (bin) {
     e = hipEventRecord(ds->bin_free, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -559,7 +582,7 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
   const int mode = precision & CCSP_TRACE_MODE_MASK;
   if (mode != CCSP_TRACE_FP64 && mode != CCSP_TRACE_FP32_FILTERED)
     return fail(CCSP_E_ARG, "unknown precision mode %d", mode);
-  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_COUNT))
+  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_COUNT | CCSP_TRACE_TIMED))
     return fail(CCSP_E_ARG, "unsupported precision flags 0x%x for trace_batch", precision);
   DeviceState* ds = nullptr;
   int rc = device_state(&ds);
@@ -611,13 +634,26 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
   }
   unsigned long long* counter = next_counters(ds);
   const bool count = precision & CCSP_TRACE_COUNT;
+  StageEvents* tev = nullptr;
+  if (precision & CCSP_TRACE_TIMED) {
+    rc = timing_slot(ds, &tev);
+    if (rc) return rc;
+    e = hipEventRecord(tev->ev[0], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  }
   if (!use_graph) {
     e = hipMemcpyAsync(ds->items_dev, ds->items_host, sizeof(BatchItem) * n_items, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "item table upload");
     e = hipEventRecord(ds->staging_free, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = launch_walk_batch(ds->items_dev, n_items, tiles, mode, count, cfg, counter, ds->ws, st);
+    e = launch_walk_batch(ds->items_dev, n_items, tiles, mode, count, cfg, counter, ds->ws, st,
+                          tev ? tev->ev[1] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    if (tev) {
+      e = hipEventRecord(tev->ev[2], st);
+      if (e == hipSuccess) e = hipEventRecord(tev->ev[3], st);
+      if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
     return CCSP_OK;
   }
   // Graph path: (upload, reset, walk) captured once per (n_items, tiles, mode, count, cfg,
@@ -646,8 +682,17 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     itg = ds->graphs.emplace(key, ge).first;
   }
+  if (tev) {
+    e = hipEventRecord(tev->ev[1], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  }
   e = hipGraphLaunch(itg->second, st);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  if (tev) {
+    e = hipEventRecord(tev->ev[2], st);
+    if (e == hipSuccess) e = hipEventRecord(tev->ev[3], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  }
   e = hipEventRecord(ds->staging_free, st);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   return CCSP_OK;
@@ -661,6 +706,31 @@ int reserve_workspace(int64_t max_rays) {
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(ds->bin_mu);
   return grow_bin_workspace(ds, max_rays);
+}
+
+int read_stage_times(int32_t max_records, float* bin_ms, float* walk_ms, float* finish_ms,
+                     int32_t* n_records) {
+  g_err.clear();
+  if (!n_records) return fail(CCSP_E_ARG, "null n_records");
+  *n_records = 0;
+  if (max_records < 0) return fail(CCSP_E_ARG, "negative max_records");
+  if (max_records > 0 && (!bin_ms || !walk_ms || !finish_ms)) return fail(CCSP_E_ARG, "null output array");
+  DeviceState* ds = nullptr;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ds->time_mu);
+  const int n = std::min(ds->time_count, (int)max_records);
+  for (int i = 0; i < n; ++i) {
+    const StageEvents& s = ds->tev[(ds->time_next - n + i + kTimeSlots) % kTimeSlots];
+    hipError_t e = hipEventSynchronize(s.ev[3]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&bin_ms[i], s.ev[0], s.ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&walk_ms[i], s.ev[1], s.ev[2]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&finish_ms[i], s.ev[2], s.ev[3]);
+    if (e != hipSuccess) return hip_fail(e, "stage timing");
+  }
+  ds->time_count = 0;
+  *n_records = n;
+  return CCSP_OK;
 }
 
 int read_counters(uint64_t out[4], int reset) {

@@ -7,9 +7,10 @@
 namespace ccsp {
 
 // Exit-edge word stored per (triangle, edge) slot:
-//   >= 0 : (neighbour << 2) | back, where `back` is the edge of the neighbour that leads back;
+//   >= 0 : (neighbour << 2) | back, where `back` is the edge of the neighbour that leads back
+//          (neighbour is an internal triangle id);
 //   -1   : unconstrained hull edge (the ray leaves the triangulation);
-//   <= -2: constrained edge of primitive (-word - 2).
+//   <= -2: constrained edge of primitive (-word - 2), the caller's primitive id.
 // Each slot also stores the vertex across the edge (the neighbour's vertex opposite `back`),
 // which is exactly the one vertex the next step needs: one dependent load per step.
 struct alignas(16) Slot32 {  // binary32 walk: 16 B per slot
@@ -28,11 +29,9 @@ struct alignas(32) TriXY32 {  // own vertices of a triangle in binary32 (first s
   float pad[2];
 };
 
-// A primitive in internal order: its segment (t is computed from it) and the caller's id.
-struct alignas(16) PrimRec {
+// A primitive, in the caller's order: its segment (t is computed from it).
+struct alignas(32) PrimRec {
   double ax, ay, bx, by;
-  int32_t id;
-  int32_t pad[3];
 };
 
 struct alignas(64) TriXY64 {  // own vertices in binary64 (first step of the binary64 walk)
@@ -47,7 +46,7 @@ struct SceneDev {
   const TriXY64* trixy64;  // T
   const int4* triv;      // T: v0, v1, v2, 0
   const double2* v64;    // V
-  const PrimRec* prim;   // P, internal order (first met along the Hilbert order of triangles)
+  const PrimRec* prim;   // P, the caller's order
   const int32_t* perm;   // T: caller's triangle id -> internal (Hilbert-ordered) id
   double org_x, org_y;   // origin of the binary32 coordinates
   double box_x0, box_y0, box_x1, box_y1;  // bounding box of the vertices
@@ -114,13 +113,18 @@ size_t bin_workspace_bytes(int64_t n);
 hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void* workspace,
                            size_t ws_bytes, RaysDev* out, hipStream_t stream);
 
+// A single trace: the walk kernel, then the finishing pass (finish_rays). `walk_begin` and
+// `walk_end`, if not null, are recorded on `stream` right before and after the walk kernel itself
+// (after the small counter reset, before the finishing pass), so that they time it alone.
 hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
                        const LaunchCfg& cfg, unsigned long long* counter, const Workspace& ws,
-                       hipStream_t stream);
+                       hipStream_t stream, hipEvent_t walk_begin = nullptr,
+                       hipEvent_t walk_end = nullptr);
 
 hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t total_tiles,
                              int mode, bool count, const LaunchCfg& cfg,
-                             unsigned long long* counter, const Workspace& ws, hipStream_t stream);
+                             unsigned long long* counter, const Workspace& ws, hipStream_t stream,
+                             hipEvent_t walk_begin = nullptr);
 
 size_t walk_lds_bytes(int mode, const LaunchCfg& cfg);
 

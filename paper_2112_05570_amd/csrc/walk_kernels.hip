@@ -12,6 +12,11 @@
 //    them in its own LDS region (origin, direction and the first exit slot, computed while the
 //    tile is loaded), and refills idle lanes from LDS as soon as `refill_min` of its 64 lanes have
 //    finished, so that divergent ray lengths do not idle the SIMD.
+//  * A single trace finishes in two kernels: at a hit, miss or bad ray the walk stores only
+//    (internal primitive or a negative code, steps) into the ray's 8-byte hit_t slot and frees the
+//    lane at once; finish_rays then turns these into (caller's primitive, t, steps) in input order,
+//    with coalesced accesses and the binary64 division out of the walk loop. A batched launch
+//    finishes its rays in the loop (FIN state).
 //  * Decisions: the sign of D(v) = dx*(vy-oy) - dy*(vx-ox), zero counting as LEFT. In binary32 mode
 //    the sign is taken from binary32 coordinates when a forward error bound proves it, otherwise
 //    from the binary64 filter, otherwise from an exact expansion; all three agree with the exact
@@ -21,6 +26,7 @@
 // formula assume every operation is rounded separately.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -115,6 +121,14 @@ __device__ __forceinline__ int first_edge(bool L0, bool L1, bool L2) {
 }
 
 // ------------------------------------------------------------------------------ persistent walk
+
+// Result of a single trace as left by the walk for finish_rays: x = internal primitive (>= 0) or
+// a CCSP_RAY_* code, y = steps; stored in the ray's hit_t slot (8 bytes), non-temporally: it is
+// read back once, by the finishing pass.
+__device__ __forceinline__ void park_result(const RaysDev& io, int64_t ray, int code, int steps) {
+  __builtin_nontemporal_store(((unsigned long long)(unsigned)steps << 32) | (unsigned)code,
+                              reinterpret_cast<unsigned long long*>(io.t) + ray);
+}
 
 __device__ __forceinline__ int lane_rank(unsigned long long mask) {
   return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
@@ -232,7 +246,7 @@ __device__ __forceinline__ long long claim_tile(unsigned long long* counter, int
 // Each lane is a small state machine that issues exactly one round of loads per iteration:
 //   FIRST: the own vertices of the start triangle (then three decisions, Sec. 5.4's first step),
 //   WALK:  the slot of the exit edge (then one decision: the vertex across the entry edge),
-//   FIN:   the hit primitive's record (then the hit distance and the results),
+//   FIN:   (batched launches) the hit primitive's record (then the hit distance and results),
 // so lanes in different states share one memory round trip, and a refilled lane starts walking
 // in the next iteration without a separate gather phase.
 template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH>
@@ -345,10 +359,14 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
           }
           if (MODE == 1) r32 = Ray32{(float)(ox - org_x), (float)(oy - org_y), (float)dx, (float)dy};
           if (s < 0) {  // bad ray: out-of-range start or failed validation
-            const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
-            io.prim[ray] = -3;
-            io.t[ray] = INFINITY;
-            io.steps[ray] = 0;
+            if (BATCH) {
+              const RaysDev& io = batch.items[item].rays;
+              io.prim[ray] = -3;
+              io.t[ray] = INFINITY;
+              io.steps[ray] = 0;
+            } else {
+              park_result(io_arg, ray, -3, 0);
+            }
             state = IDLE;
           }
         }
@@ -378,11 +396,10 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         R1 = p[1];
         R2 = p[2];
       }
-    } else if (st_now == FIN) {
-      const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.prim : sc_arg.prim) + s);
+    } else if (BATCH && st_now == FIN) {
+      const int4* p = reinterpret_cast<const int4*>(batch.items[item].scene.prim + s);
       R0 = p[0];
       R1 = p[1];
-      R2 = p[2];
     }
     // every load above is issued before any result is used (and none is split per field)
     __asm__ volatile("" ::"v"(R0.x), "v"(R0.y), "v"(R0.z), "v"(R0.w), "v"(R1.x), "v"(R1.y),
@@ -413,14 +430,29 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         e = e >= 3 ? e - 3 : e;
         s = 3 * (word >> 2) + e;
       } else if (word <= -2) {
-        s = -word - 2;  // constrained edge: hit; its primitive is loaded next iteration
-        state = FIN;
+        // constrained edge: hit. A batch loads the primitive next iteration (FIN); a single
+        // trace leaves it to finish_rays.
+        if (BATCH) {
+          s = -word - 2;
+          state = FIN;
+        } else {
+          park_result(io_arg, ray, -word - 2, steps);
+          if (COUNT) {
+            c.steps += steps;
+            ++c.rays;
+          }
+          state = IDLE;
+        }
       } else {
         // hull edge (miss) or the step guard
-        const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
-        io.prim[ray] = word >= 0 ? -2 : -1;
-        io.t[ray] = INFINITY;
-        io.steps[ray] = steps;
+        if (BATCH) {
+          const RaysDev& io = batch.items[item].rays;
+          io.prim[ray] = word >= 0 ? -2 : -1;
+          io.t[ray] = INFINITY;
+          io.steps[ray] = steps;
+        } else {
+          park_result(io_arg, ray, word >= 0 ? -2 : -1, steps);
+        }
         if (COUNT) {
           c.steps += steps;
           ++c.rays;
@@ -456,17 +488,21 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         s = 3 * s + e;
         state = WALK;
       } else {  // no exit edge: the origin is not inside the start triangle
-        const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
-        io.prim[ray] = -3;
-        io.t[ray] = INFINITY;
-        io.steps[ray] = 0;
+        if (BATCH) {
+          const RaysDev& io = batch.items[item].rays;
+          io.prim[ray] = -3;
+          io.t[ray] = INFINITY;
+          io.steps[ray] = 0;
+        } else {
+          park_result(io_arg, ray, -3, 0);
+        }
         state = IDLE;
       }
-    } else if (st_now == FIN) {
-      // Results go to the caller's (random, once binned) positions with non-temporal stores:
-      // they are never read again here, so they should not displace the scene in the L2.
+    } else if (BATCH && st_now == FIN) {
+      // Results go to the caller's positions with non-temporal stores: they are never read
+      // again here, so they should not displace the scene in the L2.
       const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
-      __builtin_nontemporal_store(R2.x, io.prim + ray);
+      __builtin_nontemporal_store(s, io.prim + ray);
       __builtin_nontemporal_store(hit_t(make_double4(lohi(R0.x, R0.y), lohi(R0.z, R0.w),
                                                      lohi(R1.x, R1.y), lohi(R1.z, R1.w)),
                                         ox, oy, dx, dy),
@@ -485,6 +521,32 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
     if (c.fb64) atomicAdd(&stats[2], (unsigned long long)c.fb64);
     if (c.rays) atomicAdd(&stats[3], (unsigned long long)c.rays);
   }
+}
+
+// Second kernel of a single trace: in input order, turn each ray's parked (internal primitive or
+// code, steps) into the caller's primitive id, the hit distance (the primitive's own segment,
+// binary64, Sec. 5.1's stop on scene geometry) and steps. Every access but the primitive record
+// is coalesced.
+__global__ void __launch_bounds__(256)
+finish_rays(const PrimRec* __restrict__ prim, const double2* __restrict__ o,
+            const double2* __restrict__ d, int32_t* __restrict__ hit_prim,
+            double* __restrict__ hit_t_io, int32_t* __restrict__ steps, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // the ray is loaded alongside the parked result (nearly every ray hits)
+  const unsigned long long v = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(hit_t_io) + i);
+  typedef double vd2 __attribute__((ext_vector_type(2)));
+  const vd2 oo = __builtin_nontemporal_load(reinterpret_cast<const vd2*>(o) + i);
+  const vd2 dd = __builtin_nontemporal_load(reinterpret_cast<const vd2*>(d) + i);
+  const int code = (int)(unsigned)v;
+  double t = INFINITY;
+  if (code >= 0) {
+    const PrimRec r = prim[code];
+    t = hit_t(make_double4(r.ax, r.ay, r.bx, r.by), oo.x, oo.y, dd.x, dd.y);
+  }
+  __builtin_nontemporal_store(code, hit_prim + i);
+  __builtin_nontemporal_store(t, hit_t_io + i);
+  __builtin_nontemporal_store((int)(unsigned)(v >> 32), steps + i);
 }
 
 __global__ void reset_counters(unsigned long long* counter) {
@@ -522,24 +584,43 @@ static hipError_t pick_tile(const SceneDev& sc, const RaysDev& io, ItemRef br, i
 
 hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
                        const LaunchCfg& cfg, unsigned long long* counter, const Workspace& ws,
-                       hipStream_t stream) {
+                       hipStream_t stream, hipEvent_t walk_begin, hipEvent_t walk_end) {
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counter);
+  hipError_t e;
+  if (walk_begin) {
+    e = hipEventRecord(walk_begin, stream);
+    if (e != hipSuccess) return e;
+  }
   const size_t lds = walk_lds_bytes(mode, cfg);
   const ItemRef none{nullptr, 0, nullptr, 0};
   const int64_t tiles = (io.n + cfg.tile - 1) / cfg.tile;
+  e = hipErrorInvalidValue;
 #define CCSP_CASE(M, C, V) \
   if (mode == M && count == C && validate == V) \
-    return pick_tile<M, C, V, false>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
+    e = pick_tile<M, C, V, false>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
   CCSP_CASE(0, false, false) CCSP_CASE(0, true, false) CCSP_CASE(0, false, true) CCSP_CASE(0, true, true)
   CCSP_CASE(1, false, false) CCSP_CASE(1, true, false) CCSP_CASE(1, false, true) CCSP_CASE(1, true, true)
 #undef CCSP_CASE
-  return hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
+  if (walk_end) {
+    e = hipEventRecord(walk_end, stream);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t blocks = (io.n + 255) / 256;
+  hipLaunchKernelGGL(finish_rays, dim3((unsigned)blocks), dim3(256), 0, stream, sc.prim, io.o, io.d,
+                     io.prim, io.t, io.steps, io.n);
+  return hipGetLastError();
 }
 
 hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t total_tiles,
                              int mode, bool count, const LaunchCfg& cfg,
-                             unsigned long long* counter, const Workspace& ws, hipStream_t stream) {
+                             unsigned long long* counter, const Workspace& ws, hipStream_t stream,
+                             hipEvent_t walk_begin) {
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counter);
+  if (walk_begin) {
+    const hipError_t e = hipEventRecord(walk_begin, stream);
+    if (e != hipSuccess) return e;
+  }
   const int n_lds = n_items < 1024 ? n_items : 1024;
   const size_t lds = walk_lds_bytes(mode, cfg) + (size_t)((n_lds + 1) & ~1) * 8;
   const ItemRef br{items_dev, n_items, nullptr, n_lds};

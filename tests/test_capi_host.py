@@ -119,3 +119,12 @@ def test_trace_batch_argument_errors():
     arr = (B.TraceItem * 1)(item)
     assert B.raw_call("trace_batch", arr, 1, 1, None, None) in (B.CCSP_E_ARG, B.CCSP_E_HIP)
     assert B.raw_call("trace_batch", arr, 1, 1 | B.CCSP_TRACE_VALIDATE, None, None) == B.CCSP_E_ARG
+
+
+def test_read_stage_times_argument_errors():
+    n = ctypes.c_int32(7)
+    assert B.raw_call("read_stage_times", 4, None, None, None, None) == B.CCSP_E_ARG
+    assert B.raw_call("read_stage_times", -1, None, None, None, ctypes.byref(n)) == B.CCSP_E_ARG
+    assert n.value == 0
+    assert B.raw_call("read_stage_times", 4, None, None, None, ctypes.byref(n)) == B.CCSP_E_ARG
+    assert "null" in B.last_error()

@@ -169,6 +169,34 @@ def test_binned_equals_input_order(ccsp, grid_pair, n):
         _assert_same((a[0][idx], a[1][idx], a[2][idx]), ref, "binned vs checker")
 
 
+def test_stage_times(ccsp, grid_pair, tiny_scene, tiny_rays):
+    """Timed traces record (binning, walk) durations; results are unchanged by timing."""
+    sc, _, rays, _ = grid_pair
+    ccsp.read_stage_times()  # forget older records
+    r = rays.slice(0, 300_000)
+    with ccsp.Scene.from_arrays(sc) as scene, ccsp.Scene.from_arrays(tiny_scene) as tiny:
+        o, d, st = _dev(r)
+        ref = _host(ccsp.trace(scene, o, d, st))
+        for _ in range(3):
+            got = ccsp.trace(scene, o, d, st, timed=True)
+        ccsp.trace(tiny, *_dev(tiny_rays), timed=True, input_order=True)
+        bin_ms, walk_ms, fin_ms = ccsp.read_stage_times()
+        _assert_same(_host(got), ref, "timed trace")
+        assert len(bin_ms) == len(walk_ms) == len(fin_ms) == 4
+        assert all(w > 0 for w in walk_ms) and all(f > 0 for f in fin_ms)
+        assert all(b > 0 for b in bin_ms[:3])      # the grid traces bin their rays
+        assert bin_ms[3] < 0.5 * walk_ms[3] + 0.05  # the tiny trace does not
+        assert ccsp.read_stage_times() == ([], [], [])  # reading forgets the records
+        # the ring keeps the last 256 records
+        o2, d2, st2 = _dev(tiny_rays.slice(0, 1000))
+        for _ in range(300):
+            ccsp.trace(tiny, o2, d2, st2, timed=True)
+        b, w, f = ccsp.read_stage_times(1000)
+        assert len(w) == 256
+        b, w, f = ccsp.read_stage_times(0)
+        assert w == []
+
+
 def test_reserve_workspace_then_trace(ccsp, tiny_scene, tiny_rays):
     ccsp.reserve_workspace(1 << 17)
     ref = oracle.walk(oracle.Triangulation.of(tiny_scene), tiny_rays.o, tiny_rays.d, tiny_rays.start)
