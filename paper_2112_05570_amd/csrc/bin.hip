@@ -9,14 +9,18 @@
 // Default (kBinBuckets): one counting-sort pass into kBuckets buckets = cells of a 16 x 16 grid
 // over the scene numbered along a Hilbert curve. A counting kernel histograms the buckets per
 // chunk of rays, a scan turns the counts into destinations, and a scatter kernel stages each
-// chunk in LDS sorted by bucket and writes it out as 48-byte records (origin, direction, internal
-// start triangle, caller's index) in runs, so that both its reads and writes are coalesced and
-// the walk then reads its rays contiguously, with no gather through a permutation.
+// chunk in LDS sorted by bucket and writes it out as 48-byte records (origin, direction, exit slot
+// of the first triangle, caller's index) in runs, so that both its reads and writes are coalesced
+// and the walk then reads its rays contiguously, with no gather through a permutation. The scatter
+// also decides each ray's first triangle (Sec. 5.4's three-candidate step) from the caller-ordered
+// first-triangle record, which it has to gather anyway for the start triangle's internal id; the
+// walk then starts every binned ray with its first step.
 // Alternative (kBinRadix): a radix sort of (internal start triangle, index) pairs; the walk then
 // gathers each ray through the sorted index.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include "decide.hpp"
 #include "walk.hpp"
 
 namespace ccsp {
@@ -77,11 +81,12 @@ bucket_count(const double2* __restrict__ o, int64_t n, BinGeom g, uint32_t* __re
   for (int b = threadIdx.x; b < kBuckets; b += kThreads) H[(size_t)b * nchunks + blockIdx.x] = h[b];
 }
 
+template <bool COUNT>
 __global__ void __launch_bounds__(kThreads)
 bucket_scatter(const double2* __restrict__ o, const double2* __restrict__ d,
-               const int32_t* __restrict__ start, const int32_t* __restrict__ perm,
-               int32_t ntri, int64_t n, BinGeom g, const uint32_t* __restrict__ Hoff,
-               int nchunks, RayRec* __restrict__ out) {
+               const int32_t* __restrict__ start, SceneDev sc, int64_t n, BinGeom g,
+               const uint32_t* __restrict__ Hoff, int nchunks, RayRec* __restrict__ out,
+               unsigned long long* __restrict__ stats) {
   __shared__ uint32_t off[kBuckets], cnt[kBuckets], pre[kBuckets];
   __shared__ RayRec stage[kChunk];
   __shared__ uint16_t stage_bucket[kChunk];
@@ -94,6 +99,8 @@ bucket_scatter(const double2* __restrict__ o, const double2* __restrict__ d,
   const int len = (int)min((int64_t)kChunk, n - base);
   RayRec r[kPerThread];
   uint32_t bk[kPerThread], rank[kPerThread];
+  int32_t s[kPerThread];
+  TriFirst f[kPerThread];
 #pragma unroll
   for (int q = 0; q < kPerThread; ++q) {
     const int j = threadIdx.x + q * kThreads;
@@ -101,13 +108,34 @@ bucket_scatter(const double2* __restrict__ o, const double2* __restrict__ d,
       const int64_t i = base + j;
       r[q].o = o[i];
       r[q].d = d[i];
-      const int32_t s = start[i];
-      r[q].start = (s >= 0 && s < ntri) ? perm[s] : -1;  // internal id, -1 if out of range
+      s[q] = start[i];
       r[q].idx = (int32_t)i;
       r[q].pad[0] = r[q].pad[1] = 0;
-      bk[q] = bucket_of(r[q].o, g);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {  // every gather issued before any is used
+    const int j = threadIdx.x + q * kThreads;
+    if (j < len && s[q] >= 0 && s[q] < sc.ntri) f[q] = sc.first[s[q]];
+  }
+  unsigned fb32 = 0, fb64 = 0;
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int j = threadIdx.x + q * kThreads;
+    if (j < len) {
+      const double2 ro = r[q].o, rd = r[q].d;
+      r[q].start = -1;  // start triangle out of range
+      if (s[q] >= 0 && s[q] < sc.ntri)
+        r[q].start = first_exit_slot<COUNT>(ray32(ro.x, ro.y, rd.x, rd.y, sc.org_x, sc.org_y), ro,
+                                            rd, f[q].x[0], f[q].x[1], f[q].x[2], f[q].y[0],
+                                            f[q].y[1], f[q].y[2], f[q].tri, sc, fb32, fb64);
+      bk[q] = bucket_of(ro, g);
       rank[q] = atomicAdd(&cnt[bk[q]], 1u);
     }
+  }
+  if (COUNT) {
+    if (fb32) atomicAdd(&stats[1], (unsigned long long)fb32);
+    if (fb64) atomicAdd(&stats[2], (unsigned long long)fb64);
   }
   __syncthreads();
   // exclusive scan of the chunk's bucket counts (kBuckets == kThreads: one bucket per thread)
@@ -191,7 +219,8 @@ size_t bin_workspace_bytes(int64_t n) {
 }
 
 hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void* workspace,
-                           size_t ws_bytes, RaysDev* out, hipStream_t stream) {
+                           size_t ws_bytes, RaysDev* out, unsigned long long* stats,
+                           hipStream_t stream) {
   const int64_t n = in.n;
   if (n <= 0 || n >= INT32_MAX || bin_workspace_bytes(n) > ws_bytes) return hipErrorInvalidValue;
   auto* p = static_cast<unsigned char*>(workspace);
@@ -207,6 +236,7 @@ hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void
     const int bs = 256;
     hipLaunchKernelGGL(start_keys, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, stream,
                        in.start, sc.perm, sc.ntri, n, k0, v0);
+    // the walk reads each ray (and its caller's start triangle) through the sorted index
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipcub::DoubleBuffer<uint32_t> keys(k0, k1);
@@ -215,7 +245,6 @@ hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void
                                            bits_for(sc.ntri), stream);
     if (e != hipSuccess) return e;
     out->order = vals.Current();
-    out->order_start = reinterpret_cast<const int32_t*>(keys.Current());
     return hipSuccess;
   }
   const int nch = n_chunks(n);
@@ -238,8 +267,12 @@ hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void
   if (e != hipSuccess) return e;
   e = hipcub::DeviceScan::ExclusiveSum(p, temp_bytes, H, Hoff, (int)items, stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(bucket_scatter, dim3(nch), dim3(kThreads), 0, stream, in.o, in.d, in.start,
-                     sc.perm, sc.ntri, n, g, Hoff, nch, recs);
+  if (stats)
+    hipLaunchKernelGGL(bucket_scatter<true>, dim3(nch), dim3(kThreads), 0, stream, in.o, in.d,
+                       in.start, sc, n, g, Hoff, nch, recs, stats);
+  else
+    hipLaunchKernelGGL(bucket_scatter<false>, dim3(nch), dim3(kThreads), 0, stream, in.o, in.d,
+                       in.start, sc, n, g, Hoff, nch, recs, stats);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   out->recs = recs;

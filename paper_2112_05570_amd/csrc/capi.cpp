@@ -355,9 +355,8 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t off_s32 = 0;
   const size_t off_s64 = align(off_s32 + sizeof(Slot32) * 3 * T);
-  const size_t off_txy = align(off_s64 + sizeof(Slot64) * 3 * T);
-  const size_t off_txy64 = align(off_txy + sizeof(TriXY32) * T);
-  const size_t off_tv = align(off_txy64 + sizeof(TriXY64) * T);
+  const size_t off_first = align(off_s64 + sizeof(Slot64) * 3 * T);
+  const size_t off_tv = align(off_first + sizeof(TriFirst) * T);
   const size_t off_v = align(off_tv + sizeof(int4) * T);
   const size_t off_p = align(off_v + sizeof(double2) * V);
   const size_t off_perm = align(off_p + sizeof(PrimRec) * std::max<int64_t>(P, 1));
@@ -365,8 +364,7 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   std::vector<unsigned char> host(total, 0);
   auto* s32 = reinterpret_cast<Slot32*>(host.data() + off_s32);
   auto* s64 = reinterpret_cast<Slot64*>(host.data() + off_s64);
-  auto* txy = reinterpret_cast<TriXY32*>(host.data() + off_txy);
-  auto* txy64 = reinterpret_cast<TriXY64*>(host.data() + off_txy64);
+  auto* tfirst = reinterpret_cast<TriFirst*>(host.data() + off_first);
   auto* t4 = reinterpret_cast<int4*>(host.data() + off_tv);
   std::memcpy(host.data() + off_v, xy, sizeof(double) * 2 * V);
   static_assert(sizeof(PrimRec) == 4 * sizeof(double), "primitive record = its segment");
@@ -377,16 +375,13 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
       const int64_t t = (int64_t)(hkey[nt] & 0xffffffffu);  // caller's id of internal triangle nt
       const int32_t* v = tv + 3 * t;
       t4[nt] = make_int4(v[0], v[1], v[2], 0);
+      TriFirst& f = tfirst[t];  // the caller's order
       for (int i = 0; i < 3; ++i) {
-        txy[nt].x[i] = (float)(xy[2 * (int64_t)v[i]] - org[0]);
-        txy[nt].y[i] = (float)(xy[2 * (int64_t)v[i] + 1] - org[1]);
+        f.x[i] = (float)(xy[2 * (int64_t)v[i]] - org[0]);
+        f.y[i] = (float)(xy[2 * (int64_t)v[i] + 1] - org[1]);
       }
-      txy64[nt].x0 = xy[2 * (int64_t)v[0]];
-      txy64[nt].y0 = xy[2 * (int64_t)v[0] + 1];
-      txy64[nt].x1 = xy[2 * (int64_t)v[1]];
-      txy64[nt].y1 = xy[2 * (int64_t)v[1] + 1];
-      txy64[nt].x2 = xy[2 * (int64_t)v[2]];
-      txy64[nt].y2 = xy[2 * (int64_t)v[2] + 1];
+      f.tri = (int32_t)nt;
+      f.pad = 0;
       for (int i = 0; i < 3; ++i) {
         const int64_t k = 3 * nt + i;
         const int32_t n = tn[3 * t + i], pr = tp[3 * t + i];
@@ -441,8 +436,7 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   tri->np = P;
   tri->dev.slot32 = reinterpret_cast<const Slot32*>(base + off_s32);
   tri->dev.slot64 = reinterpret_cast<const Slot64*>(base + off_s64);
-  tri->dev.trixy = reinterpret_cast<const TriXY32*>(base + off_txy);
-  tri->dev.trixy64 = reinterpret_cast<const TriXY64*>(base + off_txy64);
+  tri->dev.first = reinterpret_cast<const TriFirst*>(base + off_first);
   tri->dev.triv = reinterpret_cast<const int4*>(base + off_tv);
   tri->dev.v64 = reinterpret_cast<const double2*>(base + off_v);
   tri->dev.prim = reinterpret_cast<const PrimRec*>(base + off_p);
@@ -536,7 +530,7 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
     }
     RaysDev binned{};
     e = launch_bin_rays(tri->dev, io, (tune && tune->reserved[2] == kBinRadix) ? kBinRadix : kBinBuckets,
-                        ds->bin_ws, ds->bin_ws_bytes, &binned, st);
+                        ds->bin_ws, ds->bin_ws_bytes, &binned, count ? ds->ws.stats : nullptr, st);
     io = binned;
     if (e != hipSuccess) return hip_fail(e, "ray binning");
   }

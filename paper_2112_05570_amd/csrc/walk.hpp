@@ -24,9 +24,12 @@ struct alignas(32) Slot64 {  // binary64 walk: 32 B per slot
   int32_t vid;
   int32_t pad[2];
 };
-struct alignas(32) TriXY32 {  // own vertices of a triangle in binary32 (first step only)
+// First-triangle record, in the CALLER's triangle order (rays name their start triangle by the
+// caller's id): its vertices relative to the scene origin in binary32, and its internal id.
+struct alignas(32) TriFirst {
   float x[3], y[3];
-  float pad[2];
+  int32_t tri;
+  int32_t pad;
 };
 
 // A primitive, in the caller's order: its segment (t is computed from it).
@@ -34,16 +37,10 @@ struct alignas(32) PrimRec {
   double ax, ay, bx, by;
 };
 
-struct alignas(64) TriXY64 {  // own vertices in binary64 (first step of the binary64 walk)
-  double x0, y0, x1, y1, x2, y2;
-  double pad[2];
-};
-
 struct SceneDev {
   const Slot32* slot32;    // 3T
   const Slot64* slot64;    // 3T
-  const TriXY32* trixy;    // T
-  const TriXY64* trixy64;  // T
+  const TriFirst* first;   // T, the caller's order
   const int4* triv;      // T: v0, v1, v2, 0
   const double2* v64;    // V
   const PrimRec* prim;   // P, the caller's order
@@ -54,8 +51,9 @@ struct SceneDev {
   int32_t pad;
 };
 
-// A binned ray: origin, direction, internal start triangle (-1 if out of range) and the caller's
-// index of the ray.
+// A binned ray: origin, direction, the exit slot of its first triangle (3 * internal triangle +
+// exit edge; -1 if the start triangle is out of range or the origin is not inside it) and the
+// caller's index of the ray.
 struct alignas(16) RayRec {
   double2 o;
   double2 d;
@@ -65,8 +63,8 @@ struct alignas(16) RayRec {
 };
 
 // Rays in the caller's order. When `recs` is set, the ray walked at position k is recs[k] (binned
-// copies); else when `order` is set it is ray order[k] (a permutation of 0..n-1), with internal
-// start triangle order_start[k] if that is set too; otherwise it is ray k.
+// copies, first triangle already decided); else when `order` is set it is ray order[k] (a
+// permutation of 0..n-1); otherwise it is ray k.
 struct RaysDev {
   const double2* o;
   const double2* d;
@@ -76,7 +74,6 @@ struct RaysDev {
   int32_t* steps;
   int64_t n;
   const int32_t* order;
-  const int32_t* order_start;
   const RayRec* recs;
 };
 
@@ -106,12 +103,14 @@ struct Workspace {
 constexpr int kCounterSlots = 4096;
 constexpr int kClaimChunks = 8;  // tile counters per launch (one per XCD)
 
-// Binning: *out = `in` with out->order set to a cache-friendly walking order (see bin.hip for
-// the two keys). Needs bin_workspace_bytes(n) of scratch.
+// Binning: *out = `in` with a cache-friendly walking order: binned records (out->recs, the
+// default) or a sorted index (out->order); see bin.hip. Needs bin_workspace_bytes(n) of scratch.
+// `stats`, if not null, receives the first triangles' deferred decisions (as the walk's counters).
 enum { kBinBuckets = 0, kBinRadix = 2 };
 size_t bin_workspace_bytes(int64_t n);
 hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void* workspace,
-                           size_t ws_bytes, RaysDev* out, hipStream_t stream);
+                           size_t ws_bytes, RaysDev* out, unsigned long long* stats,
+                           hipStream_t stream);
 
 // A single trace: the walk kernel, then the finishing pass (finish_rays). `walk_begin` and
 // `walk_end`, if not null, are recorded on `stream` right before and after the walk kernel itself

@@ -30,95 +30,11 @@
 #include <cmath>
 #include <cstdint>
 
+#include "decide.hpp"
 #include "exact.hpp"
 #include "walk.hpp"
 
 namespace ccsp {
-
-// ------------------------------------------------------------------------------ decisions
-
-// binary32 filter. Inputs: origin and across vertex relative to the scene origin and rounded to
-// binary32 (relative error <= 2^-24 each, plus 2^-53 from the binary64 subtraction), direction
-// rounded to binary32. The rounded evaluation differs from the exact D by at most
-// u*|D~| + 4.02u*M, u = 2^-24, M = |dx|(|cy|+|oy|) + |dy|(|cx|+|ox|) (absolute magnitudes: input
-// rounding is relative to the coordinates, not to their differences). The threshold 6u*M~ + 2^-100
-// covers this with margin, also for subnormal intermediates. Returns +-1 if certain, 0 if not.
-struct Ray32 {
-  float ox, oy, dx, dy;
-};
-
-__device__ __forceinline__ int side32(const Ray32& r, float cx, float cy) {
-  const float a = cy - r.oy;
-  const float b = cx - r.ox;
-  const float D = r.dx * a - r.dy * b;
-  const float M = fabsf(r.dx) * (fabsf(cy) + fabsf(r.oy)) + fabsf(r.dy) * (fabsf(cx) + fabsf(r.ox));
-  if (fabsf(D) > 0x1.8p-22f * M + 0x1p-100f) return D > 0.0f ? 1 : -1;
-  return 0;
-}
-
-// Exact decision, kept out of line so that its expansion registers do not count against the
-// occupancy of the hot loop.
-__device__ __attribute__((noinline)) int side_exact_call(double ox, double oy, double dx, double dy,
-                                                         double vx, double vy) {
-  return side_exact(ox, oy, dx, dy, vx, vy);
-}
-
-template <bool COUNT>
-__device__ __forceinline__ bool left64(double ox, double oy, double dx, double dy, double vx,
-                                       double vy, unsigned& n_exact) {
-  bool certain;
-  int s = side_fp64_filtered(ox, oy, dx, dy, vx, vy, certain);
-  if (!certain) {
-    if (COUNT) ++n_exact;
-    s = side_exact_call(ox, oy, dx, dy, vx, vy);
-  }
-  return s >= 0;
-}
-
-struct Counters {
-  unsigned steps = 0, fb32 = 0, fb64 = 0, rays = 0;
-};
-
-// binary32 decision deferred to binary64 (out of line: rare).
-template <bool COUNT>
-__device__ __attribute__((noinline)) bool left_deferred(double2 o, double2 d, const double2* v64,
-                                                        int vid, unsigned* n_exact) {
-  const double2 v = v64[vid];
-  unsigned n = 0;
-  const bool l = left64<COUNT>(o.x, o.y, d.x, d.y, v.x, v.y, n);
-  if (COUNT) *n_exact += n;
-  return l;
-}
-
-__device__ __attribute__((noinline)) bool validate_ray(const SceneDev& sc, double2 o, double2 d,
-                                                       int st) {
-  const int4 tv = sc.triv[st];
-  const double2 v[3] = {sc.v64[tv.x], sc.v64[tv.y], sc.v64[tv.z]};
-  bool ok = isfinite(d.x) && isfinite(d.y) && (d.x != 0.0 || d.y != 0.0) && isfinite(o.x) &&
-            isfinite(o.y);
-  for (int i = 0; i < 3; ++i) {
-    const double2 a = v[(i + 1) % 3], b = v[(i + 2) % 3];
-    ok = ok && orient_exact(a.x, a.y, b.x, b.y, o.x, o.y) > 0;
-  }
-  return ok;
-}
-
-__device__ __forceinline__ double hit_t(const double4 g, double ox, double oy, double dx,
-                                        double dy) {
-  const double ex = g.z - g.x;
-  const double ey = g.w - g.y;
-  const double num = (g.x - ox) * ey - (g.y - oy) * ex;
-  const double den = dx * ey - dy * ex;
-  return num / den;
-}
-
-__device__ __forceinline__ double lohi(int lo, int hi) { return __hiloint2double(hi, lo); }
-
-// The exit edge i of the first triangle is the one whose first endpoint is RIGHT of the ray and
-// whose second is LEFT (three candidates: nothing is known about the entry).
-__device__ __forceinline__ int first_edge(bool L0, bool L1, bool L2) {
-  return (!L1 && L2) ? 0 : ((!L2 && L0) ? 1 : ((!L0 && L1) ? 2 : -1));
-}
 
 // ------------------------------------------------------------------------------ persistent walk
 
@@ -163,15 +79,15 @@ struct Tile {
         idx(reinterpret_cast<int*>(base + 36 * TILE)) {}
 };
 
-// Load rays [base, base+len) of `io` into the tile: one round of loads (plus the id map for rays
-// that were not binned). Their first triangle is handled by the walk loop itself.
+// Load rays [base, base+len) of `io` into the tile, one round of loads. A binned tile (io.recs)
+// holds each ray's first exit slot (binning decided the first triangle), any other tile the
+// caller's start triangle, whose first triangle the walk loop decides; -1 marks a bad ray.
 template <int TPL, bool VALIDATE>
 __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, int len,
                           const Tile<TPL * 64>& tl, int lane, int* errflag) {
   int st[TPL];
   int64_t ri[TPL];
   double2 o[TPL], d[TPL];
-  const bool internal = io.recs != nullptr || io.order_start != nullptr;
 #pragma unroll
   for (int q = 0; q < TPL; ++q) {
     const int k = lane + 64 * q;
@@ -189,7 +105,7 @@ __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, i
         if (io.order) ri[q] = io.order[base + k];
         o[q] = io.o[ri[q]];
         d[q] = io.d[ri[q]];
-        st[q] = io.order_start ? io.order_start[base + k] : io.start[ri[q]];
+        st[q] = io.start[ri[q]];
       }
     }
   }
@@ -197,13 +113,13 @@ __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, i
   for (int q = 0; q < TPL; ++q) {
     const int k = lane + 64 * q;
     if (k < len) {
-      if (internal) {
-        if (st[q] >= sc.ntri) st[q] = -1;  // already an internal id (binning mapped it)
-      } else {
-        // the caller's triangle id -> internal (Hilbert-ordered) id
-        st[q] = (st[q] >= 0 && st[q] < sc.ntri) ? sc.perm[st[q]] : -1;
+      if (io.recs) {
+        if (st[q] >= 3 * sc.ntri) st[q] = -1;
+      } else if (st[q] >= sc.ntri) {
+        st[q] = -1;
       }
-      if (VALIDATE && (st[q] < 0 || !validate_ray(sc, o[q], d[q], st[q]))) {
+      if (VALIDATE && (st[q] < 0 ||
+                       !validate_ray(sc, o[q], d[q], io.recs ? st[q] / 3 : sc.first[st[q]].tri))) {
         atomicOr(errflag, 1);
         st[q] = -1;
       }
@@ -244,7 +160,8 @@ __device__ __forceinline__ long long claim_tile(unsigned long long* counter, int
 }
 
 // Each lane is a small state machine that issues exactly one round of loads per iteration:
-//   FIRST: the own vertices of the start triangle (then three decisions, Sec. 5.4's first step),
+//   FIRST: the start triangle's first-triangle record (then three decisions, Sec. 5.4's first
+//          step; rays of binned tiles skip it: binning decided their first triangle),
 //   WALK:  the slot of the exit edge (then one decision: the vertex across the entry edge),
 //   FIN:   (batched launches) the hit primitive's record (then the hit distance and results),
 // so lanes in different states share one memory round trip, and a refilled lane starts walking
@@ -287,6 +204,8 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   int tlen = 0, thead = 0, titem = 0;
   bool drained = false;
   bool io_order = io_arg.order != nullptr || io_arg.recs != nullptr;
+  // rays of binned tiles start walking at once: binning decided their first triangle
+  const bool binned = !BATCH && io_arg.recs != nullptr;
   int chunk_cur = (int)(blockIdx.x % (unsigned)chunks), chunk_tried = 0;
   // tiles are claimed `group` at a time (one global atomic per group): same-address atomics
   // from thousands of waves serialise, and one per tile would stall every refill
@@ -346,7 +265,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
           s = tl.st[k];
           ray = io_order ? (int64_t)tl.idx[k] : tbase + k;
           steps = 1;
-          state = FIRST;
+          state = binned ? WALK : FIRST;
           double org_x = sc_arg.org_x, org_y = sc_arg.org_y;
           if (BATCH) {
             item = titem;
@@ -357,7 +276,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             org_x = sc.org_x;
             org_y = sc.org_y;
           }
-          if (MODE == 1) r32 = Ray32{(float)(ox - org_x), (float)(oy - org_y), (float)dx, (float)dy};
+          if (MODE == 1 || !binned) r32 = ray32(ox, oy, dx, dy, org_x, org_y);
           if (s < 0) {  // bad ray: out-of-range start or failed validation
             if (BATCH) {
               const RaysDev& io = batch.items[item].rays;
@@ -386,16 +305,9 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         R1 = p[1];
       }
     } else if (st_now == FIRST) {
-      if (MODE == 1) {
-        const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.trixy : sc_arg.trixy) + s);
-        R0 = p[0];
-        R1 = p[1];
-      } else {
-        const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.trixy64 : sc_arg.trixy64) + s);
-        R0 = p[0];
-        R1 = p[1];
-        R2 = p[2];
-      }
+      const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.first : sc_arg.first) + s);
+      R0 = p[0];
+      R1 = p[1];
     } else if (BATCH && st_now == FIN) {
       const int4* p = reinterpret_cast<const int4*>(batch.items[item].scene.prim + s);
       R0 = p[0];
@@ -460,32 +372,13 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         state = IDLE;
       }
     } else if (st_now == FIRST) {
-      bool L0, L1, L2;
-      if (MODE == 1) {
-        // TriXY32: x0 x1 x2 y0 | y1 y2 - -
-        int s0 = side32(r32, __int_as_float(R0.x), __int_as_float(R0.w));
-        int s1 = side32(r32, __int_as_float(R0.y), __int_as_float(R1.x));
-        int s2 = side32(r32, __int_as_float(R0.z), __int_as_float(R1.y));
-        if ((s0 == 0) | (s1 == 0) | (s2 == 0)) {
-          const SceneDev& sc = BATCH ? batch.items[item].scene : sc_arg;
-          const int4 tv = sc.triv[s];
-          const double2 o = make_double2(ox, oy), d = make_double2(dx, dy);
-          if (s0 == 0) { if (COUNT) ++c.fb32; s0 = left_deferred<COUNT>(o, d, sc.v64, tv.x, &c.fb64) ? 1 : -1; }
-          if (s1 == 0) { if (COUNT) ++c.fb32; s1 = left_deferred<COUNT>(o, d, sc.v64, tv.y, &c.fb64) ? 1 : -1; }
-          if (s2 == 0) { if (COUNT) ++c.fb32; s2 = left_deferred<COUNT>(o, d, sc.v64, tv.z, &c.fb64) ? 1 : -1; }
-        }
-        L0 = s0 > 0;
-        L1 = s1 > 0;
-        L2 = s2 > 0;
-      } else {
-        // TriXY64: x0 y0 | x1 y1 | x2 y2
-        L0 = left64<COUNT>(ox, oy, dx, dy, lohi(R0.x, R0.y), lohi(R0.z, R0.w), c.fb64);
-        L1 = left64<COUNT>(ox, oy, dx, dy, lohi(R1.x, R1.y), lohi(R1.z, R1.w), c.fb64);
-        L2 = left64<COUNT>(ox, oy, dx, dy, lohi(R2.x, R2.y), lohi(R2.z, R2.w), c.fb64);
-      }
-      const int e = first_edge(L0, L1, L2);
+      // TriFirst: x0 x1 x2 y0 | y1 y2 tri -
+      const int e = first_exit_slot<COUNT>(
+          r32, make_double2(ox, oy), make_double2(dx, dy), __int_as_float(R0.x),
+          __int_as_float(R0.y), __int_as_float(R0.z), __int_as_float(R0.w), __int_as_float(R1.x),
+          __int_as_float(R1.y), R1.z, BATCH ? batch.items[item].scene : sc_arg, c.fb32, c.fb64);
       if (e >= 0) {
-        s = 3 * s + e;
+        s = e;
         state = WALK;
       } else {  // no exit edge: the origin is not inside the start triangle
         if (BATCH) {
