@@ -12,7 +12,7 @@
 // chunk in LDS sorted by bucket and writes it out as 48-byte records (origin, direction, exit slot
 // of the first triangle, caller's index) in runs, so that both its reads and writes are coalesced
 // and the walk then reads its rays contiguously, with no gather through a permutation. The scatter
-// also decides each ray's first triangle (Sec. 5.4's three-candidate step) from the caller-ordered
+// also decides each ray's first triangle (three candidate edges, Sec. 7.2) from the caller-ordered
 // first-triangle record, which it has to gather anyway for the start triangle's internal id; the
 // walk then starts every binned ray with its first step.
 // Alternative (kBinRadix): a radix sort of (internal start triangle, index) pairs; the walk then

@@ -101,7 +101,7 @@ __device__ __forceinline__ int first_edge(bool L0, bool L1, bool L2) {
   return (!L1 && L2) ? 0 : ((!L2 && L0) ? 1 : ((!L0 && L1) ? 2 : -1));
 }
 
-// Exit slot (3 * internal triangle + exit edge) of a ray's first triangle (Sec. 5.4: three
+// Exit slot (3 * internal triangle + exit edge) of a ray's first triangle (Sec. 7.2: three
 // candidate edges, nothing being known about an entry). x, y: the triangle's vertices relative to
 // the scene origin in binary32, `tri` its internal id. Signs the binary32 filter leaves open go
 // to the binary64 filter and then the exact expansion, so the result is exact in either precision

@@ -1,22 +1,23 @@
 // Persistent stackless triangulation walk for gfx950 (CDNA4, wave64).
 //
 // Paper: Sec. 5.1 (the walk: find the exit edge, stop on scene geometry or at the hull, else
-// continue in the neighbour) and Sec. 5.4 (one operation per visited triangle: choosing the exit
-// edge; two candidates once the entry edge is known, three in the first triangle).
+// continue in the neighbour), Sec. 5.4 (one operation per visited triangle: choosing the exit
+// edge) and the footnote of Sec. 7.2 (two candidates once the entry edge is known, three in the
+// first triangle).
 //
 // Mapping to the hardware:
 //  * The walk is a chain of dependent gathers with a few flops each, bound by memory latency and
 //    gather bandwidth, not by MFMA or the ALUs. One step is one 16-byte load: the slot of the exit
 //    edge holds the neighbour, the entry edge there and the one vertex the next decision needs.
-//  * Waves are persistent. Each wave claims tiles of TPL*64 rays from a global counter, stages
-//    them in its own LDS region (origin, direction and the first exit slot, computed while the
-//    tile is loaded), and refills idle lanes from LDS as soon as `refill_min` of its 64 lanes have
-//    finished, so that divergent ray lengths do not idle the SIMD.
-//  * A single trace finishes in two kernels: at a hit, miss or bad ray the walk stores only
-//    (internal primitive or a negative code, steps) into the ray's 8-byte hit_t slot and frees the
-//    lane at once; finish_rays then turns these into (caller's primitive, t, steps) in input order,
-//    with coalesced accesses and the binary64 division out of the walk loop. A batched launch
-//    finishes its rays in the loop (FIN state).
+//  * Waves are persistent. Each wave claims tiles of TPL*64 rays from global counters (one per
+//    XCD), stages them in its own LDS region (origin, direction, and the start triangle or, for
+//    binned rays, the first exit slot) and refills idle lanes from LDS as soon as `refill_min` of
+//    its 64 lanes have finished, so that divergent ray lengths do not idle the SIMD.
+//  * A single trace finishes in a second kernel: at a hit, miss or bad ray the walk stores only
+//    (primitive or a negative code, steps) into the ray's 8-byte hit_t slot and frees the lane at
+//    once; finish_rays then turns these into (primitive, t, steps) in input order, with coalesced
+//    accesses and the binary64 division out of the walk loop. A batched launch finishes its rays
+//    in the loop (FIN state).
 //  * Decisions: the sign of D(v) = dx*(vy-oy) - dy*(vx-ox), zero counting as LEFT. In binary32 mode
 //    the sign is taken from binary32 coordinates when a forward error bound proves it, otherwise
 //    from the binary64 filter, otherwise from an exact expansion; all three agree with the exact
@@ -160,8 +161,8 @@ __device__ __forceinline__ long long claim_tile(unsigned long long* counter, int
 }
 
 // Each lane is a small state machine that issues exactly one round of loads per iteration:
-//   FIRST: the start triangle's first-triangle record (then three decisions, Sec. 5.4's first
-//          step; rays of binned tiles skip it: binning decided their first triangle),
+//   FIRST: the start triangle's first-triangle record (then three decisions, the first
+//          step of Sec. 7.2's footnote; rays of binned tiles skip it: binning decided their first triangle),
 //   WALK:  the slot of the exit edge (then one decision: the vertex across the entry edge),
 //   FIN:   (batched launches) the hit primitive's record (then the hit distance and results),
 // so lanes in different states share one memory round trip, and a refilled lane starts walking

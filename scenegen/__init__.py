@@ -6,7 +6,7 @@ rays with a known start triangle. It serves both the checker under ``oracle/`` a
 library, and contains none of the walk's arithmetic. The heavy lifting is C++ in ``csrc/``
 (``libscenegen.so``, built by :func:`build`).
 
-Workloads (paper: the "lines" scenes of Sec. 4.3 and the ray experiment of Sec. 5.4):
+Workloads (paper: the "lines" scenes of Sec. 4.2 and the ray experiment of Sec. 5.4):
 
 * ``tiny``   unit square + 64 segments, lengths U[0.02, 0.1]; 65,536 rays.
 * ``grid``   256 x 256 lattice of unit segments trimmed to [0.1, 0.9], rotated 30 degrees about the

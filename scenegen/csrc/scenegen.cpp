@@ -1,6 +1,6 @@
 // Seeded synthetic scenes, triangulations and rays (host side, C ABI for ctypes).
 //
-// Scenes follow the "lines" family of the paper's experiments (Sec. 4.3): non-crossing segments
+// Scenes follow the "lines" family of the paper's experiments (Sec. 4.2): non-crossing segments
 // with uniform midpoints, uniform orientations and a range of lengths, inside a bounding square
 // whose four sides are themselves constrained primitives. Triangulations are the constrained
 // Delaunay triangulation (Sec. 3.5.1 starts from one) and, optionally, a flip-only annealed
