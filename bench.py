@@ -52,7 +52,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "grid", "tiny"])
+    ap.add_argument("--workload", default="large", choices=["large", "grid", "tiny", "batch"],
+                    help="batch: the 256-scene workload in one graph-replayed, autotuned launch")
+    ap.add_argument("--tune-cache", default="", help="JSON file keeping autotuned parameters")
     ap.add_argument("--rays", type=int, default=0, help="override the ray count")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the checker leg")
     ap.add_argument("--no-cpu", action="store_true")
@@ -83,6 +85,9 @@ def main():
     import paper_2112_05570_amd as ccsp
     import scenegen as sg
 
+    if args.workload == "batch":
+        batch_bench(args)
+        return
     dev = torch.device("cuda:0")
     t0 = time.time()
     sc = sg.make_scene(args.workload, seed=0)
@@ -221,6 +226,88 @@ def main():
     }
     print(json.dumps(line), flush=True)
     scene.free()
+
+
+def batch_bench(args):
+    """256 scenes of uneven size and uneven ray counts traced in one persistent launch, replayed
+    from a HIP graph, with launch parameters from the library's autotuner."""
+    import numpy as np
+    import torch
+
+    import paper_2112_05570_amd as ccsp
+    import scenegen as sg
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    scenes, jobs = [], []
+    for _, sc, r in sg.multi_workload("batch", seed=0):
+        scenes.append(ccsp.Scene.from_arrays(sc))
+        out = ccsp.Result(torch.empty(r.n, dtype=torch.int32, device=dev),
+                          torch.empty(r.n, dtype=torch.float64, device=dev),
+                          torch.empty(r.n, dtype=torch.int32, device=dev))
+        jobs.append((scenes[-1], torch.from_numpy(r.o).to(dev), torch.from_numpy(r.d).to(dev),
+                     torch.from_numpy(r.start).to(dev), out))
+    n = sum(j[3].shape[0] for j in jobs)
+    tris = sum(s.n_triangles for s in scenes)
+    log(f"[bench] batch: {len(jobs)} scenes, {tris} triangles, {n} rays built in "
+        f"{time.time() - t0:.1f}s")
+
+    # reference results: one trace per item, default launch parameters
+    refs = [ccsp.trace(s, o, d, st) for s, o, d, st, _ in jobs]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for s, o, d, st, out in jobs:
+        ccsp.trace(s, o, d, st, out=out)
+    torch.cuda.synchronize()
+    ms_items = (time.perf_counter() - t) * 1e3
+
+    def timed(k, tune):
+        for _ in range(2):
+            ccsp.trace_batch(jobs, tune=tune, graph=True)
+        torch.cuda.synchronize()
+        ccsp.read_stage_times()
+        t = time.perf_counter()
+        for _ in range(k):
+            ccsp.trace_batch(jobs, tune=tune, graph=True, timed=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        return wall, ccsp.read_stage_times(k)
+
+    wall_default, _ = timed(max(1, args.steps // 2), ccsp.TuneParams())
+    t = time.perf_counter()
+    best, tuned_ms = ccsp.autotune(jobs, "fp32", graph=True, reps=3,
+                                   cache_path=args.tune_cache or None)
+    tune_s = time.perf_counter() - t
+    log(f"[bench] autotune: {best.as_tuple()} in {tune_s:.1f}s")
+    for _ in range(args.warmup):
+        ccsp.trace_batch(jobs, graph=True)
+    wall, (bin_ms, walk_ms, fin_ms) = timed(args.steps, None)  # None: the tuned parameters
+    torch.cuda.synchronize()
+    same = all(torch.equal(j[4].hit_prim, r.hit_prim) and torch.equal(j[4].steps, r.steps)
+               and torch.equal(j[4].hit_t, r.hit_t) for j, r in zip(jobs, refs))
+    steps_total = int(sum(int(r.steps.sum(dtype=torch.int64).item()) for r in refs))
+    ms = wall / args.steps * 1e3
+    line = {
+        "metric": "rays/s, 256-scene batch in one graph-replayed persistent launch (FP32+filter)",
+        "value": n * args.steps / wall, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"batch: {len(jobs)} scenes, segments log-U[100, 1e5], rays "
+                               f"log-U[1024, 2^20], seed 0",
+                   "items": len(jobs), "rays": n, "triangles": tris},
+        "steps_per_s": steps_total * args.steps / wall,
+        "mean_steps_per_ray": steps_total / n,
+        "graph_replay_ms": float(np.mean(walk_ms)),
+        "tuned": dict(zip(["wg_size", "tile_rays", "waves_per_cu", "refill_min",
+                           "tiles_per_claim", "xcd_chunks", "bin"], best.as_tuple())),
+        "autotune_seconds": tune_s,
+        "default_params_ms_per_step": wall_default / max(1, args.steps // 2) * 1e3,
+        "one_trace_per_item_ms": ms_items,
+        "batch_equals_single_traces": same,
+    }
+    print(json.dumps(line), flush=True)
+    for s in scenes:
+        s.free()
 
 
 def copy_calibration(mib):

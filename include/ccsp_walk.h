@@ -76,8 +76,9 @@ enum {
   CCSP_TRACE_COUNT = 1 << 9,    /* accumulate the counters read by read_counters() */
   CCSP_TRACE_INPUT_ORDER = 1 << 10, /* walk rays in input order instead of binning them first
                                        (see trace_rays) */
-  CCSP_TRACE_TIMED = 1 << 11        /* record HIP events on the stream around the stages of this
+  CCSP_TRACE_TIMED = 1 << 11,       /* record HIP events on the stream around the stages of this
                                        trace, for read_stage_times() */
+  CCSP_TRACE_GRAPH = 1 << 12        /* trace_batch only: replay the launch from a cached HIP graph */
 };
 
 typedef struct Triangulation Triangulation; /* opaque; owns its device memory */
@@ -94,13 +95,20 @@ typedef struct {
   const double *prim_seg;  /* 4*n_prims: ax,ay,bx,by (t is computed from these) */
 } TriangulationDesc;
 
-/* Tuning of the persistent walk (NULL = library defaults). Zero fields take the default. */
+/* Launch parameters of the persistent walk. A zero field takes the default. Passing NULL uses the
+ * device's tuning cache entry for the workload's shape (see autotune), else the defaults. */
 typedef struct {
-  int32_t wg_size;       /* threads per workgroup: 64, 128, 256, 512 */
-  int32_t tile_rays;     /* rays staged per wave in LDS per claim: 64..512, multiple of 64 */
-  int32_t waves_per_cu;  /* persistent waves resident per compute unit (grid size) */
-  int32_t refill_min;    /* refill a wave once at least this many of its 64 lanes are idle */
-  int32_t reserved[4];
+  int32_t wg_size;         /* threads per workgroup: 64..512, multiple of 64 (default 256) */
+  int32_t tile_rays;       /* rays a wave stages in LDS per tile: 64, 128 or 256 (default 64) */
+  int32_t waves_per_cu;    /* persistent waves per compute unit, i.e. the grid (default 24) */
+  int32_t refill_min;      /* refill a wave once this many of its 64 lanes are idle, 1..64
+                              (default 16) */
+  int32_t tiles_per_claim; /* tiles taken per global atomic, 1..4096 (default 4) */
+  int32_t xcd_chunks;      /* 1: one tile counter for the whole launch; 8: one per XCD, each XCD
+                              starting in its own eighth of the rays (default 8) */
+  int32_t bin;             /* trace_rays ray order: 1 = bucket binning by origin cell (default),
+                              2 = radix sort by start triangle; ignored by trace_batch */
+  int32_t reserved;        /* must be 0 */
 } TuneParams;
 
 /*
@@ -150,13 +158,41 @@ typedef struct {
 
 /*
  * trace_batch: walk the rays of n_items items (possibly different triangulations of uneven
- * sizes) in one persistent launch. `items` is a HOST array, read during the call. Results equal
- * those of one trace_rays per item. The item table is uploaded from library-owned pinned memory
- * reserved at the first call (no allocation afterwards unless n_items exceeds every earlier
- * call's). With tune->reserved[0] = 1 the upload and launch are replayed from a cached HIP graph.
+ * sizes) in one persistent launch, then finish them in one more. `items` is a HOST array, read
+ * during the call. Results equal those of one trace_rays per item; rays are walked in input order
+ * (no binning). The item table goes to the device through library-owned rings of pinned and device
+ * tables (allocated at the first call and when n_items exceeds every earlier call's), so batches
+ * may run concurrently on different streams. With CCSP_TRACE_GRAPH the launch is replayed from a
+ * HIP graph cached per (item count, tile count, mode, launch parameters), with its own item table
+ * and tile counters; replays of one graph on different streams are ordered one after the other.
+ * Asynchronous on `stream` (the call may block briefly while a pinned table's previous upload
+ * completes).
  */
 int trace_batch(const TraceItem *items, int32_t n_items, int precision, const TuneParams *tune,
                 void *stream);
+
+/*
+ * autotune: choose launch parameters by measurement. With n_items == 1 and no CCSP_TRACE_GRAPH it
+ * tunes trace_rays on that item, otherwise trace_batch on all items. `precision` is a mode,
+ * optionally with CCSP_TRACE_GRAPH (batches) or CCSP_TRACE_INPUT_ORDER (single traces). Every
+ * candidate is run once untimed and then `reps` times between two HIP events on `stream`; the
+ * search is coordinate-wise from the defaults over waves_per_cu {8..28}, refill_min {4..48},
+ * tile_rays {64, 128, 256}, wg_size {64..512}, tiles_per_claim {1..16} and xcd_chunks {1, 8}, two
+ * passes. The items' outputs are overwritten by every run (with the same, correct results). On
+ * success *best and *best_ms (mean milliseconds per call) hold the winner, which is also stored
+ * in the current device's tuning cache: later trace_rays/trace_batch calls with tune == NULL on a
+ * workload of the same shape (item count, total rays and total triangles rounded up to powers of
+ * two, mode and flags) use it. Synchronises `stream`.
+ */
+int autotune(const TraceItem *items, int32_t n_items, int precision, int32_t reps,
+             TuneParams *best, float *best_ms, void *stream);
+
+/* tune_cache_set: store launch parameters for a workload shape (as autotune would; for reloading
+ * results saved earlier). tune_cache_get: 1 and *out if the shape has an entry, 0 if not. */
+int tune_cache_set(int32_t n_items, int64_t total_rays, int64_t total_triangles, int precision,
+                   const TuneParams *tune);
+int tune_cache_get(int32_t n_items, int64_t total_rays, int64_t total_triangles, int precision,
+                   TuneParams *out);
 
 /* reserve_workspace: reserve the ray binning scratch for traces of up to max_rays rays on the
  * current device, so that later traces allocate nothing. */
@@ -181,8 +217,8 @@ int read_counters(uint64_t out[4], int reset);
  * current device, oldest first, measured with HIP events on each trace's stream. bin_ms[i] runs
  * from the start of the trace to the start of the walk kernel (the ray binning; about zero for a
  * trace that does not bin; the item-table upload for trace_batch), walk_ms[i] covers the walk
- * kernel alone (a whole replayed graph for trace_batch with a graph), finish_ms[i] the finishing
- * pass that writes a single trace's results (zero for trace_batch, which finishes in the walk).
+ * kernel alone, finish_ms[i] the finishing pass that writes the results (for trace_batch with
+ * CCSP_TRACE_GRAPH the whole replayed graph counts as walk and finish_ms[i] is zero).
  * The library keeps the last 256 timed traces per device; this call writes up to max_records of
  * the most recent ones, sets *n_records to their number, and forgets all kept records. Blocks
  * until those traces finish.

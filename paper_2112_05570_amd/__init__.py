@@ -13,9 +13,9 @@ import numpy as np
 
 from . import binding as B
 from .binding import (CCSP_RAY_BAD, CCSP_RAY_GUARD, CCSP_RAY_MISS, CCSP_TRACE_COUNT,
-                      CCSP_TRACE_FP32_FILTERED, CCSP_TRACE_FP64, CCSP_TRACE_INPUT_ORDER,
-                      CCSP_TRACE_TIMED, CCSP_TRACE_VALIDATE, CcspError, TuneParams,
-                      read_stage_times, reserve_workspace)
+                      CCSP_TRACE_FP32_FILTERED, CCSP_TRACE_FP64, CCSP_TRACE_GRAPH,
+                      CCSP_TRACE_INPUT_ORDER, CCSP_TRACE_TIMED, CCSP_TRACE_VALIDATE, CcspError,
+                      TuneParams, read_stage_times, reserve_workspace)
 
 PRECISION = {"fp64": CCSP_TRACE_FP64, "fp32": CCSP_TRACE_FP32_FILTERED}
 
@@ -115,9 +115,7 @@ def trace(scene: Scene, o, d, start, precision="fp32", out: Result | None = None
     return res
 
 
-def trace_batch(jobs, precision="fp32", tune: TuneParams | None = None, stream=None,
-                graph=False, count=False, timed=False):
-    """jobs: list of (Scene, o, d, start[, Result]). Returns the list of Results."""
+def _items(jobs):
     items, results = [], []
     for job in jobs:
         scene, o, d, start = job[:4]
@@ -127,13 +125,50 @@ def trace_batch(jobs, precision="fp32", tune: TuneParams | None = None, stream=N
         items.append(B.TraceItem(scene.handle, o.data_ptr(), d.data_ptr(), start.data_ptr(), n,
                                  res.hit_prim.data_ptr(), res.hit_t.data_ptr(),
                                  res.steps.data_ptr()))
-    if graph:
-        tune = tune or TuneParams()
-        tune = TuneParams(tune.wg_size, tune.tile_rays, tune.waves_per_cu, tune.refill_min,
-                          (ctypes.c_int32 * 4)(1, 0, 0, 0))
+    return items, results
+
+
+def trace_batch(jobs, precision="fp32", tune: TuneParams | None = None, stream=None,
+                graph=False, count=False, timed=False):
+    """jobs: list of (Scene, o, d, start[, Result]). Returns the list of Results. tune=None uses
+    the autotuned parameters for this workload shape if there are any."""
+    items, results = _items(jobs)
     B.trace_batch(items, _mode(precision) | (CCSP_TRACE_COUNT if count else 0)
-                  | (CCSP_TRACE_TIMED if timed else 0), tune, _stream(stream))
+                  | (CCSP_TRACE_TIMED if timed else 0) | (CCSP_TRACE_GRAPH if graph else 0),
+                  tune, _stream(stream))
     return results
+
+
+def autotune(jobs, precision="fp32", graph=False, input_order=False, reps=3, stream=None,
+             cache_path=None):
+    """Launch parameters for this workload, chosen by measurement in the library (see
+    ``autotune`` in the C header) and kept in its per-device cache, so that later traces of the
+    same shape with tune=None use them. With ``cache_path`` the choice is also kept in a JSON file
+    and a matching entry there is reused without measuring. One job without ``graph`` tunes
+    :func:`trace`; otherwise :func:`trace_batch`. Returns (TuneParams, ms per call or None)."""
+    import json
+    import os
+    flags = _mode(precision) | (CCSP_TRACE_GRAPH if graph else 0) | \
+        (CCSP_TRACE_INPUT_ORDER if input_order else 0)
+    shape = dict(n_items=len(jobs), rays=int(sum(j[3].shape[0] for j in jobs)),
+                 triangles=int(sum(j[0].n_triangles for j in jobs)), precision=flags)
+    entries = []
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            entries = json.load(f)
+        for e in entries:
+            B.tune_cache_set(e["n_items"], e["rays"], e["triangles"], e["precision"],
+                             TuneParams(*e["params"]))
+        hit = B.tune_cache_get(shape["n_items"], shape["rays"], shape["triangles"], flags)
+        if hit is not None:
+            return hit, None
+    items, _ = _items(jobs)
+    best, ms = B.autotune(items, flags, reps, _stream(stream))
+    if cache_path:
+        entries.append(dict(shape, params=list(best.as_tuple()), ms=ms))
+        with open(cache_path, "w") as f:
+            json.dump(entries, f, indent=1)
+    return best, ms
 
 
 def read_counters(reset=False):

@@ -39,10 +39,12 @@ CCSP_TRACE_VALIDATE = 1 << 8
 CCSP_TRACE_COUNT = 1 << 9
 CCSP_TRACE_INPUT_ORDER = 1 << 10
 CCSP_TRACE_TIMED = 1 << 11
+CCSP_TRACE_GRAPH = 1 << 12
 
 EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch",
            "free_triangulation", "last_error", "read_counters", "triangulation_info",
-           "reserve_workspace", "gather_roofline", "read_stage_times")
+           "reserve_workspace", "gather_roofline", "read_stage_times", "autotune",
+           "tune_cache_set", "tune_cache_get")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -55,7 +57,11 @@ class TriangulationDesc(ctypes.Structure):
 class TuneParams(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("tile_rays", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("refill_min", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("tiles_per_claim", ctypes.c_int32), ("xcd_chunks", ctypes.c_int32),
+                ("bin", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return tuple(getattr(self, f) for f, _ in self._fields_[:-1])
 
 
 class TraceItem(ctypes.Structure):
@@ -92,6 +98,13 @@ _lib.read_stage_times.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_float)
                                   ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                   ctypes.POINTER(ctypes.c_int32)]
 _lib.read_stage_times.restype = _I
+_lib.autotune.argtypes = [ctypes.POINTER(TraceItem), ctypes.c_int32, _I, ctypes.c_int32,
+                          ctypes.POINTER(TuneParams), ctypes.POINTER(ctypes.c_float), _P]
+_lib.autotune.restype = _I
+_lib.tune_cache_set.argtypes = [ctypes.c_int32, _I64, _I64, _I, ctypes.POINTER(TuneParams)]
+_lib.tune_cache_set.restype = _I
+_lib.tune_cache_get.argtypes = [ctypes.c_int32, _I64, _I64, _I, ctypes.POINTER(TuneParams)]
+_lib.tune_cache_get.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -155,6 +168,30 @@ def read_stage_times(max_records: int = 256) -> tuple:
     n = ctypes.c_int32()
     _check(_lib.read_stage_times(max_records, b, w, f, ctypes.byref(n)))
     return list(b[:n.value]), list(w[:n.value]), list(f[:n.value])
+
+
+def autotune(items, precision: int, reps: int = 3, stream: int = 0) -> tuple:
+    """(TuneParams, mean ms per call) chosen by measurement; see the header."""
+    arr = (TraceItem * len(items))(*items)
+    best = TuneParams()
+    ms = ctypes.c_float()
+    _check(_lib.autotune(arr, len(items), precision, reps, ctypes.byref(best), ctypes.byref(ms),
+                         _P(stream)))
+    return best, ms.value
+
+
+def tune_cache_set(n_items: int, total_rays: int, total_triangles: int, precision: int,
+                   tune: TuneParams) -> None:
+    _check(_lib.tune_cache_set(n_items, total_rays, total_triangles, precision, ctypes.byref(tune)))
+
+
+def tune_cache_get(n_items: int, total_rays: int, total_triangles: int, precision: int):
+    """The cached TuneParams for this workload shape, or None."""
+    out = TuneParams()
+    rc = _lib.tune_cache_get(n_items, total_rays, total_triangles, precision, ctypes.byref(out))
+    if rc < 0:
+        _check(rc)
+    return out if rc == 1 else None
 
 
 def triangulation_info(tri: int) -> list:

@@ -13,6 +13,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <array>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -103,18 +105,37 @@ struct StageEvents {
 };
 constexpr int kTimeSlots = 256;
 
+struct TableSlot {
+  void* p = nullptr;
+  hipEvent_t free_ev = nullptr;
+  bool used = false;
+};
+constexpr int kTableSlots = 16;
+
+struct BatchGraph {
+  hipGraphExec_t exec = nullptr;
+  BatchItem* dev = nullptr;             // its item table (the upload before each replay fills it)
+  unsigned long long* counter = nullptr;
+  hipEvent_t done = nullptr;            // after its last replay
+  hipStream_t last = nullptr;
+  bool used = false;
+};
+
 struct DeviceState {
   bool init = false;
   int cus = 0;
   Workspace ws{};
   std::atomic<unsigned> next_counter{0};
-  // trace_batch staging
+  // trace_batch item tables: a ring of pinned host tables and a ring of device tables, each
+  // with an event after which it may be reused (host: its upload is done; device: the launch
+  // that read it is done), so that batches on different streams never share a live table
   std::mutex mu;
-  BatchItem* items_dev = nullptr;
-  BatchItem* items_host = nullptr;  // pinned
+  std::vector<TableSlot> host_ring, dev_ring;
   int items_cap = 0;
-  hipEvent_t staging_free = nullptr;
-  std::unordered_map<uint64_t, hipGraphExec_t> graphs;
+  unsigned ring_next = 0;
+  // captured batch launches, by everything the capture bakes in; each owns its device table
+  // and tile counters
+  std::map<std::array<int64_t, 10>, BatchGraph> graphs;
   // ray binning scratch, shared by the traces on this device
   std::mutex bin_mu;
   void* bin_ws = nullptr;
@@ -125,6 +146,9 @@ struct DeviceState {
   std::mutex time_mu;
   std::vector<StageEvents> tev;
   int time_next = 0, time_count = 0;
+  // launch parameters chosen by autotune() (or set with tune_cache_set), by workload shape
+  std::mutex tune_mu;
+  std::unordered_map<uint64_t, TuneParams> tuned;
 };
 
 std::mutex g_dev_mu;
@@ -149,8 +173,7 @@ int device_state(DeviceState** out) {
     s.ws.counters = static_cast<unsigned long long*>(p);
     s.ws.stats = s.ws.counters + kCounterSlots;
     s.ws.errflag = reinterpret_cast<int*>(s.ws.stats + 4);
-    e = hipEventCreateWithFlags(&s.staging_free, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.bin_free, hipEventDisableTiming);
+    e = hipEventCreateWithFlags(&s.bin_free, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     s.init = true;
   }
@@ -162,10 +185,10 @@ int device_state(DeviceState** out) {
 constexpr int64_t kBinMinRays = 1 << 16;
 constexpr int64_t kBinMinTriangles = 1 << 18;
 
-// Tile counters of the next launch: a ring of kCounterSlots / kClaimChunks groups (the last group
-// is reserved for captured graphs), so that launches in flight on different streams never share.
+// Tile counters of the next eager launch: a ring of kCounterSlots / kClaimChunks groups, so that
+// launches in flight on different streams never share (captured graphs have their own).
 unsigned long long* next_counters(DeviceState* ds) {
-  const unsigned groups = kCounterSlots / kClaimChunks - 1;
+  const unsigned groups = kCounterSlots / kClaimChunks;
   return ds->ws.counters + (size_t)(ds->next_counter.fetch_add(1) % groups) * kClaimChunks;
 }
 
@@ -186,6 +209,29 @@ int grow_bin_workspace(DeviceState* ds, int64_t n) {
   if (e != hipSuccess) return fail(CCSP_E_OOM, "ray binning scratch of %zu bytes: %s", need, hipGetErrorString(e));
   ds->bin_ws_bytes = need;
   return CCSP_OK;
+}
+
+// Shape of a workload for the tuning cache: item count, total rays and total triangles rounded
+// up to powers of two, precision mode, graph replay, input order, and whether it is a single
+// trace (trace_rays) or a batch.
+uint64_t tune_key(int64_t n_items, int64_t rays, int64_t tris, int precision, bool single) {
+  auto lg = [](int64_t v) {
+    int b = 0;
+    while (b < 62 && (int64_t(1) << b) < v) ++b;
+    return (uint64_t)b;
+  };
+  return lg(n_items) | lg(rays) << 8 | lg(tris) << 16 |
+         (uint64_t)(precision & CCSP_TRACE_MODE_MASK) << 24 |
+         (uint64_t)((precision & CCSP_TRACE_GRAPH) != 0) << 32 | (uint64_t)single << 33 |
+         (uint64_t)((precision & CCSP_TRACE_INPUT_ORDER) != 0) << 34;
+}
+
+bool tune_lookup(DeviceState* ds, uint64_t key, TuneParams* out) {
+  std::lock_guard<std::mutex> lk(ds->tune_mu);
+  auto it = ds->tuned.find(key);
+  if (it == ds->tuned.end()) return false;
+  *out = it->second;
+  return true;
 }
 
 // The next record of the timing ring (its events are created on the first timed trace).
@@ -211,6 +257,83 @@ int timing_slot(DeviceState* ds, StageEvents** out) {
   return CCSP_OK;
 }
 
+// Grow the trace_batch item tables to hold n_items (first call, or a batch larger than any
+// before); waits for the device first, since the old tables may still be read. Caller holds
+// ds->mu.
+int grow_item_tables(DeviceState* ds, int n_items) {
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  int cap = 256;
+  while (cap < n_items) cap *= 2;
+  ds->items_cap = 0;
+  ds->host_ring.resize(kTableSlots);
+  ds->dev_ring.resize(kTableSlots);
+  for (int k = 0; k < kTableSlots; ++k) {
+    TableSlot& h = ds->host_ring[k];
+    TableSlot& d = ds->dev_ring[k];
+    if (h.p) (void)hipHostFree(h.p);
+    if (d.p) (void)hipFree(d.p);
+    h.p = d.p = nullptr;
+    h.used = d.used = false;
+    for (TableSlot* s : {&h, &d})
+      if (!s->free_ev) {
+        e = hipEventCreateWithFlags(&s->free_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+      }
+    e = hipHostMalloc(&h.p, sizeof(BatchItem) * cap, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(CCSP_E_OOM, "pinned item table allocation failed");
+    e = hipMalloc(&d.p, sizeof(BatchItem) * cap);
+    if (e != hipSuccess) return fail(CCSP_E_OOM, "item table allocation failed");
+  }
+  ds->items_cap = cap;
+  return CCSP_OK;
+}
+
+// Capture (reset, walk, finish) of a batch of n_items items and `tiles` tiles into a graph with
+// its own item table and tile counters.
+int capture_batch_graph(DeviceState* ds, int n_items, int64_t tiles, int mode, bool count,
+                        const LaunchCfg& cfg, BatchGraph* g) {
+  auto cleanup = [g] {
+    if (g->dev) (void)hipFree(g->dev);
+    if (g->counter) (void)hipFree(g->counter);
+    if (g->done) (void)hipEventDestroy(g->done);
+    *g = BatchGraph{};
+  };
+  hipError_t e = hipMalloc(&g->dev, sizeof(BatchItem) * n_items);
+  if (e == hipSuccess) e = hipMalloc(&g->counter, sizeof(unsigned long long) * kClaimChunks);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(CCSP_E_OOM, "graph item table allocation failed");
+  }
+  e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "hipEventCreate");
+  }
+  hipStream_t cs = nullptr;
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "capture stream");
+  }
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  hipError_t e2 = hipSuccess, e3 = hipSuccess;
+  if (e == hipSuccess) {
+    e2 = launch_walk_batch(g->dev, n_items, tiles, mode, count, cfg, g->counter, ds->ws, cs);
+    e3 = hipStreamEndCapture(cs, &graph);
+  }
+  (void)hipStreamDestroy(cs);
+  if (e == hipSuccess) e = e2 != hipSuccess ? e2 : e3;
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "graph capture");
+  }
+  return CCSP_OK;
+}
+
 LaunchCfg make_cfg(const DeviceState& ds, int mode, const TuneParams* tp) {
   LaunchCfg c{};
   c.wg = (tp && tp->wg_size) ? tp->wg_size : 256;
@@ -218,16 +341,28 @@ LaunchCfg make_cfg(const DeviceState& ds, int mode, const TuneParams* tp) {
   const int wpcu = (tp && tp->waves_per_cu) ? tp->waves_per_cu : 24;
   c.refill_min = (tp && tp->refill_min) ? tp->refill_min : 16;
   c.grid = std::max(1, ds.cus * wpcu / (c.wg / 64));
-  c.chunks = (tp && tp->reserved[1] == 1) ? 1 : kClaimChunks;
-  c.group = (tp && tp->reserved[3] > 0) ? tp->reserved[3] : 4;
+  c.chunks = (tp && tp->xcd_chunks) ? tp->xcd_chunks : kClaimChunks;
+  c.group = (tp && tp->tiles_per_claim) ? tp->tiles_per_claim : 4;
   return c;
+}
+
+int check_tune(const TuneParams* tp) {
+  if (!tp) return CCSP_OK;
+  if (tp->wg_size < 0 || tp->tile_rays < 0 || tp->waves_per_cu < 0 || tp->refill_min < 0 ||
+      tp->tiles_per_claim < 0 || tp->xcd_chunks < 0)
+    return fail(CCSP_E_ARG, "negative tuning field");
+  if (tp->waves_per_cu > 64) return fail(CCSP_E_ARG, "waves_per_cu %d must be at most 64", tp->waves_per_cu);
+  if (tp->bin < 0 || tp->bin > 2) return fail(CCSP_E_ARG, "bin %d must be 0, 1 or 2", tp->bin);
+  if (tp->reserved != 0) return fail(CCSP_E_ARG, "reserved tuning field must be 0");
+  return CCSP_OK;
 }
 
 int check_cfg(const LaunchCfg& c) {
   if (c.wg < 64 || c.wg > 512 || c.wg % 64) return fail(CCSP_E_ARG, "wg_size %d must be 64..512, multiple of 64", c.wg);
   if (c.tile != 64 && c.tile != 128 && c.tile != 256) return fail(CCSP_E_ARG, "tile_rays %d must be 64, 128 or 256", c.tile);
   if (c.refill_min < 1 || c.refill_min > 64) return fail(CCSP_E_ARG, "refill_min %d must be 1..64", c.refill_min);
-  if (c.group < 1 || c.group > 4096) return fail(CCSP_E_ARG, "tile group %d must be 1..4096", c.group);
+  if (c.group < 1 || c.group > 4096) return fail(CCSP_E_ARG, "tiles_per_claim %d must be 1..4096", c.group);
+  if (c.chunks != 1 && c.chunks != kClaimChunks) return fail(CCSP_E_ARG, "xcd_chunks %d must be 1 or 8", c.chunks);
   return CCSP_OK;
 }
 
@@ -499,6 +634,10 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
   DeviceState* ds = nullptr;
   rc = device_state(&ds);
   if (rc) return rc;
+  rc = check_tune(tune);
+  if (rc) return rc;
+  TuneParams cached;
+  if (!tune && tune_lookup(ds, tune_key(1, n, tri->nt, precision, true), &cached)) tune = &cached;
   const LaunchCfg cfg = make_cfg(*ds, mode, tune);
   rc = check_cfg(cfg);
   if (rc) return rc;
@@ -529,7 +668,7 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
       if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     }
     RaysDev binned{};
-    e = launch_bin_rays(tri->dev, io, (tune && tune->reserved[2] == kBinRadix) ? kBinRadix : kBinBuckets,
+    e = launch_bin_rays(tri->dev, io, (tune && tune->bin == 2) ? kBinRadix : kBinBuckets,
                         ds->bin_ws, ds->bin_ws_bytes, &binned, count ? ds->ws.stats : nullptr, st);
     io = binned;
     if (e != hipSuccess) return hip_fail(e, "ray binning");
@@ -576,57 +715,56 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
   const int mode = precision & CCSP_TRACE_MODE_MASK;
   if (mode != CCSP_TRACE_FP64 && mode != CCSP_TRACE_FP32_FILTERED)
     return fail(CCSP_E_ARG, "unknown precision mode %d", mode);
-  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_COUNT | CCSP_TRACE_TIMED))
+  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_COUNT | CCSP_TRACE_TIMED | CCSP_TRACE_GRAPH))
     return fail(CCSP_E_ARG, "unsupported precision flags 0x%x for trace_batch", precision);
+  int rc = check_tune(tune);
+  if (rc) return rc;
   DeviceState* ds = nullptr;
-  int rc = device_state(&ds);
+  rc = device_state(&ds);
   if (rc) return rc;
-  const LaunchCfg cfg = make_cfg(*ds, mode, tune);
-  rc = check_cfg(cfg);
-  if (rc) return rc;
-  const bool use_graph = tune && tune->reserved[0] == 1;
-  int64_t tiles = 0;
+  int64_t total_rays = 0, total_tris = 0;
   for (int i = 0; i < n_items; ++i) {
     const TraceItem& it = items[i];
     if (!it.scene) return fail(CCSP_E_ARG, "item %d: null scene", i);
     rc = check_rays(it.o_xy, it.d_xy, it.start_tri, it.n, it.hit_prim, it.hit_t, it.steps);
     if (rc) return fail(rc, "item %d: %s", i, g_err.c_str());
-    tiles += (it.n + cfg.tile - 1) / cfg.tile;
+    total_rays += it.n;
+    total_tris += it.scene->nt;
   }
+  TuneParams cached;
+  if (!tune && tune_lookup(ds, tune_key(n_items, total_rays, total_tris, precision, false), &cached))
+    tune = &cached;
+  const LaunchCfg cfg = make_cfg(*ds, mode, tune);
+  rc = check_cfg(cfg);
+  if (rc) return rc;
+  const bool use_graph = precision & CCSP_TRACE_GRAPH;
+  int64_t tiles = 0;
+  for (int i = 0; i < n_items; ++i) tiles += (items[i].n + cfg.tile - 1) / cfg.tile;
   if (tiles == 0) return CCSP_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(ds->mu);
   hipError_t e;
-  if (n_items > ds->items_cap) {  // grow the staging buffers (first call or a larger batch)
-    if (ds->items_dev) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(ds->items_dev);
-      (void)hipHostFree(ds->items_host);
-      for (auto& kv : ds->graphs) (void)hipGraphExecDestroy(kv.second);
-      ds->graphs.clear();
-    }
-    int cap = 256;
-    while (cap < n_items) cap *= 2;
-    e = hipMalloc(&ds->items_dev, sizeof(BatchItem) * cap);
-    if (e != hipSuccess) return fail(CCSP_E_OOM, "item table allocation failed");
-    e = hipHostMalloc(&ds->items_host, sizeof(BatchItem) * cap, hipHostMallocDefault);
-    if (e != hipSuccess) return fail(CCSP_E_OOM, "pinned item table allocation failed");
-    ds->items_cap = cap;
+  if (n_items > ds->items_cap) {
+    rc = grow_item_tables(ds, n_items);
+    if (rc) return rc;
   }
-  // the pinned table may still be read by the previous batch's upload
-  e = hipEventSynchronize(ds->staging_free);
-  if (e != hipSuccess) return hip_fail(e, "staging wait");
+  const unsigned slot = ds->ring_next++ % kTableSlots;
+  TableSlot& hs = ds->host_ring[slot];
+  if (hs.used) {  // this pinned table's previous upload must be done before it is rewritten
+    e = hipEventSynchronize(hs.free_ev);
+    if (e != hipSuccess) return hip_fail(e, "staging wait");
+  }
+  BatchItem* host = static_cast<BatchItem*>(hs.p);
   int64_t tb = 0;
   for (int i = 0; i < n_items; ++i) {
     const TraceItem& it = items[i];
-    BatchItem& b = ds->items_host[i];
+    BatchItem& b = host[i];
     b.scene = it.scene->dev;
     b.rays = RaysDev{reinterpret_cast<const double2*>(it.o_xy), reinterpret_cast<const double2*>(it.d_xy),
                      it.start_tri, it.hit_prim, it.hit_t, it.steps, it.n};
     b.tile_begin = tb;
     tb += (it.n + cfg.tile - 1) / cfg.tile;
   }
-  unsigned long long* counter = next_counters(ds);
   const bool count = precision & CCSP_TRACE_COUNT;
   StageEvents* tev = nullptr;
   if (precision & CCSP_TRACE_TIMED) {
@@ -635,14 +773,46 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
     e = hipEventRecord(tev->ev[0], st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   }
-  if (!use_graph) {
-    e = hipMemcpyAsync(ds->items_dev, ds->items_host, sizeof(BatchItem) * n_items, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "item table upload");
-    e = hipEventRecord(ds->staging_free, st);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = launch_walk_batch(ds->items_dev, n_items, tiles, mode, count, cfg, counter, ds->ws, st,
-                          tev ? tev->ev[1] : nullptr);
-    if (e != hipSuccess) return hip_fail(e, "batch launch");
+  BatchGraph* g = nullptr;
+  TableSlot* dslot = nullptr;
+  BatchItem* table = nullptr;
+  if (use_graph) {
+    // (reset, walk, finish) captured once per key and replayed; the item table is uploaded into
+    // the graph's own table before each replay
+    const std::array<int64_t, 10> key{n_items, tiles,    mode,           (int64_t)count, cfg.wg,
+                                      cfg.tile, cfg.grid, cfg.refill_min, cfg.chunks,     cfg.group};
+    auto itg = ds->graphs.find(key);
+    if (itg == ds->graphs.end()) {
+      BatchGraph ng;
+      rc = capture_batch_graph(ds, n_items, tiles, mode, count, cfg, &ng);
+      if (rc) return rc;
+      itg = ds->graphs.emplace(key, ng).first;
+    }
+    g = &itg->second;
+    if (g->used && g->last != st) {
+      e = hipStreamWaitEvent(st, g->done, 0);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    }
+    table = g->dev;
+  } else {
+    dslot = &ds->dev_ring[slot];
+    if (dslot->used) {  // the launch that last read this device table must be done
+      e = hipStreamWaitEvent(st, dslot->free_ev, 0);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    }
+    table = static_cast<BatchItem*>(dslot->p);
+  }
+  e = hipMemcpyAsync(table, host, sizeof(BatchItem) * n_items, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(hs.free_ev, st);
+  if (e != hipSuccess) return hip_fail(e, "item table upload");
+  hs.used = true;
+  if (g) {
+    if (tev) e = hipEventRecord(tev->ev[1], st);
+    if (e == hipSuccess) e = hipGraphLaunch(g->exec, st);
+    if (e == hipSuccess) e = hipEventRecord(g->done, st);
+    if (e != hipSuccess) return hip_fail(e, "graph replay");
+    g->last = st;
+    g->used = true;
     if (tev) {
       e = hipEventRecord(tev->ev[2], st);
       if (e == hipSuccess) e = hipEventRecord(tev->ev[3], st);
@@ -650,45 +820,16 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
     }
     return CCSP_OK;
   }
-  // Graph path: (upload, reset, walk) captured once per (n_items, tiles, mode, count, cfg,
-  // counter) and replayed; the upload node reads the pinned table at replay time.
-  const uint64_t key = ((uint64_t)n_items << 40) ^ ((uint64_t)tiles << 8) ^ ((uint64_t)mode << 4) ^
-                       ((uint64_t)count << 3) ^ ((uint64_t)cfg.tile << 50) ^ ((uint64_t)cfg.wg << 56) ^
-                       ((uint64_t)cfg.refill_min << 20) ^ ((uint64_t)cfg.grid << 28);
-  counter = ds->ws.counters + kCounterSlots - kClaimChunks;  // graphs use the reserved last slot
-  auto itg = ds->graphs.find(key);
-  if (itg == ds->graphs.end()) {
-    hipStream_t cap_stream;
-    e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_fail(e, "capture stream");
-    e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t e1 = hipMemcpyAsync(ds->items_dev, ds->items_host, sizeof(BatchItem) * n_items,
-                                   hipMemcpyHostToDevice, cap_stream);
-    hipError_t e2 = launch_walk_batch(ds->items_dev, n_items, tiles, mode, count, cfg, counter, ds->ws, cap_stream);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(cap_stream, &g);
-    (void)hipStreamDestroy(cap_stream);
-    if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) return hip_fail(e != hipSuccess ? e : (e1 != hipSuccess ? e1 : e2), "graph capture");
-    hipGraphExec_t ge = nullptr;
-    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    itg = ds->graphs.emplace(key, ge).first;
-  }
-  if (tev) {
-    e = hipEventRecord(tev->ev[1], st);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-  }
-  e = hipGraphLaunch(itg->second, st);
-  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-  if (tev) {
-    e = hipEventRecord(tev->ev[2], st);
-    if (e == hipSuccess) e = hipEventRecord(tev->ev[3], st);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-  }
-  e = hipEventRecord(ds->staging_free, st);
+  e = launch_walk_batch(table, n_items, tiles, mode, count, cfg, next_counters(ds), ds->ws, st,
+                        tev ? tev->ev[1] : nullptr, tev ? tev->ev[2] : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "batch launch");
+  e = hipEventRecord(dslot->free_ev, st);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  dslot->used = true;
+  if (tev) {
+    e = hipEventRecord(tev->ev[3], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  }
   return CCSP_OK;
 }
 
@@ -700,6 +841,122 @@ int reserve_workspace(int64_t max_rays) {
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(ds->bin_mu);
   return grow_bin_workspace(ds, max_rays);
+}
+
+int tune_cache_set(int32_t n_items, int64_t total_rays, int64_t total_triangles, int precision,
+                   const TuneParams* tune) {
+  g_err.clear();
+  if (!tune || n_items < 1 || total_rays < 0 || total_triangles < 0)
+    return fail(CCSP_E_ARG, "bad tuning cache entry");
+  int rc = check_tune(tune);
+  if (rc) return rc;
+  DeviceState* ds = nullptr;
+  rc = device_state(&ds);
+  if (rc) return rc;
+  LaunchCfg cfg = make_cfg(*ds, precision & CCSP_TRACE_MODE_MASK, tune);
+  rc = check_cfg(cfg);
+  if (rc) return rc;
+  const bool single = n_items == 1 && !(precision & CCSP_TRACE_GRAPH);
+  std::lock_guard<std::mutex> lk(ds->tune_mu);
+  ds->tuned[tune_key(n_items, total_rays, total_triangles, precision, single)] = *tune;
+  return CCSP_OK;
+}
+
+int tune_cache_get(int32_t n_items, int64_t total_rays, int64_t total_triangles, int precision,
+                   TuneParams* out) {
+  g_err.clear();
+  if (!out || n_items < 1 || total_rays < 0 || total_triangles < 0)
+    return fail(CCSP_E_ARG, "bad tuning cache query");
+  DeviceState* ds = nullptr;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  const bool single = n_items == 1 && !(precision & CCSP_TRACE_GRAPH);
+  return tune_lookup(ds, tune_key(n_items, total_rays, total_triangles, precision, single), out) ? 1 : 0;
+}
+
+int autotune(const TraceItem* items, int32_t n_items, int precision, int32_t reps,
+             TuneParams* best, float* best_ms, void* stream) {
+  g_err.clear();
+  if (!items || n_items < 1 || !best || !best_ms) return fail(CCSP_E_ARG, "null or empty argument");
+  if (reps < 1 || reps > 1000) return fail(CCSP_E_ARG, "reps %d must be 1..1000", reps);
+  const bool single = n_items == 1 && !(precision & CCSP_TRACE_GRAPH);
+  if (precision & (CCSP_TRACE_TIMED | CCSP_TRACE_VALIDATE | CCSP_TRACE_COUNT))
+    return fail(CCSP_E_ARG, "autotune takes a precision mode, CCSP_TRACE_GRAPH or CCSP_TRACE_INPUT_ORDER");
+  DeviceState* ds = nullptr;
+  int rc = device_state(&ds);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+      return fail(CCSP_E_HIP, "hipEventCreate");
+    }
+  auto run = [&](const TuneParams& tp) -> int {
+    const TraceItem& it = items[0];
+    return single ? trace_rays_tuned(it.scene, it.o_xy, it.d_xy, it.start_tri, it.n, precision,
+                                     it.hit_prim, it.hit_t, it.steps, &tp, stream)
+                  : trace_batch(items, n_items, precision, &tp, stream);
+  };
+  // mean time of `reps` calls after one untimed call (which also builds graphs and scratch)
+  auto measure = [&](const TuneParams& tp, float* ms) -> int {
+    int r = run(tp);
+    if (r) return r;
+    hipError_t e = hipEventRecord(ev[0], st);
+    for (int k = 0; k < reps && e == hipSuccess && r == CCSP_OK; ++k) r = run(tp);
+    if (r) return r;
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    *ms /= (float)reps;
+    return CCSP_OK;
+  };
+  // coordinate search from the defaults: each parameter in turn over its candidates, the others
+  // fixed, keeping the fastest; two passes
+  TuneParams cur{256, 64, 24, 16, 4, kClaimChunks, 0, 0};
+  float cur_ms = 0;
+  rc = measure(cur, &cur_ms);
+  struct Axis {
+    int32_t TuneParams::*field;
+    std::vector<int32_t> values;
+  };
+  const Axis axes[] = {
+      {&TuneParams::waves_per_cu, {8, 12, 16, 20, 24, 28}},
+      {&TuneParams::refill_min, {4, 8, 16, 24, 32, 48}},
+      {&TuneParams::tile_rays, {64, 128, 256}},
+      {&TuneParams::wg_size, {64, 128, 256, 512}},
+      {&TuneParams::tiles_per_claim, {1, 2, 4, 8, 16}},
+      {&TuneParams::xcd_chunks, {1, kClaimChunks}},
+  };
+  for (int pass = 0; pass < 2 && rc == CCSP_OK; ++pass)
+    for (const Axis& ax : axes)
+      for (int32_t v : ax.values) {
+        if (rc || cur.*ax.field == v) continue;
+        TuneParams cand = cur;
+        cand.*ax.field = v;
+        float ms = 0;
+        rc = measure(cand, &ms);
+        if (rc == CCSP_OK && ms < cur_ms) {
+          cur = cand;
+          cur_ms = ms;
+        }
+      }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  int64_t rays = 0, tris = 0;
+  for (int i = 0; i < n_items; ++i) {
+    rays += items[i].n;
+    tris += items[i].scene->nt;
+  }
+  {
+    std::lock_guard<std::mutex> lk(ds->tune_mu);
+    ds->tuned[tune_key(n_items, rays, tris, precision, single)] = cur;
+  }
+  *best = cur;
+  *best_ms = cur_ms;
+  return CCSP_OK;
 }
 
 int read_stage_times(int32_t max_records, float* bin_ms, float* walk_ms, float* finish_ms,

@@ -69,21 +69,6 @@ static __device__ __attribute__((noinline)) bool left_deferred(double2 o, double
   return l;
 }
 
-// Exact check of a ray's precondition: finite nonzero direction, finite origin strictly inside
-// internal triangle `st`.
-static __device__ __attribute__((noinline)) bool validate_ray(const SceneDev& sc, double2 o,
-                                                              double2 d, int st) {
-  const int4 tv = sc.triv[st];
-  const double2 v[3] = {sc.v64[tv.x], sc.v64[tv.y], sc.v64[tv.z]};
-  bool ok = isfinite(d.x) && isfinite(d.y) && (d.x != 0.0 || d.y != 0.0) && isfinite(o.x) &&
-            isfinite(o.y);
-  for (int i = 0; i < 3; ++i) {
-    const double2 a = v[(i + 1) % 3], b = v[(i + 2) % 3];
-    ok = ok && orient_exact(a.x, a.y, b.x, b.y, o.x, o.y) > 0;
-  }
-  return ok;
-}
-
 __device__ __forceinline__ double hit_t(const double4 g, double ox, double oy, double dx,
                                         double dy) {
   const double ex = g.z - g.x;

@@ -120,10 +120,11 @@ hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool cou
                        hipStream_t stream, hipEvent_t walk_begin = nullptr,
                        hipEvent_t walk_end = nullptr);
 
+// A batch: the walk kernel over every item's tiles, then finish_batch.
 hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t total_tiles,
                              int mode, bool count, const LaunchCfg& cfg,
                              unsigned long long* counter, const Workspace& ws, hipStream_t stream,
-                             hipEvent_t walk_begin = nullptr);
+                             hipEvent_t walk_begin = nullptr, hipEvent_t walk_end = nullptr);
 
 size_t walk_lds_bytes(int mode, const LaunchCfg& cfg);
 

@@ -13,11 +13,10 @@
 //    XCD), stages them in its own LDS region (origin, direction, and the start triangle or, for
 //    binned rays, the first exit slot) and refills idle lanes from LDS as soon as `refill_min` of
 //    its 64 lanes have finished, so that divergent ray lengths do not idle the SIMD.
-//  * A single trace finishes in a second kernel: at a hit, miss or bad ray the walk stores only
+//  * A trace finishes in a second kernel: at a hit, miss or bad ray the walk stores only
 //    (primitive or a negative code, steps) into the ray's 8-byte hit_t slot and frees the lane at
-//    once; finish_rays then turns these into (primitive, t, steps) in input order, with coalesced
-//    accesses and the binary64 division out of the walk loop. A batched launch finishes its rays
-//    in the loop (FIN state).
+//    once; finish_rays (finish_batch for a batch) then turns these into (primitive, t, steps) in
+//    input order, with coalesced accesses and the binary64 division out of the walk loop.
 //  * Decisions: the sign of D(v) = dx*(vy-oy) - dy*(vx-ox), zero counting as LEFT. In binary32 mode
 //    the sign is taken from binary32 coordinates when a forward error bound proves it, otherwise
 //    from the binary64 filter, otherwise from an exact expansion; all three agree with the exact
@@ -36,6 +35,21 @@
 #include "walk.hpp"
 
 namespace ccsp {
+
+// Exact check of a ray's precondition: finite nonzero direction, finite origin strictly inside
+// internal triangle `st`.
+static __device__ __attribute__((noinline)) bool validate_ray(const SceneDev& sc, double2 o,
+                                                              double2 d, int st) {
+  const int4 tv = sc.triv[st];
+  const double2 v[3] = {sc.v64[tv.x], sc.v64[tv.y], sc.v64[tv.z]};
+  bool ok = isfinite(d.x) && isfinite(d.y) && (d.x != 0.0 || d.y != 0.0) && isfinite(o.x) &&
+            isfinite(o.y);
+  for (int i = 0; i < 3; ++i) {
+    const double2 a = v[(i + 1) % 3], b = v[(i + 2) % 3];
+    ok = ok && orient_exact(a.x, a.y, b.x, b.y, o.x, o.y) > 0;
+  }
+  return ok;
+}
 
 // ------------------------------------------------------------------------------ persistent walk
 
@@ -164,7 +178,6 @@ __device__ __forceinline__ long long claim_tile(unsigned long long* counter, int
 //   FIRST: the start triangle's first-triangle record (then three decisions, the first
 //          step of Sec. 7.2's footnote; rays of binned tiles skip it: binning decided their first triangle),
 //   WALK:  the slot of the exit edge (then one decision: the vertex across the entry edge),
-//   FIN:   (batched launches) the hit primitive's record (then the hit distance and results),
 // so lanes in different states share one memory round trip, and a refilled lane starts walking
 // in the next iteration without a separate gather phase.
 template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH>
@@ -188,11 +201,11 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   const Tile<TILE> tl(tile_mem + (size_t)wave * Tile<TILE>::kBytes);
 
   Counters c;
-  enum : int { IDLE = 0, FIRST = 1, WALK = 2, FIN = 3 };
+  enum : int { IDLE = 0, FIRST = 1, WALK = 2 };
   int state = IDLE;
   Ray32 r32{0, 0, 0, 0};                  // binary32 mode
   double ox = 0, oy = 0, dx = 0, dy = 0;  // the ray in binary64
-  int s = 0, steps = 0;                   // s: start triangle (FIRST), exit slot (WALK), prim (FIN)
+  int s = 0, steps = 0;                   // s: start triangle (FIRST) or exit slot (WALK)
   int64_t ray = 0;
   int item = 0;
   // per-lane scene in a batch, kernel argument otherwise
@@ -279,14 +292,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
           }
           if (MODE == 1 || !binned) r32 = ray32(ox, oy, dx, dy, org_x, org_y);
           if (s < 0) {  // bad ray: out-of-range start or failed validation
-            if (BATCH) {
-              const RaysDev& io = batch.items[item].rays;
-              io.prim[ray] = -3;
-              io.t[ray] = INFINITY;
-              io.steps[ray] = 0;
-            } else {
-              park_result(io_arg, ray, -3, 0);
-            }
+            park_result(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
             state = IDLE;
           }
         }
@@ -296,7 +302,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
     }
     // ---- issue: one round of loads for every busy lane, whatever its state
     const int st_now = state;
-    int4 R0 = make_int4(0, 0, 0, 0), R1 = R0, R2 = R0;
+    int4 R0 = make_int4(0, 0, 0, 0), R1 = R0;
     if (st_now == WALK) {
       if (MODE == 1) {
         R0 = *reinterpret_cast<const int4*>(slot32 + s);
@@ -309,14 +315,10 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
       const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.first : sc_arg.first) + s);
       R0 = p[0];
       R1 = p[1];
-    } else if (BATCH && st_now == FIN) {
-      const int4* p = reinterpret_cast<const int4*>(batch.items[item].scene.prim + s);
-      R0 = p[0];
-      R1 = p[1];
     }
     // every load above is issued before any result is used (and none is split per field)
     __asm__ volatile("" ::"v"(R0.x), "v"(R0.y), "v"(R0.z), "v"(R0.w), "v"(R1.x), "v"(R1.y),
-                     "v"(R1.z), "v"(R1.w), "v"(R2.x), "v"(R2.y), "v"(R2.z), "v"(R2.w));
+                     "v"(R1.z), "v"(R1.w));
     // ---- process
     if (st_now == WALK) {
       int word;
@@ -342,30 +344,11 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         int e = (word & 3) + (left ? 1 : 2);
         e = e >= 3 ? e - 3 : e;
         s = 3 * (word >> 2) + e;
-      } else if (word <= -2) {
-        // constrained edge: hit. A batch loads the primitive next iteration (FIN); a single
-        // trace leaves it to finish_rays.
-        if (BATCH) {
-          s = -word - 2;
-          state = FIN;
-        } else {
-          park_result(io_arg, ray, -word - 2, steps);
-          if (COUNT) {
-            c.steps += steps;
-            ++c.rays;
-          }
-          state = IDLE;
-        }
       } else {
-        // hull edge (miss) or the step guard
-        if (BATCH) {
-          const RaysDev& io = batch.items[item].rays;
-          io.prim[ray] = word >= 0 ? -2 : -1;
-          io.t[ray] = INFINITY;
-          io.steps[ray] = steps;
-        } else {
-          park_result(io_arg, ray, word >= 0 ? -2 : -1, steps);
-        }
+        // constrained edge (hit, primitive -word - 2), hull edge (miss) or the step guard; the
+        // finishing pass computes t
+        park_result(BATCH ? batch.items[item].rays : io_arg, ray,
+                    word <= -2 ? -word - 2 : (word >= 0 ? -2 : -1), steps);
         if (COUNT) {
           c.steps += steps;
           ++c.rays;
@@ -382,31 +365,9 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         s = e;
         state = WALK;
       } else {  // no exit edge: the origin is not inside the start triangle
-        if (BATCH) {
-          const RaysDev& io = batch.items[item].rays;
-          io.prim[ray] = -3;
-          io.t[ray] = INFINITY;
-          io.steps[ray] = 0;
-        } else {
-          park_result(io_arg, ray, -3, 0);
-        }
+        park_result(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
         state = IDLE;
       }
-    } else if (BATCH && st_now == FIN) {
-      // Results go to the caller's positions with non-temporal stores: they are never read
-      // again here, so they should not displace the scene in the L2.
-      const RaysDev& io = BATCH ? batch.items[item].rays : io_arg;
-      __builtin_nontemporal_store(s, io.prim + ray);
-      __builtin_nontemporal_store(hit_t(make_double4(lohi(R0.x, R0.y), lohi(R0.z, R0.w),
-                                                     lohi(R1.x, R1.y), lohi(R1.z, R1.w)),
-                                        ox, oy, dx, dy),
-                                  io.t + ray);
-      __builtin_nontemporal_store(steps, io.steps + ray);
-      if (COUNT) {
-        c.steps += steps;
-        ++c.rays;
-      }
-      state = IDLE;
     }
   }
   if (COUNT) {
@@ -421,12 +382,12 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
 // code, steps) into the caller's primitive id, the hit distance (the primitive's own segment,
 // binary64, Sec. 5.1's stop on scene geometry) and steps. Every access but the primitive record
 // is coalesced.
-__global__ void __launch_bounds__(256)
-finish_rays(const PrimRec* __restrict__ prim, const double2* __restrict__ o,
-            const double2* __restrict__ d, int32_t* __restrict__ hit_prim,
-            double* __restrict__ hit_t_io, int32_t* __restrict__ steps, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ void finish_one(const PrimRec* __restrict__ prim,
+                                           const double2* __restrict__ o,
+                                           const double2* __restrict__ d,
+                                           int32_t* __restrict__ hit_prim,
+                                           double* __restrict__ hit_t_io,
+                                           int32_t* __restrict__ steps, int64_t i) {
   // the ray is loaded alongside the parked result (nearly every ray hits)
   const unsigned long long v = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(hit_t_io) + i);
   typedef double vd2 __attribute__((ext_vector_type(2)));
@@ -441,6 +402,31 @@ finish_rays(const PrimRec* __restrict__ prim, const double2* __restrict__ o,
   __builtin_nontemporal_store(code, hit_prim + i);
   __builtin_nontemporal_store(t, hit_t_io + i);
   __builtin_nontemporal_store((int)(unsigned)(v >> 32), steps + i);
+}
+
+__global__ void __launch_bounds__(256)
+finish_rays(const PrimRec* __restrict__ prim, const double2* __restrict__ o,
+            const double2* __restrict__ d, int32_t* __restrict__ hit_prim,
+            double* __restrict__ hit_t_io, int32_t* __restrict__ steps, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) finish_one(prim, o, d, hit_prim, hit_t_io, steps, i);
+}
+
+// The same for a batch: block b finishes tile b of the batch's tile sequence (the walk's tiling,
+// blockDim.x rays per tile).
+__global__ void __launch_bounds__(256)
+finish_batch(const BatchItem* __restrict__ items, int n_items) {
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = n_items - 1;  // the last item whose first tile is at or before this one
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile_begin <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchItem& it = items[lo];
+  const int64_t i = (tile - it.tile_begin) * blockDim.x + threadIdx.x;
+  if (i < it.rays.n)
+    finish_one(it.scene.prim, it.rays.o, it.rays.d, it.rays.prim, it.rays.t, it.rays.steps, i);
 }
 
 __global__ void reset_counters(unsigned long long* counter) {
@@ -509,10 +495,11 @@ hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool cou
 hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t total_tiles,
                              int mode, bool count, const LaunchCfg& cfg,
                              unsigned long long* counter, const Workspace& ws, hipStream_t stream,
-                             hipEvent_t walk_begin) {
+                             hipEvent_t walk_begin, hipEvent_t walk_end) {
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counter);
+  hipError_t e;
   if (walk_begin) {
-    const hipError_t e = hipEventRecord(walk_begin, stream);
+    e = hipEventRecord(walk_begin, stream);
     if (e != hipSuccess) return e;
   }
   const int n_lds = n_items < 1024 ? n_items : 1024;
@@ -520,11 +507,19 @@ hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t to
   const ItemRef br{items_dev, n_items, nullptr, n_lds};
   const SceneDev nosc{};
   const RaysDev noio{};
-  if (mode == 0 && !count) return pick_tile<0, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
-  if (mode == 0 && count) return pick_tile<0, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
-  if (mode == 1 && !count) return pick_tile<1, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
-  if (mode == 1 && count) return pick_tile<1, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
-  return hipErrorInvalidValue;
+  e = hipErrorInvalidValue;
+  if (mode == 0 && !count) e = pick_tile<0, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
+  if (mode == 0 && count) e = pick_tile<0, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
+  if (mode == 1 && !count) e = pick_tile<1, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
+  if (mode == 1 && count) e = pick_tile<1, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
+  if (e != hipSuccess) return e;
+  if (walk_end) {
+    e = hipEventRecord(walk_end, stream);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(finish_batch, dim3((unsigned)total_tiles), dim3(cfg.tile), 0, stream,
+                     items_dev, n_items);
+  return hipGetLastError();
 }
 
 }  // namespace ccsp

@@ -333,6 +333,19 @@ def make_scene(name: str, seed: int = 0, n_seg: int | None = None, index: int = 
     return triangulate(sc)
 
 
+def multi_workload(name: str, seed: int = 0, count: int | None = None,
+                   max_seg: int | None = None, max_rays: int | None = None):
+    """Yield (index, Scene, Rays) for the scenes of a multi-scene workload, in order. Scene i uses
+    the segment stream of index i and the ray stream subseed(seed, TAG_RAYS, i + 1); max_seg and
+    max_rays cap the drawn sizes (for small tests)."""
+    segs, nrays = multi_sizes(name, seed)
+    for i in range(len(segs) if count is None else count):
+        ns = int(segs[i] if max_seg is None else min(segs[i], max_seg))
+        nr = int(nrays[i] if max_rays is None else min(nrays[i], max_rays))
+        sc = make_scene(name, seed, n_seg=ns, index=i)
+        yield i, sc, sample_rays(sc, nr, seed=subseed(seed, TAG_RAYS, i + 1))
+
+
 def multi_sizes(name: str, seed: int = 0) -> tuple:
     """Segment and ray counts of the scenes of a multi-scene workload (log-uniform draws)."""
     w = WORKLOADS[name]

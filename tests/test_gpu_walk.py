@@ -320,3 +320,64 @@ def test_concurrent_streams(ccsp, tiny_scene, tiny_rays):
         torch.cuda.synchronize()
         _assert_same(_host(a), ref, "stream 1")
         _assert_same(_host(b), ref, "stream 2")
+
+
+def test_autotune_single_batch_and_cache(ccsp, tiny_scene, tiny_rays, tmp_path):
+    ref = oracle.walk(oracle.Triangulation.of(tiny_scene), tiny_rays.o, tiny_rays.d, tiny_rays.start)
+    cache = str(tmp_path / "tune.json")
+    with ccsp.Scene.from_arrays(tiny_scene) as scene:
+        o, d, st = _dev(tiny_rays)
+        best, ms = ccsp.autotune([(scene, o, d, st)], reps=1, cache_path=cache)
+        assert ms is not None and ms > 0
+        assert best.wg_size in (64, 128, 256, 512) and best.tile_rays in (64, 128, 256)
+        assert 8 <= best.waves_per_cu <= 28 and best.xcd_chunks in (1, 8)
+        # tune=None now uses the tuned parameters; the results do not depend on them
+        _assert_same(_host(ccsp.trace(scene, o, d, st)), ref, "after autotune")
+        # the JSON file is found again without measuring
+        again, ms2 = ccsp.autotune([(scene, o, d, st)], cache_path=cache)
+        assert ms2 is None and again.as_tuple() == best.as_tuple()
+        parts = [tiny_rays.slice(0, 1000), tiny_rays.slice(1000, 5000), tiny_rays.slice(5000, 5001),
+                 tiny_rays.slice(5001, 5001)]
+        jobs = [(scene, *_dev(p)) for p in parts]
+        bb, bms = ccsp.autotune(jobs, graph=True, reps=1)
+        assert bms > 0
+        for rep in range(3):
+            res = ccsp.trace_batch(jobs, graph=True)
+            for p, rs, a in zip(parts, res, (0, 1000, 5000, 5001)):
+                _assert_same(_host(rs), tuple(x[a:a + p.n] for x in ref), f"tuned graph {rep}")
+
+
+def test_concurrent_batches_and_graph_replays_on_two_streams(ccsp, grid_pair):
+    """Batches in flight on two streams use separate item tables; replays of one graph on
+    alternating streams are ordered."""
+    sc, _, rays, _ = grid_pair
+    parts = [rays.slice(k * 40_000, (k + 1) * 40_000 + 17 * k) for k in range(6)]
+    with ccsp.Scene.from_arrays(sc) as scene:
+        devp = [_dev(p) for p in parts]
+        refs = [_host(ccsp.trace(scene, *x, input_order=True)) for x in devp]
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        torch.cuda.synchronize()
+        for graph in (False, True):
+            outs = []
+            for rep in range(4):
+                # the two streams alternate between two different item lists
+                jobs = [(scene, *devp[k]) for k in ((0, 1, 2) if rep % 2 == 0 else (3, 4, 5))]
+                s = s1 if rep % 2 == 0 else s2
+                with torch.cuda.stream(s):
+                    outs.append((rep, ccsp.trace_batch(jobs, stream=s, graph=graph)))
+            torch.cuda.synchronize()
+            for rep, res in outs:
+                ks = (0, 1, 2) if rep % 2 == 0 else (3, 4, 5)
+                for k, rs in zip(ks, res):
+                    _assert_same(_host(rs), refs[k], f"graph={graph} rep {rep} item {k}")
+        # one graph replayed on alternating streams
+        jobs = [(scene, *devp[k]) for k in (0, 1, 2)]
+        outs = []
+        for rep in range(4):
+            s = s1 if rep % 2 == 0 else s2
+            with torch.cuda.stream(s):
+                outs.append(ccsp.trace_batch(jobs, stream=s, graph=True))
+        torch.cuda.synchronize()
+        for rep, res in enumerate(outs):
+            for k, rs in zip((0, 1, 2), res):
+                _assert_same(_host(rs), refs[k], f"same graph rep {rep} item {k}")
