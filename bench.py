@@ -52,8 +52,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "grid", "tiny", "batch"],
-                    help="batch: the 256-scene workload in one graph-replayed, autotuned launch")
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "grid", "tiny", "batch", "serve"],
+                    help="batch: the 256-scene workload in one graph-replayed, autotuned launch; "
+                         "serve: the request server under Poisson arrivals")
+    ap.add_argument("--requests", type=int, default=10_000, help="serve: requests per level")
+    ap.add_argument("--slots", type=int, default=4, help="serve: launch slots")
     ap.add_argument("--tune-cache", default="", help="JSON file keeping autotuned parameters")
     ap.add_argument("--rays", type=int, default=0, help="override the ray count")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the checker leg")
@@ -87,6 +91,9 @@ def main():
 
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload == "serve":
+        serve_bench(args)
         return
     dev = torch.device("cuda:0")
     t0 = time.time()
@@ -304,6 +311,126 @@ def batch_bench(args):
         "default_params_ms_per_step": wall_default / max(1, args.steps // 2) * 1e3,
         "one_trace_per_item_ms": ms_items,
         "batch_equals_single_traces": same,
+    }
+    print(json.dumps(line), flush=True)
+    for s in scenes:
+        s.free()
+
+
+def serve_bench(args):
+    """64 resident scenes; requests of log-U[256, 262144] rays, each naming a uniformly chosen
+    scene, go through the library's request server (admission by device memory, coalescing across
+    scenes, overlapping launch slots). Capacity: every request submitted at once. Then the same
+    requests arrive as a Poisson process at 30/50/70/90% of the capacity's request rate; latency
+    runs from a request's scheduled arrival to the completion the server reports."""
+    import numpy as np
+    import torch
+
+    import paper_2112_05570_amd as ccsp
+    import scenegen as sg
+
+    dev = torch.device("cuda:0")
+    pool_rays = 262_144
+    t0 = time.time()
+    segs, _ = sg.multi_sizes("serve", seed=0)
+    scenes, host = [], []
+    for i in range(len(segs)):
+        sc = sg.make_scene("serve", seed=0, n_seg=int(segs[i]), index=i)
+        r = sg.sample_rays(sc, pool_rays, seed=sg.subseed(0, sg.TAG_RAYS, i + 1))
+        scenes.append(ccsp.Scene.from_arrays(sc))
+        host.append((torch.from_numpy(r.o).pin_memory(), torch.from_numpy(r.d).pin_memory(),
+                     torch.from_numpy(r.start).pin_memory()))
+    tris = sum(s.n_triangles for s in scenes)
+    rng = np.random.default_rng(np.random.SeedSequence([0, 5]))
+    N = args.requests
+    req_scene = rng.integers(0, len(scenes), N)
+    req_n = sg.log_uniform_int(rng.random(N), 256, pool_rays)
+    req_off = (rng.random(N) * (pool_rays - req_n + 1)).astype(np.int64)
+    gaps = rng.exponential(1.0, N)
+    total_rays = int(req_n.sum())
+    log(f"[bench] serve: {len(scenes)} scenes, {tris} triangles; {N} requests, {total_rays} rays; "
+        f"built in {time.time() - t0:.1f}s")
+
+    ring = 512  # pinned result buffers, reused as requests complete
+    bufs = [ccsp.Result(torch.empty(pool_rays, dtype=torch.int32).pin_memory(),
+                        torch.empty(pool_rays, dtype=torch.float64).pin_memory(),
+                        torch.empty(pool_rays, dtype=torch.int32).pin_memory()) for _ in range(ring)]
+    sample = set(range(0, N, 97))
+
+    def run(rate):
+        """rate None: all at once. Returns (latencies s, seconds, stats, stashed sample results)."""
+        stash = {}
+        with ccsp.Server("fp32", slots=args.slots, memory_bytes=2 << 30) as srv:
+            start = time.monotonic() + 0.02
+            arrive = np.full(N, start) if rate is None else start + np.cumsum(gaps) / rate
+            free, inflight, lat = list(range(ring)), {}, np.zeros(N)
+            i = done = 0
+            t_end = start
+            while done < N:
+                now = time.monotonic()
+                while i < N and arrive[i] <= now and free:
+                    b, s, o, n = free.pop(), req_scene[i], req_off[i], req_n[i]
+                    out = ccsp.Result(bufs[b].hit_prim[:n], bufs[b].hit_t[:n], bufs[b].steps[:n])
+                    rid = srv.submit(scenes[s], host[s][0][o:o + n], host[s][1][o:o + n],
+                                     host[s][2][o:o + n], out)
+                    inflight[rid] = (i, b)
+                    i += 1
+                wait = 0.0 if (i < N and free and arrive[i] <= now) else 2e-4
+                for rid, status, _, t_done in srv.poll(timeout_s=wait):
+                    assert status == 0, f"request {rid} failed with {status}"
+                    k, b = inflight.pop(rid)
+                    lat[k] = t_done - arrive[k]
+                    t_end = max(t_end, t_done)
+                    if k in sample:
+                        n = req_n[k]
+                        stash[k] = (bufs[b].hit_prim[:n].clone(), bufs[b].hit_t[:n].clone(),
+                                    bufs[b].steps[:n].clone())
+                    free.append(b)
+                    done += 1
+            st = srv.stats()
+        return lat, t_end - start, st, stash
+
+    cap_lat, cap_s, cap_st, stash = run(None)
+    cap_rays_s = total_rays / cap_s
+    cap_req_s = N / cap_s
+    log(f"[bench] serve capacity: {cap_rays_s / 1e9:.3f} G rays/s, {cap_req_s:.0f} requests/s")
+    # the mix against the same rays traced alone (device-resident, default launch)
+    same = True
+    for k, (p, tt, s) in stash.items():
+        sc_i, o, n = req_scene[k], req_off[k], req_n[k]
+        r = ccsp.trace(scenes[sc_i], *(x[o:o + n].to(dev) for x in host[sc_i]))
+        torch.cuda.synchronize()
+        same &= bool(torch.equal(r.hit_prim.cpu(), p) and torch.equal(r.hit_t.cpu(), tt)
+                     and torch.equal(r.steps.cpu(), s))
+    levels = []
+    for load in (0.3, 0.5, 0.7, 0.9):
+        lat, secs, st, _ = run(load * cap_req_s)
+        levels.append({"load": load, "offered_requests_per_s": load * cap_req_s,
+                       "rays_per_s": total_rays / secs,
+                       "p50_ms": float(np.percentile(lat, 50)) * 1e3,
+                       "p99_ms": float(np.percentile(lat, 99)) * 1e3,
+                       "launches": st["launches"],
+                       "requests_per_launch": st["requests"] / max(1, st["launches"]),
+                       "max_slots_busy": st["max_slots_busy"]})
+        log(f"[bench] load {load}: p50 {levels[-1]['p50_ms']:.2f} ms, "
+            f"p99 {levels[-1]['p99_ms']:.2f} ms")
+    line = {
+        "metric": "rays/s and p50/p99 request latency, 64 resident scenes, Poisson arrivals "
+                  "(request server, FP32+filter)",
+        "value": cap_rays_s, "unit": "rays/s", "n_gpus": 1, "steps": N, "warmup": 0,
+        "ms_per_step": cap_s / N * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serve: {len(scenes)} resident scenes, segments log-U[1e3, 5e5]; "
+                               f"{N} requests of log-U[256, 262144] rays, uniform scene, seed 0",
+                   "triangles": tris, "rays": total_rays, "slots": args.slots,
+                   "pool_bytes": 2 << 30, "host_buffers": "pinned"},
+        "capacity": {"rays_per_s": cap_rays_s, "requests_per_s": cap_req_s,
+                     "p50_ms": float(np.percentile(cap_lat, 50)) * 1e3,
+                     "p99_ms": float(np.percentile(cap_lat, 99)) * 1e3,
+                     "launches": cap_st["launches"],
+                     "requests_per_launch": cap_st["requests"] / max(1, cap_st["launches"])},
+        "levels": levels,
+        "mix_equals_alone_sampled": same, "sampled_requests": len(stash),
     }
     print(json.dumps(line), flush=True)
     for s in scenes:

@@ -241,6 +241,58 @@ int triangulation_info(const Triangulation *tri, int64_t out[4]);
 int gather_roofline(int64_t working_set_bytes, int32_t waves_per_cu, int64_t steps_per_lane,
                     double *out_loads_per_s, void *stream);
 
+/* ------------------------------------------------------------------------------ request server
+ *
+ * Continuous batching of walk requests over resident triangulations, for callers that receive
+ * rays on the host. Each request names a triangulation and brings host arrays (pinned memory,
+ * e.g. from hipHostMalloc, lets its copies overlap other work; pageable memory works but
+ * serialises the server). A worker thread admits pending requests in arrival order while a
+ * launch slot is free and their device memory fits the server's pool, coalesces the admitted
+ * requests (of any triangulations) into one trace_batch launch on the slot's stream between
+ * their copies in and out, and reports each request once its results are in its host arrays.
+ * Requests that arrive while launches are in flight are admitted as slots and memory free up,
+ * so up to `slots` launches overlap on the device. Results are those of trace_rays on the same
+ * rays (without binning, which does not change them). Errors go to last_error().
+ */
+typedef struct Server Server;
+
+typedef struct {
+  int32_t slots;         /* launches in flight at once, each on its own stream: 1..16 (0: 4) */
+  int32_t max_items;     /* requests coalesced into one launch: 1..4096 (0: 256) */
+  int64_t max_rays;      /* rays per launch; a single larger request still runs (0: 2^22) */
+  int64_t memory_bytes;  /* device memory for admitted requests, >= 1 MiB (0: 1 GiB); a request
+                            of n rays takes about 52 n bytes */
+  int32_t precision;     /* a precision mode, without flags */
+  int32_t reserved;
+} ServerConfig;
+
+/* server_create: allocate the pool and the slot streams on the current device and start the
+ * worker thread. cfg may be NULL (defaults, binary64 mode). */
+int server_create(const ServerConfig *cfg, Server **out);
+
+/* server_submit: queue a request of n rays through `scene` (which must stay loaded until the
+ * request completes). o_xy, d_xy, start_tri and the result arrays are HOST pointers that must
+ * stay valid until server_poll reports the request. *id receives its id (ids increase from 1).
+ * A request that could never fit the pool is rejected with CCSP_E_ARG. Thread-safe. */
+int server_submit(Server *s, const Triangulation *scene, const double *o_xy, const double *d_xy,
+                  const int32_t *start_tri, int64_t n, int32_t *hit_prim, double *hit_t,
+                  int32_t *steps, uint64_t *id);
+
+/* server_poll: take up to max completed requests, in completion order, waiting up to timeout_s
+ * seconds for the first one: ids, status (CCSP_OK or an error code), and the submission and
+ * completion times in seconds of CLOCK_MONOTONIC. *n_out receives the number taken. */
+int server_poll(Server *s, int32_t max, uint64_t *ids, int32_t *status, double *t_submit,
+                double *t_done, int32_t *n_out, double timeout_s);
+
+/* server_stats: out[0] launches, out[1] requests admitted, out[2] rays admitted, out[3] most
+ * requests in one launch, out[4] peak pool bytes in use, out[5] admission attempts stopped by a
+ * full pool, out[6] most slots busy at once, out[7] requests pending now. */
+int server_stats(Server *s, int64_t out[8]);
+
+/* server_destroy: finish every queued and in-flight request, stop the worker, free the server
+ * (completed requests not yet polled are dropped). NULL is a no-op. */
+void server_destroy(Server *s);
+
 #ifdef __cplusplus
 }
 #endif

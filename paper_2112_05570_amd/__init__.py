@@ -174,3 +174,60 @@ def autotune(jobs, precision="fp32", graph=False, input_order=False, reps=3, str
 def read_counters(reset=False):
     """(steps, binary32 deferrals, binary64 deferrals, rays) since the last reset."""
     return B.read_counters(reset)
+
+
+class Server:
+    """Continuous-batching request server over resident scenes (see ``server_create`` in the C
+    header). Requests bring host tensors (pinned memory lets their copies overlap); results are
+    written into host tensors, which must stay alive until the request is reported done."""
+
+    def __init__(self, precision="fp32", slots=4, max_items=256, max_rays=1 << 22,
+                 memory_bytes=1 << 30):
+        cfg = B.ServerConfig(slots, max_items, max_rays, memory_bytes, _mode(precision), 0)
+        self.handle = None
+        self.handle = B.server_create(cfg)
+        self._live = {}
+
+    def submit(self, scene: Scene, o, d, start, out: Result) -> int:
+        """o, d: (n,2) float64, start: (n,) int32 CPU tensors; out: CPU Result of n rays."""
+        n = start.shape[0]
+        for name, x in (("o", o), ("d", d), ("start", start), ("hit_prim", out.hit_prim),
+                        ("hit_t", out.hit_t), ("steps", out.steps)):
+            if x.is_cuda or not x.is_contiguous() or x.shape[0] != n:
+                raise ValueError(f"{name} must be a contiguous CPU tensor of {n} rows")
+        rid = B.server_submit(self.handle, scene.handle, o.data_ptr(), d.data_ptr(),
+                              start.data_ptr(), n, out.hit_prim.data_ptr(), out.hit_t.data_ptr(),
+                              out.steps.data_ptr())
+        self._live[rid] = (o, d, start, out)  # keep the host buffers alive while in flight
+        return rid
+
+    def poll(self, max_n=4096, timeout_s=0.0):
+        """[(id, status, t_submit, t_done)] of completed requests (CLOCK_MONOTONIC seconds, the
+        clock of time.monotonic())."""
+        done = B.server_poll(self.handle, max_n, timeout_s)
+        for rid, *_ in done:
+            self._live.pop(rid, None)
+        return done
+
+    def stats(self) -> dict:
+        keys = ("launches", "requests", "rays", "max_items_per_launch", "peak_pool_bytes",
+                "admissions_stopped_by_memory", "max_slots_busy", "pending")
+        return dict(zip(keys, B.server_stats(self.handle)))
+
+    def close(self):
+        if self.handle:
+            B.server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

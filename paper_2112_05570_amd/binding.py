@@ -44,7 +44,8 @@ CCSP_TRACE_GRAPH = 1 << 12
 EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch",
            "free_triangulation", "last_error", "read_counters", "triangulation_info",
            "reserve_workspace", "gather_roofline", "read_stage_times", "autotune",
-           "tune_cache_set", "tune_cache_get")
+           "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
+           "server_stats", "server_destroy")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -105,6 +106,27 @@ _lib.tune_cache_set.argtypes = [ctypes.c_int32, _I64, _I64, _I, ctypes.POINTER(T
 _lib.tune_cache_set.restype = _I
 _lib.tune_cache_get.argtypes = [ctypes.c_int32, _I64, _I64, _I, ctypes.POINTER(TuneParams)]
 _lib.tune_cache_get.restype = _I
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_items", ctypes.c_int32),
+                ("max_rays", ctypes.c_int64), ("memory_bytes", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib.server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]
+_lib.server_create.restype = _I
+_lib.server_submit.argtypes = [_P, _P, _P, _P, _P, _I64, _P, _P, _P, ctypes.POINTER(ctypes.c_uint64)]
+_lib.server_submit.restype = _I
+_lib.server_poll.argtypes = [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
+                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.c_double]
+_lib.server_poll.restype = _I
+_lib.server_stats.argtypes = [_P, ctypes.POINTER(ctypes.c_int64 * 8)]
+_lib.server_stats.restype = _I
+_lib.server_destroy.argtypes = [_P]
+_lib.server_destroy.restype = None
 
 
 class CcspError(RuntimeError):
@@ -192,6 +214,41 @@ def tune_cache_get(n_items: int, total_rays: int, total_triangles: int, precisio
     if rc < 0:
         _check(rc)
     return out if rc == 1 else None
+
+
+def server_create(cfg: ServerConfig | None) -> int:
+    h = _P()
+    _check(_lib.server_create(ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(h)))
+    return h.value
+
+
+def server_submit(server: int, scene: int, o_xy: int, d_xy: int, start_tri: int, n: int,
+                  hit_prim: int, hit_t: int, steps: int) -> int:
+    rid = ctypes.c_uint64()
+    _check(_lib.server_submit(_P(server), _P(scene), _P(o_xy), _P(d_xy), _P(start_tri), n,
+                              _P(hit_prim), _P(hit_t), _P(steps), ctypes.byref(rid)))
+    return rid.value
+
+
+def server_poll(server: int, max_n: int = 1024, timeout_s: float = 0.0) -> list:
+    """[(id, status, t_submit, t_done)] of completed requests."""
+    ids = (ctypes.c_uint64 * max(1, max_n))()
+    st = (ctypes.c_int32 * max(1, max_n))()
+    ts = (ctypes.c_double * max(1, max_n))()
+    td = (ctypes.c_double * max(1, max_n))()
+    n = ctypes.c_int32()
+    _check(_lib.server_poll(_P(server), max_n, ids, st, ts, td, ctypes.byref(n), timeout_s))
+    return [(ids[k], st[k], ts[k], td[k]) for k in range(n.value)]
+
+
+def server_stats(server: int) -> list:
+    out = (ctypes.c_int64 * 8)()
+    _check(_lib.server_stats(_P(server), ctypes.byref(out)))
+    return list(out)
+
+
+def server_destroy(server: int) -> None:
+    _lib.server_destroy(_P(server))
 
 
 def triangulation_info(tri: int) -> list:

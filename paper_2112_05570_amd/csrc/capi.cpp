@@ -49,6 +49,14 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+namespace ccsp {
+void set_last_error(const char* msg) { g_err = msg; }
+}  // namespace ccsp
+
+namespace {
+
 int hip_fail(hipError_t e, const char* what) {
   return fail(CCSP_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }

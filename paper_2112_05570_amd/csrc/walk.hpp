@@ -128,4 +128,7 @@ hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t to
 
 size_t walk_lds_bytes(int mode, const LaunchCfg& cfg);
 
+// The message last_error() returns on the calling thread.
+void set_last_error(const char* msg);
+
 }  // namespace ccsp

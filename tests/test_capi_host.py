@@ -128,3 +128,21 @@ def test_read_stage_times_argument_errors():
     assert n.value == 0
     assert B.raw_call("read_stage_times", 4, None, None, None, ctypes.byref(n)) == B.CCSP_E_ARG
     assert "null" in B.last_error()
+
+
+def test_server_argument_errors():
+    out = ctypes.c_void_p()
+    bad = [B.ServerConfig(17, 0, 0, 0, 1, 0), B.ServerConfig(0, 5000, 0, 0, 1, 0),
+           B.ServerConfig(0, 0, 0, 1000, 1, 0), B.ServerConfig(0, 0, 0, 0, 7, 0),
+           B.ServerConfig(0, 0, 0, 0, 1 | (1 << 9), 0), B.ServerConfig(0, 0, -1, 0, 1, 0)]
+    for cfg in bad:  # rejected before any device call
+        assert B.raw_call("server_create", ctypes.byref(cfg), ctypes.byref(out)) == B.CCSP_E_ARG
+    assert B.raw_call("server_create", None, None) == B.CCSP_E_ARG
+    rid = ctypes.c_uint64()
+    z = ctypes.c_void_p(0)
+    assert B.raw_call("server_submit", z, z, z, z, z, ctypes.c_int64(1), z, z, z,
+                      ctypes.byref(rid)) == B.CCSP_E_ARG
+    n = ctypes.c_int32()
+    assert B.raw_call("server_poll", z, 0, None, None, None, None, ctypes.byref(n),
+                      ctypes.c_double(0)) == B.CCSP_E_ARG
+    B.raw_call("server_destroy", z)  # no-op

@@ -381,3 +381,75 @@ def test_concurrent_batches_and_graph_replays_on_two_streams(ccsp, grid_pair):
         for rep, res in enumerate(outs):
             for k, rs in zip((0, 1, 2), res):
                 _assert_same(_host(rs), refs[k], f"same graph rep {rep} item {k}")
+
+
+def _pinned(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).pin_memory()
+
+
+def test_server_alone_vs_mix(ccsp, tiny_scene, tiny_rays, grid_pair):
+    """Requests of uneven sizes over three scenes, submitted while others run, through a small
+    pool (admission waits for memory) and few slots: every result equals the same rays traced
+    alone, bit for bit; launches coalesce requests and overlap."""
+    sc_grid, sc_ann, grid_rays, start_ann = grid_pair
+    scenes = [ccsp.Scene.from_arrays(tiny_scene), ccsp.Scene.from_arrays(sc_grid),
+              ccsp.Scene.from_arrays(sc_ann)]
+    m = 300_000
+    pools = [tiny_rays, grid_rays.slice(0, m),
+             sg.Rays(grid_rays.o[:m], grid_rays.d[:m], start_ann[:m])]
+    host = [(_pinned(r.o, torch.float64), _pinned(r.d, torch.float64),
+             _pinned(r.start, torch.int32)) for r in pools]
+    rng = np.random.default_rng(5)
+    reqs = []
+    for k in range(60):
+        s = int(rng.integers(0, 3))
+        n = int(np.exp(rng.uniform(np.log(1), np.log(60_000))))
+        if k % 17 == 0:
+            n = 0
+        off = int(rng.integers(0, pools[s].n - n + 1))
+        reqs.append((s, off, n))
+    try:
+        with ccsp.Server(precision="fp32", slots=3, max_items=8, memory_bytes=8 << 20) as srv:
+            outs, ids, done = [], {}, []
+            for k, (s, off, n) in enumerate(reqs):
+                o, d, st = (x[off:off + n] for x in host[s])
+                out = ccsp.Result(torch.empty(n, dtype=torch.int32).pin_memory(),
+                                  torch.empty(n, dtype=torch.float64).pin_memory(),
+                                  torch.empty(n, dtype=torch.int32).pin_memory())
+                outs.append(out)
+                ids[srv.submit(scenes[s], o, d, st, out)] = k
+                if k % 10 == 9:
+                    done += srv.poll()
+            deadline = 60.0
+            while len(done) < len(reqs):
+                got = srv.poll(timeout_s=1.0)
+                done += got
+                deadline -= 1.0 if not got else 0.0
+                assert deadline > 0, "server did not finish"
+            st = srv.stats()
+        assert sorted(ids[i] for i, *_ in done) == list(range(len(reqs)))
+        assert all(status == 0 for _, status, *_ in done)
+        assert all(t1 >= t0 for _, _, t0, t1 in done)
+        assert st["launches"] < st["requests"] and st["max_items_per_launch"] > 1
+        assert st["max_slots_busy"] >= 2 and st["admissions_stopped_by_memory"] > 0
+        assert st["peak_pool_bytes"] <= 8 << 20
+        for k, (s, off, n) in enumerate(reqs):
+            o, d, stt = (x[off:off + n].to(DEV) for x in host[s])
+            alone = _host(ccsp.trace(scenes[s], o, d, stt, input_order=True))
+            got = (outs[k].hit_prim.numpy(), outs[k].hit_t.numpy(), outs[k].steps.numpy())
+            _assert_same(got, alone, f"request {k} (scene {s}, {n} rays)")
+    finally:
+        for s in scenes:
+            s.free()
+
+
+def test_server_rejects_oversized_request(ccsp, tiny_scene, tiny_rays):
+    with ccsp.Scene.from_arrays(tiny_scene) as scene, \
+            ccsp.Server(memory_bytes=1 << 20) as srv:
+        n = 60_000  # needs about 3 MB
+        o = torch.zeros((n, 2), dtype=torch.float64)
+        st = torch.zeros(n, dtype=torch.int32)
+        out = ccsp.Result(torch.empty(n, dtype=torch.int32), torch.empty(n, dtype=torch.float64),
+                          torch.empty(n, dtype=torch.int32))
+        with pytest.raises(ccsp.CcspError, match="more than the server"):
+            srv.submit(scene, o, o, st, out)
