@@ -154,6 +154,8 @@ def main():
 
     # diagnostics outside the timed region
     steps_total = int(out32.steps.sum(dtype=torch.int64).item())
+    steps_p99 = float(torch.quantile(out32.steps[: 1 << 24].double(), 0.99).item())
+    t32_err = pure_binary32_t_error(sc, o, d, out32, torch)
     same = bool(torch.equal(out32.hit_prim, out64.hit_prim) and torch.equal(out32.steps, out64.steps)
                 and torch.equal(out32.hit_t, out64.hit_t))
     ccsp.read_counters(reset=True)
@@ -205,6 +207,8 @@ def main():
         },
         "steps_per_s": steps_total * args.steps / wall32,
         "mean_steps_per_ray": steps_total / n,
+        "p99_steps_per_ray": steps_p99,
+        "pure_binary32_t_rel_error": t32_err,
         "ms_per_step_median": float(np.median(tr32)) * 1e3,
         "stages_ms": {"binning": float(np.mean(bin32)) * 1e3, "walk": walk_avg * 1e3,
                       "walk_median": float(np.median(walk32)) * 1e3,
@@ -461,6 +465,35 @@ def gather_sweep():
             print(json.dumps({"buffer_bytes": ws, "waves_per_cu": wpc, "loads_per_s": r}), flush=True)
 
 
+def pure_binary32_t_error(sc, o, d, res, torch, sample=1 << 20):
+    """Diagnostic only: relative error of the hit distance evaluated entirely in binary32 (ray and
+    primitive segment rounded to binary32, the same formula) against the binary64 t the walk
+    returns, on the first `sample` hits. The walk itself always finishes t in binary64."""
+    import numpy as np
+    prims = torch.from_numpy(sc.prims).to(o.device)
+    p = res.hit_prim[:sample].long()
+    hit = p >= 0
+    seg = prims[p[hit]].float()
+    oo, dd, t64 = o[:sample][hit].float(), d[:sample][hit].float(), res.hit_t[:sample][hit]
+    ax, ay, bx, by = seg[:, 0], seg[:, 1], seg[:, 2], seg[:, 3]
+    ex, ey = bx - ax, by - ay
+    t32 = ((ax - oo[:, 0]) * ey - (ay - oo[:, 1]) * ex) / (dd[:, 0] * ey - dd[:, 1] * ex)
+    rel = ((t32.double() - t64).abs() / t64.abs()).cpu().numpy()
+    return {"p50": float(np.percentile(rel, 50)), "p99": float(np.percentile(rel, 99)),
+            "max": float(rel.max()), "sample": int(rel.size)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_leg(sc, rays, budget_s):
     """The checker's walk, as it stands, on the host cores: a bounded prefix of the same rays."""
     import numpy as np
@@ -485,7 +518,8 @@ def cpu_leg(sc, rays, budget_s):
     return {"value": m / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"first {m} of the same rays (exact integer-arithmetic checker walk, "
                       f"OpenMP over rays)",
-            "steps_per_s": float(np.sum(s, dtype=np.int64)) / dt}
+            "steps_per_s": float(np.sum(s, dtype=np.int64)) / dt,
+            "rays_per_s_per_core": m / dt / threads, "cpu": cpu_model()}
 
 
 if __name__ == "__main__":
