@@ -30,9 +30,10 @@ BYTES_PER_RAY = 60
 
 # HBM traffic of one binary32 walk launch on the large workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE passes (profiles/walk_fp32_large_pmc.md), each scaled by what the same counter reports
-# for a plain copy of known size. Valid only for the kernel sources it was taken on.
-WALK_SOURCES = ("walk_kernels.hip", "walk.hpp", "exact.hpp")
-MEASURED_TRAFFIC = {"sources_sha256": "", "bytes_per_launch": None}
+# for a plain copy of known size. Valid only for the kernel sources and launch parameters it was
+# taken with.
+WALK_SOURCES = ("walk_kernels.hip", "walk.hpp", "decide.hpp", "exact.hpp")
+MEASURED_TRAFFIC = {"sources_sha256": "", "tune": [], "bytes_per_launch": None}
 
 
 def walk_sources_sha256():
@@ -41,6 +42,9 @@ def walk_sources_sha256():
         with open(os.path.join(ROOT, "paper_2112_05570_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+TUNE_TABLE = os.path.join(ROOT, "paper_2112_05570_amd", "tuned", "mi355x.json")
 
 
 def log(*a):
@@ -58,7 +62,9 @@ def main():
                          "serve: the request server under Poisson arrivals")
     ap.add_argument("--requests", type=int, default=10_000, help="serve: requests per level")
     ap.add_argument("--slots", type=int, default=4, help="serve: launch slots")
-    ap.add_argument("--tune-cache", default="", help="JSON file keeping autotuned parameters")
+    ap.add_argument("--tune-cache", default=TUNE_TABLE,
+                    help="JSON file of autotuned launch parameters (the library's table for this "
+                         "GPU by default); workloads missing from it are tuned by measurement")
     ap.add_argument("--rays", type=int, default=0, help="override the ray count")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the checker leg")
     ap.add_argument("--no-cpu", action="store_true")
@@ -115,6 +121,15 @@ def main():
     out64 = ccsp.Result(torch.empty_like(out32.hit_prim), torch.empty_like(out32.hit_t),
                         torch.empty_like(out32.steps))
     stream = torch.cuda.current_stream()
+    tuned = {}
+    if tune is None:
+        # launch parameters from the library's autotuner (kept in its cache; tune=None below)
+        for prec, out in (("fp32", out32), ("fp64", out64)):
+            t_tune = time.perf_counter()
+            best, _ = ccsp.autotune([(scene, o, d, st, out)], prec, reps=2,
+                                    cache_path=args.tune_cache)
+            tuned[prec] = best.as_tuple()
+            log(f"[bench] autotune {prec}: {tuned[prec]} in {time.perf_counter() - t_tune:.1f}s")
 
     def timed(prec, out, k, w):
         for _ in range(w):
@@ -171,7 +186,7 @@ def main():
     achieved = alg_bytes / walk_avg / 1e9
     traffic = None
     if MEASURED_TRAFFIC["sources_sha256"] == walk_sources_sha256() and args.workload == "large" \
-            and not args.rays and not args.tune:
+            and not args.rays and list(tuned.get("fp32", ())) == MEASURED_TRAFFIC["tune"]:
         traffic = MEASURED_TRAFFIC["bytes_per_launch"]
 
     # dependent-gather roofline: 16-byte pointer chases over the walk's binary32 slot array size
@@ -219,6 +234,9 @@ def main():
                                "walk": float(np.mean(walk64)) * 1e3,
                                "finish": float(np.mean(fin64)) * 1e3}},
         "fp32_input_order_ms_per_step": ms_io,
+        "tuned": {k: dict(zip(["wg_size", "tile_rays", "waves_per_cu", "refill_min",
+                               "tiles_per_claim", "xcd_chunks", "bin"], v))
+                  for k, v in tuned.items()},
         "fp32_equals_fp64": same,
         "fallback": {"fp32_to_fp64_per_step": c_fb32 / max(1, c_steps),
                      "fp64_to_exact_per_step": c_fb64 / max(1, c_steps)},
@@ -287,7 +305,7 @@ def batch_bench(args):
     wall_default, _ = timed(max(1, args.steps // 2), ccsp.TuneParams())
     t = time.perf_counter()
     best, tuned_ms = ccsp.autotune(jobs, "fp32", graph=True, reps=3,
-                                   cache_path=args.tune_cache or None)
+                                   cache_path=args.tune_cache)
     tune_s = time.perf_counter() - t
     log(f"[bench] autotune: {best.as_tuple()} in {tune_s:.1f}s")
     for _ in range(args.warmup):
