@@ -171,6 +171,17 @@ def main():
     torch.cuda.synchronize()
     ms_io = (time.perf_counter() - t_io) / k_io * 1e3
 
+    # point location of the same origins (Sec. 5.2), timed on its own
+    ccsp.locate(scene, o)
+    torch.cuda.synchronize()
+    t_loc = time.perf_counter()
+    for _ in range(3):
+        loc_tri, loc_st = ccsp.locate(scene, o)
+    torch.cuda.synchronize()
+    ms_locate = (time.perf_counter() - t_loc) / 3 * 1e3
+    locate_ok = bool(torch.equal(loc_tri, st) and int((loc_st != 0).sum().item()) == 0)
+    del loc_tri, loc_st
+
     # diagnostics outside the timed region
     steps_total = int(out32.steps.sum(dtype=torch.int64).item())
     steps_p99 = float(torch.quantile(out32.steps[: 1 << 24].double(), 0.99).item())
@@ -238,6 +249,8 @@ def main():
                                "walk": float(np.mean(walk64)) * 1e3,
                                "finish": float(np.mean(fin64)) * 1e3}},
         "fp32_input_order_ms_per_step": ms_io,
+        "locate": {"points_per_s": n / ms_locate * 1e3, "ms": ms_locate,
+                   "equals_start_triangles": locate_ok},
         "tuned": {k: dict(zip(["wg_size", "tile_rays", "waves_per_cu", "refill_min",
                                "tiles_per_claim", "xcd_chunks", "bin"], v))
                   for k, v in tuned.items()},

@@ -194,6 +194,19 @@ int tune_cache_set(int32_t n_items, int64_t total_rays, int64_t total_triangles,
 int tune_cache_get(int32_t n_items, int64_t total_rays, int64_t total_triangles, int precision,
                    TuneParams *out);
 
+/*
+ * locate_points: the triangle containing each of n points (paper Sec. 5.2). q_xy: n interleaved
+ * (x,y) binary64 pairs (DEVICE, 16-byte aligned); tri_out receives the caller's triangle id and
+ * status: 0 = strictly inside tri_out, 1 = on an edge or vertex of tri_out (a ray may not start
+ * there), -1 = outside the triangulation (tri_out -1), -2 = a coordinate not finite (tri_out -1).
+ * Each point is reached by a walk from a seed point of a grid built at load (a point strictly
+ * inside a known triangle per cell, about one cell per four triangles) along the exact segment
+ * from the seed to the point, through constrained edges as through the others; decisions are
+ * exact, so strict inclusion is decided exactly. Asynchronous on `stream`.
+ */
+int locate_points(const Triangulation *tri, const double *q_xy, int64_t n, int32_t *tri_out,
+                  int32_t *status, void *stream);
+
 /* reserve_workspace: reserve the ray binning scratch for traces of up to max_rays rays on the
  * current device, so that later traces allocate nothing. */
 int reserve_workspace(int64_t max_rays);

@@ -53,6 +53,7 @@ def _L():
         lib.oracle_brute_edges.argtypes = [P, I64, P, P, P, P, P, I]
         lib.oracle_brute_prims.argtypes = [I64, P, I64, P, P, P, P, I]
         lib.oracle_validate.argtypes = [P, I, ctypes.c_char_p, I]
+        lib.oracle_locate.argtypes = [P, I64, P, P, P, I]
         lib.oracle_num_threads.restype = I
         _lib = lib
     return _lib
@@ -136,6 +137,18 @@ def brute_prims(prims, o, d, threads: int = 0):
     st = _L().oracle_brute_prims(prims.reshape(-1, 4).shape[0], _p(prims), n, _p(o), _p(d),
                                  _p(prim), _p(t), int(threads))
     return prim, t, st
+
+
+def locate(tri: Triangulation, q, threads: int = 0):
+    """Brute-force point location (Sec. 5.2). Returns (triangle, status) per point: status 0
+    strictly inside, 1 on an edge or vertex (the first such triangle), -1 outside, -2 not
+    finite."""
+    q = _c(q, np.float64).reshape(-1, 2)
+    n = q.shape[0]
+    tr = np.empty(n, np.int32)
+    st = np.empty(n, np.int32)
+    _L().oracle_locate(ctypes.byref(tri.c), n, _p(q), _p(tr), _p(st), int(threads))
+    return tr, st
 
 
 def validate(tri: Triangulation, delaunay: bool = False) -> str:

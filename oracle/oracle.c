@@ -329,6 +329,46 @@ int oracle_walk(const oracle_tri_t *m, int64_t n, const double *o, const double 
   return 0;
 }
 
+/* ------------------------------------------------------------------ point location (Sec. 5.2) */
+
+/* The triangle containing q, by definition: q is in the closed triangle (a, b, c) (counter-
+ * clockwise) iff orient(b, c, q), orient(c, a, q) and orient(a, b, q) are all >= 0, and strictly
+ * inside iff all are > 0. Every triangle is tried in index order; a bounding-box comparison
+ * (exact: coordinates are only compared) skips the ones that cannot contain q. */
+int oracle_locate(const oracle_tri_t *m, int64_t n, const double *q, int32_t *tri,
+                  int32_t *status, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < n; ++k) {
+    const double *p = q + 2 * k;
+    tri[k] = -1;
+    status[k] = -1;
+    if (!isfinite(p[0]) || !isfinite(p[1])) {
+      status[k] = -2;
+      continue;
+    }
+    for (int64_t t = 0; t < m->nt; ++t) {
+      const double *a = m->xy + 2 * (int64_t)m->tri_v[3 * t];
+      const double *b = m->xy + 2 * (int64_t)m->tri_v[3 * t + 1];
+      const double *c = m->xy + 2 * (int64_t)m->tri_v[3 * t + 2];
+      if (p[0] < fmin(a[0], fmin(b[0], c[0])) || p[0] > fmax(a[0], fmax(b[0], c[0])) ||
+          p[1] < fmin(a[1], fmin(b[1], c[1])) || p[1] > fmax(a[1], fmax(b[1], c[1])))
+        continue;
+      const int s0 = oracle_orient(b, c, p), s1 = oracle_orient(c, a, p), s2 = oracle_orient(a, b, p);
+      if (s0 >= 0 && s1 >= 0 && s2 >= 0) {
+        tri[k] = (int32_t)t;
+        status[k] = (s0 > 0 && s1 > 0 && s2 > 0) ? 0 : 1;
+        break;
+      }
+    }
+  }
+  return 0;
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

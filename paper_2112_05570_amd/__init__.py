@@ -171,6 +171,21 @@ def autotune(jobs, precision="fp32", graph=False, input_order=False, reps=3, str
     return best, ms
 
 
+def locate(scene: Scene, q, stream=None):
+    """The triangle (caller's id) containing each point of q ((n,2) float64 CUDA tensor) and a
+    status per point: 0 strictly inside, 1 on an edge or vertex, -1 outside, -2 not finite.
+    Asynchronous."""
+    import torch
+    n = q.shape[0]
+    if not q.is_cuda or q.dtype != torch.float64 or tuple(q.shape) != (n, 2) or not q.is_contiguous():
+        raise ValueError("q must be a contiguous float64 CUDA tensor of shape (n, 2)")
+    tri = torch.empty(n, dtype=torch.int32, device=q.device)
+    status = torch.empty(n, dtype=torch.int32, device=q.device)
+    B.locate_points(scene.handle, q.data_ptr(), n, tri.data_ptr(), status.data_ptr(),
+                    _stream(stream))
+    return tri, status
+
+
 def read_counters(reset=False):
     """(steps, binary32 deferrals, binary64 deferrals, rays) since the last reset."""
     return B.read_counters(reset)

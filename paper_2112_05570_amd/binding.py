@@ -45,7 +45,7 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "free_triangulation", "last_error", "read_counters", "triangulation_info",
            "reserve_workspace", "gather_roofline", "read_stage_times", "autotune",
            "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
-           "server_stats", "server_destroy")
+           "server_stats", "server_destroy", "locate_points")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -106,6 +106,8 @@ _lib.tune_cache_set.argtypes = [ctypes.c_int32, _I64, _I64, _I, ctypes.POINTER(T
 _lib.tune_cache_set.restype = _I
 _lib.tune_cache_get.argtypes = [ctypes.c_int32, _I64, _I64, _I, ctypes.POINTER(TuneParams)]
 _lib.tune_cache_get.restype = _I
+_lib.locate_points.argtypes = [_P, _P, _I64, _P, _P, _P]
+_lib.locate_points.restype = _I
 
 
 class ServerConfig(ctypes.Structure):
@@ -214,6 +216,10 @@ def tune_cache_get(n_items: int, total_rays: int, total_triangles: int, precisio
     if rc < 0:
         _check(rc)
     return out if rc == 1 else None
+
+
+def locate_points(tri: int, q_xy: int, n: int, tri_out: int, status: int, stream: int = 0) -> None:
+    _check(_lib.locate_points(_P(tri), _P(q_xy), n, _P(tri_out), _P(status), _P(stream)))
 
 
 def server_create(cfg: ServerConfig | None) -> int:

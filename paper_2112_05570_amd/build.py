@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libccsp_walk.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("walk_kernels.hip", "bin.hip", "gather.hip", "capi.cpp", "serve.cpp")]
+           for f in ("walk_kernels.hip", "bin.hip", "gather.hip", "locate.hip", "capi.cpp",
+                     "serve.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

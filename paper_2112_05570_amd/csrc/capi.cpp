@@ -16,6 +16,7 @@
 #include <array>
 #include <map>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -493,6 +494,98 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   }
   std::vector<int32_t> new_of(T);
   for (int64_t r = 0; r < T; ++r) new_of[(int64_t)(hkey[r] & 0xffffffffu)] = (int32_t)r;
+  // ---- point-location seeds (Sec. 5.2: points with known triangles on the centres of a regular
+  // grid, from which a walk reaches any point): a G x G grid over the bounding square, about four
+  // triangles per cell; each cell keeps a point strictly inside a triangle containing its centre
+  const double seed_span = std::max(hi[0] - lo[0], hi[1] - lo[1]);
+  const int G = (int)std::min<int64_t>(
+      4096, std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)T / 4.0))));
+  const double ch = seed_span > 0 ? seed_span / G : 1.0;
+  std::vector<SeedCell> seeds((size_t)G * G);
+  {
+    std::vector<std::atomic<int32_t>> cell_tri((size_t)G * G);
+    for (auto& c : cell_tri) c.store(INT32_MAX, std::memory_order_relaxed);
+    auto P = [&](int64_t vtx) { return xy + 2 * vtx; };
+    parallel_for(T, [&](int64_t a, int64_t b) {
+      for (int64_t nt = a; nt < b; ++nt) {
+        const int32_t* v = tv + 3 * (int64_t)(hkey[nt] & 0xffffffffu);
+        const double *p0 = P(v[0]), *p1 = P(v[1]), *p2 = P(v[2]);
+        const double x0 = std::min({p0[0], p1[0], p2[0]}), x1 = std::max({p0[0], p1[0], p2[0]});
+        const double y0 = std::min({p0[1], p1[1], p2[1]}), y1 = std::max({p0[1], p1[1], p2[1]});
+        const int i0 = std::max(0, (int)std::ceil((x0 - lo[0]) / ch - 0.5));
+        const int i1 = std::min(G - 1, (int)std::floor((x1 - lo[0]) / ch - 0.5));
+        const int j0 = std::max(0, (int)std::ceil((y0 - lo[1]) / ch - 0.5));
+        const int j1 = std::min(G - 1, (int)std::floor((y1 - lo[1]) / ch - 0.5));
+        for (int j = j0; j <= j1; ++j)
+          for (int i = i0; i <= i1; ++i) {
+            const double c[2] = {lo[0] + (i + 0.5) * ch, lo[1] + (j + 0.5) * ch};
+            if (orient_host(p1, p2, c) < 0 || orient_host(p2, p0, c) < 0 || orient_host(p0, p1, c) < 0)
+              continue;
+            std::atomic<int32_t>& cell = cell_tri[(size_t)j * G + i];
+            int32_t cur = cell.load(std::memory_order_relaxed);
+            while ((int32_t)nt < cur && !cell.compare_exchange_weak(cur, (int32_t)nt)) {
+            }
+          }
+      }
+    });
+    // a point strictly inside internal triangle nt (the centroid, else other interior mixes)
+    auto interior = [&](int64_t nt, const double* pref, SeedCell* out) {
+      const int32_t* v = tv + 3 * (int64_t)(hkey[nt] & 0xffffffffu);
+      const double *p0 = P(v[0]), *p1 = P(v[1]), *p2 = P(v[2]);
+      const double w[5][3] = {{1, 1, 1}, {0, 0, 0}, {2, 1, 1}, {1, 2, 1}, {1, 1, 2}};
+      for (int k = 0; k < 5; ++k) {
+        double q[2];
+        if (k == 1) {
+          if (!pref) continue;
+          q[0] = pref[0];
+          q[1] = pref[1];
+        } else {
+          const double s = w[k][0] + w[k][1] + w[k][2];
+          for (int c = 0; c < 2; ++c) q[c] = (w[k][0] * p0[c] + w[k][1] * p1[c] + w[k][2] * p2[c]) / s;
+        }
+        if (orient_host(p1, p2, q) > 0 && orient_host(p2, p0, q) > 0 && orient_host(p0, p1, q) > 0) {
+          *out = SeedCell{q[0], q[1], (int32_t)nt, 0};
+          return true;
+        }
+      }
+      return false;
+    };
+    std::vector<uint8_t> have((size_t)G * G, 0);
+    parallel_for((int64_t)G * G, [&](int64_t a, int64_t b) {
+      for (int64_t k = a; k < b; ++k) {
+        const int32_t nt = cell_tri[k].load(std::memory_order_relaxed);
+        if (nt == INT32_MAX) continue;
+        const double c[2] = {lo[0] + ((k % G) + 0.5) * ch, lo[1] + ((k / G) + 0.5) * ch};
+        have[k] = interior(nt, c, &seeds[k]);
+      }
+    });
+    // cells left without a seed take the nearest seeded cell's (breadth-first over the grid)
+    std::queue<int64_t> bfs;
+    for (int64_t k = 0; k < (int64_t)G * G; ++k)
+      if (have[k]) bfs.push(k);
+    if (bfs.empty()) {
+      SeedCell any{};
+      bool found = false;
+      for (int64_t nt = 0; nt < T && !found; ++nt) found = interior(nt, nullptr, &any);
+      if (!found) return fail(CCSP_E_BAD_TRIANGULATION, "no point strictly inside any triangle");
+      for (auto& s : seeds) s = any;
+    }
+    while (!bfs.empty()) {
+      const int64_t k = bfs.front();
+      bfs.pop();
+      const int64_t i = k % G, j = k / G;
+      const int64_t nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+      for (const auto& n2 : nb) {
+        if (n2[0] < 0 || n2[0] >= G || n2[1] < 0 || n2[1] >= G) continue;
+        const int64_t m = n2[1] * G + n2[0];
+        if (have[m]) continue;
+        have[m] = 1;
+        seeds[m] = seeds[k];
+        bfs.push(m);
+      }
+    }
+  }
+
   // primitives stay in the caller's order: a single trace reads them in input order of the rays
   // (the finishing pass), where no renumbering would bring hits of neighbouring rays together
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -503,7 +596,9 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   const size_t off_v = align(off_tv + sizeof(int4) * T);
   const size_t off_p = align(off_v + sizeof(double2) * V);
   const size_t off_perm = align(off_p + sizeof(PrimRec) * std::max<int64_t>(P, 1));
-  const size_t total = align(off_perm + sizeof(int32_t) * T);
+  const size_t off_orig = align(off_perm + sizeof(int32_t) * T);
+  const size_t off_seed = align(off_orig + sizeof(int32_t) * T);
+  const size_t total = align(off_seed + sizeof(SeedCell) * seeds.size());
   std::vector<unsigned char> host(total, 0);
   auto* s32 = reinterpret_cast<Slot32*>(host.data() + off_s32);
   auto* s64 = reinterpret_cast<Slot64*>(host.data() + off_s64);
@@ -513,6 +608,11 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   static_assert(sizeof(PrimRec) == 4 * sizeof(double), "primitive record = its segment");
   if (P > 0) std::memcpy(host.data() + off_p, ps, sizeof(PrimRec) * P);
   std::memcpy(host.data() + off_perm, new_of.data(), sizeof(int32_t) * T);
+  {
+    auto* orig = reinterpret_cast<int32_t*>(host.data() + off_orig);
+    for (int64_t r = 0; r < T; ++r) orig[r] = (int32_t)(hkey[r] & 0xffffffffu);
+  }
+  std::memcpy(host.data() + off_seed, seeds.data(), sizeof(SeedCell) * seeds.size());
   parallel_for(T, [&](int64_t a, int64_t b) {
     for (int64_t nt = a; nt < b; ++nt) {
       const int64_t t = (int64_t)(hkey[nt] & 0xffffffffu);  // caller's id of internal triangle nt
@@ -528,27 +628,26 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
       for (int i = 0; i < 3; ++i) {
         const int64_t k = 3 * nt + i;
         const int32_t n = tn[3 * t + i], pr = tp[3 * t + i];
-        int32_t word, vid = 0;
-        if (pr >= 0) {
-          word = -(pr + 2);
-        } else if (n < 0) {
-          word = -1;
-        } else {
+        int32_t through = -1, vid = 0;
+        if (n >= 0) {
           int back = 0;
           for (int j = 0; j < 3; ++j)
             if (tn[3 * (int64_t)n + j] == t) back = j;
-          word = (new_of[n] << 2) | back;
+          through = (new_of[n] << 2) | back;
           vid = tv[3 * (int64_t)n + back];
         }
+        const int32_t word = pr >= 0 ? -(pr + 2) : through;
         const double vx = xy[2 * (int64_t)vid], vy = xy[2 * (int64_t)vid + 1];
         s32[k].word = word;
-        s32[k].vid = vid;
+        s32[k].vid = word >= 0 ? vid : 0;
         s32[k].x = word >= 0 ? (float)(vx - org[0]) : 0.0f;
         s32[k].y = word >= 0 ? (float)(vy - org[1]) : 0.0f;
         s64[k].word = word;
         s64[k].vid = vid;
-        s64[k].x = word >= 0 ? vx : 0.0;
-        s64[k].y = word >= 0 ? vy : 0.0;
+        s64[k].x = through >= 0 ? vx : 0.0;
+        s64[k].y = through >= 0 ? vy : 0.0;
+        s64[k].through = through;
+        s64[k].pad = 0;
       }
     }
   });
@@ -584,6 +683,12 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   tri->dev.v64 = reinterpret_cast<const double2*>(base + off_v);
   tri->dev.prim = reinterpret_cast<const PrimRec*>(base + off_p);
   tri->dev.perm = reinterpret_cast<const int32_t*>(base + off_perm);
+  tri->dev.orig = reinterpret_cast<const int32_t*>(base + off_orig);
+  tri->dev.seeds = reinterpret_cast<const SeedCell*>(base + off_seed);
+  tri->dev.seed_x0 = lo[0];
+  tri->dev.seed_y0 = lo[1];
+  tri->dev.seed_inv = 1.0 / ch;
+  tri->dev.seed_g = G;
   tri->dev.org_x = org[0];
   tri->dev.org_y = org[1];
   tri->dev.box_x0 = lo[0];
@@ -849,6 +954,21 @@ int reserve_workspace(int64_t max_rays) {
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(ds->bin_mu);
   return grow_bin_workspace(ds, max_rays);
+}
+
+int locate_points(const Triangulation* tri, const double* q_xy, int64_t n, int32_t* tri_out,
+                  int32_t* status, void* stream) {
+  g_err.clear();
+  if (!tri) return fail(CCSP_E_ARG, "null triangulation");
+  if (n < 0) return fail(CCSP_E_ARG, "negative point count");
+  if (n == 0) return CCSP_OK;
+  if (!q_xy || !tri_out || !status) return fail(CCSP_E_ARG, "null point or output pointer");
+  if (!aligned(q_xy, 16) || !aligned(tri_out, 4) || !aligned(status, 4))
+    return fail(CCSP_E_ARG, "q_xy must be 16-byte aligned, outputs 4-byte aligned");
+  const hipError_t e = launch_locate(tri->dev, reinterpret_cast<const double2*>(q_xy), n, tri_out,
+                                     status, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "locate launch");
+  return CCSP_OK;
 }
 
 int tune_cache_set(int32_t n_items, int64_t total_rays, int64_t total_triangles, int precision,

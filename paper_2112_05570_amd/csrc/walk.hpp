@@ -19,10 +19,12 @@ struct alignas(16) Slot32 {  // binary32 walk: 16 B per slot
   int32_t vid;                // its vertex id (for the binary64 fallback)
 };
 struct alignas(32) Slot64 {  // binary64 walk: 32 B per slot
-  double x, y;                // across vertex (binary64, absolute)
+  double x, y;                // across vertex (binary64, absolute), also across constrained edges
   int32_t word;
   int32_t vid;
-  int32_t pad[2];
+  int32_t through;            // (neighbour << 2) | back whatever the constraint, -1 on the hull:
+                              // the word of a walk to which constraints are transparent (locate)
+  int32_t pad;
 };
 // First-triangle record, in the CALLER's triangle order (rays name their start triangle by the
 // caller's id): its vertices relative to the scene origin in binary32, and its internal id.
@@ -37,6 +39,13 @@ struct alignas(32) PrimRec {
   double ax, ay, bx, by;
 };
 
+// Seed of point location: a point strictly inside internal triangle `tri`, per grid cell.
+struct SeedCell {
+  double x, y;
+  int32_t tri;
+  int32_t pad;
+};
+
 struct SceneDev {
   const Slot32* slot32;    // 3T
   const Slot64* slot64;    // 3T
@@ -45,6 +54,11 @@ struct SceneDev {
   const double2* v64;    // V
   const PrimRec* prim;   // P, the caller's order
   const int32_t* perm;   // T: caller's triangle id -> internal (Hilbert-ordered) id
+  const int32_t* orig;   // T: internal id -> the caller's id
+  const SeedCell* seeds;  // seed_g x seed_g cells over the bounding square, row-major
+  double seed_x0, seed_y0, seed_inv;  // cell = floor((p - seed_0) * seed_inv)
+  int32_t seed_g;
+  int32_t pad2;
   double org_x, org_y;   // origin of the binary32 coordinates
   double box_x0, box_y0, box_x1, box_y1;  // bounding box of the vertices
   int32_t ntri;
@@ -127,6 +141,10 @@ hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t to
                              hipEvent_t walk_begin = nullptr, hipEvent_t walk_end = nullptr);
 
 size_t walk_lds_bytes(int mode, const LaunchCfg& cfg);
+
+// Point location (locate.hip): walk from the query's seed to each query point.
+hipError_t launch_locate(const SceneDev& sc, const double2* q, int64_t n, int32_t* tri,
+                         int32_t* status, hipStream_t stream);
 
 // The message last_error() returns on the calling thread.
 void set_last_error(const char* msg);

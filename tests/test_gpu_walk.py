@@ -9,6 +9,7 @@ import ctypes
 import numpy as np
 import pytest
 
+import helpers
 import oracle
 import scenegen as sg
 
@@ -453,3 +454,50 @@ def test_server_rejects_oversized_request(ccsp, tiny_scene, tiny_rays):
                           torch.empty(n, dtype=torch.int32))
         with pytest.raises(ccsp.CcspError, match="more than the server"):
             srv.submit(scene, o, o, st, out)
+
+
+def _check_locate(tri_gpu, st_gpu, sc, q, what):
+    """Statuses equal the checker's; triangles equal where the answer is unique; where the point
+    is on an edge or vertex, the GPU's triangle must contain it in its closure."""
+    ref_t, ref_s = oracle.locate(oracle.Triangulation.of(sc), q)
+    assert np.array_equal(st_gpu, ref_s), f"{what}: status differs at {np.nonzero(st_gpu != ref_s)[0][:5]}"
+    uniq = ref_s != 1
+    assert np.array_equal(tri_gpu[uniq], ref_t[uniq]), f"{what}: triangle differs"
+    for k in np.nonzero(~uniq)[0]:
+        a, b, c = (sc.xy[v] for v in sc.tri_v[tri_gpu[k]])
+        assert min(oracle.orient(b, c, q[k]), oracle.orient(c, a, q[k]),
+                   oracle.orient(a, b, q[k])) == 0, f"{what}: point {k} not on triangle {tri_gpu[k]}"
+
+
+def test_locate_tiny_and_degenerate_points(ccsp, tiny_scene, tiny_rays):
+    rng = np.random.default_rng(3)
+    scenes = [tiny_scene] + [helpers.integer_scene(rng, int(rng.integers(3, 12))) for _ in range(4)]
+    for k, sc in enumerate(scenes):
+        e = sc.tri_v[:, [0, 1, 1, 2, 2, 0]].reshape(-1, 2)
+        mid = 0.5 * (sc.xy[e[:, 0]] + sc.xy[e[:, 1]])  # exact on the integer scenes
+        lo, hi = sc.box
+        pts = [sc.xy, mid, rng.uniform(lo, hi, (3000, 2)),
+               np.array([[lo - 1, lo], [hi + 5, hi], [np.nan, lo], [lo, np.inf], [-1e300, 0.0]])]
+        if k == 0:
+            pts.append(tiny_rays.o)
+        q = np.ascontiguousarray(np.concatenate(pts))
+        with ccsp.Scene.from_arrays(sc) as scene:
+            t, s = ccsp.locate(scene, torch.from_numpy(q).to(DEV))
+            torch.cuda.synchronize()
+            _check_locate(t.cpu().numpy(), s.cpu().numpy(), sc, q, f"scene {k}")
+
+
+def test_locate_ray_origins_at_scale(ccsp, grid_pair):
+    sc, an, rays, start_an = grid_pair
+    q = torch.from_numpy(rays.o).to(DEV)
+    for tri_sc, start in ((sc, rays.start), (an, start_an)):
+        with ccsp.Scene.from_arrays(tri_sc) as scene:
+            t, s = ccsp.locate(scene, q)
+            torch.cuda.synchronize()
+            assert (s.cpu().numpy() == 0).all() and np.array_equal(t.cpu().numpy(), start)
+    large = sg.make_scene("large")
+    r = sg.sample_rays(large, 1 << 22, seed=4)
+    with ccsp.Scene.from_arrays(large) as scene:
+        t, s = ccsp.locate(scene, torch.from_numpy(r.o).to(DEV))
+        torch.cuda.synchronize()
+        assert (s.cpu().numpy() == 0).all() and np.array_equal(t.cpu().numpy(), r.start)
