@@ -54,6 +54,7 @@ def _L():
         lib.oracle_brute_prims.argtypes = [I64, P, I64, P, P, P, P, I]
         lib.oracle_validate.argtypes = [P, I, ctypes.c_char_p, I]
         lib.oracle_locate.argtypes = [P, I64, P, P, P, I]
+        lib.oracle_bounce.argtypes = [P, I64, P, P, P, ctypes.c_int32, P, P, P, P, P, I]
         lib.oracle_num_threads.restype = I
         _lib = lib
     return _lib
@@ -137,6 +138,19 @@ def brute_prims(prims, o, d, threads: int = 0):
     st = _L().oracle_brute_prims(prims.reshape(-1, 4).shape[0], _p(prims), n, _p(o), _p(d),
                                  _p(prim), _p(t), int(threads))
     return prim, t, st
+
+
+def bounce(tri: Triangulation, o, d, start, max_bounces: int, threads: int = 0):
+    """The walk continued by specular reflections (Sec. 5.2's secondary rays). Returns
+    (prim, t, steps, hits, face) per ray; see oracle.c."""
+    o, d, start = _c(o, np.float64), _c(d, np.float64), _c(start, np.int32)
+    n = start.shape[0]
+    prim, t, steps = _outs(n)
+    hits = np.empty(n, np.int32)
+    face = np.empty(n, np.int32)
+    _L().oracle_bounce(ctypes.byref(tri.c), n, _p(o), _p(d), _p(start), int(max_bounces),
+                       _p(prim), _p(t), _p(steps), _p(hits), _p(face), int(threads))
+    return prim, t, steps, hits, face
 
 
 def locate(tri: Triangulation, q, threads: int = 0):

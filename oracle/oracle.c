@@ -329,6 +329,116 @@ int oracle_walk(const oracle_tri_t *m, int64_t n, const double *o, const double 
   return 0;
 }
 
+/* ------------------------------------------------------------------ continuation (Sec. 5.2) */
+
+/* Specular reflection at a hit of primitive seg = (a, b) at parameter t: the new origin is
+ * o + t d, the new direction d - k n with n = (-ey, ex), e = b - a, the segment's normal, and
+ * k = 2 (d . n) / (n . n); binary64, in exactly this order, no fused operations. */
+static void reflect(const double *o, const double *d, const double *seg, double t, double *o2,
+                    double *d2) {
+  const double ex = seg[2] - seg[0], ey = seg[3] - seg[1];
+  const double nx = -ey, ny = ex;
+  const double dn = d[0] * nx + d[1] * ny;
+  const double nn = nx * nx + ny * ny;
+  const double k = (2.0 * dn) / nn;
+  o2[0] = o[0] + t * d[0];
+  o2[1] = o[1] + t * d[1];
+  d2[0] = d[0] - k * nx;
+  d2[1] = d[1] - k * ny;
+}
+
+/* The walk of oracle_walk, continued at hits: while fewer than max_bounces reflections have been
+ * made, a hit reflects the ray off its primitive and the walk goes on from the hit point in the
+ * triangle it ended in (the final triangle of a traversal starts the secondary ray), which the
+ * reflected ray enters through the hit edge, so only the vertex across that edge decides the
+ * exit. Outputs: the last segment's primitive (-1 miss, -2 a segment longer than the step guard,
+ * -3 bad start), its t, the triangles visited over all segments (the hit triangle counts in both
+ * segments), the reflections made and the last segment's hit face (4 * triangle + edge, -1 if
+ * it did not hit). */
+static void bounce_one(const oracle_tri_t *m, const double *o_in, const double *d_in,
+                       int32_t start, int32_t max_bounces, int32_t *prim, double *t,
+                       int32_t *steps, int32_t *hits, int32_t *face) {
+  *prim = -3;
+  *t = INFINITY;
+  *steps = 0;
+  *hits = 0;
+  *face = -1;
+  if (start < 0 || start >= m->nt) return;
+  double o[2] = {o_in[0], o_in[1]}, d[2] = {d_in[0], d_in[1]};
+  int tri = start;
+  const int32_t *tv = m->tri_v + 3 * (int64_t)tri;
+  for (int i = 0; i < 3; ++i)
+    if (oracle_orient(VX(m, tv[(i + 1) % 3]), VX(m, tv[(i + 2) % 3]), o) <= 0) return;
+  int left[3], exit_edge = -1;
+  for (int i = 0; i < 3; ++i) left[i] = is_left(o, d, VX(m, tv[i]));
+  for (int i = 0; i < 3; ++i)
+    if (!left[(i + 1) % 3] && left[(i + 2) % 3]) exit_edge = i;
+  if (exit_edge < 0) return;
+  int64_t count = 1, seg_count = 1;
+  const int64_t guard = m->nt;
+  int32_t nb = 0;
+  for (;;) {
+    const int64_t slot = 3 * (int64_t)tri + exit_edge;
+    if (m->tri_prim[slot] >= 0) {
+      const int32_t p = m->tri_prim[slot];
+      const double *seg = m->prim + 4 * (int64_t)p;
+      const double th = oracle_t(o, d, seg);
+      if (nb < max_bounces) {
+        double o2[2], d2[2];
+        reflect(o, d, seg, th, o2, d2);
+        o[0] = o2[0];
+        o[1] = o2[1];
+        d[0] = d2[0];
+        d[1] = d2[1];
+        ++nb;
+        ++count;
+        seg_count = 1;
+        /* the reflected ray enters this triangle through the hit edge */
+        exit_edge = is_left(o, d, VX(m, tv[exit_edge])) ? (exit_edge + 1) % 3 : (exit_edge + 2) % 3;
+        continue;
+      }
+      *prim = p;
+      *t = th;
+      *face = (int32_t)(4 * (int64_t)tri + exit_edge);
+      break;
+    }
+    const int32_t nbr = m->tri_nbr[slot];
+    if (nbr < 0) {
+      *prim = -1;
+      break;
+    }
+    int back = -1;
+    for (int j = 0; j < 3; ++j)
+      if (m->tri_nbr[3 * (int64_t)nbr + j] == tri) back = j;
+    if (back < 0) return;
+    tri = nbr;
+    if (seg_count >= guard) {
+      *prim = -2;
+      break;
+    }
+    ++count;
+    ++seg_count;
+    tv = m->tri_v + 3 * (int64_t)tri;
+    exit_edge = is_left(o, d, VX(m, tv[back])) ? (back + 1) % 3 : (back + 2) % 3;
+  }
+  *steps = (int32_t)count;
+  *hits = nb;
+}
+
+int oracle_bounce(const oracle_tri_t *m, int64_t n, const double *o, const double *d,
+                  const int32_t *start, int32_t max_bounces, int32_t *prim, double *t,
+                  int32_t *steps, int32_t *hits, int32_t *face, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+  for (int64_t r = 0; r < n; ++r)
+    bounce_one(m, o + 2 * r, d + 2 * r, start[r], max_bounces, prim + r, t + r, steps + r,
+               hits + r, face + r);
+  (void)nthreads;
+  return 0;
+}
+
 /* ------------------------------------------------------------------ point location (Sec. 5.2) */
 
 /* The triangle containing q, by definition: q is in the closed triangle (a, b, c) (counter-

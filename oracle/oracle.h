@@ -33,6 +33,10 @@ int oracle_brute_edges(const oracle_tri_t *m, int64_t n, const double *o, const 
 int oracle_brute_prims(int64_t np, const double *pseg, int64_t n, const double *o,
                        const double *d, int32_t *prim, double *t, int nthreads);
 int oracle_validate(const oracle_tri_t *m, int check_delaunay, char *msg, int msglen);
+/* The walk continued by specular reflections at hits, up to max_bounces (see oracle.c). */
+int oracle_bounce(const oracle_tri_t *m, int64_t n, const double *o, const double *d,
+                  const int32_t *start, int32_t max_bounces, int32_t *prim, double *t,
+                  int32_t *steps, int32_t *hits, int32_t *face, int nthreads);
 /* Point location by brute force: the first triangle (in index order) whose closure contains q;
  * status 0 strictly inside, 1 on an edge or vertex, -1 in no triangle, -2 not finite. */
 int oracle_locate(const oracle_tri_t *m, int64_t n, const double *q, int32_t *tri,
