@@ -171,6 +171,18 @@ def main():
     torch.cuda.synchronize()
     ms_io = (time.perf_counter() - t_io) / k_io * 1e3
 
+    # continued rays: up to 4 specular reflections per ray (Sec. 5.2 secondary rays)
+    ccsp.trace_bounces(scene, o, d, st, 4)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter()
+    for _ in range(3):
+        b_res, b_hits, _ = ccsp.trace_bounces(scene, o, d, st, 4)
+    torch.cuda.synchronize()
+    ms_bounce = (time.perf_counter() - t_b) / 3 * 1e3
+    b_segments = n + int(b_hits.sum(dtype=torch.int64).item())
+    b_steps = int(b_res.steps.sum(dtype=torch.int64).item())
+    del b_res, b_hits
+
     # point location of the same origins (Sec. 5.2), timed on its own
     ccsp.locate(scene, o)
     torch.cuda.synchronize()
@@ -249,6 +261,9 @@ def main():
                                "walk": float(np.mean(walk64)) * 1e3,
                                "finish": float(np.mean(fin64)) * 1e3}},
         "fp32_input_order_ms_per_step": ms_io,
+        "bounces": {"max_bounces": 4, "ms": ms_bounce, "rays_per_s": n / ms_bounce * 1e3,
+                    "segments_per_s": b_segments / ms_bounce * 1e3,
+                    "steps_per_s": b_steps / ms_bounce * 1e3},
         "locate": {"points_per_s": n / ms_locate * 1e3, "ms": ms_locate,
                    "equals_start_triangles": locate_ok},
         "tuned": {k: dict(zip(["wg_size", "tile_rays", "waves_per_cu", "refill_min",

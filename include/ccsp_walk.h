@@ -144,6 +144,25 @@ int trace_rays_tuned(const Triangulation *tri, const double *o_xy, const double 
                      const int32_t *start_tri, int64_t n, int precision, int32_t *hit_prim,
                      double *hit_t, int32_t *steps, const TuneParams *tune, void *stream);
 
+/*
+ * trace_bounces: trace_rays with rays continued at hits (secondary rays, paper Sec. 5.2: the
+ * final triangle of a traversal is the start of the next). At a hit, while fewer than
+ * max_bounces reflections have been made, the ray is reflected specularly off the hit primitive
+ * and walks on from the hit point in the triangle it ended in, which the reflected ray enters
+ * through the hit edge; no new point location and no self-intersection with the primitive just
+ * hit. Reflection in binary64, in this order, without fused operations: o' = o + t d;
+ * n = (-ey, ex) with e = b - a of the primitive; k = (2 (d.n)) / (n.n); d' = d - k n. Outputs
+ * (DEVICE, n each): hit_prim, hit_t and steps as in trace_rays but for the LAST segment (prim and
+ * t) and over ALL segments (steps, the hit triangle counting in both segments); bounces: the
+ * reflections made; hit_face (may be NULL): 4 * (caller's triangle) + edge of the last hit, -1
+ * if the last segment did not hit. The step guard applies per segment. precision: a mode with
+ * CCSP_TRACE_COUNT / INPUT_ORDER / TIMED (no VALIDATE). Asynchronous on `stream`.
+ */
+int trace_bounces(const Triangulation *tri, const double *o_xy, const double *d_xy,
+                  const int32_t *start_tri, int64_t n, int32_t max_bounces, int precision,
+                  int32_t *hit_prim, double *hit_t, int32_t *steps, int32_t *bounces,
+                  int32_t *hit_face, const TuneParams *tune, void *stream);
+
 /* One batch item: a triangulation and its rays (device pointers, as in trace_rays). */
 typedef struct {
   const Triangulation *scene;

@@ -171,6 +171,24 @@ def autotune(jobs, precision="fp32", graph=False, input_order=False, reps=3, str
     return best, ms
 
 
+def trace_bounces(scene: Scene, o, d, start, max_bounces, precision="fp32", stream=None,
+                  tune: TuneParams | None = None, input_order=False, count=False):
+    """Rays continued by specular reflection at hits, up to max_bounces times (see
+    ``trace_bounces`` in the C header). Returns (Result of the last segment with steps over all
+    segments, reflections made, last hit face 4*triangle+edge or -1). Asynchronous."""
+    import torch
+    n = _check_rays(o, d, start)
+    res = _outputs(n, o.device, None)
+    hits = torch.empty(n, dtype=torch.int32, device=o.device)
+    face = torch.empty(n, dtype=torch.int32, device=o.device)
+    mode = (_mode(precision) | (CCSP_TRACE_INPUT_ORDER if input_order else 0)
+            | (CCSP_TRACE_COUNT if count else 0))
+    B.trace_bounces(scene.handle, o.data_ptr(), d.data_ptr(), start.data_ptr(), n, max_bounces,
+                    mode, res.hit_prim.data_ptr(), res.hit_t.data_ptr(), res.steps.data_ptr(),
+                    hits.data_ptr(), face.data_ptr(), tune, _stream(stream))
+    return res, hits, face
+
+
 def locate(scene: Scene, q, stream=None):
     """The triangle (caller's id) containing each point of q ((n,2) float64 CUDA tensor) and a
     status per point: 0 strictly inside, 1 on an edge or vertex, -1 outside, -2 not finite.

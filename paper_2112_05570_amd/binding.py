@@ -45,7 +45,7 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "free_triangulation", "last_error", "read_counters", "triangulation_info",
            "reserve_workspace", "gather_roofline", "read_stage_times", "autotune",
            "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
-           "server_stats", "server_destroy", "locate_points")
+           "server_stats", "server_destroy", "locate_points", "trace_bounces")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -108,6 +108,9 @@ _lib.tune_cache_get.argtypes = [ctypes.c_int32, _I64, _I64, _I, ctypes.POINTER(T
 _lib.tune_cache_get.restype = _I
 _lib.locate_points.argtypes = [_P, _P, _I64, _P, _P, _P]
 _lib.locate_points.restype = _I
+_lib.trace_bounces.argtypes = [_P, _P, _P, _P, _I64, ctypes.c_int32, _I, _P, _P, _P, _P, _P,
+                               ctypes.POINTER(TuneParams), _P]
+_lib.trace_bounces.restype = _I
 
 
 class ServerConfig(ctypes.Structure):
@@ -216,6 +219,15 @@ def tune_cache_get(n_items: int, total_rays: int, total_triangles: int, precisio
     if rc < 0:
         _check(rc)
     return out if rc == 1 else None
+
+
+def trace_bounces(tri: int, o_xy: int, d_xy: int, start_tri: int, n: int, max_bounces: int,
+                  precision: int, hit_prim: int, hit_t: int, steps: int, bounces: int,
+                  hit_face: int, tune: TuneParams | None = None, stream: int = 0) -> None:
+    _check(_lib.trace_bounces(_P(tri), _P(o_xy), _P(d_xy), _P(start_tri), n, max_bounces,
+                              precision, _P(hit_prim), _P(hit_t), _P(steps), _P(bounces),
+                              _P(hit_face), ctypes.byref(tune) if tune is not None else None,
+                              _P(stream)))
 
 
 def locate_points(tri: int, q_xy: int, n: int, tri_out: int, status: int, stream: int = 0) -> None:

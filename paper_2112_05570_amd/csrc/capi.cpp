@@ -639,7 +639,9 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
         const int32_t word = pr >= 0 ? -(pr + 2) : through;
         const double vx = xy[2 * (int64_t)vid], vy = xy[2 * (int64_t)vid + 1];
         s32[k].word = word;
-        s32[k].vid = word >= 0 ? vid : 0;
+        // the vertex opposite the edge in this triangle, for a ray reflected at a constrained edge
+        const int32_t own = v[i];
+        s32[k].vid = word >= 0 ? vid : own;
         s32[k].x = word >= 0 ? (float)(vx - org[0]) : 0.0f;
         s32[k].y = word >= 0 ? (float)(vy - org[1]) : 0.0f;
         s64[k].word = word;
@@ -647,7 +649,7 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
         s64[k].x = through >= 0 ? vx : 0.0;
         s64[k].y = through >= 0 ? vy : 0.0;
         s64[k].through = through;
-        s64[k].pad = 0;
+        s64[k].own = own;
       }
     }
   });
@@ -731,9 +733,10 @@ static int check_rays(const double* o, const double* d, const int32_t* s, int64_
   return CCSP_OK;
 }
 
-int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double* d_xy,
-                     const int32_t* start_tri, int64_t n, int precision, int32_t* hit_prim,
-                     double* hit_t, int32_t* steps, const TuneParams* tune, void* stream) {
+static int trace_common(const Triangulation* tri, const double* o_xy, const double* d_xy,
+                        const int32_t* start_tri, int64_t n, int precision, int32_t* hit_prim,
+                        double* hit_t, int32_t* steps, const TuneParams* tune, void* stream,
+                        int32_t* bounces, int32_t* hit_face, int32_t max_bounces) {
   g_err.clear();
   if (!tri) return fail(CCSP_E_ARG, "null triangulation");
   const int mode = precision & CCSP_TRACE_MODE_MASK;
@@ -759,6 +762,9 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
   hipStream_t st = static_cast<hipStream_t>(stream);
   RaysDev io{reinterpret_cast<const double2*>(o_xy), reinterpret_cast<const double2*>(d_xy),
              start_tri, hit_prim, hit_t, steps, n, nullptr};
+  io.hits = bounces;
+  io.face = hit_face;
+  io.max_bounces = max_bounces;
   unsigned long long* counter = next_counters(ds);
   hipError_t e;
   StageEvents* tev = nullptr;
@@ -812,6 +818,26 @@ int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double*
                                           "triangle is out of range, or its direction is zero or not finite");
   }
   return CCSP_OK;
+}
+
+int trace_rays_tuned(const Triangulation* tri, const double* o_xy, const double* d_xy,
+                     const int32_t* start_tri, int64_t n, int precision, int32_t* hit_prim,
+                     double* hit_t, int32_t* steps, const TuneParams* tune, void* stream) {
+  return trace_common(tri, o_xy, d_xy, start_tri, n, precision, hit_prim, hit_t, steps, tune,
+                      stream, nullptr, nullptr, 0);
+}
+
+int trace_bounces(const Triangulation* tri, const double* o_xy, const double* d_xy,
+                  const int32_t* start_tri, int64_t n, int32_t max_bounces, int precision,
+                  int32_t* hit_prim, double* hit_t, int32_t* steps, int32_t* bounces,
+                  int32_t* hit_face, const TuneParams* tune, void* stream) {
+  g_err.clear();
+  if (max_bounces < 0) return fail(CCSP_E_ARG, "negative max_bounces");
+  if (precision & CCSP_TRACE_VALIDATE) return fail(CCSP_E_ARG, "trace_bounces does not validate");
+  if (n > 0 && !bounces) return fail(CCSP_E_ARG, "null bounces output");
+  if (!aligned(bounces, 4) || !aligned(hit_face, 4)) return fail(CCSP_E_ARG, "misaligned output");
+  return trace_common(tri, o_xy, d_xy, start_tri, n, precision, hit_prim, hit_t, steps, tune,
+                      stream, n > 0 ? bounces : nullptr, hit_face, max_bounces);
 }
 
 int trace_rays(const Triangulation* tri, const double* o_xy, const double* d_xy,

@@ -16,7 +16,8 @@ namespace ccsp {
 struct alignas(16) Slot32 {  // binary32 walk: 16 B per slot
   int32_t word;
   float x, y;                 // across vertex, relative to the scene origin, rounded to binary32
-  int32_t vid;                // its vertex id (for the binary64 fallback)
+  int32_t vid;                // its vertex id (for the binary64 fallback); on a constrained edge,
+                              // this triangle's vertex opposite the edge (reflected rays)
 };
 struct alignas(32) Slot64 {  // binary64 walk: 32 B per slot
   double x, y;                // across vertex (binary64, absolute), also across constrained edges
@@ -24,7 +25,7 @@ struct alignas(32) Slot64 {  // binary64 walk: 32 B per slot
   int32_t vid;
   int32_t through;            // (neighbour << 2) | back whatever the constraint, -1 on the hull:
                               // the word of a walk to which constraints are transparent (locate)
-  int32_t pad;
+  int32_t own;                // this triangle's vertex opposite the edge (reflected rays)
 };
 // First-triangle record, in the CALLER's triangle order (rays name their start triangle by the
 // caller's id): its vertices relative to the scene origin in binary32, and its internal id.
@@ -89,6 +90,11 @@ struct RaysDev {
   int64_t n;
   const int32_t* order;
   const RayRec* recs;
+  // continued rays (trace_bounces): reflections made per ray and the last hit face; hits set
+  // selects the continued walk, which writes prim/t/steps itself
+  int32_t* hits;
+  int32_t* face;
+  int32_t max_bounces;
 };
 
 // One item of a batched launch: the scene, its rays and where its tiles start in the

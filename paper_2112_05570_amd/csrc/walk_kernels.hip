@@ -147,6 +147,17 @@ __device__ void fill_tile(const SceneDev& sc, const RaysDev& io, int64_t base, i
   wave_lds_fence();
 }
 
+// Results of a continued (reflecting) ray, written directly: its last segment's primitive or
+// code, t, the triangles visited over all segments, the reflections made, the last hit face.
+__device__ __forceinline__ void bounce_result(const RaysDev& io, int64_t ray, int code, double t,
+                                              int steps, int hits, int face) {
+  io.prim[ray] = code;
+  io.t[ray] = t;
+  io.steps[ray] = steps;
+  io.hits[ray] = hits;
+  if (io.face) io.face[ray] = face;
+}
+
 // Scene access in a batched launch.
 struct ItemRef {
   const BatchItem* items;
@@ -180,7 +191,11 @@ __device__ __forceinline__ long long claim_tile(unsigned long long* counter, int
 //   WALK:  the slot of the exit edge (then one decision: the vertex across the entry edge),
 // so lanes in different states share one memory round trip, and a refilled lane starts walking
 // in the next iteration without a separate gather phase.
-template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH>
+// BOUNCE: rays continue by specular reflection at hits (up to io.max_bounces times): a fourth
+// state loads the hit primitive and the hit triangle's vertex opposite the hit edge, computes t
+// and either reflects the ray, which then enters the same triangle through the hit edge (Sec.
+// 5.2: the final triangle of a traversal starts the secondary ray), or writes the results.
+template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH, bool BOUNCE>
 __global__ void __launch_bounds__(512)
 walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_tiles,
                 unsigned long long* __restrict__ counter, int refill_min, int chunks, int group,
@@ -201,11 +216,13 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   const Tile<TILE> tl(tile_mem + (size_t)wave * Tile<TILE>::kBytes);
 
   Counters c;
-  enum : int { IDLE = 0, FIRST = 1, WALK = 2 };
+  enum : int { IDLE = 0, FIRST = 1, WALK = 2, BNC = 3 };
   int state = IDLE;
   Ray32 r32{0, 0, 0, 0};                  // binary32 mode
   double ox = 0, oy = 0, dx = 0, dy = 0;  // the ray in binary64
-  int s = 0, steps = 0;                   // s: start triangle (FIRST) or exit slot (WALK)
+  int s = 0, steps = 0;                   // s: start triangle (FIRST), exit slot (WALK), prim (BNC)
+  int nb = 0, seg = 0, hs = 0, cv = 0;    // BOUNCE: reflections, steps of this segment, hit slot,
+                                          // vertex opposite the hit edge
   int64_t ray = 0;
   int item = 0;
   // per-lane scene in a batch, kernel argument otherwise
@@ -279,6 +296,10 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
           s = tl.st[k];
           ray = io_order ? (int64_t)tl.idx[k] : tbase + k;
           steps = 1;
+          if (BOUNCE) {
+            nb = 0;
+            seg = 1;
+          }
           state = binned ? WALK : FIRST;
           double org_x = sc_arg.org_x, org_y = sc_arg.org_y;
           if (BATCH) {
@@ -292,7 +313,10 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
           }
           if (MODE == 1 || !binned) r32 = ray32(ox, oy, dx, dy, org_x, org_y);
           if (s < 0) {  // bad ray: out-of-range start or failed validation
-            park_result(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
+            if (BOUNCE)
+              bounce_result(io_arg, ray, -3, INFINITY, 0, 0, -1);
+            else
+              park_result(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
             state = IDLE;
           }
         }
@@ -302,7 +326,8 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
     }
     // ---- issue: one round of loads for every busy lane, whatever its state
     const int st_now = state;
-    int4 R0 = make_int4(0, 0, 0, 0), R1 = R0;
+    int4 R0 = make_int4(0, 0, 0, 0), R1 = R0, R2 = R0;
+    int R3 = 0;
     if (st_now == WALK) {
       if (MODE == 1) {
         R0 = *reinterpret_cast<const int4*>(slot32 + s);
@@ -315,10 +340,17 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
       const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.first : sc_arg.first) + s);
       R0 = p[0];
       R1 = p[1];
+    } else if (BOUNCE && st_now == BNC) {
+      const int4* p = reinterpret_cast<const int4*>(sc_arg.prim + s);
+      R0 = p[0];
+      R1 = p[1];
+      R2 = *reinterpret_cast<const int4*>(sc_arg.v64 + cv);
+      if (nb >= io_arg.max_bounces && io_arg.face) R3 = sc_arg.orig[hs / 3];
     }
     // every load above is issued before any result is used (and none is split per field)
     __asm__ volatile("" ::"v"(R0.x), "v"(R0.y), "v"(R0.z), "v"(R0.w), "v"(R1.x), "v"(R1.y),
                      "v"(R1.z), "v"(R1.w));
+    if (BOUNCE) __asm__ volatile("" ::"v"(R2.x), "v"(R2.y), "v"(R2.z), "v"(R2.w), "v"(R3));
     // ---- process
     if (st_now == WALK) {
       int word;
@@ -339,11 +371,25 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         word = R1.x;
         if (word >= 0) left = left64<COUNT>(ox, oy, dx, dy, lohi(R0.x, R0.y), lohi(R0.z, R0.w), c.fb64);
       }
-      if (word >= 0 && steps < ntri) {
+      if (word >= 0 && (BOUNCE ? seg < ntri : steps < ntri)) {
         ++steps;
+        if (BOUNCE) ++seg;
         int e = (word & 3) + (left ? 1 : 2);
         e = e >= 3 ? e - 3 : e;
         s = 3 * (word >> 2) + e;
+      } else if (BOUNCE && word <= -2) {
+        // hit: the primitive and the vertex opposite the hit edge are loaded next iteration
+        hs = s;
+        cv = MODE == 1 ? R0.w : R1.w;
+        s = -word - 2;
+        state = BNC;
+      } else if (BOUNCE) {  // hull edge (miss) or the step guard
+        bounce_result(io_arg, ray, word >= 0 ? -2 : -1, INFINITY, steps, nb, -1);
+        if (COUNT) {
+          c.steps += steps;
+          ++c.rays;
+        }
+        state = IDLE;
       } else {
         // constrained edge (hit, primitive -word - 2), hull edge (miss) or the step guard; the
         // finishing pass computes t
@@ -365,7 +411,46 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         s = e;
         state = WALK;
       } else {  // no exit edge: the origin is not inside the start triangle
-        park_result(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
+        if (BOUNCE)
+          bounce_result(io_arg, ray, -3, INFINITY, 0, 0, -1);
+        else
+          park_result(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
+        state = IDLE;
+      }
+    } else if (BOUNCE && st_now == BNC) {
+      const double ax = lohi(R0.x, R0.y), ay = lohi(R0.z, R0.w);
+      const double bx = lohi(R1.x, R1.y), by = lohi(R1.z, R1.w);
+      const double th = hit_t(make_double4(ax, ay, bx, by), ox, oy, dx, dy);
+      if (nb < io_arg.max_bounces) {
+        // specular reflection: origin o + t d; direction d - k n, n = (-ey, ex), k = 2 (d.n)/(n.n)
+        const double ex = bx - ax, ey = by - ay;
+        const double nx = -ey, ny = ex;
+        const double dn = dx * nx + dy * ny;
+        const double nn = nx * nx + ny * ny;
+        const double k = (2.0 * dn) / nn;
+        const double nox = ox + th * dx, noy = oy + th * dy;
+        const double ndx = dx - k * nx, ndy = dy - k * ny;
+        ox = nox;
+        oy = noy;
+        dx = ndx;
+        dy = ndy;
+        if (MODE == 1) r32 = ray32(ox, oy, dx, dy, sc_arg.org_x, sc_arg.org_y);
+        ++nb;
+        ++steps;
+        seg = 1;
+        // the reflected ray enters the hit triangle through the hit edge: only the vertex
+        // opposite that edge decides the exit
+        const int e = hs % 3;
+        const bool left = left64<COUNT>(ox, oy, dx, dy, lohi(R2.x, R2.y), lohi(R2.z, R2.w), c.fb64);
+        const int ex2 = e + (left ? 1 : 2);
+        s = hs - e + (ex2 >= 3 ? ex2 - 3 : ex2);
+        state = WALK;
+      } else {
+        bounce_result(io_arg, ray, s, th, steps, nb, io_arg.face ? 4 * R3 + hs % 3 : -1);
+        if (COUNT) {
+          c.steps += steps;
+          ++c.rays;
+        }
         state = IDLE;
       }
     }
@@ -440,24 +525,24 @@ size_t walk_lds_bytes(int mode, const LaunchCfg& cfg) {
   return (size_t)(cfg.wg / 64) * cfg.tile * 40;
 }
 
-template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH>
+template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH, bool BOUNCE>
 static hipError_t go(const SceneDev& sc, const RaysDev& io, ItemRef br, int64_t total_tiles,
                      const LaunchCfg& cfg, size_t lds, unsigned long long* counter,
                      const Workspace& ws, hipStream_t stream) {
-  hipLaunchKernelGGL((walk_persistent<MODE, TPL, COUNT, VALIDATE, BATCH>), dim3(cfg.grid),
+  hipLaunchKernelGGL((walk_persistent<MODE, TPL, COUNT, VALIDATE, BATCH, BOUNCE>), dim3(cfg.grid),
                      dim3(cfg.wg), lds, stream, sc, io, br, total_tiles, counter, cfg.refill_min,
                      cfg.chunks, cfg.group, ws.stats, ws.errflag);
   return hipGetLastError();
 }
 
-template <int MODE, bool COUNT, bool VALIDATE, bool BATCH>
+template <int MODE, bool COUNT, bool VALIDATE, bool BATCH, bool BOUNCE = false>
 static hipError_t pick_tile(const SceneDev& sc, const RaysDev& io, ItemRef br, int64_t total_tiles,
                             const LaunchCfg& cfg, size_t lds, unsigned long long* counter,
                             const Workspace& ws, hipStream_t stream) {
   switch (cfg.tile) {
-    case 64: return go<MODE, 1, COUNT, VALIDATE, BATCH>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
-    case 128: return go<MODE, 2, COUNT, VALIDATE, BATCH>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
-    case 256: return go<MODE, 4, COUNT, VALIDATE, BATCH>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
+    case 64: return go<MODE, 1, COUNT, VALIDATE, BATCH, BOUNCE>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
+    case 128: return go<MODE, 2, COUNT, VALIDATE, BATCH, BOUNCE>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
+    case 256: return go<MODE, 4, COUNT, VALIDATE, BATCH, BOUNCE>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -475,8 +560,16 @@ hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool cou
   const ItemRef none{nullptr, 0, nullptr, 0};
   const int64_t tiles = (io.n + cfg.tile - 1) / cfg.tile;
   e = hipErrorInvalidValue;
+  const bool bounce = io.hits != nullptr;  // continued rays write their own results
+  if (bounce) {
+    if (validate) return hipErrorInvalidValue;
+    if (mode == 0 && !count) e = pick_tile<0, false, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
+    if (mode == 0 && count) e = pick_tile<0, true, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
+    if (mode == 1 && !count) e = pick_tile<1, false, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
+    if (mode == 1 && count) e = pick_tile<1, true, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
+  }
 #define CCSP_CASE(M, C, V) \
-  if (mode == M && count == C && validate == V) \
+  if (!bounce && mode == M && count == C && validate == V) \
     e = pick_tile<M, C, V, false>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
   CCSP_CASE(0, false, false) CCSP_CASE(0, true, false) CCSP_CASE(0, false, true) CCSP_CASE(0, true, true)
   CCSP_CASE(1, false, false) CCSP_CASE(1, true, false) CCSP_CASE(1, false, true) CCSP_CASE(1, true, true)
@@ -486,6 +579,7 @@ hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool cou
     e = hipEventRecord(walk_end, stream);
     if (e != hipSuccess) return e;
   }
+  if (bounce) return hipSuccess;
   const int64_t blocks = (io.n + 255) / 256;
   hipLaunchKernelGGL(finish_rays, dim3((unsigned)blocks), dim3(256), 0, stream, sc.prim, io.o, io.d,
                      io.prim, io.t, io.steps, io.n);

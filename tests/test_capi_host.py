@@ -146,3 +146,14 @@ def test_server_argument_errors():
     assert B.raw_call("server_poll", z, 0, None, None, None, None, ctypes.byref(n),
                       ctypes.c_double(0)) == B.CCSP_E_ARG
     B.raw_call("server_destroy", z)  # no-op
+
+
+def test_trace_bounces_argument_errors():
+    fake = ctypes.c_void_p(0x1000)
+    al = ctypes.c_void_p(0x10000)
+    z = ctypes.c_void_p(0)
+    n = ctypes.c_int64(5)
+    assert B.raw_call("trace_bounces", fake, al, al, al, n, -1, 1, al, al, al, al, z, None, z) == B.CCSP_E_ARG
+    assert B.raw_call("trace_bounces", fake, al, al, al, n, 2, 1 | B.CCSP_TRACE_VALIDATE, al, al, al, al, z, None, z) == B.CCSP_E_ARG
+    assert B.raw_call("trace_bounces", fake, al, al, al, n, 2, 1, al, al, al, z, z, None, z) == B.CCSP_E_ARG
+    assert B.raw_call("trace_bounces", z, al, al, al, n, 2, 1, al, al, al, al, z, None, z) == B.CCSP_E_ARG

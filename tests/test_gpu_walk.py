@@ -501,3 +501,57 @@ def test_locate_ray_origins_at_scale(ccsp, grid_pair):
         t, s = ccsp.locate(scene, torch.from_numpy(r.o).to(DEV))
         torch.cuda.synchronize()
         assert (s.cpu().numpy() == 0).all() and np.array_equal(t.cpu().numpy(), r.start)
+
+
+def _bounce_host(res, hits, face):
+    torch.cuda.synchronize()
+    return (res.hit_prim.cpu().numpy(), res.hit_t.cpu().numpy(), res.steps.cpu().numpy(),
+            hits.cpu().numpy(), face.cpu().numpy())
+
+
+def _assert_bounce_same(got, ref, what):
+    names = ("prim", "t", "steps", "bounces", "face")
+    for name, g, r in zip(names, got, ref):
+        bad = np.nonzero(~((g == r) | (np.isinf(g) & np.isinf(r)) if name == "t" else (g == r)))[0]
+        assert bad.size == 0, f"{what}: {name} differs at {bad[:5]}: {g[bad[:5]]} vs {r[bad[:5]]}"
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_bounces_tiny_all_rays(ccsp, tiny_scene, tiny_rays, prec):
+    tri = oracle.Triangulation.of(tiny_scene)
+    with ccsp.Scene.from_arrays(tiny_scene) as scene:
+        o, d, st = _dev(tiny_rays)
+        plain = _host(ccsp.trace(scene, o, d, st, precision=prec))
+        for mb in (0, 1, 3, 8):
+            got = _bounce_host(*ccsp.trace_bounces(scene, o, d, st, mb, precision=prec))
+            ref = oracle.bounce(tri, tiny_rays.o, tiny_rays.d, tiny_rays.start, mb)
+            _assert_bounce_same(got, ref, f"{prec} max_bounces={mb}")
+            if mb == 0:
+                _assert_same(got[:3], plain, "zero bounces vs trace")
+                hit = got[0] >= 0
+                f = got[4][hit]
+                assert np.array_equal(tiny_scene.tri_prim[f >> 2, f & 3], got[0][hit])
+            else:
+                assert (got[3] == mb).mean() > 0.9  # nearly every ray keeps hitting walls
+
+
+def test_bounces_binned_grid_and_large_sampled(ccsp, grid_pair):
+    sc, _, rays, _ = grid_pair
+    r = rays.slice(0, 300_000)
+    idx = np.arange(0, r.n, 37)
+    with ccsp.Scene.from_arrays(sc) as scene:
+        o, d, st = _dev(r)
+        got = _bounce_host(*ccsp.trace_bounces(scene, o, d, st, 4))
+        io = _bounce_host(*ccsp.trace_bounces(scene, o, d, st, 4, input_order=True))
+        _assert_bounce_same(got, io, "grid binned vs input order")
+        ref = oracle.bounce(oracle.Triangulation.of(sc), r.o[idx], r.d[idx], r.start[idx], 4)
+        _assert_bounce_same(tuple(x[idx] for x in got), ref, "grid vs checker")
+    large = sg.make_scene("large")
+    r = sg.sample_rays(large, 1 << 21, seed=8)
+    idx = np.arange(0, r.n, 211)
+    with ccsp.Scene.from_arrays(large) as scene:
+        o, d, st = _dev(r)
+        for prec in ("fp32", "fp64"):
+            got = _bounce_host(*ccsp.trace_bounces(scene, o, d, st, 3, precision=prec))
+            ref = oracle.bounce(oracle.Triangulation.of(large), r.o[idx], r.d[idx], r.start[idx], 3)
+            _assert_bounce_same(tuple(x[idx] for x in got), ref, f"large {prec} vs checker")
