@@ -138,6 +138,27 @@ def scene_from_segments(seg: np.ndarray, lo: float, hi: float, name: str = "") -
     return Scene(np.ascontiguousarray(xy), np.ascontiguousarray(prims), seg_v, (lo, hi), name=name)
 
 
+def split_segments(sc: Scene) -> Scene:
+    """The same scene (same primitives) with every segment constrained as two sub-segments that
+    meet at its midpoint, which must be exactly representable and exactly on the segment (true
+    for integer coordinates); the result is not yet triangulated."""
+    S = sc.seg_v.shape[0]
+    a = sc.xy[sc.seg_v[:, 0]]
+    b = sc.xy[sc.seg_v[:, 1]]
+    m = 0.5 * (a + b)
+    on = exact_orient(np.concatenate([a, b, m], axis=1)) == 0
+    if not on.all() or ((m == a).all(axis=1) | (m == b).all(axis=1)).any():
+        raise ValueError("a segment midpoint is not exactly on its segment")
+    V = sc.xy.shape[0]
+    xy = np.concatenate([sc.xy, m], axis=0)
+    mid = V + np.arange(S, dtype=np.int32)
+    seg_v = np.stack([np.stack([sc.seg_v[:, 0], mid], 1), np.stack([mid, sc.seg_v[:, 1]], 1)],
+                     1).reshape(-1, 2).astype(np.int32)
+    meta = dict(sc.meta, seg_prim=np.repeat(np.arange(S, dtype=np.int32), 2))
+    return Scene(np.ascontiguousarray(xy), sc.prims, np.ascontiguousarray(seg_v), sc.box,
+                 name=sc.name + "+split", meta=meta)
+
+
 def random_segments(seed, n, mid_lo, mid_hi, len_lo, len_hi, log_len, box_lo, box_hi,
                     max_draws=None) -> np.ndarray:
     out = np.empty((n, 4), dtype=np.float64)
@@ -155,8 +176,9 @@ def triangulate(sc: Scene) -> Scene:
     """Constrained Delaunay triangulation of the scene (fills tri_v / tri_nbr / tri_prim)."""
     L = _L()
     S = sc.seg_v.shape[0]
-    segp = np.arange(S, dtype=np.int32)
-    h = L.sg_build_cdt(_ptr(sc.xy), sc.xy.shape[0], _ptr(sc.seg_v), _ptr(segp), S, S)
+    segp = np.ascontiguousarray(sc.meta.get("seg_prim", np.arange(S, dtype=np.int32)), np.int32)
+    n_seg_prims = sc.prims.shape[0] - 4
+    h = L.sg_build_cdt(_ptr(sc.xy), sc.xy.shape[0], _ptr(sc.seg_v), _ptr(segp), S, n_seg_prims)
     if not h:
         _err("triangulation failed")
     try:

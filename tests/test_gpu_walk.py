@@ -555,3 +555,28 @@ def test_bounces_binned_grid_and_large_sampled(ccsp, grid_pair):
             got = _bounce_host(*ccsp.trace_bounces(scene, o, d, st, 3, precision=prec))
             ref = oracle.bounce(oracle.Triangulation.of(large), r.o[idx], r.d[idx], r.start[idx], 3)
             _assert_bounce_same(tuple(x[idx] for x in got), ref, f"large {prec} vs checker")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_split_primitives(ccsp, seed):
+    """Every segment constrained as two sub-edges meeting at its midpoint: the hit reports the
+    primitive and t its own segment's parameter, in both modes, with and without continuation;
+    point location is exact on the split vertices too."""
+    rng = np.random.default_rng(100 + seed)
+    split = sg.triangulate(sg.split_segments(helpers.integer_scene(rng, 40, size=48)))
+    o, d, start = helpers.degenerate_rays(split, rng, 6000)
+    r = sg.Rays(o, d, start.astype(np.int32))
+    tri = oracle.Triangulation.of(split)
+    ref = oracle.walk(tri, r.o, r.d, r.start)
+    with ccsp.Scene.from_arrays(split) as scene:
+        dev = _dev(r)
+        for prec in ("fp32", "fp64"):
+            _assert_same(_host(ccsp.trace(scene, *dev, precision=prec)), ref, f"split {prec}")
+            _assert_same(_host(ccsp.trace(scene, *dev, precision=prec, input_order=True)), ref,
+                         f"split {prec} input order")
+            got = _bounce_host(*ccsp.trace_bounces(scene, *dev, 3, precision=prec))
+            _assert_bounce_same(got, oracle.bounce(tri, r.o, r.d, r.start, 3), f"split bounces {prec}")
+        q = np.ascontiguousarray(np.concatenate([split.xy, r.o]))
+        t, s = ccsp.locate(scene, torch.from_numpy(q).to(DEV))
+        torch.cuda.synchronize()
+        _check_locate(t.cpu().numpy(), s.cpu().numpy(), split, q, "split")
