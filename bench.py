@@ -34,9 +34,9 @@ BYTES_PER_RAY = 60
 # taken with.
 WALK_SOURCES = ("walk_kernels.hip", "walk.hpp", "decide.hpp", "exact.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "26b9b14fa625b808f63c6b875643d9f414ed6a0769e8e53bfd8e541fbda54fa6",
+    "sources_sha256": "a117e9c7984262c11635a13123c97a6eee08fe5bacc6729628f68de54700ccb8",
     "tune": [256, 64, 20, 16, 8, 8, 0],
-    "bytes_per_launch": 7447452333,
+    "bytes_per_launch": 7477806676,
 }
 
 
