@@ -1,0 +1,261 @@
+"""Objective with fuzzy contraction and its change under vertex moves: TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU leg may import this module. The
+GPU library never does and shares no code with it.
+
+What is computed (paper Sec. 2.2):
+- the contractible weight w_contr = sum over edges of w_eps(e) * |e| (Sec. 2.2.1), where
+  w_eps(e) = x * M(x) with x the product of c_eps over the other edges of the one or two
+  triangles holding e, c_eps(e) = 1/2 + min(1, |e|/eps)/2 for a contractible edge and 1 otherwise,
+  and M the correction for multiply merged edges (0 below 1/4, 4x - 1 up to 1/2, then 1);
+- which edges are contractible (Sec. 2.2.2): the restrictions from the original geometry (vertex
+  kinds) and the 1-hop topology rule;
+- the angle penalty (Sec. 2.2.3): over the three corners of every triangle, the ramp
+  max(0, -1 + delta - cos)/delta on the cosine between the corner's two edges (in polishing, the
+  ramp max(0, cos - (1 - delta))/delta on sharp corners instead, and every edge weight 1);
+- the length penalty (Sec. 2.2.3): over edges, max(0, eps0 - |e|)/eps0;
+- f = w_contr + mu_angle * P_angle + mu_len * P_len (Sec. 2.2.4);
+- for a proposed single-vertex move (Sec. 3.2.1, 3.2.2), its validity (the triangulation keeps
+  every triangle strictly counter-clockwise, decided exactly) and
+  delta_f = f(moved) - f(current), summed term by term over every term of f.
+
+Every value is binary64, evaluated in the operation order written below with no fused operations
+(numpy does not fuse), so that each term is a fixed function of the coordinates.
+
+Readings of points the paper leaves open:
+- Edge weight: the equation of Sec. 2.2.1 writes M(x), but the worked example of its figure (a
+  merged pair weighs 1/2, an edge with two contracted neighbours weighs 0) and the remark that an
+  identity M would already handle isolated contractions fix w_eps = x * M(x).
+- 1-hop rule: a nontrivial common neighbour H of the edge's endpoints is harmless when its
+  distance to one of the edge's opposite vertices is strictly below eps (the figure's
+  ||V3 H|| < eps).
+- Restrictions from the original geometry (Sec. 2.2.2): an edge is incontractible when both ends
+  are original vertices; when one end is original and the other constrained to an original edge
+  that does not end at it; or when both are constrained to different original edges. The
+  conditioning and flat-triangle restrictions are not part of this objective.
+- A corner with a zero-length edge contributes no angle penalty (its cosine is undefined; the
+  length penalty covers it).
+- Edges are numbered by (lower vertex id, higher vertex id); the product x runs over the
+  neighbouring edges of the edge's triangles in increasing triangle id, each triangle's two edges
+  in its local order after the edge itself, multiplied left to right.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import orient
+
+ORIGINAL, CONSTRAINED, FREE = 0, 1, 2
+
+
+class Params:
+    """eps: contraction length; delta: angle-cosine threshold; eps0: minimum edge length;
+    mu_angle, mu_len: penalty weights; polish: fixed topology (no fuzzy contraction)."""
+
+    def __init__(self, eps, delta=None, eps0=1e-10, mu_angle=1.0, mu_len=10.0, polish=False):
+        self.eps = float(eps)
+        self.delta = float(np.cos(np.radians(179.0)) + 1.0) if delta is None else float(delta)
+        self.eps0 = float(eps0)
+        self.mu_angle = float(mu_angle)
+        self.mu_len = float(mu_len)
+        self.polish = bool(polish)
+
+
+class Mesh:
+    """A triangulation with movable vertices. kind[v] is ORIGINAL, CONSTRAINED (on original edge
+    line[v], an index into prim_v) or FREE; prim_v[k] are the two original vertices ending
+    original edge k. Triangles are counter-clockwise."""
+
+    def __init__(self, tri_v, kind, line, prim_v):
+        self.tri_v = np.ascontiguousarray(tri_v, dtype=np.int64)
+        self.kind = np.ascontiguousarray(kind, dtype=np.int64)
+        self.line = np.ascontiguousarray(line, dtype=np.int64)
+        self.prim_v = np.ascontiguousarray(prim_v, dtype=np.int64).reshape(-1, 2)
+        self.nv = self.kind.shape[0]
+        T = self.tri_v.shape[0]
+        # edge i of a triangle joins v[i+1] and v[i+2]
+        a = self.tri_v[:, [1, 2, 0]]
+        b = self.tri_v[:, [2, 0, 1]]
+        key = np.minimum(a, b) * self.nv + np.maximum(a, b)
+        uniq, inv = np.unique(key.ravel(), return_inverse=True)
+        self.edge_v = np.stack([uniq // self.nv, uniq % self.nv], axis=1)
+        self.edge_key = uniq
+        self.tri_edge = inv.reshape(T, 3)
+        E = uniq.shape[0]
+        cnt = np.bincount(inv, minlength=E)
+        if (cnt > 2).any():
+            raise ValueError("an edge is shared by more than two triangles")
+        # triangles of each edge, increasing id, with the edge's local index there
+        order = np.argsort(inv, kind="stable")  # flattened index = 3 t + i, so t increases
+        first = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+        self.edge_tri = -np.ones((E, 2), dtype=np.int64)
+        self.edge_loc = -np.ones((E, 2), dtype=np.int64)
+        for j in range(2):
+            has = cnt > j
+            f = order[first[has] + j]
+            self.edge_tri[has, j] = f // 3
+            self.edge_loc[has, j] = f % 3
+        # opposite vertices and neighbouring edges in the order stated above
+        self.edge_opp = -np.ones((E, 2), dtype=np.int64)
+        self.edge_nbr = -np.ones((E, 4), dtype=np.int64)
+        for j in range(2):
+            has = self.edge_tri[:, j] >= 0
+            t, i = self.edge_tri[has, j], self.edge_loc[has, j]
+            self.edge_opp[has, j] = self.tri_v[t, i]
+            self.edge_nbr[has, 2 * j] = self.tri_edge[t, (i + 1) % 3]
+            self.edge_nbr[has, 2 * j + 1] = self.tri_edge[t, (i + 2) % 3]
+        # vertex neighbours (sorted) as CSR
+        both = np.concatenate([self.edge_v, self.edge_v[:, ::-1]])
+        both = both[np.lexsort((both[:, 1], both[:, 0]))]
+        self.nbr = both[:, 1]
+        self.nbr_off = np.concatenate([[0], np.cumsum(np.bincount(both[:, 0], minlength=self.nv))])
+
+    @property
+    def n_edges(self):
+        return self.edge_v.shape[0]
+
+    def has_edge(self, a, b):
+        key = np.minimum(a, b) * self.nv + np.maximum(a, b)
+        pos = np.clip(np.searchsorted(self.edge_key, key), 0, self.n_edges - 1)
+        return self.edge_key[pos] == key
+
+
+def lengths(xy, a, b):
+    dx = xy[b, 0] - xy[a, 0]
+    dy = xy[b, 1] - xy[a, 1]
+    return np.sqrt(dx * dx + dy * dy)
+
+
+def direct_contractible(m: Mesh) -> np.ndarray:
+    """Restrictions of the original geometry (Sec. 2.2.2, first paragraph)."""
+    a, b = m.edge_v[:, 0], m.edge_v[:, 1]
+    ka, kb = m.kind[a], m.kind[b]
+    ok = np.ones(m.n_edges, dtype=bool)
+    ok[(ka == ORIGINAL) & (kb == ORIGINAL)] = False
+    for o, c in ((a, b), (b, a)):
+        sel = (m.kind[o] == ORIGINAL) & (m.kind[c] == CONSTRAINED)
+        ends = m.prim_v[m.line[c[sel]]]
+        ok[np.nonzero(sel)[0]] = (ends[:, 0] == o[sel]) | (ends[:, 1] == o[sel])
+    sel = (ka == CONSTRAINED) & (kb == CONSTRAINED)
+    ok[sel] = m.line[a[sel]] == m.line[b[sel]]
+    return ok
+
+
+def one_hop_contractible(m: Mesh, xy, eps) -> np.ndarray:
+    """1-hop topology rule (Sec. 2.2.2): every common neighbour of the edge's endpoints that is
+    not one of its opposite vertices must lie strictly closer than eps to an opposite vertex."""
+    a = m.edge_v[:, 0]
+    deg = m.nbr_off[a + 1] - m.nbr_off[a]
+    e = np.repeat(np.arange(m.n_edges), deg)
+    start = np.repeat(m.nbr_off[a], deg)
+    x = m.nbr[start + (np.arange(e.shape[0]) - np.repeat(np.cumsum(deg) - deg, deg))]
+    b = m.edge_v[e, 1]
+    o0, o1 = m.edge_opp[e, 0], m.edge_opp[e, 1]
+    common = m.has_edge(x, b) & (x != b)
+    nontrivial = common & (x != o0) & (x != o1)
+    e, x, o0, o1 = e[nontrivial], x[nontrivial], o0[nontrivial], o1[nontrivial]
+    close = lengths(xy, x, o0) < eps
+    has1 = o1 >= 0
+    close[has1] |= lengths(xy, x[has1], o1[has1]) < eps
+    ok = np.ones(m.n_edges, dtype=bool)
+    ok[e[~close]] = False
+    return ok
+
+
+def contractible(m: Mesh, xy, eps) -> np.ndarray:
+    return direct_contractible(m) & one_hop_contractible(m, xy, eps)
+
+
+def c_eps(length, contr, eps):
+    """Contraction weight (Sec. 2.2.1)."""
+    return np.where(contr, 0.5 + 0.5 * np.minimum(1.0, length / eps), 1.0)
+
+
+def merge_correction(x):
+    """M (Sec. 2.2.1): 0 below 1/4, 4x - 1 on [1/4, 1/2], 1 above."""
+    return np.where(x < 0.25, 0.0, np.where(x <= 0.5, 4.0 * x - 1.0, 1.0))
+
+
+def edge_weight(m: Mesh, c):
+    x = c[m.edge_nbr[:, 0]] * c[m.edge_nbr[:, 1]]
+    two = m.edge_nbr[:, 2] >= 0
+    x[two] = x[two] * c[m.edge_nbr[two, 2]]
+    x[two] = x[two] * c[m.edge_nbr[two, 3]]
+    return x * merge_correction(x)
+
+
+def angle_terms(m: Mesh, xy, p: Params):
+    """(T, 3) penalty of corner i (at v[i]) of every triangle (Sec. 2.2.3)."""
+    out = np.zeros(m.tri_v.shape, dtype=np.float64)
+    for i in range(3):
+        o, u, w = m.tri_v[:, i], m.tri_v[:, (i + 1) % 3], m.tri_v[:, (i + 2) % 3]
+        ux, uy = xy[u, 0] - xy[o, 0], xy[u, 1] - xy[o, 1]
+        wx, wy = xy[w, 0] - xy[o, 0], xy[w, 1] - xy[o, 1]
+        lu = np.sqrt(ux * ux + uy * uy)
+        lw = np.sqrt(wx * wx + wy * wy)
+        den = lu * lw
+        ok = den > 0
+        cos = np.zeros_like(den)
+        cos[ok] = (ux[ok] * wx[ok] + uy[ok] * wy[ok]) / den[ok]
+        if p.polish:
+            t = np.maximum(0.0, cos - (1.0 - p.delta)) / p.delta
+        else:
+            t = np.maximum(0.0, (-1.0 + p.delta) - cos) / p.delta
+        out[:, i] = np.where(ok, t, 0.0)
+    return out
+
+
+def terms(m: Mesh, xy, p: Params) -> dict:
+    """Every term of f, separately."""
+    xy = np.asarray(xy, dtype=np.float64)
+    ln = lengths(xy, m.edge_v[:, 0], m.edge_v[:, 1])
+    contr = contractible(m, xy, p.eps)
+    c = c_eps(ln, contr, p.eps)
+    w = np.ones(m.n_edges) if p.polish else edge_weight(m, c)
+    return {"length": ln, "contractible": contr, "c": c, "w": w, "edge": w * ln,
+            "angle": angle_terms(m, xy, p), "short": np.maximum(0.0, p.eps0 - ln) / p.eps0}
+
+
+def objective(m: Mesh, xy, p: Params) -> dict:
+    """f and its parts (Sec. 2.2.4), with the per-edge values."""
+    t = terms(m, xy, p)
+    wc, pa, pl = t["edge"].sum(), t["angle"].sum(), t["short"].sum()
+    t.update(wcontr=wc, pangle=pa, plen=pl, f=wc + p.mu_angle * pa + p.mu_len * pl)
+    return t
+
+
+MOVED, FOLDED, FIXED, BAD = 1, 0, -1, -2
+
+
+def move_status(m: Mesh, xy, v, q) -> int:
+    """1: valid move; 0: some triangle of v would not stay strictly counter-clockwise (exact);
+    -1: v is an original vertex (not movable); -2: v out of range or q not finite."""
+    if not (0 <= v < m.nv) or not np.isfinite(q).all():
+        return BAD
+    if m.kind[v] == ORIGINAL:
+        return FIXED
+    moved = xy.copy()
+    moved[v] = q
+    for t in np.nonzero((m.tri_v == v).any(axis=1))[0]:
+        a, b, c = (moved[k] for k in m.tri_v[t])
+        if orient(a, b, c) <= 0:
+            return FOLDED
+    return MOVED
+
+
+def delta_f(m: Mesh, xy, p: Params, v, q) -> tuple[int, float, float]:
+    """(status, delta_f, bound) of moving vertex v to q. delta_f is +inf unless the move is valid;
+    bound is the sum of the absolute term differences (the scale of delta_f's rounding)."""
+    xy = np.asarray(xy, dtype=np.float64)
+    st = move_status(m, xy, int(v), np.asarray(q, dtype=np.float64))
+    if st != MOVED:
+        return st, float("inf"), 0.0
+    moved = xy.copy()
+    moved[v] = q
+    t0, t1 = terms(m, xy, p), terms(m, moved, p)
+    de = t1["edge"] - t0["edge"]
+    da = (t1["angle"] - t0["angle"]).ravel()
+    ds = t1["short"] - t0["short"]
+    df = de.sum() + p.mu_angle * da.sum() + p.mu_len * ds.sum()
+    bound = np.abs(de).sum() + p.mu_angle * np.abs(da).sum() + p.mu_len * np.abs(ds).sum()
+    return st, float(df), float(bound)

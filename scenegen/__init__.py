@@ -87,7 +87,7 @@ def _err(msg):
 
 # Per-purpose seed tags: every draw stream is derived from (seed, tag), so the scene, the rays
 # and any later stream of the same workload never share random numbers.
-TAG_SCENE, TAG_RAYS, TAG_ANNEAL, TAG_CHOICE = 1, 2, 3, 4
+TAG_SCENE, TAG_RAYS, TAG_ANNEAL, TAG_CHOICE, TAG_MOVES = 1, 2, 3, 4, 5
 
 
 def subseed(seed: int, tag: int, index: int = 0) -> int:
@@ -157,6 +157,94 @@ def split_segments(sc: Scene) -> Scene:
     meta = dict(sc.meta, seg_prim=np.repeat(np.arange(S, dtype=np.int32), 2))
     return Scene(np.ascontiguousarray(xy), sc.prims, np.ascontiguousarray(seg_v), sc.box,
                  name=sc.name + "+split", meta=meta)
+
+
+ORIGINAL, CONSTRAINED, FREE = 0, 1, 2
+
+
+@dataclass
+class MovableMesh:
+    """A triangulation with Steiner vertices, the input of the low-weight objective: vertex
+    positions, counter-clockwise triangles, each vertex's kind (ORIGINAL, CONSTRAINED to original
+    edge line[v], or FREE) and the two original vertices ending each original edge (prim_v)."""
+
+    xy: np.ndarray       # (V,2) float64
+    tri_v: np.ndarray    # (T,3) int32
+    kind: np.ndarray     # (V,) int32
+    line: np.ndarray     # (V,) int32, -1 unless CONSTRAINED
+    prim_v: np.ndarray   # (P,2) int32
+    name: str = ""
+
+    @property
+    def n_vertices(self):
+        return int(self.xy.shape[0])
+
+    @property
+    def n_triangles(self):
+        return int(self.tri_v.shape[0])
+
+
+def subdivide(sc: Scene) -> MovableMesh:
+    """Input for the objective: the triangulation with every triangle split into four at its edge
+    midpoints (the subdivision of Sec. 3.5.2). Scene vertices are ORIGINAL; the midpoint of a
+    constrained edge is CONSTRAINED to that edge's primitive, other midpoints are FREE. Triangles
+    that rounding of a midpoint would leave not strictly counter-clockwise are reported."""
+    if "seg_prim" in sc.meta:
+        raise ValueError("subdivide expects one constrained edge chain per segment, unsplit")
+    V, T = sc.n_vertices, sc.n_triangles
+    tv = sc.tri_v.astype(np.int64)
+    a, b = tv[:, [1, 2, 0]], tv[:, [2, 0, 1]]
+    key = np.minimum(a, b) * V + np.maximum(a, b)
+    uniq, inv = np.unique(key.ravel(), return_inverse=True)
+    inv = inv.reshape(T, 3)
+    ea, eb = uniq // V, uniq % V
+    E = uniq.shape[0]
+    mid = 0.5 * (sc.xy[ea] + sc.xy[eb])
+    prim = np.full(E, -1, dtype=np.int64)
+    tp = sc.tri_prim.astype(np.int64)
+    prim[inv[tp >= 0]] = tp[tp >= 0]
+    m = V + inv  # m[:, i] is the midpoint of edge i (opposite v[i])
+    tri = np.concatenate([np.stack([tv[:, 0], m[:, 2], m[:, 1]], 1),
+                          np.stack([tv[:, 1], m[:, 0], m[:, 2]], 1),
+                          np.stack([tv[:, 2], m[:, 1], m[:, 0]], 1),
+                          np.stack([m[:, 0], m[:, 1], m[:, 2]], 1)]).astype(np.int32)
+    xy = np.ascontiguousarray(np.concatenate([sc.xy, mid]))
+    kind = np.concatenate([np.full(V, ORIGINAL), np.where(prim >= 0, CONSTRAINED, FREE)])
+    line = np.concatenate([np.full(V, -1), prim])
+    S = sc.seg_v.shape[0]
+    prim_v = np.concatenate([sc.seg_v, [[0, 1], [1, 2], [2, 3], [3, 0]]]).astype(np.int32)
+    if prim_v.shape[0] != sc.n_prims:
+        raise ValueError("scene primitives are not its segments plus four box sides")
+    bad = exact_orient(np.concatenate([xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]], 1)) <= 0
+    if bad.any():
+        raise ValueError(f"{int(bad.sum())} subdivided triangles are not strictly counter-clockwise")
+    return MovableMesh(xy, np.ascontiguousarray(tri), kind.astype(np.int32),
+                       line.astype(np.int32), prim_v, name=sc.name + "/4")
+
+
+def vertex_moves(mesh: MovableMesh, n: int, seed: int, lam: float) -> tuple:
+    """n proposed single-vertex moves (vertex ids, new positions) drawn as in Sec. 3.2.2: a movable
+    vertex chosen uniformly; a displacement lam * eta * xi, where xi is a point uniform in the unit
+    disk with its radius scaled by a Pareto(1/2) draw (x >= 1) and eta is the square root of the
+    area of the vertex's triangles; projected on the original edge for constrained vertices."""
+    rng = np.random.default_rng(subseed(seed, TAG_MOVES))
+    movable = np.nonzero(mesh.kind != ORIGINAL)[0]
+    v = movable[rng.integers(0, movable.shape[0], n)]
+    u = rng.random((n, 3))
+    r = np.sqrt(u[:, 0]) * (1.0 - u[:, 2]) ** -2.0
+    th = 2.0 * np.pi * u[:, 1]
+    p = mesh.xy[mesh.tri_v]
+    area = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+                  - (p[:, 1, 1] - p[:, 0, 1]) * (p[:, 2, 0] - p[:, 0, 0]))
+    star = np.bincount(mesh.tri_v.ravel(), weights=np.repeat(area, 3), minlength=mesh.n_vertices)
+    d = (lam * np.sqrt(star[v]) * r)[:, None] * np.stack([np.cos(th), np.sin(th)], 1)
+    con = mesh.kind[v] == CONSTRAINED
+    if con.any():
+        ends = mesh.prim_v[mesh.line[v[con]]]
+        e = mesh.xy[ends[:, 1]] - mesh.xy[ends[:, 0]]
+        k = (d[con] * e).sum(1) / (e * e).sum(1)
+        d[con] = k[:, None] * e
+    return v.astype(np.int32), np.ascontiguousarray(mesh.xy[v] + d)
 
 
 def random_segments(seed, n, mid_lo, mid_hi, len_lo, len_hi, log_len, box_lo, box_hi,
