@@ -1,0 +1,126 @@
+/*
+ * ccsp_objective: the low-weight objective with fuzzy contraction, and its change under
+ * single-vertex moves, on AMD Instinct MI355X (Frederickx & Dutre, arXiv 2112.05570, Sec. 2.2 for
+ * the objective; Sec. 3.2.1 and 3.2.2 for the local updates that simulated annealing samples).
+ *
+ * A movable mesh is a triangulation whose vertices have a kind: ORIGINAL (a vertex of the scene
+ * geometry, fixed), CONSTRAINED (a Steiner vertex on original edge line[v], which moves along it)
+ * or FREE (a Steiner vertex with two degrees of freedom). Positions are not part of the mesh: every
+ * call takes the current positions, so a caller may move vertices between calls.
+ *
+ * For positions p and parameters (eps, delta, eps0, mu_angle, mu_len), all in binary64:
+ *   |e|        = sqrt(dx*dx + dy*dy) for edge e = (a, b), a < b, dx = p[b].x - p[a].x, dy likewise;
+ *   c(e)       = 0.5 + 0.5 * min(1, |e| / eps) if e is contractible, else 1            (Sec. 2.2.1)
+ *   x(e)       = the product of c over the other edges of the one or two triangles holding e,
+ *                taken in increasing triangle id, each triangle's two edges in its local order
+ *                after e, multiplied left to right;
+ *   w(e)       = x * M(x), with M(x) = 0 if x < 1/4, 4x - 1 if x <= 1/2, else 1. The equation of
+ *                Sec. 2.2.1 writes M(x); its worked example (a merged pair weighs 1/2, an edge with
+ *                two contracted neighbours 0) fixes the product x * M(x). In polishing, w(e) = 1;
+ *   w_contr    = sum over edges of w(e) * |e|;
+ *   P_angle    = sum over the three corners of every triangle of max(0, (-1 + delta) - cos)/delta,
+ *                cos = (u.x*w.x + u.y*w.y) / (|u| * |w|) for the corner's edge vectors u, w; a
+ *                corner with a zero-length edge adds 0. In polishing, max(0, cos - (1 - delta))/delta
+ *                (Sec. 2.2.3);
+ *   P_len      = sum over edges of max(0, eps0 - |e|) / eps0                               (Sec. 2.2.3)
+ *   f          = w_contr + mu_angle * P_angle + mu_len * P_len                             (Sec. 2.2.4)
+ * An edge is contractible (Sec. 2.2.2) unless
+ *   - both ends are ORIGINAL; or one end is ORIGINAL and the other CONSTRAINED to an original edge
+ *     that does not end at it; or both are CONSTRAINED to different original edges; or
+ *   - the 1-hop rule: a common neighbour H of its ends that is not one of its opposite vertices
+ *     lies at distance >= eps from every opposite vertex (distances computed as |e| above).
+ * The conditioning and flat-triangle restrictions of Sec. 2.2.2 are not applied.
+ * Edges are numbered by (lower vertex id, higher vertex id); mesh_info returns them.
+ *
+ * Errors are the CCSP_* codes of ccsp_walk.h, with last_error() describing the failure.
+ * Scratch: a mesh owns per-edge scratch that its calls share, so calls on one mesh must be
+ * ordered (issue them on one stream, or synchronise between streams). Different meshes are
+ * independent.
+ */
+#ifndef CCSP_OBJECTIVE_H
+#define CCSP_OBJECTIVE_H
+
+#include <stdint.h>
+
+#include "ccsp_walk.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { CCSP_VERTEX_ORIGINAL = 0, CCSP_VERTEX_CONSTRAINED = 1, CCSP_VERTEX_FREE = 2 };
+
+/* Per-move status of objective_delta. */
+enum {
+  CCSP_MOVE_OK = 1,     /* valid: every triangle of the vertex stays strictly counter-clockwise */
+  CCSP_MOVE_FOLDS = 0,  /* some triangle of the vertex would not (decided exactly); delta = +inf */
+  CCSP_MOVE_FIXED = -1, /* the vertex is ORIGINAL; delta = +inf */
+  CCSP_MOVE_BAD = -2    /* vertex id out of range or a coordinate not finite; delta = +inf */
+};
+
+typedef struct MovableMesh MovableMesh; /* opaque; owns device memory */
+
+/* HOST pointers, read during mesh_load only. */
+typedef struct {
+  int64_t n_vertices;
+  const int32_t *kind;   /* n_vertices: CCSP_VERTEX_* */
+  const int32_t *line;   /* n_vertices: for CONSTRAINED vertices the original edge (index into
+                            prim_v), ignored for the others */
+  int64_t n_triangles;
+  const int32_t *tri_v;  /* 3 * n_triangles vertex ids, counter-clockwise */
+  int64_t n_prims;
+  const int32_t *prim_v; /* 2 * n_prims: the two ORIGINAL vertices ending each original edge */
+} MeshDesc;
+
+typedef struct {
+  double eps;      /* contraction length, > 0 */
+  double delta;    /* angle-cosine threshold, > 0 (the paper uses cos(179 deg) + 1) */
+  double eps0;     /* minimum edge length of the length penalty, > 0 */
+  double mu_angle; /* weight of P_angle */
+  double mu_len;   /* weight of P_len */
+  int32_t polish;  /* nonzero: fixed topology (w = 1, sharp-corner penalty) */
+  int32_t reserved;/* must be 0 */
+} ObjectiveParams;
+
+/*
+ * mesh_load: build the mesh's edges, adjacency and scratch on the current device. Fails with
+ * CCSP_E_BAD_TRIANGULATION when an id is out of range, a triangle repeats a vertex, a kind is
+ * unknown, a CONSTRAINED vertex names no original edge, an edge lies in more than two triangles,
+ * or two triangles run through their shared edge in the same direction. Synchronous.
+ */
+int mesh_load(const MeshDesc *desc, MovableMesh **out);
+
+/* mesh_info: number of edges, and (if edge_v is not NULL) their ends, 2 * n_edges HOST int32. */
+int mesh_info(const MovableMesh *mesh, int64_t *n_edges, int32_t *edge_v);
+
+/*
+ * objective_eval: f and its parts at positions xy (DEVICE, 2 * n_vertices binary64, 16-byte
+ * aligned). out (DEVICE, 4 binary64) receives f, w_contr, P_angle, P_len. If not NULL,
+ * contractible (DEVICE, n_edges bytes, 1 = contractible) and weight (DEVICE, n_edges binary64,
+ * w(e)) receive the per-edge values. Sums are reduced in a fixed order: the result is
+ * reproducible for a mesh. Every triangle is expected to be counter-clockwise at xy (not checked).
+ * Asynchronous on `stream`.
+ */
+int objective_eval(MovableMesh *mesh, const double *xy, const ObjectiveParams *params,
+                   double *out, uint8_t *contractible, double *weight, void *stream);
+
+/*
+ * objective_delta: for k proposed moves, vertex vid[i] (DEVICE int32) to q_xy[2i..2i+1] (DEVICE
+ * binary64, 16-byte aligned), each against the positions xy as they are (the moves are independent
+ * alternatives, not applied): delta[i] = f(xy with the vertex moved) - f(xy) (DEVICE binary64),
+ * the sum of the differences of every term of f that the move changes, and status[i] (DEVICE
+ * int32, CCSP_MOVE_*). A constrained vertex's new position is taken as given (the caller projects
+ * it on its original edge). Asynchronous on `stream`; overwrites the mesh's scratch.
+ */
+int objective_delta(MovableMesh *mesh, const double *xy, const ObjectiveParams *params,
+                    const int32_t *vid, const double *q_xy, int64_t k, double *delta,
+                    int32_t *status, void *stream);
+
+/* mesh_free: release the mesh (after its calls have completed). NULL is ignored. */
+void mesh_free(MovableMesh *mesh);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -243,16 +243,18 @@ def move_status(m: Mesh, xy, v, q) -> int:
     return MOVED
 
 
-def delta_f(m: Mesh, xy, p: Params, v, q) -> tuple[int, float, float]:
+def delta_f(m: Mesh, xy, p: Params, v, q, base: dict | None = None) -> tuple[int, float, float]:
     """(status, delta_f, bound) of moving vertex v to q. delta_f is +inf unless the move is valid;
-    bound is the sum of the absolute term differences (the scale of delta_f's rounding)."""
+    bound is the sum of the absolute term differences (the scale of delta_f's rounding). base may
+    hold terms(m, xy, p), computed once for several moves from the same positions."""
     xy = np.asarray(xy, dtype=np.float64)
     st = move_status(m, xy, int(v), np.asarray(q, dtype=np.float64))
     if st != MOVED:
         return st, float("inf"), 0.0
     moved = xy.copy()
     moved[v] = q
-    t0, t1 = terms(m, xy, p), terms(m, moved, p)
+    t0 = base if base is not None else terms(m, xy, p)
+    t1 = terms(m, moved, p)
     de = t1["edge"] - t0["edge"]
     da = (t1["angle"] - t0["angle"]).ravel()
     ds = t1["short"] - t0["short"]

@@ -204,6 +204,99 @@ def locate(scene: Scene, q, stream=None):
     return tri, status
 
 
+class MovableMesh:
+    """A triangulation with movable Steiner vertices for the low-weight objective (see
+    ``mesh_load`` in ccsp_objective.h). Built from host arrays: tri_v (T,3) counter-clockwise,
+    kind (V,) 0 original / 1 constrained / 2 free, line (V,) original edge of constrained
+    vertices, prim_v (P,2) ends of each original edge. Positions are passed per call."""
+
+    def __init__(self, tri_v, kind, line, prim_v):
+        tri_v = np.ascontiguousarray(tri_v, dtype=np.int32)
+        kind = np.ascontiguousarray(kind, dtype=np.int32)
+        line = np.ascontiguousarray(line, dtype=np.int32)
+        prim_v = np.ascontiguousarray(prim_v, dtype=np.int32).reshape(-1, 2)
+        if tri_v.ndim != 2 or tri_v.shape[1] != 3 or kind.shape != line.shape or kind.ndim != 1:
+            raise ValueError("tri_v must be (T,3); kind and line (V,)")
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
+        d = B.MeshDesc(kind.shape[0], p(kind), p(line), tri_v.shape[0], p(tri_v), prim_v.shape[0],
+                       p(prim_v))
+        self.handle = None
+        self.handle = B.mesh_load(d)
+        self.n_vertices = int(kind.shape[0])
+        self.n_triangles = int(tri_v.shape[0])
+        self.n_edges = B.mesh_info(self.handle)
+
+    @classmethod
+    def from_mesh(cls, mesh):
+        return cls(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+
+    def edges(self):
+        out = np.empty((self.n_edges, 2), dtype=np.int32)
+        B.mesh_info(self.handle, out.ctypes.data_as(ctypes.c_void_p).value)
+        return out
+
+    def _xy(self, xy):
+        import torch
+        if (not xy.is_cuda or xy.dtype != torch.float64 or tuple(xy.shape) != (self.n_vertices, 2)
+                or not xy.is_contiguous()):
+            raise ValueError("xy must be a contiguous float64 CUDA tensor of shape (V, 2)")
+        return xy.data_ptr()
+
+    def eval(self, xy, params, per_edge=False, stream=None):
+        """f, w_contr, P_angle, P_len (a float64 CUDA tensor of 4) and, with per_edge, the
+        contractible flags and weights of the edges. Asynchronous."""
+        import torch
+        out = torch.empty(4, dtype=torch.float64, device=xy.device)
+        con = w = None
+        if per_edge:
+            con = torch.empty(self.n_edges, dtype=torch.uint8, device=xy.device)
+            w = torch.empty(self.n_edges, dtype=torch.float64, device=xy.device)
+        B.objective_eval(self.handle, self._xy(xy), params, out.data_ptr(),
+                         con.data_ptr() if per_edge else 0, w.data_ptr() if per_edge else 0,
+                         _stream(stream))
+        return (out, con, w) if per_edge else out
+
+    def delta(self, xy, params, vid, q, stream=None):
+        """Change of f and status of each proposed move of vertex vid[i] to q[i] (int32 and
+        (k,2) float64 CUDA tensors), each against xy. Asynchronous."""
+        import torch
+        k = vid.shape[0]
+        if (not vid.is_cuda or vid.dtype != torch.int32 or not vid.is_contiguous() or not q.is_cuda
+                or q.dtype != torch.float64 or tuple(q.shape) != (k, 2) or not q.is_contiguous()):
+            raise ValueError("vid must be int32 (k,) and q float64 (k,2), contiguous CUDA tensors")
+        d = torch.empty(k, dtype=torch.float64, device=xy.device)
+        st = torch.empty(k, dtype=torch.int32, device=xy.device)
+        B.objective_delta(self.handle, self._xy(xy), params, vid.data_ptr(), q.data_ptr(), k,
+                          d.data_ptr(), st.data_ptr(), _stream(stream))
+        return d, st
+
+    def close(self):
+        if self.handle:
+            B.mesh_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def objective_params(eps, delta=None, eps0=1e-10, mu_angle=1.0, mu_len=10.0, polish=False):
+    """Parameters of the objective (defaults: delta = cos(179 deg) + 1, the paper's eps0 and
+    weights for a scene normalised to the unit square)."""
+    import math
+    if delta is None:
+        delta = math.cos(math.radians(179.0)) + 1.0
+    return B.ObjectiveParams(eps, delta, eps0, mu_angle, mu_len, int(bool(polish)), 0)
+
+
 def read_counters(reset=False):
     """(steps, binary32 deferrals, binary64 deferrals, rays) since the last reset."""
     return B.read_counters(reset)

@@ -45,7 +45,8 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "free_triangulation", "last_error", "read_counters", "triangulation_info",
            "reserve_workspace", "gather_roofline", "read_stage_times", "autotune",
            "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
-           "server_stats", "server_destroy", "locate_points", "trace_bounces")
+           "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
+           "mesh_info", "objective_eval", "objective_delta", "mesh_free")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -132,6 +133,31 @@ _lib.server_stats.argtypes = [_P, ctypes.POINTER(ctypes.c_int64 * 8)]
 _lib.server_stats.restype = _I
 _lib.server_destroy.argtypes = [_P]
 _lib.server_destroy.restype = None
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("kind", ctypes.c_void_p),
+                ("line", ctypes.c_void_p), ("n_triangles", ctypes.c_int64),
+                ("tri_v", ctypes.c_void_p), ("n_prims", ctypes.c_int64),
+                ("prim_v", ctypes.c_void_p)]
+
+
+class ObjectiveParams(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("delta", ctypes.c_double), ("eps0", ctypes.c_double),
+                ("mu_angle", ctypes.c_double), ("mu_len", ctypes.c_double),
+                ("polish", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib.mesh_load.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(_P)]
+_lib.mesh_load.restype = _I
+_lib.mesh_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), _P]
+_lib.mesh_info.restype = _I
+_lib.objective_eval.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), _P, _P, _P, _P]
+_lib.objective_eval.restype = _I
+_lib.objective_delta.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), _P, _P, _I64, _P, _P, _P]
+_lib.objective_delta.restype = _I
+_lib.mesh_free.argtypes = [_P]
+_lib.mesh_free.restype = None
 
 
 class CcspError(RuntimeError):
@@ -232,6 +258,34 @@ def trace_bounces(tri: int, o_xy: int, d_xy: int, start_tri: int, n: int, max_bo
 
 def locate_points(tri: int, q_xy: int, n: int, tri_out: int, status: int, stream: int = 0) -> None:
     _check(_lib.locate_points(_P(tri), _P(q_xy), n, _P(tri_out), _P(status), _P(stream)))
+
+
+def mesh_load(desc: MeshDesc) -> int:
+    h = _P()
+    _check(_lib.mesh_load(ctypes.byref(desc), ctypes.byref(h)))
+    return h.value
+
+
+def mesh_info(mesh: int, edge_v: int = 0) -> int:
+    n = ctypes.c_int64()
+    _check(_lib.mesh_info(_P(mesh), ctypes.byref(n), _P(edge_v)))
+    return n.value
+
+
+def objective_eval(mesh: int, xy: int, params: ObjectiveParams, out: int, contractible: int = 0,
+                   weight: int = 0, stream: int = 0) -> None:
+    _check(_lib.objective_eval(_P(mesh), _P(xy), ctypes.byref(params), _P(out), _P(contractible),
+                               _P(weight), _P(stream)))
+
+
+def objective_delta(mesh: int, xy: int, params: ObjectiveParams, vid: int, q_xy: int, k: int,
+                    delta: int, status: int, stream: int = 0) -> None:
+    _check(_lib.objective_delta(_P(mesh), _P(xy), ctypes.byref(params), _P(vid), _P(q_xy), k,
+                                _P(delta), _P(status), _P(stream)))
+
+
+def mesh_free(mesh: int) -> None:
+    _lib.mesh_free(_P(mesh))
 
 
 def server_create(cfg: ServerConfig | None) -> int:

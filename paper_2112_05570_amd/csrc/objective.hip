@@ -1,0 +1,673 @@
+// The low-weight objective with fuzzy contraction (paper Sec. 2.2) and its change under
+// single-vertex moves (Sec. 3.2.1), on the GPU: mesh construction, kernels and the C-ABI of
+// ccsp_objective.h.
+//
+// Evaluation is two passes over edges and triangles. The first computes every edge's length,
+// contractibility and contraction weight c(e) (and the length penalty). The second forms each
+// edge's weight from the c of its neighbouring edges, and the angle penalty of every triangle.
+// Both write one partial sum per workgroup, reduced in a fixed order by a last one-workgroup
+// kernel, so results are reproducible.
+//
+// A move changes only terms near its vertex v. With N(v) the neighbours of v, the edges whose c
+// can change ("C-edges") are those incident to v (length) and those joining two vertices of N(v)
+// (v may be an opposite vertex or a 1-hop vertex of such an edge). The edges whose weight can
+// change are the C-edges and the other edges of the triangles holding a C-edge. One thread per
+// move visits each of these edges once, using the canonical choice of the triangle that reports
+// it, and sums new minus old terms; the angle terms of the triangles of v and the length terms of
+// its edges are added in the same way. Every term uses the same operations, in the same order, as
+// the evaluation, so a move back gives exactly the opposite term differences.
+//
+// Compiled with -ffp-contract=off: every binary64 expression is evaluated as written.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ccsp_objective.h"
+#include "exact.hpp"
+#include "walk.hpp"
+
+struct MovableMesh;
+
+namespace ccsp {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct MeshDev {
+  int32_t nv, nt, ne, np;
+  const int2* edge_v;     // (a, b), a < b
+  const int4* edge_nbr;   // neighbouring edges in product order; -1 pads the last two
+  const int2* edge_opp;   // opposite vertex in each triangle of the edge; -1 pad
+  const int2* edge_tri;   // triangles of the edge, increasing; -1 pad
+  const int4* tri;        // vertices (x, y, z)
+  const int4* tri_edge;   // local edges (x, y, z): edge i is opposite vertex i
+  const int32_t* adj_off; // neighbours of each vertex, increasing, with the joining edge
+  const int2* adj;
+  const int32_t* vtri_off;  // triangles of each vertex, increasing
+  const int32_t* vtri;
+  const int2* vk;         // (kind, line)
+  const int2* prim_v;
+  double* c;              // scratch: contraction weight, length, contractibility per edge
+  double* len;
+  uint8_t* contr;
+  double* partial;
+};
+
+struct Par {
+  double eps, delta, eps0, mu_angle, mu_len;
+  int polish;
+};
+
+__device__ __forceinline__ double2 pos(const double2* __restrict__ xy, int u, int mv, double2 q) {
+  return u == mv ? q : xy[u];
+}
+
+__device__ __forceinline__ double dist(double2 a, double2 b) {
+  const double dx = b.x - a.x, dy = b.y - a.y;
+  return sqrt(dx * dx + dy * dy);
+}
+
+__device__ __forceinline__ double c_of_len(bool contractible, double len, double eps) {
+  return contractible ? 0.5 + 0.5 * fmin(1.0, len / eps) : 1.0;
+}
+
+__device__ __forceinline__ double merged_weight(double x) {
+  const double m = x < 0.25 ? 0.0 : (x <= 0.5 ? 4.0 * x - 1.0 : 1.0);
+  return x * m;
+}
+
+__device__ __forceinline__ double short_term(double len, double eps0) {
+  return fmax(0.0, eps0 - len) / eps0;
+}
+
+__device__ double corner_term(double2 o, double2 u, double2 w, double delta, int polish) {
+  const double ux = u.x - o.x, uy = u.y - o.y, wx = w.x - o.x, wy = w.y - o.y;
+  const double lu = sqrt(ux * ux + uy * uy), lw = sqrt(wx * wx + wy * wy);
+  const double den = lu * lw;
+  if (!(den > 0.0)) return 0.0;
+  const double cs = (ux * wx + uy * wy) / den;
+  return polish ? fmax(0.0, cs - (1.0 - delta)) / delta : fmax(0.0, (-1.0 + delta) - cs) / delta;
+}
+
+__device__ double triangle_angles(const double2* __restrict__ xy, int4 t, int mv, double2 q,
+                                  double delta, int polish) {
+  const double2 a = pos(xy, t.x, mv, q), b = pos(xy, t.y, mv, q), c = pos(xy, t.z, mv, q);
+  double s = corner_term(a, b, c, delta, polish);
+  s += corner_term(b, c, a, delta, polish);
+  s += corner_term(c, a, b, delta, polish);
+  return s;
+}
+
+// Exact sign of the orientation of (a, b, c): binary64 filter, then the exact expansion.
+__device__ __forceinline__ int orient_sign(double2 a, double2 b, double2 c) {
+  const double l = (b.x - a.x) * (c.y - a.y);
+  const double r = (b.y - a.y) * (c.x - a.x);
+  const double det = l - r, sum = fabs(l) + fabs(r);
+  if (fabs(det) > 0x1p-51 * sum && sum > 0x1p-900) return det > 0 ? 1 : -1;
+  return orient_exact(a.x, a.y, b.x, b.y, c.x, c.y);
+}
+
+__device__ bool is_neighbour(const MeshDev& m, int v, int x) {
+  int lo = m.adj_off[v], hi = m.adj_off[v + 1];
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int y = m.adj[mid].x;
+    if (y == x) return true;
+    if (y < x) lo = mid + 1; else hi = mid;
+  }
+  return false;
+}
+
+// Restrictions of the original geometry (Sec. 2.2.2).
+__device__ bool direct_ok(const MeshDev& m, int a, int b) {
+  const int2 ka = m.vk[a], kb = m.vk[b];
+  if (ka.x == CCSP_VERTEX_ORIGINAL && kb.x == CCSP_VERTEX_ORIGINAL) return false;
+  if (ka.x == CCSP_VERTEX_ORIGINAL && kb.x == CCSP_VERTEX_CONSTRAINED) {
+    const int2 e = m.prim_v[kb.y];
+    return e.x == a || e.y == a;
+  }
+  if (kb.x == CCSP_VERTEX_ORIGINAL && ka.x == CCSP_VERTEX_CONSTRAINED) {
+    const int2 e = m.prim_v[ka.y];
+    return e.x == b || e.y == b;
+  }
+  if (ka.x == CCSP_VERTEX_CONSTRAINED && kb.x == CCSP_VERTEX_CONSTRAINED) return ka.y == kb.y;
+  return true;
+}
+
+// 1-hop rule (Sec. 2.2.2), with vertex mv at q.
+__device__ bool one_hop_ok(const MeshDev& m, const double2* __restrict__ xy, int a, int b,
+                           int2 opp, double eps, int mv, double2 q) {
+  for (int j = m.adj_off[a], end = m.adj_off[a + 1]; j < end; ++j) {
+    const int x = m.adj[j].x;
+    if (x == b || x == opp.x || x == opp.y || !is_neighbour(m, b, x)) continue;
+    const double2 px = pos(xy, x, mv, q);
+    bool close = dist(px, pos(xy, opp.x, mv, q)) < eps;
+    if (!close && opp.y >= 0) close = dist(px, pos(xy, opp.y, mv, q)) < eps;
+    if (!close) return false;
+  }
+  return true;
+}
+
+__device__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Pass 1: length, contractibility and c of every edge; length-penalty partial sums.
+__global__ void __launch_bounds__(kThreads)
+edge_state(MeshDev m, const double2* __restrict__ xy, Par p, double* __restrict__ part) {
+  __shared__ double sh[kThreads];
+  const int e = blockIdx.x * kThreads + threadIdx.x;
+  double s = 0.0;
+  if (e < m.ne) {
+    const int2 ab = m.edge_v[e];
+    const double len = dist(xy[ab.x], xy[ab.y]);
+    const bool ok = direct_ok(m, ab.x, ab.y) &&
+                    one_hop_ok(m, xy, ab.x, ab.y, m.edge_opp[e], p.eps, -1, make_double2(0, 0));
+    m.len[e] = len;
+    m.contr[e] = ok ? 1 : 0;
+    m.c[e] = c_of_len(ok, len, p.eps);
+    s = short_term(len, p.eps0);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__device__ __forceinline__ double weight_from(const double* __restrict__ c, int4 n) {
+  double x = c[n.x] * c[n.y];
+  if (n.z >= 0) {
+    x = x * c[n.z];
+    x = x * c[n.w];
+  }
+  return merged_weight(x);
+}
+
+// Pass 2: weighted edge lengths and triangle angle penalties, partial sums of each.
+__global__ void __launch_bounds__(kThreads)
+terms_pass(MeshDev m, const double2* __restrict__ xy, Par p, double* __restrict__ part_edge,
+           double* __restrict__ part_angle, uint8_t* __restrict__ contr_out,
+           double* __restrict__ w_out) {
+  __shared__ double sh[kThreads];
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  double se = 0.0, sa = 0.0;
+  if (i < m.ne) {
+    const double w = p.polish ? 1.0 : weight_from(m.c, m.edge_nbr[i]);
+    se = w * m.len[i];
+    if (w_out) w_out[i] = w;
+    if (contr_out) contr_out[i] = m.contr[i];
+  }
+  if (i < m.nt) sa = triangle_angles(xy, m.tri[i], -1, make_double2(0, 0), p.delta, p.polish);
+  se = block_sum(se, sh);
+  sa = block_sum(sa, sh);
+  if (threadIdx.x == 0) {
+    part_edge[blockIdx.x] = se;
+    part_angle[blockIdx.x] = sa;
+  }
+}
+
+__device__ double sum_fixed(const double* __restrict__ v, int n, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) s += v[i];
+  return block_sum(s, sh);
+}
+
+__global__ void __launch_bounds__(kThreads)
+finish_sums(const double* __restrict__ part, int n1, int n2, Par p, double* __restrict__ out) {
+  __shared__ double sh[kThreads];
+  const double pl = sum_fixed(part, n1, sh);
+  const double wc = sum_fixed(part + n1, n2, sh);
+  const double pa = sum_fixed(part + n1 + n2, n2, sh);
+  if (threadIdx.x == 0) {
+    out[0] = wc + p.mu_angle * pa + p.mu_len * pl;
+    out[1] = wc;
+    out[2] = pa;
+    out[3] = pl;
+  }
+}
+
+// ---- moves ----
+
+struct MoveCtx {
+  MeshDev m;
+  const double2* __restrict__ xy;
+  Par p;
+  int v;
+  double2 q;
+
+  __device__ bool in_c(int e) const {
+    const int2 ab = m.edge_v[e];
+    if (ab.x == v || ab.y == v) return true;
+    return is_neighbour(m, v, ab.x) && is_neighbour(m, v, ab.y);
+  }
+  __device__ double len(int e, bool moved) const {
+    const int2 ab = m.edge_v[e];
+    if (!moved || (ab.x != v && ab.y != v)) return m.len[e];
+    return dist(pos(xy, ab.x, v, q), pos(xy, ab.y, v, q));
+  }
+  __device__ double c(int e, bool moved) const {
+    if (!moved) return m.c[e];
+    const int2 ab = m.edge_v[e];
+    if (ab.x == v || ab.y == v) return c_of_len(m.contr[e] != 0, len(e, true), p.eps);
+    if (is_neighbour(m, v, ab.x) && is_neighbour(m, v, ab.y)) {
+      const bool ok = direct_ok(m, ab.x, ab.y) &&
+                      one_hop_ok(m, xy, ab.x, ab.y, m.edge_opp[e], p.eps, v, q);
+      return c_of_len(ok, m.len[e], p.eps);
+    }
+    return m.c[e];
+  }
+  __device__ double term(int e, bool moved) const {
+    double w = 1.0;
+    if (!p.polish) {
+      const int4 n = m.edge_nbr[e];
+      double x = c(n.x, moved) * c(n.y, moved);
+      if (n.z >= 0) {
+        x = x * c(n.z, moved);
+        x = x * c(n.w, moved);
+      }
+      w = merged_weight(x);
+    }
+    return w * len(e, moved);
+  }
+  __device__ double diff(int e) const { return term(e, true) - term(e, false); }
+  __device__ bool tri_has_c(int t) const {
+    const int4 te = m.tri_edge[t];
+    return in_c(te.x) || in_c(te.y) || in_c(te.z);
+  }
+  __device__ int first_c(int t) const {
+    const int4 te = m.tri_edge[t];
+    return in_c(te.x) ? te.x : (in_c(te.y) ? te.y : te.z);
+  }
+  // The C-edge ec itself, then (once per triangle, from that triangle's first C-edge) the other
+  // edges of its triangles that are not C-edges, each from the lowest-id triangle reaching it.
+  __device__ double visit(int ec) const {
+    double s = diff(ec);
+    const int2 tt = m.edge_tri[ec];
+    for (int j = 0; j < 2; ++j) {
+      const int t = j == 0 ? tt.x : tt.y;
+      if (t < 0 || first_c(t) != ec) continue;
+      const int4 te = m.tri_edge[t];
+      for (int k = 0; k < 3; ++k) {
+        const int e2 = k == 0 ? te.x : (k == 1 ? te.y : te.z);
+        if (e2 == ec || in_c(e2)) continue;
+        const int2 t2 = m.edge_tri[e2];
+        const int tmin = tri_has_c(t2.x) ? t2.x : t2.y;
+        if (tmin == t) s += diff(e2);
+      }
+    }
+    return s;
+  }
+};
+
+__global__ void __launch_bounds__(kThreads)
+move_delta(MeshDev m, const double2* __restrict__ xy, Par p, const int32_t* __restrict__ vid,
+           const double2* __restrict__ qv, int64_t k, double* __restrict__ delta,
+           int32_t* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= k) return;
+  const int v = vid[i];
+  const double2 q = qv[i];
+  const double inf = __builtin_huge_val();
+  if (v < 0 || v >= m.nv || !isfinite(q.x) || !isfinite(q.y)) {
+    status[i] = CCSP_MOVE_BAD;
+    delta[i] = inf;
+    return;
+  }
+  if (m.vk[v].x == CCSP_VERTEX_ORIGINAL) {
+    status[i] = CCSP_MOVE_FIXED;
+    delta[i] = inf;
+    return;
+  }
+  double sa = 0.0;
+  for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j) {
+    const int4 t = m.tri[m.vtri[j]];
+    if (orient_sign(pos(xy, t.x, v, q), pos(xy, t.y, v, q), pos(xy, t.z, v, q)) <= 0) {
+      status[i] = CCSP_MOVE_FOLDS;
+      delta[i] = inf;
+      return;
+    }
+    sa += triangle_angles(xy, t, v, q, p.delta, p.polish) -
+          triangle_angles(xy, t, -1, q, p.delta, p.polish);
+  }
+  const MoveCtx ctx{m, xy, p, v, q};
+  double se = 0.0, ss = 0.0;
+  for (int j = m.adj_off[v], end = m.adj_off[v + 1]; j < end; ++j) {
+    const int e = m.adj[j].y;
+    se += ctx.visit(e);
+    ss += short_term(ctx.len(e, true), p.eps0) - short_term(m.len[e], p.eps0);
+  }
+  for (int j = m.adj_off[v], end = m.adj_off[v + 1]; j < end; ++j) {
+    const int a = m.adj[j].x;
+    for (int l = m.adj_off[a], lend = m.adj_off[a + 1]; l < lend; ++l) {
+      const int2 be = m.adj[l];
+      if (be.x > a && is_neighbour(m, v, be.x)) se += ctx.visit(be.y);
+    }
+  }
+  status[i] = CCSP_MOVE_OK;
+  delta[i] = se + p.mu_angle * sa + p.mu_len * ss;
+}
+
+}  // namespace
+}  // namespace ccsp
+
+// ---- host: mesh construction and the C-ABI ----
+
+struct MovableMesh {
+  int device = -1;
+  ccsp::MeshDev d{};
+  void* mem = nullptr;
+  int32_t max_blocks = 0;
+  std::vector<int32_t> edge_v;  // 2E, host copy for mesh_info
+};
+
+namespace {
+
+using ccsp::set_last_error;
+
+int fail(int code, const std::string& msg) {
+  set_last_error(msg.c_str());
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(CCSP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool check_params(const ObjectiveParams* p) {
+  if (!p) return false;
+  if (!(p->eps > 0) || !(p->delta > 0) || !(p->eps0 > 0) || !std::isfinite(p->eps) ||
+      !std::isfinite(p->delta) || !std::isfinite(p->eps0) || !std::isfinite(p->mu_angle) ||
+      !std::isfinite(p->mu_len) || p->reserved != 0)
+    return false;
+  return true;
+}
+
+ccsp::Par to_par(const ObjectiveParams* p) {
+  return ccsp::Par{p->eps, p->delta, p->eps0, p->mu_angle, p->mu_len, p->polish != 0};
+}
+
+int check_device(const MovableMesh* m) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != m->device) return fail(CCSP_E_ARG, "the mesh was loaded on another device");
+  return CCSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mesh_load(const MeshDesc* desc, MovableMesh** out) {
+  if (!desc || !out) return fail(CCSP_E_ARG, "mesh_load: null argument");
+  *out = nullptr;
+  const int64_t V = desc->n_vertices, T = desc->n_triangles, P = desc->n_prims;
+  if (V <= 0 || T <= 0 || P < 0 || !desc->kind || !desc->line || !desc->tri_v ||
+      (P > 0 && !desc->prim_v))
+    return fail(CCSP_E_ARG, "mesh_load: empty mesh or null array");
+  if (V >= (int64_t(1) << 30) || T >= (int64_t(1) << 29) || P >= (int64_t(1) << 30))
+    return fail(CCSP_E_ARG, "mesh_load: mesh too large for 32-bit ids");
+  const int32_t* tv = desc->tri_v;
+  for (int64_t i = 0; i < V; ++i) {
+    const int k = desc->kind[i];
+    if (k != CCSP_VERTEX_ORIGINAL && k != CCSP_VERTEX_CONSTRAINED && k != CCSP_VERTEX_FREE)
+      return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: unknown vertex kind at " + std::to_string(i));
+    if (k == CCSP_VERTEX_CONSTRAINED && (desc->line[i] < 0 || desc->line[i] >= P))
+      return fail(CCSP_E_BAD_TRIANGULATION,
+                  "mesh_load: constrained vertex " + std::to_string(i) + " names no original edge");
+  }
+  for (int64_t i = 0; i < 2 * P; ++i)
+    if (desc->prim_v[i] < 0 || desc->prim_v[i] >= V)
+      return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: original edge end out of range");
+  for (int64_t t = 0; t < T; ++t) {
+    const int a = tv[3 * t], b = tv[3 * t + 1], c = tv[3 * t + 2];
+    if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V)
+      return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: vertex id out of range in triangle " +
+                                                std::to_string(t));
+    if (a == b || b == c || c == a)
+      return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: triangle " + std::to_string(t) +
+                                                " repeats a vertex");
+  }
+  // local edges sorted by (lower end, higher end, triangle, local index): counting sort on the
+  // lower end keeps the flat order, then each bucket is sorted stably on the higher end
+  const int64_t n3 = 3 * T;
+  auto lo_of = [&](int64_t f) {
+    const int64_t t = f / 3, i = f % 3;
+    return std::min(tv[3 * t + (i + 1) % 3], tv[3 * t + (i + 2) % 3]);
+  };
+  auto hi_of = [&](int64_t f) {
+    const int64_t t = f / 3, i = f % 3;
+    return std::max(tv[3 * t + (i + 1) % 3], tv[3 * t + (i + 2) % 3]);
+  };
+  std::vector<int64_t> boff(V + 1, 0);
+  for (int64_t f = 0; f < n3; ++f) ++boff[lo_of(f) + 1];
+  for (int64_t v = 0; v < V; ++v) boff[v + 1] += boff[v];
+  std::vector<int32_t> order(n3);
+  {
+    std::vector<int64_t> fill(boff.begin(), boff.end() - 1);
+    for (int64_t f = 0; f < n3; ++f) order[fill[lo_of(f)]++] = (int32_t)f;
+  }
+  for (int64_t v = 0; v < V; ++v)
+    std::stable_sort(order.begin() + boff[v], order.begin() + boff[v + 1],
+                     [&](int32_t x, int32_t y) { return hi_of(x) < hi_of(y); });
+  std::vector<int32_t> tri_edge(n3), ev, etri, eloc;
+  ev.reserve(2 * n3 / 2 + 16);
+  for (int64_t j = 0; j < n3;) {
+    const int32_t f = order[j];
+    const int lo = lo_of(f), hi = hi_of(f);
+    int64_t k = j + 1;
+    while (k < n3 && lo_of(order[k]) == lo && hi_of(order[k]) == hi) ++k;
+    if (k - j > 2)
+      return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: edge (" + std::to_string(lo) + ", " +
+                                                std::to_string(hi) + ") lies in more than two triangles");
+    const int32_t e = (int32_t)(ev.size() / 2);
+    if (k - j == 2) {
+      auto from = [&](int32_t g) { return tv[3 * (g / 3) + (g % 3 + 1) % 3]; };
+      if (from(order[j]) == from(order[j + 1]))
+        return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: triangles " + std::to_string(order[j] / 3) +
+                                                  " and " + std::to_string(order[j + 1] / 3) +
+                                                  " run through their shared edge the same way");
+    }
+    ev.push_back(lo);
+    ev.push_back(hi);
+    for (int64_t s = 0; s < 2; ++s) {
+      etri.push_back(j + s < k ? order[j + s] / 3 : -1);
+      eloc.push_back(j + s < k ? order[j + s] % 3 : -1);
+    }
+    for (int64_t s = j; s < k; ++s) tri_edge[order[s]] = e;
+    j = k;
+  }
+  const int64_t E = (int64_t)ev.size() / 2;
+  std::vector<int32_t> enbr(4 * E, -1), eopp(2 * E, -1);
+  for (int64_t e = 0; e < E; ++e)
+    for (int s = 0; s < 2; ++s) {
+      const int32_t t = etri[2 * e + s], i = eloc[2 * e + s];
+      if (t < 0) continue;
+      eopp[2 * e + s] = tv[3 * t + i];
+      enbr[4 * e + 2 * s] = tri_edge[3 * t + (i + 1) % 3];
+      enbr[4 * e + 2 * s + 1] = tri_edge[3 * t + (i + 2) % 3];
+    }
+  // neighbours: edges are sorted by (lo, hi), so each vertex's list comes out increasing
+  std::vector<int32_t> adj_off(V + 1, 0), adj(4 * E);
+  for (int64_t e = 0; e < E; ++e) {
+    ++adj_off[ev[2 * e] + 1];
+    ++adj_off[ev[2 * e + 1] + 1];
+  }
+  for (int64_t v = 0; v < V; ++v) adj_off[v + 1] += adj_off[v];
+  {
+    std::vector<int32_t> fill(adj_off.begin(), adj_off.end() - 1);
+    for (int64_t e = 0; e < E; ++e) {
+      const int a = ev[2 * e], b = ev[2 * e + 1];
+      int32_t* pa = &adj[2 * fill[a]++];
+      pa[0] = b;
+      pa[1] = (int32_t)e;
+      int32_t* pb = &adj[2 * fill[b]++];
+      pb[0] = a;
+      pb[1] = (int32_t)e;
+    }
+  }
+  std::vector<int32_t> vtri_off(V + 1, 0), vtri(n3);
+  for (int64_t f = 0; f < n3; ++f) ++vtri_off[tv[f] + 1];
+  for (int64_t v = 0; v < V; ++v) vtri_off[v + 1] += vtri_off[v];
+  {
+    std::vector<int32_t> fill(vtri_off.begin(), vtri_off.end() - 1);
+    for (int64_t f = 0; f < n3; ++f) vtri[fill[tv[f]]++] = (int32_t)(f / 3);
+  }
+  std::vector<int32_t> tri4(4 * T), tedge4(4 * T), vk(2 * V);
+  for (int64_t t = 0; t < T; ++t)
+    for (int i = 0; i < 3; ++i) {
+      tri4[4 * t + i] = tv[3 * t + i];
+      tedge4[4 * t + i] = tri_edge[3 * t + i];
+    }
+  for (int64_t t = 0; t < T; ++t) tri4[4 * t + 3] = tedge4[4 * t + 3] = 0;
+  for (int64_t v = 0; v < V; ++v) {
+    vk[2 * v] = desc->kind[v];
+    vk[2 * v + 1] = desc->kind[v] == CCSP_VERTEX_CONSTRAINED ? desc->line[v] : -1;
+  }
+  const int64_t nmax = std::max(E, T);
+  const int32_t max_blocks = (int32_t)((nmax + ccsp::kThreads - 1) / ccsp::kThreads);
+
+  struct Part { const void* src; size_t bytes; void** dst; };
+  auto m = new MovableMesh();
+  hipError_t he = hipGetDevice(&m->device);
+  if (he != hipSuccess) {
+    delete m;
+    return hip_fail(he, "hipGetDevice");
+  }
+  ccsp::MeshDev& d = m->d;
+  d.nv = (int32_t)V;
+  d.nt = (int32_t)T;
+  d.ne = (int32_t)E;
+  d.np = (int32_t)P;
+  std::vector<int32_t> pv(desc->prim_v ? desc->prim_v : nullptr,
+                          desc->prim_v ? desc->prim_v + 2 * P : nullptr);
+  if (pv.empty()) pv.assign(2, 0);
+  void* p_edge_v; void* p_nbr; void* p_opp; void* p_etri; void* p_tri; void* p_tedge;
+  void* p_adj_off; void* p_adj; void* p_vtri_off; void* p_vtri; void* p_vk; void* p_prim;
+  void* p_c; void* p_len; void* p_contr; void* p_part;
+  const Part parts[] = {
+      {ev.data(), 8 * (size_t)E, &p_edge_v}, {enbr.data(), 16 * (size_t)E, &p_nbr},
+      {eopp.data(), 8 * (size_t)E, &p_opp}, {etri.data(), 8 * (size_t)E, &p_etri},
+      {tri4.data(), 16 * (size_t)T, &p_tri}, {tedge4.data(), 16 * (size_t)T, &p_tedge},
+      {adj_off.data(), 4 * (size_t)(V + 1), &p_adj_off}, {adj.data(), 16 * (size_t)E, &p_adj},
+      {vtri_off.data(), 4 * (size_t)(V + 1), &p_vtri_off}, {vtri.data(), 4 * (size_t)n3, &p_vtri},
+      {vk.data(), 8 * (size_t)V, &p_vk}, {pv.data(), 4 * pv.size(), &p_prim},
+      {nullptr, 8 * (size_t)E, &p_c}, {nullptr, 8 * (size_t)E, &p_len},
+      {nullptr, (size_t)E, &p_contr}, {nullptr, 8 * 3 * (size_t)max_blocks, &p_part}};
+  size_t total = 0;
+  for (const Part& pt : parts) total += (pt.bytes + 255) & ~size_t(255);
+  he = hipMalloc(&m->mem, total);
+  if (he != hipSuccess) {
+    delete m;
+    return fail(CCSP_E_OOM, "mesh_load: device allocation of " + std::to_string(total) +
+                                " bytes failed");
+  }
+  size_t off = 0;
+  for (const Part& pt : parts) {
+    *pt.dst = (char*)m->mem + off;
+    if (pt.src) {
+      he = hipMemcpy(*pt.dst, pt.src, pt.bytes, hipMemcpyHostToDevice);
+      if (he != hipSuccess) {
+        (void)hipFree(m->mem);
+        delete m;
+        return hip_fail(he, "mesh_load: hipMemcpy");
+      }
+    }
+    off += (pt.bytes + 255) & ~size_t(255);
+  }
+  d.edge_v = (const int2*)p_edge_v;
+  d.edge_nbr = (const int4*)p_nbr;
+  d.edge_opp = (const int2*)p_opp;
+  d.edge_tri = (const int2*)p_etri;
+  d.tri = (const int4*)p_tri;
+  d.tri_edge = (const int4*)p_tedge;
+  d.adj_off = (const int32_t*)p_adj_off;
+  d.adj = (const int2*)p_adj;
+  d.vtri_off = (const int32_t*)p_vtri_off;
+  d.vtri = (const int32_t*)p_vtri;
+  d.vk = (const int2*)p_vk;
+  d.prim_v = (const int2*)p_prim;
+  d.c = (double*)p_c;
+  d.len = (double*)p_len;
+  d.contr = (uint8_t*)p_contr;
+  d.partial = (double*)p_part;
+  m->max_blocks = max_blocks;
+  m->edge_v = std::move(ev);
+  *out = m;
+  return CCSP_OK;
+}
+
+int mesh_info(const MovableMesh* mesh, int64_t* n_edges, int32_t* edge_v) {
+  if (!mesh || !n_edges) return fail(CCSP_E_ARG, "mesh_info: null argument");
+  *n_edges = mesh->d.ne;
+  if (edge_v) std::memcpy(edge_v, mesh->edge_v.data(), sizeof(int32_t) * mesh->edge_v.size());
+  return CCSP_OK;
+}
+
+int objective_eval(MovableMesh* mesh, const double* xy, const ObjectiveParams* params, double* out,
+                   uint8_t* contractible, double* weight, void* stream) {
+  if (!mesh || !xy || !out) return fail(CCSP_E_ARG, "objective_eval: null argument");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)out & 7) != 0 || ((uintptr_t)weight & 7) != 0)
+    return fail(CCSP_E_ARG, "objective_eval: misaligned buffer");
+  if (!check_params(params)) return fail(CCSP_E_ARG, "objective_eval: invalid parameters");
+  if (int r = check_device(mesh)) return r;
+  const ccsp::MeshDev& d = mesh->d;
+  const ccsp::Par p = to_par(params);
+  hipStream_t s = (hipStream_t)stream;
+  const int n1 = (d.ne + ccsp::kThreads - 1) / ccsp::kThreads;
+  const int n2 = mesh->max_blocks;
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(n1), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy, p, d.partial);
+  hipLaunchKernelGGL(ccsp::terms_pass, dim3(n2), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy, p, d.partial + n1, d.partial + n1 + n2, contractible,
+                     weight);
+  hipLaunchKernelGGL(ccsp::finish_sums, dim3(1), dim3(ccsp::kThreads), 0, s, d.partial, n1, n2, p,
+                     out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_eval: launch");
+}
+
+int objective_delta(MovableMesh* mesh, const double* xy, const ObjectiveParams* params,
+                    const int32_t* vid, const double* q_xy, int64_t k, double* delta,
+                    int32_t* status, void* stream) {
+  if (!mesh || !xy || k < 0) return fail(CCSP_E_ARG, "objective_delta: null argument or k < 0");
+  if (k > 0 && (!vid || !q_xy || !delta || !status))
+    return fail(CCSP_E_ARG, "objective_delta: null argument");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)q_xy & 15) != 0 || ((uintptr_t)delta & 7) != 0 ||
+      ((uintptr_t)vid & 3) != 0 || ((uintptr_t)status & 3) != 0)
+    return fail(CCSP_E_ARG, "objective_delta: misaligned buffer");
+  if (!check_params(params)) return fail(CCSP_E_ARG, "objective_delta: invalid parameters");
+  if (k >= (int64_t(1) << 40)) return fail(CCSP_E_ARG, "objective_delta: too many moves");
+  if (int r = check_device(mesh)) return r;
+  if (k == 0) return CCSP_OK;
+  const ccsp::MeshDev& d = mesh->d;
+  const ccsp::Par p = to_par(params);
+  hipStream_t s = (hipStream_t)stream;
+  const int n1 = (d.ne + ccsp::kThreads - 1) / ccsp::kThreads;
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(n1), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy, p, d.partial);
+  const int64_t blocks = (k + ccsp::kThreads - 1) / ccsp::kThreads;
+  hipLaunchKernelGGL(ccsp::move_delta, dim3((unsigned)blocks), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy, p, vid, (const double2*)q_xy, k, delta, status);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_delta: launch");
+}
+
+void mesh_free(MovableMesh* mesh) {
+  if (!mesh) return;
+  if (mesh->mem) (void)hipFree(mesh->mem);
+  delete mesh;
+}
+
+}  // extern "C"

@@ -13,8 +13,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_exports_match_header():
-    hdr = open(os.path.join(ROOT, "include", "ccsp_walk.h")).read()
-    declared = set(re.findall(r"^(?:int|void|const char \*)\s*\*?\s*(\w+)\(", hdr, re.M))
+    declared = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        hdr = open(os.path.join(ROOT, "include", h)).read()
+        declared |= set(re.findall(r"^(?:int|void|const char \*)\s*\*?\s*(\w+)\(", hdr, re.M))
     assert declared == set(B.EXPORTS), declared ^ set(B.EXPORTS)
     lib = ctypes.CDLL(B.LIB_PATH)
     for name in declared:
@@ -157,3 +159,54 @@ def test_trace_bounces_argument_errors():
     assert B.raw_call("trace_bounces", fake, al, al, al, n, 2, 1 | B.CCSP_TRACE_VALIDATE, al, al, al, al, z, None, z) == B.CCSP_E_ARG
     assert B.raw_call("trace_bounces", fake, al, al, al, n, 2, 1, al, al, al, z, z, None, z) == B.CCSP_E_ARG
     assert B.raw_call("trace_bounces", z, al, al, al, n, 2, 1, al, al, al, al, z, None, z) == B.CCSP_E_ARG
+
+
+def _mesh_desc(tri_v, kind, line, prim_v):
+    arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (tri_v, kind, line, prim_v)]
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
+    d = B.MeshDesc(arrs[1].shape[0], p(arrs[1]), p(arrs[2]), arrs[0].shape[0], p(arrs[0]),
+                   arrs[3].shape[0], p(arrs[3]))
+    return d, arrs
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("kind", "unknown vertex kind"),
+    ("line", "names no original edge"),
+    ("repeat", "repeats a vertex"),
+    ("range", "out of range"),
+    ("three", "more than two triangles"),
+    ("orient", "the same way"),
+    ("prim", "original edge end out of range"),
+])
+def test_mesh_load_rejects(case, msg):
+    """Malformed movable meshes are rejected before any device work."""
+    tri = [[0, 1, 2], [0, 2, 3]]
+    kind, line, prim = [0, 2, 2, 1], [-1, -1, -1, 0], [[0, 1]]
+    if case == "kind":
+        kind = [0, 2, 5, 1]
+    elif case == "line":
+        line = [-1, -1, -1, 3]
+    elif case == "repeat":
+        tri = [[0, 1, 1], [0, 2, 3]]
+    elif case == "range":
+        tri = [[0, 1, 2], [0, 2, 4]]
+    elif case == "three":
+        tri = [[0, 1, 2], [0, 2, 3], [0, 4, 2]]
+        kind, line = kind + [2], line + [-1]
+    elif case == "orient":
+        tri = [[0, 1, 2], [0, 3, 2]]
+    elif case == "prim":
+        prim = [[0, 7]]
+    d, keep = _mesh_desc(tri, kind, line, prim)
+    with pytest.raises(B.CcspError, match=msg):
+        B.mesh_load(d)
+
+
+def test_objective_calls_reject_null_arguments():
+    p = B.ObjectiveParams(0.1, 1e-4, 1e-10, 1.0, 10.0, 0, 0)
+    with pytest.raises(B.CcspError, match="null argument"):
+        B.objective_eval(0, 0, p, 0)
+    with pytest.raises(B.CcspError, match="null argument"):
+        B.objective_delta(0, 0, p, 0, 0, 1, 0, 0)
+    with pytest.raises(B.CcspError, match="null argument"):
+        B.mesh_info(0)

@@ -1,0 +1,207 @@
+"""GPU parity of the low-weight objective (objective_eval, objective_delta) against the checker.
+
+Per-edge values (contractibility, weight) are computed by the same operations in the same order
+on both sides, so they are compared bit for bit, as are move statuses. Sums are compared within
+the reordering bound of a floating-point sum: |a - b| <= 2 n u sum|terms| for n terms (u = 2^-53),
+since each side's sum lies within n u sum|terms| of the exact sum of identical terms.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import objective as ob
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def ccsp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_05570_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    mesh = sg.subdivide(sg.make_scene("tiny"))
+    return mesh, ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+
+
+def _params(ccsp, p: ob.Params):
+    return ccsp.objective_params(p.eps, p.delta, p.eps0, p.mu_angle, p.mu_len, p.polish)
+
+
+def _clustered(mesh, om, p, seed, n_try=3000):
+    """Positions after moves that pull free and constrained vertices next to a neighbour
+    (contraction-to-neighbour moves of Sec. 3.2.5), each kept if the checker finds it valid."""
+    rng = np.random.default_rng(seed)
+    xy = mesh.xy.copy()
+    movable = np.nonzero(mesh.kind != sg.ORIGINAL)[0]
+    for v in rng.choice(movable, n_try):
+        nb = om.nbr[om.nbr_off[v]:om.nbr_off[v + 1]]
+        w = nb[rng.integers(0, nb.shape[0])]
+        r = 0.3 * p.eps * math.sqrt(rng.random())
+        th = 2 * math.pi * rng.random()
+        q = xy[w] + r * np.array([math.cos(th), math.sin(th)])
+        if mesh.kind[v] == sg.CONSTRAINED:
+            a, b = mesh.prim_v[mesh.line[v]]
+            e = xy[b] - xy[a]
+            q = xy[v] + ((q - xy[v]) @ e) / (e @ e) * e
+        if ob.move_status(om, xy, int(v), q) == ob.MOVED:
+            xy[v] = q
+    return xy
+
+
+def _check_eval(ccsp, om, xy, p, what):
+    ref = ob.objective(om, xy, p)
+    with ccsp.MovableMesh(om.tri_v, om.kind, om.line, om.prim_v) as gm:
+        assert np.array_equal(gm.edges(), om.edge_v), f"{what}: edge numbering"
+        out, con, w = gm.eval(torch.from_numpy(xy).to(DEV), _params(ccsp, p), per_edge=True)
+        torch.cuda.synchronize()
+        out, con, w = out.cpu().numpy(), con.cpu().numpy(), w.cpu().numpy()
+    assert np.array_equal(con.astype(bool), ref["contractible"]), f"{what}: contractibility"
+    bad = np.nonzero(w != ref["w"])[0]
+    assert bad.size == 0, f"{what}: weights differ at {bad[:5]}: {w[bad[:5]]} vs {ref['w'][bad[:5]]}"
+    ne, nc = om.n_edges, ref["angle"].size
+    parts = [("wcontr", ref["edge"], ne), ("pangle", ref["angle"], nc), ("plen", ref["short"], ne)]
+    for k, (name, t, n) in enumerate(parts, start=1):
+        tol = 2 * n * U * np.abs(t).sum()
+        assert abs(out[k] - ref[name]) <= tol, f"{what}: {name} {out[k]} vs {ref[name]}"
+    scale = (np.abs(ref["edge"]).sum() + p.mu_angle * np.abs(ref["angle"]).sum()
+             + p.mu_len * np.abs(ref["short"]).sum())
+    assert abs(out[0] - ref["f"]) <= 2 * (ne + nc) * U * scale + 4 * U * abs(ref["f"]), what
+    return ref, out
+
+
+@pytest.mark.parametrize("eps,polish", [(0.02, False), (0.05, False), (1e-300, False),
+                                        (1e6, False), (0.05, True)])
+def test_tiny_eval(ccsp, tiny, eps, polish):
+    mesh, om = tiny
+    p = ob.Params(eps, polish=polish)
+    ref, _ = _check_eval(ccsp, om, mesh.xy, p, f"eps={eps} polish={polish}")
+    if eps == 0.05 and not polish:
+        assert 0.1 < ref["contractible"].mean() < 1.0 and (ref["c"] < 1.0).any()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tiny_eval_clustered(ccsp, tiny, seed):
+    """Clusters of nearly merged vertices: weights of 1/2 and 0 and the 1-hop rule at work."""
+    mesh, om = tiny
+    p = ob.Params(0.03)
+    xy = _clustered(mesh, om, p, seed)
+    ref, _ = _check_eval(ccsp, om, xy, p, f"clustered {seed}")
+    assert (ref["w"] == 0.0).any() and ((ref["w"] > 0.4) & (ref["w"] < 0.6)).any()
+    assert (~one_hop(om, xy, p)).any()
+
+
+def one_hop(om, xy, p):
+    return ob.one_hop_contractible(om, xy, p.eps)
+
+
+def _gpu_delta(ccsp, om, xy, p, v, q):
+    with ccsp.MovableMesh(om.tri_v, om.kind, om.line, om.prim_v) as gm:
+        d, st = gm.delta(torch.from_numpy(xy).to(DEV), _params(ccsp, p),
+                         torch.from_numpy(np.ascontiguousarray(v, dtype=np.int32)).to(DEV),
+                         torch.from_numpy(np.ascontiguousarray(q, dtype=np.float64)).to(DEV))
+        torch.cuda.synchronize()
+        return d.cpu().numpy(), st.cpu().numpy()
+
+
+def _check_deltas(om, xy, p, v, q, d, st, what, idx=None):
+    base = ob.terms(om, xy, p)
+    for i in (range(v.shape[0]) if idx is None else idx):
+        rs, rd, bound = ob.delta_f(om, xy, p, v[i], q[i], base=base)
+        assert st[i] == rs, f"{what}: move {i} (vertex {v[i]}) status {st[i]} vs {rs}"
+        if rs != ob.MOVED:
+            assert d[i] == math.inf
+            continue
+        assert abs(d[i] - rd) <= 1e-12 * bound, f"{what}: move {i}: {d[i]} vs {rd} (bound {bound})"
+
+
+@pytest.mark.parametrize("state", ["subdivided", "clustered"])
+@pytest.mark.parametrize("polish", [False, True])
+def test_tiny_delta(ccsp, tiny, state, polish):
+    mesh, om = tiny
+    p = ob.Params(0.03, polish=polish)
+    xy = mesh.xy if state == "subdivided" else _clustered(mesh, om, ob.Params(0.03), 5)
+    v1, q1 = sg.vertex_moves(mesh, 300, 11, 0.05)
+    v2, q2 = sg.vertex_moves(mesh, 150, 12, 0.6)
+    free = int(np.nonzero(mesh.kind == sg.FREE)[0][0])
+    fixed = int(np.nonzero(mesh.kind == sg.ORIGINAL)[0][0])
+    special_v = np.array([free, free, fixed, mesh.n_vertices, -1, free], dtype=np.int32)
+    special_q = np.array([xy[free], [np.nan, 0.0], xy[fixed] + 1e-3, [0.0, 0.0], [0.0, 0.0],
+                          [np.inf, 0.0]])
+    v = np.concatenate([v1, v2, special_v])
+    q = np.concatenate([q1, q2, special_q])
+    d, st = _gpu_delta(ccsp, om, xy, p, v, q)
+    _check_deltas(om, xy, p, v, q, d, st, f"{state} polish={polish}")
+    n = v1.shape[0] + v2.shape[0]
+    assert d[n] == 0.0 and st[n] == 1  # null move
+    assert list(st[n + 1:]) == [-2, -1, -2, -2, -2]
+    assert (st[:n] == 1).sum() > 100 and (st[:n] == 0).sum() > 10
+
+
+def test_move_back_is_exact_negative(ccsp, tiny):
+    """Applying a move and proposing the way back gives exactly the opposite change, and the
+    change agrees with two full evaluations."""
+    mesh, om = tiny
+    p = ob.Params(0.03)
+    xy = _clustered(mesh, om, p, 7)
+    v, q = sg.vertex_moves(mesh, 400, 21, 0.05)
+    params = None
+    with ccsp.MovableMesh(om.tri_v, om.kind, om.line, om.prim_v) as gm:
+        params = _params(ccsp, p)
+        X = torch.from_numpy(xy).to(DEV)
+        d, st = gm.delta(X, params, torch.from_numpy(v).to(DEV), torch.from_numpy(q).to(DEV))
+        d, st = d.cpu().numpy(), st.cpu().numpy()
+        done = 0
+        for i in np.nonzero(st == 1)[0][:40]:
+            f0 = gm.eval(X, params).cpu().numpy()[0]
+            old = X[v[i]].clone()
+            X[v[i]] = torch.from_numpy(q[i]).to(DEV)
+            f1 = gm.eval(X, params).cpu().numpy()[0]
+            back, sb = gm.delta(X, params, torch.tensor([v[i]], dtype=torch.int32, device=DEV),
+                                old.reshape(1, 2).contiguous())
+            fwd, sf = gm.delta(X, params, torch.tensor([v[i]], dtype=torch.int32, device=DEV),
+                               torch.from_numpy(q[i:i + 1]).to(DEV))
+            assert sb.item() == 1 and sf.item() == 1 and fwd.item() == 0.0
+            X[v[i]] = old
+            dd = gm.delta(X, params, torch.tensor([v[i]], dtype=torch.int32, device=DEV),
+                          torch.from_numpy(q[i:i + 1]).to(DEV))[0].item()
+            assert dd == d[i]
+            assert back.item() == -d[i]
+            assert abs((f1 - f0) - d[i]) <= 1e-10 * abs(f0)
+            done += 1
+        assert done == 40
+
+
+@pytest.fixture(scope="module")
+def grid():
+    mesh = sg.subdivide(sg.make_scene("grid"))
+    return mesh, ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+
+
+def test_grid_eval_and_sampled_deltas(ccsp, grid):
+    """The subdivided grid scene (2,088,968 triangles): evaluation in full, and 2^16 moves with a
+    sample against the checker."""
+    mesh, om = grid
+    p = ob.Params(0.2)
+    ref, _ = _check_eval(ccsp, om, mesh.xy, p, "grid")
+    assert 0.3 < ref["contractible"].mean() < 1.0
+    v, q = sg.vertex_moves(mesh, 1 << 16, 31, 0.1)
+    d, st = _gpu_delta(ccsp, om, mesh.xy, p, v, q)
+    ok = np.nonzero(st == 1)[0]
+    folded = np.nonzero(st == 0)[0]
+    assert ok.size > 1000 and folded.size > 100
+    idx = np.concatenate([ok[:: max(1, ok.size // 5)][:5], folded[:2]])
+    _check_deltas(om, mesh.xy, p, v, q, d, st, "grid", idx=idx)
+    for i in np.concatenate([ok[:60], folded[:60]]):
+        assert st[i] == ob.move_status(om, mesh.xy, int(v[i]), q[i])
