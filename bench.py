@@ -61,9 +61,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "grid", "tiny", "batch", "serve"],
+                    choices=["large", "grid", "tiny", "batch", "serve", "objective"],
                     help="batch: the 256-scene workload in one graph-replayed, autotuned launch; "
-                         "serve: the request server under Poisson arrivals")
+                         "serve: the request server under Poisson arrivals; objective: the "
+                         "low-weight objective on the subdivided large scene")
     ap.add_argument("--requests", type=int, default=10_000, help="serve: requests per level")
     ap.add_argument("--slots", type=int, default=4, help="serve: launch slots")
     ap.add_argument("--tune-cache", default=TUNE_TABLE,
@@ -104,6 +105,9 @@ def main():
         return
     if args.workload == "serve":
         serve_bench(args)
+        return
+    if args.workload == "objective":
+        print(json.dumps(objective_leg("large", args.steps, args.warmup)), flush=True)
         return
     dev = torch.device("cuda:0")
     t0 = time.time()
@@ -224,6 +228,8 @@ def main():
     g_l2 = B.gather_roofline(2 << 20, 16, 2048, stream.cuda_stream)
     walk_steps_s = steps_total / walk_avg
 
+    objective = objective_leg("grid", args.steps, args.warmup)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_leg(sc, rays, args.cpu_seconds)
@@ -283,10 +289,76 @@ def main():
             "frac_scene_sized": walk_steps_s / g_scene,
             "chase_loads_per_s_l2_sized": g_l2, "l2_sized_bytes": 2 << 20,
             "frac_l2_sized": walk_steps_s / g_l2},
+        "objective": objective,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     scene.free()
+
+
+# Compulsory bytes of one objective evaluation (every array read once, scratch written and read
+# back once): per vertex 16 (caller's position) + 4 (its internal slot) + 16 + 16 (position in
+# internal order, written and read) + 8 (kind, line); per edge 8 (ends) + 8 (opposite vertices)
+# + 16 (neighbouring edges) + 4 (its 1-hop list offset) + 17 (length, c and contractibility
+# written) + 17 (read back); per triangle 16 (vertices).
+OBJ_BYTES_PER_VERTEX, OBJ_BYTES_PER_EDGE, OBJ_BYTES_PER_TRIANGLE = 60, 70, 16
+
+
+def objective_leg(scene_name, steps, warmup, moves=1 << 20):
+    """The low-weight objective (Sec. 2.2) on a scene's CDT subdivided once (Sec. 3.5.2): full
+    evaluations and batches of single-vertex moves (Sec. 3.2.2), parameters of the paper scaled from
+    the unit square to the scene (eps = 1e-3 of its size, a point of the annealing schedule)."""
+    import numpy as np
+    import torch
+
+    import paper_2112_05570_amd as ccsp
+    import scenegen as sg
+
+    t0 = time.time()
+    sc = sg.make_scene(scene_name, seed=0)
+    mesh = sg.subdivide(sc)
+    size = sc.box[1] - sc.box[0]
+    gm = ccsp.MovableMesh.from_mesh(mesh)
+    log(f"[bench] objective on {mesh.name}: {mesh.n_vertices} vertices, {gm.n_edges} edges, "
+        f"{mesh.n_triangles} triangles ({time.time() - t0:.1f}s to build)")
+    p = ccsp.objective_params(1e-3 * size, None, 1e-10 * size, 1.0 * size, 10.0 * size)
+    xy = torch.from_numpy(mesh.xy).cuda()
+    v, q = sg.vertex_moves(mesh, moves, 0, 0.05)
+    vid = torch.from_numpy(v).cuda()
+    qd = torch.from_numpy(q).cuda()
+
+    def timed(fn, k, w):
+        for _ in range(w):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            r = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k, r
+
+    ms_eval, out = timed(lambda: gm.eval(xy, p), steps, warmup)
+    ms_delta, (d, st) = timed(lambda: gm.delta(xy, p, vid, qd), max(1, steps // 2), 1)
+    f, wc, pa, pl = out.cpu().tolist()
+    ok = int((st == 1).sum().item())
+    comp = (OBJ_BYTES_PER_VERTEX * mesh.n_vertices + OBJ_BYTES_PER_EDGE * gm.n_edges
+            + OBJ_BYTES_PER_TRIANGLE * mesh.n_triangles)
+    achieved = comp / (ms_eval * 1e-3) / 1e9
+    res = {
+        "workload": f"{mesh.name}: {scene_name} CDT subdivided once, {mesh.n_vertices} vertices, "
+                    f"{gm.n_edges} edges, {mesh.n_triangles} triangles; {moves} moves, seed 0",
+        "eps": 1e-3 * size,
+        "eval_ms": ms_eval, "edges_per_s": gm.n_edges / ms_eval * 1e3,
+        "delta_ms": ms_delta, "moves_per_s": moves / ms_delta * 1e3,
+        "valid_moves": ok, "f": f, "w_contr": wc, "p_angle": pa, "p_len": pl,
+        "roofline_eval": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                          "bytes_per_eval": comp},
+    }
+    gm.close()
+    return res
 
 
 def batch_bench(args):

@@ -37,6 +37,7 @@ namespace ccsp {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kMaxBlocks = 2048;  // workgroups of the evaluation passes: 8 waves per CU
 
 struct MeshDev {
   int32_t nv, nt, ne, np;
@@ -52,6 +53,12 @@ struct MeshDev {
   const int32_t* vtri;
   const int2* vk;         // (kind, line)
   const int2* prim_v;
+  const int32_t* hop_off; // nontrivial 1-hop vertices of each edge (common neighbours of its ends
+  const int32_t* hop_v;   // that are not opposite vertices): topology only, found at load
+  const int32_t* vold;    // internal vertex -> caller's vertex
+  const int32_t* vnew;    // caller's vertex -> internal vertex
+  const int32_t* eperm;   // internal edge -> caller's edge numbering
+  double2* xyi;           // scratch: positions in internal order
   double* c;              // scratch: contraction weight, length, contractibility per edge
   double* len;
   uint8_t* contr;
@@ -139,13 +146,12 @@ __device__ bool direct_ok(const MeshDev& m, int a, int b) {
   return true;
 }
 
-// 1-hop rule (Sec. 2.2.2), with vertex mv at q.
-__device__ bool one_hop_ok(const MeshDev& m, const double2* __restrict__ xy, int a, int b,
-                           int2 opp, double eps, int mv, double2 q) {
-  for (int j = m.adj_off[a], end = m.adj_off[a + 1]; j < end; ++j) {
-    const int x = m.adj[j].x;
-    if (x == b || x == opp.x || x == opp.y || !is_neighbour(m, b, x)) continue;
-    const double2 px = pos(xy, x, mv, q);
+// 1-hop rule (Sec. 2.2.2), with vertex mv at q: every nontrivial 1-hop vertex of edge e lies
+// strictly closer than eps to one of its opposite vertices.
+__device__ bool one_hop_ok(const MeshDev& m, const double2* __restrict__ xy, int e, int2 opp,
+                           double eps, int mv, double2 q) {
+  for (int j = m.hop_off[e], end = m.hop_off[e + 1]; j < end; ++j) {
+    const double2 px = pos(xy, m.hop_v[j], mv, q);
     bool close = dist(px, pos(xy, opp.x, mv, q)) < eps;
     if (!close && opp.y >= 0) close = dist(px, pos(xy, opp.y, mv, q)) < eps;
     if (!close) return false;
@@ -165,21 +171,29 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// Pass 1: length, contractibility and c of every edge; length-penalty partial sums.
+// Caller positions into the mesh's internal vertex order.
 __global__ void __launch_bounds__(kThreads)
-edge_state(MeshDev m, const double2* __restrict__ xy, Par p, double* __restrict__ part) {
+permute_positions(MeshDev m, const double2* __restrict__ xy) {
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < m.nv; i += gridDim.x * kThreads)
+    m.xyi[i] = xy[m.vold[i]];
+}
+
+// Pass 1: length, contractibility and c of every edge; length-penalty partial sums. Each thread
+// takes a fixed stride of edges, so the partial sums do not depend on timing.
+__global__ void __launch_bounds__(kThreads)
+edge_state(MeshDev m, Par p, double* __restrict__ part) {
   __shared__ double sh[kThreads];
-  const int e = blockIdx.x * kThreads + threadIdx.x;
+  const double2* __restrict__ xy = m.xyi;
   double s = 0.0;
-  if (e < m.ne) {
+  for (int e = blockIdx.x * kThreads + threadIdx.x; e < m.ne; e += gridDim.x * kThreads) {
     const int2 ab = m.edge_v[e];
     const double len = dist(xy[ab.x], xy[ab.y]);
     const bool ok = direct_ok(m, ab.x, ab.y) &&
-                    one_hop_ok(m, xy, ab.x, ab.y, m.edge_opp[e], p.eps, -1, make_double2(0, 0));
+                    one_hop_ok(m, xy, e, m.edge_opp[e], p.eps, -1, make_double2(0, 0));
     m.len[e] = len;
     m.contr[e] = ok ? 1 : 0;
     m.c[e] = c_of_len(ok, len, p.eps);
-    s = short_term(len, p.eps0);
+    s += short_term(len, p.eps0);
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -194,21 +208,24 @@ __device__ __forceinline__ double weight_from(const double* __restrict__ c, int4
   return merged_weight(x);
 }
 
-// Pass 2: weighted edge lengths and triangle angle penalties, partial sums of each.
+// Pass 2: weighted edge lengths and triangle angle penalties, partial sums of each. Per-edge
+// outputs go to the caller's edge numbering.
 __global__ void __launch_bounds__(kThreads)
-terms_pass(MeshDev m, const double2* __restrict__ xy, Par p, double* __restrict__ part_edge,
-           double* __restrict__ part_angle, uint8_t* __restrict__ contr_out,
-           double* __restrict__ w_out) {
+terms_pass(MeshDev m, Par p, double* __restrict__ part_edge, double* __restrict__ part_angle,
+           uint8_t* __restrict__ contr_out, double* __restrict__ w_out) {
   __shared__ double sh[kThreads];
-  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const int n = m.ne > m.nt ? m.ne : m.nt;
   double se = 0.0, sa = 0.0;
-  if (i < m.ne) {
-    const double w = p.polish ? 1.0 : weight_from(m.c, m.edge_nbr[i]);
-    se = w * m.len[i];
-    if (w_out) w_out[i] = w;
-    if (contr_out) contr_out[i] = m.contr[i];
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    if (i < m.ne) {
+      const double w = p.polish ? 1.0 : weight_from(m.c, m.edge_nbr[i]);
+      se += w * m.len[i];
+      if (w_out) w_out[m.eperm[i]] = w;
+      if (contr_out) contr_out[m.eperm[i]] = m.contr[i];
+    }
+    if (i < m.nt)
+      sa += triangle_angles(m.xyi, m.tri[i], -1, make_double2(0, 0), p.delta, p.polish);
   }
-  if (i < m.nt) sa = triangle_angles(xy, m.tri[i], -1, make_double2(0, 0), p.delta, p.polish);
   se = block_sum(se, sh);
   sa = block_sum(sa, sh);
   if (threadIdx.x == 0) {
@@ -239,35 +256,44 @@ finish_sums(const double* __restrict__ part, int n1, int n2, Par p, double* __re
 
 // ---- moves ----
 
+constexpr int kLdsNbrs = 16;  // neighbours of a moved vertex kept in LDS (Steiner vertices have ~6)
+
 struct MoveCtx {
   MeshDev m;
   const double2* __restrict__ xy;
   Par p;
   int v;
   double2 q;
+  const int* nb;  // this thread's neighbours of v in LDS, stride kThreads, when deg <= kLdsNbrs
+  int deg;
 
-  __device__ bool in_c(int e) const {
+  __device__ __forceinline__ bool adjacent(int x) const {
+    if (deg > kLdsNbrs) return is_neighbour(m, v, x);
+    for (int j = 0; j < deg; ++j)
+      if (nb[j * kThreads] == x) return true;
+    return false;
+  }
+  __device__ __forceinline__ bool in_c(int e) const {
     const int2 ab = m.edge_v[e];
     if (ab.x == v || ab.y == v) return true;
-    return is_neighbour(m, v, ab.x) && is_neighbour(m, v, ab.y);
+    return adjacent(ab.x) && adjacent(ab.y);
   }
-  __device__ double len(int e, bool moved) const {
+  __device__ __forceinline__ double len(int e, bool moved) const {
     const int2 ab = m.edge_v[e];
     if (!moved || (ab.x != v && ab.y != v)) return m.len[e];
     return dist(pos(xy, ab.x, v, q), pos(xy, ab.y, v, q));
   }
-  __device__ double c(int e, bool moved) const {
+  __device__ __forceinline__ double c(int e, bool moved) const {
     if (!moved) return m.c[e];
     const int2 ab = m.edge_v[e];
     if (ab.x == v || ab.y == v) return c_of_len(m.contr[e] != 0, len(e, true), p.eps);
-    if (is_neighbour(m, v, ab.x) && is_neighbour(m, v, ab.y)) {
-      const bool ok = direct_ok(m, ab.x, ab.y) &&
-                      one_hop_ok(m, xy, ab.x, ab.y, m.edge_opp[e], p.eps, v, q);
+    if (adjacent(ab.x) && adjacent(ab.y)) {
+      const bool ok = direct_ok(m, ab.x, ab.y) && one_hop_ok(m, xy, e, m.edge_opp[e], p.eps, v, q);
       return c_of_len(ok, m.len[e], p.eps);
     }
     return m.c[e];
   }
-  __device__ double term(int e, bool moved) const {
+  __device__ __forceinline__ double term(int e, bool moved) const {
     double w = 1.0;
     if (!p.polish) {
       const int4 n = m.edge_nbr[e];
@@ -280,18 +306,18 @@ struct MoveCtx {
     }
     return w * len(e, moved);
   }
-  __device__ double diff(int e) const { return term(e, true) - term(e, false); }
-  __device__ bool tri_has_c(int t) const {
+  __device__ __forceinline__ double diff(int e) const { return term(e, true) - term(e, false); }
+  __device__ __forceinline__ bool tri_has_c(int t) const {
     const int4 te = m.tri_edge[t];
     return in_c(te.x) || in_c(te.y) || in_c(te.z);
   }
-  __device__ int first_c(int t) const {
+  __device__ __forceinline__ int first_c(int t) const {
     const int4 te = m.tri_edge[t];
     return in_c(te.x) ? te.x : (in_c(te.y) ? te.y : te.z);
   }
   // The C-edge ec itself, then (once per triangle, from that triangle's first C-edge) the other
   // edges of its triangles that are not C-edges, each from the lowest-id triangle reaching it.
-  __device__ double visit(int ec) const {
+  __device__ __forceinline__ double visit(int ec) const {
     double s = diff(ec);
     const int2 tt = m.edge_tri[ec];
     for (int j = 0; j < 2; ++j) {
@@ -311,19 +337,20 @@ struct MoveCtx {
 };
 
 __global__ void __launch_bounds__(kThreads)
-move_delta(MeshDev m, const double2* __restrict__ xy, Par p, const int32_t* __restrict__ vid,
-           const double2* __restrict__ qv, int64_t k, double* __restrict__ delta,
-           int32_t* __restrict__ status) {
+move_delta(MeshDev m, Par p, const int32_t* __restrict__ vid, const double2* __restrict__ qv,
+           int64_t k, double* __restrict__ delta, int32_t* __restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= k) return;
-  const int v = vid[i];
+  const double2* __restrict__ xy = m.xyi;
+  const int cv = vid[i];
   const double2 q = qv[i];
   const double inf = __builtin_huge_val();
-  if (v < 0 || v >= m.nv || !isfinite(q.x) || !isfinite(q.y)) {
+  if (cv < 0 || cv >= m.nv || !isfinite(q.x) || !isfinite(q.y)) {
     status[i] = CCSP_MOVE_BAD;
     delta[i] = inf;
     return;
   }
+  const int v = m.vnew[cv];
   if (m.vk[v].x == CCSP_VERTEX_ORIGINAL) {
     status[i] = CCSP_MOVE_FIXED;
     delta[i] = inf;
@@ -340,7 +367,12 @@ move_delta(MeshDev m, const double2* __restrict__ xy, Par p, const int32_t* __re
     sa += triangle_angles(xy, t, v, q, p.delta, p.polish) -
           triangle_angles(xy, t, -1, q, p.delta, p.polish);
   }
-  const MoveCtx ctx{m, xy, p, v, q};
+  __shared__ int snb[kLdsNbrs * kThreads];
+  const int a0 = m.adj_off[v], deg = m.adj_off[v + 1] - a0;
+  int* nb = snb + threadIdx.x;
+  if (deg <= kLdsNbrs)
+    for (int j = 0; j < deg; ++j) nb[j * kThreads] = m.adj[a0 + j].x;
+  const MoveCtx ctx{m, xy, p, v, q, nb, deg};
   double se = 0.0, ss = 0.0;
   for (int j = m.adj_off[v], end = m.adj_off[v + 1]; j < end; ++j) {
     const int e = m.adj[j].y;
@@ -351,7 +383,7 @@ move_delta(MeshDev m, const double2* __restrict__ xy, Par p, const int32_t* __re
     const int a = m.adj[j].x;
     for (int l = m.adj_off[a], lend = m.adj_off[a + 1]; l < lend; ++l) {
       const int2 be = m.adj[l];
-      if (be.x > a && is_neighbour(m, v, be.x)) se += ctx.visit(be.y);
+      if (be.x > a && ctx.adjacent(be.x)) se += ctx.visit(be.y);
     }
   }
   status[i] = CCSP_MOVE_OK;
@@ -367,8 +399,7 @@ struct MovableMesh {
   int device = -1;
   ccsp::MeshDev d{};
   void* mem = nullptr;
-  int32_t max_blocks = 0;
-  std::vector<int32_t> edge_v;  // 2E, host copy for mesh_info
+  std::vector<int32_t> edge_v;  // 2E in the caller's numbering, for mesh_info
 };
 
 namespace {
@@ -391,6 +422,13 @@ bool check_params(const ObjectiveParams* p) {
       !std::isfinite(p->mu_len) || p->reserved != 0)
     return false;
   return true;
+}
+
+// Workgroups of a pass over n items: enough to cover them, at most kMaxBlocks (the partial sums
+// buffer holds 3 * kMaxBlocks values).
+int grid_for(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ccsp::kMaxBlocks,
+                                                     (n + ccsp::kThreads - 1) / ccsp::kThreads));
 }
 
 ccsp::Par to_par(const ObjectiveParams* p) {
@@ -418,7 +456,7 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
     return fail(CCSP_E_ARG, "mesh_load: empty mesh or null array");
   if (V >= (int64_t(1) << 30) || T >= (int64_t(1) << 29) || P >= (int64_t(1) << 30))
     return fail(CCSP_E_ARG, "mesh_load: mesh too large for 32-bit ids");
-  const int32_t* tv = desc->tri_v;
+  const int32_t* ctv = desc->tri_v;
   for (int64_t i = 0; i < V; ++i) {
     const int k = desc->kind[i];
     if (k != CCSP_VERTEX_ORIGINAL && k != CCSP_VERTEX_CONSTRAINED && k != CCSP_VERTEX_FREE)
@@ -431,7 +469,7 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
     if (desc->prim_v[i] < 0 || desc->prim_v[i] >= V)
       return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: original edge end out of range");
   for (int64_t t = 0; t < T; ++t) {
-    const int a = tv[3 * t], b = tv[3 * t + 1], c = tv[3 * t + 2];
+    const int a = ctv[3 * t], b = ctv[3 * t + 1], c = ctv[3 * t + 2];
     if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V)
       return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: vertex id out of range in triangle " +
                                                 std::to_string(t));
@@ -439,9 +477,56 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
       return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: triangle " + std::to_string(t) +
                                                 " repeats a vertex");
   }
-  // local edges sorted by (lower end, higher end, triangle, local index): counting sort on the
-  // lower end keeps the flat order, then each bucket is sorted stably on the higher end
   const int64_t n3 = 3 * T;
+
+  // Internal vertex order: breadth-first over the triangles' adjacency, so that neighbours get
+  // nearby ids and the gathers of a pass stay within a narrow band of memory.
+  std::vector<int32_t> vold, vnew(V, -1);
+  {
+    std::vector<int64_t> noff(V + 1, 0);
+    for (int64_t f = 0; f < n3; ++f) noff[ctv[f] + 1] += 2;
+    for (int64_t v = 0; v < V; ++v) noff[v + 1] += noff[v];
+    std::vector<int32_t> nb(2 * n3);
+    std::vector<int64_t> fill(noff.begin(), noff.end() - 1);
+    for (int64_t t = 0; t < T; ++t)
+      for (int i = 0; i < 3; ++i) {
+        const int a = ctv[3 * t + i];
+        nb[fill[a]++] = ctv[3 * t + (i + 1) % 3];
+        nb[fill[a]++] = ctv[3 * t + (i + 2) % 3];
+      }
+    vold.reserve(V);
+    for (int64_t s = 0; s < V; ++s) {
+      if (vnew[s] >= 0) continue;
+      size_t head = vold.size();
+      vnew[s] = (int32_t)vold.size();
+      vold.push_back((int32_t)s);
+      while (head < vold.size()) {
+        const int u = vold[head++];
+        for (int64_t j = noff[u]; j < noff[u + 1]; ++j) {
+          const int w = nb[j];
+          if (vnew[w] < 0) {
+            vnew[w] = (int32_t)vold.size();
+            vold.push_back(w);
+          }
+        }
+      }
+    }
+  }
+  // Internal triangles: ordered by their lowest internal vertex (stable in the caller's order),
+  // vertices relabelled, local order kept.
+  std::vector<int32_t> told(T), tv(n3);
+  {
+    std::vector<int64_t> off(V + 1, 0);
+    auto low = [&](int64_t t) {
+      return std::min(vnew[ctv[3 * t]], std::min(vnew[ctv[3 * t + 1]], vnew[ctv[3 * t + 2]]));
+    };
+    for (int64_t t = 0; t < T; ++t) ++off[low(t) + 1];
+    for (int64_t v = 0; v < V; ++v) off[v + 1] += off[v];
+    for (int64_t t = 0; t < T; ++t) told[off[low(t)]++] = (int32_t)t;
+    for (int64_t ti = 0; ti < T; ++ti)
+      for (int i = 0; i < 3; ++i) tv[3 * ti + i] = vnew[ctv[3 * told[ti] + i]];
+  }
+  // local edges of the internal triangles sorted by (lower end, higher end, flat index)
   auto lo_of = [&](int64_t f) {
     const int64_t t = f / 3, i = f % 3;
     return std::min(tv[3 * t + (i + 1) % 3], tv[3 * t + (i + 2) % 3]);
@@ -450,41 +535,46 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
     const int64_t t = f / 3, i = f % 3;
     return std::max(tv[3 * t + (i + 1) % 3], tv[3 * t + (i + 2) % 3]);
   };
-  std::vector<int64_t> boff(V + 1, 0);
-  for (int64_t f = 0; f < n3; ++f) ++boff[lo_of(f) + 1];
-  for (int64_t v = 0; v < V; ++v) boff[v + 1] += boff[v];
   std::vector<int32_t> order(n3);
   {
+    std::vector<int64_t> boff(V + 1, 0);
+    for (int64_t f = 0; f < n3; ++f) ++boff[lo_of(f) + 1];
+    for (int64_t v = 0; v < V; ++v) boff[v + 1] += boff[v];
     std::vector<int64_t> fill(boff.begin(), boff.end() - 1);
     for (int64_t f = 0; f < n3; ++f) order[fill[lo_of(f)]++] = (int32_t)f;
+    for (int64_t v = 0; v < V; ++v)
+      std::stable_sort(order.begin() + boff[v], order.begin() + boff[v + 1],
+                       [&](int32_t x, int32_t y) { return hi_of(x) < hi_of(y); });
   }
-  for (int64_t v = 0; v < V; ++v)
-    std::stable_sort(order.begin() + boff[v], order.begin() + boff[v + 1],
-                     [&](int32_t x, int32_t y) { return hi_of(x) < hi_of(y); });
+  // Edges. The triangles of an edge are kept in the caller's triangle order: it fixes the order
+  // of the product x.
   std::vector<int32_t> tri_edge(n3), ev, etri, eloc;
-  ev.reserve(2 * n3 / 2 + 16);
+  ev.reserve(n3 + 16);
   for (int64_t j = 0; j < n3;) {
     const int32_t f = order[j];
     const int lo = lo_of(f), hi = hi_of(f);
     int64_t k = j + 1;
     while (k < n3 && lo_of(order[k]) == lo && hi_of(order[k]) == hi) ++k;
     if (k - j > 2)
-      return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: edge (" + std::to_string(lo) + ", " +
-                                                std::to_string(hi) + ") lies in more than two triangles");
-    const int32_t e = (int32_t)(ev.size() / 2);
-    if (k - j == 2) {
+      return fail(CCSP_E_BAD_TRIANGULATION,
+                  "mesh_load: edge (" + std::to_string(vold[lo]) + ", " + std::to_string(vold[hi]) +
+                      ") lies in more than two triangles");
+    int32_t g0 = order[j], g1 = k - j == 2 ? order[j + 1] : -1;
+    if (g1 >= 0) {
       auto from = [&](int32_t g) { return tv[3 * (g / 3) + (g % 3 + 1) % 3]; };
-      if (from(order[j]) == from(order[j + 1]))
-        return fail(CCSP_E_BAD_TRIANGULATION, "mesh_load: triangles " + std::to_string(order[j] / 3) +
-                                                  " and " + std::to_string(order[j + 1] / 3) +
-                                                  " run through their shared edge the same way");
+      if (from(g0) == from(g1))
+        return fail(CCSP_E_BAD_TRIANGULATION,
+                    "mesh_load: triangles " + std::to_string(told[g0 / 3]) + " and " +
+                        std::to_string(told[g1 / 3]) + " run through their shared edge the same way");
+      if (told[g1 / 3] < told[g0 / 3]) std::swap(g0, g1);
     }
+    const int32_t e = (int32_t)(ev.size() / 2);
     ev.push_back(lo);
     ev.push_back(hi);
-    for (int64_t s = 0; s < 2; ++s) {
-      etri.push_back(j + s < k ? order[j + s] / 3 : -1);
-      eloc.push_back(j + s < k ? order[j + s] % 3 : -1);
-    }
+    etri.push_back(g0 / 3);
+    eloc.push_back(g0 % 3);
+    etri.push_back(g1 >= 0 ? g1 / 3 : -1);
+    eloc.push_back(g1 >= 0 ? g1 % 3 : -1);
     for (int64_t s = j; s < k; ++s) tri_edge[order[s]] = e;
     j = k;
   }
@@ -498,6 +588,30 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
       enbr[4 * e + 2 * s] = tri_edge[3 * t + (i + 1) % 3];
       enbr[4 * e + 2 * s + 1] = tri_edge[3 * t + (i + 2) % 3];
     }
+  // the caller's edge numbering: edges sorted by (lower, higher) caller vertex id
+  std::vector<int32_t> eperm(E), edge_can(2 * E);
+  {
+    std::vector<int32_t> clo(E), chi(E);
+    for (int64_t e = 0; e < E; ++e) {
+      const int32_t a = vold[ev[2 * e]], b = vold[ev[2 * e + 1]];
+      clo[e] = std::min(a, b);
+      chi[e] = std::max(a, b);
+    }
+    std::vector<int64_t> off(V + 1, 0);
+    for (int64_t e = 0; e < E; ++e) ++off[clo[e] + 1];
+    for (int64_t v = 0; v < V; ++v) off[v + 1] += off[v];
+    std::vector<int32_t> eo(E);
+    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+    for (int64_t e = 0; e < E; ++e) eo[fill[clo[e]]++] = (int32_t)e;
+    for (int64_t v = 0; v < V; ++v)
+      std::sort(eo.begin() + off[v], eo.begin() + off[v + 1],
+                [&](int32_t x, int32_t y) { return chi[x] < chi[y]; });
+    for (int64_t r = 0; r < E; ++r) {
+      eperm[eo[r]] = (int32_t)r;
+      edge_can[2 * r] = clo[eo[r]];
+      edge_can[2 * r + 1] = chi[eo[r]];
+    }
+  }
   // neighbours: edges are sorted by (lo, hi), so each vertex's list comes out increasing
   std::vector<int32_t> adj_off(V + 1, 0), adj(4 * E);
   for (int64_t e = 0; e < E; ++e) {
@@ -517,6 +631,28 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
       pb[1] = (int32_t)e;
     }
   }
+  // nontrivial 1-hop vertices: common neighbours of an edge's ends other than its opposite
+  // vertices (rows of adj are increasing, so a merge finds the common ones)
+  std::vector<int32_t> hop_off(E + 1, 0), hop_v;
+  for (int64_t e = 0; e < E; ++e) {
+    const int a = ev[2 * e], b = ev[2 * e + 1];
+    int32_t i = adj_off[a], j = adj_off[b];
+    const int32_t ie = adj_off[a + 1], je = adj_off[b + 1];
+    while (i < ie && j < je) {
+      const int x = adj[2 * i], y = adj[2 * j];
+      if (x < y) {
+        ++i;
+      } else if (y < x) {
+        ++j;
+      } else {
+        if (x != eopp[2 * e] && x != eopp[2 * e + 1]) hop_v.push_back(x);
+        ++i;
+        ++j;
+      }
+    }
+    hop_off[e + 1] = (int32_t)hop_v.size();
+  }
+  if (hop_v.empty()) hop_v.push_back(0);
   std::vector<int32_t> vtri_off(V + 1, 0), vtri(n3);
   for (int64_t f = 0; f < n3; ++f) ++vtri_off[tv[f] + 1];
   for (int64_t v = 0; v < V; ++v) vtri_off[v + 1] += vtri_off[v];
@@ -525,18 +661,20 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
     for (int64_t f = 0; f < n3; ++f) vtri[fill[tv[f]]++] = (int32_t)(f / 3);
   }
   std::vector<int32_t> tri4(4 * T), tedge4(4 * T), vk(2 * V);
-  for (int64_t t = 0; t < T; ++t)
+  for (int64_t t = 0; t < T; ++t) {
     for (int i = 0; i < 3; ++i) {
       tri4[4 * t + i] = tv[3 * t + i];
       tedge4[4 * t + i] = tri_edge[3 * t + i];
     }
-  for (int64_t t = 0; t < T; ++t) tri4[4 * t + 3] = tedge4[4 * t + 3] = 0;
-  for (int64_t v = 0; v < V; ++v) {
-    vk[2 * v] = desc->kind[v];
-    vk[2 * v + 1] = desc->kind[v] == CCSP_VERTEX_CONSTRAINED ? desc->line[v] : -1;
+    tri4[4 * t + 3] = tedge4[4 * t + 3] = 0;
   }
-  const int64_t nmax = std::max(E, T);
-  const int32_t max_blocks = (int32_t)((nmax + ccsp::kThreads - 1) / ccsp::kThreads);
+  for (int64_t vi = 0; vi < V; ++vi) {
+    const int32_t v = vold[vi];
+    vk[2 * vi] = desc->kind[v];
+    vk[2 * vi + 1] = desc->kind[v] == CCSP_VERTEX_CONSTRAINED ? desc->line[v] : -1;
+  }
+  std::vector<int32_t> pv(2 * std::max<int64_t>(P, 1), 0);
+  for (int64_t i = 0; i < 2 * P; ++i) pv[i] = vnew[desc->prim_v[i]];
 
   struct Part { const void* src; size_t bytes; void** dst; };
   auto m = new MovableMesh();
@@ -550,11 +688,9 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
   d.nt = (int32_t)T;
   d.ne = (int32_t)E;
   d.np = (int32_t)P;
-  std::vector<int32_t> pv(desc->prim_v ? desc->prim_v : nullptr,
-                          desc->prim_v ? desc->prim_v + 2 * P : nullptr);
-  if (pv.empty()) pv.assign(2, 0);
   void* p_edge_v; void* p_nbr; void* p_opp; void* p_etri; void* p_tri; void* p_tedge;
   void* p_adj_off; void* p_adj; void* p_vtri_off; void* p_vtri; void* p_vk; void* p_prim;
+  void* p_vold; void* p_vnew; void* p_eperm; void* p_xyi; void* p_hop_off; void* p_hop_v;
   void* p_c; void* p_len; void* p_contr; void* p_part;
   const Part parts[] = {
       {ev.data(), 8 * (size_t)E, &p_edge_v}, {enbr.data(), 16 * (size_t)E, &p_nbr},
@@ -563,8 +699,11 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
       {adj_off.data(), 4 * (size_t)(V + 1), &p_adj_off}, {adj.data(), 16 * (size_t)E, &p_adj},
       {vtri_off.data(), 4 * (size_t)(V + 1), &p_vtri_off}, {vtri.data(), 4 * (size_t)n3, &p_vtri},
       {vk.data(), 8 * (size_t)V, &p_vk}, {pv.data(), 4 * pv.size(), &p_prim},
+      {vold.data(), 4 * (size_t)V, &p_vold}, {vnew.data(), 4 * (size_t)V, &p_vnew},
+      {eperm.data(), 4 * (size_t)E, &p_eperm}, {nullptr, 16 * (size_t)V, &p_xyi},
+      {hop_off.data(), 4 * (size_t)(E + 1), &p_hop_off}, {hop_v.data(), 4 * hop_v.size(), &p_hop_v},
       {nullptr, 8 * (size_t)E, &p_c}, {nullptr, 8 * (size_t)E, &p_len},
-      {nullptr, (size_t)E, &p_contr}, {nullptr, 8 * 3 * (size_t)max_blocks, &p_part}};
+      {nullptr, (size_t)E, &p_contr}, {nullptr, 8 * 3 * (size_t)ccsp::kMaxBlocks, &p_part}};
   size_t total = 0;
   for (const Part& pt : parts) total += (pt.bytes + 255) & ~size_t(255);
   he = hipMalloc(&m->mem, total);
@@ -598,12 +737,17 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
   d.vtri = (const int32_t*)p_vtri;
   d.vk = (const int2*)p_vk;
   d.prim_v = (const int2*)p_prim;
+  d.hop_off = (const int32_t*)p_hop_off;
+  d.hop_v = (const int32_t*)p_hop_v;
+  d.vold = (const int32_t*)p_vold;
+  d.vnew = (const int32_t*)p_vnew;
+  d.eperm = (const int32_t*)p_eperm;
+  d.xyi = (double2*)p_xyi;
   d.c = (double*)p_c;
   d.len = (double*)p_len;
   d.contr = (uint8_t*)p_contr;
   d.partial = (double*)p_part;
-  m->max_blocks = max_blocks;
-  m->edge_v = std::move(ev);
+  m->edge_v = std::move(edge_can);
   *out = m;
   return CCSP_OK;
 }
@@ -625,13 +769,12 @@ int objective_eval(MovableMesh* mesh, const double* xy, const ObjectiveParams* p
   const ccsp::MeshDev& d = mesh->d;
   const ccsp::Par p = to_par(params);
   hipStream_t s = (hipStream_t)stream;
-  const int n1 = (d.ne + ccsp::kThreads - 1) / ccsp::kThreads;
-  const int n2 = mesh->max_blocks;
-  hipLaunchKernelGGL(ccsp::edge_state, dim3(n1), dim3(ccsp::kThreads), 0, s, d,
-                     (const double2*)xy, p, d.partial);
-  hipLaunchKernelGGL(ccsp::terms_pass, dim3(n2), dim3(ccsp::kThreads), 0, s, d,
-                     (const double2*)xy, p, d.partial + n1, d.partial + n1 + n2, contractible,
-                     weight);
+  const int n1 = grid_for(d.ne), n2 = grid_for(std::max(d.ne, d.nt));
+  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy);
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(n1), dim3(ccsp::kThreads), 0, s, d, p, d.partial);
+  hipLaunchKernelGGL(ccsp::terms_pass, dim3(n2), dim3(ccsp::kThreads), 0, s, d, p,
+                     d.partial + n1, d.partial + n1 + n2, contractible, weight);
   hipLaunchKernelGGL(ccsp::finish_sums, dim3(1), dim3(ccsp::kThreads), 0, s, d.partial, n1, n2, p,
                      out);
   hipError_t e = hipGetLastError();
@@ -654,12 +797,13 @@ int objective_delta(MovableMesh* mesh, const double* xy, const ObjectiveParams* 
   const ccsp::MeshDev& d = mesh->d;
   const ccsp::Par p = to_par(params);
   hipStream_t s = (hipStream_t)stream;
-  const int n1 = (d.ne + ccsp::kThreads - 1) / ccsp::kThreads;
-  hipLaunchKernelGGL(ccsp::edge_state, dim3(n1), dim3(ccsp::kThreads), 0, s, d,
-                     (const double2*)xy, p, d.partial);
+  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy);
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
+                     d.partial);
   const int64_t blocks = (k + ccsp::kThreads - 1) / ccsp::kThreads;
-  hipLaunchKernelGGL(ccsp::move_delta, dim3((unsigned)blocks), dim3(ccsp::kThreads), 0, s, d,
-                     (const double2*)xy, p, vid, (const double2*)q_xy, k, delta, status);
+  hipLaunchKernelGGL(ccsp::move_delta, dim3((unsigned)blocks), dim3(ccsp::kThreads), 0, s, d, p,
+                     vid, (const double2*)q_xy, k, delta, status);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_delta: launch");
 }
