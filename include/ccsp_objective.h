@@ -55,7 +55,8 @@ enum {
   CCSP_MOVE_OK = 1,     /* valid: every triangle of the vertex stays strictly counter-clockwise */
   CCSP_MOVE_FOLDS = 0,  /* some triangle of the vertex would not (decided exactly); delta = +inf */
   CCSP_MOVE_FIXED = -1, /* the vertex is ORIGINAL; delta = +inf */
-  CCSP_MOVE_BAD = -2    /* vertex id out of range or a coordinate not finite; delta = +inf */
+  CCSP_MOVE_BAD = -2,   /* vertex id out of range or a coordinate not finite; delta = +inf */
+  CCSP_MOVE_REJECTED = 2 /* anneal_moves: valid, not accepted by the Metropolis rule */
 };
 
 typedef struct MovableMesh MovableMesh; /* opaque; owns device memory */
@@ -115,6 +116,48 @@ int objective_eval(MovableMesh *mesh, const double *xy, const ObjectiveParams *p
 int objective_delta(MovableMesh *mesh, const double *xy, const ObjectiveParams *params,
                     const int32_t *vid, const double *q_xy, int64_t k, double *delta,
                     int32_t *status, void *stream);
+
+/*
+ * mesh_classes: a partition of the movable (non-ORIGINAL) vertices into classes whose members are
+ * pairwise more than four edges apart. A move's change of f reads positions within four edges of
+ * its vertex only, so the moves of one class do not interact: evaluating them all against the same
+ * positions and applying the accepted ones gives what applying them one after another would, in
+ * any order. Greedy colouring over the mesh's internal order, computed on the first call and kept.
+ * *n_classes receives the number of classes; if class_off is not NULL it receives n_classes + 1
+ * offsets into class_v, which (if not NULL) receives the caller's vertex ids of every movable
+ * vertex, class by class (HOST arrays). Synchronous.
+ */
+int mesh_classes(MovableMesh *mesh, int32_t *n_classes, int64_t *class_off, int32_t *class_v);
+
+/*
+ * anneal_moves: one Metropolis step (Sec. 3.1) for each of k single-vertex moves (Sec. 3.2.2), for
+ * moves that do not interact (the vertices of one class of mesh_classes; for other sets, every
+ * move is still evaluated against the positions before the call). Move i displaces vertex vid[i]
+ * (DEVICE int32) by disp[2i..2i+1] (DEVICE binary64, 16-byte aligned); for a CONSTRAINED vertex the
+ * displacement d is first projected on its original edge (a, b): d <- s * e with e = b - a and
+ * s = (d.x*e.x + d.y*e.y) / (e.x*e.x + e.y*e.y). The move is accepted when it is valid (as in
+ * objective_delta) and delta <= 0 or u[i] < exp(-delta / temperature) (u DEVICE binary64 in
+ * [0, 1), temperature >= 0); accepted positions are written into xy (DEVICE, in place). delta
+ * (DEVICE binary64) receives the change of f of each move and status (DEVICE int32) CCSP_MOVE_OK
+ * for an accepted move, CCSP_MOVE_REJECTED for a valid one not accepted, or the objective_delta
+ * codes. A vertex may appear at most once. Asynchronous on `stream`; overwrites the mesh's scratch.
+ */
+int anneal_moves(MovableMesh *mesh, double *xy, const ObjectiveParams *params, double temperature,
+                 const int32_t *vid, const double *disp, const double *u, int64_t k, double *delta,
+                 int32_t *status, void *stream);
+
+/*
+ * anneal_sweep: one Metropolis step for every movable vertex, class by class in the order of
+ * mesh_classes (classes computed on first use): the result is that of the sequential chain over
+ * the vertices in the order mesh_classes lists them. Entry i of disp (DEVICE, 2 binary64 per
+ * movable vertex, 16-byte aligned), u, delta and status (DEVICE, one per movable vertex) belongs to
+ * the i-th vertex of that list; moves, acceptance, projection and status codes are those of
+ * anneal_moves, and every move is evaluated against the positions its predecessors in the list
+ * left. xy (DEVICE) is updated in place. One launch per class after one pass over the edges.
+ * Asynchronous on `stream`; overwrites the mesh's scratch.
+ */
+int anneal_sweep(MovableMesh *mesh, double *xy, const ObjectiveParams *params, double temperature,
+                 const double *disp, const double *u, double *delta, int32_t *status, void *stream);
 
 /* mesh_free: release the mesh (after its calls have completed). NULL is ignored. */
 void mesh_free(MovableMesh *mesh);

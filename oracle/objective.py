@@ -261,3 +261,49 @@ def delta_f(m: Mesh, xy, p: Params, v, q, base: dict | None = None) -> tuple[int
     df = de.sum() + p.mu_angle * da.sum() + p.mu_len * ds.sum()
     bound = np.abs(de).sum() + p.mu_angle * np.abs(da).sum() + p.mu_len * np.abs(ds).sum()
     return st, float(df), float(bound)
+
+
+ACCEPTED, REJECTED = 1, 2
+
+
+def project(m: Mesh, xy, v, d):
+    """A constrained vertex's displacement projected on its original edge (a, b): s * e with
+    e = b - a and s = (d.e)/(e.e); other kinds keep d."""
+    d = np.asarray(d, dtype=np.float64)
+    if m.kind[v] != CONSTRAINED:
+        return d
+    a, b = m.prim_v[m.line[v]]
+    ex, ey = xy[b, 0] - xy[a, 0], xy[b, 1] - xy[a, 1]
+    s = (d[0] * ex + d[1] * ey) / (ex * ex + ey * ey)
+    return np.array([s * ex, s * ey])
+
+
+def metropolis_chain(m: Mesh, xy, p: Params, temperature, vid, disp, u):
+    """Single-vertex Metropolis steps (Sec. 3.1, acceptance min(1, exp(-delta f / T)); moves of
+    Sec. 3.2.2), applied one after another in the given order. Returns the final positions and,
+    per move, the status (ACCEPTED, REJECTED or the move_status codes), delta f and the decision
+    margin |delta f + T ln u| (a decision within rounding of 0 may differ between implementations)."""
+    xy = np.array(xy, dtype=np.float64)
+    st = np.zeros(len(vid), dtype=np.int64)
+    df = np.full(len(vid), np.inf)
+    margin = np.full(len(vid), np.inf)
+    for i, v in enumerate(vid):
+        v = int(v)
+        if not (0 <= v < m.nv):
+            st[i] = BAD
+            continue
+        q = xy[v] + project(m, xy, v, disp[i])
+        s, d, bound = delta_f(m, xy, p, v, q)
+        df[i] = d
+        if s != MOVED:
+            st[i] = s
+            continue
+        with np.errstate(divide="ignore", over="ignore"):
+            accept = d <= 0.0 or u[i] < np.exp(-np.float64(d) / np.float64(temperature))
+        if accept:
+            st[i] = ACCEPTED
+            xy[v] = q
+        else:
+            st[i] = REJECTED
+        margin[i] = abs(d + temperature * np.log(u[i])) if u[i] > 0 else np.inf
+    return xy, st, df, margin

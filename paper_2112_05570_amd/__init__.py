@@ -270,6 +270,55 @@ class MovableMesh:
                           d.data_ptr(), st.data_ptr(), _stream(stream))
         return d, st
 
+    def classes(self):
+        """Classes of movable vertices (caller ids) whose moves do not interact."""
+        n = B.mesh_classes(self.handle)
+        off = np.empty(n + 1, dtype=np.int64)
+        B.mesh_classes(self.handle, off.ctypes.data_as(ctypes.c_void_p).value)
+        v = np.empty(int(off[-1]), dtype=np.int32)
+        B.mesh_classes(self.handle, off.ctypes.data_as(ctypes.c_void_p).value,
+                       v.ctypes.data_as(ctypes.c_void_p).value)
+        return [v[off[i]:off[i + 1]] for i in range(n)]
+
+    def anneal(self, xy, params, temperature, vid, disp, u, stream=None):
+        """One Metropolis step for each move (see ``anneal_moves``); accepted positions are written
+        into xy in place. Returns (delta, status). Asynchronous."""
+        import torch
+        k = vid.shape[0]
+        if (not vid.is_cuda or vid.dtype != torch.int32 or not vid.is_contiguous()
+                or tuple(disp.shape) != (k, 2) or disp.dtype != torch.float64
+                or not disp.is_contiguous() or tuple(u.shape) != (k,) or u.dtype != torch.float64
+                or not u.is_contiguous()):
+            raise ValueError("vid int32 (k,), disp float64 (k,2), u float64 (k,): contiguous CUDA")
+        d = torch.empty(k, dtype=torch.float64, device=xy.device)
+        st = torch.empty(k, dtype=torch.int32, device=xy.device)
+        B.anneal_moves(self.handle, self._xy(xy), params, float(temperature), vid.data_ptr(),
+                       disp.data_ptr(), u.data_ptr(), k, d.data_ptr(), st.data_ptr(),
+                       _stream(stream))
+        return d, st
+
+    def sweep(self, xy, params, temperature, disp, u, stream=None):
+        """One Metropolis step for every movable vertex, class by class (see ``anneal_sweep``):
+        disp (M,2) and u (M,) float64 CUDA tensors in the order of ``classes()``. xy is updated in
+        place. Returns (delta, status) in that order. Asynchronous."""
+        import torch
+        m = self.n_movable()
+        if (tuple(disp.shape) != (m, 2) or disp.dtype != torch.float64 or not disp.is_contiguous()
+                or not disp.is_cuda or tuple(u.shape) != (m,) or u.dtype != torch.float64
+                or not u.is_contiguous() or not u.is_cuda):
+            raise ValueError(f"disp float64 ({m},2) and u float64 ({m},), contiguous CUDA tensors")
+        d = torch.empty(m, dtype=torch.float64, device=xy.device)
+        st = torch.empty(m, dtype=torch.int32, device=xy.device)
+        B.anneal_sweep(self.handle, self._xy(xy), params, float(temperature), disp.data_ptr(),
+                       u.data_ptr(), d.data_ptr(), st.data_ptr(), _stream(stream))
+        return d, st
+
+    def n_movable(self):
+        n = B.mesh_classes(self.handle)
+        off = np.empty(n + 1, dtype=np.int64)
+        B.mesh_classes(self.handle, off.ctypes.data_as(ctypes.c_void_p).value)
+        return int(off[-1])
+
     def close(self):
         if self.handle:
             B.mesh_free(self.handle)

@@ -46,7 +46,8 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "reserve_workspace", "gather_roofline", "read_stage_times", "autotune",
            "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
            "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
-           "mesh_info", "objective_eval", "objective_delta", "mesh_free")
+           "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
+           "anneal_moves", "anneal_sweep")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -158,6 +159,14 @@ _lib.objective_delta.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), _P, _P
 _lib.objective_delta.restype = _I
 _lib.mesh_free.argtypes = [_P]
 _lib.mesh_free.restype = None
+_lib.mesh_classes.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), _P, _P]
+_lib.mesh_classes.restype = _I
+_lib.anneal_moves.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double, _P, _P, _P,
+                              _I64, _P, _P, _P]
+_lib.anneal_moves.restype = _I
+_lib.anneal_sweep.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double, _P, _P, _P,
+                              _P, _P]
+_lib.anneal_sweep.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -282,6 +291,24 @@ def objective_delta(mesh: int, xy: int, params: ObjectiveParams, vid: int, q_xy:
                     delta: int, status: int, stream: int = 0) -> None:
     _check(_lib.objective_delta(_P(mesh), _P(xy), ctypes.byref(params), _P(vid), _P(q_xy), k,
                                 _P(delta), _P(status), _P(stream)))
+
+
+def mesh_classes(mesh: int, class_off: int = 0, class_v: int = 0) -> int:
+    n = ctypes.c_int32()
+    _check(_lib.mesh_classes(_P(mesh), ctypes.byref(n), _P(class_off), _P(class_v)))
+    return n.value
+
+
+def anneal_moves(mesh: int, xy: int, params: ObjectiveParams, temperature: float, vid: int,
+                 disp: int, u: int, k: int, delta: int, status: int, stream: int = 0) -> None:
+    _check(_lib.anneal_moves(_P(mesh), _P(xy), ctypes.byref(params), temperature, _P(vid), _P(disp),
+                             _P(u), k, _P(delta), _P(status), _P(stream)))
+
+
+def anneal_sweep(mesh: int, xy: int, params: ObjectiveParams, temperature: float, disp: int,
+                 u: int, delta: int, status: int, stream: int = 0) -> None:
+    _check(_lib.anneal_sweep(_P(mesh), _P(xy), ctypes.byref(params), temperature, _P(disp), _P(u),
+                             _P(delta), _P(status), _P(stream)))
 
 
 def mesh_free(mesh: int) -> None:

@@ -336,58 +336,160 @@ struct MoveCtx {
   }
 };
 
-__global__ void __launch_bounds__(kThreads)
-move_delta(MeshDev m, Par p, const int32_t* __restrict__ vid, const double2* __restrict__ qv,
-           int64_t k, double* __restrict__ delta, int32_t* __restrict__ status) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= k) return;
-  const double2* __restrict__ xy = m.xyi;
-  const int cv = vid[i];
-  const double2 q = qv[i];
-  const double inf = __builtin_huge_val();
-  if (cv < 0 || cv >= m.nv || !isfinite(q.x) || !isfinite(q.y)) {
-    status[i] = CCSP_MOVE_BAD;
-    delta[i] = inf;
-    return;
-  }
+// Status and change of f (through *df, +inf unless valid) of moving the vertex of caller id cv
+// to q, against positions xy (internal order) and the per-edge scratch of edge_state. nb is this
+// thread's LDS column for the vertex's neighbours.
+__device__ __forceinline__ int evaluate_move(const MeshDev& m, const double2* __restrict__ xy,
+                                             const Par& p, int cv, double2 q, int* nb, double* df) {
+  *df = __builtin_huge_val();
+  if (cv < 0 || cv >= m.nv || !isfinite(q.x) || !isfinite(q.y)) return CCSP_MOVE_BAD;
   const int v = m.vnew[cv];
-  if (m.vk[v].x == CCSP_VERTEX_ORIGINAL) {
-    status[i] = CCSP_MOVE_FIXED;
-    delta[i] = inf;
-    return;
-  }
+  if (m.vk[v].x == CCSP_VERTEX_ORIGINAL) return CCSP_MOVE_FIXED;
   double sa = 0.0;
   for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j) {
     const int4 t = m.tri[m.vtri[j]];
-    if (orient_sign(pos(xy, t.x, v, q), pos(xy, t.y, v, q), pos(xy, t.z, v, q)) <= 0) {
-      status[i] = CCSP_MOVE_FOLDS;
-      delta[i] = inf;
-      return;
-    }
+    if (orient_sign(pos(xy, t.x, v, q), pos(xy, t.y, v, q), pos(xy, t.z, v, q)) <= 0)
+      return CCSP_MOVE_FOLDS;
     sa += triangle_angles(xy, t, v, q, p.delta, p.polish) -
           triangle_angles(xy, t, -1, q, p.delta, p.polish);
   }
-  __shared__ int snb[kLdsNbrs * kThreads];
   const int a0 = m.adj_off[v], deg = m.adj_off[v + 1] - a0;
-  int* nb = snb + threadIdx.x;
   if (deg <= kLdsNbrs)
     for (int j = 0; j < deg; ++j) nb[j * kThreads] = m.adj[a0 + j].x;
   const MoveCtx ctx{m, xy, p, v, q, nb, deg};
   double se = 0.0, ss = 0.0;
-  for (int j = m.adj_off[v], end = m.adj_off[v + 1]; j < end; ++j) {
+  for (int j = a0, end = a0 + deg; j < end; ++j) {
     const int e = m.adj[j].y;
     se += ctx.visit(e);
     ss += short_term(ctx.len(e, true), p.eps0) - short_term(m.len[e], p.eps0);
   }
-  for (int j = m.adj_off[v], end = m.adj_off[v + 1]; j < end; ++j) {
+  for (int j = a0, end = a0 + deg; j < end; ++j) {
     const int a = m.adj[j].x;
     for (int l = m.adj_off[a], lend = m.adj_off[a + 1]; l < lend; ++l) {
       const int2 be = m.adj[l];
       if (be.x > a && ctx.adjacent(be.x)) se += ctx.visit(be.y);
     }
   }
-  status[i] = CCSP_MOVE_OK;
-  delta[i] = se + p.mu_angle * sa + p.mu_len * ss;
+  *df = se + p.mu_angle * sa + p.mu_len * ss;
+  return CCSP_MOVE_OK;
+}
+
+__global__ void __launch_bounds__(kThreads)
+move_delta(MeshDev m, Par p, const int32_t* __restrict__ vid, const double2* __restrict__ qv,
+           int64_t k, double* __restrict__ delta, int32_t* __restrict__ status) {
+  __shared__ int snb[kLdsNbrs * kThreads];
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= k) return;
+  double df;
+  status[i] = evaluate_move(m, m.xyi, p, vid[i], qv[i], snb + threadIdx.x, &df);
+  delta[i] = df;
+}
+
+// Metropolis moves (Sec. 3.1): vertex vid[i] displaced by disp[i] (projected on its original edge
+// when constrained), accepted when valid and delta <= 0 or u[i] < exp(-delta / temperature);
+// accepted positions are written to the caller's xy. Every move is evaluated against the
+// positions before the call (xyi).
+__global__ void __launch_bounds__(kThreads)
+anneal_moves(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out,
+             const int32_t* __restrict__ vid, const double2* __restrict__ disp,
+             const double* __restrict__ u, int64_t k, double* __restrict__ delta,
+             int32_t* __restrict__ status) {
+  __shared__ int snb[kLdsNbrs * kThreads];
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= k) return;
+  const int cv = vid[i];
+  double2 q = make_double2(__builtin_nan(""), 0.0);
+  if (cv >= 0 && cv < m.nv) {
+    const int v = m.vnew[cv];
+    const double2 o = m.xyi[v];
+    double2 d = disp[i];
+    const int2 kl = m.vk[v];
+    if (kl.x == CCSP_VERTEX_CONSTRAINED) {
+      const int2 ends = m.prim_v[kl.y];
+      const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
+      const double ex = b.x - a.x, ey = b.y - a.y;
+      const double s = (d.x * ex + d.y * ey) / (ex * ex + ey * ey);
+      d = make_double2(s * ex, s * ey);
+    }
+    q = make_double2(o.x + d.x, o.y + d.y);
+  }
+  double df;
+  int st = evaluate_move(m, m.xyi, p, cv, q, snb + threadIdx.x, &df);
+  if (st == CCSP_MOVE_OK) {
+    if (df <= 0.0 || u[i] < exp(-df / temperature))
+      xy_out[cv] = q;
+    else
+      st = CCSP_MOVE_REJECTED;
+  }
+  status[i] = st;
+  delta[i] = df;
+}
+
+// After an accepted move of internal vertex v (already at its new position in m.xyi): recompute
+// the scratch of the edges whose values depend on v's position, with the operations of
+// edge_state: length and c of its edges, contractibility and c of the edges joining two of its
+// neighbours (v may be an opposite or 1-hop vertex of those).
+__device__ __forceinline__ void refresh_scratch(const MeshDev& m, const Par& p, int v) {
+  const double2* __restrict__ xy = m.xyi;
+  const int a0 = m.adj_off[v], a1 = m.adj_off[v + 1];
+  for (int j = a0; j < a1; ++j) {
+    const int e = m.adj[j].y;
+    const int2 ab = m.edge_v[e];
+    const double len = dist(xy[ab.x], xy[ab.y]);
+    m.len[e] = len;
+    m.c[e] = c_of_len(m.contr[e] != 0, len, p.eps);
+  }
+  for (int j = a0; j < a1; ++j) {
+    const int a = m.adj[j].x;
+    for (int l = m.adj_off[a], lend = m.adj_off[a + 1]; l < lend; ++l) {
+      const int2 be = m.adj[l];
+      if (be.x <= a || !is_neighbour(m, v, be.x)) continue;
+      const int e = be.y;
+      const bool ok = direct_ok(m, a, be.x) &&
+                      one_hop_ok(m, xy, e, m.edge_opp[e], p.eps, -1, make_double2(0, 0));
+      m.contr[e] = ok ? 1 : 0;
+      m.c[e] = c_of_len(ok, m.len[e], p.eps);
+    }
+  }
+}
+
+// One class of a sweep: Metropolis steps for its vertices (internal ids), which are pairwise more
+// than four edges apart, so that each thread's reads (within four edges of its vertex) and writes
+// (its position, and scratch of edges within one edge of it) never meet another thread's.
+__global__ void __launch_bounds__(kThreads)
+anneal_class(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out,
+             const int32_t* __restrict__ cls, const double2* __restrict__ disp,
+             const double* __restrict__ u, int n, double* __restrict__ delta,
+             int32_t* __restrict__ status) {
+  __shared__ int snb[kLdsNbrs * kThreads];
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int v = cls[i];
+  const int cv = m.vold[v];
+  const double2 o = m.xyi[v];
+  double2 d = disp[i];
+  const int2 kl = m.vk[v];
+  if (kl.x == CCSP_VERTEX_CONSTRAINED) {
+    const int2 ends = m.prim_v[kl.y];
+    const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
+    const double ex = b.x - a.x, ey = b.y - a.y;
+    const double s = (d.x * ex + d.y * ey) / (ex * ex + ey * ey);
+    d = make_double2(s * ex, s * ey);
+  }
+  const double2 q = make_double2(o.x + d.x, o.y + d.y);
+  double df;
+  int st = evaluate_move(m, m.xyi, p, cv, q, snb + threadIdx.x, &df);
+  if (st == CCSP_MOVE_OK) {
+    if (df <= 0.0 || u[i] < exp(-df / temperature)) {
+      m.xyi[v] = q;
+      xy_out[cv] = q;
+      refresh_scratch(m, p, v);
+    } else {
+      st = CCSP_MOVE_REJECTED;
+    }
+  }
+  status[i] = st;
+  delta[i] = df;
 }
 
 }  // namespace
@@ -400,6 +502,9 @@ struct MovableMesh {
   ccsp::MeshDev d{};
   void* mem = nullptr;
   std::vector<int32_t> edge_v;  // 2E in the caller's numbering, for mesh_info
+  std::vector<int64_t> class_off;  // mesh_classes, computed on the first call
+  std::vector<int32_t> class_v;    // caller ids, class by class
+  int32_t* class_dev = nullptr;    // the same vertices, internal ids, on the device
 };
 
 namespace {
@@ -808,8 +913,148 @@ int objective_delta(MovableMesh* mesh, const double* xy, const ObjectiveParams* 
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_delta: launch");
 }
 
+int ensure_classes(MovableMesh* mesh) {
+  if (mesh->class_off.empty()) {
+    if (int r = check_device(mesh)) return r;
+    const ccsp::MeshDev& d = mesh->d;
+    const int64_t V = d.nv;
+    std::vector<int32_t> adj_off(V + 1), adj(4 * (int64_t)d.ne), vk(2 * V), vold(V);
+    hipError_t e = hipMemcpy(adj_off.data(), d.adj_off, 4 * (V + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(adj.data(), d.adj, 16 * (size_t)d.ne, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(vk.data(), d.vk, 8 * V, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(vold.data(), d.vold, 4 * V, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "mesh_classes: hipMemcpy");
+    // greedy colouring: each movable vertex takes the smallest class not used by a movable
+    // vertex within four edges
+    std::vector<int32_t> colour(V, -1), stamp(V, -1), ball, used;
+    int32_t n = 0;
+    for (int64_t v = 0; v < V; ++v) {
+      if (vk[2 * v] == CCSP_VERTEX_ORIGINAL) continue;
+      ball.assign(1, (int32_t)v);
+      stamp[v] = (int32_t)v;
+      size_t lo = 0;
+      for (int r = 0; r < 4; ++r) {
+        const size_t hi = ball.size();
+        for (size_t j = lo; j < hi; ++j)
+          for (int32_t k = adj_off[ball[j]]; k < adj_off[ball[j] + 1]; ++k) {
+            const int32_t w = adj[2 * k];
+            if (stamp[w] != (int32_t)v) {
+              stamp[w] = (int32_t)v;
+              ball.push_back(w);
+            }
+          }
+        lo = hi;
+      }
+      used.assign(n + 1, 0);
+      for (int32_t w : ball)
+        if (colour[w] >= 0) used[colour[w]] = 1;
+      int32_t c = 0;
+      while (used[c]) ++c;
+      colour[v] = c;
+      n = std::max(n, c + 1);
+    }
+    std::vector<int64_t> off(n + 1, 0);
+    for (int64_t v = 0; v < V; ++v)
+      if (colour[v] >= 0) ++off[colour[v] + 1];
+    for (int32_t c = 0; c < n; ++c) off[c + 1] += off[c];
+    std::vector<int32_t> cv(off[n]), ci(off[n]);
+    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+    for (int64_t v = 0; v < V; ++v)
+      if (colour[v] >= 0) {
+        ci[fill[colour[v]]] = (int32_t)v;
+        cv[fill[colour[v]]++] = vold[v];
+      }
+    if (n == 0) off.assign(1, 0);
+    if (!ci.empty()) {
+      e = hipMalloc(&mesh->class_dev, 4 * ci.size());
+      if (e != hipSuccess) return fail(CCSP_E_OOM, "mesh_classes: device allocation failed");
+      e = hipMemcpy(mesh->class_dev, ci.data(), 4 * ci.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        (void)hipFree(mesh->class_dev);
+        mesh->class_dev = nullptr;
+        return hip_fail(e, "mesh_classes: hipMemcpy");
+      }
+    }
+    mesh->class_off = std::move(off);
+    mesh->class_v = std::move(cv);
+  }
+  return CCSP_OK;
+}
+
+int mesh_classes(MovableMesh* mesh, int32_t* n_classes, int64_t* class_off, int32_t* class_v) {
+  if (!mesh || !n_classes) return fail(CCSP_E_ARG, "mesh_classes: null argument");
+  if (int r = ensure_classes(mesh)) return r;
+  *n_classes = (int32_t)mesh->class_off.size() - 1;
+  if (class_off) std::memcpy(class_off, mesh->class_off.data(), 8 * mesh->class_off.size());
+  if (class_v) std::memcpy(class_v, mesh->class_v.data(), 4 * mesh->class_v.size());
+  return CCSP_OK;
+}
+
+int anneal_moves(MovableMesh* mesh, double* xy, const ObjectiveParams* params, double temperature,
+                 const int32_t* vid, const double* disp, const double* u, int64_t k, double* delta,
+                 int32_t* status, void* stream) {
+  if (!mesh || !xy || k < 0) return fail(CCSP_E_ARG, "anneal_moves: null argument or k < 0");
+  if (k > 0 && (!vid || !disp || !u || !delta || !status))
+    return fail(CCSP_E_ARG, "anneal_moves: null argument");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)disp & 15) != 0 || ((uintptr_t)u & 7) != 0 ||
+      ((uintptr_t)delta & 7) != 0 || ((uintptr_t)vid & 3) != 0 || ((uintptr_t)status & 3) != 0)
+    return fail(CCSP_E_ARG, "anneal_moves: misaligned buffer");
+  if (!check_params(params)) return fail(CCSP_E_ARG, "anneal_moves: invalid parameters");
+  if (!(temperature >= 0) || !std::isfinite(temperature))
+    return fail(CCSP_E_ARG, "anneal_moves: temperature must be finite and >= 0");
+  if (k >= (int64_t(1) << 40)) return fail(CCSP_E_ARG, "anneal_moves: too many moves");
+  if (int r = check_device(mesh)) return r;
+  if (k == 0) return CCSP_OK;
+  const ccsp::MeshDev& d = mesh->d;
+  const ccsp::Par p = to_par(params);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy);
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
+                     d.partial);
+  const int64_t blocks = (k + ccsp::kThreads - 1) / ccsp::kThreads;
+  hipLaunchKernelGGL(ccsp::anneal_moves, dim3((unsigned)blocks), dim3(ccsp::kThreads), 0, s, d, p,
+                     temperature, (double2*)xy, vid, (const double2*)disp, u, k, delta, status);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_moves: launch");
+}
+
+int anneal_sweep(MovableMesh* mesh, double* xy, const ObjectiveParams* params, double temperature,
+                 const double* disp, const double* u, double* delta, int32_t* status,
+                 void* stream) {
+  if (!mesh || !xy || !disp || !u || !delta || !status)
+    return fail(CCSP_E_ARG, "anneal_sweep: null argument");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)disp & 15) != 0 || ((uintptr_t)u & 7) != 0 ||
+      ((uintptr_t)delta & 7) != 0 || ((uintptr_t)status & 3) != 0)
+    return fail(CCSP_E_ARG, "anneal_sweep: misaligned buffer");
+  if (!check_params(params)) return fail(CCSP_E_ARG, "anneal_sweep: invalid parameters");
+  if (!(temperature >= 0) || !std::isfinite(temperature))
+    return fail(CCSP_E_ARG, "anneal_sweep: temperature must be finite and >= 0");
+  if (int r = check_device(mesh)) return r;
+  if (int r = ensure_classes(mesh)) return r;
+  const ccsp::MeshDev& d = mesh->d;
+  const ccsp::Par p = to_par(params);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy);
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
+                     d.partial);
+  const std::vector<int64_t>& off = mesh->class_off;
+  for (size_t c = 0; c + 1 < off.size(); ++c) {
+    const int n = (int)(off[c + 1] - off[c]);
+    if (n == 0) continue;
+    hipLaunchKernelGGL(ccsp::anneal_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
+                       dim3(ccsp::kThreads), 0, s, d, p, temperature, (double2*)xy,
+                       mesh->class_dev + off[c], (const double2*)disp + off[c], u + off[c], n,
+                       delta + off[c], status + off[c]);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_sweep: launch");
+}
+
 void mesh_free(MovableMesh* mesh) {
   if (!mesh) return;
+  if (mesh->class_dev) (void)hipFree(mesh->class_dev);
   if (mesh->mem) (void)hipFree(mesh->mem);
   delete mesh;
 }

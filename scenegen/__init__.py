@@ -247,6 +247,22 @@ def vertex_moves(mesh: MovableMesh, n: int, seed: int, lam: float) -> tuple:
     return v.astype(np.int32), np.ascontiguousarray(mesh.xy[v] + d)
 
 
+def vertex_displacements(mesh: MovableMesh, vid, seed: int, lam: float) -> np.ndarray:
+    """Displacements lam * eta * xi for the given vertices, drawn as in vertex_moves (not yet
+    projected on original edges)."""
+    vid = np.asarray(vid, dtype=np.int64)
+    rng = np.random.default_rng(subseed(seed, TAG_MOVES, 1))
+    u = rng.random((vid.shape[0], 3))
+    r = np.sqrt(u[:, 0]) * (1.0 - u[:, 2]) ** -2.0
+    th = 2.0 * np.pi * u[:, 1]
+    p = mesh.xy[mesh.tri_v]
+    area = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+                  - (p[:, 1, 1] - p[:, 0, 1]) * (p[:, 2, 0] - p[:, 0, 0]))
+    star = np.bincount(mesh.tri_v.ravel(), weights=np.repeat(area, 3), minlength=mesh.n_vertices)
+    return np.ascontiguousarray((lam * np.sqrt(star[vid]) * r)[:, None]
+                                * np.stack([np.cos(th), np.sin(th)], 1))
+
+
 def random_segments(seed, n, mid_lo, mid_hi, len_lo, len_hi, log_len, box_lo, box_hi,
                     max_draws=None) -> np.ndarray:
     out = np.empty((n, 4), dtype=np.float64)

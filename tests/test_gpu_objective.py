@@ -205,3 +205,148 @@ def test_grid_eval_and_sampled_deltas(ccsp, grid):
     _check_deltas(om, mesh.xy, p, v, q, d, st, "grid", idx=idx)
     for i in np.concatenate([ok[:60], folded[:60]]):
         assert st[i] == ob.move_status(om, mesh.xy, int(v[i]), q[i])
+
+
+def _ball(om, v, r):
+    seen, front = {v}, [v]
+    for _ in range(r):
+        nxt = []
+        for a in front:
+            for w in om.nbr[om.nbr_off[a]:om.nbr_off[a + 1]].tolist():
+                if w not in seen:
+                    seen.add(w)
+                    nxt.append(w)
+        front = nxt
+    return seen
+
+
+def test_classes_partition_and_separation(ccsp, tiny):
+    """Every movable vertex is in exactly one class; members of a class are more than four edges
+    apart."""
+    mesh, om = tiny
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        cls = gm.classes()
+    assert np.array_equal(np.sort(np.concatenate(cls)), np.nonzero(mesh.kind != sg.ORIGINAL)[0])
+    for c in cls:
+        s = set(c.tolist())
+        for v in c.tolist():
+            assert not (_ball(om, v, 4) & s) - {v}, f"class members within four edges of {v}"
+
+
+def _sweep(ccsp, gm, params, xy0, cls, disp, u, temperature):
+    X = torch.from_numpy(xy0.copy()).to(DEV)
+    sts, dfs, off = [], [], 0
+    for c in cls:
+        k = c.shape[0]
+        d, st = gm.anneal(X, params, temperature, torch.from_numpy(c).to(DEV),
+                          torch.from_numpy(disp[off:off + k]).to(DEV),
+                          torch.from_numpy(u[off:off + k]).to(DEV))
+        sts.append(st.cpu().numpy())
+        dfs.append(d.cpu().numpy())
+        off += k
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), np.concatenate(sts), np.concatenate(dfs)
+
+
+@pytest.mark.parametrize("state,temperature", [("subdivided", 1e-3), ("clustered", 1e-4),
+                                               ("subdivided", 0.0), ("clustered", 1e-2)])
+def test_anneal_sweep_equals_sequential_chain(ccsp, tiny, state, temperature):
+    """One sweep over all classes equals the checker's Metropolis chain over the same moves in the
+    same order: positions bit for bit, statuses equal, changes of f within rounding."""
+    mesh, om = tiny
+    p = ob.Params(0.03)
+    xy0 = mesh.xy.copy() if state == "subdivided" else _clustered(mesh, om, p, 9)
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        cls = gm.classes()
+        order = np.concatenate(cls)
+        disp = sg.vertex_displacements(mesh, order, 3, 0.05)
+        u = np.random.default_rng(5).random(order.shape[0])
+        xy_gpu, st_gpu, df_gpu = _sweep(ccsp, gm, _params(ccsp, p), xy0, cls, disp, u, temperature)
+        X = torch.from_numpy(xy0.copy()).to(DEV)
+        d_s, st_s = gm.sweep(X, _params(ccsp, p), temperature, torch.from_numpy(disp).to(DEV),
+                             torch.from_numpy(u).to(DEV))
+        xy_s, st_s, d_s = X.cpu().numpy(), st_s.cpu().numpy(), d_s.cpu().numpy()
+    # the whole sweep in one call equals the class-by-class calls
+    assert np.array_equal(xy_s, xy_gpu) and np.array_equal(st_s, st_gpu)
+    assert np.array_equal(d_s, df_gpu)
+    xy_ref, st_ref, df_ref, margin = ob.metropolis_chain(om, xy0, p, temperature, order, disp, u)
+    valid = (st_ref == ob.ACCEPTED) | (st_ref == ob.REJECTED)
+    assert (margin[valid] > 1e-10).all(), "a decision lies within rounding of its threshold"
+    assert np.array_equal(st_gpu, st_ref), np.nonzero(st_gpu != st_ref)[0][:5]
+    assert np.array_equal(xy_gpu, xy_ref)
+    fin = np.isfinite(df_ref)
+    assert np.array_equal(np.isfinite(df_gpu), fin)
+    assert np.allclose(df_gpu[fin], df_ref[fin], rtol=1e-9, atol=1e-13)
+    assert (st_ref == ob.ACCEPTED).sum() > 20
+    if temperature > 0:
+        assert (st_ref == ob.REJECTED).sum() > 0
+
+
+def test_anneal_class_at_scale(ccsp, grid):
+    """Subdivided grid scene: a class applied in one call or in two halves gives the same
+    positions; the accepted changes add up to the change of f; a sample agrees with the checker;
+    sampled members are more than four edges apart."""
+    mesh, om = grid
+    p = ob.Params(0.2)
+    temperature = 1e-3
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        cls = gm.classes()
+        assert len(cls) > 20
+        c = max(cls, key=len)
+        disp = sg.vertex_displacements(mesh, c, 7, 0.05)
+        u = np.random.default_rng(8).random(c.shape[0])
+        params = _params(ccsp, p)
+        X0 = torch.from_numpy(mesh.xy).to(DEV)
+        X1 = X0.clone()
+        d1, s1 = gm.anneal(X1, params, temperature, torch.from_numpy(c).to(DEV),
+                           torch.from_numpy(disp).to(DEV), torch.from_numpy(u).to(DEV))
+        X2 = X0.clone()
+        h = c.shape[0] // 2
+        for lo, hi in ((0, h), (h, c.shape[0])):
+            gm.anneal(X2, params, temperature, torch.from_numpy(c[lo:hi]).to(DEV),
+                      torch.from_numpy(disp[lo:hi]).to(DEV), torch.from_numpy(u[lo:hi]).to(DEV))
+        assert torch.equal(X1, X2)
+        f0 = gm.eval(X0, params).cpu().numpy()[0]
+        f1 = gm.eval(X1, params).cpu().numpy()[0]
+        d1, s1 = d1.cpu().numpy(), s1.cpu().numpy()
+    acc = s1 == 1
+    assert acc.sum() > 1000 and (s1 == 2).sum() > 0
+    assert abs((f1 - f0) - d1[acc].sum()) <= 1e-9 * abs(f0)
+    base = ob.terms(om, mesh.xy, p)
+    for i in np.nonzero(acc)[0][:3]:
+        q = mesh.xy[c[i]] + ob.project(om, mesh.xy, int(c[i]), disp[i])
+        rs, rd, bound = ob.delta_f(om, mesh.xy, p, int(c[i]), q, base=base)
+        assert rs == ob.MOVED and abs(rd - d1[i]) <= 1e-12 * bound
+    s = set(c.tolist())
+    for v in c[:: max(1, c.shape[0] // 40)].tolist():
+        assert not (_ball(om, v, 4) & s) - {v}
+
+
+def test_sweep_at_scale_equals_class_calls(ccsp, grid):
+    """Subdivided grid scene: two sweeps in single calls (scratch refreshed in the kernel after each
+    accepted move) equal the same moves made class by class with a full recomputation per call."""
+    mesh, om = grid
+    p = ob.Params(0.2)
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        cls = gm.classes()
+        order = np.concatenate(cls)
+        params = _params(ccsp, p)
+        XA = torch.from_numpy(mesh.xy).to(DEV)
+        XB = XA.clone()
+        for sweep, temperature in ((0, 1e-2), (1, 1e-3)):
+            disp = sg.vertex_displacements(mesh, order, 40 + sweep, 0.05)
+            u = np.random.default_rng(50 + sweep).random(order.shape[0])
+            dA, sA = gm.sweep(XA, params, temperature, torch.from_numpy(disp).to(DEV),
+                              torch.from_numpy(u).to(DEV))
+            off = 0
+            sB = []
+            for c in cls:
+                k = c.shape[0]
+                _, s = gm.anneal(XB, params, temperature, torch.from_numpy(c).to(DEV),
+                                 torch.from_numpy(disp[off:off + k]).to(DEV),
+                                 torch.from_numpy(u[off:off + k]).to(DEV))
+                sB.append(s)
+                off += k
+            assert torch.equal(XA, XB), f"sweep {sweep}: positions differ"
+            assert torch.equal(sA, torch.cat(sB))
+            assert (sA == 1).sum().item() > 10000

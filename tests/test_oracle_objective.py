@@ -249,3 +249,30 @@ def test_delta_properties():
               key=lambda w: np.linalg.norm(xy[w] - xy[free]))
     beyond = xy[free] + 2.0 * (xy[far] - xy[free])
     assert ob.delta_f(m, xy, p, free, beyond)[0] == ob.FOLDED
+
+
+def test_metropolis_chain_properties():
+    """T = 0 accepts exactly the moves that do not increase f, so f never rises and the accepted
+    changes add up to the change of f; a huge T accepts every valid move; constrained vertices stay
+    on their original edges."""
+    mesh = sg.subdivide(sg.make_scene("tiny"))
+    m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+    p = ob.Params(0.03)
+    rng = np.random.default_rng(4)
+    vid = rng.choice(np.nonzero(mesh.kind != sg.ORIGINAL)[0], 150)
+    disp = sg.vertex_displacements(mesh, vid, 2, 0.05)
+    u = rng.random(150)
+    f0 = ob.objective(m, mesh.xy, p)["f"]
+    xy, st, df, _ = ob.metropolis_chain(m, mesh.xy, p, 0.0, vid, disp, u)
+    acc = st == ob.ACCEPTED
+    assert acc.any() and (st == ob.REJECTED).any()
+    assert (df[acc] <= 0).all() and (df[st == ob.REJECTED] > 0).all()
+    f1 = ob.objective(m, xy, p)["f"]
+    assert f1 <= f0 and abs((f1 - f0) - df[acc].sum()) <= 1e-12 * f0 * m.n_edges
+    _, st_hot, _, _ = ob.metropolis_chain(m, mesh.xy, p, 1e300, vid, disp, u)
+    assert ((st_hot == ob.ACCEPTED) | (st_hot == ob.FOLDED)).all()
+    con = mesh.kind == sg.CONSTRAINED
+    a, b = mesh.xy[mesh.prim_v[mesh.line[con]]].transpose(1, 0, 2)
+    c = xy[con]
+    cross = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
+    assert (np.abs(cross) <= 1e-12 * (np.abs(b - a).sum(1) * (np.abs(c - a).sum(1) + 1))).all()
