@@ -343,6 +343,48 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
     ms_delta, (d, st) = timed(lambda: gm.delta(xy, p, vid, qd), max(1, steps // 2), 1)
     f, wc, pa, pl = out.cpu().tolist()
     ok = int((st == 1).sum().item())
+
+    # Metropolis sweeps (Sec. 3.1): every movable vertex once per sweep, class by class, moves of
+    # Sec. 3.2.2 with eta from the starting positions, at a fixed point of the schedule
+    t1 = time.time()
+    classes = gm.classes()
+    t_classes = time.time() - t1
+    order = torch.from_numpy(np.concatenate(classes).astype(np.int64)).cuda()
+    n_mov = int(order.shape[0])
+    tri = torch.from_numpy(mesh.tri_v.astype(np.int64)).cuda()
+    pt = xy[tri]
+    area = 0.5 * ((pt[:, 1, 0] - pt[:, 0, 0]) * (pt[:, 2, 1] - pt[:, 0, 1])
+                  - (pt[:, 1, 1] - pt[:, 0, 1]) * (pt[:, 2, 0] - pt[:, 0, 0]))
+    star = torch.zeros(mesh.n_vertices, dtype=torch.float64, device=xy.device)
+    star.index_add_(0, tri.reshape(-1), area.repeat_interleave(3))
+    eta = torch.sqrt(star[order]) * 0.05
+    gen = torch.Generator(device=xy.device)
+    gen.manual_seed(0)
+    n_sweeps = max(2, steps // 2)
+    draws = []
+    for _ in range(n_sweeps + 1):
+        r = torch.rand((n_mov, 3), generator=gen, device=xy.device, dtype=torch.float64)
+        rad = torch.sqrt(r[:, 0]) * (1.0 - r[:, 2]) ** -2.0 * eta
+        th = 2.0 * np.pi * r[:, 1]
+        disp = torch.stack([rad * torch.cos(th), rad * torch.sin(th)], 1).contiguous()
+        draws.append((disp, torch.rand(n_mov, generator=gen, device=xy.device,
+                                       dtype=torch.float64)))
+    X = xy.clone()
+    temperature = 1e-3 * size
+    gm.sweep(X, p, temperature, *draws[0])  # warm-up sweep
+    f_before = gm.eval(X, p).cpu().tolist()[0]
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    accepted = torch.zeros((), dtype=torch.int64, device=xy.device)
+    a.record()
+    for k in range(n_sweeps):
+        _, sst = gm.sweep(X, p, temperature, *draws[k + 1])
+        accepted += (sst == 1).sum()
+    b.record()
+    torch.cuda.synchronize()
+    ms_sweep = a.elapsed_time(b) / n_sweeps
+    f_after = gm.eval(X, p).cpu().tolist()[0]
+    del draws
     comp = (OBJ_BYTES_PER_VERTEX * mesh.n_vertices + OBJ_BYTES_PER_EDGE * gm.n_edges
             + OBJ_BYTES_PER_TRIANGLE * mesh.n_triangles)
     achieved = comp / (ms_eval * 1e-3) / 1e9
@@ -353,6 +395,11 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
         "eval_ms": ms_eval, "edges_per_s": gm.n_edges / ms_eval * 1e3,
         "delta_ms": ms_delta, "moves_per_s": moves / ms_delta * 1e3,
         "valid_moves": ok, "f": f, "w_contr": wc, "p_angle": pa, "p_len": pl,
+        "anneal": {"classes": len(classes), "movable_vertices": n_mov,
+                   "classes_host_s": t_classes, "temperature": temperature,
+                   "sweep_ms": ms_sweep, "vertex_moves_per_s": n_mov / ms_sweep * 1e3,
+                   "acceptance": int(accepted.item()) / (n_mov * n_sweeps), "sweeps": n_sweeps,
+                   "f_before": f_before, "f_after": f_after},
         "roofline_eval": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                           "bytes_per_eval": comp},

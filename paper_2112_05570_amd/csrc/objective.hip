@@ -10,7 +10,8 @@
 //
 // A move changes only terms near its vertex v. With N(v) the neighbours of v, the edges whose c
 // can change ("C-edges") are those incident to v (length) and those joining two vertices of N(v)
-// (v may be an opposite vertex or a 1-hop vertex of such an edge). The edges whose weight can
+// (v may be an opposite vertex or a 1-hop vertex of such an edge), found by looking up each pair of
+// neighbours, so that a neighbour with a long row (the apex of a fan) costs one binary search. The edges whose weight can
 // change are the C-edges and the other edges of the triangles holding a C-edge. One thread per
 // move visits each of these edges once, using the canonical choice of the triangle that reports
 // it, and sums new minus old terms; the angle terms of the triangles of v and the length terms of
@@ -128,6 +129,23 @@ __device__ bool is_neighbour(const MeshDev& m, int v, int x) {
     if (y < x) lo = mid + 1; else hi = mid;
   }
   return false;
+}
+
+// Id of the edge joining a and b, or -1: binary search in the shorter of the two rows.
+__device__ __forceinline__ int find_edge(const MeshDev& m, int a, int b) {
+  if (m.adj_off[a + 1] - m.adj_off[a] > m.adj_off[b + 1] - m.adj_off[b]) {
+    const int t = a;
+    a = b;
+    b = t;
+  }
+  int lo = m.adj_off[a], hi = m.adj_off[a + 1];
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int2 y = m.adj[mid];
+    if (y.x == b) return y.y;
+    if (y.x < b) lo = mid + 1; else hi = mid;
+  }
+  return -1;
 }
 
 // Restrictions of the original geometry (Sec. 2.2.2).
@@ -363,13 +381,12 @@ __device__ __forceinline__ int evaluate_move(const MeshDev& m, const double2* __
     se += ctx.visit(e);
     ss += short_term(ctx.len(e, true), p.eps0) - short_term(m.len[e], p.eps0);
   }
-  for (int j = a0, end = a0 + deg; j < end; ++j) {
-    const int a = m.adj[j].x;
-    for (int l = m.adj_off[a], lend = m.adj_off[a + 1]; l < lend; ++l) {
-      const int2 be = m.adj[l];
-      if (be.x > a && ctx.adjacent(be.x)) se += ctx.visit(be.y);
+  // edges joining two neighbours of v: pairs of its (increasing) neighbour row
+  for (int j = a0, end = a0 + deg; j < end; ++j)
+    for (int l = j + 1; l < end; ++l) {
+      const int e = find_edge(m, m.adj[j].x, m.adj[l].x);
+      if (e >= 0) se += ctx.visit(e);
     }
-  }
   *df = se + p.mu_angle * sa + p.mu_len * ss;
   return CCSP_MOVE_OK;
 }
@@ -439,18 +456,16 @@ __device__ __forceinline__ void refresh_scratch(const MeshDev& m, const Par& p, 
     m.len[e] = len;
     m.c[e] = c_of_len(m.contr[e] != 0, len, p.eps);
   }
-  for (int j = a0; j < a1; ++j) {
-    const int a = m.adj[j].x;
-    for (int l = m.adj_off[a], lend = m.adj_off[a + 1]; l < lend; ++l) {
-      const int2 be = m.adj[l];
-      if (be.x <= a || !is_neighbour(m, v, be.x)) continue;
-      const int e = be.y;
-      const bool ok = direct_ok(m, a, be.x) &&
+  for (int j = a0; j < a1; ++j)
+    for (int l = j + 1; l < a1; ++l) {
+      const int a = m.adj[j].x, b = m.adj[l].x;
+      const int e = find_edge(m, a, b);
+      if (e < 0) continue;
+      const bool ok = direct_ok(m, a, b) &&
                       one_hop_ok(m, xy, e, m.edge_opp[e], p.eps, -1, make_double2(0, 0));
       m.contr[e] = ok ? 1 : 0;
       m.c[e] = c_of_len(ok, m.len[e], p.eps);
     }
-  }
 }
 
 // One class of a sweep: Metropolis steps for its vertices (internal ids), which are pairwise more
