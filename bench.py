@@ -35,7 +35,7 @@ BYTES_PER_RAY = 60
 WALK_SOURCES = ("walk_kernels.hip", "walk.hpp", "decide.hpp", "exact.hpp")
 MEASURED_TRAFFIC = {
     "sources_sha256": "a117e9c7984262c11635a13123c97a6eee08fe5bacc6729628f68de54700ccb8",
-    "tune": [256, 64, 20, 16, 8, 8, 0],
+    "tune": [256, 64, 16, 16, 8, 8, 0],
     "bytes_per_launch": 7477806676,
 }
 
@@ -341,6 +341,10 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
 
     ms_eval, out = timed(lambda: gm.eval(xy, p), steps, warmup)
     ms_delta, (d, st) = timed(lambda: gm.delta(xy, p, vid, qd), max(1, steps // 2), 1)
+    # the same moves submitted in vertex order (neighbouring threads then share cache lines)
+    srt = torch.argsort(vid)
+    vid_s, q_s = vid[srt].contiguous(), qd[srt].contiguous()
+    ms_delta_sorted, _ = timed(lambda: gm.delta(xy, p, vid_s, q_s), max(1, steps // 2), 1)
     f, wc, pa, pl = out.cpu().tolist()
     ok = int((st == 1).sum().item())
 
@@ -394,6 +398,7 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
         "eps": 1e-3 * size,
         "eval_ms": ms_eval, "edges_per_s": gm.n_edges / ms_eval * 1e3,
         "delta_ms": ms_delta, "moves_per_s": moves / ms_delta * 1e3,
+        "delta_sorted_ms": ms_delta_sorted, "moves_sorted_per_s": moves / ms_delta_sorted * 1e3,
         "valid_moves": ok, "f": f, "w_contr": wc, "p_angle": pa, "p_len": pl,
         "anneal": {"classes": len(classes), "movable_vertices": n_mov,
                    "classes_host_s": t_classes, "temperature": temperature,

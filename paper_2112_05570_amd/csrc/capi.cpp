@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <array>
 #include <map>
 #include <mutex>
@@ -598,7 +599,8 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   const size_t off_perm = align(off_p + sizeof(PrimRec) * std::max<int64_t>(P, 1));
   const size_t off_orig = align(off_perm + sizeof(int32_t) * T);
   const size_t off_seed = align(off_orig + sizeof(int32_t) * T);
-  const size_t total = align(off_seed + sizeof(SeedCell) * seeds.size());
+  const size_t off_pair = align(off_seed + sizeof(SeedCell) * seeds.size());
+  const size_t total = align(off_pair + sizeof(Pair32) * 3 * T);
   std::vector<unsigned char> host(total, 0);
   auto* s32 = reinterpret_cast<Slot32*>(host.data() + off_s32);
   auto* s64 = reinterpret_cast<Slot64*>(host.data() + off_s64);
@@ -653,6 +655,33 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
       }
     }
   });
+  // two-step records from the single-step slots
+  auto* pr32 = reinterpret_cast<Pair32*>(host.data() + off_pair);
+  parallel_for(3 * T, [&](int64_t a, int64_t b) {
+    for (int64_t k = a; k < b; ++k) {
+      const Slot32& sl = s32[k];
+      Pair32& pr = pr32[k];
+      if (sl.word < 0) {
+        pr.nx = pr.ny = std::numeric_limits<float>::quiet_NaN();
+        pr.w0 = sl.word;
+        pr.x0 = pr.y0 = pr.x1 = pr.y1 = 0.0f;
+        pr.w1 = 0;
+        continue;
+      }
+      pr.nx = sl.x;
+      pr.ny = sl.y;
+      const int64_t n = sl.word >> 2;
+      const int en = sl.word & 3;
+      const Slot32& l = s32[3 * n + (en + 1) % 3];
+      const Slot32& r = s32[3 * n + (en + 2) % 3];
+      pr.w0 = l.word;
+      pr.x0 = l.x;
+      pr.y0 = l.y;
+      pr.w1 = r.word;
+      pr.x1 = r.x;
+      pr.y1 = r.y;
+    }
+  });
 
   // ---- upload
   DeviceState* ds = nullptr;
@@ -679,6 +708,7 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   tri->nt = T;
   tri->np = P;
   tri->dev.slot32 = reinterpret_cast<const Slot32*>(base + off_s32);
+  tri->dev.pair32 = reinterpret_cast<const Pair32*>(base + off_pair);
   tri->dev.slot64 = reinterpret_cast<const Slot64*>(base + off_s64);
   tri->dev.first = reinterpret_cast<const TriFirst*>(base + off_first);
   tri->dev.triv = reinterpret_cast<const int4*>(base + off_tv);

@@ -19,6 +19,17 @@ struct alignas(16) Slot32 {  // binary32 walk: 16 B per slot
   int32_t vid;                // its vertex id (for the binary64 fallback); on a constrained edge,
                               // this triangle's vertex opposite the edge (reflected rays)
 };
+// Two steps of the binary32 walk in one 32-B load. For exit slot s of a triangle: the across
+// vertex of the neighbour n across that edge, then the slots of n's two candidate exits, in the
+// order (across vertex LEFT, RIGHT): their words and across vertices. A slot on a constrained or
+// hull edge has nx = NaN and w0 = its word. Vertex ids (for the binary64 fallback) stay in Slot32.
+struct alignas(32) Pair32 {
+  float nx, ny;
+  int32_t w0;
+  float x0, y0;
+  int32_t w1;
+  float x1, y1;
+};
 struct alignas(32) Slot64 {  // binary64 walk: 32 B per slot
   double x, y;                // across vertex (binary64, absolute), also across constrained edges
   int32_t word;
@@ -49,6 +60,7 @@ struct SeedCell {
 
 struct SceneDev {
   const Slot32* slot32;    // 3T
+  const Pair32* pair32;    // 3T
   const Slot64* slot64;    // 3T
   const TriFirst* first;   // T, the caller's order
   const int4* triv;      // T: v0, v1, v2, 0

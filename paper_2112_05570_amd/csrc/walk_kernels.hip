@@ -201,6 +201,8 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
                 unsigned long long* __restrict__ counter, int refill_min, int chunks, int group,
                 unsigned long long* __restrict__ stats, int* __restrict__ errflag) {
   constexpr int TILE = TPL * 64;
+  // binary32 walks of unreflected rays take two triangles per load (Pair32)
+  constexpr bool PAIRS = MODE == 1 && !BOUNCE;
   extern __shared__ unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -227,6 +229,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   int item = 0;
   // per-lane scene in a batch, kernel argument otherwise
   const Slot32* slot32 = sc_arg.slot32;
+  const Pair32* pair32 = sc_arg.pair32;
   const Slot64* slot64 = sc_arg.slot64;
   int ntri = sc_arg.ntri;
 
@@ -306,6 +309,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             item = titem;
             const SceneDev& sc = batch.items[item].scene;
             slot32 = sc.slot32;
+            pair32 = sc.pair32;
             slot64 = sc.slot64;
             ntri = sc.ntri;
             org_x = sc.org_x;
@@ -329,7 +333,11 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
     int4 R0 = make_int4(0, 0, 0, 0), R1 = R0, R2 = R0;
     int R3 = 0;
     if (st_now == WALK) {
-      if (MODE == 1) {
+      if (PAIRS) {
+        const int4* p = reinterpret_cast<const int4*>(pair32 + s);
+        R0 = p[0];
+        R1 = p[1];
+      } else if (MODE == 1) {
         R0 = *reinterpret_cast<const int4*>(slot32 + s);
       } else {
         const int4* p = reinterpret_cast<const int4*>(slot64 + s);
@@ -352,7 +360,63 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
                      "v"(R1.z), "v"(R1.w));
     if (BOUNCE) __asm__ volatile("" ::"v"(R2.x), "v"(R2.y), "v"(R2.z), "v"(R2.w), "v"(R3));
     // ---- process
-    if (st_now == WALK) {
+    if (PAIRS && st_now == WALK) {
+      // Pair32 of exit slot s: nx ny w0 x0 | y0 w1 x1 y1. Up to two triangles per load: n (across
+      // slot s) and, unless n's exit is constrained or on the hull, the triangle after it.
+      const float nx = __int_as_float(R0.x), ny = __int_as_float(R0.y);
+      int word = R0.z;  // the word that ends the walk, when it ends in this iteration
+      bool more = false;
+      if (!isnan(nx) && steps < ntri) {
+        ++steps;  // in n
+        bool left;
+        const int sg = side32(r32, nx, ny);
+        if (sg != 0) {
+          left = sg > 0;
+        } else {
+          if (COUNT) ++c.fb32;
+          const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
+          left = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64,
+                                      slot32[s].vid, &c.fb64);
+        }
+        word = left ? R0.z : R1.y;
+        if (word >= 0 && steps < ntri) {
+          ++steps;  // in the triangle after n
+          const float cx = __int_as_float(left ? R0.w : R1.z);
+          const float cy = __int_as_float(left ? R1.x : R1.w);
+          bool left2;
+          const int sg2 = side32(r32, cx, cy);
+          if (sg2 != 0) {
+            left2 = sg2 > 0;
+          } else {
+            if (COUNT) ++c.fb32;
+            // the across vertex of n's exit slot: n and its entry edge from the one-step slot
+            const int wn = slot32[s].word;
+            int en = (wn & 3) + (left ? 1 : 2);
+            en = en >= 3 ? en - 3 : en;
+            const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
+            left2 = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64,
+                                         slot32[3 * (wn >> 2) + en].vid, &c.fb64);
+          }
+          int e = (word & 3) + (left2 ? 1 : 2);
+          e = e >= 3 ? e - 3 : e;
+          s = 3 * (word >> 2) + e;
+          more = true;
+        }
+      } else if (!isnan(nx)) {
+        word = 0;  // the step guard: another triangle to enter
+      }
+      if (!more) {
+        // constrained edge (hit, primitive -word - 2), hull edge (miss) or the step guard; the
+        // finishing pass computes t
+        park_result(BATCH ? batch.items[item].rays : io_arg, ray,
+                    word <= -2 ? -word - 2 : (word >= 0 ? -2 : -1), steps);
+        if (COUNT) {
+          c.steps += steps;
+          ++c.rays;
+        }
+        state = IDLE;
+      }
+    } else if (st_now == WALK) {
       int word;
       bool left = false;
       if (MODE == 1) {
