@@ -34,9 +34,9 @@ BYTES_PER_RAY = 60
 # taken with.
 WALK_SOURCES = ("walk_kernels.hip", "walk.hpp", "decide.hpp", "exact.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "a117e9c7984262c11635a13123c97a6eee08fe5bacc6729628f68de54700ccb8",
+    "sources_sha256": "2fc229e351680377671607880b761910116e6704fe5d0099f32761e9578c8572",
     "tune": [256, 64, 16, 16, 8, 8, 0],
-    "bytes_per_launch": 7477806676,
+    "bytes_per_launch": 12150331677,
 }
 
 
