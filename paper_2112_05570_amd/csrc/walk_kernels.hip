@@ -201,8 +201,8 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
                 unsigned long long* __restrict__ counter, int refill_min, int chunks, int group,
                 unsigned long long* __restrict__ stats, int* __restrict__ errflag) {
   constexpr int TILE = TPL * 64;
-  // binary32 walks of unreflected rays take two triangles per load (Pair32)
-  constexpr bool PAIRS = MODE == 1 && !BOUNCE;
+  // binary32 walks take two triangles per load (Pair32)
+  constexpr bool PAIRS = MODE == 1;
   extern __shared__ unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -365,10 +365,11 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
       // slot s) and, unless n's exit is constrained or on the hull, the triangle after it.
       const float nx = __int_as_float(R0.x), ny = __int_as_float(R0.y);
       int word = R0.z;  // the word that ends the walk, when it ends in this iteration
-      bool more = false;
-      if (!isnan(nx) && steps < ntri) {
+      int end_slot = s;  // the slot whose word that is
+      bool more = false, left = false;
+      if (!isnan(nx) && (BOUNCE ? seg < ntri : steps < ntri)) {
         ++steps;  // in n
-        bool left;
+        if (BOUNCE) ++seg;
         const int sg = side32(r32, nx, ny);
         if (sg != 0) {
           left = sg > 0;
@@ -379,8 +380,10 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
                                       slot32[s].vid, &c.fb64);
         }
         word = left ? R0.z : R1.y;
-        if (word >= 0 && steps < ntri) {
+        end_slot = -1;  // n's exit slot, found from the one-step slot when needed
+        if (word >= 0 && (BOUNCE ? seg < ntri : steps < ntri)) {
           ++steps;  // in the triangle after n
+          if (BOUNCE) ++seg;
           const float cx = __int_as_float(left ? R0.w : R1.z);
           const float cy = __int_as_float(left ? R1.x : R1.w);
           bool left2;
@@ -406,15 +409,36 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         word = 0;  // the step guard: another triangle to enter
       }
       if (!more) {
-        // constrained edge (hit, primitive -word - 2), hull edge (miss) or the step guard; the
-        // finishing pass computes t
-        park_result(BATCH ? batch.items[item].rays : io_arg, ray,
-                    word <= -2 ? -word - 2 : (word >= 0 ? -2 : -1), steps);
-        if (COUNT) {
-          c.steps += steps;
-          ++c.rays;
+        if (BOUNCE && word <= -2) {
+          // hit: the primitive and the vertex opposite the hit edge are loaded next iteration
+          if (end_slot < 0) {
+            const int wn = slot32[s].word;
+            int en = (wn & 3) + (left ? 1 : 2);
+            en = en >= 3 ? en - 3 : en;
+            end_slot = 3 * (wn >> 2) + en;
+          }
+          hs = end_slot;
+          cv = slot32[hs].vid;
+          s = -word - 2;
+          state = BNC;
+        } else if (BOUNCE) {  // hull edge (miss) or the step guard
+          bounce_result(io_arg, ray, word >= 0 ? -2 : -1, INFINITY, steps, nb, -1);
+          if (COUNT) {
+            c.steps += steps;
+            ++c.rays;
+          }
+          state = IDLE;
+        } else {
+          // constrained edge (hit, primitive -word - 2), hull edge (miss) or the step guard; the
+          // finishing pass computes t
+          park_result(BATCH ? batch.items[item].rays : io_arg, ray,
+                      word <= -2 ? -word - 2 : (word >= 0 ? -2 : -1), steps);
+          if (COUNT) {
+            c.steps += steps;
+            ++c.rays;
+          }
+          state = IDLE;
         }
-        state = IDLE;
       }
     } else if (st_now == WALK) {
       int word;
