@@ -600,7 +600,8 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   const size_t off_orig = align(off_perm + sizeof(int32_t) * T);
   const size_t off_seed = align(off_orig + sizeof(int32_t) * T);
   const size_t off_pair = align(off_seed + sizeof(SeedCell) * seeds.size());
-  const size_t total = align(off_pair + sizeof(Pair32) * 3 * T);
+  const size_t off_pair64 = align(off_pair + sizeof(Pair32) * 3 * T);
+  const size_t total = align(off_pair64 + sizeof(Pair64) * 3 * T);
   std::vector<unsigned char> host(total, 0);
   auto* s32 = reinterpret_cast<Slot32*>(host.data() + off_s32);
   auto* s64 = reinterpret_cast<Slot64*>(host.data() + off_s64);
@@ -682,6 +683,33 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
       pr.y1 = r.y;
     }
   });
+  auto* pr64 = reinterpret_cast<Pair64*>(host.data() + off_pair64);
+  parallel_for(3 * T, [&](int64_t a, int64_t b) {
+    for (int64_t k = a; k < b; ++k) {
+      const Slot64& sl = s64[k];
+      Pair64& pr = pr64[k];
+      pr.pad[0] = pr.pad[1] = 0;
+      if (sl.word < 0) {
+        pr.nx = pr.ny = std::numeric_limits<double>::quiet_NaN();
+        pr.x0 = pr.y0 = pr.x1 = pr.y1 = 0.0;
+        pr.w0 = sl.word;
+        pr.w1 = 0;
+        continue;
+      }
+      pr.nx = sl.x;
+      pr.ny = sl.y;
+      const int64_t n = sl.word >> 2;
+      const int en = sl.word & 3;
+      const Slot64& l = s64[3 * n + (en + 1) % 3];
+      const Slot64& r = s64[3 * n + (en + 2) % 3];
+      pr.x0 = l.x;
+      pr.y0 = l.y;
+      pr.w0 = l.word;
+      pr.x1 = r.x;
+      pr.y1 = r.y;
+      pr.w1 = r.word;
+    }
+  });
 
   // ---- upload
   DeviceState* ds = nullptr;
@@ -709,6 +737,7 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
   tri->np = P;
   tri->dev.slot32 = reinterpret_cast<const Slot32*>(base + off_s32);
   tri->dev.pair32 = reinterpret_cast<const Pair32*>(base + off_pair);
+  tri->dev.pair64 = reinterpret_cast<const Pair64*>(base + off_pair64);
   tri->dev.slot64 = reinterpret_cast<const Slot64*>(base + off_s64);
   tri->dev.first = reinterpret_cast<const TriFirst*>(base + off_first);
   tri->dev.triv = reinterpret_cast<const int4*>(base + off_tv);

@@ -30,6 +30,16 @@ struct alignas(32) Pair32 {
   int32_t w1;
   float x1, y1;
 };
+// The same two steps for the binary64 walk, in one 64-B load: across vertices of n and of its two
+// candidate exits (LEFT, RIGHT), and the words of those exits. A slot on a constrained or hull
+// edge has nx = NaN and w0 = its word.
+struct alignas(64) Pair64 {
+  double nx, ny;
+  double x0, y0;
+  double x1, y1;
+  int32_t w0, w1;
+  int32_t pad[2];
+};
 struct alignas(32) Slot64 {  // binary64 walk: 32 B per slot
   double x, y;                // across vertex (binary64, absolute), also across constrained edges
   int32_t word;
@@ -61,6 +71,7 @@ struct SeedCell {
 struct SceneDev {
   const Slot32* slot32;    // 3T
   const Pair32* pair32;    // 3T
+  const Pair64* pair64;    // 3T
   const Slot64* slot64;    // 3T
   const TriFirst* first;   // T, the caller's order
   const int4* triv;      // T: v0, v1, v2, 0

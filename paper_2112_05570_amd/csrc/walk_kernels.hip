@@ -188,7 +188,9 @@ __device__ __forceinline__ long long claim_tile(unsigned long long* counter, int
 // Each lane is a small state machine that issues exactly one round of loads per iteration:
 //   FIRST: the start triangle's first-triangle record (then three decisions, the first
 //          step of Sec. 7.2's footnote; rays of binned tiles skip it: binning decided their first triangle),
-//   WALK:  the slot of the exit edge (then one decision: the vertex across the entry edge),
+//   WALK:  the two-step record of the exit edge (Pair32 or Pair64: then one decision for the
+//          neighbour across that edge and, unless its exit ends the walk, one for the triangle
+//          after it; the one-step slots are read only for rare fallbacks and at hits),
 // so lanes in different states share one memory round trip, and a refilled lane starts walking
 // in the next iteration without a separate gather phase.
 // BOUNCE: rays continue by specular reflection at hits (up to io.max_bounces times): a fourth
@@ -201,8 +203,6 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
                 unsigned long long* __restrict__ counter, int refill_min, int chunks, int group,
                 unsigned long long* __restrict__ stats, int* __restrict__ errflag) {
   constexpr int TILE = TPL * 64;
-  // binary32 walks take two triangles per load (Pair32)
-  constexpr bool PAIRS = MODE == 1;
   extern __shared__ unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -230,7 +230,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   // per-lane scene in a batch, kernel argument otherwise
   const Slot32* slot32 = sc_arg.slot32;
   const Pair32* pair32 = sc_arg.pair32;
-  const Slot64* slot64 = sc_arg.slot64;
+  const Pair64* pair64 = sc_arg.pair64;
   int ntri = sc_arg.ntri;
 
   // wave-uniform tile state
@@ -310,7 +310,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             const SceneDev& sc = batch.items[item].scene;
             slot32 = sc.slot32;
             pair32 = sc.pair32;
-            slot64 = sc.slot64;
+            pair64 = sc.pair64;
             ntri = sc.ntri;
             org_x = sc.org_x;
             org_y = sc.org_y;
@@ -330,19 +330,19 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
     }
     // ---- issue: one round of loads for every busy lane, whatever its state
     const int st_now = state;
-    int4 R0 = make_int4(0, 0, 0, 0), R1 = R0, R2 = R0;
+    int4 R0 = make_int4(0, 0, 0, 0), R1 = R0, R2 = R0, RW = R0;
     int R3 = 0;
     if (st_now == WALK) {
-      if (PAIRS) {
+      if (MODE == 1) {
         const int4* p = reinterpret_cast<const int4*>(pair32 + s);
         R0 = p[0];
         R1 = p[1];
-      } else if (MODE == 1) {
-        R0 = *reinterpret_cast<const int4*>(slot32 + s);
       } else {
-        const int4* p = reinterpret_cast<const int4*>(slot64 + s);
+        const int4* p = reinterpret_cast<const int4*>(pair64 + s);
         R0 = p[0];
         R1 = p[1];
+        R2 = p[2];
+        RW = p[3];
       }
     } else if (st_now == FIRST) {
       const int4* p = reinterpret_cast<const int4*>((BATCH ? batch.items[item].scene.first : sc_arg.first) + s);
@@ -358,54 +358,68 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
     // every load above is issued before any result is used (and none is split per field)
     __asm__ volatile("" ::"v"(R0.x), "v"(R0.y), "v"(R0.z), "v"(R0.w), "v"(R1.x), "v"(R1.y),
                      "v"(R1.z), "v"(R1.w));
-    if (BOUNCE) __asm__ volatile("" ::"v"(R2.x), "v"(R2.y), "v"(R2.z), "v"(R2.w), "v"(R3));
+    if (BOUNCE || MODE == 0)
+      __asm__ volatile("" ::"v"(R2.x), "v"(R2.y), "v"(R2.z), "v"(R2.w), "v"(R3));
+    if (MODE == 0) __asm__ volatile("" ::"v"(RW.x), "v"(RW.y));
     // ---- process
-    if (PAIRS && st_now == WALK) {
-      // Pair32 of exit slot s: nx ny w0 x0 | y0 w1 x1 y1. Up to two triangles per load: n (across
-      // slot s) and, unless n's exit is constrained or on the hull, the triangle after it.
-      const float nx = __int_as_float(R0.x), ny = __int_as_float(R0.y);
-      int word = R0.z;  // the word that ends the walk, when it ends in this iteration
+    if (st_now == WALK) {
+      // Pair32 of exit slot s: nx ny w0 x0 | y0 w1 x1 y1; Pair64: nx ny | x0 y0 | x1 y1 | w0 w1.
+      // Up to two triangles per load: n (across slot s) and, unless n's exit is constrained or
+      // on the hull, the triangle after it.
+      const bool terminal = MODE == 1 ? isnan(__int_as_float(R0.x)) : isnan(lohi(R0.x, R0.y));
+      int word = MODE == 1 ? R0.z : RW.x;  // the word that ends the walk, if it ends here
       int end_slot = s;  // the slot whose word that is
       bool more = false, left = false;
-      if (!isnan(nx) && (BOUNCE ? seg < ntri : steps < ntri)) {
+      if (!terminal && (BOUNCE ? seg < ntri : steps < ntri)) {
         ++steps;  // in n
         if (BOUNCE) ++seg;
-        const int sg = side32(r32, nx, ny);
-        if (sg != 0) {
-          left = sg > 0;
+        if (MODE == 1) {
+          const int sg = side32(r32, __int_as_float(R0.x), __int_as_float(R0.y));
+          if (sg != 0) {
+            left = sg > 0;
+          } else {
+            if (COUNT) ++c.fb32;
+            const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
+            left = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64,
+                                        slot32[s].vid, &c.fb64);
+          }
+          word = left ? R0.z : R1.y;
         } else {
-          if (COUNT) ++c.fb32;
-          const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
-          left = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64,
-                                      slot32[s].vid, &c.fb64);
+          left = left64<COUNT>(ox, oy, dx, dy, lohi(R0.x, R0.y), lohi(R0.z, R0.w), c.fb64);
+          word = left ? RW.x : RW.y;
         }
-        word = left ? R0.z : R1.y;
         end_slot = -1;  // n's exit slot, found from the one-step slot when needed
         if (word >= 0 && (BOUNCE ? seg < ntri : steps < ntri)) {
           ++steps;  // in the triangle after n
           if (BOUNCE) ++seg;
-          const float cx = __int_as_float(left ? R0.w : R1.z);
-          const float cy = __int_as_float(left ? R1.x : R1.w);
           bool left2;
-          const int sg2 = side32(r32, cx, cy);
-          if (sg2 != 0) {
-            left2 = sg2 > 0;
+          if (MODE == 1) {
+            const float cx = __int_as_float(left ? R0.w : R1.z);
+            const float cy = __int_as_float(left ? R1.x : R1.w);
+            const int sg2 = side32(r32, cx, cy);
+            if (sg2 != 0) {
+              left2 = sg2 > 0;
+            } else {
+              if (COUNT) ++c.fb32;
+              // the across vertex of n's exit slot: n and its entry edge from the one-step slot
+              const int wn = slot32[s].word;
+              int en = (wn & 3) + (left ? 1 : 2);
+              en = en >= 3 ? en - 3 : en;
+              const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
+              left2 = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64,
+                                           slot32[3 * (wn >> 2) + en].vid, &c.fb64);
+            }
           } else {
-            if (COUNT) ++c.fb32;
-            // the across vertex of n's exit slot: n and its entry edge from the one-step slot
-            const int wn = slot32[s].word;
-            int en = (wn & 3) + (left ? 1 : 2);
-            en = en >= 3 ? en - 3 : en;
-            const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
-            left2 = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64,
-                                         slot32[3 * (wn >> 2) + en].vid, &c.fb64);
+            const double cx = left ? lohi(R1.x, R1.y) : lohi(R2.x, R2.y);
+            const double cy = left ? lohi(R1.z, R1.w) : lohi(R2.z, R2.w);
+            left2 = left64<COUNT>(ox, oy, dx, dy, cx, cy, c.fb64);
           }
           int e = (word & 3) + (left2 ? 1 : 2);
           e = e >= 3 ? e - 3 : e;
           s = 3 * (word >> 2) + e;
           more = true;
         }
-      } else if (!isnan(nx)) {
+      } else if (!terminal) {
         word = 0;  // the step guard: another triangle to enter
       }
       if (!more) {
@@ -439,55 +453,6 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
           }
           state = IDLE;
         }
-      }
-    } else if (st_now == WALK) {
-      int word;
-      bool left = false;
-      if (MODE == 1) {
-        word = R0.x;
-        const int sg = side32(r32, __int_as_float(R0.y), __int_as_float(R0.z));
-        if (word >= 0) {
-          if (sg != 0) {
-            left = sg > 0;
-          } else {
-            if (COUNT) ++c.fb32;
-            const double2* v64 = BATCH ? batch.items[item].scene.v64 : sc_arg.v64;
-            left = left_deferred<COUNT>(make_double2(ox, oy), make_double2(dx, dy), v64, R0.w, &c.fb64);
-          }
-        }
-      } else {
-        word = R1.x;
-        if (word >= 0) left = left64<COUNT>(ox, oy, dx, dy, lohi(R0.x, R0.y), lohi(R0.z, R0.w), c.fb64);
-      }
-      if (word >= 0 && (BOUNCE ? seg < ntri : steps < ntri)) {
-        ++steps;
-        if (BOUNCE) ++seg;
-        int e = (word & 3) + (left ? 1 : 2);
-        e = e >= 3 ? e - 3 : e;
-        s = 3 * (word >> 2) + e;
-      } else if (BOUNCE && word <= -2) {
-        // hit: the primitive and the vertex opposite the hit edge are loaded next iteration
-        hs = s;
-        cv = MODE == 1 ? R0.w : R1.w;
-        s = -word - 2;
-        state = BNC;
-      } else if (BOUNCE) {  // hull edge (miss) or the step guard
-        bounce_result(io_arg, ray, word >= 0 ? -2 : -1, INFINITY, steps, nb, -1);
-        if (COUNT) {
-          c.steps += steps;
-          ++c.rays;
-        }
-        state = IDLE;
-      } else {
-        // constrained edge (hit, primitive -word - 2), hull edge (miss) or the step guard; the
-        // finishing pass computes t
-        park_result(BATCH ? batch.items[item].rays : io_arg, ray,
-                    word <= -2 ? -word - 2 : (word >= 0 ? -2 : -1), steps);
-        if (COUNT) {
-          c.steps += steps;
-          ++c.rays;
-        }
-        state = IDLE;
       }
     } else if (st_now == FIRST) {
       // TriFirst: x0 x1 x2 y0 | y1 y2 tri -
