@@ -159,6 +159,26 @@ int anneal_moves(MovableMesh *mesh, double *xy, const ObjectiveParams *params, d
 int anneal_sweep(MovableMesh *mesh, double *xy, const ObjectiveParams *params, double temperature,
                  const double *disp, const double *u, double *delta, int32_t *status, void *stream);
 
+/*
+ * anneal_schedule: n_sweeps sweeps (as anneal_sweep) of simulated annealing with both the
+ * temperature and the contraction length lowered by the caller's schedule (Sec. 3.3.1: sweep k
+ * uses temperature[k] and eps[k], HOST arrays; params supplies the other parameters) and an
+ * adaptive step scale (Sec. 3.2): the move of the i-th movable vertex (in mesh_classes order) in
+ * sweep k is lambda_k * eta * xi[k][i], with xi (DEVICE, n_sweeps x movable x 2 binary64, 16-byte
+ * aligned) unit draws supplied by the caller and eta the square root of the area of the vertex's
+ * triangles at the current positions, summed in the caller's triangle order, each area as
+ * 0.5 * ((b.x-a.x)*(c.y-a.y) - (b.y-a.y)*(c.x-a.x)); the move is then (lambda_k * eta) * xi,
+ * projected as in anneal_moves, and accepted with u[k][i] (DEVICE, n_sweeps x movable). lambda_0
+ * = lambda0; after sweep k, with a the accepted fraction, lambda_{k+1} = lambda_k * f, f =
+ * 1 + (a - target) limited to [1/2, 2] (the paper keeps acceptance near a target, 23%, without
+ * giving the rule). lambda_out[k] and accepted_out[k] (HOST) receive lambda_k and the number of
+ * accepted moves. xy (DEVICE) is updated in place. Synchronises `stream` after every sweep.
+ */
+int anneal_schedule(MovableMesh *mesh, double *xy, const ObjectiveParams *params, int32_t n_sweeps,
+                    const double *temperature, const double *eps, double lambda0, double target,
+                    const double *xi, const double *u, double *lambda_out, int64_t *accepted_out,
+                    void *stream);
+
 /* mesh_free: release the mesh (after its calls have completed). NULL is ignored. */
 void mesh_free(MovableMesh *mesh);
 

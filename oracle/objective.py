@@ -307,3 +307,43 @@ def metropolis_chain(m: Mesh, xy, p: Params, temperature, vid, disp, u):
             st[i] = REJECTED
         margin[i] = abs(d + temperature * np.log(u[i])) if u[i] > 0 else np.inf
     return xy, st, df, margin
+
+
+def star_area(m: Mesh, xy, v):
+    """Area of the triangles of vertex v, summed in increasing triangle id, each as
+    0.5 * ((b - a) x (c - a)) on its vertices in their stored order."""
+    s = 0.0
+    for t in np.nonzero((m.tri_v == v).any(axis=1))[0]:
+        a, b, c = (xy[k] for k in m.tri_v[t])
+        s = s + 0.5 * ((b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]))
+    return s
+
+
+def annealing_schedule(m: Mesh, xy, p: Params, temperatures, eps, lambda0, target, order, xi, u):
+    """Simulated annealing (Sec. 3.1) with temperature and contraction length lowered together
+    (Sec. 3.3.1) and an adaptive step scale (Sec. 3.2): sweep k visits the vertices of `order`
+    one after another; the move of vertex v is (lambda_k * sqrt(star area of v)) * xi[k][i] (Sec.
+    3.2.2), projected for constrained vertices and accepted by the Metropolis rule with u[k][i].
+    After a sweep, with a its accepted fraction, lambda is scaled by 1 + (a - target) limited to
+    [1/2, 2] (the paper targets an acceptance rate without giving the rule). Returns the final
+    positions, the step scale of every sweep, its accepted moves and the smallest decision margin."""
+    xy = np.array(xy, dtype=np.float64)
+    lam = float(lambda0)
+    lams, accs, margin_min = [], [], np.inf
+    for k in range(len(temperatures)):
+        pk = Params(eps[k], p.delta, p.eps0, p.mu_angle, p.mu_len, p.polish)
+        acc = 0
+        for i, v in enumerate(order):
+            v = int(v)
+            sc = lam * np.sqrt(star_area(m, xy, v))
+            d = np.array([sc * xi[k][i][0], sc * xi[k][i][1]])
+            _, st, _, margin = metropolis_chain(m, xy, pk, temperatures[k], [v], [d], [u[k][i]])
+            if st[0] == ACCEPTED:
+                xy[v] = xy[v] + project(m, xy, v, d)
+                acc += 1
+            margin_min = min(margin_min, margin[0])
+        lams.append(lam)
+        accs.append(acc)
+        a = acc / len(order)
+        lam = lam * min(2.0, max(0.5, 1.0 + (a - target)))
+    return xy, np.array(lams), np.array(accs), margin_min

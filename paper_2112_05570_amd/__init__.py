@@ -313,6 +313,28 @@ class MovableMesh:
                        u.data_ptr(), d.data_ptr(), st.data_ptr(), _stream(stream))
         return d, st
 
+    def schedule(self, xy, params, temperatures, eps, lambda0, xi, u, target=0.23, stream=None):
+        """Simulated annealing with a temperature and contraction-length schedule and an adaptive
+        step scale (see ``anneal_schedule``): temperatures and eps are sequences of one value per
+        sweep; xi (S, M, 2) and u (S, M) float64 CUDA tensors hold the unit draws of the movable
+        vertices in the order of ``classes()``. xy is updated in place. Returns the step scale of
+        every sweep and its accepted moves (numpy arrays). Synchronous."""
+        import torch
+        temps = np.ascontiguousarray(temperatures, dtype=np.float64)
+        epss = np.ascontiguousarray(eps, dtype=np.float64)
+        s, m = temps.shape[0], self.n_movable()
+        if (epss.shape != (s,) or tuple(xi.shape) != (s, m, 2) or tuple(u.shape) != (s, m)
+                or xi.dtype != torch.float64 or u.dtype != torch.float64 or not xi.is_cuda
+                or not u.is_cuda or not xi.is_contiguous() or not u.is_contiguous()):
+            raise ValueError(f"{s} eps values, xi float64 ({s},{m},2) and u ({s},{m}) CUDA tensors")
+        lam = np.zeros(s, dtype=np.float64)
+        acc = np.zeros(s, dtype=np.int64)
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
+        B.anneal_schedule(self.handle, self._xy(xy), params, s, p(temps), p(epss), float(lambda0),
+                          float(target), xi.data_ptr(), u.data_ptr(), p(lam), p(acc),
+                          _stream(stream))
+        return lam, acc
+
     def n_movable(self):
         n = B.mesh_classes(self.handle)
         off = np.empty(n + 1, dtype=np.int64)

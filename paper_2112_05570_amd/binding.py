@@ -47,7 +47,7 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
            "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
-           "anneal_moves", "anneal_sweep")
+           "anneal_moves", "anneal_sweep", "anneal_schedule")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -167,6 +167,9 @@ _lib.anneal_moves.restype = _I
 _lib.anneal_sweep.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double, _P, _P, _P,
                               _P, _P]
 _lib.anneal_sweep.restype = _I
+_lib.anneal_schedule.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_int32, _P, _P,
+                                 ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P]
+_lib.anneal_schedule.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -309,6 +312,14 @@ def anneal_sweep(mesh: int, xy: int, params: ObjectiveParams, temperature: float
                  u: int, delta: int, status: int, stream: int = 0) -> None:
     _check(_lib.anneal_sweep(_P(mesh), _P(xy), ctypes.byref(params), temperature, _P(disp), _P(u),
                              _P(delta), _P(status), _P(stream)))
+
+
+def anneal_schedule(mesh: int, xy: int, params: ObjectiveParams, n_sweeps: int, temperature: int,
+                    eps: int, lambda0: float, target: float, xi: int, u: int, lambda_out: int,
+                    accepted_out: int, stream: int = 0) -> None:
+    _check(_lib.anneal_schedule(_P(mesh), _P(xy), ctypes.byref(params), n_sweeps, _P(temperature),
+                                _P(eps), lambda0, target, _P(xi), _P(u), _P(lambda_out),
+                                _P(accepted_out), _P(stream)))
 
 
 def mesh_free(mesh: int) -> None:

@@ -472,10 +472,10 @@ __device__ __forceinline__ void refresh_scratch(const MeshDev& m, const Par& p, 
 // than four edges apart, so that each thread's reads (within four edges of its vertex) and writes
 // (its position, and scratch of edges within one edge of it) never meet another thread's.
 __global__ void __launch_bounds__(kThreads)
-anneal_class(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out,
+anneal_class(MeshDev m, Par p, double temperature, double lambda, double2* __restrict__ xy_out,
              const int32_t* __restrict__ cls, const double2* __restrict__ disp,
              const double* __restrict__ u, int n, double* __restrict__ delta,
-             int32_t* __restrict__ status) {
+             int32_t* __restrict__ status, unsigned long long* __restrict__ accepted) {
   __shared__ int snb[kLdsNbrs * kThreads];
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
@@ -483,6 +483,18 @@ anneal_class(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out,
   const int cv = m.vold[v];
   const double2 o = m.xyi[v];
   double2 d = disp[i];
+  if (lambda > 0.0) {
+    // disp is a unit draw: scale by lambda * eta, eta the square root of the area of v's
+    // triangles (Sec. 3.2.2), summed in the caller's triangle order at the current positions
+    double area = 0.0;
+    for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j) {
+      const int4 tr = m.tri[m.vtri[j]];
+      const double2 a = m.xyi[tr.x], b = m.xyi[tr.y], c = m.xyi[tr.z];
+      area += 0.5 * ((b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x));
+    }
+    const double k = lambda * sqrt(area);
+    d = make_double2(k * d.x, k * d.y);
+  }
   const int2 kl = m.vk[v];
   if (kl.x == CCSP_VERTEX_CONSTRAINED) {
     const int2 ends = m.prim_v[kl.y];
@@ -499,12 +511,17 @@ anneal_class(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out,
       m.xyi[v] = q;
       xy_out[cv] = q;
       refresh_scratch(m, p, v);
+      if (accepted) atomicAdd(accepted, 1ull);
     } else {
       st = CCSP_MOVE_REJECTED;
     }
   }
   status[i] = st;
   delta[i] = df;
+}
+
+__global__ void zero_counter(unsigned long long* __restrict__ c) {
+  if (threadIdx.x == 0) c[0] = 0ull;
 }
 
 }  // namespace
@@ -520,6 +537,7 @@ struct MovableMesh {
   std::vector<int64_t> class_off;  // mesh_classes, computed on the first call
   std::vector<int32_t> class_v;    // caller ids, class by class
   int32_t* class_dev = nullptr;    // the same vertices, internal ids, on the device
+  void* sched = nullptr;           // anneal_schedule: delta and status per movable vertex, counter
 };
 
 namespace {
@@ -777,8 +795,15 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
   for (int64_t f = 0; f < n3; ++f) ++vtri_off[tv[f] + 1];
   for (int64_t v = 0; v < V; ++v) vtri_off[v + 1] += vtri_off[v];
   {
+    // each vertex's triangles in the caller's triangle order (sums over a vertex's triangles,
+    // such as its star area, then have a caller-visible order)
+    std::vector<int32_t> tnew(T);
+    for (int64_t ti = 0; ti < T; ++ti) tnew[told[ti]] = (int32_t)ti;
     std::vector<int32_t> fill(vtri_off.begin(), vtri_off.end() - 1);
-    for (int64_t f = 0; f < n3; ++f) vtri[fill[tv[f]]++] = (int32_t)(f / 3);
+    for (int64_t ct = 0; ct < T; ++ct) {
+      const int32_t ti = tnew[ct];
+      for (int i = 0; i < 3; ++i) vtri[fill[tv[3 * (int64_t)ti + i]]++] = ti;
+    }
   }
   std::vector<int32_t> tri4(4 * T), tedge4(4 * T), vk(2 * V);
   for (int64_t t = 0; t < T; ++t) {
@@ -1059,16 +1084,85 @@ int anneal_sweep(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
     const int n = (int)(off[c + 1] - off[c]);
     if (n == 0) continue;
     hipLaunchKernelGGL(ccsp::anneal_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
-                       dim3(ccsp::kThreads), 0, s, d, p, temperature, (double2*)xy,
+                       dim3(ccsp::kThreads), 0, s, d, p, temperature, 0.0, (double2*)xy,
                        mesh->class_dev + off[c], (const double2*)disp + off[c], u + off[c], n,
-                       delta + off[c], status + off[c]);
+                       delta + off[c], status + off[c], (unsigned long long*)nullptr);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_sweep: launch");
 }
 
+int anneal_schedule(MovableMesh* mesh, double* xy, const ObjectiveParams* params, int32_t n_sweeps,
+                    const double* temperature, const double* eps, double lambda0, double target,
+                    const double* xi, const double* u, double* lambda_out, int64_t* accepted_out,
+                    void* stream) {
+  if (!mesh || !xy || !params || n_sweeps < 0)
+    return fail(CCSP_E_ARG, "anneal_schedule: null argument or n_sweeps < 0");
+  if (n_sweeps > 0 && (!temperature || !eps || !xi || !u || !lambda_out || !accepted_out))
+    return fail(CCSP_E_ARG, "anneal_schedule: null argument");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)xi & 15) != 0 || ((uintptr_t)u & 7) != 0)
+    return fail(CCSP_E_ARG, "anneal_schedule: misaligned buffer");
+  if (!(lambda0 > 0) || !std::isfinite(lambda0) || !(target > 0) || !(target < 1))
+    return fail(CCSP_E_ARG, "anneal_schedule: lambda0 must be > 0 and target in (0, 1)");
+  for (int32_t k = 0; k < n_sweeps; ++k) {
+    ObjectiveParams pk = *params;
+    pk.eps = eps[k];
+    if (!check_params(&pk)) return fail(CCSP_E_ARG, "anneal_schedule: invalid parameters");
+    if (!(temperature[k] >= 0) || !std::isfinite(temperature[k]))
+      return fail(CCSP_E_ARG, "anneal_schedule: temperatures must be finite and >= 0");
+  }
+  if (int r = check_device(mesh)) return r;
+  if (int r = ensure_classes(mesh)) return r;
+  const int64_t M = mesh->class_off.back();
+  if (M == 0 || n_sweeps == 0) return CCSP_OK;
+  const size_t need = 8 * (size_t)M + 4 * (size_t)M + 256;
+  if (!mesh->sched) {
+    hipError_t e = hipMalloc(&mesh->sched, need);
+    if (e != hipSuccess) return fail(CCSP_E_OOM, "anneal_schedule: device allocation failed");
+  }
+  double* delta = (double*)mesh->sched;
+  int32_t* status = (int32_t*)(delta + M);
+  auto* counter = (unsigned long long*)((char*)mesh->sched + ((12 * (size_t)M + 255) & ~size_t(255)));
+  const ccsp::MeshDev& d = mesh->d;
+  hipStream_t s = (hipStream_t)stream;
+  const std::vector<int64_t>& off = mesh->class_off;
+  double lam = lambda0;
+  for (int32_t k = 0; k < n_sweeps; ++k) {
+    ObjectiveParams pk = *params;
+    pk.eps = eps[k];
+    const ccsp::Par p = to_par(&pk);
+    hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s,
+                       d, (const double2*)xy);
+    hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
+                       d.partial);
+    hipLaunchKernelGGL(ccsp::zero_counter, dim3(1), dim3(64), 0, s, counter);
+    const double2* xk = (const double2*)xi + (size_t)k * M;
+    const double* uk = u + (size_t)k * M;
+    for (size_t c = 0; c + 1 < off.size(); ++c) {
+      const int n = (int)(off[c + 1] - off[c]);
+      if (n == 0) continue;
+      hipLaunchKernelGGL(ccsp::anneal_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
+                         dim3(ccsp::kThreads), 0, s, d, p, temperature[k], lam, (double2*)xy,
+                         mesh->class_dev + off[c], xk + off[c], uk + off[c], n, delta + off[c],
+                         status + off[c], counter);
+    }
+    unsigned long long acc = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&acc, counter, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "anneal_schedule");
+    lambda_out[k] = lam;
+    accepted_out[k] = (int64_t)acc;
+    // adaptive aggressiveness (Sec. 3.2): scale lambda by 1 + (acceptance - target), within [1/2, 2]
+    const double a = (double)acc / (double)M;
+    lam = lam * std::min(2.0, std::max(0.5, 1.0 + (a - target)));
+  }
+  return CCSP_OK;
+}
+
 void mesh_free(MovableMesh* mesh) {
   if (!mesh) return;
+  if (mesh->sched) (void)hipFree(mesh->sched);
   if (mesh->class_dev) (void)hipFree(mesh->class_dev);
   if (mesh->mem) (void)hipFree(mesh->mem);
   delete mesh;

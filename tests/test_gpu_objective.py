@@ -350,3 +350,60 @@ def test_sweep_at_scale_equals_class_calls(ccsp, grid):
             assert torch.equal(XA, XB), f"sweep {sweep}: positions differ"
             assert torch.equal(sA, torch.cat(sB))
             assert (sA == 1).sum().item() > 10000
+
+
+def _unit_draws(rng, s, m):
+    """Heavy-tailed unit draws of Sec. 3.2.2: a point uniform in the unit disk, its radius scaled by
+    a Pareto(1/2) factor (x >= 1)."""
+    r = np.sqrt(rng.random((s, m)))
+    th = 2 * np.pi * rng.random((s, m))
+    f = (1.0 - rng.random((s, m))) ** -2.0
+    return np.ascontiguousarray(np.stack([r * f * np.cos(th), r * f * np.sin(th)], -1))
+
+
+def test_schedule_equals_sequential_annealing(ccsp, tiny):
+    """Four sweeps with falling temperature and contraction length and the adaptive step scale
+    equal the checker's sequential annealing: positions bit for bit, step scales and accepted
+    counts exactly."""
+    mesh, om = tiny
+    p = ob.Params(0.05)
+    temps = [1e-2, 3e-3, 1e-3, 3e-4]
+    epss = [0.05, 0.03, 0.02, 0.01]
+    rng = np.random.default_rng(17)
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        order = np.concatenate(gm.classes())
+        xi = _unit_draws(rng, 4, order.shape[0])
+        u = np.ascontiguousarray(rng.random((4, order.shape[0])))
+        X = torch.from_numpy(mesh.xy.copy()).to(DEV)
+        lam, acc = gm.schedule(X, _params(ccsp, p), temps, epss, 0.05,
+                               torch.from_numpy(xi).to(DEV), torch.from_numpy(u).to(DEV))
+        xy_gpu = X.cpu().numpy()
+    xy_ref, lam_ref, acc_ref, margin = ob.annealing_schedule(om, mesh.xy, p, temps, epss, 0.05,
+                                                              0.23, order, xi, u)
+    assert margin > 1e-10, "a decision lies within rounding of its threshold"
+    assert np.array_equal(acc, acc_ref), (acc, acc_ref)
+    assert np.array_equal(lam, lam_ref), (lam, lam_ref)
+    assert np.array_equal(xy_gpu, xy_ref)
+    assert (acc > 0).all() and len(set(lam.tolist())) > 1
+
+
+def test_schedule_at_scale(ccsp, grid):
+    """Subdivided grid scene: the step scale follows its rule from the accepted counts, and a cold
+    schedule lowers f."""
+    mesh, om = grid
+    p = ob.Params(0.2)
+    rng = np.random.default_rng(23)
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        m = gm.n_movable()
+        params = _params(ccsp, p)
+        X = torch.from_numpy(mesh.xy).to(DEV)
+        f0 = gm.eval(X, params).cpu().numpy()[0]
+        s = 3
+        xi = torch.from_numpy(_unit_draws(rng, s, m)).to(DEV)
+        u = torch.from_numpy(rng.random((s, m))).to(DEV)
+        lam, acc = gm.schedule(X, params, [1e-6] * s, [0.2] * s, 0.02, xi, u)
+        f1 = gm.eval(X, params).cpu().numpy()[0]
+    assert f1 < f0
+    for k in range(s - 1):
+        a = acc[k] / m
+        assert lam[k + 1] == lam[k] * min(2.0, max(0.5, 1.0 + (a - 0.23)))
