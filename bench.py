@@ -389,6 +389,29 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
     ms_sweep = a.elapsed_time(b) / n_sweeps
     f_after = gm.eval(X, p).cpu().tolist()[0]
     del draws
+
+    # an annealing schedule (Secs. 3.2, 3.3.1): temperature and contraction length lowered together
+    # by a factor of 10 over the sweeps, step scale adapted toward 23% acceptance
+    n_sched = 10 if scene_name == "large" else 4
+    ratio = np.geomspace(1.0, 0.1, n_sched)
+    temps = 1e-3 * size * ratio
+    epss = 1e-3 * size * ratio
+    r1 = torch.sqrt(torch.rand((n_sched, n_mov), generator=gen, device=xy.device, dtype=torch.float64))
+    th = 2.0 * np.pi * torch.rand((n_sched, n_mov), generator=gen, device=xy.device,
+                                  dtype=torch.float64)
+    fac = (1.0 - torch.rand((n_sched, n_mov), generator=gen, device=xy.device,
+                            dtype=torch.float64)) ** -2.0
+    xi = torch.stack([r1 * fac * torch.cos(th), r1 * fac * torch.sin(th)], -1).contiguous()
+    us = torch.rand((n_sched, n_mov), generator=gen, device=xy.device, dtype=torch.float64)
+    XS = xy.clone()
+    start = gm.eval(XS, p).cpu().tolist()
+    t_s = time.perf_counter()
+    lam, acc = gm.schedule(XS, p, temps, epss, 0.05, xi, us)
+    ms_sched = (time.perf_counter() - t_s) * 1e3
+    p_end = ccsp.objective_params(epss[-1], None, 1e-10 * size, 1.0 * size, 10.0 * size)
+    end = gm.eval(XS, p_end).cpu().tolist()
+    start_at_end_eps = gm.eval(xy, p_end).cpu().tolist()
+    del xi, us
     comp = (OBJ_BYTES_PER_VERTEX * mesh.n_vertices + OBJ_BYTES_PER_EDGE * gm.n_edges
             + OBJ_BYTES_PER_TRIANGLE * mesh.n_triangles)
     achieved = comp / (ms_eval * 1e-3) / 1e9
@@ -405,6 +428,14 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
                    "sweep_ms": ms_sweep, "vertex_moves_per_s": n_mov / ms_sweep * 1e3,
                    "acceptance": int(accepted.item()) / (n_mov * n_sweeps), "sweeps": n_sweeps,
                    "f_before": f_before, "f_after": f_after},
+        "schedule": {"sweeps": n_sched, "ms_per_sweep": ms_sched / n_sched,
+                     "temperature": [temps[0], temps[-1]], "eps": [epss[0], epss[-1]],
+                     "acceptance": [int(a) / n_mov for a in acc],
+                     "step_scale": [float(x) for x in lam],
+                     "f_start": start[0], "w_contr_start": start[1],
+                     "f_end_at_final_eps": end[0], "w_contr_end_at_final_eps": end[1],
+                     "f_start_at_final_eps": start_at_end_eps[0],
+                     "w_contr_start_at_final_eps": start_at_end_eps[1]},
         "roofline_eval": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                           "bytes_per_eval": comp},
