@@ -34,9 +34,9 @@ BYTES_PER_RAY = 60
 # taken with.
 WALK_SOURCES = ("walk_kernels.hip", "walk.hpp", "decide.hpp", "exact.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "2fc229e351680377671607880b761910116e6704fe5d0099f32761e9578c8572",
-    "tune": [256, 64, 16, 16, 8, 8, 0],
-    "bytes_per_launch": 12150331677,
+    "sources_sha256": "c89874a0a01830dac8ccfdda3cc86ea5ace36e430c0dc5344680c141e6afb45e",
+    "tune": [128, 64, 16, 8, 8, 8, 0],
+    "bytes_per_launch": 12221037820,
 }
 
 
@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--rays", type=int, default=0, help="override the ray count")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the checker leg")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-objective", action="store_true",
+                    help="leave out the objective leg (for profiler runs of the walk)")
     ap.add_argument("--tune", default="", help="wg,tile,waves_per_cu,refill_min")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling HBM "
@@ -228,7 +230,7 @@ def main():
     g_l2 = B.gather_roofline(2 << 20, 16, 2048, stream.cuda_stream)
     walk_steps_s = steps_total / walk_avg
 
-    objective = objective_leg("grid", args.steps, args.warmup)
+    objective = None if args.no_objective else objective_leg("grid", args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu:
