@@ -76,9 +76,18 @@ class Mesh:
         # edge i of a triangle joins v[i+1] and v[i+2]
         a = self.tri_v[:, [1, 2, 0]]
         b = self.tri_v[:, [2, 0, 1]]
-        key = np.minimum(a, b) * self.nv + np.maximum(a, b)
-        uniq, inv = np.unique(key.ravel(), return_inverse=True)
-        self.edge_v = np.stack([uniq // self.nv, uniq % self.nv], axis=1)
+        key = (np.minimum(a, b) * self.nv + np.maximum(a, b)).ravel()
+        # edges = distinct keys in increasing order; a stable sort keeps, for each edge, its
+        # triangles in increasing id (flattened index = 3 t + i)
+        order = np.argsort(key, kind="stable")
+        sk = key[order]
+        first_of = np.ones(sk.shape[0], dtype=bool)
+        first_of[1:] = sk[1:] != sk[:-1]
+        uniq = sk[first_of]
+        inv = np.empty(sk.shape[0], dtype=np.int64)
+        inv[order] = np.cumsum(first_of) - 1
+        lo = uniq // self.nv
+        self.edge_v = np.stack([lo, uniq - lo * self.nv], axis=1)
         self.edge_key = uniq
         self.tri_edge = inv.reshape(T, 3)
         E = uniq.shape[0]
@@ -86,7 +95,6 @@ class Mesh:
         if (cnt > 2).any():
             raise ValueError("an edge is shared by more than two triangles")
         # triangles of each edge, increasing id, with the edge's local index there
-        order = np.argsort(inv, kind="stable")  # flattened index = 3 t + i, so t increases
         first = np.concatenate([[0], np.cumsum(cnt)[:-1]])
         self.edge_tri = -np.ones((E, 2), dtype=np.int64)
         self.edge_loc = -np.ones((E, 2), dtype=np.int64)
@@ -106,7 +114,7 @@ class Mesh:
             self.edge_nbr[has, 2 * j + 1] = self.tri_edge[t, (i + 2) % 3]
         # vertex neighbours (sorted) as CSR
         both = np.concatenate([self.edge_v, self.edge_v[:, ::-1]])
-        both = both[np.lexsort((both[:, 1], both[:, 0]))]
+        both = both[np.argsort(both[:, 0] * self.nv + both[:, 1])]
         self.nbr = both[:, 1]
         self.nbr_off = np.concatenate([[0], np.cumsum(np.bincount(both[:, 0], minlength=self.nv))])
 
@@ -164,6 +172,52 @@ def one_hop_contractible(m: Mesh, xy, eps) -> np.ndarray:
 
 def contractible(m: Mesh, xy, eps) -> np.ndarray:
     return direct_contractible(m) & one_hop_contractible(m, xy, eps)
+
+
+def edge_values(m: Mesh, xy, p: Params, edges):
+    """(contractible, c, w) of the given edges only, from the same definitions applied one edge at
+    a time (for sampling meshes too large to evaluate whole)."""
+    xy = np.asarray(xy, dtype=np.float64)
+
+    def contr_one(e):
+        a, b = m.edge_v[e]
+        ka, kb = m.kind[a], m.kind[b]
+        if ka == ORIGINAL and kb == ORIGINAL:
+            return False
+        for o, c in ((a, b), (b, a)):
+            if m.kind[o] == ORIGINAL and m.kind[c] == CONSTRAINED:
+                if o not in m.prim_v[m.line[c]]:
+                    return False
+        if ka == CONSTRAINED and kb == CONSTRAINED and m.line[a] != m.line[b]:
+            return False
+        na = set(m.nbr[m.nbr_off[a]:m.nbr_off[a + 1]].tolist())
+        nb = set(m.nbr[m.nbr_off[b]:m.nbr_off[b + 1]].tolist())
+        opp = [x for x in m.edge_opp[e] if x >= 0]
+        for h in sorted((na & nb) - set(opp)):
+            if not any(lengths(xy, np.array([h]), np.array([o]))[0] < p.eps for o in opp):
+                return False
+        return True
+
+    def c_one(e):
+        ln = lengths(xy, m.edge_v[e:e + 1, 0], m.edge_v[e:e + 1, 1])
+        return c_eps(ln, np.array([contr_one(e)]), p.eps)[0]
+
+    out_c, out_k, out_w = [], [], []
+    for e in edges:
+        e = int(e)
+        k = contr_one(e)
+        out_k.append(k)
+        out_c.append(c_one(e))
+        if p.polish:
+            out_w.append(1.0)
+            continue
+        n = m.edge_nbr[e]
+        x = c_one(n[0]) * c_one(n[1])
+        if n[2] >= 0:
+            x = x * c_one(n[2])
+            x = x * c_one(n[3])
+        out_w.append(float(x * merge_correction(np.array(x))))
+    return np.array(out_k), np.array(out_c), np.array(out_w)
 
 
 def c_eps(length, contr, eps):

@@ -407,3 +407,62 @@ def test_schedule_at_scale(ccsp, grid):
     for k in range(s - 1):
         a = acc[k] / m
         assert lam[k + 1] == lam[k] * min(2.0, max(0.5, 1.0 + (a - 0.23)))
+
+
+def _submesh(mesh, seeds, rings):
+    """The checker's mesh of the triangles touching a vertex within `rings` edges of the seed
+    vertices, in their original order, vertices relabelled (original-edge ends outside it become
+    -1): enough to evaluate per-edge values of edges between seeds, which read two rings."""
+    tv = mesh.tri_v
+    near = np.zeros(mesh.n_vertices, dtype=bool)
+    near[seeds] = True
+    for _ in range(rings):
+        hit = near[tv].any(axis=1)
+        near[tv[hit].ravel()] = True
+    keep = np.nonzero(near[tv].any(axis=1))[0]
+    sub = tv[keep]
+    verts = np.unique(sub)
+    new = -np.ones(mesh.n_vertices, dtype=np.int64)
+    new[verts] = np.arange(verts.shape[0])
+    pv = np.where(mesh.prim_v >= 0, new[mesh.prim_v], -1)
+    return ob.Mesh(new[sub], mesh.kind[verts], mesh.line[verts], pv), new, verts
+
+
+def test_large_bench_configuration_sampled(ccsp):
+    """The objective's bench configuration: the large scene subdivided once (16,000,008 triangles)
+    with the bench's parameters. Sampled edges' contractibility and weights equal the checker's,
+    computed on the triangles around them, bit for bit; f and its parts equal the sums of terms
+    built from the per-edge weights within the reordering bound."""
+    sc = sg.make_scene("large")
+    mesh = sg.subdivide(sc)
+    size = sc.box[1] - sc.box[0]
+    p = ob.Params(1e-3 * size, eps0=1e-10 * size, mu_angle=1.0 * size, mu_len=10.0 * size)
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        ev = gm.edges().astype(np.int64)
+        out, con, w = gm.eval(torch.from_numpy(mesh.xy).to(DEV), _params(ccsp, p), per_edge=True)
+        torch.cuda.synchronize()
+        out, con, w = out.cpu().numpy(), con.cpu().numpy().astype(bool), w.cpu().numpy()
+    assert ev.shape[0] == 24_000_016
+    rng = np.random.default_rng(12)
+    active = np.nonzero(w < 1.0)[0]
+    assert active.size > 1000 and (~con).any()
+    sample = np.concatenate([rng.choice(ev.shape[0], 1500, replace=False),
+                             rng.choice(active, 500, replace=False),
+                             np.nonzero(~con)[0][:100]])
+    om, new, verts = _submesh(mesh, np.unique(ev[sample]), 2)
+    key = new[ev[sample, 0]] * om.nv + new[ev[sample, 1]]
+    local = np.searchsorted(om.edge_key, key)
+    assert np.array_equal(om.edge_key[local], key), "sampled edges are edges of the mesh"
+    k, _, wr = ob.edge_values(om, mesh.xy[verts], p, local)
+    assert np.array_equal(con[sample], k)
+    assert np.array_equal(w[sample], wr)
+    ln = ob.lengths(mesh.xy, ev[:, 0], ev[:, 1])
+    edge = w * ln
+    tri = type("Triangles", (), {"tri_v": mesh.tri_v.astype(np.int64)})()
+    ang = ob.angle_terms(tri, mesh.xy, p)
+    short = np.maximum(0.0, p.eps0 - ln) / p.eps0
+    for got, terms in ((out[1], edge), (out[2], ang), (out[3], short)):
+        assert abs(got - terms.sum()) <= 2 * terms.size * U * np.abs(terms).sum()
+    f = edge.sum() + p.mu_angle * ang.sum() + p.mu_len * short.sum()
+    scale = np.abs(edge).sum() + p.mu_angle * np.abs(ang).sum() + p.mu_len * np.abs(short).sum()
+    assert abs(out[0] - f) <= 2 * (edge.size + ang.size) * U * scale

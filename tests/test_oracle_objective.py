@@ -276,3 +276,24 @@ def test_metropolis_chain_properties():
     c = xy[con]
     cross = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
     assert (np.abs(cross) <= 1e-12 * (np.abs(b - a).sum(1) * (np.abs(c - a).sum(1) + 1))).all()
+
+
+def test_edge_values_one_by_one_equal_whole_evaluation():
+    """The per-edge evaluation used to sample large meshes equals the whole-mesh evaluation, on a
+    clustered state where contractions, merges and the 1-hop rule all occur."""
+    mesh = sg.subdivide(sg.make_scene("tiny"))
+    m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+    rng = np.random.default_rng(9)
+    xy = mesh.xy.copy()
+    for v in rng.choice(np.nonzero(mesh.kind == sg.FREE)[0], 300):
+        nb = m.nbr[m.nbr_off[v]:m.nbr_off[v + 1]]
+        q = xy[nb[rng.integers(0, nb.shape[0])]] + 0.005 * (rng.random(2) - 0.5)
+        if ob.move_status(m, xy, int(v), q) == ob.MOVED:
+            xy[v] = q
+    for p in (ob.Params(0.03), ob.Params(0.03, polish=True)):
+        ref = ob.objective(m, xy, p)
+        edges = np.arange(m.n_edges)
+        k, c, w = ob.edge_values(m, xy, p, edges)
+        assert np.array_equal(k, ref["contractible"]) and np.array_equal(c, ref["c"])
+        assert np.array_equal(w, ref["w"])
+    assert (ref["w"] == 1.0).all() and (~ref["contractible"]).any()
