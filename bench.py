@@ -231,6 +231,9 @@ def main():
     walk_steps_s = steps_total / walk_avg
 
     objective = None if args.no_objective else objective_leg("grid", args.steps, args.warmup)
+    triangulations = None
+    if args.workload == "grid":
+        triangulations = grid_triangulations(sc, rays, scene, o, d, st, out32, args.steps)
 
     cpu = None
     if not args.no_cpu:
@@ -292,10 +295,43 @@ def main():
             "chase_loads_per_s_l2_sized": g_l2, "l2_sized_bytes": 2 << 20,
             "frac_l2_sized": walk_steps_s / g_l2},
         "objective": objective,
+        "triangulations": triangulations,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     scene.free()
+
+
+def grid_triangulations(sc, rays, scene, o, d, st, out, steps):
+    """The grid scene's CDT and its flip-annealed low-weight triangulation (the paper's claim: lower
+    weight, fewer traversal steps), walked by the same rays: weight, mean steps per ray and rays/s."""
+    import numpy as np
+    import torch
+
+    import paper_2112_05570_amd as ccsp
+    import scenegen as sg
+
+    an, _ = sg.anneal_flips(sc, seed=0)
+    start_an = sg.locate(an, rays.o)
+    assert (start_an >= 0).all()
+    st_an = torch.from_numpy(start_an.astype(np.int32)).to(o.device)
+    res = {}
+    with ccsp.Scene.from_arrays(an) as scene_an:
+        for name, tri, sc_, s in (("cdt", scene, sc, st), ("annealed", scene_an, an, st_an)):
+            ccsp.trace(tri, o, d, s, precision="fp32", out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ccsp.trace(tri, o, d, s, precision="fp32", out=out)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            res[name] = {"triangles": sc_.n_triangles, "weight": sg.weight(sc_),
+                         "mean_steps_per_ray": float(out.steps.double().mean().item()),
+                         "rays_per_s": rays.n / ms * 1e3, "ms_per_trace": ms,
+                         "hits": out.hit_prim.clone()}
+    same = bool(torch.equal(res["cdt"].pop("hits"), res["annealed"].pop("hits")))
+    res["hits_identical"] = same
+    return res
 
 
 # Compulsory bytes of one objective evaluation (every array read once, scratch written and read
