@@ -179,6 +179,32 @@ int anneal_schedule(MovableMesh *mesh, double *xy, const ObjectiveParams *params
                     const double *xi, const double *u, double *lambda_out, int64_t *accepted_out,
                     void *stream);
 
+/*
+ * flip_anneal: simulated annealing of a constrained triangulation by edge flips (Sec. 3.2.6), the
+ * energy being its weight (total edge length), in n_rounds rounds at temperature[r] (HOST). The
+ * triangulation is given in the arrays of ccsp_walk.h, here DEVICE buffers updated in place:
+ * tri_v, tri_nbr, tri_prim (3 * n_triangles int32 each) over positions xy (DEVICE, 2 * n_vertices
+ * binary64, 16-byte aligned). A flip replaces the unconstrained interior edge (b, c) of
+ * t = (a, b, c) and u = (d, c, b) by (a, d) when both (a, b, d) and (a, d, c) are strictly
+ * counter-clockwise (exact); its change of weight is |ad| - |bc| (lengths as in the objective).
+ * It is accepted when the change is < 0, or, at temperature T > 0, when u < exp(-change / T).
+ * Round r: every unconstrained interior edge, named by its slot 3t + i in the triangle of lower
+ * id, draws a 64-bit priority and u = (x >> 11) * 2^-53 as outputs k + 1 and k + 2 of the
+ * SplitMix64 sequence from state seed, k = 2 * (r * 2^32 + slot); each is tested against the
+ * triangulation as the round found it; among the accepted flips, one is applied when its
+ * (priority, slot) beats every other accepted flip touching one of the triangles its flip touches
+ * (its two triangles and their neighbours). The applied flips are independent, so the round is
+ * the same as applying them one after another. After a flip, t holds (a, b, d) and u holds
+ * (a, d, c), in that vertex order, with neighbours and primitive ids following their edges.
+ * flips_out[r] (HOST) receives the number of flips of round r; a round with none at T = 0 leaves
+ * no flip that would lower the weight. The triangulation must be valid (as load_triangulation
+ * checks); triangle ids read from it are range-checked. Allocates scratch of 5 bytes per slot for
+ * the call. Synchronises `stream` after every round.
+ */
+int flip_anneal(int64_t n_vertices, const double *xy, int64_t n_triangles, int32_t *tri_v,
+                int32_t *tri_nbr, int32_t *tri_prim, int32_t n_rounds, const double *temperature,
+                uint64_t seed, int64_t *flips_out, void *stream);
+
 /* mesh_free: release the mesh (after its calls have completed). NULL is ignored. */
 void mesh_free(MovableMesh *mesh);
 

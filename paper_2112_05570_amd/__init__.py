@@ -359,6 +359,29 @@ class MovableMesh:
             pass
 
 
+def flip_anneal(xy, tri_v, tri_nbr, tri_prim, temperatures, seed, stream=None):
+    """Annealing by edge flips with the weight as energy (see ``flip_anneal`` in
+    ccsp_objective.h): xy (V,2) float64 and tri_v, tri_nbr, tri_prim (T,3) int32 CUDA tensors, the
+    latter three updated in place; one round per temperature. Returns the flips of each round
+    (numpy). Synchronous."""
+    import torch
+    for a, dt in ((tri_v, torch.int32), (tri_nbr, torch.int32), (tri_prim, torch.int32)):
+        if not a.is_cuda or a.dtype != dt or a.dim() != 2 or a.shape[1] != 3 or not a.is_contiguous():
+            raise ValueError("tri_v, tri_nbr, tri_prim must be contiguous int32 CUDA tensors (T,3)")
+    if not xy.is_cuda or xy.dtype != torch.float64 or xy.dim() != 2 or xy.shape[1] != 2 \
+            or not xy.is_contiguous():
+        raise ValueError("xy must be a contiguous float64 CUDA tensor (V,2)")
+    if tri_nbr.shape != tri_v.shape or tri_prim.shape != tri_v.shape:
+        raise ValueError("tri_v, tri_nbr and tri_prim must have the same shape")
+    temps = np.ascontiguousarray(temperatures, dtype=np.float64)
+    counts = np.zeros(temps.shape[0], dtype=np.int64)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
+    B.flip_anneal(xy.shape[0], xy.data_ptr(), tri_v.shape[0], tri_v.data_ptr(), tri_nbr.data_ptr(),
+                  tri_prim.data_ptr(), temps.shape[0], p(temps), int(seed), p(counts),
+                  _stream(stream))
+    return counts
+
+
 def objective_params(eps, delta=None, eps0=1e-10, mu_angle=1.0, mu_len=10.0, polish=False):
     """Parameters of the objective (defaults: delta = cos(179 deg) + 1, the paper's eps0 and
     weights for a scene normalised to the unit square)."""

@@ -47,7 +47,7 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
            "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
-           "anneal_moves", "anneal_sweep", "anneal_schedule")
+           "anneal_moves", "anneal_sweep", "anneal_schedule", "flip_anneal")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -170,6 +170,8 @@ _lib.anneal_sweep.restype = _I
 _lib.anneal_schedule.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_int32, _P, _P,
                                  ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P]
 _lib.anneal_schedule.restype = _I
+_lib.flip_anneal.argtypes = [_I64, _P, _I64, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]
+_lib.flip_anneal.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -320,6 +322,14 @@ def anneal_schedule(mesh: int, xy: int, params: ObjectiveParams, n_sweeps: int, 
     _check(_lib.anneal_schedule(_P(mesh), _P(xy), ctypes.byref(params), n_sweeps, _P(temperature),
                                 _P(eps), lambda0, target, _P(xi), _P(u), _P(lambda_out),
                                 _P(accepted_out), _P(stream)))
+
+
+def flip_anneal(n_vertices: int, xy: int, n_triangles: int, tri_v: int, tri_nbr: int,
+                tri_prim: int, n_rounds: int, temperature: int, seed: int, flips_out: int,
+                stream: int = 0) -> None:
+    _check(_lib.flip_anneal(n_vertices, _P(xy), n_triangles, _P(tri_v), _P(tri_nbr), _P(tri_prim),
+                            n_rounds, _P(temperature), seed & ((1 << 64) - 1), _P(flips_out),
+                            _P(stream)))
 
 
 def mesh_free(mesh: int) -> None:

@@ -1,0 +1,269 @@
+// Annealing of a constrained triangulation by edge flips on the GPU (paper Sec. 3.2.6 for the move,
+// Sec. 3.1 for the acceptance), with the total edge length as the energy: the C-ABI flip_anneal of
+// ccsp_objective.h.
+//
+// A flip of the unconstrained interior edge (b, c) between triangles t = (a, b, c) and
+// u = (d, c, b) replaces it by (a, d) when the quad a, b, d, c is strictly convex (exact
+// orientations). It reads and writes t, u and the up to four triangles across their other edges.
+// Each round therefore takes three passes over the edges:
+//   flip_eval    tests every candidate against the triangulation as the round found it (convexity,
+//                change of weight, Metropolis with its own uniform) and records, in both of the
+//                edge's slots, the id of its canonical slot if the flip would be accepted;
+//   flip_select  keeps an accepted flip when its (priority, canonical slot) beats every other
+//                accepted flip that touches one of its touched triangles;
+//   flip_apply   rewrites the kept flips, whose touched triangles are pairwise disjoint.
+// The first two only read the triangulation, the third writes disjoint sets, so a round is the
+// same as applying its kept flips one after another. Priorities and uniforms come from a
+// counter-based generator, SplitMix64 (Steele, Lea and Flood, 2014): outputs k + 1 and k + 2 of the
+// sequence from state seed, k = 2 * (round * 2^32 + canonical slot).
+//
+// Every triangle id read from the arrays is checked against the triangle count before use.
+// Compiled with -ffp-contract=off.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "ccsp_objective.h"
+#include "exact.hpp"
+#include "walk.hpp"
+
+namespace ccsp {
+namespace {
+
+constexpr int kFlipThreads = 256;
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t priority(uint64_t seed, int round, int slot) {
+  const uint64_t k = 2ull * (((uint64_t)round << 32) + (uint64_t)slot);
+  return splitmix64(seed + (k + 1) * kGolden);
+}
+
+__device__ __forceinline__ double uniform(uint64_t seed, int round, int slot) {
+  const uint64_t k = 2ull * (((uint64_t)round << 32) + (uint64_t)slot);
+  return (double)(splitmix64(seed + (k + 2) * kGolden) >> 11) * 0x1p-53;
+}
+
+struct Tri {
+  int32_t* v;
+  int32_t* nbr;
+  int32_t* prim;
+  int32_t nt;
+  int32_t nv;
+};
+
+__device__ __forceinline__ int orient_sign(double2 a, double2 b, double2 c) {
+  const double l = (b.x - a.x) * (c.y - a.y);
+  const double r = (b.y - a.y) * (c.x - a.x);
+  const double det = l - r, sum = fabs(l) + fabs(r);
+  if (fabs(det) > 0x1p-51 * sum && sum > 0x1p-900) return det > 0 ? 1 : -1;
+  return orient_exact(a.x, a.y, b.x, b.y, c.x, c.y);
+}
+
+__device__ __forceinline__ double seg_len(double2 p, double2 q) {
+  const double dx = q.x - p.x, dy = q.y - p.y;
+  return sqrt(dx * dx + dy * dy);
+}
+
+// Local index in w of its edge shared with t, or -1.
+__device__ __forceinline__ int back_of(const Tri& T, int w, int t) {
+  for (int j = 0; j < 3; ++j)
+    if (T.nbr[3 * w + j] == t) return j;
+  return -1;
+}
+
+__device__ __forceinline__ bool valid_tri(const Tri& T, int x) { return x >= 0 && x < T.nt; }
+__device__ __forceinline__ bool valid_vertex(const Tri& T, int x) { return x >= 0 && x < T.nv; }
+
+// Scratch of a round: no accepted flip yet, no flip applied.
+__global__ void __launch_bounds__(kFlipThreads)
+flip_clear(int32_t* __restrict__ key, int64_t n, unsigned long long* __restrict__ count) {
+  const int64_t s = (int64_t)blockIdx.x * kFlipThreads + threadIdx.x;
+  if (s < n) key[s] = -1;
+  if (s == 0) *count = 0;
+}
+
+__global__ void __launch_bounds__(kFlipThreads)
+flip_eval(Tri T, const double2* __restrict__ xy, double temperature, uint64_t seed, int round,
+          int32_t* __restrict__ key) {
+  const int s = blockIdx.x * kFlipThreads + threadIdx.x;
+  if (s >= 3 * T.nt) return;
+  const int t = s / 3, i = s - 3 * t;
+  const int u = T.nbr[s];
+  if (!valid_tri(T, u) || u <= t) return;  // hull, malformed, or the slot of the other triangle
+  int res = -1;
+  const int j = back_of(T, u, t);
+  if (T.prim[s] < 0 && j >= 0) {
+    const int a = T.v[3 * t + i], b = T.v[3 * t + (i + 1) % 3], c = T.v[3 * t + (i + 2) % 3];
+    const int d = T.v[3 * u + j];
+    if (!valid_vertex(T, a) || !valid_vertex(T, b) || !valid_vertex(T, c) || !valid_vertex(T, d))
+      return;
+    const double2 pa = xy[a], pb = xy[b], pc = xy[c], pd = xy[d];
+    if (orient_sign(pa, pb, pd) > 0 && orient_sign(pa, pd, pc) > 0) {
+      const double change = seg_len(pa, pd) - seg_len(pb, pc);
+      if (change < 0.0 ||
+          (temperature > 0.0 && uniform(seed, round, s) < exp(-change / temperature)))
+        res = s;
+    }
+  }
+  key[s] = res;
+  if (j >= 0) key[3 * u + j] = res;
+}
+
+__global__ void __launch_bounds__(kFlipThreads)
+flip_select(Tri T, const int32_t* __restrict__ key, uint64_t seed, int round,
+            uint8_t* __restrict__ keep) {
+  const int s = blockIdx.x * kFlipThreads + threadIdx.x;
+  if (s >= 3 * T.nt) return;
+  const int t = s / 3;
+  if (key[s] != s) {
+    keep[s] = 0;
+    return;
+  }
+  const int u = T.nbr[s];
+  const uint64_t mine = priority(seed, round, s);
+  // touched triangles: t, u and their neighbours
+  int touch[8];
+  int nt = 0;
+  touch[nt++] = t;
+  touch[nt++] = u;
+  for (int w = 0; w < 2; ++w) {
+    const int tw = w == 0 ? t : u;
+    for (int k = 0; k < 3; ++k) {
+      const int x = T.nbr[3 * tw + k];
+      if (valid_tri(T, x) && x != t && x != u) touch[nt++] = x;
+    }
+  }
+  bool win = true;
+  // every accepted flip touching one of those triangles is an edge of it or of a neighbour of it
+  for (int m = 0; m < nt && win; ++m) {
+    const int x = touch[m];
+    for (int h = -1; h < 3 && win; ++h) {
+      const int y = h < 0 ? x : T.nbr[3 * x + h];
+      if (!valid_tri(T, y)) continue;
+      for (int k = 0; k < 3; ++k) {
+        const int s2 = key[3 * y + k];
+        if (s2 < 0 || s2 == s) continue;
+        const uint64_t p2 = priority(seed, round, s2);
+        if (p2 > mine || (p2 == mine && s2 > s)) {
+          win = false;
+          break;
+        }
+      }
+    }
+  }
+  keep[s] = win ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kFlipThreads)
+flip_apply(Tri T, const uint8_t* __restrict__ keep, unsigned long long* __restrict__ count) {
+  const int s = blockIdx.x * kFlipThreads + threadIdx.x;
+  if (s >= 3 * T.nt || !keep[s]) return;
+  const int t = s / 3, i = s - 3 * t;
+  const int u = T.nbr[s];
+  const int j = back_of(T, u, t);
+  if (j < 0) return;  // flip_eval accepted none such
+  const int i1 = i == 2 ? 0 : i + 1, i2 = i1 == 2 ? 0 : i1 + 1;
+  const int j1 = j == 2 ? 0 : j + 1, j2 = j1 == 2 ? 0 : j1 + 1;
+  const int a = T.v[3 * t + i], b = T.v[3 * t + i1], c = T.v[3 * t + i2];
+  const int d = T.v[3 * u + j];
+  const int nt1 = T.nbr[3 * t + i1], pt1 = T.prim[3 * t + i1];  // edge (c, a)
+  const int nt2 = T.nbr[3 * t + i2], pt2 = T.prim[3 * t + i2];  // edge (a, b)
+  const int nu1 = T.nbr[3 * u + j1], pu1 = T.prim[3 * u + j1];  // edge (b, d)
+  const int nu2 = T.nbr[3 * u + j2], pu2 = T.prim[3 * u + j2];  // edge (d, c)
+  T.v[3 * t] = a;
+  T.v[3 * t + 1] = b;
+  T.v[3 * t + 2] = d;
+  T.nbr[3 * t] = nu1;
+  T.nbr[3 * t + 1] = u;
+  T.nbr[3 * t + 2] = nt2;
+  T.prim[3 * t] = pu1;
+  T.prim[3 * t + 1] = -1;
+  T.prim[3 * t + 2] = pt2;
+  T.v[3 * u] = a;
+  T.v[3 * u + 1] = d;
+  T.v[3 * u + 2] = c;
+  T.nbr[3 * u] = nu2;
+  T.nbr[3 * u + 1] = nt1;
+  T.nbr[3 * u + 2] = t;
+  T.prim[3 * u] = pu2;
+  T.prim[3 * u + 1] = pt1;
+  T.prim[3 * u + 2] = -1;
+  if (valid_tri(T, nu1)) {
+    const int k = back_of(T, nu1, u);
+    if (k >= 0) T.nbr[3 * nu1 + k] = t;
+  }
+  if (valid_tri(T, nt1)) {
+    const int k = back_of(T, nt1, t);
+    if (k >= 0) T.nbr[3 * nt1 + k] = u;
+  }
+  atomicAdd(count, 1ull);
+}
+
+}  // namespace
+}  // namespace ccsp
+
+extern "C" int flip_anneal(int64_t n_vertices, const double* xy, int64_t n_triangles,
+                           int32_t* tri_v, int32_t* tri_nbr, int32_t* tri_prim, int32_t n_rounds,
+                           const double* temperature, uint64_t seed, int64_t* flips_out,
+                           void* stream) {
+  using ccsp::set_last_error;
+  auto fail = [](int code, const char* msg) {
+    set_last_error(msg);
+    return code;
+  };
+  if (!xy || !tri_v || !tri_nbr || !tri_prim || n_vertices <= 0 || n_triangles <= 0 ||
+      n_rounds < 0 || (n_rounds > 0 && (!temperature || !flips_out)))
+    return fail(CCSP_E_ARG, "flip_anneal: null argument or empty triangulation");
+  if (n_triangles >= (int64_t(1) << 29) || n_vertices >= (int64_t(1) << 31))
+    return fail(CCSP_E_ARG, "flip_anneal: triangulation too large for 32-bit slots");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)tri_v & 3) != 0 || ((uintptr_t)tri_nbr & 3) != 0 ||
+      ((uintptr_t)tri_prim & 3) != 0)
+    return fail(CCSP_E_ARG, "flip_anneal: misaligned buffer");
+  for (int32_t r = 0; r < n_rounds; ++r)
+    if (!(temperature[r] >= 0) || !std::isfinite(temperature[r]))
+      return fail(CCSP_E_ARG, "flip_anneal: temperatures must be finite and >= 0");
+  if (n_rounds == 0) return CCSP_OK;
+  const int64_t slots = 3 * n_triangles;
+  void* mem = nullptr;
+  const size_t bytes = 4 * (size_t)slots + (size_t)slots + 256;
+  hipError_t e = hipMalloc(&mem, bytes);
+  if (e != hipSuccess) return fail(CCSP_E_OOM, "flip_anneal: device allocation failed");
+  auto* key = (int32_t*)mem;
+  auto* keep = (uint8_t*)(key + slots);
+  // the counter sits past both arrays, 8-byte aligned (within the 256 bytes of slack)
+  auto* count = (unsigned long long*)(((uintptr_t)(keep + slots) + 7) & ~uintptr_t(7));
+  hipStream_t s = (hipStream_t)stream;
+  const ccsp::Tri T{tri_v, tri_nbr, tri_prim, (int32_t)n_triangles, (int32_t)n_vertices};
+  const unsigned blocks = (unsigned)((slots + ccsp::kFlipThreads - 1) / ccsp::kFlipThreads);
+  int rc = CCSP_OK;
+  for (int32_t r = 0; r < n_rounds && rc == CCSP_OK; ++r) {
+    hipLaunchKernelGGL(ccsp::flip_clear, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, key, slots,
+                       count);
+    hipLaunchKernelGGL(ccsp::flip_eval, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, T,
+                       (const double2*)xy, temperature[r], seed, r, key);
+    hipLaunchKernelGGL(ccsp::flip_select, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, T, key,
+                       seed, r, keep);
+    hipLaunchKernelGGL(ccsp::flip_apply, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, T, keep,
+                       count);
+    unsigned long long n = 0;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&n, count, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      rc = fail(CCSP_E_HIP, "flip_anneal: launch or copy failed");
+      break;
+    }
+    flips_out[r] = (int64_t)n;
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(mem);
+  return rc;
+}

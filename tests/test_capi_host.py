@@ -210,3 +210,23 @@ def test_objective_calls_reject_null_arguments():
         B.objective_delta(0, 0, p, 0, 0, 1, 0, 0)
     with pytest.raises(B.CcspError, match="null argument"):
         B.mesh_info(0)
+
+
+def test_flip_anneal_rejects_before_any_device_call():
+    """Argument errors are found on the host; zero rounds return at once (no device call)."""
+    xy = np.zeros((4, 2), np.float64)
+    tri = np.zeros((2, 3), np.int32)
+    temps = np.array([1.0, -0.5])
+    cnt = np.zeros(2, np.int64)
+    p = lambda a: a.ctypes.data
+    with pytest.raises(B.CcspError, match="null argument"):
+        B.flip_anneal(4, 0, 2, p(tri), p(tri), p(tri), 2, p(temps), 0, p(cnt))
+    with pytest.raises(B.CcspError, match="null argument"):
+        B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), 2, 0, 0, p(cnt))
+    with pytest.raises(B.CcspError, match="temperatures"):
+        B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), 2, p(temps), 0, p(cnt))
+    with pytest.raises(B.CcspError, match="misaligned"):
+        B.flip_anneal(4, p(xy) + 8, 2, p(tri), p(tri), p(tri), 1, p(temps), 0, p(cnt))
+    with pytest.raises(B.CcspError, match="too large"):
+        B.flip_anneal(4, p(xy), 1 << 29, p(tri), p(tri), p(tri), 1, p(temps), 0, p(cnt))
+    B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), 0, 0, 0, 0)
