@@ -198,8 +198,9 @@ int anneal_schedule(MovableMesh *mesh, double *xy, const ObjectiveParams *params
  * (a, d, c), in that vertex order, with neighbours and primitive ids following their edges.
  * flips_out[r] (HOST) receives the number of flips of round r; a round with none at T = 0 leaves
  * no flip that would lower the weight. The triangulation must be valid (as load_triangulation
- * checks); triangle ids read from it are range-checked. Allocates scratch of 5 bytes per slot for
- * the call. Synchronises `stream` after every round.
+ * checks); triangle and vertex ids read from it are range-checked. n_rounds <= 2^20. Allocates
+ * device scratch for the call: 5 bytes per slot, 4 per triangle and 512 per round; the rounds are
+ * queued on `stream` back to back and the call synchronises it once, at the end.
  */
 int flip_anneal(int64_t n_vertices, const double *xy, int64_t n_triangles, int32_t *tri_v,
                 int32_t *tri_nbr, int32_t *tri_prim, int32_t n_rounds, const double *temperature,

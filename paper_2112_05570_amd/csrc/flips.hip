@@ -4,15 +4,19 @@
 //
 // A flip of the unconstrained interior edge (b, c) between triangles t = (a, b, c) and
 // u = (d, c, b) replaces it by (a, d) when the quad a, b, d, c is strictly convex (exact
-// orientations). It reads and writes t, u and the up to four triangles across their other edges.
-// Each round therefore takes three passes over the edges:
-//   flip_eval    tests every candidate against the triangulation as the round found it (convexity,
-//                change of weight, Metropolis with its own uniform) and records, in both of the
-//                edge's slots, the id of its canonical slot if the flip would be accepted;
-//   flip_select  keeps an accepted flip when its (priority, canonical slot) beats every other
-//                accepted flip that touches one of its touched triangles;
-//   flip_apply   rewrites the kept flips, whose touched triangles are pairwise disjoint.
-// The first two only read the triangulation, the third writes disjoint sets, so a round is the
+// orientations). It reads and writes t, u and the up to four triangles across their other edges
+// (its touched triangles). Each round takes four passes:
+//   flip_eval    (per slot) tests every candidate against the triangulation as the round found
+//                it (convexity, change of weight, Metropolis with its own uniform) and records, in
+//                both of the edge's slots, the id of its canonical slot if the flip would be
+//                accepted;
+//   flip_best    (per triangle) the accepted flip of highest (priority, canonical slot) among
+//                those that touch the triangle: the edges of the triangle and of its neighbours;
+//   flip_select  (per slot) keeps an accepted flip when it is the best of all its touched
+//                triangles, i.e. beats every other accepted flip touching one of them;
+//   flip_apply   (per slot) rewrites the kept flips, whose touched triangles are pairwise
+//                disjoint, counts them per block, and clears the slot's record for the next round.
+// The first three only read the triangulation, the fourth writes disjoint sets, so a round is the
 // same as applying its kept flips one after another. Priorities and uniforms come from a
 // counter-based generator, SplitMix64 (Steele, Lea and Flood, 2014): outputs k + 1 and k + 2 of the
 // sequence from state seed, k = 2 * (round * 2^32 + canonical slot).
@@ -24,6 +28,7 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "ccsp_objective.h"
 #include "exact.hpp"
@@ -82,12 +87,19 @@ __device__ __forceinline__ int back_of(const Tri& T, int w, int t) {
 __device__ __forceinline__ bool valid_tri(const Tri& T, int x) { return x >= 0 && x < T.nt; }
 __device__ __forceinline__ bool valid_vertex(const Tri& T, int x) { return x >= 0 && x < T.nv; }
 
-// Scratch of a round: no accepted flip yet, no flip applied.
+// Flip counts of a round are spread over this many counters, a block adding into one of them.
+constexpr int kCountLanes = 64;
+
+// Scratch of a call: no accepted flip recorded, no flip counted.
 __global__ void __launch_bounds__(kFlipThreads)
-flip_clear(int32_t* __restrict__ key, int64_t n, unsigned long long* __restrict__ count) {
-  const int64_t s = (int64_t)blockIdx.x * kFlipThreads + threadIdx.x;
-  if (s < n) key[s] = -1;
-  if (s == 0) *count = 0;
+flip_clear(int32_t* __restrict__ key, int64_t n, unsigned long long* __restrict__ count,
+           int64_t n_count) {
+  const int64_t stride = (int64_t)gridDim.x * kFlipThreads;
+  for (int64_t s = (int64_t)blockIdx.x * kFlipThreads + threadIdx.x; s < n || s < n_count;
+       s += stride) {
+    if (s < n) key[s] = -1;
+    if (s < n_count) count[s] = 0;
+  }
 }
 
 __global__ void __launch_bounds__(kFlipThreads)
@@ -118,58 +130,52 @@ flip_eval(Tri T, const double2* __restrict__ xy, double temperature, uint64_t se
 }
 
 __global__ void __launch_bounds__(kFlipThreads)
-flip_select(Tri T, const int32_t* __restrict__ key, uint64_t seed, int round,
+flip_best(Tri T, const int32_t* __restrict__ key, uint64_t seed, int round,
+          int32_t* __restrict__ best) {
+  const int x = blockIdx.x * kFlipThreads + threadIdx.x;
+  if (x >= T.nt) return;
+  int top = -1;
+  uint64_t top_p = 0;
+  for (int h = -1; h < 3; ++h) {
+    const int y = h < 0 ? x : T.nbr[3 * x + h];
+    if (!valid_tri(T, y)) continue;
+    for (int k = 0; k < 3; ++k) {
+      const int s2 = key[3 * y + k];
+      if (s2 < 0 || s2 == top) continue;
+      const uint64_t p2 = priority(seed, round, s2);
+      if (top < 0 || p2 > top_p || (p2 == top_p && s2 > top)) {
+        top = s2;
+        top_p = p2;
+      }
+    }
+  }
+  best[x] = top;
+}
+
+__global__ void __launch_bounds__(kFlipThreads)
+flip_select(Tri T, const int32_t* __restrict__ key, const int32_t* __restrict__ best,
             uint8_t* __restrict__ keep) {
   const int s = blockIdx.x * kFlipThreads + threadIdx.x;
   if (s >= 3 * T.nt) return;
-  const int t = s / 3;
-  if (key[s] != s) {
-    keep[s] = 0;
-    return;
-  }
-  const int u = T.nbr[s];
-  const uint64_t mine = priority(seed, round, s);
-  // touched triangles: t, u and their neighbours
-  int touch[8];
-  int nt = 0;
-  touch[nt++] = t;
-  touch[nt++] = u;
-  for (int w = 0; w < 2; ++w) {
-    const int tw = w == 0 ? t : u;
-    for (int k = 0; k < 3; ++k) {
-      const int x = T.nbr[3 * tw + k];
-      if (valid_tri(T, x) && x != t && x != u) touch[nt++] = x;
-    }
-  }
-  bool win = true;
-  // every accepted flip touching one of those triangles is an edge of it or of a neighbour of it
-  for (int m = 0; m < nt && win; ++m) {
-    const int x = touch[m];
-    for (int h = -1; h < 3 && win; ++h) {
-      const int y = h < 0 ? x : T.nbr[3 * x + h];
-      if (!valid_tri(T, y)) continue;
-      for (int k = 0; k < 3; ++k) {
-        const int s2 = key[3 * y + k];
-        if (s2 < 0 || s2 == s) continue;
-        const uint64_t p2 = priority(seed, round, s2);
-        if (p2 > mine || (p2 == mine && s2 > s)) {
-          win = false;
-          break;
-        }
-      }
+  bool win = key[s] == s;
+  if (win) {
+    const int t = s / 3, u = T.nbr[s];  // valid: flip_eval accepted the flip
+    win = best[t] == s && best[u] == s;
+    for (int k = 0; k < 3 && win; ++k) {
+      const int xt = T.nbr[3 * t + k], xu = T.nbr[3 * u + k];
+      if (valid_tri(T, xt) && best[xt] != s) win = false;
+      if (valid_tri(T, xu) && best[xu] != s) win = false;
     }
   }
   keep[s] = win ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(kFlipThreads)
-flip_apply(Tri T, const uint8_t* __restrict__ keep, unsigned long long* __restrict__ count) {
-  const int s = blockIdx.x * kFlipThreads + threadIdx.x;
-  if (s >= 3 * T.nt || !keep[s]) return;
+// Rewrites the flip of slot s; false if the adjacency is not symmetric (never for a kept flip).
+__device__ __forceinline__ bool apply_one(const Tri& T, int s) {
   const int t = s / 3, i = s - 3 * t;
   const int u = T.nbr[s];
   const int j = back_of(T, u, t);
-  if (j < 0) return;  // flip_eval accepted none such
+  if (j < 0) return false;
   const int i1 = i == 2 ? 0 : i + 1, i2 = i1 == 2 ? 0 : i1 + 1;
   const int j1 = j == 2 ? 0 : j + 1, j2 = j1 == 2 ? 0 : j1 + 1;
   const int a = T.v[3 * t + i], b = T.v[3 * t + i1], c = T.v[3 * t + i2];
@@ -204,7 +210,20 @@ flip_apply(Tri T, const uint8_t* __restrict__ keep, unsigned long long* __restri
     const int k = back_of(T, nt1, t);
     if (k >= 0) T.nbr[3 * nt1 + k] = u;
   }
-  atomicAdd(count, 1ull);
+  return true;
+}
+
+__global__ void __launch_bounds__(kFlipThreads)
+flip_apply(Tri T, const uint8_t* __restrict__ keep, int32_t* __restrict__ key,
+           unsigned long long* __restrict__ count) {
+  const int s = blockIdx.x * kFlipThreads + threadIdx.x;
+  bool flip = false;
+  if (s < 3 * T.nt) {
+    key[s] = -1;  // the record is not read again this round
+    flip = keep[s] && apply_one(T, s);
+  }
+  const int n = __syncthreads_count(flip);
+  if (threadIdx.x == 0 && n > 0) atomicAdd(count + blockIdx.x % kCountLanes, (unsigned long long)n);
 }
 
 }  // namespace
@@ -224,6 +243,7 @@ extern "C" int flip_anneal(int64_t n_vertices, const double* xy, int64_t n_trian
     return fail(CCSP_E_ARG, "flip_anneal: null argument or empty triangulation");
   if (n_triangles >= (int64_t(1) << 29) || n_vertices >= (int64_t(1) << 31))
     return fail(CCSP_E_ARG, "flip_anneal: triangulation too large for 32-bit slots");
+  if (n_rounds > (1 << 20)) return fail(CCSP_E_ARG, "flip_anneal: more than 2^20 rounds");
   if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)tri_v & 3) != 0 || ((uintptr_t)tri_nbr & 3) != 0 ||
       ((uintptr_t)tri_prim & 3) != 0)
     return fail(CCSP_E_ARG, "flip_anneal: misaligned buffer");
@@ -232,35 +252,43 @@ extern "C" int flip_anneal(int64_t n_vertices, const double* xy, int64_t n_trian
       return fail(CCSP_E_ARG, "flip_anneal: temperatures must be finite and >= 0");
   if (n_rounds == 0) return CCSP_OK;
   const int64_t slots = 3 * n_triangles;
+  const int64_t n_count = (int64_t)n_rounds * ccsp::kCountLanes;
   void* mem = nullptr;
-  const size_t bytes = 4 * (size_t)slots + (size_t)slots + 256;
+  // per-round counters first (8-byte aligned), then key, best and keep
+  const size_t bytes = 8 * (size_t)n_count + 4 * (size_t)slots + 4 * (size_t)n_triangles +
+                       (size_t)slots;
   hipError_t e = hipMalloc(&mem, bytes);
   if (e != hipSuccess) return fail(CCSP_E_OOM, "flip_anneal: device allocation failed");
-  auto* key = (int32_t*)mem;
-  auto* keep = (uint8_t*)(key + slots);
-  // the counter sits past both arrays, 8-byte aligned (within the 256 bytes of slack)
-  auto* count = (unsigned long long*)(((uintptr_t)(keep + slots) + 7) & ~uintptr_t(7));
+  auto* count = (unsigned long long*)mem;
+  auto* key = (int32_t*)(count + n_count);
+  auto* best = key + slots;
+  auto* keep = (uint8_t*)(best + n_triangles);
   hipStream_t s = (hipStream_t)stream;
   const ccsp::Tri T{tri_v, tri_nbr, tri_prim, (int32_t)n_triangles, (int32_t)n_vertices};
   const unsigned blocks = (unsigned)((slots + ccsp::kFlipThreads - 1) / ccsp::kFlipThreads);
-  int rc = CCSP_OK;
-  for (int32_t r = 0; r < n_rounds && rc == CCSP_OK; ++r) {
-    hipLaunchKernelGGL(ccsp::flip_clear, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, key, slots,
-                       count);
+  const unsigned tblocks = (unsigned)((n_triangles + ccsp::kFlipThreads - 1) / ccsp::kFlipThreads);
+  hipLaunchKernelGGL(ccsp::flip_clear, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, key, slots,
+                     count, n_count);
+  for (int32_t r = 0; r < n_rounds; ++r) {
     hipLaunchKernelGGL(ccsp::flip_eval, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, T,
                        (const double2*)xy, temperature[r], seed, r, key);
+    hipLaunchKernelGGL(ccsp::flip_best, dim3(tblocks), dim3(ccsp::kFlipThreads), 0, s, T, key, seed,
+                       r, best);
     hipLaunchKernelGGL(ccsp::flip_select, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, T, key,
-                       seed, r, keep);
-    hipLaunchKernelGGL(ccsp::flip_apply, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, T, keep,
-                       count);
+                       best, keep);
+    hipLaunchKernelGGL(ccsp::flip_apply, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, T, keep, key,
+                       count + (int64_t)r * ccsp::kCountLanes);
+  }
+  int rc = CCSP_OK;
+  std::vector<unsigned long long> lanes((size_t)n_count);
+  e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(lanes.data(), count, 8 * (size_t)n_count, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) rc = fail(CCSP_E_HIP, "flip_anneal: launch or copy failed");
+  for (int32_t r = 0; r < n_rounds && rc == CCSP_OK; ++r) {
     unsigned long long n = 0;
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&n, count, 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      rc = fail(CCSP_E_HIP, "flip_anneal: launch or copy failed");
-      break;
-    }
+    for (int l = 0; l < ccsp::kCountLanes; ++l) n += lanes[(size_t)r * ccsp::kCountLanes + l];
     flips_out[r] = (int64_t)n;
   }
   (void)hipStreamSynchronize(s);
