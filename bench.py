@@ -61,10 +61,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "grid", "tiny", "batch", "serve", "objective"],
+                    choices=["large", "grid", "tiny", "batch", "serve", "objective", "flips"],
                     help="batch: the 256-scene workload in one graph-replayed, autotuned launch; "
                          "serve: the request server under Poisson arrivals; objective: the "
-                         "low-weight objective on the subdivided large scene")
+                         "low-weight objective on the subdivided large scene; flips: edge-flip "
+                         "annealing of the grid scene's CDT")
     ap.add_argument("--requests", type=int, default=10_000, help="serve: requests per level")
     ap.add_argument("--slots", type=int, default=4, help="serve: launch slots")
     ap.add_argument("--tune-cache", default=TUNE_TABLE,
@@ -110,6 +111,10 @@ def main():
         return
     if args.workload == "objective":
         print(json.dumps(objective_leg("large", args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "flips":
+        sc = sg.make_scene("grid", seed=0)
+        print(json.dumps(flip_leg(sc, args.steps)[2]), flush=True)
         return
     dev = torch.device("cuda:0")
     t0 = time.time()
@@ -302,22 +307,67 @@ def main():
     scene.free()
 
 
-def grid_triangulations(sc, rays, scene, o, d, st, out, steps):
-    """The grid scene's CDT and its flip-annealed low-weight triangulation (the paper's claim: lower
-    weight, fewer traversal steps), walked by the same rays: weight, mean steps per ray and rays/s."""
+def flip_leg(sc, steps, hot=300, cold=100, t0_rel=5e-3, t1_rel=1e-5, seed=0):
+    """GPU edge-flip annealing (flip_anneal) of a scene's CDT with the weight as energy: `hot`
+    rounds at temperatures falling geometrically from t0_rel to t1_rel of the box side, then
+    `cold` rounds at 0. Each timed run starts from a fresh copy of the CDT (copied outside the
+    timed region). The scene generator's sequential flip annealer is timed beside it for
+    context. Returns (annealed Scene, results)."""
     import numpy as np
     import torch
 
     import paper_2112_05570_amd as ccsp
     import scenegen as sg
 
-    an, _ = sg.anneal_flips(sc, seed=0)
-    start_an = sg.locate(an, rays.o)
-    assert (start_an >= 0).all()
-    st_an = torch.from_numpy(start_an.astype(np.int32)).to(o.device)
-    res = {}
-    with ccsp.Scene.from_arrays(an) as scene_an:
-        for name, tri, sc_, s in (("cdt", scene, sc, st), ("annealed", scene_an, an, st_an)):
+    side = sc.box[1] - sc.box[0]
+    temps = list(side * np.geomspace(t0_rel, t1_rel, hot)) + [0.0] * cold
+    xy = torch.from_numpy(np.ascontiguousarray(sc.xy)).cuda()
+    base = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+            for a in (sc.tri_v, sc.tri_nbr, sc.tri_prim)]
+    times = []
+    for _ in range(max(1, steps)):
+        arrs = [a.clone() for a in base]
+        torch.cuda.synchronize()
+        t_s = time.perf_counter()
+        counts = ccsp.flip_anneal(xy, *arrs, temps, seed)  # synchronous
+        times.append((time.perf_counter() - t_s) * 1e3)
+    an = sc.copy_with(*[a.cpu().numpy() for a in arrs], name=sc.name + "/gpu-annealed")
+    t_s = time.perf_counter()
+    host, host_stats = sg.anneal_flips(sc, seed=0)
+    host_s = time.perf_counter() - t_s
+    ms = float(np.median(times))
+    res = {"rounds": len(temps), "hot_rounds": hot, "temperature": [temps[0], temps[hot - 1]],
+           "ms": ms, "us_per_round": ms * 1e3 / len(temps), "flips": int(counts.sum()),
+           "last_round_with_flips": int(np.nonzero(counts)[0][-1]),
+           "weight_cdt": sg.weight(sc), "weight": sg.weight(an),
+           "host_sequential": {"s": host_s, "weight": sg.weight(host),
+                               "proposals": int(host_stats["proposals"])}}
+    return an, host, res
+
+
+def grid_triangulations(sc, rays, scene, o, d, st, out, steps):
+    """The grid scene's CDT and its low-weight triangulations by edge-flip annealing (the paper's
+    claim: lower weight, fewer traversal steps), walked by the same rays: weight, mean steps per
+    ray and rays/s. Annealed by the GPU (flip_anneal) and by the scene generator's sequential
+    annealer."""
+    import numpy as np
+    import torch
+
+    import paper_2112_05570_amd as ccsp
+    import scenegen as sg
+
+    gpu_an, host_an, flips = flip_leg(sc, steps)
+    res = {"flip_anneal": flips}
+    hits = {}
+    for name, sc_ in (("cdt", sc), ("gpu_annealed", gpu_an), ("host_annealed", host_an)):
+        if name == "cdt":
+            tri, s = scene, st
+        else:
+            start = sg.locate(sc_, rays.o)
+            assert (start >= 0).all()
+            s = torch.from_numpy(start.astype(np.int32)).to(o.device)
+            tri = ccsp.Scene.from_arrays(sc_)
+        try:
             ccsp.trace(tri, o, d, s, precision="fp32", out=out)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -325,12 +375,15 @@ def grid_triangulations(sc, rays, scene, o, d, st, out, steps):
                 ccsp.trace(tri, o, d, s, precision="fp32", out=out)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) / steps * 1e3
-            res[name] = {"triangles": sc_.n_triangles, "weight": sg.weight(sc_),
-                         "mean_steps_per_ray": float(out.steps.double().mean().item()),
-                         "rays_per_s": rays.n / ms * 1e3, "ms_per_trace": ms,
-                         "hits": out.hit_prim.clone()}
-    same = bool(torch.equal(res["cdt"].pop("hits"), res["annealed"].pop("hits")))
-    res["hits_identical"] = same
+        finally:
+            if tri is not scene:
+                tri.free()
+        res[name] = {"triangles": sc_.n_triangles, "weight": sg.weight(sc_),
+                     "mean_steps_per_ray": float(out.steps.double().mean().item()),
+                     "rays_per_s": rays.n / ms * 1e3, "ms_per_trace": ms}
+        hits[name] = (out.hit_prim.clone(), out.hit_t.clone())
+    res["hits_identical"] = all(torch.equal(hits["cdt"][0], h[0]) and torch.equal(hits["cdt"][1], h[1])
+                                for h in hits.values())
     return res
 
 

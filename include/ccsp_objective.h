@@ -180,7 +180,7 @@ int anneal_schedule(MovableMesh *mesh, double *xy, const ObjectiveParams *params
                     void *stream);
 
 /*
- * flip_anneal: simulated annealing of a constrained triangulation by edge flips (Sec. 3.2.6), the
+ * flip_anneal: simulated annealing of a constrained triangulation by edge flips (Sec. 3.2.7), the
  * energy being its weight (total edge length), in n_rounds rounds at temperature[r] (HOST). The
  * triangulation is given in the arrays of ccsp_walk.h, here DEVICE buffers updated in place:
  * tri_v, tri_nbr, tri_prim (3 * n_triangles int32 each) over positions xy (DEVICE, 2 * n_vertices

@@ -3,7 +3,7 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU leg may import this module. The
 GPU library never does and shares no code with it.
 
-What is computed (paper Sec. 3.2.6 for the move, Sec. 3.1 for the acceptance; the energy is the
+What is computed (paper Sec. 3.2.7 for the move, Sec. 3.1 for the acceptance; the energy is the
 total edge length, the weight the paper minimises):
 - an unconstrained interior edge (b, c) between triangles (a, b, c) and (d, c, b) may flip to
   (a, d) when the quad a, b, d, c is strictly convex (both new triangles strictly

@@ -1,4 +1,4 @@
-// Annealing of a constrained triangulation by edge flips on the GPU (paper Sec. 3.2.6 for the move,
+// Annealing of a constrained triangulation by edge flips on the GPU (paper Sec. 3.2.7 for the move,
 // Sec. 3.1 for the acceptance), with the total edge length as the energy: the C-ABI flip_anneal of
 // ccsp_objective.h.
 //

@@ -41,7 +41,7 @@ def _params(ccsp, p: ob.Params):
 
 def _clustered(mesh, om, p, seed, n_try=3000):
     """Positions after moves that pull free and constrained vertices next to a neighbour
-    (contraction-to-neighbour moves of Sec. 3.2.5), each kept if the checker finds it valid."""
+    (contraction-to-neighbour moves of Sec. 3.2.6), each kept if the checker finds it valid."""
     rng = np.random.default_rng(seed)
     xy = mesh.xy.copy()
     movable = np.nonzero(mesh.kind != sg.ORIGINAL)[0]
