@@ -17,7 +17,11 @@ What is computed (paper Sec. 2.2):
 - f = w_contr + mu_angle * P_angle + mu_len * P_len (Sec. 2.2.4);
 - for a proposed single-vertex move (Sec. 3.2.1, 3.2.2), its validity (the triangulation keeps
   every triangle strictly counter-clockwise, decided exactly) and
-  delta_f = f(moved) - f(current), summed term by term over every term of f.
+  delta_f = f(moved) - f(current), summed term by term over every term of f;
+- the proposals of Secs. 3.2.4-3.2.6 for one vertex at a time: a position uniform by area over
+  its triangles (resampling), a position near one of its neighbours for a vertex on an edge
+  shorter than a drawn length (swapping a contracted edge), and a resampling kept only when it
+  changes whether the vertex is contracted (contracting to a neighbour).
 
 Every value is binary64, evaluated in the operation order written below with no fused operations
 (numpy does not fuse), so that each term is a fixed function of the coordinates.
@@ -40,6 +44,8 @@ Readings of points the paper leaves open:
   in its local order after the edge itself, multiplied left to right.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -401,3 +407,108 @@ def annealing_schedule(m: Mesh, xy, p: Params, temperatures, eps, lambda0, targe
         a = acc / len(order)
         lam = lam * min(2.0, max(0.5, 1.0 + (a - target)))
     return xy, np.array(lams), np.array(accs), margin_min
+
+
+# Proposal kinds of proposal_chain and the status of a vertex the perturbation does not apply to.
+RESAMPLE, SWAP, CONTRACT = 1, 2, 3
+SKIPPED = 3
+
+
+def _tri_area(xy, tv):
+    a, b, c = (xy[k] for k in tv)
+    return 0.5 * ((b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]))
+
+
+def resample_in_star(m: Mesh, xy, v, r0, r1, r2):
+    """Sec. 3.2.4: a position uniform by area over the triangles around vertex v (its star).
+    With r0, r1, r2 uniform on [0, 1): the triangle is the first, in increasing id, at which the
+    running sum of the star's areas (each as in star_area) exceeds r0 times their total; the point
+    is (1 - s) a + s (1 - r2) b + s r2 c on its vertices in stored order, s = sqrt(r1), which is
+    uniform on the triangle (Osada, Funkhouser, Chazelle and Dobkin, 2002)."""
+    tris = np.nonzero((m.tri_v == v).any(axis=1))[0]
+    areas = [_tri_area(xy, m.tri_v[t]) for t in tris]
+    total = 0.0
+    for a in areas:
+        total = total + a
+    target = r0 * total
+    run, pick = 0.0, tris[-1]
+    for t, a in zip(tris, areas):
+        run = run + a
+        if target < run:
+            pick = t
+            break
+    a, b, c = (xy[k] for k in m.tri_v[pick])
+    s = math.sqrt(r1)
+    ka, kb, kc = 1.0 - s, s * (1.0 - r2), s * r2
+    return np.array([ka * a[0] + kb * b[0] + kc * c[0], ka * a[1] + kb * b[1] + kc * c[1]])
+
+
+def incident_lengths(m: Mesh, xy, v, q=None):
+    """Lengths of the edges at v (neighbours in increasing id), with v at q when given."""
+    nb = m.nbr[m.nbr_off[v]:m.nbr_off[v + 1]]
+    P = xy[v] if q is None else q
+    dx = xy[nb, 0] - P[0]
+    dy = xy[nb, 1] - P[1]
+    return np.sqrt(dx * dx + dy * dy)
+
+
+def propose(m: Mesh, xy, p: Params, v, kind, r):
+    """The position proposed for vertex v by one perturbation, or None when it does not apply.
+    r holds four numbers: r[0], r[1], r[2] uniform on [0, 1) and, for SWAP, (r[2], r[3]) a point of
+    the unit disk.
+    - RESAMPLE (Sec. 3.2.4): resample_in_star with r[0], r[1], r[2].
+    - SWAP (Sec. 3.2.5): l = (0.2 + 1.8 r[0]) eps, uniform on [0.2 eps, 2 eps); v must have an edge
+      shorter than l; its neighbour w of rank floor(r[1] deg) (increasing id) is chosen and the
+      position is w + l (r[2], r[3]), uniform on the disk of radius l around w.
+    - CONTRACT (Sec. 3.2.6): the RESAMPLE position, kept only when v is contracted (has an edge
+      shorter than eps) at exactly one of its old and new positions: one try, no repetition.
+    A constrained vertex's move q - o is projected on its original edge first (Sec. 3.2.1)."""
+    o = xy[v]
+    if kind in (RESAMPLE, CONTRACT):
+        q = resample_in_star(m, xy, v, r[0], r[1], r[2])
+    elif kind == SWAP:
+        ln = (0.2 + 1.8 * r[0]) * p.eps
+        if not (incident_lengths(m, xy, v) < ln).any():
+            return None
+        nb = m.nbr[m.nbr_off[v]:m.nbr_off[v + 1]]
+        w = nb[min(int(r[1] * nb.shape[0]), nb.shape[0] - 1)]
+        q = np.array([xy[w, 0] + ln * r[2], xy[w, 1] + ln * r[3]])
+    else:
+        raise ValueError(f"unknown proposal kind {kind}")
+    q = o + project(m, xy, v, q - o)
+    if kind == CONTRACT:
+        before = bool((incident_lengths(m, xy, v) < p.eps).any())
+        after = bool((incident_lengths(m, xy, v, q) < p.eps).any())
+        if before == after:
+            return None
+    return q
+
+
+def proposal_chain(m: Mesh, xy, p: Params, temperature, kind, vid, r, u):
+    """Metropolis steps (Sec. 3.1) with the proposals of one kind (see propose), for the vertices
+    of vid one after another, each proposal drawn from the positions its predecessors left.
+    Returns the final positions and, per vertex, the status (ACCEPTED, REJECTED, SKIPPED or the
+    move_status codes), delta f and the decision margin, as metropolis_chain."""
+    xy = np.array(xy, dtype=np.float64)
+    n = len(vid)
+    st = np.zeros(n, dtype=np.int64)
+    df = np.full(n, np.inf)
+    margin = np.full(n, np.inf)
+    for i, v in enumerate(vid):
+        v = int(v)
+        q = propose(m, xy, p, v, kind, r[i])
+        if q is None:
+            st[i] = SKIPPED
+            continue
+        s, d, _ = delta_f(m, xy, p, v, q)
+        df[i] = d
+        if s != MOVED:
+            st[i] = s
+            continue
+        with np.errstate(divide="ignore", over="ignore"):
+            accept = d <= 0.0 or u[i] < np.exp(-np.float64(d) / np.float64(temperature))
+        st[i] = ACCEPTED if accept else REJECTED
+        if accept:
+            xy[v] = q
+        margin[i] = abs(d + temperature * np.log(u[i])) if u[i] > 0 else np.inf
+    return xy, st, df, margin

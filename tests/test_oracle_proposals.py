@@ -1,0 +1,170 @@
+"""Pins of the checker's vertex proposals of Secs. 3.2.4-3.2.6 (oracle/objective.py); CPU only.
+
+Each pin checks the proposal against what the paper states it samples, not against its own code:
+uniform density by area over the vertex's triangles, validity inside a convex star, positions
+within the drawn radius of the chosen neighbour, the contraction-change rule, the constrained
+projection, and a zero-temperature chain that never raises f.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+from oracle import objective as ob
+
+scipy_stats = pytest.importorskip("scipy.stats")
+
+
+def _star(radii, centre=(0.0, 0.0)):
+    """A free vertex 0 at `centre` inside a ring of original vertices 1..n at angles 2 pi k / n."""
+    n = len(radii)
+    ring = [[r * math.cos(2 * math.pi * k / n), r * math.sin(2 * math.pi * k / n)]
+            for k, r in enumerate(radii)]
+    xy = np.array([list(centre)] + ring)
+    tv = np.array([[0, 1 + k, 1 + (k + 1) % n] for k in range(n)])
+    kind = np.array([ob.FREE] + [ob.ORIGINAL] * n)
+    m = ob.Mesh(tv, kind, np.zeros(n + 1, dtype=np.int64), np.zeros((0, 2), dtype=np.int64))
+    return m, xy
+
+
+def _containing(xy, tv, q):
+    """Ids of the triangles holding q (closed), by exact orientation."""
+    return [t for t in range(tv.shape[0])
+            if all(oracle.orient(xy[tv[t, i]], xy[tv[t, (i + 1) % 3]], q) >= 0 for i in range(3))]
+
+
+def test_resample_is_uniform_by_area():
+    """Counts per triangle follow the areas (chi-square), each point lies in the triangle it was
+    drawn in, and the points of the largest triangle average to its centroid."""
+    radii = [1.0, 2.0, 1.0, 3.0, 1.5, 1.0]
+    m, xy = _star(radii)
+    areas = np.array([ob._tri_area(xy, m.tri_v[t]) for t in range(6)])
+    rng = np.random.default_rng(1)
+    n = 30000
+    r = rng.random((n, 3))
+    pts = np.array([ob.resample_in_star(m, xy, 0, *r[i]) for i in range(n)])
+    # the triangle drawn: the running-sum rule, written out independently
+    cum = np.cumsum(areas)
+    drawn = np.searchsorted(cum, r[:, 0] * cum[-1], side="right").clip(max=5)
+    for i in range(0, n, 97):
+        assert drawn[i] in _containing(xy, m.tri_v, pts[i])
+    counts = np.bincount(drawn, minlength=6)
+    chi2 = ((counts - n * areas / areas.sum()) ** 2 / (n * areas / areas.sum())).sum()
+    assert chi2 < scipy_stats.chi2.ppf(1 - 1e-6, 5), (counts, areas)
+    big = int(np.argmax(areas))
+    sel = pts[drawn == big]
+    centroid = xy[m.tri_v[big]].mean(axis=0)
+    se = sel.std(axis=0) / math.sqrt(sel.shape[0])
+    assert (np.abs(sel.mean(axis=0) - centroid) < 5 * se).all()
+
+
+def test_resample_in_convex_star_is_always_valid():
+    """Inside a convex star every resampled position keeps the triangulation valid (Sec. 3.2.4)."""
+    radii = [1.0, 1.2, 1.0, 1.1, 1.0, 1.3]
+    m, xy = _star(radii, centre=(0.2, -0.1))
+    ring = xy[1:]
+    assert all(oracle.orient(ring[k], ring[(k + 1) % 6], ring[(k + 2) % 6]) > 0 for k in range(6))
+    rng = np.random.default_rng(2)
+    for r in rng.random((2000, 3)):
+        q = ob.resample_in_star(m, xy, 0, *r)
+        assert ob.move_status(m, xy, 0, q) == ob.MOVED
+
+
+def _disk(rng, n):
+    rad = np.sqrt(rng.random(n))
+    th = 2 * math.pi * rng.random(n)
+    return np.stack([rad * np.cos(th), rad * np.sin(th)], axis=1)
+
+
+def test_swap_proposal():
+    """A vertex with an edge shorter than the drawn l moves into the disk of radius l around the
+    neighbour of rank floor(r1 deg); with none shorter, nothing is proposed; l covers
+    [0.2 eps, 2 eps)."""
+    m, xy = _star([1.0] * 6, centre=(0.95, 0.0))  # 0.05 from vertex 1
+    p = ob.Params(0.1)
+    rng = np.random.default_rng(3)
+    n = 4000
+    r = np.concatenate([rng.random((n, 2)), _disk(rng, n)], axis=1)
+    nb = m.nbr[m.nbr_off[0]:m.nbr_off[1]]
+    assert nb.tolist() == [1, 2, 3, 4, 5, 6]
+    skipped, ranks = 0, np.zeros(6, dtype=np.int64)
+    for i in range(n):
+        ln = 0.02 + 0.18 * r[i, 0]
+        q = ob.propose(m, xy, p, 0, ob.SWAP, r[i])
+        if ln <= 0.05 - 1e-12:
+            assert q is None
+        if q is None:
+            skipped += 1
+            assert ln <= 0.05 + 1e-12
+            continue
+        k = int(r[i, 1] * 6)
+        ranks[k] += 1
+        assert np.hypot(*(q - xy[nb[k]])) <= ln * (1 + 1e-12)
+    assert abs(skipped / n - 0.03 / 0.18) < 0.03
+    assert ranks.min() > 0.8 * ranks.mean()
+
+
+def test_contract_proposal_changes_the_contracted_state():
+    """A contraction move is proposed exactly when the vertex's contracted state (an edge shorter
+    than eps) differs between its old and new positions; an uncontracted vertex goes near a
+    neighbour, a contracted one away from all."""
+    p = ob.Params(0.3)
+    rng = np.random.default_rng(4)
+    for centre, was in (((0.1, 0.05), False), ((0.8, 0.05), True)):
+        m, xy = _star([1.0] * 6, centre=centre)
+        assert bool((ob.incident_lengths(m, xy, 0) < p.eps).any()) == was
+        kept = 0
+        for r in rng.random((3000, 4)):
+            q = ob.propose(m, xy, p, 0, ob.CONTRACT, r)
+            raw = ob.resample_in_star(m, xy, 0, r[0], r[1], r[2])
+            base = xy[0] + (raw - xy[0])  # the move is formed as o + (q - o)
+            now = bool((ob.incident_lengths(m, xy, 0, base) < p.eps).any())
+            if now == was:
+                assert q is None
+            else:
+                kept += 1
+                assert np.array_equal(q, base)
+        assert kept > 30
+
+
+def test_constrained_proposals_stay_on_their_edge():
+    """Proposals for a constrained vertex are projected on its original edge (Sec. 3.2.1)."""
+    mesh = sg.subdivide(sg.make_scene("tiny"))
+    m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+    xy = mesh.xy
+    cons = np.nonzero(mesh.kind == ob.CONSTRAINED)[0][:10]
+    rng = np.random.default_rng(5)
+    p = ob.Params(0.05)
+    for v in cons:
+        a, b = xy[m.prim_v[m.line[v]]]
+        e = b - a
+        for r in rng.random((20, 3)):
+            q = ob.propose(m, xy, p, int(v), ob.RESAMPLE, np.append(r, 0.0))
+            w = q - a
+            assert abs(e[0] * w[1] - e[1] * w[0]) <= 1e-12 * np.hypot(*e) * (1 + np.hypot(*w))
+
+
+@pytest.mark.parametrize("kind", [ob.RESAMPLE, ob.SWAP, ob.CONTRACT])
+def test_zero_temperature_chain_never_raises_f(kind):
+    """At T = 0 only moves that do not raise f are taken: f falls by the sum of the accepted
+    changes, and only accepted vertices move."""
+    mesh = sg.subdivide(sg.make_scene("tiny"))
+    m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+    p = ob.Params(0.05)
+    rng = np.random.default_rng(6)
+    vid = np.nonzero(mesh.kind != ob.ORIGINAL)[0]
+    r = np.concatenate([rng.random((vid.shape[0], 2)), _disk(rng, vid.shape[0])], axis=1)
+    if kind != ob.SWAP:
+        r[:, 2] = rng.random(vid.shape[0])
+    xy1, st, df, _ = ob.proposal_chain(m, mesh.xy, p, 0.0, kind, vid, r, rng.random(vid.shape[0]))
+    f0 = ob.objective(m, mesh.xy, p)["f"]
+    f1 = ob.objective(m, xy1, p)["f"]
+    acc = st == ob.ACCEPTED
+    assert acc.sum() > 0 and (df[acc] <= 0).all()
+    assert abs((f1 - f0) - df[acc].sum()) < 1e-9 * (1 + abs(f0))
+    moved = (xy1 != mesh.xy).any(axis=1)
+    assert not moved[np.setdiff1d(np.arange(mesh.kind.shape[0]), vid[acc])].any()
+    if kind == ob.SWAP:
+        assert (st == ob.SKIPPED).sum() > 0
