@@ -56,7 +56,17 @@ enum {
   CCSP_MOVE_FOLDS = 0,  /* some triangle of the vertex would not (decided exactly); delta = +inf */
   CCSP_MOVE_FIXED = -1, /* the vertex is ORIGINAL; delta = +inf */
   CCSP_MOVE_BAD = -2,   /* vertex id out of range or a coordinate not finite; delta = +inf */
-  CCSP_MOVE_REJECTED = 2 /* anneal_moves: valid, not accepted by the Metropolis rule */
+  CCSP_MOVE_REJECTED = 2, /* anneal_moves: valid, not accepted by the Metropolis rule */
+  CCSP_MOVE_SKIPPED = 3   /* anneal_propose: the perturbation does not apply to the vertex (no
+                             move tried); delta = +inf */
+};
+
+/* Proposal kinds of anneal_propose (CCSP_PROPOSE_DISPLACE is the displacement of anneal_sweep). */
+enum {
+  CCSP_PROPOSE_DISPLACE = 0,
+  CCSP_PROPOSE_RESAMPLE = 1, /* Sec. 3.2.4: uniform by area over the vertex's triangles */
+  CCSP_PROPOSE_SWAP = 2,     /* Sec. 3.2.5: near a neighbour, for a vertex on a short edge */
+  CCSP_PROPOSE_CONTRACT = 3  /* Sec. 3.2.6: a resampling that changes the contracted state */
 };
 
 typedef struct MovableMesh MovableMesh; /* opaque; owns device memory */
@@ -158,6 +168,30 @@ int anneal_moves(MovableMesh *mesh, double *xy, const ObjectiveParams *params, d
  */
 int anneal_sweep(MovableMesh *mesh, double *xy, const ObjectiveParams *params, double temperature,
                  const double *disp, const double *u, double *delta, int32_t *status, void *stream);
+
+/*
+ * anneal_propose: one sweep as anneal_sweep (class by class, equal to the sequential chain in the
+ * order of mesh_classes) with the proposals of Secs. 3.2.4-3.2.6 in place of displacements. The
+ * i-th movable vertex v (mesh_classes order) uses draws[4i..4i+3] = r0, r1, r2, r3 (DEVICE
+ * binary64, 16-byte aligned; r0, r1, r2 in [0, 1), and for SWAP (r2, r3) a point of the closed unit
+ * disk) and u[i]; positions are the current ones, left by the vertices before it.
+ *  - RESAMPLE: over v's triangles in increasing caller id, with areas
+ *    0.5 * ((b.x-a.x)*(c.y-a.y) - (b.y-a.y)*(c.x-a.x)) on their stored vertices summed left to right,
+ *    the first triangle whose running sum exceeds r0 times the total; in it (a, b, c) the point
+ *    (1 - s) a + s (1 - r2) b + s r2 c, s = sqrt(r1), each coordinate summed left to right.
+ *  - SWAP: l = (0.2 + 1.8 * r0) * eps; if no edge of v is shorter than l, the vertex is SKIPPED;
+ *    otherwise w = the neighbour of rank min(floor(r1 * deg), deg - 1) in increasing caller id,
+ *    and the point w + l * (r2, r3).
+ *  - CONTRACT: the RESAMPLE point (after the projection below); SKIPPED unless exactly one of v's
+ *    old and new positions has an edge of v shorter than eps.
+ * The move d = point - v is projected as in anneal_moves for a CONSTRAINED vertex and the
+ * proposal is v + d; acceptance, delta and status are those of anneal_moves, plus
+ * CCSP_MOVE_SKIPPED. Edge lengths are sqrt(dx*dx + dy*dy). xy (DEVICE) is updated in place.
+ * Asynchronous on `stream`; overwrites the mesh's scratch.
+ */
+int anneal_propose(MovableMesh *mesh, double *xy, const ObjectiveParams *params, double temperature,
+                   int32_t kind, const double *draws, const double *u, double *delta,
+                   int32_t *status, void *stream);
 
 /*
  * anneal_schedule: n_sweeps sweeps (as anneal_sweep) of simulated annealing with both the

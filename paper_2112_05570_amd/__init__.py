@@ -313,6 +313,27 @@ class MovableMesh:
                        u.data_ptr(), d.data_ptr(), st.data_ptr(), _stream(stream))
         return d, st
 
+    def propose(self, xy, params, temperature, kind, draws, u, stream=None):
+        """One sweep with the proposals of Secs. 3.2.4-3.2.6 (see ``anneal_propose``): kind is
+        "resample", "swap" or "contract"; draws (M,4) and u (M,) float64 CUDA tensors in the order
+        of ``classes()``. xy is updated in place. Returns (delta, status). Asynchronous."""
+        import torch
+        kinds = {"resample": B.CCSP_PROPOSE_RESAMPLE, "swap": B.CCSP_PROPOSE_SWAP,
+                 "contract": B.CCSP_PROPOSE_CONTRACT}
+        if kind not in kinds:
+            raise ValueError(f"kind must be one of {sorted(kinds)}")
+        m = self.n_movable()
+        if (tuple(draws.shape) != (m, 4) or draws.dtype != torch.float64
+                or not draws.is_contiguous() or not draws.is_cuda or tuple(u.shape) != (m,)
+                or u.dtype != torch.float64 or not u.is_contiguous() or not u.is_cuda):
+            raise ValueError(f"draws float64 ({m},4) and u float64 ({m},), contiguous CUDA tensors")
+        d = torch.empty(m, dtype=torch.float64, device=xy.device)
+        st = torch.empty(m, dtype=torch.int32, device=xy.device)
+        B.anneal_propose(self.handle, self._xy(xy), params, float(temperature), kinds[kind],
+                         draws.data_ptr(), u.data_ptr(), d.data_ptr(), st.data_ptr(),
+                         _stream(stream))
+        return d, st
+
     def schedule(self, xy, params, temperatures, eps, lambda0, xi, u, target=0.23, stream=None):
         """Simulated annealing with a temperature and contraction-length schedule and an adaptive
         step scale (see ``anneal_schedule``): temperatures and eps are sequences of one value per

@@ -40,6 +40,8 @@ CCSP_TRACE_COUNT = 1 << 9
 CCSP_TRACE_INPUT_ORDER = 1 << 10
 CCSP_TRACE_TIMED = 1 << 11
 CCSP_TRACE_GRAPH = 1 << 12
+CCSP_MOVE_SKIPPED = 3
+CCSP_PROPOSE_DISPLACE, CCSP_PROPOSE_RESAMPLE, CCSP_PROPOSE_SWAP, CCSP_PROPOSE_CONTRACT = 0, 1, 2, 3
 
 EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch",
            "free_triangulation", "last_error", "read_counters", "triangulation_info",
@@ -47,7 +49,8 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
            "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
-           "anneal_moves", "anneal_sweep", "anneal_schedule", "flip_anneal")
+           "anneal_moves", "anneal_sweep", "anneal_propose", "anneal_schedule",
+           "flip_anneal")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -167,6 +170,9 @@ _lib.anneal_moves.restype = _I
 _lib.anneal_sweep.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double, _P, _P, _P,
                               _P, _P]
 _lib.anneal_sweep.restype = _I
+_lib.anneal_propose.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double,
+                                ctypes.c_int32, _P, _P, _P, _P, _P]
+_lib.anneal_propose.restype = _I
 _lib.anneal_schedule.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_int32, _P, _P,
                                  ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P]
 _lib.anneal_schedule.restype = _I
@@ -314,6 +320,12 @@ def anneal_sweep(mesh: int, xy: int, params: ObjectiveParams, temperature: float
                  u: int, delta: int, status: int, stream: int = 0) -> None:
     _check(_lib.anneal_sweep(_P(mesh), _P(xy), ctypes.byref(params), temperature, _P(disp), _P(u),
                              _P(delta), _P(status), _P(stream)))
+
+
+def anneal_propose(mesh: int, xy: int, params: ObjectiveParams, temperature: float, kind: int,
+                   draws: int, u: int, delta: int, status: int, stream: int = 0) -> None:
+    _check(_lib.anneal_propose(_P(mesh), _P(xy), ctypes.byref(params), temperature, kind,
+                               _P(draws), _P(u), _P(delta), _P(status), _P(stream)))
 
 
 def anneal_schedule(mesh: int, xy: int, params: ObjectiveParams, n_sweeps: int, temperature: int,

@@ -468,56 +468,149 @@ __device__ __forceinline__ void refresh_scratch(const MeshDev& m, const Par& p, 
     }
 }
 
+// Area of triangle t at the current positions, its vertices in the caller's order.
+__device__ __forceinline__ double tri_area(const MeshDev& m, int t) {
+  const int4 tr = m.tri[t];
+  const double2 a = m.xyi[tr.x], b = m.xyi[tr.y], c = m.xyi[tr.z];
+  return 0.5 * ((b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x));
+}
+
+// A position uniform by area over the triangles of internal vertex v (Sec. 3.2.4): the first
+// triangle (caller order) at which the running sum of areas exceeds r0 times their total, and in
+// it (1 - s) a + s (1 - r2) b + s r2 c, s = sqrt(r1), the sampling of Osada et al. (2002).
+__device__ __forceinline__ double2 resample_star(const MeshDev& m, int v, double r0, double r1,
+                                                 double r2) {
+  const int j0 = m.vtri_off[v], j1 = m.vtri_off[v + 1];
+  double total = 0.0;
+  for (int j = j0; j < j1; ++j) total = total + tri_area(m, m.vtri[j]);
+  const double target = r0 * total;
+  double run = 0.0;
+  int pick = m.vtri[j1 - 1];
+  for (int j = j0; j < j1; ++j) {
+    run = run + tri_area(m, m.vtri[j]);
+    if (target < run) {
+      pick = m.vtri[j];
+      break;
+    }
+  }
+  const int4 tr = m.tri[pick];
+  const double2 a = m.xyi[tr.x], b = m.xyi[tr.y], c = m.xyi[tr.z];
+  const double s = sqrt(r1);
+  const double ka = 1.0 - s, kb = s * (1.0 - r2), kc = s * r2;
+  return make_double2(ka * a.x + kb * b.x + kc * c.x, ka * a.y + kb * b.y + kc * c.y);
+}
+
+// Whether internal vertex v has an edge shorter than l: at its current position (the edges'
+// current lengths), or with v at q.
+__device__ __forceinline__ bool has_short_edge(const MeshDev& m, int v, double l) {
+  for (int j = m.adj_off[v], end = m.adj_off[v + 1]; j < end; ++j)
+    if (m.len[m.adj[j].y] < l) return true;
+  return false;
+}
+__device__ __forceinline__ bool has_short_edge_at(const MeshDev& m, int v, double2 q, double l) {
+  for (int j = m.adj_off[v], end = m.adj_off[v + 1]; j < end; ++j)
+    if (dist(q, m.xyi[m.adj[j].x]) < l) return true;
+  return false;
+}
+
+// The neighbour of internal vertex v whose caller id has rank k among its neighbours' caller ids.
+__device__ __forceinline__ int neighbour_of_rank(const MeshDev& m, int v, int k) {
+  const int a0 = m.adj_off[v], a1 = m.adj_off[v + 1];
+  for (int j = a0; j < a1; ++j) {
+    const int w = m.adj[j].x, cw = m.vold[w];
+    int below = 0;
+    for (int l = a0; l < a1; ++l) below += m.vold[m.adj[l].x] < cw ? 1 : 0;
+    if (below == k) return w;
+  }
+  return m.adj[a1 - 1].x;  // not reached: caller ids are distinct
+}
+
 // One class of a sweep: Metropolis steps for its vertices (internal ids), which are pairwise more
 // than four edges apart, so that each thread's reads (within four edges of its vertex) and writes
 // (its position, and scratch of edges within one edge of it) never meet another thread's.
+// kind CCSP_PROPOSE_DISPLACE: the vertex moves by disp[i] (scaled by lambda * eta when lambda > 0);
+// the other kinds draw the new position from the vertex's neighbourhood with draws[2i], draws[2i+1]
+// (Secs. 3.2.4-3.2.6). Accepted moves are counted per block into *accepted when it is given.
 __global__ void __launch_bounds__(kThreads)
-anneal_class(MeshDev m, Par p, double temperature, double lambda, double2* __restrict__ xy_out,
-             const int32_t* __restrict__ cls, const double2* __restrict__ disp,
-             const double* __restrict__ u, int n, double* __restrict__ delta,
-             int32_t* __restrict__ status, unsigned long long* __restrict__ accepted) {
+anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
+             double2* __restrict__ xy_out, const int32_t* __restrict__ cls,
+             const double2* __restrict__ disp, const double* __restrict__ u, int n,
+             double* __restrict__ delta, int32_t* __restrict__ status,
+             unsigned long long* __restrict__ accepted) {
   __shared__ int snb[kLdsNbrs * kThreads];
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const int v = cls[i];
-  const int cv = m.vold[v];
-  const double2 o = m.xyi[v];
-  double2 d = disp[i];
-  if (lambda > 0.0) {
-    // disp is a unit draw: scale by lambda * eta, eta the square root of the area of v's
-    // triangles (Sec. 3.2.2), summed in the caller's triangle order at the current positions
-    double area = 0.0;
-    for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j) {
-      const int4 tr = m.tri[m.vtri[j]];
-      const double2 a = m.xyi[tr.x], b = m.xyi[tr.y], c = m.xyi[tr.z];
-      area += 0.5 * ((b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x));
-    }
-    const double k = lambda * sqrt(area);
-    d = make_double2(k * d.x, k * d.y);
-  }
-  const int2 kl = m.vk[v];
-  if (kl.x == CCSP_VERTEX_CONSTRAINED) {
-    const int2 ends = m.prim_v[kl.y];
-    const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
-    const double ex = b.x - a.x, ey = b.y - a.y;
-    const double s = (d.x * ex + d.y * ey) / (ex * ex + ey * ey);
-    d = make_double2(s * ex, s * ey);
-  }
-  const double2 q = make_double2(o.x + d.x, o.y + d.y);
-  double df;
-  int st = evaluate_move(m, m.xyi, p, cv, q, snb + threadIdx.x, &df);
-  if (st == CCSP_MOVE_OK) {
-    if (df <= 0.0 || u[i] < exp(-df / temperature)) {
-      m.xyi[v] = q;
-      xy_out[cv] = q;
-      refresh_scratch(m, p, v);
-      if (accepted) atomicAdd(accepted, 1ull);
+  bool took = false;
+  if (i < n) {
+    const int v = cls[i];
+    const int cv = m.vold[v];
+    const double2 o = m.xyi[v];
+    bool skip = false;
+    double2 d;
+    if (kind == CCSP_PROPOSE_DISPLACE) {
+      d = disp[i];
+      if (lambda > 0.0) {
+        // disp is a unit draw: scale by lambda * eta, eta the square root of the area of v's
+        // triangles (Sec. 3.2.2), summed in the caller's triangle order at the current positions
+        double area = 0.0;
+        for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j)
+          area += tri_area(m, m.vtri[j]);
+        const double k = lambda * sqrt(area);
+        d = make_double2(k * d.x, k * d.y);
+      }
     } else {
-      st = CCSP_MOVE_REJECTED;
+      const double2 ra = disp[2 * i], rb = disp[2 * i + 1];
+      double2 target = o;
+      if (kind == CCSP_PROPOSE_SWAP) {
+        // Sec. 3.2.5: l uniform on [0.2 eps, 2 eps); only a vertex with an edge shorter than l
+        const double l = (0.2 + 1.8 * ra.x) * p.eps;
+        if (has_short_edge(m, v, l)) {
+          const int deg = m.adj_off[v + 1] - m.adj_off[v];
+          const int w = neighbour_of_rank(m, v, min((int)(ra.y * (double)deg), deg - 1));
+          const double2 pw = m.xyi[w];
+          target = make_double2(pw.x + l * rb.x, pw.y + l * rb.y);
+        } else {
+          skip = true;
+        }
+      } else {
+        target = resample_star(m, v, ra.x, ra.y, rb.x);
+      }
+      d = make_double2(target.x - o.x, target.y - o.y);
     }
+    const int2 kl = m.vk[v];
+    if (kl.x == CCSP_VERTEX_CONSTRAINED) {
+      const int2 ends = m.prim_v[kl.y];
+      const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
+      const double ex = b.x - a.x, ey = b.y - a.y;
+      const double s = (d.x * ex + d.y * ey) / (ex * ex + ey * ey);
+      d = make_double2(s * ex, s * ey);
+    }
+    const double2 q = make_double2(o.x + d.x, o.y + d.y);
+    // Sec. 3.2.6: only a change of the contracted state is tried, once
+    if (kind == CCSP_PROPOSE_CONTRACT &&
+        has_short_edge(m, v, p.eps) == has_short_edge_at(m, v, q, p.eps))
+      skip = true;
+    double df = __builtin_huge_val();
+    int st = CCSP_MOVE_SKIPPED;
+    if (!skip) {
+      st = evaluate_move(m, m.xyi, p, cv, q, snb + threadIdx.x, &df);
+      if (st == CCSP_MOVE_OK) {
+        if (df <= 0.0 || u[i] < exp(-df / temperature)) {
+          m.xyi[v] = q;
+          xy_out[cv] = q;
+          refresh_scratch(m, p, v);
+          took = true;
+        } else {
+          st = CCSP_MOVE_REJECTED;
+        }
+      }
+    }
+    status[i] = st;
+    delta[i] = df;
   }
-  status[i] = st;
-  delta[i] = df;
+  if (accepted) {
+    const int c = __syncthreads_count(took);
+    if (threadIdx.x == 0 && c > 0) atomicAdd(accepted, (unsigned long long)c);
+  }
 }
 
 __global__ void zero_counter(unsigned long long* __restrict__ c) {
@@ -1084,12 +1177,49 @@ int anneal_sweep(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
     const int n = (int)(off[c + 1] - off[c]);
     if (n == 0) continue;
     hipLaunchKernelGGL(ccsp::anneal_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
-                       dim3(ccsp::kThreads), 0, s, d, p, temperature, 0.0, (double2*)xy,
-                       mesh->class_dev + off[c], (const double2*)disp + off[c], u + off[c], n,
-                       delta + off[c], status + off[c], (unsigned long long*)nullptr);
+                       dim3(ccsp::kThreads), 0, s, d, p, temperature, 0.0,
+                       (int)CCSP_PROPOSE_DISPLACE, (double2*)xy, mesh->class_dev + off[c],
+                       (const double2*)disp + off[c], u + off[c], n, delta + off[c],
+                       status + off[c], (unsigned long long*)nullptr);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_sweep: launch");
+}
+
+int anneal_propose(MovableMesh* mesh, double* xy, const ObjectiveParams* params, double temperature,
+                   int32_t kind, const double* draws, const double* u, double* delta,
+                   int32_t* status, void* stream) {
+  if (!mesh || !xy || !draws || !u || !delta || !status)
+    return fail(CCSP_E_ARG, "anneal_propose: null argument");
+  if (kind != CCSP_PROPOSE_RESAMPLE && kind != CCSP_PROPOSE_SWAP && kind != CCSP_PROPOSE_CONTRACT)
+    return fail(CCSP_E_ARG, "anneal_propose: unknown proposal kind");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)draws & 15) != 0 || ((uintptr_t)u & 7) != 0 ||
+      ((uintptr_t)delta & 7) != 0 || ((uintptr_t)status & 3) != 0)
+    return fail(CCSP_E_ARG, "anneal_propose: misaligned buffer");
+  if (!check_params(params)) return fail(CCSP_E_ARG, "anneal_propose: invalid parameters");
+  if (!(temperature >= 0) || !std::isfinite(temperature))
+    return fail(CCSP_E_ARG, "anneal_propose: temperature must be finite and >= 0");
+  if (int r = check_device(mesh)) return r;
+  if (int r = ensure_classes(mesh)) return r;
+  const ccsp::MeshDev& d = mesh->d;
+  const ccsp::Par p = to_par(params);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy);
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
+                     d.partial);
+  const std::vector<int64_t>& off = mesh->class_off;
+  for (size_t c = 0; c + 1 < off.size(); ++c) {
+    const int n = (int)(off[c + 1] - off[c]);
+    if (n == 0) continue;
+    hipLaunchKernelGGL(ccsp::anneal_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
+                       dim3(ccsp::kThreads), 0, s, d, p, temperature, 0.0, (int)kind,
+                       (double2*)xy, mesh->class_dev + off[c],
+                       (const double2*)draws + 2 * off[c], u + off[c], n, delta + off[c],
+                       status + off[c], (unsigned long long*)nullptr);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_propose: launch");
 }
 
 int anneal_schedule(MovableMesh* mesh, double* xy, const ObjectiveParams* params, int32_t n_sweeps,
@@ -1142,9 +1272,9 @@ int anneal_schedule(MovableMesh* mesh, double* xy, const ObjectiveParams* params
       const int n = (int)(off[c + 1] - off[c]);
       if (n == 0) continue;
       hipLaunchKernelGGL(ccsp::anneal_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
-                         dim3(ccsp::kThreads), 0, s, d, p, temperature[k], lam, (double2*)xy,
-                         mesh->class_dev + off[c], xk + off[c], uk + off[c], n, delta + off[c],
-                         status + off[c], counter);
+                         dim3(ccsp::kThreads), 0, s, d, p, temperature[k], lam,
+                         (int)CCSP_PROPOSE_DISPLACE, (double2*)xy, mesh->class_dev + off[c],
+                         xk + off[c], uk + off[c], n, delta + off[c], status + off[c], counter);
     }
     unsigned long long acc = 0;
     hipError_t e = hipGetLastError();

@@ -466,3 +466,106 @@ def test_large_bench_configuration_sampled(ccsp):
     f = edge.sum() + p.mu_angle * ang.sum() + p.mu_len * short.sum()
     scale = np.abs(edge).sum() + p.mu_angle * np.abs(ang).sum() + p.mu_len * np.abs(short).sum()
     assert abs(out[0] - f) <= 2 * (edge.size + ang.size) * U * scale
+
+
+_KINDS = {"resample": ob.RESAMPLE, "swap": ob.SWAP, "contract": ob.CONTRACT}
+
+
+def _proposal_draws(rng, m, kind):
+    """Four draws per vertex: uniforms, with (r2, r3) a unit-disk point for swaps."""
+    r = rng.random((m, 4))
+    if kind == "swap":
+        rad = np.sqrt(rng.random(m))
+        th = 2 * math.pi * rng.random(m)
+        r[:, 2], r[:, 3] = rad * np.cos(th), rad * np.sin(th)
+    return r
+
+
+@pytest.mark.parametrize("kind", ["resample", "swap", "contract"])
+@pytest.mark.parametrize("state,temperature", [("subdivided", 1e-3), ("clustered", 1e-4),
+                                               ("clustered", 0.0)])
+def test_propose_sweep_equals_sequential_chain(ccsp, tiny, kind, state, temperature):
+    """A sweep of resampling, swap or contraction proposals (Secs. 3.2.4-3.2.6) equals the
+    checker's chain over the same draws in the same order: positions bit for bit, statuses
+    (skipped ones included) equal, changes of f within rounding."""
+    mesh, om = tiny
+    p = ob.Params(0.03)
+    xy0 = mesh.xy.copy() if state == "subdivided" else _clustered(mesh, om, p, 9)
+    rng = np.random.default_rng(11)
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        order = np.concatenate(gm.classes())
+        draws = _proposal_draws(rng, order.shape[0], kind)
+        u = rng.random(order.shape[0])
+        X = torch.from_numpy(xy0.copy()).to(DEV)
+        d, st = gm.propose(X, _params(ccsp, p), temperature, kind, torch.from_numpy(draws).to(DEV),
+                           torch.from_numpy(u).to(DEV))
+        xy_g, st_g, df_g = X.cpu().numpy(), st.cpu().numpy(), d.cpu().numpy()
+    xy_r, st_r, df_r, margin = ob.proposal_chain(om, xy0, p, temperature, _KINDS[kind], order,
+                                                 draws, u)
+    valid = (st_r == ob.ACCEPTED) | (st_r == ob.REJECTED)
+    assert (margin[valid] > 1e-10).all(), "a decision lies within rounding of its threshold"
+    assert np.array_equal(st_g, st_r), np.nonzero(st_g != st_r)[0][:5]
+    assert np.array_equal(xy_g, xy_r)
+    fin = np.isfinite(df_r)
+    assert np.array_equal(np.isfinite(df_g), fin)
+    assert np.allclose(df_g[fin], df_r[fin], rtol=1e-9, atol=1e-13)
+    assert (st_r == ob.ACCEPTED).sum() > 0
+    if kind != "resample":
+        assert (st_r == ob.SKIPPED).sum() > 0
+
+
+def test_propose_rejects_bad_kind(ccsp, tiny):
+    mesh, _ = tiny
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        m = gm.n_movable()
+        X = torch.from_numpy(mesh.xy.copy()).to(DEV)
+        r = torch.zeros((m, 4), dtype=torch.float64, device=DEV)
+        u = torch.zeros(m, dtype=torch.float64, device=DEV)
+        with pytest.raises(ValueError):
+            gm.propose(X, _params(ccsp, ob.Params(0.03)), 0.0, "jump", r, u)
+        from paper_2112_05570_amd import binding as B
+        with pytest.raises(B.CcspError, match="unknown proposal kind"):
+            B.anneal_propose(gm.handle, X.data_ptr(), _params(ccsp, ob.Params(0.03)), 0.0, 7,
+                             r.data_ptr(), u.data_ptr(), u.data_ptr(), u.data_ptr())
+
+
+@pytest.mark.parametrize("kind", ["resample", "swap", "contract"])
+def test_propose_at_scale(ccsp, grid, kind):
+    """Subdivided grid scene, one sweep at T = 0: accepted changes are <= 0 and add up to the
+    change of f; only accepted vertices move; vertices of the first class (tried against the
+    initial positions) match the checker's proposal, status and new position exactly."""
+    mesh, om = grid
+    p = ob.Params(0.2)
+    rng = np.random.default_rng(12)
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        cls = gm.classes()
+        order = np.concatenate(cls)
+        draws = _proposal_draws(rng, order.shape[0], kind)
+        u = rng.random(order.shape[0])
+        params = _params(ccsp, p)
+        X0 = torch.from_numpy(mesh.xy).to(DEV)
+        X = X0.clone()
+        d, st = gm.propose(X, params, 0.0, kind, torch.from_numpy(draws).to(DEV),
+                           torch.from_numpy(u).to(DEV))
+        f0 = gm.eval(X0, params).cpu().numpy()[0]
+        f1 = gm.eval(X, params).cpu().numpy()[0]
+        xy1, d, st = X.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+    acc = st == ob.ACCEPTED
+    assert acc.sum() > 100 and (d[acc] <= 0).all()
+    assert set(np.unique(st).tolist()) <= {ob.ACCEPTED, ob.REJECTED, ob.SKIPPED, ob.FOLDED}
+    assert abs((f1 - f0) - d[acc].sum()) <= 1e-9 * abs(f0)
+    moved = np.nonzero((xy1 != mesh.xy).any(axis=1))[0]
+    assert np.array_equal(np.sort(moved), np.sort(order[acc]))
+    first = cls[0].shape[0]
+    for i in range(0, first, max(1, first // 25)):
+        v = int(order[i])
+        q = ob.propose(om, mesh.xy, p, v, _KINDS[kind], draws[i])
+        if q is None:
+            assert st[i] == ob.SKIPPED
+            continue
+        assert st[i] in (ob.ACCEPTED, ob.REJECTED, ob.FOLDED)
+        assert (st[i] == ob.FOLDED) == (ob.move_status(om, mesh.xy, v, q) == ob.FOLDED)
+        if st[i] == ob.ACCEPTED:
+            assert np.array_equal(xy1[v], q)
+        else:
+            assert np.array_equal(xy1[v], mesh.xy[v])
