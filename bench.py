@@ -481,6 +481,32 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
     f_after = gm.eval(X, p).cpu().tolist()[0]
     del draws
 
+    # sweeps of the proposals of Secs. 3.2.4-3.2.6 from the state the displacement sweeps left
+    proposals = {}
+    for kind in ("resample", "swap", "contract"):
+        r = torch.rand((n_mov, 4), generator=gen, device=xy.device, dtype=torch.float64)
+        if kind == "swap":
+            rad = torch.sqrt(torch.rand(n_mov, generator=gen, device=xy.device,
+                                        dtype=torch.float64))
+            th = 2.0 * np.pi * torch.rand(n_mov, generator=gen, device=xy.device,
+                                          dtype=torch.float64)
+            r[:, 2], r[:, 3] = rad * torch.cos(th), rad * torch.sin(th)
+        uk = torch.rand(n_mov, generator=gen, device=xy.device, dtype=torch.float64)
+        XP = X.clone()
+        f0k = gm.eval(XP, p).cpu().tolist()[0]
+        torch.cuda.synchronize()
+        a.record()
+        _, pst = gm.propose(XP, p, temperature, kind, r, uk)
+        b.record()
+        torch.cuda.synchronize()
+        ms_k = a.elapsed_time(b)
+        cnt = torch.bincount((pst + 2).long(), minlength=6).cpu().tolist()  # codes -2 .. 3
+        proposals[kind] = {"sweep_ms": ms_k, "vertex_moves_per_s": n_mov / ms_k * 1e3,
+                           "accepted": cnt[3], "rejected": cnt[4], "skipped": cnt[5],
+                           "folded": cnt[2], "f_before": f0k,
+                           "f_after": gm.eval(XP, p).cpu().tolist()[0]}
+        del XP
+
     # an annealing schedule (Secs. 3.2, 3.3.1): temperature and contraction length lowered together
     # by a factor of 10 over the sweeps, step scale adapted toward 23% acceptance
     n_sched = 10 if scene_name == "large" else 4
@@ -518,7 +544,7 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
                    "classes_host_s": t_classes, "temperature": temperature,
                    "sweep_ms": ms_sweep, "vertex_moves_per_s": n_mov / ms_sweep * 1e3,
                    "acceptance": int(accepted.item()) / (n_mov * n_sweeps), "sweeps": n_sweeps,
-                   "f_before": f_before, "f_after": f_after},
+                   "f_before": f_before, "f_after": f_after, "proposals": proposals},
         "schedule": {"sweeps": n_sched, "ms_per_sweep": ms_sched / n_sched,
                      "temperature": [temps[0], temps[-1]], "eps": [epss[0], epss[-1]],
                      "acceptance": [int(a) / n_mov for a in acc],
