@@ -214,6 +214,36 @@ int anneal_schedule(MovableMesh *mesh, double *xy, const ObjectiveParams *params
                     void *stream);
 
 /*
+ * mesh_contract: contraction of the edges shorter than eps (Sec. 3.4.1), turning a triangulation
+ * whose short edges stand for merged vertices into one where they are merged. HOST code and HOST
+ * pointers throughout (sequential, as each contraction changes the next one's neighbourhood).
+ * Input: desc (as mesh_load; triangles must be strictly counter-clockwise) and xy (2 * n_vertices
+ * binary64). Contraction runs in passes; a pass lists the edges shorter than eps at its start in
+ * increasing (length, lower id, higher id), lengths sqrt(dx*dx + dy*dy), and tries each that is
+ * still an edge and still shorter; passes repeat until one contracts nothing. An edge (a, b) is
+ * contracted only when
+ *  - the original geometry allows it: not two ORIGINAL vertices, not an ORIGINAL vertex with a
+ *    CONSTRAINED one whose original edge does not end at it, not two CONSTRAINED vertices on
+ *    different original edges;
+ *  - the common neighbours of a and b are exactly the vertices opposite the edge;
+ *  - it is not an interior edge with both ends on the hull;
+ *  - the survivor has a position where every remaining triangle around it is strictly
+ *    counter-clockwise (exact): an ORIGINAL vertex survives where it is, as does a CONSTRAINED
+ *    one against a FREE one; otherwise the lower id survives at a + t (b - a), t tried as 1/2,
+ *    1/4, 3/4, 0, 1.
+ * The edge's triangles are removed and the other vertex is replaced by the survivor. Output (HOST,
+ * caller-allocated with the input's sizes): tri_out (3 per triangle), kind_out, line_out, xy_out
+ * (2 per vertex) of the surviving vertices renumbered in increasing old id and the surviving
+ * triangles in increasing old id, each with its vertex order; old_to_new[v] (n_vertices) the new
+ * id of v's survivor (-1 for a vertex in no triangle); the counts and the number of contractions.
+ * Errors: CCSP_E_ARG, CCSP_E_BAD_TRIANGULATION (ids out of range, a triangle not strictly
+ * counter-clockwise). Allocates host memory for the call; thread-safe.
+ */
+int mesh_contract(const MeshDesc *desc, const double *xy, double eps, int32_t *tri_out,
+                  int64_t *n_triangles_out, int32_t *kind_out, int32_t *line_out, double *xy_out,
+                  int64_t *n_vertices_out, int32_t *old_to_new, int64_t *n_contracted);
+
+/*
  * flip_anneal: simulated annealing of a constrained triangulation by edge flips (Sec. 3.2.7), the
  * energy being its weight (total edge length), in n_rounds rounds at temperature[r] (HOST). The
  * triangulation is given in the arrays of ccsp_walk.h, here DEVICE buffers updated in place:

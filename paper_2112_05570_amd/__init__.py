@@ -204,6 +204,34 @@ def locate(scene: Scene, q, stream=None):
     return tri, status
 
 
+def contract(tri_v, kind, line, prim_v, xy, eps):
+    """Contract the edges shorter than eps (see ``mesh_contract`` in ccsp_objective.h; host code).
+    Arguments as for MovableMesh plus positions xy (V,2) float64 (numpy). Returns a dict of numpy
+    arrays: tri_v, kind, line, xy of the contracted mesh, old_to_new (V,) and the number of
+    contractions."""
+    tri_v = np.ascontiguousarray(tri_v, dtype=np.int32)
+    kind = np.ascontiguousarray(kind, dtype=np.int32)
+    line = np.ascontiguousarray(line, dtype=np.int32)
+    prim_v = np.ascontiguousarray(prim_v, dtype=np.int32).reshape(-1, 2)
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    V, T = kind.shape[0], tri_v.shape[0]
+    if tri_v.ndim != 2 or tri_v.shape[1] != 3 or line.shape != (V,) or xy.shape != (V, 2):
+        raise ValueError("tri_v (T,3); kind, line (V,); xy (V,2)")
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
+    d = B.MeshDesc(V, p(kind), p(line), T, p(tri_v), prim_v.shape[0], p(prim_v))
+    t_out = np.empty((T, 3), dtype=np.int32)
+    k_out = np.empty(V, dtype=np.int32)
+    l_out = np.empty(V, dtype=np.int32)
+    xy_out = np.empty((V, 2), dtype=np.float64)
+    m = np.empty(V, dtype=np.int32)
+    counts = np.zeros(3, dtype=np.int64)  # triangles, vertices, contractions
+    B.mesh_contract(d, p(xy), float(eps), p(t_out), p(counts[0:]), p(k_out), p(l_out), p(xy_out),
+                    p(counts[1:]), p(m), p(counts[2:]))
+    nt, nv = int(counts[0]), int(counts[1])
+    return {"tri_v": t_out[:nt], "kind": k_out[:nv], "line": l_out[:nv], "xy": xy_out[:nv],
+            "old_to_new": m, "contracted": int(counts[2])}
+
+
 class MovableMesh:
     """A triangulation with movable Steiner vertices for the low-weight objective (see
     ``mesh_load`` in ccsp_objective.h). Built from host arrays: tri_v (T,3) counter-clockwise,

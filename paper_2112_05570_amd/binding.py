@@ -50,7 +50,7 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
            "anneal_moves", "anneal_sweep", "anneal_propose", "anneal_schedule",
-           "flip_anneal")
+           "flip_anneal", "mesh_contract")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -178,6 +178,9 @@ _lib.anneal_schedule.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes
 _lib.anneal_schedule.restype = _I
 _lib.flip_anneal.argtypes = [_I64, _P, _I64, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]
 _lib.flip_anneal.restype = _I
+_lib.mesh_contract.argtypes = [ctypes.POINTER(MeshDesc), _P, ctypes.c_double, _P, _P, _P, _P, _P,
+                               _P, _P, _P]
+_lib.mesh_contract.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -342,6 +345,14 @@ def flip_anneal(n_vertices: int, xy: int, n_triangles: int, tri_v: int, tri_nbr:
     _check(_lib.flip_anneal(n_vertices, _P(xy), n_triangles, _P(tri_v), _P(tri_nbr), _P(tri_prim),
                             n_rounds, _P(temperature), seed & ((1 << 64) - 1), _P(flips_out),
                             _P(stream)))
+
+
+def mesh_contract(desc: MeshDesc, xy: int, eps: float, tri_out: int, n_triangles_out: int,
+                  kind_out: int, line_out: int, xy_out: int, n_vertices_out: int,
+                  old_to_new: int, n_contracted: int) -> None:
+    _check(_lib.mesh_contract(ctypes.byref(desc), _P(xy), eps, _P(tri_out), _P(n_triangles_out),
+                              _P(kind_out), _P(line_out), _P(xy_out), _P(n_vertices_out),
+                              _P(old_to_new), _P(n_contracted)))
 
 
 def mesh_free(mesh: int) -> None:

@@ -1,0 +1,63 @@
+"""The library's contraction (mesh_contract, host code) against the checker (oracle/contract.py):
+identical triangles, kinds, lines, positions, vertex maps and counts. CPU only: the entry point
+makes no device call."""
+import numpy as np
+import pytest
+
+import paper_2112_05570_amd as ccsp
+import scenegen as sg
+from oracle import contract as ct
+from oracle import objective as ob
+from test_oracle_contract import _clustered_mesh, _square
+
+
+def _same(r, o):
+    return (np.array_equal(r["tri_v"], o[0]) and np.array_equal(r["kind"], o[1])
+            and np.array_equal(r["line"], o[2]) and np.array_equal(r["xy"], o[3])
+            and np.array_equal(r["old_to_new"], o[4]) and r["contracted"] == o[5])
+
+
+def test_square_cases():
+    for k4, k5 in ((ob.FREE, ob.FREE), (ob.ORIGINAL, ob.FREE), (ob.ORIGINAL, ob.ORIGINAL)):
+        tv, kind, line, prim_v, xy = _square(k4, k5)
+        assert _same(ccsp.contract(tv, kind, line, prim_v, xy, 0.05),
+                     ct.contract(tv, kind, line, prim_v, xy, 0.05))
+
+
+@pytest.mark.parametrize("seed,eps", [(1, 0.02), (2, 0.05), (3, 0.01), (4, 0.1)])
+def test_clustered_tiny(seed, eps):
+    mesh, xy = _clustered_mesh(seed, eps)
+    r = ccsp.contract(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, xy, eps)
+    o = ct.contract(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, xy, eps)
+    assert o[5] > 50 and _same(r, o)
+
+
+def test_subdivided_mid_scene():
+    """An 8,002-triangle scene subdivided (32,008 triangles), vertices jittered by valid moves,
+    contracted at a length that catches many of its edges."""
+    mesh = sg.subdivide(sg.make_scene("large", n_seg=2000))
+    om = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+    rng = np.random.default_rng(7)
+    xy = mesh.xy.copy()
+    lens = ob.lengths(xy, om.edge_v[:, 0], om.edge_v[:, 1])
+    eps = float(np.quantile(lens, 0.03))
+    for v in rng.choice(np.nonzero(mesh.kind == ob.FREE)[0], 3000, replace=False):
+        nb = om.nbr[om.nbr_off[v]:om.nbr_off[v + 1]]
+        q = xy[v] + 0.7 * (xy[nb[rng.integers(0, nb.shape[0])]] - xy[v])
+        if ob.move_status(om, xy, int(v), q) == ob.MOVED:
+            xy[v] = q
+    r = ccsp.contract(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, xy, eps)
+    o = ct.contract(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, xy, eps)
+    assert o[5] > 500 and _same(r, o)
+
+
+def test_rejects_bad_input():
+    tv, kind, line, prim_v, xy = _square()
+    with pytest.raises(ccsp.CcspError, match="eps"):
+        ccsp.contract(tv, kind, line, prim_v, xy, 0.0)
+    with pytest.raises(ccsp.CcspError, match="counter-clockwise"):
+        ccsp.contract(tv[:, ::-1], kind, line, prim_v, xy, 0.05)
+    bad = kind.copy()
+    bad[4] = ob.CONSTRAINED
+    with pytest.raises(ccsp.CcspError, match="constrained vertex without edge"):
+        ccsp.contract(tv, bad, line, prim_v, xy, 0.05)
