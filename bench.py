@@ -61,11 +61,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "grid", "tiny", "batch", "serve", "objective", "flips"],
+                    choices=["large", "grid", "tiny", "batch", "serve", "objective", "flips",
+                             "pipeline"],
                     help="batch: the 256-scene workload in one graph-replayed, autotuned launch; "
                          "serve: the request server under Poisson arrivals; objective: the "
                          "low-weight objective on the subdivided large scene; flips: edge-flip "
-                         "annealing of the grid scene's CDT")
+                         "annealing of the grid scene's CDT; pipeline: the low-weight pipeline "
+                         "on the grid scene, walked by its rays")
     ap.add_argument("--requests", type=int, default=10_000, help="serve: requests per level")
     ap.add_argument("--slots", type=int, default=4, help="serve: launch slots")
     ap.add_argument("--tune-cache", default=TUNE_TABLE,
@@ -111,6 +113,11 @@ def main():
         return
     if args.workload == "objective":
         print(json.dumps(objective_leg("large", args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "pipeline":
+        sc = sg.make_scene("grid", seed=0)
+        rays = sg.sample_rays(sc, args.rays or (1 << 20), seed=0)
+        print(json.dumps(pipeline_leg(sc, rays, verbose=True)), flush=True)
         return
     if args.workload == "flips":
         sc = sg.make_scene("grid", seed=0)
@@ -384,6 +391,75 @@ def grid_triangulations(sc, rays, scene, o, d, st, out, steps):
         hits[name] = (out.hit_prim.clone(), out.hit_t.clone())
     res["hits_identical"] = all(torch.equal(hits["cdt"][0], h[0]) and torch.equal(hits["cdt"][1], h[1])
                                 for h in hits.values())
+    return res
+
+
+def pipeline_leg(sc, rays, stages=24, verbose=False):
+    """The paper's low-weight pipeline on a scene (``paper_2112_05570_amd.pipeline.optimise``:
+    annealing with every single-vertex proposal, contraction, polishing and greedy flips, raised
+    contraction lengths) from its CDT subdivided once (Sec. 3.5.2), then the CDT and the result
+    walked by the same rays (origins located in the result by the library's point location).
+    Returns weights, counts, times and the walk comparison: steps per ray, trace time, the share
+    of rays hitting the same original primitive, and the largest relative difference of t (the
+    result's constrained edges are sub-segments of the primitives, collinear to rounding)."""
+    import numpy as np
+    import torch
+
+    import paper_2112_05570_amd as ccsp
+    import scenegen as sg
+    from paper_2112_05570_amd import pipeline as pl
+
+    size = sc.box[1] - sc.box[0]
+    t0 = time.perf_counter()
+    mesh = sg.subdivide(sc)
+    t_sub = time.perf_counter() - t0
+    r = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, size,
+                    pl.Schedule(stages=stages), verbose=verbose)
+    res = {"subdivided": {"vertices": mesh.n_vertices, "triangles": mesh.n_triangles,
+                          "weight": r.log["weight_start"], "subdivide_s": t_sub},
+           "stages": stages, "anneal_s": r.log["anneal_s"],
+           "weight_annealed": r.log["weight_annealed"],
+           "contract_polish_s": r.log["contract_polish_s"],
+           "contract_polish": r.log["contract_polish"],
+           "final": {"vertices": int(r.xy.shape[0]), "triangles": int(r.tri_v.shape[0]),
+                     "steiner_vertices": int((r.kind != 0).sum()), "weight": r.log["weight_final"]},
+           "total_s": time.perf_counter() - t0}
+    nbr, prim, prims, sub_to_orig = pl.walk_arrays(r.tri_v, r.kind, r.line, mesh.prim_v, r.xy)
+    dev = torch.device("cuda:0")
+    o = torch.from_numpy(rays.o).to(dev)
+    d = torch.from_numpy(rays.d).to(dev)
+    walks = {}
+    with ccsp.Scene(sc.xy, sc.tri_v, sc.tri_nbr, sc.tri_prim, sc.prims) as s_cdt, \
+            ccsp.Scene(r.xy, r.tri_v, nbr, prim, prims) as s_opt:
+        st_opt, stat = ccsp.locate(s_opt, o)
+        keep = torch.nonzero(stat == 0).squeeze(1)
+        o, d = o[keep].contiguous(), d[keep].contiguous()
+        st_cdt = torch.from_numpy(rays.start).to(dev)[keep].contiguous()
+        st_opt = st_opt[keep].contiguous()
+        for name, scene, st in (("cdt", s_cdt, st_cdt), ("pipeline", s_opt, st_opt)):
+            out = ccsp.trace(scene, o, d, st, precision="fp32")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(5):
+                out = ccsp.trace(scene, o, d, st, precision="fp32", out=out)
+            torch.cuda.synchronize()
+            walks[name] = (out.hit_prim.cpu().numpy(), out.hit_t.cpu().numpy(),
+                           out.steps.cpu().numpy(), (time.perf_counter() - t1) / 5 * 1e3)
+    hp = walks["pipeline"][0]
+    mapped = np.where(hp >= 0, sub_to_orig[np.maximum(hp, 0)], hp)
+    same = mapped == walks["cdt"][0]
+    tc, tp = walks["cdt"][1][same], walks["pipeline"][1][same]
+    fin = np.isfinite(tc)
+    rel = np.abs(tp[fin] - tc[fin]) / np.abs(tc[fin])
+    res["walk"] = {"rays": int(o.shape[0]),
+                   "cdt": {"weight": sg.weight(sc), "triangles": sc.n_triangles,
+                           "mean_steps_per_ray": float(walks["cdt"][2].mean()),
+                           "ms_per_trace": walks["cdt"][3]},
+                   "pipeline": {"weight": r.log["weight_final"], "triangles": int(r.tri_v.shape[0]),
+                                "mean_steps_per_ray": float(walks["pipeline"][2].mean()),
+                                "ms_per_trace": walks["pipeline"][3]},
+                   "same_primitive_hit": float(same.mean()),
+                   "max_rel_t_difference": float(rel.max(initial=0.0))}
     return res
 
 

@@ -61,3 +61,20 @@ def test_rejects_bad_input():
     bad[4] = ob.CONSTRAINED
     with pytest.raises(ccsp.CcspError, match="constrained vertex without edge"):
         ccsp.contract(tv, bad, line, prim_v, xy, 0.05)
+
+
+def test_walk_arrays_of_a_subdivided_mesh():
+    """Every constrained edge of the subdivided tiny scene becomes its own primitive, lying on its
+    original one (to rounding of the midpoints); the arrays pass the checker's validator."""
+    import oracle
+    from paper_2112_05570_amd import pipeline as pl
+    sc = sg.make_scene("tiny")
+    mesh = sg.subdivide(sc)
+    nbr, prim, prims, s2o = pl.walk_arrays(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy)
+    assert prims.shape == (2 * sc.n_prims, 4) and np.bincount(s2o).tolist() == [2] * sc.n_prims
+    assert oracle.validate(oracle.Triangulation(mesh.xy, mesh.tri_v, nbr, prim, prims)) == ""
+    for j in range(prims.shape[0]):
+        a, b = sc.prims[s2o[j], :2], sc.prims[s2o[j], 2:]
+        for p in (prims[j, :2], prims[j, 2:]):
+            cross = (b[0] - a[0]) * (p[1] - a[1]) - (b[1] - a[1]) * (p[0] - a[0])
+            assert abs(cross) <= 1e-12 * np.hypot(*(b - a)) * (1 + np.abs(p).max())

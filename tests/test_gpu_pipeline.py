@@ -1,0 +1,85 @@
+"""The low-weight pipeline (paper_2112_05570_amd.pipeline.optimise) end to end on the tiny scene:
+annealing with every single-vertex proposal on the GPU, the library's contraction, polishing and
+greedy flips. The result is a valid constrained triangulation that keeps the original vertices,
+weighs less than the subdivided input, and on which the GPU walk equals the checker's walk bit for
+bit; hits match the CDT's primitives; two runs with one seed are identical."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ccsp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_05570_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def run(ccsp):
+    from paper_2112_05570_amd import pipeline as pl
+    sc = sg.make_scene("tiny")
+    mesh = sg.subdivide(sc)
+    size = sc.box[1] - sc.box[0]
+    sched = pl.Schedule(stages=9, t0_rel=1e-3, t1_rel=1e-5, e0_rel=2e-2, e1_rel=2e-3,
+                        outer_max=4, flip_rounds=32, seed=3)
+    r = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, size, sched)
+    return sc, mesh, sched, r
+
+
+def test_result_is_valid_and_lighter(ccsp, run):
+    from paper_2112_05570_amd import pipeline as pl
+    sc, mesh, _, r = run
+    nbr, prim, prims, s2o = pl.walk_arrays(r.tri_v, r.kind, r.line, mesh.prim_v, r.xy)
+    assert oracle.validate(oracle.Triangulation(r.xy, r.tri_v, nbr, prim, prims)) == ""
+    assert (r.kind == 0).sum() == sc.n_vertices
+    assert np.array_equal(r.xy[r.kind == 0], sc.xy)  # original vertices keep id order and place
+    assert r.log["weight_final"] < r.log["weight_start"]
+    assert r.log["weight_final"] == pl.weight(r.tri_v, r.xy)
+    assert r.xy.shape[0] < mesh.n_vertices
+
+
+def test_walk_on_result_equals_checker(ccsp, run):
+    from paper_2112_05570_amd import pipeline as pl
+    sc, mesh, _, r = run
+    nbr, prim, prims, s2o = pl.walk_arrays(r.tri_v, r.kind, r.line, mesh.prim_v, r.xy)
+    rays = sg.sample_rays(sc, 20000, seed=5)
+    with ccsp.Scene(r.xy, r.tri_v, nbr, prim, prims) as s_opt, ccsp.Scene.from_arrays(sc) as s_cdt:
+        o = torch.from_numpy(rays.o).to(DEV)
+        d = torch.from_numpy(rays.d).to(DEV)
+        st, stat = ccsp.locate(s_opt, o)
+        keep = torch.nonzero(stat == 0).squeeze(1)
+        assert keep.shape[0] > 19000
+        o, d, st = o[keep].contiguous(), d[keep].contiguous(), st[keep].contiguous()
+        got = ccsp.trace(s_opt, o, d, st, precision="fp32")
+        cdt = ccsp.trace(s_cdt, o, d, torch.from_numpy(rays.start).to(DEV)[keep].contiguous(),
+                         precision="fp64")
+        torch.cuda.synchronize()
+        g = [x.cpu().numpy() for x in (got.hit_prim, got.hit_t, got.steps)]
+        c = [x.cpu().numpy() for x in (cdt.hit_prim, cdt.hit_t, cdt.steps)]
+    k = keep.cpu().numpy()
+    ref = oracle.walk(oracle.Triangulation(r.xy, r.tri_v, nbr, prim, prims), rays.o[k], rays.d[k],
+                      st.cpu().numpy())
+    assert np.array_equal(g[0], ref[0]) and np.array_equal(g[1], ref[1])
+    assert np.array_equal(g[2], ref[2])
+    mapped = np.where(g[0] >= 0, s2o[np.maximum(g[0], 0)], g[0])
+    assert (mapped == c[0]).mean() > 0.999
+    assert g[2].mean() < c[2].mean() * 1.5
+
+
+def test_same_seed_same_result(ccsp, run):
+    from paper_2112_05570_amd import pipeline as pl
+    _, mesh, sched, r = run
+    sc = sg.make_scene("tiny")
+    r2 = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, sc.box[1] - sc.box[0],
+                     sched)
+    assert np.array_equal(r2.tri_v, r.tri_v) and np.array_equal(r2.xy, r.xy)
