@@ -243,6 +243,9 @@ def main():
     walk_steps_s = steps_total / walk_avg
 
     objective = None if args.no_objective else objective_leg("grid", args.steps, args.warmup)
+    low_weight = None
+    if args.workload == "large" and not args.no_objective:
+        low_weight = low_weight_leg(sc, scene, o, d, out32, args.steps)
     triangulations = None
     if args.workload == "grid":
         triangulations = grid_triangulations(sc, rays, scene, o, d, st, out32, args.steps)
@@ -308,6 +311,7 @@ def main():
             "frac_l2_sized": walk_steps_s / g_l2},
         "objective": objective,
         "triangulations": triangulations,
+        "low_weight": low_weight,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -350,6 +354,59 @@ def flip_leg(sc, steps, hot=300, cold=100, t0_rel=5e-3, t1_rel=1e-5, seed=0):
            "host_sequential": {"s": host_s, "weight": sg.weight(host),
                                "proposals": int(host_stats["proposals"])}}
     return an, host, res
+
+
+def low_weight_leg(sc, scene, o, d, out, steps, hot=300, cold=100, seed=0):
+    """The paper's claim on this workload: the scene's CDT flip-annealed on the GPU with the
+    weight as energy (flip_anneal; temperatures from 2.5 to 0.005 mean edge lengths over `hot`
+    rounds, then `cold` rounds at 0), the rays' origins located in the result by the library's
+    point location, and the same rays walked on it. `out` holds the CDT trace of these rays."""
+    import numpy as np
+    import torch
+
+    import paper_2112_05570_amd as ccsp
+    from paper_2112_05570_amd import pipeline as pl
+
+    w0 = pl.weight(sc.tri_v, sc.xy)
+    mean_len = w0 / (sc.n_vertices + sc.n_triangles - 1)  # Euler: E = V + T - 1
+    temps = list(mean_len * np.geomspace(2.5, 0.005, hot)) + [0.0] * cold
+    xy = torch.from_numpy(np.ascontiguousarray(sc.xy)).to(o.device)
+    arrs = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(o.device)
+            for a in (sc.tri_v, sc.tri_nbr, sc.tri_prim)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    counts = ccsp.flip_anneal(xy, *arrs, temps, seed)
+    ms_anneal = (time.perf_counter() - t0) * 1e3
+    tv, nbr, prim = (a.cpu().numpy() for a in arrs)
+    del arrs
+    res = {"anneal": {"rounds": len(temps), "ms": ms_anneal, "flips": int(counts.sum()),
+                      "last_round_with_flips": int(np.nonzero(counts)[0][-1])},
+           "weight_cdt": w0, "weight": pl.weight(tv, sc.xy)}
+    with ccsp.Scene(sc.xy, tv, nbr, prim, sc.prims) as an:
+        st, stat = ccsp.locate(an, o)
+        keep = torch.nonzero(stat == 0).squeeze(1)
+        full = keep.shape[0] == o.shape[0]
+        oo = o if full else o[keep].contiguous()
+        dd = d if full else d[keep].contiguous()
+        st = st if full else st[keep].contiguous()
+        r = ccsp.trace(an, oo, dd, st, precision="fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = ccsp.trace(an, oo, dd, st, precision="fp32", out=r)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        cdt_prim = out.hit_prim if full else out.hit_prim[keep]
+        cdt_t = out.hit_t if full else out.hit_t[keep]
+        cdt_steps = out.steps if full else out.steps[keep]
+        res.update({"rays": int(oo.shape[0]), "ms_per_trace": ms,
+                    "rays_per_s": oo.shape[0] / ms * 1e3,
+                    "mean_steps_per_ray": float(r.steps.double().mean().item()),
+                    "mean_steps_per_ray_cdt": float(cdt_steps.double().mean().item()),
+                    "hits_identical": bool(torch.equal(r.hit_prim, cdt_prim)
+                                           and torch.equal(r.hit_t, cdt_t))})
+        del r
+    return res
 
 
 def grid_triangulations(sc, rays, scene, o, d, st, out, steps):
