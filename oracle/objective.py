@@ -512,3 +512,70 @@ def proposal_chain(m: Mesh, xy, p: Params, temperature, kind, vid, r, u):
             xy[v] = q
         margin[i] = abs(d + temperature * np.log(u[i])) if u[i] > 0 else np.inf
     return xy, st, df, margin
+
+
+def group_members(m: Mesh, xy, c, d):
+    """Sec. 3.2.3: the group of centre c, read as c and its movable neighbours (increasing id)
+    within distance d of it (lengths as everywhere)."""
+    nb = m.nbr[m.nbr_off[c]:m.nbr_off[c + 1]]
+    dist = incident_lengths(m, xy, c)
+    return [int(c)] + [int(w) for w, l in zip(nb, dist) if m.kind[w] != ORIGINAL and l <= d]
+
+
+def group_area(m: Mesh, xy, members):
+    """Area of the triangles holding any member, each once: members in order, each member's
+    triangles in increasing id, a triangle counted at the first member it holds; areas as in
+    star_area, summed in that order."""
+    s = 0.0
+    for j, v in enumerate(members):
+        for t in np.nonzero((m.tri_v == v).any(axis=1))[0]:
+            if any(w in members[:j] for w in m.tri_v[t]):
+                continue
+            s = s + _tri_area(xy, m.tri_v[t])
+    return s
+
+
+def group_move(m: Mesh, xy, p: Params, c, lam, xi, rd):
+    """The group move of centre c (Sec. 3.2.3): d = (0.5 + 4.5 rd) eps, uniform on [eps/2, 5 eps);
+    every member moves by (lam * sqrt(group area)) * xi, projected on its original edge when
+    constrained. Returns (members, new positions)."""
+    d = (0.5 + 4.5 * rd) * p.eps
+    members = group_members(m, xy, c, d)
+    k = lam * math.sqrt(group_area(m, xy, members))
+    D = np.array([k * xi[0], k * xi[1]])
+    return members, [xy[v] + project(m, xy, v, D) for v in members]
+
+
+def group_chain(m: Mesh, xy, p: Params, temperature, lam, centres, xi, rd, u):
+    """Metropolis steps (Sec. 3.1) with group moves, the centres one after another. A move is
+    valid when every triangle holding a member is strictly counter-clockwise afterwards (exact);
+    its delta f is f(moved) - f(current) over every term. Returns the final positions and, per
+    centre, the status (ACCEPTED, REJECTED, FOLDED), delta f, the decision margin and the
+    number of members."""
+    xy = np.array(xy, dtype=np.float64)
+    n = len(centres)
+    st = np.zeros(n, dtype=np.int64)
+    df = np.full(n, np.inf)
+    margin = np.full(n, np.inf)
+    size = np.zeros(n, dtype=np.int64)
+    for i, c in enumerate(centres):
+        members, qs = group_move(m, xy, p, int(c), lam, xi[i], rd[i])
+        size[i] = len(members)
+        moved = xy.copy()
+        for v, q in zip(members, qs):
+            moved[v] = q
+        tris = np.nonzero(np.isin(m.tri_v, members).any(axis=1))[0]
+        if any(orient(*moved[m.tri_v[t]]) <= 0 for t in tris):
+            st[i] = FOLDED
+            continue
+        t0, t1 = terms(m, xy, p), terms(m, moved, p)
+        d = float((t1["edge"] - t0["edge"]).sum() + p.mu_angle * (t1["angle"] - t0["angle"]).sum()
+                  + p.mu_len * (t1["short"] - t0["short"]).sum())
+        df[i] = d
+        with np.errstate(divide="ignore", over="ignore"):
+            accept = d <= 0.0 or u[i] < np.exp(-np.float64(d) / np.float64(temperature))
+        st[i] = ACCEPTED if accept else REJECTED
+        if accept:
+            xy = moved
+        margin[i] = abs(d + temperature * np.log(u[i])) if u[i] > 0 else np.inf
+    return xy, st, df, margin, size

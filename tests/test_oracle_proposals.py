@@ -168,3 +168,71 @@ def test_zero_temperature_chain_never_raises_f(kind):
     assert not moved[np.setdiff1d(np.arange(mesh.kind.shape[0]), vid[acc])].any()
     if kind == ob.SWAP:
         assert (st == ob.SKIPPED).sum() > 0
+
+
+def test_group_members_and_area():
+    """Members are the centre and its movable neighbours within d; the group area counts the
+    triangles two members share once (star areas added, shared ones taken off)."""
+    mesh = sg.subdivide(sg.make_scene("tiny"))
+    m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+    xy = mesh.xy
+    checked = 0
+    for c in np.nonzero(mesh.kind == ob.FREE)[0][:200]:
+        nb = m.nbr[m.nbr_off[c]:m.nbr_off[c + 1]]
+        lens = np.hypot(*(xy[nb] - xy[c]).T)
+        d = float(np.sort(lens)[1]) * (1 + 1e-9)  # the two nearest neighbours
+        mem = ob.group_members(m, xy, int(c), d)
+        want = [int(w) for w, l in zip(nb, lens) if l <= d and mesh.kind[w] != ob.ORIGINAL]
+        assert mem == [int(c)] + want
+        if len(mem) == 2:
+            w = mem[1]
+            shared = [t for t in range(m.tri_v.shape[0]) if c in m.tri_v[t] and w in m.tri_v[t]]
+            expect = ob.star_area(m, xy, c) + ob.star_area(m, xy, w) - sum(
+                ob._tri_area(xy, m.tri_v[t]) for t in shared)
+            assert abs(ob.group_area(m, xy, mem) - expect) <= 1e-12 * expect
+            checked += 1
+    assert checked > 10
+
+
+def test_lone_centre_is_the_single_vertex_move():
+    """A group with no member but its centre makes the move of Sec. 3.2.2: the same position,
+    status and acceptance as the single-vertex chain with displacement lam * sqrt(star area) * xi."""
+    mesh = sg.subdivide(sg.make_scene("tiny"))
+    m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+    p = ob.Params(1e-9)  # d < every edge: lone centres
+    rng = np.random.default_rng(8)
+    c = rng.choice(np.nonzero(mesh.kind != ob.ORIGINAL)[0], 40, replace=False)
+    xi = rng.standard_normal((40, 2)) * 0.5
+    rd, u = rng.random(40), rng.random(40)
+    xy_g, st_g, df_g, _, size = ob.group_chain(m, mesh.xy, p, 1e-3, 0.05, c, xi, rd, u)
+    assert (size == 1).all()
+    xy_s = mesh.xy.copy()
+    for i, v in enumerate(c):
+        k = 0.05 * math.sqrt(ob.star_area(m, xy_s, int(v)))
+        d = np.array([k * xi[i, 0], k * xi[i, 1]])
+        xy_s, st, df, _ = ob.metropolis_chain(m, xy_s, p, 1e-3, [int(v)], [d], [u[i]])
+        assert st[0] == st_g[i]
+        if np.isfinite(df[0]):
+            assert abs(df[0] - df_g[i]) <= 1e-9 * (1 + abs(df[0]))
+    assert np.array_equal(xy_s, xy_g)
+
+
+def test_group_moves_rigidly():
+    """Free members share one displacement: the edges between them keep their lengths (to
+    rounding) when the move is accepted."""
+    mesh = sg.subdivide(sg.make_scene("tiny"))
+    m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
+    p = ob.Params(0.2)  # d up to 1: whole neighbourhoods
+    rng = np.random.default_rng(9)
+    seen = 0
+    for c in np.nonzero(mesh.kind == ob.FREE)[0][:60]:
+        mem, qs = ob.group_move(m, mesh.xy, p, int(c), 0.05, rng.standard_normal(2), 0.9)
+        free = [j for j, v in enumerate(mem) if mesh.kind[v] == ob.FREE]
+        for j in free:
+            for k in free:
+                if j < k and m.has_edge(mem[j], mem[k]):
+                    before = np.hypot(*(mesh.xy[mem[j]] - mesh.xy[mem[k]]))
+                    after = np.hypot(*(qs[j] - qs[k]))
+                    assert abs(after - before) <= 1e-12 * (1 + before)
+                    seen += 1
+    assert seen > 20
