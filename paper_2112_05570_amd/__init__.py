@@ -362,6 +362,35 @@ class MovableMesh:
                          _stream(stream))
         return d, st
 
+    def group_classes(self):
+        """Classes of movable vertices (caller ids) more than seven edges apart, the order of
+        ``group_sweep``."""
+        n = B.mesh_group_classes(self.handle)
+        off = np.empty(n + 1, dtype=np.int64)
+        B.mesh_group_classes(self.handle, off.ctypes.data_as(ctypes.c_void_p).value)
+        v = np.empty(int(off[-1]), dtype=np.int32)
+        B.mesh_group_classes(self.handle, off.ctypes.data_as(ctypes.c_void_p).value,
+                             v.ctypes.data_as(ctypes.c_void_p).value)
+        return [v[off[i]:off[i + 1]] for i in range(n)]
+
+    def group_sweep(self, xy, params, temperature, lam, draws, u, stream=None):
+        """One sweep of group moves (see ``anneal_group``): draws (M,4) (xi.x, xi.y, r, unused) and
+        u (M,) float64 CUDA tensors in the order of ``group_classes()``. xy is updated in place.
+        Returns (delta, status, members). Asynchronous."""
+        import torch
+        m = self.n_movable()
+        if (tuple(draws.shape) != (m, 4) or draws.dtype != torch.float64
+                or not draws.is_contiguous() or not draws.is_cuda or tuple(u.shape) != (m,)
+                or u.dtype != torch.float64 or not u.is_contiguous() or not u.is_cuda):
+            raise ValueError(f"draws float64 ({m},4) and u float64 ({m},), contiguous CUDA tensors")
+        d = torch.empty(m, dtype=torch.float64, device=xy.device)
+        st = torch.empty(m, dtype=torch.int32, device=xy.device)
+        mem = torch.empty(m, dtype=torch.int32, device=xy.device)
+        B.anneal_group(self.handle, self._xy(xy), params, float(temperature), float(lam),
+                       draws.data_ptr(), u.data_ptr(), d.data_ptr(), st.data_ptr(), mem.data_ptr(),
+                       _stream(stream))
+        return d, st, mem
+
     def schedule(self, xy, params, temperatures, eps, lambda0, xi, u, target=0.23, stream=None):
         """Simulated annealing with a temperature and contraction-length schedule and an adaptive
         step scale (see ``anneal_schedule``): temperatures and eps are sequences of one value per

@@ -354,19 +354,18 @@ struct MoveCtx {
   }
 };
 
-// Status and change of f (through *df, +inf unless valid) of moving the vertex of caller id cv
-// to q, against positions xy (internal order) and the per-edge scratch of edge_state. nb is this
-// thread's LDS column for the vertex's neighbours.
-__device__ __forceinline__ int evaluate_move(const MeshDev& m, const double2* __restrict__ xy,
-                                             const Par& p, int cv, double2 q, int* nb, double* df) {
-  *df = __builtin_huge_val();
-  if (cv < 0 || cv >= m.nv || !isfinite(q.x) || !isfinite(q.y)) return CCSP_MOVE_BAD;
-  const int v = m.vnew[cv];
-  if (m.vk[v].x == CCSP_VERTEX_ORIGINAL) return CCSP_MOVE_FIXED;
+// Change of f (through *df) of moving internal vertex v to q, against positions xy (internal
+// order) and the per-edge scratch of edge_state; with CHECK, CCSP_MOVE_FOLDS (and *df untouched)
+// when a triangle of v would not stay strictly counter-clockwise. nb is this thread's LDS column
+// for the vertex's neighbours.
+template <bool CHECK>
+__device__ __forceinline__ int move_change(const MeshDev& m, const double2* __restrict__ xy,
+                                           const Par& p, int v, double2 q, int* nb, double* df) {
   double sa = 0.0;
   for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j) {
     const int4 t = m.tri[m.vtri[j]];
-    if (orient_sign(pos(xy, t.x, v, q), pos(xy, t.y, v, q), pos(xy, t.z, v, q)) <= 0)
+    if (CHECK &&
+        orient_sign(pos(xy, t.x, v, q), pos(xy, t.y, v, q), pos(xy, t.z, v, q)) <= 0)
       return CCSP_MOVE_FOLDS;
     sa += triangle_angles(xy, t, v, q, p.delta, p.polish) -
           triangle_angles(xy, t, -1, q, p.delta, p.polish);
@@ -389,6 +388,18 @@ __device__ __forceinline__ int evaluate_move(const MeshDev& m, const double2* __
     }
   *df = se + p.mu_angle * sa + p.mu_len * ss;
   return CCSP_MOVE_OK;
+}
+
+// Status and change of f (through *df, +inf unless valid) of moving the vertex of caller id cv
+// to q, against positions xy (internal order) and the per-edge scratch of edge_state. nb is this
+// thread's LDS column for the vertex's neighbours.
+__device__ __forceinline__ int evaluate_move(const MeshDev& m, const double2* __restrict__ xy,
+                                             const Par& p, int cv, double2 q, int* nb, double* df) {
+  *df = __builtin_huge_val();
+  if (cv < 0 || cv >= m.nv || !isfinite(q.x) || !isfinite(q.y)) return CCSP_MOVE_BAD;
+  const int v = m.vnew[cv];
+  if (m.vk[v].x == CCSP_VERTEX_ORIGINAL) return CCSP_MOVE_FIXED;
+  return move_change<true>(m, xy, p, v, q, nb, df);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -613,6 +624,128 @@ anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
   }
 }
 
+constexpr int kGroupMax = 16;  // members of a group move at most
+
+// One class of group moves (Sec. 3.2.3): the centres (internal ids) are pairwise more than seven
+// edges apart, so that a group's writes (within two edges of its centre) never meet another
+// group's reads (within five). The group of centre c: c, then its movable neighbours within
+// d = (0.5 + 4.5 r) eps, by increasing caller id (at most kGroupMax members). Every member moves
+// by (lambda * sqrt(area)) * xi, projected when constrained, where area sums the triangles holding
+// any member, each at the first member (in order) that it holds, a member's triangles in caller
+// order. The members are moved one after another, each with its change of f against the
+// positions and scratch its predecessors left, so that the changes add up to the change of f of
+// the whole move. Valid when every triangle of every member is strictly counter-clockwise at the
+// end; rejected or invalid moves are undone from xy_out, which holds the positions before them.
+__global__ void __launch_bounds__(kThreads)
+anneal_group_class(MeshDev m, Par p, double temperature, double lambda,
+                   double2* __restrict__ xy_out, const int32_t* __restrict__ cls,
+                   const double2* __restrict__ draws, const double* __restrict__ u, int n,
+                   double* __restrict__ delta, int32_t* __restrict__ status,
+                   int32_t* __restrict__ members, unsigned long long* __restrict__ accepted) {
+  __shared__ int snb[kLdsNbrs * kThreads];
+  __shared__ int smem[kGroupMax * kThreads];
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  bool took = false;
+  if (i < n) {
+    int* mem = smem + threadIdx.x;  // stride kThreads
+    const int c = cls[i];
+    const double2 xi = draws[2 * i], rr = draws[2 * i + 1];
+    const double dd = (0.5 + 4.5 * rr.x) * p.eps;
+    const double2 pc = m.xyi[c];
+    int nm = 1;
+    mem[0] = c;
+    {
+      const int a0 = m.adj_off[c], a1 = m.adj_off[c + 1];
+      int last = -1;
+      for (int step = a0; step < a1; ++step) {  // neighbours by increasing caller id
+        int w = -1, cw = 0x7fffffff;
+        for (int j = a0; j < a1; ++j) {
+          const int x = m.adj[j].x, cx = m.vold[x];
+          if (cx > last && cx < cw) {
+            cw = cx;
+            w = x;
+          }
+        }
+        last = cw;
+        if (nm < kGroupMax && m.vk[w].x != CCSP_VERTEX_ORIGINAL && dist(pc, m.xyi[w]) <= dd)
+          mem[kThreads * nm++] = w;
+      }
+    }
+    double area = 0.0;
+    for (int j = 0; j < nm; ++j) {
+      const int v = mem[kThreads * j];
+      for (int k = m.vtri_off[v], end = m.vtri_off[v + 1]; k < end; ++k) {
+        const int tid = m.vtri[k];
+        const int4 tr = m.tri[tid];
+        bool earlier = false;
+        for (int l = 0; l < j; ++l) {
+          const int w = mem[kThreads * l];
+          earlier = earlier || tr.x == w || tr.y == w || tr.z == w;
+        }
+        if (!earlier) area = area + tri_area(m, tid);
+      }
+    }
+    const double k = lambda * sqrt(area);
+    const double2 D = make_double2(k * xi.x, k * xi.y);
+    double df = 0.0;
+    for (int j = 0; j < nm; ++j) {
+      const int v = mem[kThreads * j];
+      const double2 o = m.xyi[v];
+      double2 d = D;
+      const int2 kl = m.vk[v];
+      if (kl.x == CCSP_VERTEX_CONSTRAINED) {
+        const int2 ends = m.prim_v[kl.y];
+        const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
+        const double ex = b.x - a.x, ey = b.y - a.y;
+        const double s = (d.x * ex + d.y * ey) / (ex * ex + ey * ey);
+        d = make_double2(s * ex, s * ey);
+      }
+      const double2 q = make_double2(o.x + d.x, o.y + d.y);
+      double dfj = 0.0;
+      move_change<false>(m, m.xyi, p, v, q, snb + threadIdx.x, &dfj);
+      df += dfj;
+      m.xyi[v] = q;
+      refresh_scratch(m, p, v);
+    }
+    bool ok = true;
+    for (int j = 0; j < nm && ok; ++j) {
+      const int v = mem[kThreads * j];
+      for (int k = m.vtri_off[v], end = m.vtri_off[v + 1]; k < end && ok; ++k) {
+        const int4 tr = m.tri[m.vtri[k]];
+        ok = orient_sign(m.xyi[tr.x], m.xyi[tr.y], m.xyi[tr.z]) > 0;
+      }
+    }
+    int st = CCSP_MOVE_FOLDS;
+    if (ok) {
+      st = CCSP_MOVE_REJECTED;
+      if (df <= 0.0 || u[i] < exp(-df / temperature)) {
+        st = CCSP_MOVE_OK;
+        took = true;
+        for (int j = 0; j < nm; ++j) {
+          const int v = mem[kThreads * j];
+          xy_out[m.vold[v]] = m.xyi[v];
+        }
+      }
+    } else {
+      df = __builtin_huge_val();
+    }
+    if (!took) {
+      for (int j = 0; j < nm; ++j) {
+        const int v = mem[kThreads * j];
+        m.xyi[v] = xy_out[m.vold[v]];
+      }
+      for (int j = 0; j < nm; ++j) refresh_scratch(m, p, mem[kThreads * j]);
+    }
+    status[i] = st;
+    delta[i] = df;
+    members[i] = nm;
+  }
+  if (accepted) {
+    const int cnt = __syncthreads_count(took);
+    if (threadIdx.x == 0 && cnt > 0) atomicAdd(accepted, (unsigned long long)cnt);
+  }
+}
+
 __global__ void zero_counter(unsigned long long* __restrict__ c) {
   if (threadIdx.x == 0) c[0] = 0ull;
 }
@@ -630,6 +763,9 @@ struct MovableMesh {
   std::vector<int64_t> class_off;  // mesh_classes, computed on the first call
   std::vector<int32_t> class_v;    // caller ids, class by class
   int32_t* class_dev = nullptr;    // the same vertices, internal ids, on the device
+  std::vector<int64_t> gclass_off;  // mesh_group_classes: centres more than seven edges apart
+  std::vector<int32_t> gclass_v;
+  int32_t* gclass_dev = nullptr;
   void* sched = nullptr;           // anneal_schedule: delta and status per movable vertex, counter
 };
 
@@ -1046,8 +1182,11 @@ int objective_delta(MovableMesh* mesh, const double* xy, const ObjectiveParams* 
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_delta: launch");
 }
 
-int ensure_classes(MovableMesh* mesh) {
-  if (mesh->class_off.empty()) {
+// Greedy colouring of the movable vertices over balls of `radius` edges: members of a class are
+// more than `radius` edges apart.
+int build_classes(MovableMesh* mesh, int radius, std::vector<int64_t>& class_off,
+                  std::vector<int32_t>& class_v, int32_t*& class_dev) {
+  if (class_off.empty()) {
     if (int r = check_device(mesh)) return r;
     const ccsp::MeshDev& d = mesh->d;
     const int64_t V = d.nv;
@@ -1057,8 +1196,7 @@ int ensure_classes(MovableMesh* mesh) {
     if (e == hipSuccess) e = hipMemcpy(vk.data(), d.vk, 8 * V, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(vold.data(), d.vold, 4 * V, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "mesh_classes: hipMemcpy");
-    // greedy colouring: each movable vertex takes the smallest class not used by a movable
-    // vertex within four edges
+    // each movable vertex takes the smallest class not used by a movable vertex within radius
     std::vector<int32_t> colour(V, -1), stamp(V, -1), ball, used;
     int32_t n = 0;
     for (int64_t v = 0; v < V; ++v) {
@@ -1066,7 +1204,7 @@ int ensure_classes(MovableMesh* mesh) {
       ball.assign(1, (int32_t)v);
       stamp[v] = (int32_t)v;
       size_t lo = 0;
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < radius; ++r) {
         const size_t hi = ball.size();
         for (size_t j = lo; j < hi; ++j)
           for (int32_t k = adj_off[ball[j]]; k < adj_off[ball[j] + 1]; ++k) {
@@ -1099,19 +1237,27 @@ int ensure_classes(MovableMesh* mesh) {
       }
     if (n == 0) off.assign(1, 0);
     if (!ci.empty()) {
-      e = hipMalloc(&mesh->class_dev, 4 * ci.size());
+      e = hipMalloc(&class_dev, 4 * ci.size());
       if (e != hipSuccess) return fail(CCSP_E_OOM, "mesh_classes: device allocation failed");
-      e = hipMemcpy(mesh->class_dev, ci.data(), 4 * ci.size(), hipMemcpyHostToDevice);
+      e = hipMemcpy(class_dev, ci.data(), 4 * ci.size(), hipMemcpyHostToDevice);
       if (e != hipSuccess) {
-        (void)hipFree(mesh->class_dev);
-        mesh->class_dev = nullptr;
+        (void)hipFree(class_dev);
+        class_dev = nullptr;
         return hip_fail(e, "mesh_classes: hipMemcpy");
       }
     }
-    mesh->class_off = std::move(off);
-    mesh->class_v = std::move(cv);
+    class_off = std::move(off);
+    class_v = std::move(cv);
   }
   return CCSP_OK;
+}
+
+int ensure_classes(MovableMesh* mesh) {
+  return build_classes(mesh, 4, mesh->class_off, mesh->class_v, mesh->class_dev);
+}
+
+int ensure_group_classes(MovableMesh* mesh) {
+  return build_classes(mesh, 7, mesh->gclass_off, mesh->gclass_v, mesh->gclass_dev);
 }
 
 int mesh_classes(MovableMesh* mesh, int32_t* n_classes, int64_t* class_off, int32_t* class_v) {
@@ -1121,6 +1267,52 @@ int mesh_classes(MovableMesh* mesh, int32_t* n_classes, int64_t* class_off, int3
   if (class_off) std::memcpy(class_off, mesh->class_off.data(), 8 * mesh->class_off.size());
   if (class_v) std::memcpy(class_v, mesh->class_v.data(), 4 * mesh->class_v.size());
   return CCSP_OK;
+}
+
+int mesh_group_classes(MovableMesh* mesh, int32_t* n_classes, int64_t* class_off,
+                       int32_t* class_v) {
+  if (!mesh || !n_classes) return fail(CCSP_E_ARG, "mesh_group_classes: null argument");
+  if (int r = ensure_group_classes(mesh)) return r;
+  *n_classes = (int32_t)mesh->gclass_off.size() - 1;
+  if (class_off) std::memcpy(class_off, mesh->gclass_off.data(), 8 * mesh->gclass_off.size());
+  if (class_v) std::memcpy(class_v, mesh->gclass_v.data(), 4 * mesh->gclass_v.size());
+  return CCSP_OK;
+}
+
+int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, double temperature,
+                 double lambda, const double* draws, const double* u, double* delta,
+                 int32_t* status, int32_t* members, void* stream) {
+  if (!mesh || !xy || !draws || !u || !delta || !status || !members)
+    return fail(CCSP_E_ARG, "anneal_group: null argument");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)draws & 15) != 0 || ((uintptr_t)u & 7) != 0 ||
+      ((uintptr_t)delta & 7) != 0 || ((uintptr_t)status & 3) != 0 || ((uintptr_t)members & 3) != 0)
+    return fail(CCSP_E_ARG, "anneal_group: misaligned buffer");
+  if (!check_params(params)) return fail(CCSP_E_ARG, "anneal_group: invalid parameters");
+  if (!(temperature >= 0) || !std::isfinite(temperature))
+    return fail(CCSP_E_ARG, "anneal_group: temperature must be finite and >= 0");
+  if (!(lambda >= 0) || !std::isfinite(lambda))
+    return fail(CCSP_E_ARG, "anneal_group: lambda must be finite and >= 0");
+  if (int r = check_device(mesh)) return r;
+  if (int r = ensure_group_classes(mesh)) return r;
+  const ccsp::MeshDev& d = mesh->d;
+  const ccsp::Par p = to_par(params);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy);
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
+                     d.partial);
+  const std::vector<int64_t>& off = mesh->gclass_off;
+  for (size_t c = 0; c + 1 < off.size(); ++c) {
+    const int n = (int)(off[c + 1] - off[c]);
+    if (n == 0) continue;
+    hipLaunchKernelGGL(ccsp::anneal_group_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
+                       dim3(ccsp::kThreads), 0, s, d, p, temperature, lambda, (double2*)xy,
+                       mesh->gclass_dev + off[c], (const double2*)draws + 2 * off[c], u + off[c],
+                       n, delta + off[c], status + off[c], members + off[c],
+                       (unsigned long long*)nullptr);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_group: launch");
 }
 
 int anneal_moves(MovableMesh* mesh, double* xy, const ObjectiveParams* params, double temperature,
@@ -1294,6 +1486,7 @@ void mesh_free(MovableMesh* mesh) {
   if (!mesh) return;
   if (mesh->sched) (void)hipFree(mesh->sched);
   if (mesh->class_dev) (void)hipFree(mesh->class_dev);
+  if (mesh->gclass_dev) (void)hipFree(mesh->gclass_dev);
   if (mesh->mem) (void)hipFree(mesh->mem);
   delete mesh;
 }

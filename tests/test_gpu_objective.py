@@ -569,3 +569,45 @@ def test_propose_at_scale(ccsp, grid, kind):
             assert np.array_equal(xy1[v], q)
         else:
             assert np.array_equal(xy1[v], mesh.xy[v])
+
+
+@pytest.mark.parametrize("state,temperature,eps", [("subdivided", 1e-3, 0.03),
+                                                   ("clustered", 1e-4, 0.03),
+                                                   ("clustered", 0.0, 0.1)])
+def test_group_sweep_equals_sequential_chain(ccsp, tiny, state, temperature, eps):
+    """A sweep of group moves (Sec. 3.2.3) equals the checker's chain over the same centres and
+    draws: positions bit for bit, statuses and group sizes equal, changes of f within rounding
+    (the GPU adds the members' changes one by one, the checker differences f as a whole)."""
+    mesh, om = tiny
+    p = ob.Params(eps)
+    xy0 = mesh.xy.copy() if state == "subdivided" else _clustered(mesh, om, ob.Params(0.03), 9)
+    rng = np.random.default_rng(13)
+    lam = 0.05
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        cls = gm.group_classes()
+        order = np.concatenate(cls)
+        assert len(cls) > len(gm.classes())
+        M = order.shape[0]
+        draws = np.zeros((M, 4))
+        draws[:, :2] = rng.standard_normal((M, 2))
+        draws[:, 2] = rng.random(M)
+        u = rng.random(M)
+        X = torch.from_numpy(xy0.copy()).to(DEV)
+        d, st, mem = gm.group_sweep(X, _params(ccsp, p), temperature, lam,
+                                    torch.from_numpy(draws).to(DEV), torch.from_numpy(u).to(DEV))
+        xy_g, st_g, df_g, mem_g = (X.cpu().numpy(), st.cpu().numpy(), d.cpu().numpy(),
+                                   mem.cpu().numpy())
+    xy_r, st_r, df_r, margin, size = ob.group_chain(om, xy0, p, temperature, lam, order,
+                                                    draws[:, :2], draws[:, 2], u)
+    valid = (st_r == ob.ACCEPTED) | (st_r == ob.REJECTED)
+    # a decision within rounding of its threshold is only comparable when both sides computed the
+    # same change exactly (a cluster whose edges all weigh 0 moves with a change of exactly 0)
+    close = valid & (margin <= 1e-10)
+    assert (df_g[close] == df_r[close]).all(), "a decision lies within rounding of its threshold"
+    assert np.array_equal(mem_g, size)
+    assert np.array_equal(st_g, st_r), np.nonzero(st_g != st_r)[0][:5]
+    assert np.array_equal(xy_g, xy_r)
+    fin = np.isfinite(df_r)
+    assert np.array_equal(np.isfinite(df_g), fin)
+    assert np.allclose(df_g[fin], df_r[fin], rtol=1e-9, atol=1e-12)
+    assert (st_r == ob.ACCEPTED).sum() > 5 and (size > 1).sum() > 20
