@@ -112,8 +112,9 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
              verbose=False) -> Result:
     """Turn a subdivided triangulation into a low-weight one (Secs. 3.1-3.4):
     1. `stages` stages of annealing: each one displacement sweep with the adaptive step scale
-       (Secs. 3.2, 3.2.2) and one sweep of a resampling, contraction or swap proposal in turn
-       (Secs. 3.2.4-3.2.6), at the stage's temperature and contraction length;
+       (Secs. 3.2, 3.2.2) and one sweep of resampling, contraction, swap or group moves in turn
+       (Secs. 3.2.3-3.2.6; group moves with the displacement's step scale), at the stage's
+       temperature and contraction length;
     2. contraction of the edges shorter than the final length (Sec. 3.4.1);
     3. polishing sweeps without fuzzy contraction alternated with greedy flips (the weight as
        energy, T = 0) (Sec. 3.4.2);
@@ -163,8 +164,14 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
                                uniforms(1, m), target=s.target)
             frac = int(a[0]) / m
             lam = lam * min(2.0, max(0.5, 1.0 + (frac - s.target)))
-            kind_k = ("resample", "contract", "swap")[k % 3]
-            _, st = gm.propose(X, p, temps[k], kind_k, proposal_draws(m, kind_k), uniforms(m))
+            kind_k = ("resample", "contract", "swap", "group")[k % 4]
+            if kind_k == "group":
+                r = proposal_draws(m, "group")
+                r[:, :2] = unit_draws(m)
+                _, st, _ = gm.group_sweep(X, p, temps[k], lam, r, uniforms(m))
+            else:
+                _, st = gm.propose(X, p, temps[k], kind_k, proposal_draws(m, kind_k),
+                                   uniforms(m))
             acc.append([frac, int((st == 1).sum().item()) / m])
             if verbose:
                 f = gm.eval(X, p).cpu().tolist()
