@@ -514,12 +514,17 @@ def proposal_chain(m: Mesh, xy, p: Params, temperature, kind, vid, r, u):
     return xy, st, df, margin
 
 
+GROUP_MAX = 16
+
+
 def group_members(m: Mesh, xy, c, d):
     """Sec. 3.2.3: the group of centre c, read as c and its movable neighbours (increasing id)
-    within distance d of it (lengths as everywhere)."""
+    within distance d of it (lengths as everywhere), at most GROUP_MAX members in all (the first
+    ones in that order)."""
     nb = m.nbr[m.nbr_off[c]:m.nbr_off[c + 1]]
     dist = incident_lengths(m, xy, c)
-    return [int(c)] + [int(w) for w, l in zip(nb, dist) if m.kind[w] != ORIGINAL and l <= d]
+    out = [int(c)] + [int(w) for w, l in zip(nb, dist) if m.kind[w] != ORIGINAL and l <= d]
+    return out[:GROUP_MAX]
 
 
 def group_area(m: Mesh, xy, members):

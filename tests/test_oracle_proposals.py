@@ -236,3 +236,14 @@ def test_group_moves_rigidly():
                     assert abs(after - before) <= 1e-12 * (1 + before)
                     seen += 1
     assert seen > 20
+
+
+def test_group_is_capped_at_sixteen_members():
+    """A centre with twenty movable neighbours within d keeps itself and its first fifteen."""
+    n = 20
+    ring = [[math.cos(2 * math.pi * k / n), math.sin(2 * math.pi * k / n)] for k in range(n)]
+    xy = np.array([[0.0, 0.0]] + ring)
+    tv = np.array([[0, 1 + k, 1 + (k + 1) % n] for k in range(n)])
+    m = ob.Mesh(tv, np.array([ob.FREE] * (n + 1)), np.zeros(n + 1, dtype=np.int64),
+                np.zeros((0, 2), dtype=np.int64))
+    assert ob.group_members(m, xy, 0, 2.0) == list(range(ob.GROUP_MAX))
