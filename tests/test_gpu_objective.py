@@ -611,3 +611,36 @@ def test_group_sweep_equals_sequential_chain(ccsp, tiny, state, temperature, eps
     assert np.array_equal(np.isfinite(df_g), fin)
     assert np.allclose(df_g[fin], df_r[fin], rtol=1e-9, atol=1e-12)
     assert (st_r == ob.ACCEPTED).sum() > 5 and (size > 1).sum() > 20
+
+
+def test_group_cap_equals_checker(ccsp):
+    """A free centre with twenty free neighbours: its group keeps sixteen members, on the GPU as in
+    the checker, and the sweep over the fan equals the checker's chain."""
+    n = 20
+    ring = [[math.cos(2 * math.pi * k / n), math.sin(2 * math.pi * k / n)] for k in range(n)]
+    xy0 = np.array([[0.0, 0.0]] + ring)
+    tv = np.array([[0, 1 + k, 1 + (k + 1) % n] for k in range(n)], dtype=np.int32)
+    kind = np.full(n + 1, ob.FREE, dtype=np.int32)
+    line = np.zeros(n + 1, dtype=np.int32)
+    prim_v = np.zeros((0, 2), dtype=np.int32)
+    om = ob.Mesh(tv, kind, line, prim_v)
+    p = ob.Params(2.0)
+    rng = np.random.default_rng(21)
+    with ccsp.MovableMesh(tv, kind, line, prim_v) as gm:
+        order = np.concatenate(gm.group_classes())
+        M = order.shape[0]
+        draws = np.zeros((M, 4))
+        draws[:, :2] = 0.02 * rng.standard_normal((M, 2))
+        draws[:, 2] = 0.99
+        u = rng.random(M)
+        X = torch.from_numpy(xy0.copy()).to(DEV)
+        d, st, mem = gm.group_sweep(X, _params(ccsp, p), 1e-3, 0.05,
+                                    torch.from_numpy(draws).to(DEV), torch.from_numpy(u).to(DEV))
+        xy_g, st_g, mem_g = X.cpu().numpy(), st.cpu().numpy(), mem.cpu().numpy()
+    xy_r, st_r, _, margin, size = ob.group_chain(om, xy0, p, 1e-3, 0.05, order, draws[:, :2],
+                                                 draws[:, 2], u)
+    assert size[list(order).index(0)] == ob.GROUP_MAX
+    assert np.array_equal(mem_g, size) and np.array_equal(st_g, st_r)
+    valid = (st_r == ob.ACCEPTED) | (st_r == ob.REJECTED)
+    assert (margin[valid] > 1e-10).all()
+    assert np.array_equal(xy_g, xy_r)
