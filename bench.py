@@ -74,6 +74,9 @@ def main():
                     help="JSON file of autotuned launch parameters (the library's table for this "
                          "GPU by default); workloads missing from it are tuned by measurement")
     ap.add_argument("--rays", type=int, default=0, help="override the ray count")
+    ap.add_argument("--scene", default="grid",
+                    help="pipeline: 'grid', or 'lines:N' for N random segments drawn as in the "
+                         "large scene")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the checker leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-objective", action="store_true",
@@ -115,7 +118,8 @@ def main():
         print(json.dumps(objective_leg("large", args.steps, args.warmup)), flush=True)
         return
     if args.workload == "pipeline":
-        sc = sg.make_scene("grid", seed=0)
+        sc = (sg.make_scene("grid", seed=0) if args.scene == "grid"
+              else sg.make_scene("large", seed=0, n_seg=int(args.scene.split(":")[1])))
         rays = sg.sample_rays(sc, args.rays or (1 << 20), seed=0)
         print(json.dumps(pipeline_leg(sc, rays, verbose=True)), flush=True)
         return
@@ -451,7 +455,7 @@ def grid_triangulations(sc, rays, scene, o, d, st, out, steps):
     return res
 
 
-def pipeline_leg(sc, rays, stages=24, verbose=False):
+def pipeline_leg(sc, rays, stages=24, verbose=False, schedule=None):
     """The paper's low-weight pipeline on a scene (``paper_2112_05570_amd.pipeline.optimise``:
     annealing with every single-vertex proposal, contraction, polishing and greedy flips, raised
     contraction lengths) from its CDT subdivided once (Sec. 3.5.2), then the CDT and the result
@@ -471,7 +475,7 @@ def pipeline_leg(sc, rays, stages=24, verbose=False):
     mesh = sg.subdivide(sc)
     t_sub = time.perf_counter() - t0
     r = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, size,
-                    pl.Schedule(stages=stages), verbose=verbose)
+                    schedule or pl.Schedule(stages=stages), verbose=verbose)
     res = {"subdivided": {"vertices": mesh.n_vertices, "triangles": mesh.n_triangles,
                           "weight": r.log["weight_start"], "subdivide_s": t_sub},
            "stages": stages, "anneal_s": r.log["anneal_s"],
@@ -502,6 +506,28 @@ def pipeline_leg(sc, rays, stages=24, verbose=False):
             torch.cuda.synchronize()
             walks[name] = (out.hit_prim.cpu().numpy(), out.hit_t.cpu().numpy(),
                            out.steps.cpu().numpy(), (time.perf_counter() - t1) / 5 * 1e3)
+    # flip-only annealing of the same CDT (flip_anneal, as in the low-weight leg), walked too
+    w_cdt = pl.weight(sc.tri_v, sc.xy)
+    mean_len = w_cdt / (sc.n_vertices + sc.n_triangles - 1)
+    temps = list(mean_len * np.geomspace(2.5, 0.005, 300)) + [0.0] * 100
+    fxy = torch.from_numpy(np.ascontiguousarray(sc.xy)).to(dev)
+    farr = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+            for a in (sc.tri_v, sc.tri_nbr, sc.tri_prim)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ccsp.flip_anneal(fxy, *farr, temps, 0)
+    ms_flip = (time.perf_counter() - t1) * 1e3
+    ftv, fnbr, fprim = (a.cpu().numpy() for a in farr)
+    with ccsp.Scene(sc.xy, ftv, fnbr, fprim, sc.prims) as s_flip:
+        st_f, stat_f = ccsp.locate(s_flip, o)
+        okf = bool((stat_f == 0).all().item())
+        out = ccsp.trace(s_flip, o, d, st_f, precision="fp32") if okf else None
+        torch.cuda.synchronize()
+        flip_only = {"weight": pl.weight(ftv, sc.xy), "anneal_ms": ms_flip,
+                     "mean_steps_per_ray": float(out.steps.double().mean().item()) if okf else None,
+                     "hits_identical": bool(torch.equal(out.hit_prim.cpu(),
+                                                        torch.from_numpy(walks["cdt"][0])))
+                     if okf else None}
     hp = walks["pipeline"][0]
     mapped = np.where(hp >= 0, sub_to_orig[np.maximum(hp, 0)], hp)
     same = mapped == walks["cdt"][0]
@@ -515,6 +541,7 @@ def pipeline_leg(sc, rays, stages=24, verbose=False):
                    "pipeline": {"weight": r.log["weight_final"], "triangles": int(r.tri_v.shape[0]),
                                 "mean_steps_per_ray": float(walks["pipeline"][2].mean()),
                                 "ms_per_trace": walks["pipeline"][3]},
+                   "flip_only": flip_only,
                    "same_primitive_hit": float(same.mean()),
                    "max_rel_t_difference": float(rel.max(initial=0.0))}
     return res
