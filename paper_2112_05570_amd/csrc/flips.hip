@@ -12,9 +12,9 @@
 //                accepted;
 //   flip_best    (per triangle) the accepted flip of highest (priority, canonical slot) among
 //                those that touch the triangle: the edges of the triangle and of its neighbours;
-//   flip_select  (per slot) keeps an accepted flip when it is the best of all its touched
+//   flip_select  (per triangle) keeps an accepted flip when it is the best of all its touched
 //                triangles, i.e. beats every other accepted flip touching one of them;
-//   flip_apply   (per slot) rewrites the kept flips, whose touched triangles are pairwise
+//   flip_apply   (per triangle) rewrites the kept flips, whose touched triangles are pairwise
 //                disjoint, counts them per block, and clears the slot's record for the next round.
 // The first three only read the triangulation, the fourth writes disjoint sets, so a round is the
 // same as applying its kept flips one after another. Priorities and uniforms come from a
@@ -102,6 +102,7 @@ flip_clear(int32_t* __restrict__ key, int64_t n, unsigned long long* __restrict_
   }
 }
 
+// One thread per slot: the slot of a candidate edge in the triangle of lower id does the work.
 __global__ void __launch_bounds__(kFlipThreads)
 flip_eval(Tri T, const double2* __restrict__ xy, double temperature, uint64_t seed, int round,
           int32_t* __restrict__ key) {
@@ -152,22 +153,27 @@ flip_best(Tri T, const int32_t* __restrict__ key, uint64_t seed, int round,
   best[x] = top;
 }
 
+// One thread per triangle, over its three slots.
 __global__ void __launch_bounds__(kFlipThreads)
 flip_select(Tri T, const int32_t* __restrict__ key, const int32_t* __restrict__ best,
             uint8_t* __restrict__ keep) {
-  const int s = blockIdx.x * kFlipThreads + threadIdx.x;
-  if (s >= 3 * T.nt) return;
-  bool win = key[s] == s;
-  if (win) {
-    const int t = s / 3, u = T.nbr[s];  // valid: flip_eval accepted the flip
-    win = best[t] == s && best[u] == s;
-    for (int k = 0; k < 3 && win; ++k) {
-      const int xt = T.nbr[3 * t + k], xu = T.nbr[3 * u + k];
-      if (valid_tri(T, xt) && best[xt] != s) win = false;
-      if (valid_tri(T, xu) && best[xu] != s) win = false;
+  const int t = blockIdx.x * kFlipThreads + threadIdx.x;
+  if (t >= T.nt) return;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int s = 3 * t + i;
+    bool win = key[s] == s;
+    if (win) {
+      const int u = T.nbr[s];  // valid: flip_eval accepted the flip
+      win = best[t] == s && best[u] == s;
+      for (int k = 0; k < 3 && win; ++k) {
+        const int xt = T.nbr[3 * t + k], xu = T.nbr[3 * u + k];
+        if (valid_tri(T, xt) && best[xt] != s) win = false;
+        if (valid_tri(T, xu) && best[xu] != s) win = false;
+      }
     }
+    keep[s] = win ? 1 : 0;
   }
-  keep[s] = win ? 1 : 0;
 }
 
 // Rewrites the flip of slot s; false if the adjacency is not symmetric (never for a kept flip).
@@ -213,14 +219,20 @@ __device__ __forceinline__ bool apply_one(const Tri& T, int s) {
   return true;
 }
 
+// One thread per triangle: a triangle holds at most one kept flip (kept flips touch disjoint
+// triangles), which its thread rewrites; the thread also clears the triangle's three records.
 __global__ void __launch_bounds__(kFlipThreads)
 flip_apply(Tri T, const uint8_t* __restrict__ keep, int32_t* __restrict__ key,
            unsigned long long* __restrict__ count) {
-  const int s = blockIdx.x * kFlipThreads + threadIdx.x;
+  const int t = blockIdx.x * kFlipThreads + threadIdx.x;
   bool flip = false;
-  if (s < 3 * T.nt) {
-    key[s] = -1;  // the record is not read again this round
-    flip = keep[s] && apply_one(T, s);
+  if (t < T.nt) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int s = 3 * t + i;
+      key[s] = -1;  // the record is not read again this round
+      if (!flip && keep[s]) flip = apply_one(T, s);
+    }
   }
   const int n = __syncthreads_count(flip);
   if (threadIdx.x == 0 && n > 0) atomicAdd(count + blockIdx.x % kCountLanes, (unsigned long long)n);
@@ -274,9 +286,9 @@ extern "C" int flip_anneal(int64_t n_vertices, const double* xy, int64_t n_trian
                        (const double2*)xy, temperature[r], seed, r, key);
     hipLaunchKernelGGL(ccsp::flip_best, dim3(tblocks), dim3(ccsp::kFlipThreads), 0, s, T, key, seed,
                        r, best);
-    hipLaunchKernelGGL(ccsp::flip_select, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, T, key,
+    hipLaunchKernelGGL(ccsp::flip_select, dim3(tblocks), dim3(ccsp::kFlipThreads), 0, s, T, key,
                        best, keep);
-    hipLaunchKernelGGL(ccsp::flip_apply, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, T, keep, key,
+    hipLaunchKernelGGL(ccsp::flip_apply, dim3(tblocks), dim3(ccsp::kFlipThreads), 0, s, T, keep, key,
                        count + (int64_t)r * ccsp::kCountLanes);
   }
   int rc = CCSP_OK;
