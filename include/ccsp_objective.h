@@ -256,6 +256,8 @@ int anneal_schedule(MovableMesh *mesh, double *xy, const ObjectiveParams *params
  *    different original edges;
  *  - the common neighbours of a and b are exactly the vertices opposite the edge;
  *  - it is not an interior edge with both ends on the hull;
+ *  - no remaining triangle around the survivor has all three vertices on one original edge (its
+ *    ORIGINAL ends or vertices CONSTRAINED to it);
  *  - the survivor has a position where every remaining triangle around it is strictly
  *    counter-clockwise (exact): an ORIGINAL vertex survives where it is, as does a CONSTRAINED
  *    one against a FREE one; otherwise the lower id survives at a + t (b - a), t tried as 1/2,

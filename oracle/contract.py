@@ -17,8 +17,11 @@ What is computed (paper Sec. 3.4.1, with the readings stated here):
   edge, tried at a + t (b - a) for t = 1/2, 1/4, 3/4, 0, 1 in that order.
 - A contraction is kept only if the topology stays a triangulation: the common neighbours of a and
   b are exactly the vertices opposite the edge (the link condition); an interior edge whose two
-  ends both lie on the hull is not contracted; and every remaining triangle of the merged vertex
-  is strictly counter-clockwise at the chosen position (exact orientation). The edge's one or two
+  ends both lie on the hull is not contracted; no remaining triangle of the merged vertex has all
+  three vertices on one original edge (its ends or vertices constrained to it: a triangle of zero
+  area in intent, whatever rounding makes of it, as the paper's strict convexity for flips also
+  excludes); and every remaining triangle of the merged vertex is strictly counter-clockwise at
+  the chosen position (exact orientation). The edge's one or two
   triangles disappear and the other vertex is replaced by the survivor everywhere.
 - At the end, surviving vertices are renumbered in increasing old id and surviving triangles kept
   in increasing old id, each with its vertex order (the removed vertex replaced by the survivor).
@@ -107,6 +110,15 @@ def contract(tri_v, kind, line, prim_v, xy, eps):
             dx, dy = xy[b][0] - ax, xy[b][1] - ay
             cands = [(ax + t * dx, ay + t * dy) for t in TRIES]
         rest = sorted((star[a] | star[b]) - set(shared))
+
+        def on_edge(v, k):
+            return (kind[v] == CONSTRAINED and line[v] == k) or (kind[v] == ORIGINAL
+                                                               and v in prim_v[k])
+        for t in rest:
+            tv = [s if w in (a, b) else w for w in tris[t]]
+            ks = {line[w] for w in tv if kind[w] == CONSTRAINED}
+            if any(all(on_edge(w, k) for w in tv) for k in ks):
+                return False
         for P in cands:
             ok = True
             for t in rest:

@@ -6,7 +6,9 @@
 // higher id) and tries each that is still an edge and still shorter; passes repeat until one
 // contracts nothing. A contraction of (a, b) needs: the original geometry to allow it; the common
 // neighbours of a and b to be exactly the vertices opposite the edge (otherwise the result would
-// not be a triangulation); not both ends on the hull for an interior edge; and a position of the
+// not be a triangulation); not both ends on the hull for an interior edge; no remaining triangle
+// with all three vertices on one original edge (zero area in intent, whatever rounding makes of
+// the constrained vertices' positions); and a position of the
 // survivor at which every remaining triangle around it is strictly counter-clockwise (exact).
 // The survivor is the vertex with fewer degrees of freedom (original over constrained over free),
 // kept where it is; two vertices of one kind merge into the lower id at a + t (b - a), t tried as
@@ -101,6 +103,23 @@ struct Contractor {
     return s;
   }
 
+  bool on_edge(int v, int k) const {
+    if (kind[v] == CCSP_VERTEX_CONSTRAINED) return line[v] == k;
+    return kind[v] == CCSP_VERTEX_ORIGINAL && (prim[k][0] == v || prim[k][1] == v);
+  }
+
+  // Whether triangle t, with a and b read as s, would have all three vertices on one original edge.
+  bool flat_on_original(int t, int a, int b, int s) const {
+    int tv[3];
+    for (int k = 0; k < 3; ++k) tv[k] = (tri[t][k] == a || tri[t][k] == b) ? s : tri[t][k];
+    for (int k = 0; k < 3; ++k) {
+      if (kind[tv[k]] != CCSP_VERTEX_CONSTRAINED) continue;
+      const int ln = line[tv[k]];
+      if (on_edge(tv[0], ln) && on_edge(tv[1], ln) && on_edge(tv[2], ln)) return true;
+    }
+    return false;
+  }
+
   bool try_edge(int a, int b) {
     if (!kinds_allow(a, b)) return false;
     const std::vector<int32_t> shared = shared_triangles(a, b);
@@ -153,6 +172,8 @@ struct Contractor {
         if (!std::binary_search(shared.begin(), shared.end(), t)) rest.push_back(t);
     std::sort(rest.begin(), rest.end());
     rest.erase(std::unique(rest.begin(), rest.end()), rest.end());
+    for (int t : rest)
+      if (flat_on_original(t, a, b, s)) return false;
     for (const auto& P : cands) {
       bool ok = true;
       for (int t : rest) {

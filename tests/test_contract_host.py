@@ -78,3 +78,38 @@ def test_walk_arrays_of_a_subdivided_mesh():
         for p in (prims[j, :2], prims[j, 2:]):
             cross = (b[0] - a[0]) * (p[1] - a[1]) - (b[1] - a[1]) * (p[0] - a[0])
             assert abs(cross) <= 1e-12 * np.hypot(*(b - a)) * (1 + np.abs(p).max())
+
+
+@pytest.mark.parametrize("seed,eps", [(1, 0.02), (4, 0.1)])
+def test_walk_arrays_after_contraction(seed, eps):
+    """A clustered mesh contracted by the library still gives valid walk arrays: every
+    constrained edge of the result is its own primitive on its original one, and the checker's
+    validator accepts the triangulation."""
+    import oracle
+    from paper_2112_05570_amd import pipeline as pl
+    mesh, xy = _clustered_mesh(seed, eps)
+    r = ccsp.contract(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, xy, eps)
+    nbr, prim, prims, s2o = pl.walk_arrays(r["tri_v"], r["kind"], r["line"], mesh.prim_v, r["xy"])
+    tri = oracle.Triangulation(r["xy"], r["tri_v"], nbr, prim, prims)
+    assert oracle.validate(tri) == ""
+    # each original primitive is covered by its sub-primitives end to end
+    sc = sg.make_scene("tiny")
+    for k in range(sc.n_prims):
+        sub = prims[s2o == k]
+        ends = np.concatenate([sub[:, :2], sub[:, 2:]])
+        u, c = np.unique(ends, axis=0, return_counts=True)
+        assert (c == 1).sum() == 2  # a chain: only its two ends appear once
+    assert pl.weight(r["tri_v"], r["xy"]) < pl.weight(mesh.tri_v, xy)
+
+
+def test_flat_triangle_case_matches():
+    """The hand-built case of a contraction that would leave a triangle flat on an original edge:
+    the library refuses it too."""
+    xy = np.array([[0, 0], [3, 0], [1, -2.0 ** -60], [0.01, 0.005], [1.5, 1], [1.5, -1]])
+    tv = np.array([[0, 2, 3], [2, 1, 3], [0, 3, 4], [3, 1, 4], [0, 5, 2], [2, 5, 1]])
+    kind = np.array([0, 0, 1, 2, 0, 0])
+    line = np.zeros(6, dtype=np.int64)
+    prim_v = np.array([[0, 1]])
+    r = ccsp.contract(tv, kind, line, prim_v, xy, 0.05)
+    o = ct.contract(tv, kind, line, prim_v, xy, 0.05)
+    assert _same(r, o) and r["contracted"] == 0

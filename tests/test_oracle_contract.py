@@ -129,3 +129,24 @@ def test_contracted_mesh_is_a_valid_triangulation():
     w0 = sum(ct._len(xy, a, b) for a, b in _edges(mesh.tri_v))
     w1 = sum(ct._len(xy2, a, b) for a, b in e)
     assert w1 < w0
+
+
+def test_no_triangle_flat_on_an_original_edge():
+    """Segment A-B (original edge 0) with C constrained to it, 2^-60 below the line as rounding
+    may leave it. Contracting the short edge A-G would turn (C, B, G) into (C, B, A): three
+    vertices on the original edge, a triangle of zero area in intent that exact orientation alone
+    accepts. It is refused."""
+    va, vb, vc, vg, vf, vy = 0, 1, 2, 3, 4, 5
+    xy = np.array([[0, 0], [3, 0], [1, -2.0 ** -60], [0.01, 0.005], [1.5, 1], [1.5, -1]])
+    tv = np.array([[va, vc, vg], [vc, vb, vg], [va, vg, vf], [vg, vb, vf], [va, vy, vc],
+                   [vc, vy, vb]])
+    for tri in tv:
+        assert oracle.orient(*xy[tri]) > 0
+    assert oracle.orient(xy[vc], xy[vb], xy[va]) > 0  # the sliver would pass the orientation test
+    kind = np.array([O, O, C, F, O, O])
+    line = np.array([0, 0, 0, 0, 0, 0])
+    prim_v = np.array([[va, vb]])
+    short = [k for k in _edges(tv) if ct._len(xy, *k) < 0.05]
+    assert short == [(va, vg)]
+    t2, _, _, xy2, _, n = ct.contract(tv, kind, line, prim_v, xy, 0.05)
+    assert n == 0 and np.array_equal(t2, tv)
