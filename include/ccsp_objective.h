@@ -291,6 +291,12 @@ int mesh_contract(const MeshDesc *desc, const double *xy, double eps, int32_t *t
  * (its two triangles and their neighbours). The applied flips are independent, so the round is
  * the same as applying them one after another. After a flip, t holds (a, b, d) and u holds
  * (a, d, c), in that vertex order, with neighbours and primitive ids following their edges.
+ * With vertex_line (DEVICE, n_vertices int32: the original edge of each Steiner vertex on one,
+ * -1 for the other vertices) and prim_v (DEVICE, 2 * n_prims int32: the ends of each original
+ * edge), a flip is also refused when one of its new triangles has all three vertices on one
+ * original edge (its ends or Steiner vertices on it): zero area in intent, which the exact test
+ * lets through when rounding leaves a Steiner vertex off its line (Sec. 3.2.7 asks for strict
+ * convexity against exactly this). vertex_line NULL: no such test (prim_v and n_prims ignored).
  * flips_out[r] (HOST) receives the number of flips of round r; a round with none at T = 0 leaves
  * no flip that would lower the weight. The triangulation must be valid (as load_triangulation
  * checks); triangle and vertex ids read from it are range-checked. n_rounds <= 2^20. Allocates
@@ -298,8 +304,9 @@ int mesh_contract(const MeshDesc *desc, const double *xy, double eps, int32_t *t
  * queued on `stream` back to back and the call synchronises it once, at the end.
  */
 int flip_anneal(int64_t n_vertices, const double *xy, int64_t n_triangles, int32_t *tri_v,
-                int32_t *tri_nbr, int32_t *tri_prim, int32_t n_rounds, const double *temperature,
-                uint64_t seed, int64_t *flips_out, void *stream);
+                int32_t *tri_nbr, int32_t *tri_prim, const int32_t *vertex_line, int64_t n_prims,
+                const int32_t *prim_v, int32_t n_rounds, const double *temperature, uint64_t seed,
+                int64_t *flips_out, void *stream);
 
 /* mesh_free: release the mesh (after its calls have completed). NULL is ignored. */
 void mesh_free(MovableMesh *mesh);

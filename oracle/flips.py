@@ -22,6 +22,12 @@ total edge length, the weight the paper minimises):
 
 After a flip of (t, i) with neighbour u: t holds (a, b, d) and u holds (a, d, c), each listed from
 a in that order; neighbours and constraint ids follow their edges.
+
+With Steiner vertices on the original edges (line[v] = the original edge of such a vertex, -1 for
+the others; prim_v[k] = the two ends of original edge k), a flip is also refused when one of its
+new triangles has all three vertices on one original edge: zero area in intent, which the exact
+test accepts only because rounding leaves the constrained vertex off its line, and which the
+paper's strict convexity excludes.
 """
 from __future__ import annotations
 
@@ -91,7 +97,18 @@ def touched(nbr, s):
     return out
 
 
-def test_flip(xy, tv, nbr, s, temperature, u):
+def flat(tri, line, prim_v):
+    """Whether the three vertices of tri lie on one original edge (see the module docstring)."""
+    if line is None:
+        return False
+    for w in tri:
+        k = line[w]
+        if k >= 0 and all(line[x] == k or x in prim_v[k] for x in tri):
+            return True
+    return False
+
+
+def test_flip(xy, tv, nbr, s, temperature, u, line=None, prim_v=None):
     """(accepted, change) of the flip of slot s against the current triangulation, not applied."""
     t, i = divmod(s, 3)
     ut = int(nbr[t, i])
@@ -100,18 +117,21 @@ def test_flip(xy, tv, nbr, s, temperature, u):
     d = tv[ut, j]
     if orient(xy[a], xy[b], xy[d]) <= 0 or orient(xy[a], xy[d], xy[c]) <= 0:
         return False, 0.0
+    if flat((a, b, d), line, prim_v) or flat((a, d, c), line, prim_v):
+        return False, 0.0
     change = _len(xy, a, d) - _len(xy, b, c)
     return change < 0.0 or (temperature > 0.0 and u < math.exp(-change / temperature)), change
 
 
-def chosen(tv, nbr, prim, seed, rnd, xy=None, temperature=None):
+def chosen(tv, nbr, prim, seed, rnd, xy=None, temperature=None, line=None, prim_v=None):
     """The round's independent flips: candidates (with xy and temperature given: those whose flip
     would be accepted) whose (priority, slot) beats every other such candidate whose touched
     triangles meet theirs."""
     cand = candidates(tv, nbr, prim)
     if xy is not None:
         cand = [s for s in cand
-                if test_flip(xy, tv, nbr, s, temperature, draws(seed, rnd, s)[1])[0]]
+                if test_flip(xy, tv, nbr, s, temperature, draws(seed, rnd, s)[1], line,
+                             prim_v)[0]]
     pr = {s: draws(seed, rnd, s)[0] for s in cand}
     tri_of = {}
     for s in cand:
@@ -132,9 +152,9 @@ def chosen(tv, nbr, prim, seed, rnd, xy=None, temperature=None):
     return out
 
 
-def try_flip(xy, tv, nbr, prim, s, temperature, u):
+def try_flip(xy, tv, nbr, prim, s, temperature, u, line=None, prim_v=None):
     """Test and (if accepted) apply the flip of slot s. Returns (accepted, change of weight)."""
-    ok, change = test_flip(xy, tv, nbr, s, temperature, u)
+    ok, change = test_flip(xy, tv, nbr, s, temperature, u, line, prim_v)
     if not ok:
         return False, change
     t, i = divmod(s, 3)
@@ -159,9 +179,12 @@ def try_flip(xy, tv, nbr, prim, s, temperature, u):
     return True, change
 
 
-def anneal(xy, tri_v, tri_nbr, tri_prim, temperatures, seed):
+def anneal(xy, tri_v, tri_nbr, tri_prim, temperatures, seed, line=None, prim_v=None):
     """Rounds of flips at the given temperatures, applied one after another. Returns the new
     (tri_v, tri_nbr, tri_prim) and the accepted flips of each round."""
+    if line is not None:
+        line = [int(k) for k in line]
+        prim_v = [tuple(map(int, p)) for p in np.asarray(prim_v).reshape(-1, 2)]
     xy = np.asarray(xy, dtype=np.float64)
     tv = np.array(tri_v, dtype=np.int64).reshape(-1, 3)
     nbr = np.array(tri_nbr, dtype=np.int64).reshape(-1, 3)
@@ -169,8 +192,8 @@ def anneal(xy, tri_v, tri_nbr, tri_prim, temperatures, seed):
     counts = []
     for r, temp in enumerate(temperatures):
         n = 0
-        for s in chosen(tv, nbr, prim, seed, r, xy, float(temp)):
-            ok, _ = try_flip(xy, tv, nbr, prim, s, float(temp), draws(seed, r, s)[1])
+        for s in chosen(tv, nbr, prim, seed, r, xy, float(temp), line, prim_v):
+            ok, _ = try_flip(xy, tv, nbr, prim, s, float(temp), draws(seed, r, s)[1], line, prim_v)
             assert ok
             n += 1
         counts.append(n)

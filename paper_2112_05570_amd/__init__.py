@@ -437,11 +437,14 @@ class MovableMesh:
             pass
 
 
-def flip_anneal(xy, tri_v, tri_nbr, tri_prim, temperatures, seed, stream=None):
+def flip_anneal(xy, tri_v, tri_nbr, tri_prim, temperatures, seed, vertex_line=None, prim_v=None,
+                stream=None):
     """Annealing by edge flips with the weight as energy (see ``flip_anneal`` in
     ccsp_objective.h): xy (V,2) float64 and tri_v, tri_nbr, tri_prim (T,3) int32 CUDA tensors, the
-    latter three updated in place; one round per temperature. Returns the flips of each round
-    (numpy). Synchronous."""
+    latter three updated in place; one round per temperature. With Steiner vertices on original
+    edges, vertex_line (V,) int32 (original edge of each such vertex, -1 otherwise) and prim_v
+    (P,2) int32 CUDA tensors keep flips from making triangles flat on an original edge. Returns
+    the flips of each round (numpy). Synchronous."""
     import torch
     for a, dt in ((tri_v, torch.int32), (tri_nbr, torch.int32), (tri_prim, torch.int32)):
         if not a.is_cuda or a.dtype != dt or a.dim() != 2 or a.shape[1] != 3 or not a.is_contiguous():
@@ -451,11 +454,19 @@ def flip_anneal(xy, tri_v, tri_nbr, tri_prim, temperatures, seed, stream=None):
         raise ValueError("xy must be a contiguous float64 CUDA tensor (V,2)")
     if tri_nbr.shape != tri_v.shape or tri_prim.shape != tri_v.shape:
         raise ValueError("tri_v, tri_nbr and tri_prim must have the same shape")
+    lp, np_, pp = 0, 0, 0
+    if vertex_line is not None:
+        if (not vertex_line.is_cuda or vertex_line.dtype != torch.int32
+                or tuple(vertex_line.shape) != (xy.shape[0],) or not vertex_line.is_contiguous()
+                or prim_v is None or not prim_v.is_cuda or prim_v.dtype != torch.int32
+                or prim_v.dim() != 2 or prim_v.shape[1] != 2 or not prim_v.is_contiguous()):
+            raise ValueError("vertex_line (V,) and prim_v (P,2): contiguous int32 CUDA tensors")
+        lp, np_, pp = vertex_line.data_ptr(), prim_v.shape[0], prim_v.data_ptr()
     temps = np.ascontiguousarray(temperatures, dtype=np.float64)
     counts = np.zeros(temps.shape[0], dtype=np.int64)
     p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
     B.flip_anneal(xy.shape[0], xy.data_ptr(), tri_v.shape[0], tri_v.data_ptr(), tri_nbr.data_ptr(),
-                  tri_prim.data_ptr(), temps.shape[0], p(temps), int(seed), p(counts),
+                  tri_prim.data_ptr(), lp, np_, pp, temps.shape[0], p(temps), int(seed), p(counts),
                   _stream(stream))
     return counts
 

@@ -176,7 +176,8 @@ _lib.anneal_propose.restype = _I
 _lib.anneal_schedule.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_int32, _P, _P,
                                  ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P]
 _lib.anneal_schedule.restype = _I
-_lib.flip_anneal.argtypes = [_I64, _P, _I64, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_uint64, _P, _P]
+_lib.flip_anneal.argtypes = [_I64, _P, _I64, _P, _P, _P, _P, _I64, _P, ctypes.c_int32, _P,
+                             ctypes.c_uint64, _P, _P]
 _lib.flip_anneal.restype = _I
 _lib.mesh_contract.argtypes = [ctypes.POINTER(MeshDesc), _P, ctypes.c_double, _P, _P, _P, _P, _P,
                                _P, _P, _P]
@@ -345,11 +346,11 @@ def anneal_schedule(mesh: int, xy: int, params: ObjectiveParams, n_sweeps: int, 
 
 
 def flip_anneal(n_vertices: int, xy: int, n_triangles: int, tri_v: int, tri_nbr: int,
-                tri_prim: int, n_rounds: int, temperature: int, seed: int, flips_out: int,
-                stream: int = 0) -> None:
+                tri_prim: int, vertex_line: int, n_prims: int, prim_v: int, n_rounds: int,
+                temperature: int, seed: int, flips_out: int, stream: int = 0) -> None:
     _check(_lib.flip_anneal(n_vertices, _P(xy), n_triangles, _P(tri_v), _P(tri_nbr), _P(tri_prim),
-                            n_rounds, _P(temperature), seed & ((1 << 64) - 1), _P(flips_out),
-                            _P(stream)))
+                            _P(vertex_line), n_prims, _P(prim_v), n_rounds, _P(temperature),
+                            seed & ((1 << 64) - 1), _P(flips_out), _P(stream)))
 
 
 def mesh_contract(desc: MeshDesc, xy: int, eps: float, tri_out: int, n_triangles_out: int,

@@ -62,6 +62,9 @@ struct Tri {
   int32_t* prim;
   int32_t nt;
   int32_t nv;
+  const int32_t* line;    // per vertex: its original edge if it is a Steiner vertex on one, else -1;
+  const int32_t* prim_v;  // the two end vertices of each original edge; both null when not given
+  int32_t np;
 };
 
 __device__ __forceinline__ int orient_sign(double2 a, double2 b, double2 c) {
@@ -86,6 +89,26 @@ __device__ __forceinline__ int back_of(const Tri& T, int w, int t) {
 
 __device__ __forceinline__ bool valid_tri(const Tri& T, int x) { return x >= 0 && x < T.nt; }
 __device__ __forceinline__ bool valid_vertex(const Tri& T, int x) { return x >= 0 && x < T.nv; }
+
+__device__ __forceinline__ bool on_original(const Tri& T, int v, int k) {
+  const int lv = T.line[v];
+  if (lv >= 0) return lv == k;
+  return T.prim_v[2 * k] == v || T.prim_v[2 * k + 1] == v;
+}
+
+// Whether the triangle (x, y, z) has all three vertices on one original edge: zero area in intent,
+// which the exact convexity test lets through when rounding leaves a Steiner vertex off its line.
+__device__ __forceinline__ bool flat_on_original(const Tri& T, int x, int y, int z) {
+  if (!T.line) return false;
+  const int ks[3] = {T.line[x], T.line[y], T.line[z]};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const int k = ks[m];
+    if (k >= 0 && k < T.np && on_original(T, x, k) && on_original(T, y, k) && on_original(T, z, k))
+      return true;
+  }
+  return false;
+}
 
 // Flip counts of a round are spread over this many counters, a block adding into one of them.
 constexpr int kCountLanes = 64;
@@ -119,7 +142,8 @@ flip_eval(Tri T, const double2* __restrict__ xy, double temperature, uint64_t se
     if (!valid_vertex(T, a) || !valid_vertex(T, b) || !valid_vertex(T, c) || !valid_vertex(T, d))
       return;
     const double2 pa = xy[a], pb = xy[b], pc = xy[c], pd = xy[d];
-    if (orient_sign(pa, pb, pd) > 0 && orient_sign(pa, pd, pc) > 0) {
+    if (orient_sign(pa, pb, pd) > 0 && orient_sign(pa, pd, pc) > 0 &&
+        !flat_on_original(T, a, b, d) && !flat_on_original(T, a, d, c)) {
       const double change = seg_len(pa, pd) - seg_len(pb, pc);
       if (change < 0.0 ||
           (temperature > 0.0 && uniform(seed, round, s) < exp(-change / temperature)))
@@ -242,9 +266,10 @@ flip_apply(Tri T, const uint8_t* __restrict__ keep, int32_t* __restrict__ key,
 }  // namespace ccsp
 
 extern "C" int flip_anneal(int64_t n_vertices, const double* xy, int64_t n_triangles,
-                           int32_t* tri_v, int32_t* tri_nbr, int32_t* tri_prim, int32_t n_rounds,
-                           const double* temperature, uint64_t seed, int64_t* flips_out,
-                           void* stream) {
+                           int32_t* tri_v, int32_t* tri_nbr, int32_t* tri_prim,
+                           const int32_t* vertex_line, int64_t n_prims, const int32_t* prim_v,
+                           int32_t n_rounds, const double* temperature, uint64_t seed,
+                           int64_t* flips_out, void* stream) {
   using ccsp::set_last_error;
   auto fail = [](int code, const char* msg) {
     set_last_error(msg);
@@ -256,6 +281,10 @@ extern "C" int flip_anneal(int64_t n_vertices, const double* xy, int64_t n_trian
   if (n_triangles >= (int64_t(1) << 29) || n_vertices >= (int64_t(1) << 31))
     return fail(CCSP_E_ARG, "flip_anneal: triangulation too large for 32-bit slots");
   if (n_rounds > (1 << 20)) return fail(CCSP_E_ARG, "flip_anneal: more than 2^20 rounds");
+  if (vertex_line && (n_prims <= 0 || n_prims >= (int64_t(1) << 31) || !prim_v))
+    return fail(CCSP_E_ARG, "flip_anneal: vertex_line needs the original edges' ends");
+  if (((uintptr_t)vertex_line & 3) != 0 || ((uintptr_t)prim_v & 3) != 0)
+    return fail(CCSP_E_ARG, "flip_anneal: misaligned buffer");
   if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)tri_v & 3) != 0 || ((uintptr_t)tri_nbr & 3) != 0 ||
       ((uintptr_t)tri_prim & 3) != 0)
     return fail(CCSP_E_ARG, "flip_anneal: misaligned buffer");
@@ -276,7 +305,14 @@ extern "C" int flip_anneal(int64_t n_vertices, const double* xy, int64_t n_trian
   auto* best = key + slots;
   auto* keep = (uint8_t*)(best + n_triangles);
   hipStream_t s = (hipStream_t)stream;
-  const ccsp::Tri T{tri_v, tri_nbr, tri_prim, (int32_t)n_triangles, (int32_t)n_vertices};
+  const ccsp::Tri T{tri_v,
+                    tri_nbr,
+                    tri_prim,
+                    (int32_t)n_triangles,
+                    (int32_t)n_vertices,
+                    vertex_line,
+                    vertex_line ? prim_v : nullptr,
+                    vertex_line ? (int32_t)n_prims : 0};
   const unsigned blocks = (unsigned)((slots + ccsp::kFlipThreads - 1) / ccsp::kFlipThreads);
   const unsigned tblocks = (unsigned)((n_triangles + ccsp::kFlipThreads - 1) / ccsp::kFlipThreads);
   hipLaunchKernelGGL(ccsp::flip_clear, dim3(blocks), dim3(ccsp::kFlipThreads), 0, s, key, slots,

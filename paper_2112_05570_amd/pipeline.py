@@ -183,6 +183,7 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
     log["weight_annealed"] = weight(tri_v, xy_opt)
 
     pol = objective_params(epss[-1], None, *mu, polish=True)
+    pv_dev = torch.from_numpy(prim_v).to(dev)
 
     def polish_and_flip(tv, kd, ln, pos, rounds, seed):
         nflips = 0
@@ -203,7 +204,9 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
                 break
             nbr, prim, _, _ = walk_arrays(tv, kd, ln, prim_v, pos)
             arrs = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (tv, nbr, prim)]
-            nflips += int(flip_anneal(Xp, *arrs, [0.0] * s.flip_rounds, seed + rnd).sum())
+            vline = torch.from_numpy(np.where(kd == CONSTRAINED, ln, -1).astype(np.int32)).to(dev)
+            nflips += int(flip_anneal(Xp, *arrs, [0.0] * s.flip_rounds, seed + rnd, vline,
+                                      pv_dev).sum())
             tv = arrs[0].cpu().numpy()
         return tv, pos, nflips
 

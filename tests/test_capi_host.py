@@ -220,13 +220,15 @@ def test_flip_anneal_rejects_before_any_device_call():
     cnt = np.zeros(2, np.int64)
     p = lambda a: a.ctypes.data
     with pytest.raises(B.CcspError, match="null argument"):
-        B.flip_anneal(4, 0, 2, p(tri), p(tri), p(tri), 2, p(temps), 0, p(cnt))
+        B.flip_anneal(4, 0, 2, p(tri), p(tri), p(tri), 0, 0, 0, 2, p(temps), 0, p(cnt))
     with pytest.raises(B.CcspError, match="null argument"):
-        B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), 2, 0, 0, p(cnt))
+        B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), 0, 0, 0, 2, 0, 0, p(cnt))
     with pytest.raises(B.CcspError, match="temperatures"):
-        B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), 2, p(temps), 0, p(cnt))
+        B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), 0, 0, 0, 2, p(temps), 0, p(cnt))
     with pytest.raises(B.CcspError, match="misaligned"):
-        B.flip_anneal(4, p(xy) + 8, 2, p(tri), p(tri), p(tri), 1, p(temps), 0, p(cnt))
+        B.flip_anneal(4, p(xy) + 8, 2, p(tri), p(tri), p(tri), 0, 0, 0, 1, p(temps), 0, p(cnt))
     with pytest.raises(B.CcspError, match="too large"):
-        B.flip_anneal(4, p(xy), 1 << 29, p(tri), p(tri), p(tri), 1, p(temps), 0, p(cnt))
-    B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), 0, 0, 0, 0)
+        B.flip_anneal(4, p(xy), 1 << 29, p(tri), p(tri), p(tri), 0, 0, 0, 1, p(temps), 0, p(cnt))
+    with pytest.raises(B.CcspError, match="original edges' ends"):
+        B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), p(tri), 0, 0, 1, p(temps), 0, p(cnt))
+    B.flip_anneal(4, p(xy), 2, p(tri), p(tri), p(tri), 0, 0, 0, 0, 0, 0, 0)

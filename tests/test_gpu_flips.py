@@ -163,3 +163,57 @@ def test_grid_walk_on_annealed(ccsp, grid_annealed):
     ref = oracle.walk(oracle.Triangulation.of(an), rays.o[idx], rays.d[idx],
                       start_an[keep][idx].astype(np.int32))
     assert np.array_equal(res[1][0][idx], ref[0]) and np.array_equal(res[1][2][idx], ref[2])
+
+
+def _flat_case():
+    A, B, Cv, X, Y = 0, 1, 2, 3, 4
+    xy = np.array([[0, 0], [3, 0], [1.5, -2.0 ** -60], [1.5, 0.05], [1.5, -1]])
+    tv = np.array([[X, A, Cv], [X, Cv, B], [Cv, A, Y], [Cv, Y, B]], dtype=np.int32)
+    nbr = np.array([[2, 1, -1], [3, -1, 0], [-1, 3, 0], [-1, 1, 2]], dtype=np.int32)
+    prim = np.array([[0, -1, -1], [0, -1, -1], [-1, -1, 0], [-1, 0, -1]], dtype=np.int32)
+    line = np.array([-1, -1, 0, -1, -1], dtype=np.int32)
+    return xy, tv, nbr, prim, line, np.array([[A, B]], dtype=np.int32)
+
+
+def _gpu_lines(ccsp, xy, tv, nbr, prim, temps, seed, line=None, pv=None):
+    X = torch.from_numpy(np.ascontiguousarray(xy)).to(DEV)
+    arrs = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(DEV)
+            for a in (tv, nbr, prim)]
+    extra = () if line is None else (torch.from_numpy(line).to(DEV), torch.from_numpy(pv).to(DEV))
+    counts = ccsp.flip_anneal(X, *arrs, temps, seed, *extra)
+    return [a.cpu().numpy() for a in arrs], counts
+
+
+def test_flat_flip_refused_with_original_edges(ccsp):
+    """The hand-built quad whose flip would make a triangle flat on an original edge: the GPU
+    flips it without the vertices' original edges and refuses it with them, as the checker."""
+    xy, tv, nbr, prim, line, pv = _flat_case()
+    (tv1, _, _), c1 = _gpu_lines(ccsp, xy, tv, nbr, prim, [1e9], 5)
+    assert list(c1) == [1] and not np.array_equal(tv1, tv)
+    (tv2, _, _), c2 = _gpu_lines(ccsp, xy, tv, nbr, prim, [1e9, 1e9], 5, line, pv)
+    assert list(c2) == [0, 0] and np.array_equal(tv2, tv)
+    assert fl.anneal(xy, tv, nbr, prim, [1e9, 1e9], 5, line, pv)[3] == [0, 0]
+
+
+@pytest.mark.parametrize("seed,eps", [(1, 0.02), (4, 0.1)])
+def test_matches_checker_with_steiner_vertices(ccsp, seed, eps):
+    """A clustered mesh contracted by the library (Steiner vertices on the original edges, each
+    constrained edge its own primitive): GPU flips with the vertices' original edges equal the
+    checker's bit for bit, and so do flips without them."""
+    import sys
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from test_oracle_contract import _clustered_mesh
+    from paper_2112_05570_amd import pipeline as pl
+    mesh, xy0 = _clustered_mesh(seed, eps)
+    r = ccsp.contract(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, xy0, eps)
+    nbr, prim, _, _ = pl.walk_arrays(r["tri_v"], r["kind"], r["line"], mesh.prim_v, r["xy"])
+    line = np.where(r["kind"] == 1, r["line"], -1).astype(np.int32)
+    pv = np.ascontiguousarray(mesh.prim_v, dtype=np.int32)
+    side = 1.0
+    temps = list(side * np.geomspace(2e-2, 1e-4, 8)) + [0.0] * 8
+    for with_lines in (True, False):
+        args = (line, pv) if with_lines else (None, None)
+        (tv, nb, pr), counts = _gpu_lines(ccsp, r["xy"], r["tri_v"], nbr, prim, temps, seed, *args)
+        rv, rn, rp, rc = fl.anneal(r["xy"], r["tri_v"], nbr, prim, temps, seed, *args)
+        assert list(counts) == list(rc) and sum(rc) > 0
+        assert np.array_equal(tv, rv) and np.array_equal(nb, rn) and np.array_equal(pr, rp)

@@ -87,3 +87,33 @@ def test_annealing_keeps_a_valid_triangulation_and_converges():
         convex = oracle.orient(sc.xy[a], sc.xy[b], sc.xy[d]) > 0 and \
             oracle.orient(sc.xy[a], sc.xy[d], sc.xy[c]) > 0
         assert not convex or fl._len(sc.xy, a, d) >= fl._len(sc.xy, b, c)
+
+
+def test_no_flip_makes_a_triangle_flat_on_an_original_edge():
+    """Segment A-B (original edge 0) through constrained C, 2^-60 below the line. The quad
+    A, C, B, X is strictly convex by exact orientation only through that rounding; flipping X-C to
+    A-B would make the triangle (A, C, B) of zero area in intent. At a temperature that accepts any
+    valid flip, it happens without the vertices' original edges and is refused with them."""
+    A, B, Cv, X, Y = 0, 1, 2, 3, 4
+    xy = np.array([[0, 0], [3, 0], [1.5, -2.0 ** -60], [1.5, 0.05], [1.5, -1]])
+    tv = np.array([[X, A, Cv], [X, Cv, B], [Cv, A, Y], [Cv, Y, B]])
+    nbr = np.array([[2, 1, -1], [3, -1, 0], [-1, 3, 0], [-1, 1, 2]])
+    prim = np.array([[0, -1, -1], [0, -1, -1], [-1, -1, 0], [-1, 0, -1]])
+    for ti in range(4):
+        assert oracle.orient(*xy[tv[ti]]) > 0
+        for i in range(3):
+            u = nbr[ti, i]
+            if u >= 0:  # edge i is (v[i+1], v[i+2]); the neighbour holds it reversed
+                k = [k for k in range(3) if nbr[u, k] == ti][0]
+                assert (tv[u, (k + 1) % 3], tv[u, (k + 2) % 3]) == \
+                    (tv[ti, (i + 2) % 3], tv[ti, (i + 1) % 3])
+                assert prim[u, k] == prim[ti, i]
+    s = 1  # edge (C, X) in triangle 0, the lower id of its two triangles
+    assert oracle.orient(xy[A], xy[Cv], xy[B]) > 0  # the new triangle passes the exact test
+    assert fl.test_flip(xy, tv, nbr, s, 1e9, 0.5)[0]
+    line = np.array([-1, -1, 0, -1, -1])
+    pv = np.array([[A, B]])
+    assert fl.test_flip(xy, tv, nbr, s, 1e9, 0.5, line, [tuple(p) for p in pv]) == (False, 0.0)
+    tv2, nbr2, prim2, counts = fl.anneal(xy, tv, nbr, prim, [1e9, 1e9], 5, line, pv)
+    assert counts == [0, 0] and np.array_equal(tv2, tv)
+    assert fl.anneal(xy, tv, nbr, prim, [1e9], 5)[3] == [1]
