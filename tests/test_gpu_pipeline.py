@@ -83,3 +83,39 @@ def test_same_seed_same_result(ccsp, run):
     r2 = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, sc.box[1] - sc.box[0],
                      sched)
     assert np.array_equal(r2.tri_v, r.tri_v) and np.array_equal(r2.xy, r.xy)
+
+
+@pytest.mark.parametrize("name,kw,seed", [("tiny", {}, 7), ("large", dict(n_seg=2000), 1)])
+def test_other_scenes_and_seeds(ccsp, name, kw, seed):
+    """The pipeline on another seed and on an 8,002-triangle random-lines scene: valid result,
+    original vertices kept, lighter than the subdivided input, and the GPU walk on it equal to the
+    checker's on a sample of located rays, hitting the CDT's primitives."""
+    from paper_2112_05570_amd import pipeline as pl
+    sc = sg.make_scene(name, **kw)
+    mesh = sg.subdivide(sc)
+    size = sc.box[1] - sc.box[0]
+    sched = pl.Schedule(stages=8, t0_rel=1e-3, t1_rel=1e-5, e0_rel=5e-3, e1_rel=5e-4,
+                        outer_max=3, flip_rounds=32, seed=seed)
+    r = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, size, sched)
+    nbr, prim, prims, s2o = pl.walk_arrays(r.tri_v, r.kind, r.line, mesh.prim_v, r.xy)
+    tri = oracle.Triangulation(r.xy, r.tri_v, nbr, prim, prims)
+    assert oracle.validate(tri) == ""
+    assert (r.kind == 0).sum() == sc.n_vertices and np.array_equal(r.xy[r.kind == 0], sc.xy)
+    assert r.log["weight_final"] < r.log["weight_start"]
+    rays = sg.sample_rays(sc, 8192, seed=seed)
+    with ccsp.Scene(r.xy, r.tri_v, nbr, prim, prims) as s_opt:
+        o = torch.from_numpy(rays.o).to(DEV)
+        d = torch.from_numpy(rays.d).to(DEV)
+        st, stat = ccsp.locate(s_opt, o)
+        keep = torch.nonzero(stat == 0).squeeze(1)
+        got = ccsp.trace(s_opt, o[keep].contiguous(), d[keep].contiguous(),
+                         st[keep].contiguous(), precision="fp64")
+        torch.cuda.synchronize()
+        g = [x.cpu().numpy() for x in (got.hit_prim, got.hit_t, got.steps)]
+    k = keep.cpu().numpy()
+    assert k.shape[0] > 8000
+    ref = oracle.walk(tri, rays.o[k], rays.d[k], st.cpu().numpy()[k])
+    assert all(np.array_equal(a, b) for a, b in zip(g, ref))
+    cdt = oracle.walk(oracle.Triangulation.of(sc), rays.o[k], rays.d[k], rays.start[k])
+    mapped = np.where(g[0] >= 0, s2o[np.maximum(g[0], 0)], g[0])
+    assert (mapped == cdt[0]).mean() > 0.999
