@@ -49,12 +49,12 @@ def _L():
         lib.oracle_incircle.restype = I
         lib.oracle_t.argtypes = [P, P, P]
         lib.oracle_t.restype = ctypes.c_double
-        lib.oracle_walk.argtypes = [P, I64, P, P, P, P, P, P, I]
+        lib.oracle_walk.argtypes = [P, I64, P, P, P, I64, P, P, P, I]
         lib.oracle_brute_edges.argtypes = [P, I64, P, P, P, P, P, I]
         lib.oracle_brute_prims.argtypes = [I64, P, I64, P, P, P, P, I]
         lib.oracle_validate.argtypes = [P, I, ctypes.c_char_p, I]
         lib.oracle_locate.argtypes = [P, I64, P, P, P, I]
-        lib.oracle_bounce.argtypes = [P, I64, P, P, P, ctypes.c_int32, P, P, P, P, P, I]
+        lib.oracle_bounce.argtypes = [P, I64, P, P, P, ctypes.c_int32, I64, P, P, P, P, P, I]
         lib.oracle_num_threads.restype = I
         _lib = lib
     return _lib
@@ -109,13 +109,14 @@ def _outs(n):
     return np.empty(n, np.int32), np.empty(n, np.float64), np.empty(n, np.int32)
 
 
-def walk(tri: Triangulation, o, d, start, threads: int = 0):
-    """The walk of Sec. 5.1 ray by ray. Returns (prim, t, steps)."""
+def walk(tri: Triangulation, o, d, start, threads: int = 0, max_steps: int = 0):
+    """The walk of Sec. 5.1 ray by ray. Returns (prim, t, steps). A ray whose walk would enter
+    more than max_steps triangles ends with -2 and steps = max_steps (0: the triangle count)."""
     o, d, start = _c(o, np.float64), _c(d, np.float64), _c(start, np.int32)
     n = start.shape[0]
     prim, t, steps = _outs(n)
-    _L().oracle_walk(ctypes.byref(tri.c), n, _p(o), _p(d), _p(start), _p(prim), _p(t), _p(steps),
-                     int(threads))
+    _L().oracle_walk(ctypes.byref(tri.c), n, _p(o), _p(d), _p(start), int(max_steps), _p(prim),
+                     _p(t), _p(steps), int(threads))
     return prim, t, steps
 
 
@@ -140,16 +141,19 @@ def brute_prims(prims, o, d, threads: int = 0):
     return prim, t, st
 
 
-def bounce(tri: Triangulation, o, d, start, max_bounces: int, threads: int = 0):
+def bounce(tri: Triangulation, o, d, start, max_bounces: int, threads: int = 0,
+           max_steps: int = 0):
     """The walk continued by specular reflections (Sec. 5.2's secondary rays). Returns
-    (prim, t, steps, hits, face) per ray; see oracle.c."""
+    (prim, t, steps, hits, face) per ray; see oracle.c. max_steps limits each segment as in
+    walk()."""
     o, d, start = _c(o, np.float64), _c(d, np.float64), _c(start, np.int32)
     n = start.shape[0]
     prim, t, steps = _outs(n)
     hits = np.empty(n, np.int32)
     face = np.empty(n, np.int32)
     _L().oracle_bounce(ctypes.byref(tri.c), n, _p(o), _p(d), _p(start), int(max_bounces),
-                       _p(prim), _p(t), _p(steps), _p(hits), _p(face), int(threads))
+                       int(max_steps), _p(prim), _p(t), _p(steps), _p(hits), _p(face),
+                       int(threads))
     return prim, t, steps, hits, face
 
 

@@ -25,7 +25,10 @@
  * is an integer times a power of two, summed here limb by limb.
  *
  * Entry points:
- *   oracle_walk        the walk itself, step by step in the paper's order;
+ *   oracle_walk        the walk itself, step by step in the paper's order, with a step limit:
+ *                      a ray whose walk would enter more than max_steps triangles (at most
+ *                      the triangle count, which an exact walk never exceeds) stops with -2 and
+ *                      steps = max_steps (a guard the library exposes; not in the paper);
  *   oracle_brute_edges the definition above, by brute force over every triangulation edge;
  *   oracle_brute_prims hit_prim and t by brute force over every primitive (no triangulation);
  *   oracle_validate    triangulation checks (orientation, adjacency, Euler, constrained
@@ -269,7 +272,7 @@ double oracle_t(const double *o, const double *d, const double *seg) {
 static const double *VX(const oracle_tri_t *m, int v) { return m->xy + 2 * (int64_t)v; }
 
 static void walk_one(const oracle_tri_t *m, const double *o, const double *d, int32_t start,
-                     int32_t *prim, double *t, int32_t *steps) {
+                     int64_t max_steps, int32_t *prim, double *t, int32_t *steps) {
   *prim = -3;
   *t = INFINITY;
   *steps = 0;
@@ -286,7 +289,6 @@ static void walk_one(const oracle_tri_t *m, const double *o, const double *d, in
     if (!left[(i + 1) % 3] && left[(i + 2) % 3]) exit_edge = i;
   if (exit_edge < 0) return;
   int64_t count = 1;
-  const int64_t guard = m->nt + 1;
   for (;;) {
     const int64_t slot = 3 * (int64_t)tri + exit_edge;
     if (m->tri_prim[slot] >= 0) { /* the exit edge is scene geometry: closest hit */
@@ -299,16 +301,18 @@ static void walk_one(const oracle_tri_t *m, const double *o, const double *d, in
       *prim = -1;
       break;
     }
+    /* the step guard: the walk would enter triangle max_steps + 1 */
+    if (count >= max_steps) {
+      *prim = -2;
+      break;
+    }
     /* continue in the neighbour, entered through its edge back to tri */
     int back = -1;
     for (int j = 0; j < 3; ++j)
       if (m->tri_nbr[3 * (int64_t)nb + j] == tri) back = j;
     if (back < 0) return;
     tri = nb;
-    if (++count > guard) {
-      *prim = -2;
-      break;
-    }
+    ++count;
     tv = m->tri_v + 3 * (int64_t)tri;
     /* the entry edge's endpoints are LEFT (first) and RIGHT (second); only the vertex across
      * decides between the two remaining edges */
@@ -318,13 +322,15 @@ static void walk_one(const oracle_tri_t *m, const double *o, const double *d, in
 }
 
 int oracle_walk(const oracle_tri_t *m, int64_t n, const double *o, const double *d,
-                const int32_t *start, int32_t *prim, double *t, int32_t *steps, int nthreads) {
+                const int32_t *start, int64_t max_steps, int32_t *prim, double *t,
+                int32_t *steps, int nthreads) {
+  const int64_t limit = (max_steps <= 0 || max_steps > m->nt) ? m->nt : max_steps;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(static, 4096)
 #endif
   for (int64_t r = 0; r < n; ++r)
-    walk_one(m, o + 2 * r, d + 2 * r, start[r], prim + r, t + r, steps + r);
+    walk_one(m, o + 2 * r, d + 2 * r, start[r], limit, prim + r, t + r, steps + r);
   (void)nthreads;
   return 0;
 }
@@ -356,8 +362,8 @@ static void reflect(const double *o, const double *d, const double *seg, double 
  * segments), the reflections made and the last segment's hit face (4 * triangle + edge, -1 if
  * it did not hit). */
 static void bounce_one(const oracle_tri_t *m, const double *o_in, const double *d_in,
-                       int32_t start, int32_t max_bounces, int32_t *prim, double *t,
-                       int32_t *steps, int32_t *hits, int32_t *face) {
+                       int32_t start, int32_t max_bounces, int64_t max_steps, int32_t *prim,
+                       double *t, int32_t *steps, int32_t *hits, int32_t *face) {
   *prim = -3;
   *t = INFINITY;
   *steps = 0;
@@ -375,7 +381,7 @@ static void bounce_one(const oracle_tri_t *m, const double *o_in, const double *
     if (!left[(i + 1) % 3] && left[(i + 2) % 3]) exit_edge = i;
   if (exit_edge < 0) return;
   int64_t count = 1, seg_count = 1;
-  const int64_t guard = m->nt;
+  const int64_t guard = max_steps;
   int32_t nb = 0;
   for (;;) {
     const int64_t slot = 3 * (int64_t)tri + exit_edge;
@@ -407,15 +413,15 @@ static void bounce_one(const oracle_tri_t *m, const double *o_in, const double *
       *prim = -1;
       break;
     }
+    if (seg_count >= guard) { /* this segment would enter triangle max_steps + 1 */
+      *prim = -2;
+      break;
+    }
     int back = -1;
     for (int j = 0; j < 3; ++j)
       if (m->tri_nbr[3 * (int64_t)nbr + j] == tri) back = j;
     if (back < 0) return;
     tri = nbr;
-    if (seg_count >= guard) {
-      *prim = -2;
-      break;
-    }
     ++count;
     ++seg_count;
     tv = m->tri_v + 3 * (int64_t)tri;
@@ -426,15 +432,16 @@ static void bounce_one(const oracle_tri_t *m, const double *o_in, const double *
 }
 
 int oracle_bounce(const oracle_tri_t *m, int64_t n, const double *o, const double *d,
-                  const int32_t *start, int32_t max_bounces, int32_t *prim, double *t,
-                  int32_t *steps, int32_t *hits, int32_t *face, int nthreads) {
+                  const int32_t *start, int32_t max_bounces, int64_t max_steps, int32_t *prim,
+                  double *t, int32_t *steps, int32_t *hits, int32_t *face, int nthreads) {
+  const int64_t limit = (max_steps <= 0 || max_steps > m->nt) ? m->nt : max_steps;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 256)
 #endif
   for (int64_t r = 0; r < n; ++r)
-    bounce_one(m, o + 2 * r, d + 2 * r, start[r], max_bounces, prim + r, t + r, steps + r,
-               hits + r, face + r);
+    bounce_one(m, o + 2 * r, d + 2 * r, start[r], max_bounces, limit, prim + r, t + r,
+               steps + r, hits + r, face + r);
   (void)nthreads;
   return 0;
 }

@@ -159,6 +159,31 @@ def split_segments(sc: Scene) -> Scene:
                  name=sc.name + "+split", meta=meta)
 
 
+def open_hull(sc: Scene, sides=(0, 1, 2, 3)) -> Scene:
+    """The same triangulation with the given box sides (0 bottom, 1 right, 2 top, 3 left) no
+    longer scene geometry: their hull edges become unconstrained, so a ray reaching them leaves
+    the triangulation without a hit. The opened sides are dropped from the primitives and the
+    kept sides renumbered after the segments, in their order."""
+    S = sc.n_prims - 4
+    if S < 0 or sc.tri_prim is None:
+        raise ValueError("open_hull needs a triangulated scene whose last four primitives are the box sides")
+    opened = sorted(set(int(k) for k in sides))
+    if any(k < 0 or k > 3 for k in opened):
+        raise ValueError("box sides are numbered 0..3")
+    kept = [k for k in range(4) if k not in opened]
+    remap = np.arange(sc.n_prims + 1, dtype=np.int64) - 1  # index p + 1 -> new id of p (-1 -> -1)
+    for k in opened:
+        remap[S + k + 1] = -1
+    for j, k in enumerate(kept):
+        remap[S + k + 1] = S + j
+    tp = remap[sc.tri_prim.astype(np.int64) + 1].astype(np.int32)
+    prims = np.ascontiguousarray(np.concatenate([sc.prims[:S], sc.prims[S + np.array(kept, dtype=np.int64)]])
+                                 if kept else sc.prims[:S])
+    meta = dict(sc.meta, open_sides=tuple(opened))
+    return Scene(sc.xy, prims, sc.seg_v, sc.box, sc.tri_v, sc.tri_nbr, np.ascontiguousarray(tp),
+                 sc.name + "+open" + "".join(str(k) for k in opened), meta)
+
+
 ORIGINAL, CONSTRAINED, FREE = 0, 1, 2
 
 

@@ -7,7 +7,11 @@
   vertices, along edges and through box corners;
 * Cauchy-Crofton: the mean number of interior edges crossed by isotropic lines equals
   2 * (interior edge length) / (box perimeter) (the weight/cost relation of Sec. 1.4);
-* invariance of hit and distance across two triangulations of one scene.
+* invariance of hit and distance across two triangulations of one scene;
+* the miss outcome (a hull edge that is not scene geometry): a hand-derived fixture, and brute
+  force on scenes whose box sides are opened, degenerate rays included;
+* the step guard against the unlimited walk: rays that need more triangles than the limit stop
+  there, every other ray is unchanged.
 """
 import json
 import math
@@ -190,3 +194,97 @@ def test_invariance_cdt_vs_annealed(tiny_scene, tiny_rays):
     p2, t2, s2 = oracle.walk(tri_a, r.o[keep], r.d[keep], start[keep])
     assert (p1 == p2).all() and np.array_equal(t1, t2)
     assert (s1 != s2).any()
+
+
+def _golden(name):
+    g = json.load(open(os.path.join(GOLDEN, name)))
+    tri = oracle.Triangulation(g["xy"], g["tri_v"], g["tri_nbr"], g["tri_prim"], g["prims"])
+    o = np.array([r["o"] for r in g["rays"]], float)
+    d = np.array([r["d"] for r in g["rays"]], float)
+    s = np.array([r["start"] for r in g["rays"]], np.int32)
+    return g, tri, o, d, s
+
+
+def _tval(x):
+    return math.inf if x == "inf" else float(x)
+
+
+def test_golden_open_sides_miss_and_guard():
+    g, tri, o, d, s = _golden("unit_square_open_sides.json")
+    assert oracle.validate(tri, delaunay=True) == ""
+    prim, t, steps = oracle.walk(tri, o, d, s)
+    assert prim.tolist() == [r["prim"] for r in g["rays"]]
+    assert t.tolist() == [_tval(r["t"]) for r in g["rays"]]
+    assert steps.tolist() == [r["steps"] for r in g["rays"]]
+    assert (prim == -1).sum() == 5
+    pb, tb, sb, status = oracle.brute_edges(tri, o, d)
+    assert status == 0
+    assert np.array_equal(pb, prim) and np.array_equal(tb, t) and np.array_equal(sb, steps)
+    # the guard: a limit of one triangle
+    prim, t, steps = oracle.walk(tri, o, d, s, max_steps=g["guard_max_steps"])
+    assert prim.tolist() == [r["prim"] for r in g["guard"]]
+    assert t.tolist() == [_tval(r["t"]) for r in g["guard"]]
+    assert steps.tolist() == [r["steps"] for r in g["guard"]]
+    # zero bounces is the walk; a reflection off the bottom side then leaves through the top
+    pr, tr, sr, hits, face = oracle.bounce(tri, o, d, s, 0)
+    p0, t0, s0 = oracle.walk(tri, o, d, s)
+    assert np.array_equal(pr, p0) and np.array_equal(tr, t0) and np.array_equal(sr, s0)
+    pr, tr, sr, hits, face = oracle.bounce(tri, o[3:4], d[3:4], s[3:4], 2)
+    # o = (0.75, 0.25) straight down: hits the bottom at (0.75, 0) in triangle 0, reflects
+    # straight up, crosses the diagonal at (0.75, 0.75) and leaves through the open top side
+    assert pr.tolist() == [-1] and hits.tolist() == [1] and sr.tolist() == [3] and face.tolist() == [-1]
+    assert math.isinf(tr[0])
+
+
+@pytest.mark.parametrize("sides", [(0, 1, 2, 3), (1, 2), (3,)])
+def test_open_hull_walk_equals_brute_force(tiny_scene, tiny_rays, sides):
+    sc = sg.open_hull(tiny_scene, sides)
+    tri = _tri(sc)
+    assert oracle.validate(tri, delaunay=True) == ""
+    r = tiny_rays.slice(0, 8192)
+    p, t, s = oracle.walk(tri, r.o, r.d, r.start)
+    miss = p == -1
+    assert miss.sum() > 100 and (p >= -1).all()
+    assert np.isinf(t[miss]).all() and np.isfinite(t[~miss]).all()
+    pb, tb, sb, status = oracle.brute_edges(tri, r.o, r.d)
+    assert status == 0
+    assert np.array_equal(p, pb) and np.array_equal(s, sb) and np.array_equal(t, tb)
+    # brute force over the remaining primitives alone: -1 exactly when no primitive is ahead
+    pp, tp, status = oracle.brute_prims(sc.prims, r.o, r.d)
+    assert status == 0 and np.array_equal(pp, p) and np.array_equal(tp, t)
+    # hits on primitives that stayed scene geometry are unchanged by opening the others
+    p0, t0, s0 = oracle.walk(_tri(tiny_scene), r.o, r.d, r.start)
+    S = tiny_scene.n_prims - 4
+    seg_hit = p0 < S
+    assert np.array_equal(p[seg_hit], p0[seg_hit]) and np.array_equal(t[seg_hit], t0[seg_hit])
+    assert np.array_equal(s[seg_hit], s0[seg_hit])
+
+
+@settings(max_examples=25, deadline=None)
+@given(st.integers(0, 2**31 - 1))
+def test_open_hull_degenerate_rays(seed):
+    rng = np.random.default_rng(seed)
+    sc = sg.open_hull(_integer_scene(rng, int(rng.integers(3, 14))),
+                      tuple(k for k in range(4) if rng.random() < 0.6) or (0,))
+    tri = _tri(sc)
+    o, d, start = _degenerate_rays(sc, rng, 200)
+    p, t, s = oracle.walk(tri, o, d, start)
+    pb, tb, sb, status = oracle.brute_edges(tri, o, d)
+    assert status == 0
+    assert np.array_equal(p, pb) and np.array_equal(s, sb) and np.array_equal(t, tb)
+
+
+@pytest.mark.parametrize("limit", [1, 2, 5, 17])
+def test_guard_against_unlimited_walk(tiny_scene, tiny_rays, limit):
+    tri = _tri(sg.open_hull(tiny_scene, (1, 2)))
+    r = tiny_rays.slice(0, 8192)
+    p, t, s = oracle.walk(tri, r.o, r.d, r.start)
+    pg, tg, sg_ = oracle.walk(tri, r.o, r.d, r.start, max_steps=limit)
+    long = s > limit
+    assert long.any() and (~long).any()
+    assert np.array_equal(pg[~long], p[~long]) and np.array_equal(tg[~long], t[~long])
+    assert np.array_equal(sg_[~long], s[~long])
+    assert (pg[long] == -2).all() and (sg_[long] == limit).all() and np.isinf(tg[long]).all()
+    # a limit at or above the triangle count changes nothing
+    pn, tn, sn = oracle.walk(tri, r.o, r.d, r.start, max_steps=tri.tri_v.shape[0])
+    assert np.array_equal(pn, p) and np.array_equal(tn, t) and np.array_equal(sn, s)
