@@ -31,8 +31,8 @@
  * Errors: every call returns CCSP_OK (0) or a negative code; last_error() then describes the
  * failure (thread-local, valid until the next call on the same thread). Per-ray outcomes are
  * data: hit_prim >= 0 hit; CCSP_RAY_MISS (-1) left through an unconstrained hull edge, hit_t=+inf;
- * CCSP_RAY_GUARD (-2) more steps than triangles (impossible with exact decisions, kept as a
- * guard); CCSP_RAY_BAD (-3) start_tri out of range or the origin is not strictly inside it (then
+ * CCSP_RAY_GUARD (-2) the walk reached the step limit (by default the triangle count, which an
+ * exact walk never exceeds; TuneParams.step_limit lowers it) with another triangle to enter; CCSP_RAY_BAD (-3) start_tri out of range or the origin is not strictly inside it (then
  * steps = 0). A ray whose origin is not strictly inside start_tri is a precondition violation;
  * without CCSP_TRACE_VALIDATE it may also end as a hit or miss along a wrong path, but never reads
  * out of bounds.
@@ -108,7 +108,13 @@ typedef struct {
                               starting in its own eighth of the rays (default 8) */
   int32_t bin;             /* trace_rays ray order: 1 = bucket binning by origin cell (default),
                               2 = radix sort by start triangle; ignored by trace_batch */
-  int32_t reserved;        /* must be 0 */
+  int32_t step_limit;      /* not a launch parameter: the step guard's limit. A walk that would
+                              enter one triangle more than this ends with CCSP_RAY_GUARD and
+                              steps = step_limit (trace_bounces: the limit applies to each segment
+                              and steps still counts all segments). 0 or more than the triangle
+                              count: the triangle count, which an exact walk never exceeds. Applies
+                              to every item of a batch; never stored in the tuning cache, so a
+                              TuneParams with only this field set takes the default launch. */
 } TuneParams;
 
 /*

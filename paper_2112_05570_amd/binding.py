@@ -64,7 +64,7 @@ class TuneParams(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("tile_rays", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("refill_min", ctypes.c_int32),
                 ("tiles_per_claim", ctypes.c_int32), ("xcd_chunks", ctypes.c_int32),
-                ("bin", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bin", ctypes.c_int32), ("step_limit", ctypes.c_int32)]
 
     def as_tuple(self):
         return tuple(getattr(self, f) for f, _ in self._fields_[:-1])

@@ -175,14 +175,15 @@ int device_state(DeviceState** out) {
     e = hipDeviceGetAttribute(&s.cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
     void* p = nullptr;
-    const size_t bytes = sizeof(unsigned long long) * (kCounterSlots + 4) + 256;
+    const size_t bytes = sizeof(unsigned long long) * (kCounterSlots + 4) +
+                         sizeof(int) * (kCounterSlots / kClaimChunks);
     e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return fail(CCSP_E_OOM, "workspace allocation failed: %s", hipGetErrorString(e));
     e = hipMemset(p, 0, bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMemset");
     s.ws.counters = static_cast<unsigned long long*>(p);
     s.ws.stats = s.ws.counters + kCounterSlots;
-    s.ws.errflag = reinterpret_cast<int*>(s.ws.stats + 4);
+    s.ws.errflags = reinterpret_cast<int*>(s.ws.stats + 4);
     e = hipEventCreateWithFlags(&s.bin_free, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     s.init = true;
@@ -195,11 +196,14 @@ int device_state(DeviceState** out) {
 constexpr int64_t kBinMinRays = 1 << 16;
 constexpr int64_t kBinMinTriangles = 1 << 18;
 
-// Tile counters of the next eager launch: a ring of kCounterSlots / kClaimChunks groups, so that
-// launches in flight on different streams never share (captured graphs have their own).
-unsigned long long* next_counters(DeviceState* ds) {
+// Tile counters (and validation flag) of the next eager launch: a ring of kCounterSlots /
+// kClaimChunks groups, so that launches in flight on different streams never share (captured
+// graphs have their own).
+unsigned long long* next_counters(DeviceState* ds, int** errflag = nullptr) {
   const unsigned groups = kCounterSlots / kClaimChunks;
-  return ds->ws.counters + (size_t)(ds->next_counter.fetch_add(1) % groups) * kClaimChunks;
+  const unsigned g = ds->next_counter.fetch_add(1) % groups;
+  if (errflag) *errflag = ds->ws.errflags + g;
+  return ds->ws.counters + (size_t)g * kClaimChunks;
 }
 
 // Grow the per-device ray binning scratch to hold n rays (allocates only when n exceeds every
@@ -363,7 +367,7 @@ int check_tune(const TuneParams* tp) {
     return fail(CCSP_E_ARG, "negative tuning field");
   if (tp->waves_per_cu > 64) return fail(CCSP_E_ARG, "waves_per_cu %d must be at most 64", tp->waves_per_cu);
   if (tp->bin < 0 || tp->bin > 2) return fail(CCSP_E_ARG, "bin %d must be 0, 1 or 2", tp->bin);
-  if (tp->reserved != 0) return fail(CCSP_E_ARG, "reserved tuning field must be 0");
+  if (tp->step_limit < 0) return fail(CCSP_E_ARG, "negative step_limit");
   return CCSP_OK;
 }
 
@@ -824,7 +828,9 @@ static int trace_common(const Triangulation* tri, const double* o_xy, const doub
   io.hits = bounces;
   io.face = hit_face;
   io.max_bounces = max_bounces;
-  unsigned long long* counter = next_counters(ds);
+  io.max_steps = tune ? tune->step_limit : 0;
+  int* errflag = nullptr;
+  unsigned long long* counter = next_counters(ds, &errflag);
   hipError_t e;
   StageEvents* tev = nullptr;
   if (precision & CCSP_TRACE_TIMED) {
@@ -852,10 +858,10 @@ static int trace_common(const Triangulation* tri, const double* o_xy, const doub
     if (e != hipSuccess) return hip_fail(e, "ray binning");
   }
   if (validate) {
-    e = hipMemsetAsync(ds->ws.errflag, 0, sizeof(int), st);
+    e = hipMemsetAsync(errflag, 0, sizeof(int), st);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
   }
-  e = launch_walk(tri->dev, io, mode, count, validate, cfg, counter, ds->ws, st,
+  e = launch_walk(tri->dev, io, mode, count, validate, cfg, counter, errflag, ds->ws, st,
                   tev ? tev->ev[1] : nullptr, tev ? tev->ev[2] : nullptr);
   if (e != hipSuccess) return hip_fail(e, "walk launch");
   if (tev) {
@@ -870,7 +876,7 @@ static int trace_common(const Triangulation* tri, const double* o_xy, const doub
   }
   if (validate) {
     int flag = 0;
-    e = hipMemcpyAsync(&flag, ds->ws.errflag, sizeof(int), hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(&flag, errflag, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "validation read-back");
     if (flag) return fail(CCSP_E_BAD_RAY, "a ray's origin is not strictly inside its start triangle, its start "
@@ -960,6 +966,7 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
     b.scene = it.scene->dev;
     b.rays = RaysDev{reinterpret_cast<const double2*>(it.o_xy), reinterpret_cast<const double2*>(it.d_xy),
                      it.start_tri, it.hit_prim, it.hit_t, it.steps, it.n};
+    b.rays.max_steps = tune ? tune->step_limit : 0;
     b.tile_begin = tb;
     tb += (it.n + cfg.tile - 1) / cfg.tile;
   }
@@ -1071,7 +1078,9 @@ int tune_cache_set(int32_t n_items, int64_t total_rays, int64_t total_triangles,
   if (rc) return rc;
   const bool single = n_items == 1 && !(precision & CCSP_TRACE_GRAPH);
   std::lock_guard<std::mutex> lk(ds->tune_mu);
-  ds->tuned[tune_key(n_items, total_rays, total_triangles, precision, single)] = *tune;
+  TuneParams t = *tune;
+  t.step_limit = 0;  // a limit of the walk, not a launch parameter of the shape
+  ds->tuned[tune_key(n_items, total_rays, total_triangles, precision, single)] = t;
   return CCSP_OK;
 }
 

@@ -118,6 +118,9 @@ struct RaysDev {
   int32_t* hits;
   int32_t* face;
   int32_t max_bounces;
+  // the step guard: a walk (a segment of a continued ray) that would enter one triangle more than
+  // this ends with CCSP_RAY_GUARD; 0 or more than the triangle count means the triangle count
+  int32_t max_steps;
 };
 
 // One item of a batched launch: the scene, its rays and where its tiles start in the
@@ -141,7 +144,8 @@ struct LaunchCfg {
 struct Workspace {
   unsigned long long* counters;  // ring of kCounterSlots tile counters
   unsigned long long* stats;     // 4 diagnostic counters
-  int* errflag;                  // set by validating launches
+  int* errflags;                 // ring of kCounterSlots / kClaimChunks validation flags, one per
+                                 // launch slot of the counter ring
 };
 constexpr int kCounterSlots = 4096;
 constexpr int kClaimChunks = 8;  // tile counters per launch (one per XCD)
@@ -158,9 +162,10 @@ hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void
 // A single trace: the walk kernel, then the finishing pass (finish_rays). `walk_begin` and
 // `walk_end`, if not null, are recorded on `stream` right before and after the walk kernel itself
 // (after the small counter reset, before the finishing pass), so that they time it alone.
+// `errflag` (validating launches only) receives 1 if a ray fails its precondition.
 hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
-                       const LaunchCfg& cfg, unsigned long long* counter, const Workspace& ws,
-                       hipStream_t stream, hipEvent_t walk_begin = nullptr,
+                       const LaunchCfg& cfg, unsigned long long* counter, int* errflag,
+                       const Workspace& ws, hipStream_t stream, hipEvent_t walk_begin = nullptr,
                        hipEvent_t walk_end = nullptr);
 
 // A batch: the walk kernel over every item's tiles, then finish_batch.

@@ -231,7 +231,9 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   const Slot32* slot32 = sc_arg.slot32;
   const Pair32* pair32 = sc_arg.pair32;
   const Pair64* pair64 = sc_arg.pair64;
+  // the step guard's limit: the triangle count, or the caller's smaller limit
   int ntri = sc_arg.ntri;
+  if (!BATCH && io_arg.max_steps > 0 && io_arg.max_steps < ntri) ntri = io_arg.max_steps;
 
   // wave-uniform tile state
   int64_t tbase = 0;
@@ -312,6 +314,8 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             pair32 = sc.pair32;
             pair64 = sc.pair64;
             ntri = sc.ntri;
+            const int lim = batch.items[item].rays.max_steps;
+            if (lim > 0 && lim < ntri) ntri = lim;
             org_x = sc.org_x;
             org_y = sc.org_y;
           }
@@ -581,28 +585,29 @@ size_t walk_lds_bytes(int mode, const LaunchCfg& cfg) {
 template <int MODE, int TPL, bool COUNT, bool VALIDATE, bool BATCH, bool BOUNCE>
 static hipError_t go(const SceneDev& sc, const RaysDev& io, ItemRef br, int64_t total_tiles,
                      const LaunchCfg& cfg, size_t lds, unsigned long long* counter,
-                     const Workspace& ws, hipStream_t stream) {
+                     const Workspace& ws, int* errflag, hipStream_t stream) {
   hipLaunchKernelGGL((walk_persistent<MODE, TPL, COUNT, VALIDATE, BATCH, BOUNCE>), dim3(cfg.grid),
                      dim3(cfg.wg), lds, stream, sc, io, br, total_tiles, counter, cfg.refill_min,
-                     cfg.chunks, cfg.group, ws.stats, ws.errflag);
+                     cfg.chunks, cfg.group, ws.stats, errflag);
   return hipGetLastError();
 }
 
 template <int MODE, bool COUNT, bool VALIDATE, bool BATCH, bool BOUNCE = false>
 static hipError_t pick_tile(const SceneDev& sc, const RaysDev& io, ItemRef br, int64_t total_tiles,
                             const LaunchCfg& cfg, size_t lds, unsigned long long* counter,
-                            const Workspace& ws, hipStream_t stream) {
+                            const Workspace& ws, int* errflag, hipStream_t stream) {
   switch (cfg.tile) {
-    case 64: return go<MODE, 1, COUNT, VALIDATE, BATCH, BOUNCE>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
-    case 128: return go<MODE, 2, COUNT, VALIDATE, BATCH, BOUNCE>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
-    case 256: return go<MODE, 4, COUNT, VALIDATE, BATCH, BOUNCE>(sc, io, br, total_tiles, cfg, lds, counter, ws, stream);
+    case 64: return go<MODE, 1, COUNT, VALIDATE, BATCH, BOUNCE>(sc, io, br, total_tiles, cfg, lds, counter, ws, errflag, stream);
+    case 128: return go<MODE, 2, COUNT, VALIDATE, BATCH, BOUNCE>(sc, io, br, total_tiles, cfg, lds, counter, ws, errflag, stream);
+    case 256: return go<MODE, 4, COUNT, VALIDATE, BATCH, BOUNCE>(sc, io, br, total_tiles, cfg, lds, counter, ws, errflag, stream);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
-                       const LaunchCfg& cfg, unsigned long long* counter, const Workspace& ws,
-                       hipStream_t stream, hipEvent_t walk_begin, hipEvent_t walk_end) {
+                       const LaunchCfg& cfg, unsigned long long* counter, int* errflag,
+                       const Workspace& ws, hipStream_t stream, hipEvent_t walk_begin,
+                       hipEvent_t walk_end) {
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counter);
   hipError_t e;
   if (walk_begin) {
@@ -616,14 +621,14 @@ hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool cou
   const bool bounce = io.hits != nullptr;  // continued rays write their own results
   if (bounce) {
     if (validate) return hipErrorInvalidValue;
-    if (mode == 0 && !count) e = pick_tile<0, false, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
-    if (mode == 0 && count) e = pick_tile<0, true, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
-    if (mode == 1 && !count) e = pick_tile<1, false, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
-    if (mode == 1 && count) e = pick_tile<1, true, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
+    if (mode == 0 && !count) e = pick_tile<0, false, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, errflag, stream);
+    if (mode == 0 && count) e = pick_tile<0, true, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, errflag, stream);
+    if (mode == 1 && !count) e = pick_tile<1, false, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, errflag, stream);
+    if (mode == 1 && count) e = pick_tile<1, true, false, false, true>(sc, io, none, tiles, cfg, lds, counter, ws, errflag, stream);
   }
 #define CCSP_CASE(M, C, V) \
   if (!bounce && mode == M && count == C && validate == V) \
-    e = pick_tile<M, C, V, false>(sc, io, none, tiles, cfg, lds, counter, ws, stream);
+    e = pick_tile<M, C, V, false>(sc, io, none, tiles, cfg, lds, counter, ws, errflag, stream);
   CCSP_CASE(0, false, false) CCSP_CASE(0, true, false) CCSP_CASE(0, false, true) CCSP_CASE(0, true, true)
   CCSP_CASE(1, false, false) CCSP_CASE(1, true, false) CCSP_CASE(1, false, true) CCSP_CASE(1, true, true)
 #undef CCSP_CASE
@@ -655,10 +660,10 @@ hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t to
   const SceneDev nosc{};
   const RaysDev noio{};
   e = hipErrorInvalidValue;
-  if (mode == 0 && !count) e = pick_tile<0, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
-  if (mode == 0 && count) e = pick_tile<0, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
-  if (mode == 1 && !count) e = pick_tile<1, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
-  if (mode == 1 && count) e = pick_tile<1, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, stream);
+  if (mode == 0 && !count) e = pick_tile<0, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, nullptr, stream);
+  if (mode == 0 && count) e = pick_tile<0, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, nullptr, stream);
+  if (mode == 1 && !count) e = pick_tile<1, false, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, nullptr, stream);
+  if (mode == 1 && count) e = pick_tile<1, true, false, true>(nosc, noio, br, total_tiles, cfg, lds, counter, ws, nullptr, stream);
   if (e != hipSuccess) return e;
   if (walk_end) {
     e = hipEventRecord(walk_end, stream);
