@@ -232,6 +232,25 @@ int tune_cache_get(int32_t n_items, int64_t total_rays, int64_t total_triangles,
 int locate_points(const Triangulation *tri, const double *q_xy, int64_t n, int32_t *tri_out,
                   int32_t *status, void *stream);
 
+/*
+ * trace_rays_static: trace_rays_tuned for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). It calls no hipMalloc,
+ * hipFree or allocating library routine: its scratch (the launch's tile counters and the ray
+ * binning records) lives in one fixed device array of 64 MiB per GPU, part of the library's code
+ * object, which each GPU the call runs on holds until the process ends. Results equal
+ * trace_rays_tuned's on the same arguments. Differences: at most CCSP_STATIC_MAX_RAYS rays per call
+ * (more: CCSP_E_ARG); precision takes a mode and CCSP_TRACE_INPUT_ORDER only (VALIDATE, COUNT and
+ * TIMED: CCSP_E_ARG); tune == NULL means the default launch (the tuning cache is not consulted).
+ * Every call on one GPU shares that GPU's array: calls whose executions overlap on the device
+ * (other streams, other host threads) race and give wrong results; order them on one stream or
+ * with events. The array keeps the last call's contents; each call clears what must start at zero
+ * (with a kernel, not a memset). Asynchronous on `stream`.
+ */
+#define CCSP_STATIC_MAX_RAYS (1 << 20)
+int trace_rays_static(const Triangulation *tri, const double *o_xy, const double *d_xy,
+                      const int32_t *start_tri, int64_t n, int precision, int32_t *hit_prim,
+                      double *hit_t, int32_t *steps, const TuneParams *tune, void *stream);
+
 /* reserve_workspace: reserve the ray binning scratch for traces of up to max_rays rays on the
  * current device, so that later traces allocate nothing. */
 int reserve_workspace(int64_t max_rays);

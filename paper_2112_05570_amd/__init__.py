@@ -115,6 +115,18 @@ def trace(scene: Scene, o, d, start, precision="fp32", out: Result | None = None
     return res
 
 
+def trace_static(scene: Scene, o, d, start, out: Result, precision="fp32", stream=None,
+                 tune: TuneParams | None = None, input_order=False) -> Result:
+    """:func:`trace` through the entry point that allocates nothing (``trace_rays_static`` in the
+    C header): at most CCSP_STATIC_MAX_RAYS rays, outputs passed in, one call at a time per GPU."""
+    n = _check_rays(o, d, start)
+    mode = _mode(precision) | (CCSP_TRACE_INPUT_ORDER if input_order else 0)
+    B.trace_rays_static(scene.handle, o.data_ptr(), d.data_ptr(), start.data_ptr(), n, mode,
+                        out.hit_prim.data_ptr(), out.hit_t.data_ptr(), out.steps.data_ptr(), tune,
+                        _stream(stream))
+    return out
+
+
 def _items(jobs):
     items, results = [], []
     for job in jobs:

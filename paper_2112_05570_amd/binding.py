@@ -50,7 +50,8 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
            "anneal_moves", "anneal_sweep", "anneal_propose", "anneal_schedule",
-           "flip_anneal", "mesh_contract", "mesh_group_classes", "anneal_group")
+           "flip_anneal", "mesh_contract", "mesh_group_classes", "anneal_group",
+           "trace_rays_static")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -85,6 +86,9 @@ _lib.trace_rays.restype = _I
 _lib.trace_rays_tuned.argtypes = [_P, _P, _P, _P, _I64, _I, _P, _P, _P,
                                   ctypes.POINTER(TuneParams), _P]
 _lib.trace_rays_tuned.restype = _I
+_lib.trace_rays_static.argtypes = [_P, _P, _P, _P, _I64, _I, _P, _P, _P,
+                                   ctypes.POINTER(TuneParams), _P]
+_lib.trace_rays_static.restype = _I
 _lib.trace_batch.argtypes = [ctypes.POINTER(TraceItem), ctypes.c_int32, _I,
                              ctypes.POINTER(TuneParams), _P]
 _lib.trace_batch.restype = _I
@@ -223,6 +227,17 @@ def trace_rays_tuned(tri: int, o_xy: int, d_xy: int, start_tri: int, n: int, pre
     _check(_lib.trace_rays_tuned(_P(tri), _P(o_xy), _P(d_xy), _P(start_tri), n, precision,
                                  _P(hit_prim), _P(hit_t), _P(steps),
                                  ctypes.byref(tune) if tune is not None else None, _P(stream)))
+
+
+def trace_rays_static(tri: int, o_xy: int, d_xy: int, start_tri: int, n: int, precision: int,
+                      hit_prim: int, hit_t: int, steps: int, tune: TuneParams | None,
+                      stream: int = 0) -> None:
+    _check(_lib.trace_rays_static(_P(tri), _P(o_xy), _P(d_xy), _P(start_tri), n, precision,
+                                  _P(hit_prim), _P(hit_t), _P(steps),
+                                  ctypes.byref(tune) if tune is not None else None, _P(stream)))
+
+
+CCSP_STATIC_MAX_RAYS = 1 << 20
 
 
 def trace_batch(items, precision: int, tune: TuneParams | None = None, stream: int = 0) -> None:

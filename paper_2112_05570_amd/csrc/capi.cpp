@@ -348,13 +348,13 @@ int capture_batch_graph(DeviceState* ds, int n_items, int64_t tiles, int mode, b
   return CCSP_OK;
 }
 
-LaunchCfg make_cfg(const DeviceState& ds, int mode, const TuneParams* tp) {
+LaunchCfg make_cfg(int cus, int mode, const TuneParams* tp) {
   LaunchCfg c{};
   c.wg = (tp && tp->wg_size) ? tp->wg_size : 256;
   c.tile = (tp && tp->tile_rays) ? tp->tile_rays : (mode == 1 ? 64 : 64);
   const int wpcu = (tp && tp->waves_per_cu) ? tp->waves_per_cu : 24;
   c.refill_min = (tp && tp->refill_min) ? tp->refill_min : 16;
-  c.grid = std::max(1, ds.cus * wpcu / (c.wg / 64));
+  c.grid = std::max(1, cus * wpcu / (c.wg / 64));
   c.chunks = (tp && tp->xcd_chunks) ? tp->xcd_chunks : kClaimChunks;
   c.group = (tp && tp->tiles_per_claim) ? tp->tiles_per_claim : 4;
   return c;
@@ -381,6 +381,52 @@ int check_cfg(const LaunchCfg& c) {
 }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ trace without allocation
+//
+// trace_rays_static keeps all of its device scratch (the tile counters of its launch and the ray
+// binning records) in one file-scope device array per GPU, whose address is looked up once per
+// device; it never calls hipMalloc or anything that allocates.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr size_t kStaticBinOffset = 256;  // counters (8 x 8 B) and unused stats before the bins
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+struct StaticScratch {
+  bool init = false;
+  unsigned char* ptr = nullptr;  // device address of `scratch` on this device
+  int cus = 0;
+};
+std::mutex g_static_mu;
+StaticScratch g_static[64];
+
+// The current device's copy of `scratch`: looked up with the device current on its first call
+// (the array's host-side name is not a device address).
+int static_scratch(StaticScratch** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(CCSP_E_HIP, "device index %d unsupported", dev);
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  StaticScratch& s = g_static[dev];
+  if (!s.init) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    e = hipDeviceGetAttribute(&s.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    if (bin_workspace_bytes(CCSP_STATIC_MAX_RAYS) > kStaticScratchBytes - kStaticBinOffset)
+      return fail(CCSP_E_HIP, "static scratch of %zu bytes too small for %d binned rays",
+                  kStaticScratchBytes, CCSP_STATIC_MAX_RAYS);
+    s.ptr = static_cast<unsigned char*>(p);
+    s.init = true;
+  }
+  *out = &s;
+  return CCSP_OK;
+}
 
 }  // namespace
 
@@ -817,7 +863,7 @@ static int trace_common(const Triangulation* tri, const double* o_xy, const doub
   if (rc) return rc;
   TuneParams cached;
   if (!tune && tune_lookup(ds, tune_key(1, n, tri->nt, precision, true), &cached)) tune = &cached;
-  const LaunchCfg cfg = make_cfg(*ds, mode, tune);
+  const LaunchCfg cfg = make_cfg(ds->cus, mode, tune);
   rc = check_cfg(cfg);
   if (rc) return rc;
   const bool validate = precision & CCSP_TRACE_VALIDATE;
@@ -938,7 +984,7 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
   TuneParams cached;
   if (!tune && tune_lookup(ds, tune_key(n_items, total_rays, total_tris, precision, false), &cached))
     tune = &cached;
-  const LaunchCfg cfg = make_cfg(*ds, mode, tune);
+  const LaunchCfg cfg = make_cfg(ds->cus, mode, tune);
   rc = check_cfg(cfg);
   if (rc) return rc;
   const bool use_graph = precision & CCSP_TRACE_GRAPH;
@@ -1038,6 +1084,54 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
   return CCSP_OK;
 }
 
+int trace_rays_static(const Triangulation* tri, const double* o_xy, const double* d_xy,
+                      const int32_t* start_tri, int64_t n, int precision, int32_t* hit_prim,
+                      double* hit_t, int32_t* steps, const TuneParams* tune, void* stream) {
+  g_err.clear();
+  if (!tri) return fail(CCSP_E_ARG, "null triangulation");
+  const int mode = precision & CCSP_TRACE_MODE_MASK;
+  if (mode != CCSP_TRACE_FP64 && mode != CCSP_TRACE_FP32_FILTERED)
+    return fail(CCSP_E_ARG, "unknown precision mode %d", mode);
+  if (precision & ~(CCSP_TRACE_MODE_MASK | CCSP_TRACE_INPUT_ORDER))
+    return fail(CCSP_E_ARG, "trace_rays_static takes a precision mode and CCSP_TRACE_INPUT_ORDER "
+                            "only (flags 0x%x)", precision);
+  int rc = check_rays(o_xy, d_xy, start_tri, n, hit_prim, hit_t, steps);
+  if (rc) return rc;
+  if (n > CCSP_STATIC_MAX_RAYS)
+    return fail(CCSP_E_ARG, "trace_rays_static traces at most %d rays per call (%lld given)",
+                CCSP_STATIC_MAX_RAYS, (long long)n);
+  if (n == 0) return CCSP_OK;
+  rc = check_tune(tune);
+  if (rc) return rc;
+  StaticScratch* ss = nullptr;
+  rc = static_scratch(&ss);
+  if (rc) return rc;
+  const LaunchCfg cfg = make_cfg(ss->cus, mode, tune);
+  rc = check_cfg(cfg);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  RaysDev io{reinterpret_cast<const double2*>(o_xy), reinterpret_cast<const double2*>(d_xy),
+             start_tri, hit_prim, hit_t, steps, n, nullptr};
+  io.max_steps = tune ? tune->step_limit : 0;
+  Workspace ws{};
+  ws.counters = reinterpret_cast<unsigned long long*>(ss->ptr);  // zeroed by the walk launch
+  ws.stats = ws.counters + kClaimChunks;                          // not written (no counting)
+  hipError_t e;
+  const bool bin = !(precision & CCSP_TRACE_INPUT_ORDER) && n >= kBinMinRays &&
+                   tri->nt >= kBinMinTriangles;
+  if (bin) {
+    RaysDev binned{};
+    e = launch_bin_rays(tri->dev, io, (tune && tune->bin == 2) ? kBinRadix : kBinBuckets,
+                        ss->ptr + kStaticBinOffset, kStaticScratchBytes - kStaticBinOffset, &binned,
+                        nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "ray binning");
+    io = binned;
+  }
+  e = launch_walk(tri->dev, io, mode, false, false, cfg, ws.counters, nullptr, ws, st);
+  if (e != hipSuccess) return hip_fail(e, "walk launch");
+  return CCSP_OK;
+}
+
 int reserve_workspace(int64_t max_rays) {
   g_err.clear();
   if (max_rays < 0 || max_rays >= INT32_MAX) return fail(CCSP_E_ARG, "max_rays out of range");
@@ -1073,7 +1167,7 @@ int tune_cache_set(int32_t n_items, int64_t total_rays, int64_t total_triangles,
   DeviceState* ds = nullptr;
   rc = device_state(&ds);
   if (rc) return rc;
-  LaunchCfg cfg = make_cfg(*ds, precision & CCSP_TRACE_MODE_MASK, tune);
+  LaunchCfg cfg = make_cfg(ds->cus, precision & CCSP_TRACE_MODE_MASK, tune);
   rc = check_cfg(cfg);
   if (rc) return rc;
   const bool single = n_items == 1 && !(precision & CCSP_TRACE_GRAPH);
