@@ -1,0 +1,159 @@
+"""GPU parity against the checker on the multi-scene workloads at their real sizes.
+
+* Batch: the 256-scene workload (segments log-U[100, 1e5], rays log-U[1024, 2^20]), every item in
+  one graph-replayed persistent launch (binary32 filter) and in one eager launch (binary64); a
+  sample of 1000 rays of every item equals the checker's walk bit for bit.
+* Serving: resident scenes of the serving workload's generator; requests of log-U[256, 262144]
+  rays arriving while earlier ones run (continuous batching); a sample of every request's rays
+  equals the checker's walk bit for bit.
+* Point location on the flip-annealed grid scene: 50,000 points against the checker's brute-force
+  location (statuses exact; triangles where the answer is unique).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ccsp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_05570_amd as m
+    return m
+
+
+def _same(got, ref, what):
+    for name, g, r in zip(("prim", "t", "steps"), got, ref):
+        ok = (g == r) | (np.isinf(g) & np.isinf(r)) if name == "t" else (g == r)
+        bad = np.nonzero(~ok)[0]
+        assert bad.size == 0, f"{what}: {name} differs at {bad[:5]}: {g[bad[:5]]} vs {r[bad[:5]]}"
+
+
+def _sample(n, k, rng):
+    if n <= k:
+        return np.arange(n)
+    return np.unique(np.concatenate([rng.choice(n, k - 2, replace=False), [0, n - 1]]))
+
+
+def test_batch_full_size_vs_checker(ccsp):
+    t0 = time.time()
+    data = list(sg.multi_workload("batch", seed=0))
+    assert len(data) == 256
+    print(f"batch workload built in {time.time() - t0:.1f}s: "
+          f"{sum(r.n for _, _, r in data)} rays", flush=True)
+    scenes = [ccsp.Scene.from_arrays(sc) for _, sc, _ in data]
+    try:
+        dev = [tuple(torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (r.o, r.d, r.start))
+               for _, _, r in data]
+        jobs = [(s, *x) for s, x in zip(scenes, dev)]
+        res32 = ccsp.trace_batch(jobs, precision="fp32", graph=True)
+        res64 = ccsp.trace_batch(jobs, precision="fp64")
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(7)
+        for (i, sc, r), a, b in zip(data, res32, res64):
+            idx = _sample(r.n, 1000, rng)
+            ref = oracle.walk(oracle.Triangulation.of(sc), r.o[idx], r.d[idx], r.start[idx])
+            ii = torch.from_numpy(idx).to(DEV)
+            for prec, res in (("fp32 graph", a), ("fp64", b)):
+                got = tuple(x[ii].cpu().numpy() for x in (res.hit_prim, res.hit_t, res.steps))
+                _same(got, ref, f"batch item {i} ({sc.n_triangles} triangles, {r.n} rays) {prec}")
+            assert int((a.hit_prim < 0).sum().item()) == 0
+    finally:
+        for s in scenes:
+            s.free()
+
+
+def test_server_serve_workload_vs_checker(ccsp):
+    """16 scenes of the serving workload's generator (log-U[1e3, 5e5] segments), 400 requests
+    arriving as a Poisson process at about the server's capacity, so that requests are admitted
+    while others run."""
+    segs, _ = sg.multi_sizes("serve", seed=0)
+    k_scenes, pool = 16, 262_144
+    tris, hosts, rays = [], [], []
+    for i in range(k_scenes):
+        sc = sg.make_scene("serve", seed=0, n_seg=int(segs[i]), index=i)
+        r = sg.sample_rays(sc, pool, seed=sg.subseed(0, sg.TAG_RAYS, i + 1))
+        tris.append(sc)
+        rays.append(r)
+        hosts.append(tuple(torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+                           for a in (r.o, r.d, r.start)))
+    scenes = [ccsp.Scene.from_arrays(sc) for sc in tris]
+    rng = np.random.default_rng(np.random.SeedSequence([0, 9]))
+    N = 400
+    req_s = rng.integers(0, k_scenes, N)
+    req_n = sg.log_uniform_int(rng.random(N), 256, pool)
+    req_o = (rng.random(N) * (pool - req_n + 1)).astype(np.int64)
+    arrive = np.cumsum(rng.exponential(1.0 / 4000.0, N))  # about 4,000 requests/s
+    outs = [ccsp.Result(torch.empty(int(n), dtype=torch.int32).pin_memory(),
+                        torch.empty(int(n), dtype=torch.float64).pin_memory(),
+                        torch.empty(int(n), dtype=torch.int32).pin_memory()) for n in req_n]
+    try:
+        with ccsp.Server("fp32", slots=4, memory_bytes=256 << 20) as srv:
+            ids, done = {}, []
+            t_start = time.monotonic()
+            for k in range(N):
+                while time.monotonic() - t_start < arrive[k]:
+                    done += srv.poll(timeout_s=1e-4)
+                s, o, n = req_s[k], req_o[k], req_n[k]
+                ids[srv.submit(scenes[s], *(x[o:o + n] for x in hosts[s]), outs[k])] = k
+            deadline = time.monotonic() + 120.0
+            while len(done) < N:
+                done += srv.poll(timeout_s=0.5)
+                assert time.monotonic() < deadline, "server did not finish"
+            st = srv.stats()
+        assert all(status == 0 for _, status, *_ in done)
+        assert sorted(ids[i] for i, *_ in done) == list(range(N))
+        assert st["max_items_per_launch"] > 1 and st["max_slots_busy"] >= 2
+        # the checker walks each scene's sampled rays of all its requests in one call
+        samples = [_sample(int(n), 1500, rng) for n in req_n]
+        for s in range(k_scenes):
+            ks = np.nonzero(req_s == s)[0]
+            if ks.size == 0:
+                continue
+            pos = np.concatenate([req_o[k] + samples[k] for k in ks])
+            r = rays[s]
+            ref = oracle.walk(oracle.Triangulation.of(tris[s]), r.o[pos], r.d[pos], r.start[pos])
+            at = 0
+            for k in ks:
+                m = samples[k].size
+                got = tuple(x.numpy()[samples[k]]
+                            for x in (outs[k].hit_prim, outs[k].hit_t, outs[k].steps))
+                _same(got, tuple(x[at:at + m] for x in ref), f"request {k} (scene {s}, {req_n[k]} rays)")
+                at += m
+    finally:
+        for s in scenes:
+            s.free()
+
+
+def test_locate_annealed_grid_vs_checker(ccsp):
+    sc = sg.make_scene("grid")
+    an, _ = sg.anneal_flips(sc, seed=0)
+    rng = np.random.default_rng(21)
+    lo, hi = an.box
+    e = an.tri_v[rng.integers(0, an.n_triangles, 2000)][:, :2]
+    pts = [rng.uniform(lo, hi, (46_000, 2)), an.xy[rng.integers(0, an.n_vertices, 1000)],
+           0.5 * (an.xy[e[:, 0]] + an.xy[e[:, 1]]), sg.sample_rays(an, 1000, seed=5).o]
+    q = np.ascontiguousarray(np.concatenate(pts))
+    with ccsp.Scene.from_arrays(an) as scene:
+        t, s = ccsp.locate(scene, torch.from_numpy(q).to(DEV))
+        torch.cuda.synchronize()
+        t, s = t.cpu().numpy(), s.cpu().numpy()
+    ref_t, ref_s = oracle.locate(oracle.Triangulation.of(an), q)
+    assert np.array_equal(s, ref_s), f"status differs at {np.nonzero(s != ref_s)[0][:5]}"
+    assert (ref_s == 1).sum() >= 1000 and (ref_s == 0).sum() > 40_000
+    uniq = ref_s != 1
+    assert np.array_equal(t[uniq], ref_t[uniq])
+    for k in np.nonzero(~uniq)[0]:
+        a, b, c = (an.xy[v] for v in an.tri_v[t[k]])
+        assert min(oracle.orient(b, c, q[k]), oracle.orient(c, a, q[k]),
+                   oracle.orient(a, b, q[k])) == 0, f"point {k} not on triangle {t[k]}"
