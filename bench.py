@@ -22,11 +22,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 # Algorithmic bytes of the walk kernel: per step the exit word, the across vertex in binary32 and
-# its id; per ray its input (origin, direction, start triangle: 36), the two first-triangle
-# vertices beyond the one a step would read (16) and the parked result (8). The finishing pass
-# (primitive record, hit distance, the three outputs) is a separate kernel.
+# its id (16); per ray its input (origin, direction, start triangle: 36), the two first-triangle
+# vertices beyond the one a step would read (16), the hit primitive's segment (32) and the parked
+# result (16). The whole trace moves the same per-step bytes and 100 B per ray of its own (36 in,
+# 16 out, 16 first-triangle vertices, 32 primitive segment).
 BYTES_PER_STEP = 16
-BYTES_PER_RAY = 60
+BYTES_PER_RAY = 100
+TRACE_BYTES_PER_RAY = 100
 
 # HBM traffic of one binary32 walk launch on the large workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE passes (profiles/walk_fp32_large_pmc.md), each scaled by what the same counter reports
@@ -34,9 +36,9 @@ BYTES_PER_RAY = 60
 # taken with.
 WALK_SOURCES = ("walk_kernels.hip", "walk.hpp", "decide.hpp", "exact.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "c89874a0a01830dac8ccfdda3cc86ea5ace36e430c0dc5344680c141e6afb45e",
+    "sources_sha256": "e4892b4746b1801658487388c9c7b818be986a3d9f24828c765ffd64c18c9d57",
     "tune": [128, 64, 16, 8, 8, 8, 0],
-    "bytes_per_launch": 12221037820,
+    "bytes_per_launch": 17194156288,
 }
 
 
@@ -81,6 +83,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-objective", action="store_true",
                     help="leave out the objective leg (for profiler runs of the walk)")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="leave out the batch and serving legs of the default run")
+    ap.add_argument("--multi-requests", type=int, default=3000,
+                    help="requests per load level of the default run's serving leg")
     ap.add_argument("--tune", default="", help="wg,tile,waves_per_cu,refill_min")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling HBM "
@@ -218,6 +224,9 @@ def main():
 
     # diagnostics outside the timed region
     steps_total = int(out32.steps.sum(dtype=torch.int64).item())
+    # dependent loads of the binned walk: binning decides the first triangle, and each 32-B
+    # record load then advances up to two steps, so a ray of k steps makes (k + 1) // 2 loads
+    loads_total = int(((out32.steps.to(torch.int64) + 1) // 2).sum().item())
     steps_p99 = float(torch.quantile(out32.steps[: 1 << 24].double(), 0.99).item())
     t32_err = pure_binary32_t_error(sc, o, d, out32, torch)
     same = bool(torch.equal(out32.hit_prim, out64.hit_prim) and torch.equal(out32.steps, out64.steps)
@@ -245,6 +254,7 @@ def main():
     g_scene = B.gather_roofline(ws_bytes, 16, 2048, stream.cuda_stream)
     g_l2 = B.gather_roofline(2 << 20, 16, 2048, stream.cuda_stream)
     walk_steps_s = steps_total / walk_avg
+    walk_loads_s = loads_total / walk_avg
 
     objective = None if args.no_objective else objective_leg("grid", args.steps, args.warmup)
     low_weight = None
@@ -253,6 +263,12 @@ def main():
     triangulations = None
     if args.workload == "grid":
         triangulations = grid_triangulations(sc, rays, scene, o, d, st, out32, args.steps)
+
+    batch = serve = None
+    if args.workload == "large" and not args.no_multi:
+        del out64
+        batch = batch_leg(3, 1, args.tune_cache)
+        serve = serve_leg(args.multi_requests, args.slots)
 
     cpu = None
     if not args.no_cpu:
@@ -306,13 +322,33 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "walk_persistent (binary32)", "kernel_ms": walk_avg * 1e3,
-                     "bytes_per_launch": alg_bytes},
+                     "bytes_per_launch": alg_bytes,
+                     "bytes_model": f"{BYTES_PER_STEP} B/step + {BYTES_PER_RAY} B/ray (algorithmic)",
+                     "measured_GBs": (traffic / walk_avg / 1e9) if traffic else None,
+                     "measured_frac": (traffic / walk_avg / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "note": "achieved counts algorithmic bytes, which caches partly serve; "
+                             "measured_GBs is the rocprofv3 HBM traffic over the same time"},
+        "trace_roofline": {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "bytes_per_trace": BYTES_PER_STEP * steps_total + TRACE_BYTES_PER_RAY * n,
+            "achieved": (BYTES_PER_STEP * steps_total + TRACE_BYTES_PER_RAY * n) / (ms / 1e3) / 1e9,
+            "frac": (BYTES_PER_STEP * steps_total + TRACE_BYTES_PER_RAY * n) / (ms / 1e3) / 1e9
+                    / HBM_PEAK_GBS,
+            "what": "whole trace (binning, walk, copy) per step of the benchmark"},
         "gather_roofline": {
-            "walk_steps_per_s": walk_steps_s,
+            "walk_steps_per_s": walk_steps_s, "walk_loads_per_s": walk_loads_s,
+            "loads_per_ray": loads_total / n,
             "chase_loads_per_s_scene_sized": g_scene, "scene_sized_bytes": ws_bytes,
-            "frac_scene_sized": walk_steps_s / g_scene,
+            "frac_scene_sized_per_load": walk_loads_s / g_scene,
             "chase_loads_per_s_l2_sized": g_l2, "l2_sized_bytes": 2 << 20,
-            "frac_l2_sized": walk_steps_s / g_l2},
+            "frac_l2_sized_per_load": walk_loads_s / g_l2,
+            "note": "one 32-B record load advances up to two steps; fractions compare loads "
+                    "with the chase's loads"},
+        "batch": batch,
+        "serve": serve,
+        "latency": None if serve is None else {
+            "source": "serve leg, Poisson arrivals at 50% of capacity",
+            "p50_ms": serve["levels"][1]["p50_ms"], "p99_ms": serve["levels"][1]["p99_ms"]},
         "objective": objective,
         "triangulations": triangulations,
         "low_weight": low_weight,
@@ -746,8 +782,23 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
 
 
 def batch_bench(args):
+    """The batch workload on its own line."""
+    leg = batch_leg(args.steps, args.warmup, args.tune_cache)
+    line = {
+        "metric": "rays/s, 256-scene batch in one graph-replayed persistent launch (FP32+filter)",
+        "value": leg["rays_per_s"], "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": leg["workload"], "items": leg["items"], "rays": leg["rays"],
+                   "triangles": leg["triangles"]},
+    }
+    line.update({k: v for k, v in leg.items() if k not in ("workload",)})
+    print(json.dumps(line), flush=True)
+
+
+def batch_leg(steps, warmup, tune_cache):
     """256 scenes of uneven size and uneven ray counts traced in one persistent launch, replayed
-    from a HIP graph, with launch parameters from the library's autotuner."""
+    from a HIP graph, with launch parameters from the library's autotuner. Returns a dict."""
     import numpy as np
     import torch
 
@@ -790,44 +841,57 @@ def batch_bench(args):
         wall = time.perf_counter() - t
         return wall, ccsp.read_stage_times(k)
 
-    wall_default, _ = timed(max(1, args.steps // 2), ccsp.TuneParams())
+    wall_default, _ = timed(max(1, steps // 2), ccsp.TuneParams())
     t = time.perf_counter()
-    best, tuned_ms = ccsp.autotune(jobs, "fp32", graph=True, reps=3,
-                                   cache_path=args.tune_cache)
+    best, tuned_ms = ccsp.autotune(jobs, "fp32", graph=True, reps=3, cache_path=tune_cache)
     tune_s = time.perf_counter() - t
     log(f"[bench] autotune: {best.as_tuple()} in {tune_s:.1f}s")
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         ccsp.trace_batch(jobs, graph=True)
-    wall, (bin_ms, walk_ms, fin_ms) = timed(args.steps, None)  # None: the tuned parameters
+    wall, (bin_ms, walk_ms, fin_ms) = timed(steps, None)  # None: the tuned parameters
     torch.cuda.synchronize()
     same = all(torch.equal(j[4].hit_prim, r.hit_prim) and torch.equal(j[4].steps, r.steps)
                and torch.equal(j[4].hit_t, r.hit_t) for j, r in zip(jobs, refs))
     steps_total = int(sum(int(r.steps.sum(dtype=torch.int64).item()) for r in refs))
-    ms = wall / args.steps * 1e3
-    line = {
-        "metric": "rays/s, 256-scene batch in one graph-replayed persistent launch (FP32+filter)",
-        "value": n * args.steps / wall, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"batch: {len(jobs)} scenes, segments log-U[100, 1e5], rays "
-                               f"log-U[1024, 2^20], seed 0",
-                   "items": len(jobs), "rays": n, "triangles": tris},
-        "steps_per_s": steps_total * args.steps / wall,
+    ms = wall / steps * 1e3
+    leg = {
+        "workload": f"batch: {len(jobs)} scenes, segments log-U[100, 1e5], rays "
+                    f"log-U[1024, 2^20], seed 0",
+        "items": len(jobs), "rays": n, "triangles": tris,
+        "rays_per_s": n * steps / wall, "ms_per_step": ms,
+        "steps_per_s": steps_total * steps / wall,
         "mean_steps_per_ray": steps_total / n,
         "graph_replay_ms": float(np.mean(walk_ms)),
         "tuned": dict(zip(["wg_size", "tile_rays", "waves_per_cu", "refill_min",
                            "tiles_per_claim", "xcd_chunks", "bin"], best.as_tuple())),
         "autotune_seconds": tune_s,
-        "default_params_ms_per_step": wall_default / max(1, args.steps // 2) * 1e3,
+        "default_params_ms_per_step": wall_default / max(1, steps // 2) * 1e3,
         "one_trace_per_item_ms": ms_items,
         "batch_equals_single_traces": same,
     }
-    print(json.dumps(line), flush=True)
+    del refs, jobs
     for s in scenes:
         s.free()
+    return leg
 
 
 def serve_bench(args):
+    """The serving workload on its own line."""
+    leg = serve_leg(args.requests, args.slots)
+    line = {
+        "metric": "rays/s and p50/p99 request latency, 64 resident scenes, Poisson arrivals "
+                  "(request server, FP32+filter)",
+        "value": leg["capacity"]["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": 0,
+        "ms_per_step": leg["capacity"]["seconds"] / args.requests * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic", "config": leg["config"],
+    }
+    line.update({k: v for k, v in leg.items() if k != "config"})
+    print(json.dumps(line), flush=True)
+
+
+def serve_leg(n_requests, slots):
     """64 resident scenes; requests of log-U[256, 262144] rays, each naming a uniformly chosen
     scene, go through the library's request server (admission by device memory, coalescing across
     scenes, overlapping launch slots). Capacity: every request submitted at once. Then the same
@@ -852,7 +916,7 @@ def serve_bench(args):
                      torch.from_numpy(r.start).pin_memory()))
     tris = sum(s.n_triangles for s in scenes)
     rng = np.random.default_rng(np.random.SeedSequence([0, 5]))
-    N = args.requests
+    N = n_requests
     req_scene = rng.integers(0, len(scenes), N)
     req_n = sg.log_uniform_int(rng.random(N), 256, pool_rays)
     req_off = (rng.random(N) * (pool_rays - req_n + 1)).astype(np.int64)
@@ -870,7 +934,7 @@ def serve_bench(args):
     def run(rate):
         """rate None: all at once. Returns (latencies s, seconds, stats, stashed sample results)."""
         stash = {}
-        with ccsp.Server("fp32", slots=args.slots, memory_bytes=2 << 30) as srv:
+        with ccsp.Server("fp32", slots=slots, memory_bytes=2 << 30) as srv:
             start = time.monotonic() + 0.02
             arrive = np.full(N, start) if rate is None else start + np.cumsum(gaps) / rate
             free, inflight, lat = list(range(ring)), {}, np.zeros(N)
@@ -924,17 +988,12 @@ def serve_bench(args):
                        "max_slots_busy": st["max_slots_busy"]})
         log(f"[bench] load {load}: p50 {levels[-1]['p50_ms']:.2f} ms, "
             f"p99 {levels[-1]['p99_ms']:.2f} ms")
-    line = {
-        "metric": "rays/s and p50/p99 request latency, 64 resident scenes, Poisson arrivals "
-                  "(request server, FP32+filter)",
-        "value": cap_rays_s, "unit": "rays/s", "n_gpus": 1, "steps": N, "warmup": 0,
-        "ms_per_step": cap_s / N * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+    leg = {
         "config": {"workload": f"serve: {len(scenes)} resident scenes, segments log-U[1e3, 5e5]; "
                                f"{N} requests of log-U[256, 262144] rays, uniform scene, seed 0",
-                   "triangles": tris, "rays": total_rays, "slots": args.slots,
+                   "triangles": tris, "rays": total_rays, "slots": slots,
                    "pool_bytes": 2 << 30, "host_buffers": "pinned"},
-        "capacity": {"rays_per_s": cap_rays_s, "requests_per_s": cap_req_s,
+        "capacity": {"rays_per_s": cap_rays_s, "requests_per_s": cap_req_s, "seconds": cap_s,
                      "p50_ms": float(np.percentile(cap_lat, 50)) * 1e3,
                      "p99_ms": float(np.percentile(cap_lat, 99)) * 1e3,
                      "launches": cap_st["launches"],
@@ -942,9 +1001,9 @@ def serve_bench(args):
         "levels": levels,
         "mix_equals_alone_sampled": same, "sampled_requests": len(stash),
     }
-    print(json.dumps(line), flush=True)
     for s in scenes:
         s.free()
+    return leg
 
 
 def copy_calibration(mib):

@@ -236,7 +236,7 @@ int locate_points(const Triangulation *tri, const double *q_xy, int64_t n, int32
  * trace_rays_static: trace_rays_tuned for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). It calls no hipMalloc,
  * hipFree or allocating library routine: its scratch (the launch's tile counters and the ray
- * binning records) lives in one fixed device array of 64 MiB per GPU, part of the library's code
+ * binning records) lives in one fixed device array of 80 MiB per GPU, part of the library's code
  * object, which each GPU the call runs on holds until the process ends. Results equal
  * trace_rays_tuned's on the same arguments. Differences: at most CCSP_STATIC_MAX_RAYS rays per call
  * (more: CCSP_E_ARG); precision takes a mode and CCSP_TRACE_INPUT_ORDER only (VALIDATE, COUNT and
@@ -274,8 +274,9 @@ int read_counters(uint64_t out[4], int reset);
  * current device, oldest first, measured with HIP events on each trace's stream. bin_ms[i] runs
  * from the start of the trace to the start of the walk kernel (the ray binning; about zero for a
  * trace that does not bin; the item-table upload for trace_batch), walk_ms[i] covers the walk
- * kernel alone, finish_ms[i] the finishing pass that writes the results (for trace_batch with
- * CCSP_TRACE_GRAPH the whole replayed graph counts as walk and finish_ms[i] is zero).
+ * kernel alone, finish_ms[i] the finishing pass that writes the caller's arrays (a copy of the
+ * parked results for a binned trace; for trace_batch with CCSP_TRACE_GRAPH the whole replayed
+ * graph counts as walk and finish_ms[i] is zero).
  * The library keeps the last 256 timed traces per device; this call writes up to max_records of
  * the most recent ones, sets *n_records to their number, and forgets all kept records. Blocks
  * until those traces finish.

@@ -215,7 +215,8 @@ size_t bin_workspace_bytes(int64_t n) {
   const size_t bucket = align256(sizeof(RayRec) * (size_t)n) + 2 * align256(sizeof(uint32_t) * items) +
                         align256(scan_temp_bytes(items));
   const size_t radix = 4 * align256(sizeof(uint32_t) * (size_t)n) + align256(sort_temp_bytes(n));
-  return bucket > radix ? bucket : radix;
+  // plus the parked results (16 B per ray, at the start)
+  return align256(16 * (size_t)n) + (bucket > radix ? bucket : radix);
 }
 
 hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void* workspace,
@@ -225,6 +226,9 @@ hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void
   if (n <= 0 || n >= INT32_MAX || bin_workspace_bytes(n) > ws_bytes) return hipErrorInvalidValue;
   auto* p = static_cast<unsigned char*>(workspace);
   *out = in;
+  out->park = reinterpret_cast<double2*>(p);
+  p += align256(16 * (size_t)n);
+  ws_bytes -= align256(16 * (size_t)n);
   hipError_t e;
   if (kind == kBinRadix) {
     const size_t a = align256(sizeof(uint32_t) * (size_t)n);

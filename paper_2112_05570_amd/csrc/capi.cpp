@@ -109,7 +109,7 @@ uint32_t hilbert16(uint32_t x, uint32_t y) {
 }
 
 // Events of one timed trace: start of the trace, start and end of the walk kernel, end of the
-// trace (after the finishing pass).
+// trace (after the copy of parked results, if any).
 struct StageEvents {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
@@ -303,7 +303,7 @@ int grow_item_tables(DeviceState* ds, int n_items) {
   return CCSP_OK;
 }
 
-// Capture (reset, walk, finish) of a batch of n_items items and `tiles` tiles into a graph with
+// Capture (reset, walk) of a batch of n_items items and `tiles` tiles into a graph with
 // its own item table and tile counters.
 int capture_batch_graph(DeviceState* ds, int n_items, int64_t tiles, int mode, bool count,
                         const LaunchCfg& cfg, BatchGraph* g) {
@@ -389,7 +389,7 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 // trace_rays_static keeps all of its device scratch (the tile counters of its launch and the ray
 // binning records) in one file-scope device array per GPU, whose address is looked up once per
 // device; it never calls hipMalloc or anything that allocates.
-constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr size_t kStaticScratchBytes = size_t(80) << 20;
 constexpr size_t kStaticBinOffset = 256;  // counters (8 x 8 B) and unused stats before the bins
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
@@ -637,8 +637,8 @@ int load_triangulation(const TriangulationDesc* desc, void* stream, Triangulatio
     }
   }
 
-  // primitives stay in the caller's order: a single trace reads them in input order of the rays
-  // (the finishing pass), where no renumbering would bring hits of neighbouring rays together
+  // primitives stay in the caller's order: the walk reads a primitive's segment at a hit, and
+  // binned rays hit the primitives of one region at a time, whose lines then stay in L2
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t off_s32 = 0;
   const size_t off_s64 = align(off_s32 + sizeof(Slot32) * 3 * T);
@@ -1028,7 +1028,7 @@ int trace_batch(const TraceItem* items, int32_t n_items, int precision, const Tu
   TableSlot* dslot = nullptr;
   BatchItem* table = nullptr;
   if (use_graph) {
-    // (reset, walk, finish) captured once per key and replayed; the item table is uploaded into
+    // (reset, walk) captured once per key and replayed; the item table is uploaded into
     // the graph's own table before each replay
     const std::array<int64_t, 10> key{n_items, tiles,    mode,           (int64_t)count, cfg.wg,
                                       cfg.tile, cfg.grid, cfg.refill_min, cfg.chunks,     cfg.group};

@@ -117,6 +117,9 @@ struct RaysDev {
   // selects the continued walk, which writes prim/t/steps itself
   int32_t* hits;
   int32_t* face;
+  // rays walked in another order than the caller's (binned): 16-byte result records in the
+  // caller's order, turned into prim/t/steps by a coalesced pass after the walk
+  double2* park;
   int32_t max_bounces;
   // the step guard: a walk (a segment of a continued ray) that would enter one triangle more than
   // this ends with CCSP_RAY_GUARD; 0 or more than the triangle count means the triangle count
@@ -159,16 +162,17 @@ hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void
                            size_t ws_bytes, RaysDev* out, unsigned long long* stats,
                            hipStream_t stream);
 
-// A single trace: the walk kernel, then the finishing pass (finish_rays). `walk_begin` and
-// `walk_end`, if not null, are recorded on `stream` right before and after the walk kernel itself
-// (after the small counter reset, before the finishing pass), so that they time it alone.
+// A single trace: the walk kernel, then (rays walked in another order than the caller's, i.e.
+// io.park set) the copy of the parked results into the caller's arrays (finish_copy).
+// `walk_begin` and `walk_end`, if not null, are recorded on `stream` right before and after the
+// walk kernel itself (after the small counter reset, before the copy), so that they time it alone.
 // `errflag` (validating launches only) receives 1 if a ray fails its precondition.
 hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool count, bool validate,
                        const LaunchCfg& cfg, unsigned long long* counter, int* errflag,
                        const Workspace& ws, hipStream_t stream, hipEvent_t walk_begin = nullptr,
                        hipEvent_t walk_end = nullptr);
 
-// A batch: the walk kernel over every item's tiles, then finish_batch.
+// A batch: the walk kernel over every item's tiles (it writes every item's results).
 hipError_t launch_walk_batch(const BatchItem* items_dev, int n_items, int64_t total_tiles,
                              int mode, bool count, const LaunchCfg& cfg,
                              unsigned long long* counter, const Workspace& ws, hipStream_t stream,

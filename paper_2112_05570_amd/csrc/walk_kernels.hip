@@ -13,10 +13,17 @@
 //    XCD), stages them in its own LDS region (origin, direction, and the start triangle or, for
 //    binned rays, the first exit slot) and refills idle lanes from LDS as soon as `refill_min` of
 //    its 64 lanes have finished, so that divergent ray lengths do not idle the SIMD.
-//  * A trace finishes in a second kernel: at a hit, miss or bad ray the walk stores only
-//    (primitive or a negative code, steps) into the ray's 8-byte hit_t slot and frees the lane at
-//    once; finish_rays (finish_batch for a batch) then turns these into (primitive, t, steps) in
-//    input order, with coalesced accesses and the binary64 division out of the walk loop.
+//  * A trace finishes in a second kernel, in input order with coalesced accesses, because the
+//    caller's three result arrays would take three scattered stores per ray from the walk.
+//    Binned rays (walked in another order than the caller's): a hit frees the lane at once, but
+//    the lane keeps the ray and the primitive as a pending hit, fetches the primitive's segment in
+//    the next iteration's load round (which the wave makes anyway, for its other lanes or the
+//    lane's next ray), computes t and parks a 16-byte record (t, primitive, steps) per ray;
+//    binned rays hit the primitives of one region at a time, so that fetch mostly hits in L2.
+//    finish_copy then copies the records into the caller's arrays. Rays walked in input order
+//    (batches, unbinned traces) park only (primitive, steps) in the ray's 8-byte hit_t slot and
+//    finish_rays / finish_batch compute t there, since their hits gather primitives at random
+//    either way.
 //  * Decisions: the sign of D(v) = dx*(vy-oy) - dy*(vx-ox), zero counting as LEFT. In binary32 mode
 //    the sign is taken from binary32 coordinates when a forward error bound proves it, otherwise
 //    from the binary64 filter, otherwise from an exact expansion; all three agree with the exact
@@ -53,12 +60,30 @@ static __device__ __attribute__((noinline)) bool validate_ray(const SceneDev& sc
 
 // ------------------------------------------------------------------------------ persistent walk
 
-// Result of a single trace as left by the walk for finish_rays: x = internal primitive (>= 0) or
-// a CCSP_RAY_* code, y = steps; stored in the ray's hit_t slot (8 bytes), non-temporally: it is
-// read back once, by the finishing pass.
+// Result of a ray walked in input order, as left for finish_rays / finish_batch: x = the caller's
+// primitive id (>= 0) or a CCSP_RAY_* code, y = steps; stored in the ray's hit_t slot (8 bytes),
+// non-temporally: it is read back once, by the finishing pass.
 __device__ __forceinline__ void park_result(const RaysDev& io, int64_t ray, int code, int steps) {
   __builtin_nontemporal_store(((unsigned long long)(unsigned)steps << 32) | (unsigned)code,
                               reinterpret_cast<unsigned long long*>(io.t) + ray);
+}
+
+// Result of a binned ray, t included, as left for finish_copy: one 16-byte record at io.park[ray].
+__device__ __forceinline__ void park_record(const RaysDev& io, int64_t ray, int code, double t,
+                                            int steps) {
+  typedef long long vl2 __attribute__((ext_vector_type(2)));
+  vl2 v;
+  v.x = __double_as_longlong(t);
+  v.y = (long long)(((unsigned long long)(unsigned)steps << 32) | (unsigned)code);
+  __builtin_nontemporal_store(v, reinterpret_cast<vl2*>(io.park) + ray);
+}
+
+// A ray that ends without a hit (a CCSP_RAY_* code).
+__device__ __forceinline__ void park_code(const RaysDev& io, int64_t ray, int code, int steps) {
+  if (io.park)
+    park_record(io, ray, code, INFINITY, steps);
+  else
+    park_result(io, ray, code, steps);
 }
 
 __device__ __forceinline__ int lane_rank(unsigned long long mask) {
@@ -227,6 +252,13 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
                                           // vertex opposite the hit edge
   int64_t ray = 0;
   int item = 0;
+  // a binned ray's hit waiting for its primitive's segment: ray, primitive, steps and the ray
+  // itself (a refill in the same iteration replaces ox..dy)
+  constexpr bool PEND = !BOUNCE && !BATCH;
+  const bool parked = PEND && io_arg.park != nullptr;
+  int64_t pray = -1;
+  int pprim = 0, psteps = 0;
+  double pox = 0, poy = 0, pdx = 0, pdy = 0;
   // per-lane scene in a batch, kernel argument otherwise
   const Slot32* slot32 = sc_arg.slot32;
   const Pair32* pair32 = sc_arg.pair32;
@@ -251,7 +283,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
   for (;;) {
     const unsigned long long idle = __ballot(state == IDLE);
     const int nidle = __popcll(idle);
-    if (drained && nidle == 64) break;
+    if (drained && nidle == 64 && (!PEND || __ballot(pray >= 0) == 0)) break;
     if (!drained && nidle >= refill_min) {
       const int rank = lane_rank(idle);
       int served = 0;
@@ -324,7 +356,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             if (BOUNCE)
               bounce_result(io_arg, ray, -3, INFINITY, 0, 0, -1);
             else
-              park_result(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
+              park_code(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
             state = IDLE;
           }
         }
@@ -359,13 +391,29 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
       R2 = *reinterpret_cast<const int4*>(sc_arg.v64 + cv);
       if (nb >= io_arg.max_bounces && io_arg.face) R3 = sc_arg.orig[hs / 3];
     }
+    int4 P0 = make_int4(0, 0, 0, 0), P1 = P0;  // the pending hit's primitive record
+    if (PEND && pray >= 0) {
+      const int4* p = reinterpret_cast<const int4*>(sc_arg.prim + pprim);
+      P0 = p[0];
+      P1 = p[1];
+    }
     // every load above is issued before any result is used (and none is split per field)
     __asm__ volatile("" ::"v"(R0.x), "v"(R0.y), "v"(R0.z), "v"(R0.w), "v"(R1.x), "v"(R1.y),
                      "v"(R1.z), "v"(R1.w));
+    if (PEND)
+      __asm__ volatile("" ::"v"(P0.x), "v"(P0.y), "v"(P0.z), "v"(P0.w), "v"(P1.x), "v"(P1.y),
+                       "v"(P1.z), "v"(P1.w));
     if (BOUNCE || MODE == 0)
       __asm__ volatile("" ::"v"(R2.x), "v"(R2.y), "v"(R2.z), "v"(R2.w), "v"(R3));
     if (MODE == 0) __asm__ volatile("" ::"v"(RW.x), "v"(RW.y));
     // ---- process
+    if (PEND && pray >= 0) {  // the pending hit: t from the primitive's own segment
+      const double th = hit_t(make_double4(lohi(P0.x, P0.y), lohi(P0.z, P0.w), lohi(P1.x, P1.y),
+                                           lohi(P1.z, P1.w)),
+                              pox, poy, pdx, pdy);
+      park_record(io_arg, pray, pprim, th, psteps);
+      pray = -1;
+    }
     if (st_now == WALK) {
       // Pair32 of exit slot s: nx ny w0 x0 | y0 w1 x1 y1; Pair64: nx ny | x0 y0 | x1 y1 | w0 w1.
       // Up to two triangles per load: n (across slot s) and, unless n's exit is constrained or
@@ -446,11 +494,28 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
             ++c.rays;
           }
           state = IDLE;
+        } else if (parked && word <= -2) {
+          // constrained edge: a hit of primitive -word - 2, finished in the next iteration
+          pray = ray;
+          pprim = -word - 2;
+          psteps = steps;
+          pox = ox;
+          poy = oy;
+          pdx = dx;
+          pdy = dy;
+          if (COUNT) {
+            c.steps += steps;
+            ++c.rays;
+          }
+          state = IDLE;
         } else {
-          // constrained edge (hit, primitive -word - 2), hull edge (miss) or the step guard; the
-          // finishing pass computes t
-          park_result(BATCH ? batch.items[item].rays : io_arg, ray,
-                      word <= -2 ? -word - 2 : (word >= 0 ? -2 : -1), steps);
+          // constrained edge (hit, primitive -word - 2; t from the finishing pass), hull edge
+          // (miss) or the step guard
+          const int code = word <= -2 ? -word - 2 : (word >= 0 ? -2 : -1);
+          if (parked)
+            park_record(io_arg, ray, code, INFINITY, steps);
+          else
+            park_result(BATCH ? batch.items[item].rays : io_arg, ray, code, steps);
           if (COUNT) {
             c.steps += steps;
             ++c.rays;
@@ -471,7 +536,7 @@ walk_persistent(SceneDev sc_arg, RaysDev io_arg, ItemRef batch, int64_t total_ti
         if (BOUNCE)
           bounce_result(io_arg, ray, -3, INFINITY, 0, 0, -1);
         else
-          park_result(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
+          park_code(BATCH ? batch.items[item].rays : io_arg, ray, -3, 0);
         state = IDLE;
       }
     } else if (BOUNCE && st_now == BNC) {
@@ -571,6 +636,19 @@ finish_batch(const BatchItem* __restrict__ items, int n_items) {
     finish_one(it.scene.prim, it.rays.o, it.rays.d, it.rays.prim, it.rays.t, it.rays.steps, i);
 }
 
+// Parked records of binned rays (t, code | steps << 32) to the caller's arrays, in input order.
+__global__ void __launch_bounds__(256)
+finish_copy(const double2* __restrict__ park, int32_t* __restrict__ hit_prim,
+            double* __restrict__ hit_t, int32_t* __restrict__ steps, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  typedef long long vl2 __attribute__((ext_vector_type(2)));
+  const vl2 v = __builtin_nontemporal_load(reinterpret_cast<const vl2*>(park) + i);
+  __builtin_nontemporal_store(__longlong_as_double(v.x), hit_t + i);
+  __builtin_nontemporal_store((int)(unsigned)(unsigned long long)v.y, hit_prim + i);
+  __builtin_nontemporal_store((int)(unsigned)((unsigned long long)v.y >> 32), steps + i);
+}
+
 __global__ void reset_counters(unsigned long long* counter) {
   if (threadIdx.x < kClaimChunks) counter[threadIdx.x] = 0ull;
 }
@@ -639,8 +717,12 @@ hipError_t launch_walk(const SceneDev& sc, const RaysDev& io, int mode, bool cou
   }
   if (bounce) return hipSuccess;
   const int64_t blocks = (io.n + 255) / 256;
-  hipLaunchKernelGGL(finish_rays, dim3((unsigned)blocks), dim3(256), 0, stream, sc.prim, io.o, io.d,
-                     io.prim, io.t, io.steps, io.n);
+  if (io.park)
+    hipLaunchKernelGGL(finish_copy, dim3((unsigned)blocks), dim3(256), 0, stream, io.park,
+                       io.prim, io.t, io.steps, io.n);
+  else
+    hipLaunchKernelGGL(finish_rays, dim3((unsigned)blocks), dim3(256), 0, stream, sc.prim, io.o,
+                       io.d, io.prim, io.t, io.steps, io.n);
   return hipGetLastError();
 }
 
