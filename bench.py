@@ -702,10 +702,8 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
                            "folded": cnt[2], "f_before": f0k,
                            "f_after": gm.eval(XP, p).cpu().tolist()[0]}
         del XP
-    # group moves (Sec. 3.2.3): every movable vertex once as a centre, classes eight edges apart
-    t1 = time.time()
-    n_gcls = len(gm.group_classes())
-    t_gcls = time.time() - t1
+    # group moves (Sec. 3.2.3): every movable vertex once as a centre, in rounds of independent
+    # groups
     r = torch.rand((n_mov, 4), generator=gen, device=xy.device, dtype=torch.float64)
     rad = torch.sqrt(r[:, 0]) * (1.0 - r[:, 1]) ** -2.0
     th = 2.0 * np.pi * torch.rand(n_mov, generator=gen, device=xy.device, dtype=torch.float64)
@@ -714,12 +712,13 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
     XP = X.clone()
     torch.cuda.synchronize()
     a.record()
-    _, gst, gmem = gm.group_sweep(XP, p, temperature, 0.05, r, uk)
+    _, gst, gmem, grnd = gm.group_sweep(XP, p, temperature, 0.05, r, uk)
     b.record()
     torch.cuda.synchronize()
     ms_g = a.elapsed_time(b)
     proposals["group"] = {"sweep_ms": ms_g, "vertex_moves_per_s": n_mov / ms_g * 1e3,
-                          "classes": n_gcls, "classes_host_s": t_gcls,
+                          "rounds": int(grnd.max().item()) + 1,
+                          "max_group_size": int(gmem.max().item()),
                           "accepted": int((gst == 1).sum().item()),
                           "rejected": int((gst == 2).sum().item()),
                           "folded": int((gst == 0).sum().item()),

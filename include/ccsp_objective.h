@@ -194,20 +194,14 @@ int anneal_propose(MovableMesh *mesh, double *xy, const ObjectiveParams *params,
                    int32_t *status, void *stream);
 
 /*
- * mesh_group_classes: as mesh_classes, for group moves: the movable vertices coloured so that
- * members of a class are more than seven edges apart. Computed on the first call.
- */
-int mesh_group_classes(MovableMesh *mesh, int32_t *n_classes, int64_t *class_off,
-                       int32_t *class_v);
-
-/*
- * anneal_group: one sweep of group moves (Sec. 3.2.3), every movable vertex once as a centre,
- * class by class in the order of mesh_group_classes; the result is that of the sequential chain
- * over the centres in that order. The i-th centre c uses draws[4i..4i+3] = xi.x, xi.y, r, (unused)
- * (DEVICE binary64, 16-byte aligned; r in [0, 1)) and u[i]:
- *  - d = (0.5 + 4.5 * r) * eps; the members are c, then the neighbours of c that are not
- *    ORIGINAL and lie within d of it (sqrt(dx*dx + dy*dy) <= d), by increasing caller id, at most
- *    16 members in all;
+ * anneal_group: group moves (Sec. 3.2.3) for the n centres (DEVICE int32 caller ids, movable
+ * vertices; anything else gets status CCSP_MOVE_BAD or CCSP_MOVE_FIXED and round -1). Centre i
+ * uses draws[4i..4i+3] = xi.x, xi.y, r, (unused) (DEVICE binary64, 16-byte aligned; r in [0, 1))
+ * and u[i]:
+ *  - d = (0.5 + 4.5 * r) * eps; the members are c and every vertex that is not ORIGINAL and lies
+ *    within d of it (sqrt(dx*dx + dy*dy) <= d at the positions when the move is made), whether
+ *    or not an edge joins it to c, with no limit on their number: c first, then by increasing
+ *    caller id. They are found with a uniform grid of the positions, as the paper does;
  *  - area = the area of the triangles holding any member, each counted at the first member (in
  *    that order) it holds, a member's triangles in increasing caller id, each area as in
  *    anneal_schedule, summed left to right; the displacement is (lambda * sqrt(area)) * xi,
@@ -216,11 +210,16 @@ int mesh_group_classes(MovableMesh *mesh, int32_t *n_classes, int64_t *class_off
  *    delta[i] is the change of f of the whole move (+inf when not valid), accepted as in
  *    anneal_moves. status[i] is CCSP_MOVE_OK, CCSP_MOVE_REJECTED or CCSP_MOVE_FOLDS and
  *    members[i] (DEVICE int32) the group's size.
- * xy (DEVICE) is updated in place. Asynchronous on `stream`; overwrites the mesh's scratch.
+ * The moves are made in rounds; round[i] (DEVICE int32) receives the round of centre i. Moves of
+ * one round are independent (more than six edges apart, neither moving a vertex into or out of
+ * the other's disc), so the result equals the sequential chain over the centres in the order of
+ * increasing (round[i], i). xy (DEVICE) is updated in place. Allocates its scratch and
+ * synchronises `stream` once per round; overwrites the mesh's scratch.
  */
 int anneal_group(MovableMesh *mesh, double *xy, const ObjectiveParams *params, double temperature,
-                 double lambda, const double *draws, const double *u, double *delta,
-                 int32_t *status, int32_t *members, void *stream);
+                 double lambda, const int32_t *centres, int64_t n, const double *draws,
+                 const double *u, double *delta, int32_t *status, int32_t *members,
+                 int32_t *round, void *stream);
 
 /*
  * anneal_schedule: n_sweeps sweeps (as anneal_sweep) of simulated annealing with both the

@@ -514,17 +514,18 @@ def proposal_chain(m: Mesh, xy, p: Params, temperature, kind, vid, r, u):
     return xy, st, df, margin
 
 
-GROUP_MAX = 16
-
-
 def group_members(m: Mesh, xy, c, d):
-    """Sec. 3.2.3: the group of centre c, read as c and its movable neighbours (increasing id)
-    within distance d of it (lengths as everywhere), at most GROUP_MAX members in all (the first
-    ones in that order)."""
-    nb = m.nbr[m.nbr_off[c]:m.nbr_off[c + 1]]
-    dist = incident_lengths(m, xy, c)
-    out = [int(c)] + [int(w) for w, l in zip(nb, dist) if m.kind[w] != ORIGINAL and l <= d]
-    return out[:GROUP_MAX]
+    """Sec. 3.2.3: the group of centre c is every movable (not ORIGINAL) vertex whose distance to
+    c is at most d, whether or not an edge joins it to c, with no limit on its size: c first,
+    then the others in increasing id. The distance is sqrt(dx*dx + dy*dy) of the coordinate
+    differences, as for edge lengths. (The paper finds these vertices with a uniform grid; a scan
+    over all vertices finds the same ones.)"""
+    v = np.arange(m.nv)
+    dx = xy[:, 0] - xy[c, 0]
+    dy = xy[:, 1] - xy[c, 1]
+    dist = np.sqrt(dx * dx + dy * dy)
+    near = (dist <= d) & (m.kind != ORIGINAL) & (v != c)
+    return [int(c)] + [int(w) for w in v[near]]
 
 
 def group_area(m: Mesh, xy, members):
@@ -552,7 +553,8 @@ def group_move(m: Mesh, xy, p: Params, c, lam, xi, rd):
 
 
 def group_chain(m: Mesh, xy, p: Params, temperature, lam, centres, xi, rd, u):
-    """Metropolis steps (Sec. 3.1) with group moves, the centres one after another. A move is
+    """Metropolis steps (Sec. 3.1) with group moves, the centres one after another, each group
+    taken at the positions its predecessors left. A move is
     valid when every triangle holding a member is strictly counter-clockwise afterwards (exact);
     its delta f is f(moved) - f(current) over every term. Returns the final positions and, per
     centre, the status (ACCEPTED, REJECTED, FOLDED), delta f, the decision margin and the

@@ -264,6 +264,7 @@ class MovableMesh:
         self.handle = B.mesh_load(d)
         self.n_vertices = int(kind.shape[0])
         self.n_triangles = int(tri_v.shape[0])
+        self.movable = np.nonzero(kind != 0)[0].astype(np.int32)  # caller ids, increasing
         self.n_edges = B.mesh_info(self.handle)
 
     @classmethod
@@ -374,23 +375,18 @@ class MovableMesh:
                          _stream(stream))
         return d, st
 
-    def group_classes(self):
-        """Classes of movable vertices (caller ids) more than seven edges apart, the order of
-        ``group_sweep``."""
-        n = B.mesh_group_classes(self.handle)
-        off = np.empty(n + 1, dtype=np.int64)
-        B.mesh_group_classes(self.handle, off.ctypes.data_as(ctypes.c_void_p).value)
-        v = np.empty(int(off[-1]), dtype=np.int32)
-        B.mesh_group_classes(self.handle, off.ctypes.data_as(ctypes.c_void_p).value,
-                             v.ctypes.data_as(ctypes.c_void_p).value)
-        return [v[off[i]:off[i + 1]] for i in range(n)]
-
-    def group_sweep(self, xy, params, temperature, lam, draws, u, stream=None):
-        """One sweep of group moves (see ``anneal_group``): draws (M,4) (xi.x, xi.y, r, unused) and
-        u (M,) float64 CUDA tensors in the order of ``group_classes()``. xy is updated in place.
-        Returns (delta, status, members). Asynchronous."""
+    def group_sweep(self, xy, params, temperature, lam, draws, u, centres=None, stream=None):
+        """Group moves (see ``anneal_group``) for the centres (caller ids; default every movable
+        vertex once, in increasing id): draws (M,4) (xi.x, xi.y, r, unused) and u (M,) float64
+        CUDA tensors, one row per centre. xy is updated in place. Returns (delta, status, members,
+        round) per centre; the result is that of the sequential chain over the centres in the
+        order of increasing (round, index). Synchronous (one synchronisation per round)."""
         import torch
-        m = self.n_movable()
+        if centres is None:
+            centres = self.movable
+        cen = torch.as_tensor(np.ascontiguousarray(centres, dtype=np.int32)).to(xy.device) \
+            if not isinstance(centres, torch.Tensor) else centres.to(torch.int32).contiguous()
+        m = cen.shape[0]
         if (tuple(draws.shape) != (m, 4) or draws.dtype != torch.float64
                 or not draws.is_contiguous() or not draws.is_cuda or tuple(u.shape) != (m,)
                 or u.dtype != torch.float64 or not u.is_contiguous() or not u.is_cuda):
@@ -398,10 +394,11 @@ class MovableMesh:
         d = torch.empty(m, dtype=torch.float64, device=xy.device)
         st = torch.empty(m, dtype=torch.int32, device=xy.device)
         mem = torch.empty(m, dtype=torch.int32, device=xy.device)
+        rnd = torch.empty(m, dtype=torch.int32, device=xy.device)
         B.anneal_group(self.handle, self._xy(xy), params, float(temperature), float(lam),
-                       draws.data_ptr(), u.data_ptr(), d.data_ptr(), st.data_ptr(), mem.data_ptr(),
-                       _stream(stream))
-        return d, st, mem
+                       cen.data_ptr(), m, draws.data_ptr(), u.data_ptr(), d.data_ptr(),
+                       st.data_ptr(), mem.data_ptr(), rnd.data_ptr(), _stream(stream))
+        return d, st, mem, rnd
 
     def schedule(self, xy, params, temperatures, eps, lambda0, xi, u, target=0.23, stream=None):
         """Simulated annealing with a temperature and contraction-length schedule and an adaptive

@@ -41,6 +41,7 @@ CCSP_TRACE_INPUT_ORDER = 1 << 10
 CCSP_TRACE_TIMED = 1 << 11
 CCSP_TRACE_GRAPH = 1 << 12
 CCSP_MOVE_SKIPPED = 3
+CCSP_MOVE_FIXED, CCSP_MOVE_BAD = -1, -2
 CCSP_PROPOSE_DISPLACE, CCSP_PROPOSE_RESAMPLE, CCSP_PROPOSE_SWAP, CCSP_PROPOSE_CONTRACT = 0, 1, 2, 3
 
 EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch",
@@ -50,7 +51,7 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
            "anneal_moves", "anneal_sweep", "anneal_propose", "anneal_schedule",
-           "flip_anneal", "mesh_contract", "mesh_group_classes", "anneal_group",
+           "flip_anneal", "mesh_contract", "anneal_group",
            "trace_rays_static")
 
 
@@ -186,10 +187,8 @@ _lib.flip_anneal.restype = _I
 _lib.mesh_contract.argtypes = [ctypes.POINTER(MeshDesc), _P, ctypes.c_double, _P, _P, _P, _P, _P,
                                _P, _P, _P]
 _lib.mesh_contract.restype = _I
-_lib.mesh_group_classes.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), _P, _P]
-_lib.mesh_group_classes.restype = _I
 _lib.anneal_group.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double,
-                              ctypes.c_double, _P, _P, _P, _P, _P, _P]
+                              ctypes.c_double, _P, _I64, _P, _P, _P, _P, _P, _P, _P]
 _lib.anneal_group.restype = _I
 
 
@@ -376,17 +375,12 @@ def mesh_contract(desc: MeshDesc, xy: int, eps: float, tri_out: int, n_triangles
                               _P(old_to_new), _P(n_contracted)))
 
 
-def mesh_group_classes(mesh: int, class_off: int = 0, class_v: int = 0) -> int:
-    n = ctypes.c_int32(0)
-    _check(_lib.mesh_group_classes(_P(mesh), ctypes.byref(n), _P(class_off), _P(class_v)))
-    return n.value
-
-
 def anneal_group(mesh: int, xy: int, params: ObjectiveParams, temperature: float, lam: float,
-                 draws: int, u: int, delta: int, status: int, members: int,
-                 stream: int = 0) -> None:
-    _check(_lib.anneal_group(_P(mesh), _P(xy), ctypes.byref(params), temperature, lam, _P(draws),
-                             _P(u), _P(delta), _P(status), _P(members), _P(stream)))
+                 centres: int, n: int, draws: int, u: int, delta: int, status: int, members: int,
+                 rounds: int, stream: int = 0) -> None:
+    _check(_lib.anneal_group(_P(mesh), _P(xy), ctypes.byref(params), temperature, lam,
+                             _P(centres), n, _P(draws), _P(u), _P(delta), _P(status), _P(members),
+                             _P(rounds), _P(stream)))
 
 
 def mesh_free(mesh: int) -> None:

@@ -28,6 +28,8 @@
 #include <string>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "ccsp_objective.h"
 #include "exact.hpp"
 #include "walk.hpp"
@@ -624,83 +626,250 @@ anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
   }
 }
 
-constexpr int kGroupMax = 16;  // members of a group move at most
+// ---- group moves (Sec. 3.2.3)
+//
+// The group of centre c is every movable vertex within distance d of it (a range query on a
+// uniform grid of the current positions, as the paper does), with no limit on its size. A sweep
+// runs in rounds. In a round every pending group finds its members and claims, by the lowest
+// centre index (atomicMin): the vertices within three edges of its members, and the grid cells
+// of its query disc and of its members' positions before and after the move. A group that holds
+// all its claims moves; the others wait for the next round. Two groups that move in one round
+// are therefore more than six edges apart (a move writes positions and edge scratch within one
+// edge of its members and reads within four), and neither moves a vertex into or out of the
+// other's disc: they commute, and the sweep equals the sequential chain over the centres in the
+// order (round, index).
 
-// One class of group moves (Sec. 3.2.3): the centres (internal ids) are pairwise more than seven
-// edges apart, so that a group's writes (within two edges of its centre) never meet another
-// group's reads (within five). The group of centre c: c, then its movable neighbours within
-// d = (0.5 + 4.5 r) eps, by increasing caller id (at most kGroupMax members). Every member moves
-// by (lambda * sqrt(area)) * xi, projected when constrained, where area sums the triangles holding
-// any member, each at the first member (in order) that it holds, a member's triangles in caller
-// order. The members are moved one after another, each with its change of f against the
-// positions and scratch its predecessors left, so that the changes add up to the change of f of
-// the whole move. Valid when every triangle of every member is strictly counter-clockwise at the
-// end; rejected or invalid moves are undone from xy_out, which holds the positions before them.
+constexpr double kQueryWiden = 1.0 + 0x1p-40;  // query extents, widened against rounding
+
+struct VGrid {
+  double x0, y0, inv;      // cell of p: floor((p - p0) * inv), clamped to the grid
+  int gx, gy;
+  const int32_t* start;    // gx * gy + 1 offsets into vert
+  const int32_t* vert;     // internal vertex ids, cell by cell
+};
+
+// Clamped (so that a range stays a superset of the cells of the points in it) and monotone.
+__device__ __forceinline__ int clamp_cell(double f, int g) {
+  if (!(f > 0.0)) return 0;
+  if (f >= (double)(g - 1)) return g - 1;
+  return (int)f;
+}
+
+__device__ __forceinline__ int cell_of(const VGrid& g, double2 q) {
+  return clamp_cell((q.y - g.y0) * g.inv, g.gy) * g.gx + clamp_cell((q.x - g.x0) * g.inv, g.gx);
+}
+
+// f(cell) for every cell meeting the square of half-side r around q.
+template <class F>
+__device__ __forceinline__ void for_cells(const VGrid& g, double2 q, double r, F&& f) {
+  const int x0 = clamp_cell((q.x - r - g.x0) * g.inv, g.gx);
+  const int x1 = clamp_cell((q.x + r - g.x0) * g.inv, g.gx);
+  const int y0 = clamp_cell((q.y - r - g.y0) * g.inv, g.gy);
+  const int y1 = clamp_cell((q.y + r - g.y0) * g.inv, g.gy);
+  for (int cy = y0; cy <= y1; ++cy)
+    for (int cx = x0; cx <= x1; ++cx) f(cy * g.gx + cx);
+}
+
+// f(w) for every movable vertex w != c with dist(p_c, p_w) <= d (the distance as for edges).
+template <class F>
+__device__ __forceinline__ void for_members(const MeshDev& m, const VGrid& g, int c, double d,
+                                            F&& f) {
+  const double2 pc = m.xyi[c];
+  for_cells(g, pc, d * kQueryWiden, [&](int cell) {
+    for (int k = g.start[cell], end = g.start[cell + 1]; k < end; ++k) {
+      const int w = g.vert[k];
+      if (w != c && m.vk[w].x != CCSP_VERTEX_ORIGINAL && dist(pc, m.xyi[w]) <= d) f(w);
+    }
+  });
+}
+
+// f(x) for every vertex within three edges of v (with repeats).
+template <class F>
+__device__ __forceinline__ void for_hops3(const MeshDev& m, int v, F&& f) {
+  f(v);
+  for (int a = m.adj_off[v], ae = m.adj_off[v + 1]; a < ae; ++a) {
+    const int w = m.adj[a].x;
+    f(w);
+    for (int b = m.adj_off[w], be = m.adj_off[w + 1]; b < be; ++b) {
+      const int x = m.adj[b].x;
+      f(x);
+      for (int e = m.adj_off[x], ee = m.adj_off[x + 1]; e < ee; ++e) f(m.adj[e].x);
+    }
+  }
+}
+
+// The displacement D projected for a CONSTRAINED vertex v (as for single-vertex moves).
+__device__ __forceinline__ double2 member_disp(const MeshDev& m, int v, double2 D) {
+  const int2 kl = m.vk[v];
+  if (kl.x != CCSP_VERTEX_CONSTRAINED) return D;
+  const int2 ends = m.prim_v[kl.y];
+  const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
+  const double ex = b.x - a.x, ey = b.y - a.y;
+  const double s = (D.x * ex + D.y * ey) / (ex * ex + ey * ey);
+  return make_double2(s * ex, s * ey);
+}
+
 __global__ void __launch_bounds__(kThreads)
-anneal_group_class(MeshDev m, Par p, double temperature, double lambda,
-                   double2* __restrict__ xy_out, const int32_t* __restrict__ cls,
-                   const double2* __restrict__ draws, const double* __restrict__ u, int n,
-                   double* __restrict__ delta, int32_t* __restrict__ status,
-                   int32_t* __restrict__ members, unsigned long long* __restrict__ accepted) {
-  __shared__ int snb[kLdsNbrs * kThreads];
-  __shared__ int smem[kGroupMax * kThreads];
+vgrid_count(MeshDev m, VGrid g, int32_t* __restrict__ cnt) {
+  const int v = blockIdx.x * kThreads + threadIdx.x;
+  if (v < m.nv) atomicAdd(&cnt[cell_of(g, m.xyi[v])], 1);
+}
+
+__global__ void __launch_bounds__(kThreads)
+vgrid_fill(MeshDev m, VGrid g, int32_t* __restrict__ cursor, int32_t* __restrict__ vert) {
+  const int v = blockIdx.x * kThreads + threadIdx.x;
+  if (v >= m.nv) return;
+  const int cell = cell_of(g, m.xyi[v]);
+  vert[g.start[cell] + atomicAdd(&cursor[cell], 1)] = v;
+}
+
+// Centres by caller id to internal ids; a centre that is not a movable vertex is done at once
+// (status CCSP_MOVE_BAD or CCSP_MOVE_FIXED, round -1).
+__global__ void __launch_bounds__(kThreads)
+group_setup(MeshDev m, const int32_t* __restrict__ centres, int n, int32_t* __restrict__ gcen,
+            uint8_t* __restrict__ done, double* __restrict__ delta, int32_t* __restrict__ status,
+            int32_t* __restrict__ members, int32_t* __restrict__ round) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  bool took = false;
-  if (i < n) {
-    int* mem = smem + threadIdx.x;  // stride kThreads
-    const int c = cls[i];
-    const double2 xi = draws[2 * i], rr = draws[2 * i + 1];
-    const double dd = (0.5 + 4.5 * rr.x) * p.eps;
-    const double2 pc = m.xyi[c];
-    int nm = 1;
-    mem[0] = c;
-    {
-      const int a0 = m.adj_off[c], a1 = m.adj_off[c + 1];
-      int last = -1;
-      for (int step = a0; step < a1; ++step) {  // neighbours by increasing caller id
-        int w = -1, cw = 0x7fffffff;
-        for (int j = a0; j < a1; ++j) {
-          const int x = m.adj[j].x, cx = m.vold[x];
-          if (cx > last && cx < cw) {
-            cw = cx;
-            w = x;
-          }
-        }
-        last = cw;
-        if (nm < kGroupMax && m.vk[w].x != CCSP_VERTEX_ORIGINAL && dist(pc, m.xyi[w]) <= dd)
-          mem[kThreads * nm++] = w;
-      }
+  if (i >= n) return;
+  const int cv = centres[i];
+  const bool bad = cv < 0 || cv >= m.nv;
+  const bool fixed = !bad && m.vk[m.vnew[cv]].x == CCSP_VERTEX_ORIGINAL;
+  gcen[i] = bad || fixed ? -1 : m.vnew[cv];
+  done[i] = bad || fixed ? 1 : 0;
+  if (bad || fixed) {
+    status[i] = bad ? CCSP_MOVE_BAD : CCSP_MOVE_FIXED;
+    delta[i] = __builtin_huge_val();
+    members[i] = 0;
+    round[i] = -1;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+group_count(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
+            const double2* __restrict__ draws, const uint8_t* __restrict__ done, int n,
+            int32_t* __restrict__ cnt) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  int k = 0;
+  if (!done[i]) {
+    const double d = (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps;
+    k = 1;
+    for_members(m, g, gcen[i], d, [&](int) { ++k; });
+  }
+  cnt[i] = k;
+}
+
+// Members (the centre, then the others by increasing caller id) into mem[off[i]..], the move's
+// displacement, and the claims.
+__global__ void __launch_bounds__(kThreads)
+group_claim(MeshDev m, VGrid g, Par p, double lambda, const int32_t* __restrict__ gcen,
+            const double2* __restrict__ draws, const uint8_t* __restrict__ done, int n,
+            const int32_t* __restrict__ off, int32_t* __restrict__ mem,
+            double2* __restrict__ disp, int32_t* __restrict__ own_v,
+            int32_t* __restrict__ own_c) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n || done[i]) return;
+  const int c = gcen[i];
+  const double d = (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps;
+  int* M = mem + off[i];
+  int nm = 1;
+  M[0] = c;
+  for_members(m, g, c, d, [&](int w) {
+    const int cw = m.vold[w];
+    int j = nm++;
+    while (j > 1 && m.vold[M[j - 1]] > cw) {
+      M[j] = M[j - 1];
+      --j;
     }
-    double area = 0.0;
-    for (int j = 0; j < nm; ++j) {
-      const int v = mem[kThreads * j];
-      for (int k = m.vtri_off[v], end = m.vtri_off[v + 1]; k < end; ++k) {
-        const int tid = m.vtri[k];
-        const int4 tr = m.tri[tid];
-        bool earlier = false;
-        for (int l = 0; l < j; ++l) {
-          const int w = mem[kThreads * l];
-          earlier = earlier || tr.x == w || tr.y == w || tr.z == w;
-        }
-        if (!earlier) area = area + tri_area(m, tid);
+    M[j] = w;
+  });
+  // area of the triangles holding any member, each at the first member (in order) holding it
+  double area = 0.0;
+  for (int j = 0; j < nm; ++j) {
+    const int v = M[j];
+    for (int k = m.vtri_off[v], end = m.vtri_off[v + 1]; k < end; ++k) {
+      const int tid = m.vtri[k];
+      const int4 tr = m.tri[tid];
+      bool earlier = false;
+      for (int l = 0; l < j; ++l) {
+        const int w = M[l];
+        earlier = earlier || tr.x == w || tr.y == w || tr.z == w;
       }
+      if (!earlier) area = area + tri_area(m, tid);
     }
-    const double k = lambda * sqrt(area);
-    const double2 D = make_double2(k * xi.x, k * xi.y);
+  }
+  const double k = lambda * sqrt(area);
+  const double2 xi = draws[2 * i];
+  const double2 D = make_double2(k * xi.x, k * xi.y);
+  disp[i] = D;
+  auto claim_c = [&](int cell) { atomicMin(&own_c[cell], i); };
+  for_cells(g, m.xyi[c], d * kQueryWiden, claim_c);
+  for (int j = 0; j < nm; ++j) {
+    const int v = M[j];
+    const double2 o = m.xyi[v], dv = member_disp(m, v, D);
+    claim_c(cell_of(g, o));
+    claim_c(cell_of(g, make_double2(o.x + dv.x, o.y + dv.y)));
+    for_hops3(m, v, [&](int x) { atomicMin(&own_v[x], i); });
+  }
+}
+
+// Whether group i holds every claim it made (no position changes during this pass).
+__global__ void __launch_bounds__(kThreads)
+group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
+            const double2* __restrict__ draws, const uint8_t* __restrict__ done, int n,
+            const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
+            const int32_t* __restrict__ mem, const double2* __restrict__ disp,
+            const int32_t* __restrict__ own_v, const int32_t* __restrict__ own_c,
+            uint8_t* __restrict__ won) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  if (done[i]) {
+    won[i] = 0;
+    return;
+  }
+  const int c = gcen[i];
+  const double d = (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps;
+  bool ok = true;
+  auto held_c = [&](int cell) { ok = ok && own_c[cell] == i; };
+  for_cells(g, m.xyi[c], d * kQueryWiden, held_c);
+  const int* M = mem + off[i];
+  const double2 D = disp[i];
+  for (int j = 0; j < cnt[i] && ok; ++j) {
+    const int v = M[j];
+    const double2 o = m.xyi[v], dv = member_disp(m, v, D);
+    held_c(cell_of(g, o));
+    held_c(cell_of(g, make_double2(o.x + dv.x, o.y + dv.y)));
+    for_hops3(m, v, [&](int x) { ok = ok && own_v[x] == i; });
+  }
+  won[i] = ok ? 1 : 0;
+}
+
+// The move of every group that holds its claims: its members moved one after another by D
+// (projected when constrained), each with its change of f against the positions and scratch its
+// predecessors left, so that the changes add up to the change of f of the whole move; valid when
+// every triangle of every member is strictly counter-clockwise at the end; rejected or invalid
+// moves are undone from xy_out, which holds the positions before them.
+__global__ void __launch_bounds__(kThreads)
+group_apply(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out, int n,
+            const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
+            const int32_t* __restrict__ mem, const double2* __restrict__ disp,
+            const double* __restrict__ u, const uint8_t* __restrict__ won, int rnd,
+            uint8_t* __restrict__ done, double* __restrict__ delta,
+            int32_t* __restrict__ status, int32_t* __restrict__ members,
+            int32_t* __restrict__ round, unsigned long long* __restrict__ applied) {
+  __shared__ int snb[kLdsNbrs * kThreads];
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  bool moved = false;
+  if (i < n && won[i]) {
+    moved = true;
+    const int* M = mem + off[i];
+    const int nm = cnt[i];
+    const double2 D = disp[i];
     double df = 0.0;
     for (int j = 0; j < nm; ++j) {
-      const int v = mem[kThreads * j];
-      const double2 o = m.xyi[v];
-      double2 d = D;
-      const int2 kl = m.vk[v];
-      if (kl.x == CCSP_VERTEX_CONSTRAINED) {
-        const int2 ends = m.prim_v[kl.y];
-        const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
-        const double ex = b.x - a.x, ey = b.y - a.y;
-        const double s = (d.x * ex + d.y * ey) / (ex * ex + ey * ey);
-        d = make_double2(s * ex, s * ey);
-      }
-      const double2 q = make_double2(o.x + d.x, o.y + d.y);
+      const int v = M[j];
+      const double2 o = m.xyi[v], dv = member_disp(m, v, D);
+      const double2 q = make_double2(o.x + dv.x, o.y + dv.y);
       double dfj = 0.0;
       move_change<false>(m, m.xyi, p, v, q, snb + threadIdx.x, &dfj);
       df += dfj;
@@ -709,41 +878,71 @@ anneal_group_class(MeshDev m, Par p, double temperature, double lambda,
     }
     bool ok = true;
     for (int j = 0; j < nm && ok; ++j) {
-      const int v = mem[kThreads * j];
+      const int v = M[j];
       for (int k = m.vtri_off[v], end = m.vtri_off[v + 1]; k < end && ok; ++k) {
         const int4 tr = m.tri[m.vtri[k]];
         ok = orient_sign(m.xyi[tr.x], m.xyi[tr.y], m.xyi[tr.z]) > 0;
       }
     }
     int st = CCSP_MOVE_FOLDS;
+    bool took = false;
     if (ok) {
       st = CCSP_MOVE_REJECTED;
       if (df <= 0.0 || u[i] < exp(-df / temperature)) {
         st = CCSP_MOVE_OK;
         took = true;
-        for (int j = 0; j < nm; ++j) {
-          const int v = mem[kThreads * j];
-          xy_out[m.vold[v]] = m.xyi[v];
-        }
+        for (int j = 0; j < nm; ++j) xy_out[m.vold[M[j]]] = m.xyi[M[j]];
       }
     } else {
       df = __builtin_huge_val();
     }
     if (!took) {
-      for (int j = 0; j < nm; ++j) {
-        const int v = mem[kThreads * j];
-        m.xyi[v] = xy_out[m.vold[v]];
-      }
-      for (int j = 0; j < nm; ++j) refresh_scratch(m, p, mem[kThreads * j]);
+      for (int j = 0; j < nm; ++j) m.xyi[M[j]] = xy_out[m.vold[M[j]]];
+      for (int j = 0; j < nm; ++j) refresh_scratch(m, p, M[j]);
     }
     status[i] = st;
     delta[i] = df;
     members[i] = nm;
+    round[i] = rnd;
+    done[i] = 1;
   }
-  if (accepted) {
-    const int cnt = __syncthreads_count(took);
-    if (threadIdx.x == 0 && cnt > 0) atomicAdd(accepted, (unsigned long long)cnt);
+  const int cnt_moved = __syncthreads_count(moved);
+  if (threadIdx.x == 0 && cnt_moved > 0) atomicAdd(applied, (unsigned long long)cnt_moved);
+}
+
+__global__ void __launch_bounds__(kThreads)
+fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// Bounding box of the positions (one workgroup; out: min x, min y, max x, max y).
+__global__ void __launch_bounds__(kThreads)
+bbox_kernel(MeshDev m, double* __restrict__ out) {
+  __shared__ double sh[4][kThreads];
+  double a = __builtin_huge_val(), b = a, c = -a, e = -a;
+  for (int v = threadIdx.x; v < m.nv; v += kThreads) {
+    const double2 q = m.xyi[v];
+    a = fmin(a, q.x);
+    b = fmin(b, q.y);
+    c = fmax(c, q.x);
+    e = fmax(e, q.y);
   }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  sh[2][threadIdx.x] = c;
+  sh[3][threadIdx.x] = e;
+  __syncthreads();
+  for (int s2 = kThreads / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) {
+      sh[0][threadIdx.x] = fmin(sh[0][threadIdx.x], sh[0][threadIdx.x + s2]);
+      sh[1][threadIdx.x] = fmin(sh[1][threadIdx.x], sh[1][threadIdx.x + s2]);
+      sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + s2]);
+      sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + s2]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ void zero_counter(unsigned long long* __restrict__ c) {
@@ -763,9 +962,6 @@ struct MovableMesh {
   std::vector<int64_t> class_off;  // mesh_classes, computed on the first call
   std::vector<int32_t> class_v;    // caller ids, class by class
   int32_t* class_dev = nullptr;    // the same vertices, internal ids, on the device
-  std::vector<int64_t> gclass_off;  // mesh_group_classes: centres more than seven edges apart
-  std::vector<int32_t> gclass_v;
-  int32_t* gclass_dev = nullptr;
   void* sched = nullptr;           // anneal_schedule: delta and status per movable vertex, counter
 };
 
@@ -811,6 +1007,22 @@ int check_device(const MovableMesh* m) {
 }
 
 }  // namespace
+
+// Device scratch of one group sweep, released on every return.
+struct GroupScratch {
+  std::vector<void*> blocks;
+  ~GroupScratch() {
+    for (void* b : blocks) (void)hipFree(b);
+  }
+  template <class T>
+  hipError_t get(T** p, size_t count) {
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) blocks.push_back(q);
+    *p = static_cast<T*>(q);
+    return e;
+  }
+};
 
 extern "C" {
 
@@ -1256,9 +1468,6 @@ int ensure_classes(MovableMesh* mesh) {
   return build_classes(mesh, 4, mesh->class_off, mesh->class_v, mesh->class_dev);
 }
 
-int ensure_group_classes(MovableMesh* mesh) {
-  return build_classes(mesh, 7, mesh->gclass_off, mesh->gclass_v, mesh->gclass_dev);
-}
 
 int mesh_classes(MovableMesh* mesh, int32_t* n_classes, int64_t* class_off, int32_t* class_v) {
   if (!mesh || !n_classes) return fail(CCSP_E_ARG, "mesh_classes: null argument");
@@ -1269,23 +1478,18 @@ int mesh_classes(MovableMesh* mesh, int32_t* n_classes, int64_t* class_off, int3
   return CCSP_OK;
 }
 
-int mesh_group_classes(MovableMesh* mesh, int32_t* n_classes, int64_t* class_off,
-                       int32_t* class_v) {
-  if (!mesh || !n_classes) return fail(CCSP_E_ARG, "mesh_group_classes: null argument");
-  if (int r = ensure_group_classes(mesh)) return r;
-  *n_classes = (int32_t)mesh->gclass_off.size() - 1;
-  if (class_off) std::memcpy(class_off, mesh->gclass_off.data(), 8 * mesh->gclass_off.size());
-  if (class_v) std::memcpy(class_v, mesh->gclass_v.data(), 4 * mesh->gclass_v.size());
-  return CCSP_OK;
-}
-
 int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, double temperature,
-                 double lambda, const double* draws, const double* u, double* delta,
-                 int32_t* status, int32_t* members, void* stream) {
-  if (!mesh || !xy || !draws || !u || !delta || !status || !members)
+                 double lambda, const int32_t* centres, int64_t n, const double* draws,
+                 const double* u, double* delta, int32_t* status, int32_t* members,
+                 int32_t* round, void* stream) {
+  if (!mesh || !xy || (n > 0 && (!centres || !draws || !u || !delta || !status || !members ||
+                                 !round)))
     return fail(CCSP_E_ARG, "anneal_group: null argument");
+  if (n < 0 || n >= (int64_t(1) << 30)) return fail(CCSP_E_ARG, "anneal_group: bad centre count");
   if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)draws & 15) != 0 || ((uintptr_t)u & 7) != 0 ||
-      ((uintptr_t)delta & 7) != 0 || ((uintptr_t)status & 3) != 0 || ((uintptr_t)members & 3) != 0)
+      ((uintptr_t)delta & 7) != 0 || ((uintptr_t)status & 3) != 0 ||
+      ((uintptr_t)members & 3) != 0 || ((uintptr_t)round & 3) != 0 ||
+      ((uintptr_t)centres & 3) != 0)
     return fail(CCSP_E_ARG, "anneal_group: misaligned buffer");
   if (!check_params(params)) return fail(CCSP_E_ARG, "anneal_group: invalid parameters");
   if (!(temperature >= 0) || !std::isfinite(temperature))
@@ -1293,25 +1497,118 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   if (!(lambda >= 0) || !std::isfinite(lambda))
     return fail(CCSP_E_ARG, "anneal_group: lambda must be finite and >= 0");
   if (int r = check_device(mesh)) return r;
-  if (int r = ensure_group_classes(mesh)) return r;
+  if (n == 0) return CCSP_OK;
   const ccsp::MeshDev& d = mesh->d;
   const ccsp::Par p = to_par(params);
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
+  const int N = (int)n;
+  const int T = ccsp::kThreads;
+  const unsigned gb = (unsigned)((N + T - 1) / T), vb = (unsigned)((d.nv + T - 1) / T);
+  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(T), 0, s, d,
                      (const double2*)xy);
-  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
-                     d.partial);
-  const std::vector<int64_t>& off = mesh->gclass_off;
-  for (size_t c = 0; c + 1 < off.size(); ++c) {
-    const int n = (int)(off[c + 1] - off[c]);
-    if (n == 0) continue;
-    hipLaunchKernelGGL(ccsp::anneal_group_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
-                       dim3(ccsp::kThreads), 0, s, d, p, temperature, lambda, (double2*)xy,
-                       mesh->gclass_dev + off[c], (const double2*)draws + 2 * off[c], u + off[c],
-                       n, delta + off[c], status + off[c], members + off[c],
-                       (unsigned long long*)nullptr);
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(T), 0, s, d, p, d.partial);
+  GroupScratch gs;
+  double* box = nullptr;
+  unsigned long long* applied = nullptr;
+  hipError_t e = gs.get(&box, 4);
+  if (e == hipSuccess) e = gs.get(&applied, 1);
+  if (e != hipSuccess) return fail(CCSP_E_OOM, "anneal_group: scratch allocation failed");
+  hipLaunchKernelGGL(ccsp::bbox_kernel, dim3(1), dim3(T), 0, s, d, box);
+  double hb[4];
+  e = hipMemcpyAsync(hb, box, sizeof hb, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "anneal_group: bounding box");
+  // grid cells of side at least 5 eps (the largest query radius), at most 1024 per side
+  const double ext = std::max(hb[2] - hb[0], hb[3] - hb[1]);
+  double h = std::max(5.0 * p.eps, ext / 1024.0);
+  if (!(h > 0) || !std::isfinite(h)) h = 1.0;
+  ccsp::VGrid g{};
+  g.x0 = std::isfinite(hb[0]) ? hb[0] : 0.0;
+  g.y0 = std::isfinite(hb[1]) ? hb[1] : 0.0;
+  g.inv = 1.0 / h;
+  g.gx = (int)std::min(1024.0, std::max(1.0, std::floor((hb[2] - g.x0) * g.inv) + 1.0));
+  g.gy = (int)std::min(1024.0, std::max(1.0, std::floor((hb[3] - g.y0) * g.inv) + 1.0));
+  if (!(g.gx >= 1)) g.gx = 1;
+  if (!(g.gy >= 1)) g.gy = 1;
+  const int ncells = g.gx * g.gy;
+  int32_t *gcen = nullptr, *cnt = nullptr, *off = nullptr, *start = nullptr, *cursor = nullptr;
+  int32_t *vert = nullptr, *own_v = nullptr, *own_c = nullptr, *mem = nullptr;
+  uint8_t *done = nullptr, *won = nullptr;
+  double2* disp = nullptr;
+  e = gs.get(&gcen, N);
+  if (e == hipSuccess) e = gs.get(&cnt, (size_t)N + 1);
+  if (e == hipSuccess) e = gs.get(&off, (size_t)N + 1);
+  if (e == hipSuccess) e = gs.get(&start, (size_t)ncells + 1);
+  if (e == hipSuccess) e = gs.get(&cursor, (size_t)ncells + 1);
+  if (e == hipSuccess) e = gs.get(&vert, d.nv);
+  if (e == hipSuccess) e = gs.get(&own_v, d.nv);
+  if (e == hipSuccess) e = gs.get(&own_c, ncells);
+  if (e == hipSuccess) e = gs.get(&done, N);
+  if (e == hipSuccess) e = gs.get(&won, N);
+  if (e == hipSuccess) e = gs.get(&disp, N);
+  size_t scan_bytes = 0;
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, cnt, off,
+                                         std::max(N, ncells) + 1);
+  void* scan_tmp = nullptr;
+  if (e == hipSuccess) e = gs.get(reinterpret_cast<unsigned char**>(&scan_tmp), scan_bytes);
+  if (e != hipSuccess) return fail(CCSP_E_OOM, "anneal_group: scratch allocation failed");
+  size_t mem_cap = 0;
+  g.start = start;
+  g.vert = vert;
+  hipLaunchKernelGGL(ccsp::group_setup, dim3(gb), dim3(T), 0, s, d, centres, N, gcen, done, delta,
+                     status, members, round);
+  std::vector<uint8_t> hd(N);
+  e = hipMemcpyAsync(hd.data(), done, N, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "anneal_group: setup");
+  int64_t remaining = 0;
+  for (uint8_t x : hd) remaining += x ? 0 : 1;
+  for (int rnd = 0; remaining > 0; ++rnd) {
+    if (rnd > N) return fail(CCSP_E_HIP, "anneal_group: no group could move in a round");
+    // the grid of the current positions
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3((ncells + T) / T), dim3(T), 0, s, cursor,
+                       (int64_t)ncells + 1, 0);
+    hipLaunchKernelGGL(ccsp::vgrid_count, dim3(vb), dim3(T), 0, s, d, g, cursor);
+    e = hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, cursor, start, ncells + 1, s);
+    if (e != hipSuccess) return hip_fail(e, "anneal_group: grid scan");
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3((ncells + T) / T), dim3(T), 0, s, cursor,
+                       (int64_t)ncells + 1, 0);
+    hipLaunchKernelGGL(ccsp::vgrid_fill, dim3(vb), dim3(T), 0, s, d, g, cursor, vert);
+    // group sizes, their offsets, and room for the members
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3((N + T) / T), dim3(T), 0, s, cnt, (int64_t)N + 1, 0);
+    hipLaunchKernelGGL(ccsp::group_count, dim3(gb), dim3(T), 0, s, d, g, p, gcen,
+                       (const double2*)draws, done, N, cnt);
+    e = hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, cnt, off, N + 1, s);
+    if (e != hipSuccess) return hip_fail(e, "anneal_group: member scan");
+    int32_t total = 0;
+    e = hipMemcpyAsync(&total, off + N, sizeof total, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "anneal_group: member count");
+    if ((size_t)total > mem_cap) {
+      mem_cap = std::max<size_t>((size_t)total, 2 * mem_cap);
+      if (gs.get(&mem, mem_cap) != hipSuccess)
+        return fail(CCSP_E_OOM, "anneal_group: member buffer allocation failed");
+    }
+    // claims, their check, and the moves of the groups holding all of theirs
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3(vb), dim3(T), 0, s, own_v, (int64_t)d.nv, 0x7fffffff);
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3((ncells + T - 1) / T), dim3(T), 0, s, own_c,
+                       (int64_t)ncells, 0x7fffffff);
+    hipLaunchKernelGGL(ccsp::group_claim, dim3(gb), dim3(T), 0, s, d, g, p, lambda, gcen,
+                       (const double2*)draws, done, N, off, mem, disp, own_v, own_c);
+    hipLaunchKernelGGL(ccsp::group_check, dim3(gb), dim3(T), 0, s, d, g, p, gcen,
+                       (const double2*)draws, done, N, off, cnt, mem, disp, own_v, own_c, won);
+    hipLaunchKernelGGL(ccsp::zero_counter, dim3(1), dim3(64), 0, s, applied);
+    hipLaunchKernelGGL(ccsp::group_apply, dim3(gb), dim3(T), 0, s, d, p, temperature,
+                       (double2*)xy, N, off, cnt, mem, disp, u, won, rnd, done, delta, status,
+                       members, round, applied);
+    unsigned long long got = 0;
+    e = hipMemcpyAsync(&got, applied, sizeof got, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "anneal_group: round");
+    if (got == 0) return fail(CCSP_E_HIP, "anneal_group: no group could move in a round");
+    remaining -= (int64_t)got;
   }
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_group: launch");
 }
 
@@ -1486,7 +1783,6 @@ void mesh_free(MovableMesh* mesh) {
   if (!mesh) return;
   if (mesh->sched) (void)hipFree(mesh->sched);
   if (mesh->class_dev) (void)hipFree(mesh->class_dev);
-  if (mesh->gclass_dev) (void)hipFree(mesh->gclass_dev);
   if (mesh->mem) (void)hipFree(mesh->mem);
   delete mesh;
 }

@@ -168,7 +168,7 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
             if kind_k == "group":
                 r = proposal_draws(m, "group")
                 r[:, :2] = unit_draws(m)
-                _, st, _ = gm.group_sweep(X, p, temps[k], lam, r, uniforms(m))
+                _, st, _, _ = gm.group_sweep(X, p, temps[k], lam, r, uniforms(m))
             else:
                 _, st = gm.propose(X, p, temps[k], kind_k, proposal_draws(m, kind_k),
                                    uniforms(m))

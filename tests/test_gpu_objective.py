@@ -10,6 +10,7 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 import scenegen as sg
 from oracle import objective as ob
 
@@ -571,34 +572,23 @@ def test_propose_at_scale(ccsp, grid, kind):
             assert np.array_equal(xy1[v], mesh.xy[v])
 
 
-@pytest.mark.parametrize("state,temperature,eps", [("subdivided", 1e-3, 0.03),
-                                                   ("clustered", 1e-4, 0.03),
-                                                   ("clustered", 0.0, 0.1)])
-def test_group_sweep_equals_sequential_chain(ccsp, tiny, state, temperature, eps):
-    """A sweep of group moves (Sec. 3.2.3) equals the checker's chain over the same centres and
-    draws: positions bit for bit, statuses and group sizes equal, changes of f within rounding
-    (the GPU adds the members' changes one by one, the checker differences f as a whole)."""
-    mesh, om = tiny
-    p = ob.Params(eps)
-    xy0 = mesh.xy.copy() if state == "subdivided" else _clustered(mesh, om, ob.Params(0.03), 9)
-    rng = np.random.default_rng(13)
-    lam = 0.05
-    with ccsp.MovableMesh.from_mesh(mesh) as gm:
-        cls = gm.group_classes()
-        order = np.concatenate(cls)
-        assert len(cls) > len(gm.classes())
-        M = order.shape[0]
-        draws = np.zeros((M, 4))
-        draws[:, :2] = rng.standard_normal((M, 2))
-        draws[:, 2] = rng.random(M)
-        u = rng.random(M)
-        X = torch.from_numpy(xy0.copy()).to(DEV)
-        d, st, mem = gm.group_sweep(X, _params(ccsp, p), temperature, lam,
-                                    torch.from_numpy(draws).to(DEV), torch.from_numpy(u).to(DEV))
-        xy_g, st_g, df_g, mem_g = (X.cpu().numpy(), st.cpu().numpy(), d.cpu().numpy(),
-                                   mem.cpu().numpy())
-    xy_r, st_r, df_r, margin, size = ob.group_chain(om, xy0, p, temperature, lam, order,
-                                                    draws[:, :2], draws[:, 2], u)
+def _group_sweep_vs_chain(ccsp, gm, om, xy0, p, temperature, lam, draws, u, centres=None):
+    """A GPU group sweep against the checker's chain over the centres in the order the GPU made
+    the moves, (round, index): positions bit for bit, statuses and group sizes equal, changes of
+    f within rounding (the GPU adds the members' changes one by one, the checker differences f as
+    a whole). Returns (statuses, sizes, rounds) per centre."""
+    X = torch.from_numpy(xy0.copy()).to(DEV)
+    d, st, mem, rnd = gm.group_sweep(X, _params(ccsp, p), temperature, lam,
+                                     torch.from_numpy(draws).to(DEV), torch.from_numpy(u).to(DEV),
+                                     centres=centres)
+    xy_g, st_g, df_g, mem_g, rnd_g = (X.cpu().numpy(), st.cpu().numpy(), d.cpu().numpy(),
+                                      mem.cpu().numpy(), rnd.cpu().numpy())
+    cen = gm.movable if centres is None else np.asarray(centres)
+    order = np.lexsort((np.arange(cen.shape[0]), rnd_g))
+    assert (rnd_g >= 0).all()
+    xy_r, st_r, df_r, margin, size = ob.group_chain(om, xy0, p, temperature, lam, cen[order],
+                                                    draws[order, :2], draws[order, 2], u[order])
+    st_g, df_g, mem_g = st_g[order], df_g[order], mem_g[order]
     valid = (st_r == ob.ACCEPTED) | (st_r == ob.REJECTED)
     # a decision within rounding of its threshold is only comparable when both sides computed the
     # same change exactly (a cluster whose edges all weigh 0 moves with a change of exactly 0)
@@ -610,37 +600,93 @@ def test_group_sweep_equals_sequential_chain(ccsp, tiny, state, temperature, eps
     fin = np.isfinite(df_r)
     assert np.array_equal(np.isfinite(df_g), fin)
     assert np.allclose(df_g[fin], df_r[fin], rtol=1e-9, atol=1e-12)
-    assert (st_r == ob.ACCEPTED).sum() > 5 and (size > 1).sum() > 20
+    return st_r, size, rnd_g
 
 
-def test_group_cap_equals_checker(ccsp):
-    """A free centre with twenty free neighbours: its group keeps sixteen members, on the GPU as in
-    the checker, and the sweep over the fan equals the checker's chain."""
-    n = 20
-    ring = [[math.cos(2 * math.pi * k / n), math.sin(2 * math.pi * k / n)] for k in range(n)]
-    xy0 = np.array([[0.0, 0.0]] + ring)
-    tv = np.array([[0, 1 + k, 1 + (k + 1) % n] for k in range(n)], dtype=np.int32)
-    kind = np.full(n + 1, ob.FREE, dtype=np.int32)
-    line = np.zeros(n + 1, dtype=np.int32)
-    prim_v = np.zeros((0, 2), dtype=np.int32)
-    om = ob.Mesh(tv, kind, line, prim_v)
-    p = ob.Params(2.0)
-    rng = np.random.default_rng(21)
-    with ccsp.MovableMesh(tv, kind, line, prim_v) as gm:
-        order = np.concatenate(gm.group_classes())
-        M = order.shape[0]
+@pytest.mark.parametrize("state,temperature,eps", [("subdivided", 1e-3, 0.03),
+                                                   ("clustered", 1e-4, 0.03),
+                                                   ("clustered", 0.0, 0.1)])
+def test_group_sweep_equals_sequential_chain(ccsp, tiny, state, temperature, eps):
+    """A sweep of group moves (Sec. 3.2.3, every movable vertex within d of the centre) equals the
+    checker's chain over the same centres and draws, in the order the GPU made the moves."""
+    mesh, om = tiny
+    p = ob.Params(eps)
+    xy0 = mesh.xy.copy() if state == "subdivided" else _clustered(mesh, om, ob.Params(0.03), 9)
+    rng = np.random.default_rng(13)
+    with ccsp.MovableMesh.from_mesh(mesh) as gm:
+        M = gm.movable.shape[0]
         draws = np.zeros((M, 4))
-        draws[:, :2] = 0.02 * rng.standard_normal((M, 2))
-        draws[:, 2] = 0.99
+        draws[:, :2] = rng.standard_normal((M, 2))
+        draws[:, 2] = rng.random(M)
         u = rng.random(M)
-        X = torch.from_numpy(xy0.copy()).to(DEV)
-        d, st, mem = gm.group_sweep(X, _params(ccsp, p), 1e-3, 0.05,
-                                    torch.from_numpy(draws).to(DEV), torch.from_numpy(u).to(DEV))
-        xy_g, st_g, mem_g = X.cpu().numpy(), st.cpu().numpy(), mem.cpu().numpy()
-    xy_r, st_r, _, margin, size = ob.group_chain(om, xy0, p, 1e-3, 0.05, order, draws[:, :2],
-                                                 draws[:, 2], u)
-    assert size[list(order).index(0)] == ob.GROUP_MAX
-    assert np.array_equal(mem_g, size) and np.array_equal(st_g, st_r)
-    valid = (st_r == ob.ACCEPTED) | (st_r == ob.REJECTED)
-    assert (margin[valid] > 1e-10).all()
-    assert np.array_equal(xy_g, xy_r)
+        st_r, size, rnd = _group_sweep_vs_chain(ccsp, gm, om, xy0, p, temperature, 0.05, draws, u)
+    assert (st_r == ob.ACCEPTED).sum() > 5 and (size > 1).sum() > 20 and rnd.max() >= 1
+    # groups that reach past the centre's neighbours occur (the paper's definition)
+    far = 0
+    for i, c in enumerate(gm.movable[:400]):
+        d = (0.5 + 4.5 * draws[i, 2]) * p.eps
+        mem = ob.group_members(om, xy0, int(c), d)
+        far += any(not om.has_edge(int(c), w) for w in mem[1:])
+    assert far > 0 or state == "subdivided"
+
+
+def _fan_mesh(n_ring, n_outer):
+    """A free centre 0 inside a ring of n_ring free vertices at radius 1, with n_outer free
+    vertices at radius 1.5 hanging off the ring and an ORIGINAL frame around everything."""
+    ring = [[math.cos(2 * math.pi * k / n_ring), math.sin(2 * math.pi * k / n_ring)]
+            for k in range(n_ring)]
+    step = n_ring // n_outer
+    outer = [[1.5 * math.cos(2 * math.pi * (j * step + 0.5) / n_ring),
+              1.5 * math.sin(2 * math.pi * (j * step + 0.5) / n_ring)] for j in range(n_outer)]
+    frame = [[4.0 * math.cos(2 * math.pi * k / 8), 4.0 * math.sin(2 * math.pi * k / 8)]
+             for k in range(8)]
+    xy = np.array([[0.0, 0.0]] + ring + outer + frame)
+    return xy
+
+
+def test_large_and_far_reaching_groups(ccsp):
+    """Groups of up to thirty-one members, ten of them two edges from their centre (no edge joins
+    them to it), repeated centres and a centre that cannot move: the GPU equals the checker's
+    chain. The mesh is the Delaunay triangulation of the points (scipy), counter-clockwise, with
+    the octagon frame ORIGINAL and every other vertex free."""
+    spatial = pytest.importorskip("scipy.spatial")
+    xy = _fan_mesh(20, 10)
+    n = xy.shape[0]
+    frame = list(range(n - 8, n))
+    tri = spatial.Delaunay(xy).simplices.astype(np.int32)
+    a, b, c = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    cw = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]) < 0
+    tri[cw] = tri[cw][:, [0, 2, 1]]
+    assert all(oracle.orient(*xy[t]) > 0 for t in tri)
+    kind = np.full(n, ob.FREE, dtype=np.int32)
+    kind[frame] = ob.ORIGINAL
+    line = np.zeros(n, dtype=np.int32)
+    prim_v = np.array([[frame[k], frame[(k + 1) % 8]] for k in range(8)], dtype=np.int32)
+    om = ob.Mesh(tri, kind, line, prim_v)
+    p = ob.Params(0.5)  # d up to 2.5: the whole cluster
+    rng = np.random.default_rng(21)
+    with ccsp.MovableMesh(tri, kind, line, prim_v) as gm:
+        M = gm.movable.shape[0]
+        for rep in range(3):
+            draws = np.zeros((M, 4))
+            draws[:, :2] = 0.02 * rng.standard_normal((M, 2))
+            draws[:, 2] = rng.random(M)
+            draws[0, 2] = 0.99
+            u = rng.random(M)
+            st_r, size, rnd = _group_sweep_vs_chain(ccsp, gm, om, xy, p, 1e-3, 0.05, draws, u)
+            assert size.max() >= 20 and rnd.max() >= 3
+        # repeated centres, in any order, and a vertex that is not movable
+        cen = np.array([0, 5, 0, frame[0], 3, 0], dtype=np.int32)
+        draws = np.zeros((cen.shape[0], 4))
+        draws[:, :2] = 0.02 * rng.standard_normal((cen.shape[0], 2))
+        draws[:, 2] = 0.9
+        u = rng.random(cen.shape[0])
+        X = torch.from_numpy(xy.copy()).to(DEV)
+        d, st, mem, rnd = gm.group_sweep(X, _params(ccsp, p), 1e-3, 0.05,
+                                         torch.from_numpy(draws).to(DEV),
+                                         torch.from_numpy(u).to(DEV), centres=cen)
+        st, rnd = st.cpu().numpy(), rnd.cpu().numpy()
+        assert st[3] == ccsp.binding.CCSP_MOVE_FIXED and rnd[3] == -1
+        keep = np.array([0, 1, 2, 4, 5])
+        _group_sweep_vs_chain(ccsp, gm, om, xy, p, 1e-3, 0.05, draws[keep], u[keep],
+                              centres=cen[keep])

@@ -171,8 +171,9 @@ def test_zero_temperature_chain_never_raises_f(kind):
 
 
 def test_group_members_and_area():
-    """Members are the centre and its movable neighbours within d; the group area counts the
-    triangles two members share once (star areas added, shared ones taken off)."""
+    """With d just above the two nearest neighbours' distance, no other vertex comes that close in
+    a CDT-based mesh, so the members are the centre and those movable neighbours; the group area
+    counts the triangles two members share once (star areas added, shared ones taken off)."""
     mesh = sg.subdivide(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     xy = mesh.xy
@@ -183,7 +184,10 @@ def test_group_members_and_area():
         d = float(np.sort(lens)[1]) * (1 + 1e-9)  # the two nearest neighbours
         mem = ob.group_members(m, xy, int(c), d)
         want = [int(w) for w, l in zip(nb, lens) if l <= d and mesh.kind[w] != ob.ORIGINAL]
-        assert mem == [int(c)] + want
+        if mem != [int(c)] + want:  # a vertex closer than a neighbour without an edge to c
+            far = set(mem) - set(want) - {int(c)}
+            assert far and all(not m.has_edge(int(c), w) for w in far)
+            continue
         if len(mem) == 2:
             w = mem[1]
             shared = [t for t in range(m.tri_v.shape[0]) if c in m.tri_v[t] and w in m.tri_v[t]]
@@ -238,12 +242,49 @@ def test_group_moves_rigidly():
     assert seen > 20
 
 
-def test_group_is_capped_at_sixteen_members():
-    """A centre with twenty movable neighbours within d keeps itself and its first fifteen."""
+def _fan_chain(k, step):
+    """Free vertices 0..k-1 on the x axis at spacing `step` (a contracted chain) under an apex of
+    original vertices: vertex i joins only its chain neighbours and the apexes above and below,
+    so 0 and 2 share no edge. Apexes k (above) and k+1 (below) are ORIGINAL."""
+    xy = np.array([[i * step, 0.0] for i in range(k)] + [[0.5 * (k - 1) * step, 5.0],
+                                                          [0.5 * (k - 1) * step, -5.0]])
+    up, down = k, k + 1
+    tv = [[i, i + 1, up] for i in range(k - 1)] + [[i + 1, i, down] for i in range(k - 1)]
+    kind = np.array([ob.FREE] * k + [ob.ORIGINAL] * 2)
+    m = ob.Mesh(np.array(tv), kind, np.zeros(k + 2, dtype=np.int64),
+                np.zeros((0, 2), dtype=np.int64))
+    return m, xy
+
+
+def test_group_of_a_chain_reaches_past_the_neighbours():
+    """Sec. 3.2.3 moves every vertex within d of the centre: on a chain of spacing 0.4, the centre
+    2 with d = 0.9 takes 0 and 4 (0.8 away, two edges away) besides its neighbours 1 and 3, and not
+    5 (1.2 away); the ORIGINAL apexes never belong."""
+    m, xy = _fan_chain(9, 0.4)
+    assert not m.has_edge(2, 0) and not m.has_edge(2, 4)
+    assert ob.group_members(m, xy, 2, 0.9) == [2, 0, 1, 3, 4]
+    assert ob.group_members(m, xy, 2, 0.79) == [2, 1, 3]
+    assert ob.group_members(m, xy, 8, 1.25) == [8, 5, 6, 7]
+    # d just covering the apex distance still leaves the ORIGINAL apexes out
+    assert 9 not in ob.group_members(m, xy, 4, 5.5) and len(ob.group_members(m, xy, 4, 5.5)) == 9
+
+
+def test_group_has_no_size_limit():
+    """A centre with twenty movable neighbours within d and ten more free vertices 1.5 away,
+    reached by no edge from it: all thirty join, the centre first."""
     n = 20
     ring = [[math.cos(2 * math.pi * k / n), math.sin(2 * math.pi * k / n)] for k in range(n)]
-    xy = np.array([[0.0, 0.0]] + ring)
-    tv = np.array([[0, 1 + k, 1 + (k + 1) % n] for k in range(n)])
-    m = ob.Mesh(tv, np.array([ob.FREE] * (n + 1)), np.zeros(n + 1, dtype=np.int64),
+    outer = [[1.5 * math.cos(2 * math.pi * (k + 0.5) / 10), 1.5 * math.sin(2 * math.pi * (k + 0.5) / 10)]
+             for k in range(10)]
+    xy = np.array([[0.0, 0.0]] + ring + outer)
+    tv = [[0, 1 + k, 1 + (k + 1) % n] for k in range(n)]
+    # the outer vertices hang off the ring: outer j between ring vertices 2j+1 and 2j+2
+    for j in range(10):
+        a, b = 1 + (2 * j + 1) % n, 1 + (2 * j + 2) % n
+        tv.append([a, 21 + j, b])
+    m = ob.Mesh(np.array(tv), np.array([ob.FREE] * 31), np.zeros(31, dtype=np.int64),
                 np.zeros((0, 2), dtype=np.int64))
-    assert ob.group_members(m, xy, 0, 2.0) == list(range(ob.GROUP_MAX))
+    assert all(not m.has_edge(0, 21 + j) for j in range(10))
+    assert ob.group_members(m, xy, 0, 2.0) == list(range(31))
+    assert ob.group_members(m, xy, 0, 1.2) == list(range(21))
+    assert ob.group_members(m, xy, 25, 0.0) == [25]
