@@ -35,8 +35,12 @@ Readings of points the paper leaves open:
   ||V3 H|| < eps).
 - Restrictions from the original geometry (Sec. 2.2.2): an edge is incontractible when both ends
   are original vertices; when one end is original and the other constrained to an original edge
-  that does not end at it; or when both are constrained to different original edges. The
-  conditioning and flat-triangle restrictions are not part of this objective.
+  that does not end at it; or when both are constrained to different original edges.
+- Conditioning and flat-triangle restrictions (Sec. 2.2.2): see conditioning_ok and flat_ok.
+  Near-collinearity compares a triangle's area with the square of equal perimeter against
+  COLLINEAR = 0.01 (the paper gives no value). Trapped vertices count as already contracted when
+  a path of edges shorter than eps along their original edge, through the free vertex's fan,
+  reaches the vertex contracted to or an original end of that edge.
 - A corner with a zero-length edge contributes no angle penalty (its cosine is undefined; the
   length penalty covers it).
 - Edges are numbered by (lower vertex id, higher vertex id); the product x runs over the
@@ -176,8 +180,285 @@ def one_hop_contractible(m: Mesh, xy, eps) -> np.ndarray:
     return ok
 
 
+# Collinearity (Sec. 2.2.2): three points are near-collinear when the area of their triangle is
+# below this fraction of the area of the square with the triangle's perimeter (the paper calls
+# it a small critical value without giving it; 0.01 is the ratio of a triangle with a 179-degree
+# corner between two equal sides, where the angle penalty starts).
+COLLINEAR = 0.01
+
+
+def near_collinear(a, b, c) -> bool:
+    """16 * area / perimeter^2 below COLLINEAR (a zero perimeter counts as collinear). Lengths as
+    for edges; cross product (b - a) x (c - a)."""
+    cross = (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0])
+    area = 0.5 * abs(cross)
+
+    def ln(u, w):
+        dx = w[0] - u[0]
+        dy = w[1] - u[1]
+        return math.sqrt(dx * dx + dy * dy)
+    per = (ln(a, b) + ln(b, c)) + ln(c, a)
+    if not per > 0.0:
+        return True
+    return (16.0 * area) / (per * per) < COLLINEAR
+
+
+def _dof(kind):
+    return {ORIGINAL: 0, CONSTRAINED: 1, FREE: 2}[int(kind)]
+
+
+def _vertex_triangles(m: Mesh):
+    if not hasattr(m, "_vtri"):
+        vt = [[] for _ in range(m.nv)]
+        for t, tv in enumerate(m.tri_v.tolist()):
+            for v in tv:
+                vt[v].append(t)
+        m._vtri = vt
+        m._nbrs = [set(m.nbr[m.nbr_off[v]:m.nbr_off[v + 1]].tolist()) for v in range(m.nv)]
+    return m._vtri, m._nbrs
+
+
+def conditioning_bad(m: Mesh, xy, lo, tri) -> bool:
+    """Sec. 2.2.2, conditioning: the triangle `tri` (three vertex ids, the contracted vertex
+    already replaced by `lo`) is badly conditioned for good. Only ORIGINAL positions and the
+    original edges of CONSTRAINED vertices are used (fixed during optimisation):
+    - a FREE vertex: never;
+    - three ORIGINAL: near-collinear;
+    - two ORIGINAL o1, o2 and a CONSTRAINED s: near-collinear with s at each end of its original
+      edge and at its middle ((a + b) * 0.5), all three;
+    - one ORIGINAL o and CONSTRAINED s1, s2: their original edges are collinear with each other
+      (both ends of the second near-collinear with the first) and with o;
+    - three CONSTRAINED: all their original edges collinear with the first one.
+    A triangle whose three vertices lie on one original edge is the flat-triangle case, judged by
+    flat_ok instead (its trapped vertices may still be contracted away, as the paper's figure
+    of that rule allows)."""
+    kinds = [int(m.kind[v]) for v in tri]
+    if FREE in kinds:
+        return False
+    for v, k in zip(tri, kinds):
+        if k == CONSTRAINED and all(_on_line(m, x, int(m.line[v])) for x in tri):
+            return False
+    orig = [v for v, k in zip(tri, kinds) if k == ORIGINAL]
+    cons = [v for v, k in zip(tri, kinds) if k == CONSTRAINED]
+    P = lambda v: xy[v]
+    ends = lambda s: (xy[m.prim_v[m.line[s], 0]], xy[m.prim_v[m.line[s], 1]])
+    if len(orig) == 3:
+        return near_collinear(*(P(v) for v in orig))
+    if len(orig) == 2:
+        a, b = ends(cons[0])
+        mid = np.array([(a[0] + b[0]) * 0.5, (a[1] + b[1]) * 0.5])
+        o1, o2 = P(orig[0]), P(orig[1])
+        return all(near_collinear(o1, o2, q) for q in (a, b, mid))
+    a1, b1 = ends(cons[0])
+    lines_collinear = all(near_collinear(a1, b1, q) for s in cons[1:] for q in ends(s))
+    if len(orig) == 1:
+        return lines_collinear and near_collinear(a1, b1, P(orig[0]))
+    return lines_collinear
+
+
+def conditioning_ok(m: Mesh, xy, a, b) -> bool:
+    """Sec. 2.2.2, conditioning restriction: when the contraction of edge (a, b) snaps the vertex
+    with more degrees of freedom (FREE 2, CONSTRAINED 1, ORIGINAL 0) onto the other, every
+    triangle of that vertex that does not hold the other becomes the triangle with the other in
+    its place; the edge is not contractible if one of those is badly conditioned for good. Edges
+    whose ends have equal degrees of freedom lose none and are not restricted here."""
+    da, db = _dof(m.kind[a]), _dof(m.kind[b])
+    if da == db:
+        return True
+    hi, lo = (a, b) if da > db else (b, a)
+    vtri, _ = _vertex_triangles(m)
+    for t in vtri[hi]:
+        tv = [int(x) for x in m.tri_v[t]]
+        if lo in tv:
+            continue
+        if conditioning_bad(m, xy, lo, [lo if x == hi else x for x in tv]):
+            return False
+    return True
+
+
+def _on_line(m: Mesh, v, line) -> bool:
+    k = int(m.kind[v])
+    if k == CONSTRAINED:
+        return int(m.line[v]) == line
+    if k == ORIGINAL:
+        return int(v) in (int(m.prim_v[line, 0]), int(m.prim_v[line, 1]))
+    return False
+
+
+def _length(xy, u, w):
+    dx = xy[w, 0] - xy[u, 0]
+    dy = xy[w, 1] - xy[u, 1]
+    return math.sqrt(dx * dx + dy * dy)
+
+
+def flat_ok(m: Mesh, xy, a, b, eps) -> bool:
+    """Sec. 2.2.2, flat triangles (the paper's figure of a free vertex F fanned over an original
+    edge): for an edge joining a FREE vertex F and a CONSTRAINED or ORIGINAL vertex C, the
+    contraction would snap F onto C, and each triangle (F, X, Y) of F without C whose X and Y lie
+    on an original edge L through C becomes the zero-area (C, X, Y). Its CONSTRAINED vertices are
+    trapped. The edge is contractible only if every trapped vertex is already contracted to C or
+    to an ORIGINAL vertex of L: joined to it by a path along L of edges shorter than eps through
+    vertices of F's fan (F's neighbours on L, and C). 'On L': CONSTRAINED to L, or an ORIGINAL end
+    of L."""
+    ka, kb = int(m.kind[a]), int(m.kind[b])
+    if ka == FREE and kb != FREE:
+        F, C = a, b
+    elif kb == FREE and ka != FREE:
+        F, C = b, a
+    else:
+        return True
+    vtri, nbrs = _vertex_triangles(m)
+    for t in vtri[F]:
+        tv = [int(x) for x in m.tri_v[t]]
+        if C in tv:
+            continue
+        X, Y = [x for x in tv if x != F]
+        cx = [x for x in (X, Y) if int(m.kind[x]) == CONSTRAINED]
+        if not cx:
+            continue
+        L = int(m.line[cx[0]])
+        if not (_on_line(m, X, L) and _on_line(m, Y, L) and _on_line(m, C, L)):
+            continue
+        fan = {x for x in nbrs[F] if _on_line(m, x, L)} | {C}
+        for T in cx:
+            # walk along L through the fan over edges shorter than eps
+            seen, todo, reached = {T}, [T], False
+            while todo and not reached:
+                u = todo.pop()
+                for w in nbrs[u]:
+                    if w in fan and w not in seen and _length(xy, u, w) < eps:
+                        if w == C or int(m.kind[w]) == ORIGINAL:
+                            reached = True
+                            break
+                        seen.add(w)
+                        todo.append(w)
+            if not reached:
+                return False
+    return True
+
+
+def _near_collinear_v(a, b, c):
+    """near_collinear over arrays of points (rows), the same operations in the same order."""
+    cross = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
+    area = 0.5 * np.abs(cross)
+
+    def ln(u, w):
+        dx = w[:, 0] - u[:, 0]
+        dy = w[:, 1] - u[:, 1]
+        return np.sqrt(dx * dx + dy * dy)
+    per = (ln(a, b) + ln(b, c)) + ln(c, a)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = (16.0 * area) / (per * per)
+    return ~(per > 0.0) | (r < COLLINEAR)
+
+
+def _on_line_v(m: Mesh, v, L):
+    k = m.kind[v]
+    return (((k == CONSTRAINED) & (m.line[v] == L)) |
+            ((k == ORIGINAL) & ((m.prim_v[L, 0] == v) | (m.prim_v[L, 1] == v))))
+
+
+def _star_pairs(m: Mesh, edges, centre, other):
+    """(edge index, triangle) for every triangle of centre[k] that does not hold other[k]."""
+    T = m.tri_v.shape[0]
+    flat_v = m.tri_v.ravel()
+    order = np.argsort(flat_v, kind="stable")
+    vt = order // 3
+    off = np.concatenate([[0], np.cumsum(np.bincount(flat_v, minlength=m.nv))])
+    deg = off[centre + 1] - off[centre]
+    k = np.repeat(np.arange(edges.shape[0]), deg)
+    start = np.repeat(off[centre], deg)
+    t = vt[start + (np.arange(k.shape[0]) - np.repeat(np.cumsum(deg) - deg, deg))]
+    keep = ~(m.tri_v[t] == other[k][:, None]).any(axis=1)
+    return k[keep], t[keep]
+
+
+def conditioning_contractible(m: Mesh, xy) -> np.ndarray:
+    """conditioning_ok of every edge, vectorised (the same decisions)."""
+    ok = np.ones(m.n_edges, dtype=bool)
+    a, b = m.edge_v[:, 0], m.edge_v[:, 1]
+    dof = np.where(m.kind == ORIGINAL, 0, np.where(m.kind == CONSTRAINED, 1, 2))
+    cand = np.nonzero(dof[a] != dof[b])[0]
+    if cand.size == 0 or m.prim_v.shape[0] == 0:
+        return ok
+    hi = np.where(dof[a[cand]] > dof[b[cand]], a[cand], b[cand])
+    lo = np.where(dof[a[cand]] > dof[b[cand]], b[cand], a[cand])
+    k, t = _star_pairs(m, cand, hi, lo)
+    tri = np.where(m.tri_v[t] == hi[k][:, None], lo[k][:, None], m.tri_v[t])
+    kinds = m.kind[tri]
+    sel = ~(kinds == FREE).any(axis=1)
+    k, tri, kinds = k[sel], tri[sel], kinds[sel]
+    # three vertices on the line of one of its constrained vertices: the flat-triangle case
+    flat = np.zeros(k.shape[0], dtype=bool)
+    for j in range(3):
+        cj = kinds[:, j] == CONSTRAINED
+        Lj = np.where(cj, m.line[tri[:, j]], 0)
+        flat |= cj & _on_line_v(m, tri[:, 0], Lj) & _on_line_v(m, tri[:, 1], Lj) & \
+            _on_line_v(m, tri[:, 2], Lj)
+    k, tri, kinds = k[~flat], tri[~flat], kinds[~flat]
+    bad = np.zeros(k.shape[0], dtype=bool)
+    isorig = kinds == ORIGINAL
+    no = isorig.sum(axis=1)
+    # the vertices of each kind in triangle order
+    ordo = np.argsort(~isorig, axis=1, kind="stable")
+    ordc = np.argsort(isorig, axis=1, kind="stable")
+    O = np.take_along_axis(tri, ordo, axis=1)
+    Cn = np.take_along_axis(tri, ordc, axis=1)
+    P = lambda v: xy[v]
+    E0 = m.prim_v[np.where(m.kind[Cn[:, 0]] == CONSTRAINED, m.line[Cn[:, 0]], 0)]
+    A, B = xy[E0[:, 0]], xy[E0[:, 1]]
+    s3 = no == 3
+    bad[s3] = _near_collinear_v(P(O[s3, 0]), P(O[s3, 1]), P(O[s3, 2]))
+    s2 = no == 2
+    if s2.any():
+        a2, b2 = A[s2], B[s2]
+        mid = np.stack([(a2[:, 0] + b2[:, 0]) * 0.5, (a2[:, 1] + b2[:, 1]) * 0.5], axis=1)
+        o1, o2 = P(O[s2, 0]), P(O[s2, 1])
+        bad[s2] = (_near_collinear_v(o1, o2, a2) & _near_collinear_v(o1, o2, b2) &
+                   _near_collinear_v(o1, o2, mid))
+    s1 = no <= 1
+    if s1.any():
+        lines = np.ones(k.shape[0], dtype=bool)
+        for j in (1, 2):
+            has = s1 & (3 - no > j)
+            Ej = m.prim_v[m.line[Cn[has, j]]]
+            lines[has] &= (_near_collinear_v(A[has], B[has], xy[Ej[:, 0]]) &
+                           _near_collinear_v(A[has], B[has], xy[Ej[:, 1]]))
+        one = s1 & (no == 1)
+        bad[one] = lines[one] & _near_collinear_v(A[one], B[one], P(O[one, 0]))
+        zero = s1 & (no == 0)
+        bad[zero] = lines[zero]
+    ok[cand[np.unique(k[bad])]] = False
+    return ok
+
+
 def contractible(m: Mesh, xy, eps) -> np.ndarray:
-    return direct_contractible(m) & one_hop_contractible(m, xy, eps)
+    """Sec. 2.2.2: the original-geometry, conditioning, 1-hop and flat-triangle restrictions."""
+    xy = np.asarray(xy, dtype=np.float64)
+    ok = direct_contractible(m) & one_hop_contractible(m, xy, eps) & \
+        conditioning_contractible(m, xy)
+    # the flat-triangle rule can only restrict an edge (F FREE, C not) where a triangle of F
+    # without C has its other two vertices on an original edge through C; the rest is flat_ok
+    a, b = m.edge_v[:, 0], m.edge_v[:, 1]
+    fa, fb = m.kind[a] == FREE, m.kind[b] == FREE
+    cand = np.nonzero(ok & (fa != fb))[0]
+    if cand.size and m.prim_v.shape[0]:
+        F = np.where(fa[cand], a[cand], b[cand])
+        C = np.where(fa[cand], b[cand], a[cand])
+        k, t = _star_pairs(m, cand, F, C)
+        tv = m.tri_v[t]
+        isF = tv == F[k][:, None]
+        XY = tv[~isF].reshape(-1, 2)
+        cx = m.kind[XY[:, 0]] == CONSTRAINED
+        cy = m.kind[XY[:, 1]] == CONSTRAINED
+        L = np.where(cx, m.line[XY[:, 0]], np.where(cy, m.line[XY[:, 1]], 0))
+        hit = (cx | cy) & _on_line_v(m, XY[:, 0], L) & _on_line_v(m, XY[:, 1], L) & \
+            _on_line_v(m, C[k], L)
+        for j in np.unique(k[hit]):
+            e = cand[j]
+            if not flat_ok(m, xy, int(a[e]), int(b[e]), eps):
+                ok[e] = False
+    return ok
 
 
 def edge_values(m: Mesh, xy, p: Params, edges):
@@ -202,7 +483,7 @@ def edge_values(m: Mesh, xy, p: Params, edges):
         for h in sorted((na & nb) - set(opp)):
             if not any(lengths(xy, np.array([h]), np.array([o]))[0] < p.eps for o in opp):
                 return False
-        return True
+        return conditioning_ok(m, xy, int(a), int(b)) and flat_ok(m, xy, int(a), int(b), p.eps)
 
     def c_one(e):
         ln = lengths(xy, m.edge_v[e:e + 1, 0], m.edge_v[e:e + 1, 1])

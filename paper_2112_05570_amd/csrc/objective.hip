@@ -179,6 +179,158 @@ __device__ bool one_hop_ok(const MeshDev& m, const double2* __restrict__ xy, int
   return true;
 }
 
+// Near-collinearity (Sec. 2.2.2): 16 * area / perimeter^2 below kCollinear (a zero perimeter
+// counts as collinear). The paper compares the area with the square of equal perimeter against a
+// small critical value it does not give; 0.01 is the ratio of a triangle whose corner between two
+// equal sides is 179 degrees, where the angle penalty starts.
+constexpr double kCollinear = 0.01;
+
+__device__ bool near_collinear(double2 a, double2 b, double2 c) {
+  const double cross = (b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x);
+  const double area = 0.5 * fabs(cross);
+  const double per = (dist(a, b) + dist(b, c)) + dist(c, a);
+  if (!(per > 0.0)) return true;
+  return (16.0 * area) / (per * per) < kCollinear;
+}
+
+__device__ __forceinline__ bool on_line(const MeshDev& m, int v, int line) {
+  const int2 k = m.vk[v];
+  if (k.x == CCSP_VERTEX_CONSTRAINED) return k.y == line;
+  if (k.x == CCSP_VERTEX_ORIGINAL) {
+    const int2 e = m.prim_v[line];
+    return e.x == v || e.y == v;
+  }
+  return false;
+}
+
+__device__ __forceinline__ int dof(int kind) {
+  return kind == CCSP_VERTEX_ORIGINAL ? 0 : (kind == CCSP_VERTEX_CONSTRAINED ? 1 : 2);
+}
+
+// Conditioning (Sec. 2.2.2) of the triangle (t0, t1, t2), in that order: badly conditioned for
+// good from the positions of ORIGINAL vertices and the original edges of CONSTRAINED ones (all
+// fixed while optimising). A FREE vertex: never. Three ORIGINAL: near-collinear. Two ORIGINAL and
+// a CONSTRAINED s: near-collinear with s at both ends of its original edge and at its middle.
+// One ORIGINAL o and two CONSTRAINED: their original edges collinear with each other and with o.
+// Three CONSTRAINED: their original edges collinear. Three vertices on one original edge are the
+// flat-triangle case (flat_ok), not this one.
+__device__ bool conditioning_bad(const MeshDev& m, const double2* __restrict__ xy, int t0, int t1,
+                                 int t2) {
+  const int tv[3] = {t0, t1, t2};
+  int no = 0, nc = 0, orig[3], cons[3];
+  for (int j = 0; j < 3; ++j) {
+    const int k = m.vk[tv[j]].x;
+    if (k == CCSP_VERTEX_FREE) return false;
+    if (k == CCSP_VERTEX_ORIGINAL) orig[no++] = tv[j];
+    else cons[nc++] = tv[j];
+  }
+  for (int j = 0; j < nc; ++j) {
+    const int L = m.vk[cons[j]].y;
+    if (on_line(m, t0, L) && on_line(m, t1, L) && on_line(m, t2, L)) return false;
+  }
+  if (no == 3) return near_collinear(xy[orig[0]], xy[orig[1]], xy[orig[2]]);
+  const int2 e0 = m.prim_v[m.vk[cons[0]].y];
+  const double2 a = xy[e0.x], b = xy[e0.y];
+  if (no == 2) {
+    const double2 mid = make_double2((a.x + b.x) * 0.5, (a.y + b.y) * 0.5);
+    const double2 o1 = xy[orig[0]], o2 = xy[orig[1]];
+    return near_collinear(o1, o2, a) && near_collinear(o1, o2, b) && near_collinear(o1, o2, mid);
+  }
+  bool lines = true;
+  for (int j = 1; j < nc; ++j) {
+    const int2 ej = m.prim_v[m.vk[cons[j]].y];
+    lines = lines && near_collinear(a, b, xy[ej.x]) && near_collinear(a, b, xy[ej.y]);
+  }
+  if (no == 1) return lines && near_collinear(a, b, xy[orig[0]]);
+  return lines;
+}
+
+// Conditioning restriction of edge (a, b): when contracting it snaps the vertex with more degrees
+// of freedom onto the other, no triangle of that vertex without the other may become badly
+// conditioned for good (the other taking its place).
+__device__ bool conditioning_ok(const MeshDev& m, const double2* __restrict__ xy, int a, int b) {
+  const int da = dof(m.vk[a].x), db = dof(m.vk[b].x);
+  if (da == db) return true;
+  const int hi = da > db ? a : b, lo = da > db ? b : a;
+  for (int k = m.vtri_off[hi], end = m.vtri_off[hi + 1]; k < end; ++k) {
+    const int4 t = m.tri[m.vtri[k]];
+    if (t.x == lo || t.y == lo || t.z == lo) continue;
+    if (conditioning_bad(m, xy, t.x == hi ? lo : t.x, t.y == hi ? lo : t.y, t.z == hi ? lo : t.z))
+      return false;
+  }
+  return true;
+}
+
+// Flat-triangle restriction (Sec. 2.2.2), with vertex mv at q: for an edge joining a FREE vertex F
+// and a CONSTRAINED or ORIGINAL vertex C, every CONSTRAINED vertex of a triangle (F, X, Y) without C
+// whose X and Y lie on an original edge L through C (it becomes the zero-area (C, X, Y)) must
+// already be contracted to C or to an ORIGINAL end of L: a path along L of edges shorter than eps
+// through F's fan (F's neighbours on L, and C) reaches one of them. Along L a vertex has at most
+// two neighbours, so the path is followed in each direction from the trapped vertex.
+__device__ bool flat_ok(const MeshDev& m, const double2* __restrict__ xy, int a, int b, double eps,
+                        int mv, double2 q) {
+  const int ka = m.vk[a].x, kb = m.vk[b].x;
+  int F, C;
+  if (ka == CCSP_VERTEX_FREE && kb != CCSP_VERTEX_FREE) {
+    F = a;
+    C = b;
+  } else if (kb == CCSP_VERTEX_FREE && ka != CCSP_VERTEX_FREE) {
+    F = b;
+    C = a;
+  } else {
+    return true;
+  }
+  const int deg = m.adj_off[F + 1] - m.adj_off[F];
+  for (int k = m.vtri_off[F], end = m.vtri_off[F + 1]; k < end; ++k) {
+    const int4 t = m.tri[m.vtri[k]];
+    if (t.x == C || t.y == C || t.z == C) continue;
+    const int X = t.x == F ? t.y : t.x;
+    const int Y = t.z == F ? t.y : t.z;
+    const bool cx = m.vk[X].x == CCSP_VERTEX_CONSTRAINED, cy = m.vk[Y].x == CCSP_VERTEX_CONSTRAINED;
+    if (!cx && !cy) continue;
+    const int L = m.vk[cx ? X : Y].y;
+    if (!(on_line(m, X, L) && on_line(m, Y, L) && on_line(m, C, L))) continue;
+    for (int j = 0; j < 2; ++j) {
+      const int T = j == 0 ? X : Y;
+      if (m.vk[T].x != CCSP_VERTEX_CONSTRAINED) continue;
+      bool reached = false;
+      // each neighbour of T along L in the fan, reached by a short edge, starts one direction
+      for (int s0 = m.adj_off[T], s1 = m.adj_off[T + 1]; s0 < s1 && !reached; ++s0) {
+        int prev = T, cur = m.adj[s0].x;
+        for (int steps = 0; steps <= deg + 1; ++steps) {
+          if (!on_line(m, cur, L) || !(cur == C || is_neighbour(m, F, cur)) ||
+              !(dist(pos(xy, prev, mv, q), pos(xy, cur, mv, q)) < eps))
+            break;
+          if (cur == C || m.vk[cur].x == CCSP_VERTEX_ORIGINAL) {
+            reached = true;
+            break;
+          }
+          int next = -1;
+          for (int r = m.adj_off[cur], re = m.adj_off[cur + 1]; r < re; ++r) {
+            const int w = m.adj[r].x;
+            if (w != prev && on_line(m, w, L) && (w == C || is_neighbour(m, F, w))) {
+              next = w;
+              break;
+            }
+          }
+          if (next < 0) break;
+          prev = cur;
+          cur = next;
+        }
+      }
+      if (!reached) return false;
+    }
+  }
+  return true;
+}
+
+// Contractibility of edge e = (a, b) (Sec. 2.2.2), with vertex mv at q.
+__device__ bool contractible_at(const MeshDev& m, const double2* __restrict__ xy, int e, int a,
+                                int b, double eps, int mv, double2 q) {
+  return direct_ok(m, a, b) && one_hop_ok(m, xy, e, m.edge_opp[e], eps, mv, q) &&
+         conditioning_ok(m, xy, a, b) && flat_ok(m, xy, a, b, eps, mv, q);
+}
+
 __device__ double block_sum(double v, double* sh) {
   sh[threadIdx.x] = v;
   __syncthreads();
@@ -208,8 +360,7 @@ edge_state(MeshDev m, Par p, double* __restrict__ part) {
   for (int e = blockIdx.x * kThreads + threadIdx.x; e < m.ne; e += gridDim.x * kThreads) {
     const int2 ab = m.edge_v[e];
     const double len = dist(xy[ab.x], xy[ab.y]);
-    const bool ok = direct_ok(m, ab.x, ab.y) &&
-                    one_hop_ok(m, xy, e, m.edge_opp[e], p.eps, -1, make_double2(0, 0));
+    const bool ok = contractible_at(m, xy, e, ab.x, ab.y, p.eps, -1, make_double2(0, 0));
     m.len[e] = len;
     m.contr[e] = ok ? 1 : 0;
     m.c[e] = c_of_len(ok, len, p.eps);
@@ -293,10 +444,17 @@ struct MoveCtx {
       if (nb[j * kThreads] == x) return true;
     return false;
   }
+  // The edges whose c may change when v moves: v's edges (lengths; the flat-triangle rule of
+  // an edge at v reads lengths at v), edges joining two neighbours of v (1-hop rule), and edges
+  // joining a FREE neighbour of v to a vertex that is not FREE (the flat-triangle rule reads the
+  // lengths of the edges among that neighbour's neighbours, v's among them).
   __device__ __forceinline__ bool in_c(int e) const {
     const int2 ab = m.edge_v[e];
     if (ab.x == v || ab.y == v) return true;
-    return adjacent(ab.x) && adjacent(ab.y);
+    const bool na = adjacent(ab.x), nb2 = adjacent(ab.y);
+    if (na && nb2) return true;
+    const bool fa = m.vk[ab.x].x == CCSP_VERTEX_FREE, fb = m.vk[ab.y].x == CCSP_VERTEX_FREE;
+    return (fa && na && !fb) || (fb && nb2 && !fa);
   }
   __device__ __forceinline__ double len(int e, bool moved) const {
     const int2 ab = m.edge_v[e];
@@ -304,14 +462,9 @@ struct MoveCtx {
     return dist(pos(xy, ab.x, v, q), pos(xy, ab.y, v, q));
   }
   __device__ __forceinline__ double c(int e, bool moved) const {
-    if (!moved) return m.c[e];
+    if (!moved || !in_c(e)) return m.c[e];
     const int2 ab = m.edge_v[e];
-    if (ab.x == v || ab.y == v) return c_of_len(m.contr[e] != 0, len(e, true), p.eps);
-    if (adjacent(ab.x) && adjacent(ab.y)) {
-      const bool ok = direct_ok(m, ab.x, ab.y) && one_hop_ok(m, xy, e, m.edge_opp[e], p.eps, v, q);
-      return c_of_len(ok, m.len[e], p.eps);
-    }
-    return m.c[e];
+    return c_of_len(contractible_at(m, xy, e, ab.x, ab.y, p.eps, v, q), len(e, true), p.eps);
   }
   __device__ __forceinline__ double term(int e, bool moved) const {
     double w = 1.0;
@@ -388,6 +541,17 @@ __device__ __forceinline__ int move_change(const MeshDev& m, const double2* __re
       const int e = find_edge(m, m.adj[j].x, m.adj[l].x);
       if (e >= 0) se += ctx.visit(e);
     }
+  // edges from a FREE neighbour F of v to a vertex that is not FREE and not v or a neighbour of
+  // v (each once, from its FREE end)
+  for (int j = a0, end = a0 + deg; j < end; ++j) {
+    const int F = m.adj[j].x;
+    if (m.vk[F].x != CCSP_VERTEX_FREE) continue;
+    for (int k = m.adj_off[F], ke = m.adj_off[F + 1]; k < ke; ++k) {
+      const int C = m.adj[k].x;
+      if (C == v || m.vk[C].x == CCSP_VERTEX_FREE || ctx.adjacent(C)) continue;
+      se += ctx.visit(m.adj[k].y);
+    }
+  }
   *df = se + p.mu_angle * sa + p.mu_len * ss;
   return CCSP_MOVE_OK;
 }
@@ -462,23 +626,40 @@ anneal_moves(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out,
 __device__ __forceinline__ void refresh_scratch(const MeshDev& m, const Par& p, int v) {
   const double2* __restrict__ xy = m.xyi;
   const int a0 = m.adj_off[v], a1 = m.adj_off[v + 1];
+  const double2 nq = make_double2(0, 0);
+  for (int j = a0; j < a1; ++j) {  // lengths first: the rules below read them
+    const int e = m.adj[j].y;
+    const int2 ab = m.edge_v[e];
+    m.len[e] = dist(xy[ab.x], xy[ab.y]);
+  }
   for (int j = a0; j < a1; ++j) {
     const int e = m.adj[j].y;
     const int2 ab = m.edge_v[e];
-    const double len = dist(xy[ab.x], xy[ab.y]);
-    m.len[e] = len;
-    m.c[e] = c_of_len(m.contr[e] != 0, len, p.eps);
+    const bool ok = contractible_at(m, xy, e, ab.x, ab.y, p.eps, -1, nq);
+    m.contr[e] = ok ? 1 : 0;
+    m.c[e] = c_of_len(ok, m.len[e], p.eps);
   }
   for (int j = a0; j < a1; ++j)
     for (int l = j + 1; l < a1; ++l) {
       const int a = m.adj[j].x, b = m.adj[l].x;
       const int e = find_edge(m, a, b);
       if (e < 0) continue;
-      const bool ok = direct_ok(m, a, b) &&
-                      one_hop_ok(m, xy, e, m.edge_opp[e], p.eps, -1, make_double2(0, 0));
+      const bool ok = contractible_at(m, xy, e, a, b, p.eps, -1, nq);
       m.contr[e] = ok ? 1 : 0;
       m.c[e] = c_of_len(ok, m.len[e], p.eps);
     }
+  for (int j = a0; j < a1; ++j) {
+    const int F = m.adj[j].x;
+    if (m.vk[F].x != CCSP_VERTEX_FREE) continue;
+    for (int k = m.adj_off[F], ke = m.adj_off[F + 1]; k < ke; ++k) {
+      const int C = m.adj[k].x;
+      if (C == v || m.vk[C].x == CCSP_VERTEX_FREE || is_neighbour(m, v, C)) continue;
+      const int e = m.adj[k].y;
+      const bool ok = contractible_at(m, xy, e, F, C, p.eps, -1, nq);
+      m.contr[e] = ok ? 1 : 0;
+      m.c[e] = c_of_len(ok, m.len[e], p.eps);
+    }
+  }
 }
 
 // Area of triangle t at the current positions, its vertices in the caller's order.

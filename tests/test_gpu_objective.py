@@ -10,6 +10,7 @@ import math
 import numpy as np
 import pytest
 
+import helpers
 import oracle
 import scenegen as sg
 from oracle import objective as ob
@@ -690,3 +691,49 @@ def test_large_and_far_reaching_groups(ccsp):
         keep = np.array([0, 1, 2, 4, 5])
         _group_sweep_vs_chain(ccsp, gm, om, xy, p, 1e-3, 0.05, draws[keep], u[keep],
                               centres=cen[keep])
+
+
+@pytest.mark.parametrize("seed,eps", [(0, 0.3), (1, 1.0), (2, 2.0), (3, 0.3)])
+def test_conditioning_and_flat_rules_on_gpu(ccsp, seed, eps):
+    """Sec. 2.2.2's conditioning and flat-triangle restrictions: on meshes where both fire (the
+    checker finds edges that they alone make incontractible), the GPU's evaluation, changes of f,
+    a single-vertex sweep and a group sweep equal the checker's."""
+    tri, kind, line, prim_v, xy = helpers.rules_mesh(seed)
+    om = ob.Mesh(tri, kind, line, prim_v)
+    p = ob.Params(eps)
+    base = ob.direct_contractible(om) & ob.one_hop_contractible(om, xy, eps)
+    cond = ob.conditioning_contractible(om, xy)
+    full = ob.contractible(om, xy, eps)
+    assert (base & ~cond).sum() > 5, "the conditioning rule does not fire"
+    if eps < 1.5:
+        assert (base & cond & ~full).sum() > 5, "the flat-triangle rule does not fire"
+    _check_eval(ccsp, om, xy, p, f"rules mesh {seed}")
+    rng = np.random.default_rng(40 + seed)
+    movable = np.nonzero(kind != ob.ORIGINAL)[0]
+    v = rng.choice(movable, 400).astype(np.int32)
+    q = xy[v] + rng.normal(0.0, 0.2, (400, 2))
+    for i in range(400):  # constrained vertices move along their original edge
+        if kind[v[i]] == ob.CONSTRAINED:
+            q[i] = xy[v[i]] + ob.project(om, xy, int(v[i]), q[i] - xy[v[i]])
+    d, st = _gpu_delta(ccsp, om, xy, p, v, q)
+    _check_deltas(om, xy, p, v, q, d, st, f"rules mesh {seed}")
+    assert (st == 1).sum() > 100
+    with ccsp.MovableMesh(tri, kind, line, prim_v) as gm:
+        cls = gm.classes()
+        order = np.concatenate(cls)
+        disp = rng.normal(0.0, 0.3, (order.shape[0], 2))
+        u = rng.random(order.shape[0])
+        X = torch.from_numpy(xy.copy()).to(DEV)
+        d_s, st_s = gm.sweep(X, _params(ccsp, p), 1e-2, torch.from_numpy(disp).to(DEV),
+                             torch.from_numpy(u).to(DEV))
+        xy_s, st_s, d_s = X.cpu().numpy(), st_s.cpu().numpy(), d_s.cpu().numpy()
+        xy_r, st_r, df_r, margin = ob.metropolis_chain(om, xy, p, 1e-2, order, disp, u)
+        valid = (st_r == ob.ACCEPTED) | (st_r == ob.REJECTED)
+        close = valid & (margin <= 1e-10)
+        assert (d_s[close] == df_r[close]).all(), "a decision lies within rounding of its threshold"
+        assert np.array_equal(st_s, st_r) and np.array_equal(xy_s, xy_r)
+        M = gm.movable.shape[0]
+        draws = np.zeros((M, 4))
+        draws[:, :2] = rng.standard_normal((M, 2))
+        draws[:, 2] = rng.random(M)
+        _group_sweep_vs_chain(ccsp, gm, om, xy, p, 1e-2, 0.05, draws, rng.random(M))

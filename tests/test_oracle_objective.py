@@ -297,3 +297,74 @@ def test_edge_values_one_by_one_equal_whole_evaluation():
         assert np.array_equal(k, ref["contractible"]) and np.array_equal(c, ref["c"])
         assert np.array_equal(w, ref["w"])
     assert (ref["w"] == 1.0).all() and (~ref["contractible"]).any()
+
+
+# ---- Sec. 2.2.2: the flat-triangle and conditioning restrictions, on hand-built meshes
+
+def _fan_over_line(xs, f=(1.0, 3.0), end=10.0):
+    """The paper's figure of the flat-triangle rule: an original edge from C0 = (0, 0) to
+    CN = (end, 0), CONSTRAINED vertices at x = xs on it, and a FREE vertex F above fanned over all
+    of them. Vertex ids: C0 0, CN 1, the constrained ones 2.., F last."""
+    cs = [[x, 0.0] for x in xs]
+    xy = np.array([[0.0, 0.0], [end, 0.0]] + cs + [list(f)])
+    F = xy.shape[0] - 1
+    line_v = [0] + list(range(2, 2 + len(xs))) + [1]
+    tv = [[line_v[i], line_v[i + 1], F] for i in range(len(line_v) - 1)]
+    kind = np.array([ob.ORIGINAL, ob.ORIGINAL] + [ob.CONSTRAINED] * len(xs) + [ob.FREE])
+    line = np.zeros(xy.shape[0], dtype=np.int64)
+    m = ob.Mesh(np.array(tv), kind, line, np.array([[0, 1]]))
+    return m, xy, F
+
+
+def _contractible_edge(m, xy, a, b, eps):
+    e = int(np.nonzero((m.edge_v[:, 0] == min(a, b)) & (m.edge_v[:, 1] == max(a, b)))[0][0])
+    return bool(ob.contractible(m, xy, eps)[e]), bool(ob.edge_values(m, xy, ob.Params(eps), [e])[0][0])
+
+
+def test_flat_triangle_rule_as_in_the_figure():
+    """Snapping F onto C0 flattens F's triangles over the original edge; the trapped vertices
+    C1..C4 must already be contracted (edges shorter than eps along the edge) to C0 or to CN.
+    With one gap longer than eps the edge F-C0 is contractible, as the figure states; with two
+    gaps it is not (C3 reaches neither end); with every gap short it is."""
+    eps = 0.5
+    m, xy, F = _fan_over_line([0.3, 0.6, 9.4, 9.7])  # gaps 0.3 0.3 8.8 0.3 0.3
+    assert _contractible_edge(m, xy, F, 0, eps) == (True, True)
+    m, xy, F = _fan_over_line([0.3, 0.6, 8.0, 9.7])  # gaps 0.3 0.3 7.4 1.7 0.3: C3 is stuck
+    assert _contractible_edge(m, xy, F, 0, eps) == (False, False)
+    assert _contractible_edge(m, xy, F, 0, 2.0) == (True, True)  # 1.7 < eps: C3 reaches CN
+    # the rule does not concern an edge between F and a vertex off the line's fan, nor two free
+    # vertices: with F's contraction onto C1 the trapped C2..C4 must reach C1 or an end
+    m, xy, F = _fan_over_line([0.3, 0.6, 9.4, 9.7])
+    assert _contractible_edge(m, xy, F, 2, eps) == (True, True)
+    m, xy, F = _fan_over_line([2.0, 4.0, 6.0, 8.0])  # every gap 2
+    assert _contractible_edge(m, xy, F, 0, eps) == (False, False)
+    assert _contractible_edge(m, xy, F, 0, 2.5) == (True, True)
+
+
+def test_conditioning_rule():
+    """Snapping a vertex onto a less free one must not force a badly conditioned triangle: three
+    ORIGINAL vertices near-collinear (16 * area / perimeter^2 = 0.0005 < 0.01) forbid it, a
+    well-shaped triple (0.23) does not; two ORIGINAL and a CONSTRAINED vertex forbid it only if
+    the constrained vertex is near-collinear at both ends and the middle of its original edge."""
+    # F = 3 free, O1 = 0, O2 = 1, O3 = 2 original; F's triangle (F, O2, O3) becomes (O1, O2, O3)
+    for o3, bad in (((20.0, 0.01), True), ((20.0, 5.0), False)):
+        xy = np.array([[0.0, 0.0], [10.0, 0.0], list(o3), [5.0, -3.0]])
+        tv = np.array([[0, 1, 3], [3, 1, 2]]) if ob.orient(xy[3], xy[1], xy[2]) > 0 else \
+            np.array([[0, 1, 3], [3, 2, 1]])
+        if ob.orient(*xy[tv[0]]) < 0:
+            tv[0] = tv[0][[0, 2, 1]]
+        m = ob.Mesh(tv, np.array([ob.ORIGINAL] * 3 + [ob.FREE]), np.zeros(4, dtype=np.int64),
+                    np.array([[0, 1], [1, 2]]))
+        assert ob.near_collinear(xy[0], xy[1], xy[2]) == bad
+        assert ob.conditioning_ok(m, xy, 3, 0) == (not bad)
+    # two ORIGINAL (0, 1) and a CONSTRAINED S (4) on the original edge 2-3
+    for b3, bad in (((30.0, 0.0), True), ((30.0, 20.0), False)):
+        xy = np.array([[0.0, 0.0], [10.0, 0.0], [20.0, 0.0], list(b3), [25.0, b3[1] / 2], [5.0, -3.0]])
+        tv = np.array([[0, 1, 5], [5, 1, 4]])
+        for t in range(2):
+            if ob.orient(*xy[tv[t]]) < 0:
+                tv[t] = tv[t][[0, 2, 1]]
+        kind = np.array([ob.ORIGINAL] * 4 + [ob.CONSTRAINED, ob.FREE])
+        line = np.array([0, 0, 0, 0, 1, 0])
+        m = ob.Mesh(tv, kind, line, np.array([[0, 1], [2, 3]]))
+        assert ob.conditioning_ok(m, xy, 5, 0) == (not bad)
