@@ -358,6 +358,18 @@ def main():
     scene.free()
 
 
+def subdivided(sc):
+    """The scene's CDT subdivided once (Sec. 3.5.2) by the library (mesh_subdivide)."""
+    from types import SimpleNamespace
+
+    import paper_2112_05570_amd as ccsp
+    import scenegen as sg
+    xy, tv, kd, ln, pv = sg.movable_input(sc)
+    tv, kd, ln, pv, xy = ccsp.subdivide(tv, kd, ln, pv, xy)
+    return SimpleNamespace(xy=xy, tri_v=tv, kind=kd, line=ln, prim_v=pv, n_vertices=xy.shape[0],
+                           n_triangles=tv.shape[0], name=sc.name + "/4")
+
+
 def flip_leg(sc, steps, hot=300, cold=100, t0_rel=5e-3, t1_rel=1e-5, seed=0):
     """GPU edge-flip annealing (flip_anneal) of a scene's CDT with the weight as energy: `hot`
     rounds at temperatures falling geometrically from t0_rel to t1_rel of the box side, then
@@ -508,7 +520,7 @@ def pipeline_leg(sc, rays, stages=24, verbose=False, schedule=None):
 
     size = sc.box[1] - sc.box[0]
     t0 = time.perf_counter()
-    mesh = sg.subdivide(sc)
+    mesh = subdivided(sc)
     t_sub = time.perf_counter() - t0
     r = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, size,
                     schedule or pl.Schedule(stages=stages), verbose=verbose)
@@ -603,7 +615,7 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
 
     t0 = time.time()
     sc = sg.make_scene(scene_name, seed=0)
-    mesh = sg.subdivide(sc)
+    mesh = subdivided(sc)
     size = sc.box[1] - sc.box[0]
     gm = ccsp.MovableMesh.from_mesh(mesh)
     log(f"[bench] objective on {mesh.name}: {mesh.n_vertices} vertices, {gm.n_edges} edges, "

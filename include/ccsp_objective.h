@@ -242,6 +242,25 @@ int anneal_schedule(MovableMesh *mesh, double *xy, const ObjectiveParams *params
                     void *stream);
 
 /*
+ * mesh_subdivide: the subdivision of Sec. 3.5.2, every triangle split into four at the midpoints
+ * of its edges. HOST code and HOST pointers. Input: desc (as mesh_load) and xy (2 * n_vertices
+ * binary64). The vertices keep their ids, kinds and lines; edge e (edges numbered by
+ * min * n_vertices + max of their ends, increasing) adds vertex n_vertices + e at
+ * ((xa + xb) * 0.5, (ya + yb) * 0.5), CONSTRAINED to the original edge that holds both ends (the
+ * line of a CONSTRAINED end, or the original edge joining two ORIGINAL ends) if there is one,
+ * else FREE (line -1). Triangle t = (v0, v1, v2) with midpoints m_i of its edges opposite v_i gives
+ * t, T + t, 2T + t, 3T + t = (v0, m2, m1), (v1, m0, m2), (v2, m1, m0), (m0, m1, m2). Sizes go to
+ * *n_vertices_out = n_vertices + edges and *n_triangles_out = 4 * n_triangles; with xy_out,
+ * tri_out, kind_out or line_out NULL only the sizes are computed, else those HOST arrays
+ * (caller-allocated at these sizes) receive the result. Errors: CCSP_E_ARG,
+ * CCSP_E_BAD_TRIANGULATION (ids, kinds or lines out of range, or a sub-triangle that rounding of a
+ * midpoint leaves not strictly counter-clockwise, decided exactly). Thread-safe.
+ */
+int mesh_subdivide(const MeshDesc *desc, const double *xy, int64_t *n_vertices_out,
+                   int64_t *n_triangles_out, double *xy_out, int32_t *tri_out, int32_t *kind_out,
+                   int32_t *line_out);
+
+/*
  * mesh_contract: contraction of the edges shorter than eps (Sec. 3.4.1), turning a triangulation
  * whose short edges stand for merged vertices into one where they are merged. HOST code and HOST
  * pointers throughout (sequential, as each contraction changes the next one's neighbourhood).

@@ -244,6 +244,31 @@ def contract(tri_v, kind, line, prim_v, xy, eps):
             "old_to_new": m, "contracted": int(counts[2])}
 
 
+def subdivide(tri_v, kind, line, prim_v, xy):
+    """The subdivision of Sec. 3.5.2 (see ``mesh_subdivide`` in ccsp_objective.h; host code):
+    every triangle split into four at its edge midpoints. Arguments as for MovableMesh plus
+    positions xy (V,2) float64. Returns (tri_v, kind, line, prim_v, xy) of the result (numpy)."""
+    tri_v = np.ascontiguousarray(tri_v, dtype=np.int32)
+    kind = np.ascontiguousarray(kind, dtype=np.int32)
+    line = np.ascontiguousarray(line, dtype=np.int32)
+    prim_v = np.ascontiguousarray(prim_v, dtype=np.int32).reshape(-1, 2)
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    V, T = kind.shape[0], tri_v.shape[0]
+    if tri_v.ndim != 2 or tri_v.shape[1] != 3 or line.shape != (V,) or xy.shape != (V, 2):
+        raise ValueError("tri_v (T,3); kind, line (V,); xy (V,2)")
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
+    d = B.MeshDesc(V, p(kind), p(line), T, p(tri_v), prim_v.shape[0], p(prim_v))
+    sizes = np.zeros(2, dtype=np.int64)
+    B.mesh_subdivide(d, p(xy), p(sizes))
+    nv, nt = int(sizes[0]), int(sizes[1])
+    xo = np.empty((nv, 2), dtype=np.float64)
+    to = np.empty((nt, 3), dtype=np.int32)
+    ko = np.empty(nv, dtype=np.int32)
+    lo = np.empty(nv, dtype=np.int32)
+    B.mesh_subdivide(d, p(xy), p(sizes), p(xo), p(to), p(ko), p(lo))
+    return to, ko, lo, prim_v, xo
+
+
 class MovableMesh:
     """A triangulation with movable Steiner vertices for the low-weight objective (see
     ``mesh_load`` in ccsp_objective.h). Built from host arrays: tri_v (T,3) counter-clockwise,

@@ -52,7 +52,7 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
            "anneal_moves", "anneal_sweep", "anneal_propose", "anneal_schedule",
            "flip_anneal", "mesh_contract", "anneal_group",
-           "trace_rays_static")
+           "trace_rays_static", "mesh_subdivide")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -157,6 +157,8 @@ class ObjectiveParams(ctypes.Structure):
                 ("polish", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+_lib.mesh_subdivide.argtypes = [ctypes.POINTER(MeshDesc), _P, _P, _P, _P, _P, _P, _P]
+_lib.mesh_subdivide.restype = _I
 _lib.mesh_load.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(_P)]
 _lib.mesh_load.restype = _I
 _lib.mesh_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), _P]
@@ -226,6 +228,13 @@ def trace_rays_tuned(tri: int, o_xy: int, d_xy: int, start_tri: int, n: int, pre
     _check(_lib.trace_rays_tuned(_P(tri), _P(o_xy), _P(d_xy), _P(start_tri), n, precision,
                                  _P(hit_prim), _P(hit_t), _P(steps),
                                  ctypes.byref(tune) if tune is not None else None, _P(stream)))
+
+
+def mesh_subdivide(desc, xy: int, sizes: int, xy_out: int = 0, tri_out: int = 0,
+                   kind_out: int = 0, line_out: int = 0) -> None:
+    """sizes: address of two int64 (vertices, triangles)."""
+    _check(_lib.mesh_subdivide(ctypes.byref(desc), _P(xy), _P(sizes), _P(sizes + 8), _P(xy_out),
+                               _P(tri_out), _P(kind_out), _P(line_out)))
 
 
 def trace_rays_static(tri: int, o_xy: int, d_xy: int, start_tri: int, n: int, precision: int,

@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libccsp_walk.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("walk_kernels.hip", "bin.hip", "gather.hip", "locate.hip", "objective.hip", "flips.hip", "capi.cpp", "contract.cpp",
+           for f in ("walk_kernels.hip", "bin.hip", "gather.hip", "locate.hip", "objective.hip", "flips.hip", "capi.cpp", "contract.cpp", "subdivide.cpp",
                      "serve.cpp")]
 
 HIPCC_FLAGS = [

@@ -209,42 +209,18 @@ class MovableMesh:
         return int(self.tri_v.shape[0])
 
 
-def subdivide(sc: Scene) -> MovableMesh:
-    """Input for the objective: the triangulation with every triangle split into four at its edge
-    midpoints (the subdivision of Sec. 3.5.2). Scene vertices are ORIGINAL; the midpoint of a
-    constrained edge is CONSTRAINED to that edge's primitive, other midpoints are FREE. Triangles
-    that rounding of a midpoint would leave not strictly counter-clockwise are reported."""
+def movable_input(sc: Scene) -> tuple:
+    """A scene's triangulation as the input of the low-weight optimiser, before any subdivision:
+    (xy, tri_v, kind, line, prim_v) with every vertex ORIGINAL (line -1) and the original edges
+    being the scene's segments followed by the four box sides."""
     if "seg_prim" in sc.meta:
-        raise ValueError("subdivide expects one constrained edge chain per segment, unsplit")
-    V, T = sc.n_vertices, sc.n_triangles
-    tv = sc.tri_v.astype(np.int64)
-    a, b = tv[:, [1, 2, 0]], tv[:, [2, 0, 1]]
-    key = np.minimum(a, b) * V + np.maximum(a, b)
-    uniq, inv = np.unique(key.ravel(), return_inverse=True)
-    inv = inv.reshape(T, 3)
-    ea, eb = uniq // V, uniq % V
-    E = uniq.shape[0]
-    mid = 0.5 * (sc.xy[ea] + sc.xy[eb])
-    prim = np.full(E, -1, dtype=np.int64)
-    tp = sc.tri_prim.astype(np.int64)
-    prim[inv[tp >= 0]] = tp[tp >= 0]
-    m = V + inv  # m[:, i] is the midpoint of edge i (opposite v[i])
-    tri = np.concatenate([np.stack([tv[:, 0], m[:, 2], m[:, 1]], 1),
-                          np.stack([tv[:, 1], m[:, 0], m[:, 2]], 1),
-                          np.stack([tv[:, 2], m[:, 1], m[:, 0]], 1),
-                          np.stack([m[:, 0], m[:, 1], m[:, 2]], 1)]).astype(np.int32)
-    xy = np.ascontiguousarray(np.concatenate([sc.xy, mid]))
-    kind = np.concatenate([np.full(V, ORIGINAL), np.where(prim >= 0, CONSTRAINED, FREE)])
-    line = np.concatenate([np.full(V, -1), prim])
-    S = sc.seg_v.shape[0]
+        raise ValueError("movable_input expects one constrained edge per segment, unsplit")
     prim_v = np.concatenate([sc.seg_v, [[0, 1], [1, 2], [2, 3], [3, 0]]]).astype(np.int32)
     if prim_v.shape[0] != sc.n_prims:
         raise ValueError("scene primitives are not its segments plus four box sides")
-    bad = exact_orient(np.concatenate([xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]], 1)) <= 0
-    if bad.any():
-        raise ValueError(f"{int(bad.sum())} subdivided triangles are not strictly counter-clockwise")
-    return MovableMesh(xy, np.ascontiguousarray(tri), kind.astype(np.int32),
-                       line.astype(np.int32), prim_v, name=sc.name + "/4")
+    V = sc.n_vertices
+    return (np.ascontiguousarray(sc.xy), np.ascontiguousarray(sc.tri_v, dtype=np.int32),
+            np.full(V, ORIGINAL, dtype=np.int32), np.full(V, -1, dtype=np.int32), prim_v)
 
 
 def vertex_moves(mesh: MovableMesh, n: int, seed: int, lam: float) -> tuple:

@@ -117,3 +117,10 @@ def rules_mesh(seed):
         if ok:
             return (tri.astype(np.int32), kind_a.astype(np.int32), line_a.astype(np.int32),
                     np.array(prims, dtype=np.int32), xy)
+
+
+def subdivided(sc):
+    """The scene's CDT subdivided once (Sec. 3.5.2) by the checker's subdivision: the input of
+    the objective's tests on both sides."""
+    from oracle.subdivide import subdivide
+    return subdivide(*sg.movable_input(sc), name=sc.name + "/4")

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import paper_2112_05570_amd as ccsp
+import helpers
 import scenegen as sg
 from oracle import contract as ct
 from oracle import objective as ob
@@ -35,7 +36,7 @@ def test_clustered_tiny(seed, eps):
 def test_subdivided_mid_scene():
     """An 8,002-triangle scene subdivided (32,008 triangles), vertices jittered by valid moves,
     contracted at a length that catches many of its edges."""
-    mesh = sg.subdivide(sg.make_scene("large", n_seg=2000))
+    mesh = helpers.subdivided(sg.make_scene("large", n_seg=2000))
     om = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     rng = np.random.default_rng(7)
     xy = mesh.xy.copy()
@@ -69,7 +70,7 @@ def test_walk_arrays_of_a_subdivided_mesh():
     import oracle
     from paper_2112_05570_amd import pipeline as pl
     sc = sg.make_scene("tiny")
-    mesh = sg.subdivide(sc)
+    mesh = helpers.subdivided(sc)
     nbr, prim, prims, s2o = pl.walk_arrays(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy)
     assert prims.shape == (2 * sc.n_prims, 4) and np.bincount(s2o).tolist() == [2] * sc.n_prims
     assert oracle.validate(oracle.Triangulation(mesh.xy, mesh.tri_v, nbr, prim, prims)) == ""

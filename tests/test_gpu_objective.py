@@ -33,7 +33,7 @@ def ccsp():
 
 @pytest.fixture(scope="module")
 def tiny():
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     return mesh, ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
 
 
@@ -187,7 +187,7 @@ def test_move_back_is_exact_negative(ccsp, tiny):
 
 @pytest.fixture(scope="module")
 def grid():
-    mesh = sg.subdivide(sg.make_scene("grid"))
+    mesh = helpers.subdivided(sg.make_scene("grid"))
     return mesh, ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
 
 
@@ -436,7 +436,7 @@ def test_large_bench_configuration_sampled(ccsp):
     computed on the triangles around them, bit for bit; f and its parts equal the sums of terms
     built from the per-edge weights within the reordering bound."""
     sc = sg.make_scene("large")
-    mesh = sg.subdivide(sc)
+    mesh = helpers.subdivided(sc)
     size = sc.box[1] - sc.box[0]
     p = ob.Params(1e-3 * size, eps0=1e-10 * size, mu_angle=1.0 * size, mu_len=10.0 * size)
     with ccsp.MovableMesh.from_mesh(mesh) as gm:

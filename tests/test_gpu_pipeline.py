@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+import helpers
 import scenegen as sg
 
 pytestmark = pytest.mark.gpu
@@ -28,7 +29,7 @@ def ccsp():
 def run(ccsp):
     from paper_2112_05570_amd import pipeline as pl
     sc = sg.make_scene("tiny")
-    mesh = sg.subdivide(sc)
+    mesh = helpers.subdivided(sc)
     size = sc.box[1] - sc.box[0]
     sched = pl.Schedule(stages=9, t0_rel=1e-3, t1_rel=1e-5, e0_rel=2e-2, e1_rel=2e-3,
                         outer_max=4, flip_rounds=32, seed=3)
@@ -112,7 +113,7 @@ def test_other_scenes_and_seeds(ccsp, name, kw, seed):
     checker's on a sample of located rays, hitting the CDT's primitives."""
     from paper_2112_05570_amd import pipeline as pl
     sc = sg.make_scene(name, **kw)
-    mesh = sg.subdivide(sc)
+    mesh = helpers.subdivided(sc)
     size = sc.box[1] - sc.box[0]
     sched = pl.Schedule(stages=8, t0_rel=1e-3, t1_rel=1e-5, e0_rel=5e-3, e1_rel=5e-4,
                         outer_max=3, flip_rounds=32, seed=seed)

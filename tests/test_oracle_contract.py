@@ -12,6 +12,7 @@ import math
 import numpy as np
 
 import oracle
+import helpers
 import scenegen as sg
 from oracle import contract as ct
 from oracle import objective as ob
@@ -82,7 +83,7 @@ def _edges(tv):
 
 def _clustered_mesh(seed, eps):
     """The subdivided tiny scene with many vertices pulled next to a neighbour."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     om = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     rng = np.random.default_rng(seed)
     xy = mesh.xy.copy()

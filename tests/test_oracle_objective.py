@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+import helpers
 import scenegen as sg
 from oracle import objective as ob
 
@@ -179,7 +180,7 @@ def test_length_penalty_and_total():
 def test_vanishing_eps_is_plain_weight():
     """As eps -> 0 every edge weighs 1: w_contr is the triangulation's weight."""
     sc = sg.make_scene("tiny")
-    mesh = sg.subdivide(sc)
+    mesh = helpers.subdivided(sc)
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     r = ob.objective(m, mesh.xy, ob.Params(1e-300))
     assert (r["w"] == 1.0).all()
@@ -198,7 +199,7 @@ def test_vanishing_eps_is_plain_weight():
 def test_large_eps_halves_contractible_edges():
     """With eps beyond every length, contractible edges have c -> 1/2 as |e|/eps -> 0; an edge
     whose neighbours are all contractible weighs x M(x) for x = 1/16 (two triangles) = 0."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     r = ob.objective(m, mesh.xy, ob.Params(1e12))
     assert np.allclose(r["c"][r["contractible"]], 0.5, atol=1e-11)
@@ -215,7 +216,7 @@ def _moves(mesh, n, seed, lam):
 def test_delta_properties():
     """Null moves change nothing; moving back undoes a move; a chain of accepted moves adds up to
     the change of f; folding, fixed and malformed moves are flagged."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     p = ob.Params(0.02)
     xy = mesh.xy.copy()
@@ -255,7 +256,7 @@ def test_metropolis_chain_properties():
     """T = 0 accepts exactly the moves that do not increase f, so f never rises and the accepted
     changes add up to the change of f; a huge T accepts every valid move; constrained vertices stay
     on their original edges."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     p = ob.Params(0.03)
     rng = np.random.default_rng(4)
@@ -281,7 +282,7 @@ def test_metropolis_chain_properties():
 def test_edge_values_one_by_one_equal_whole_evaluation():
     """The per-edge evaluation used to sample large meshes equals the whole-mesh evaluation, on a
     clustered state where contractions, merges and the 1-hop rule all occur."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     rng = np.random.default_rng(9)
     xy = mesh.xy.copy()

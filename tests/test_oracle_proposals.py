@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+import helpers
 import scenegen as sg
 from oracle import objective as ob
 
@@ -131,7 +132,7 @@ def test_contract_proposal_changes_the_contracted_state():
 
 def test_constrained_proposals_stay_on_their_edge():
     """Proposals for a constrained vertex are projected on its original edge (Sec. 3.2.1)."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     xy = mesh.xy
     cons = np.nonzero(mesh.kind == ob.CONSTRAINED)[0][:10]
@@ -150,7 +151,7 @@ def test_constrained_proposals_stay_on_their_edge():
 def test_zero_temperature_chain_never_raises_f(kind):
     """At T = 0 only moves that do not raise f are taken: f falls by the sum of the accepted
     changes, and only accepted vertices move."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     p = ob.Params(0.05)
     rng = np.random.default_rng(6)
@@ -174,7 +175,7 @@ def test_group_members_and_area():
     """With d just above the two nearest neighbours' distance, no other vertex comes that close in
     a CDT-based mesh, so the members are the centre and those movable neighbours; the group area
     counts the triangles two members share once (star areas added, shared ones taken off)."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     xy = mesh.xy
     checked = 0
@@ -201,7 +202,7 @@ def test_group_members_and_area():
 def test_lone_centre_is_the_single_vertex_move():
     """A group with no member but its centre makes the move of Sec. 3.2.2: the same position,
     status and acceptance as the single-vertex chain with displacement lam * sqrt(star area) * xi."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     p = ob.Params(1e-9)  # d < every edge: lone centres
     rng = np.random.default_rng(8)
@@ -224,7 +225,7 @@ def test_lone_centre_is_the_single_vertex_move():
 def test_group_moves_rigidly():
     """Free members share one displacement: the edges between them keep their lengths (to
     rounding) when the move is accepted."""
-    mesh = sg.subdivide(sg.make_scene("tiny"))
+    mesh = helpers.subdivided(sg.make_scene("tiny"))
     m = ob.Mesh(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v)
     p = ob.Params(0.2)  # d up to 1: whole neighbourhoods
     rng = np.random.default_rng(9)
