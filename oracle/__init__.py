@@ -23,7 +23,8 @@ _lib = None
 def build() -> str:
     """Compile liboracle.so with gcc (C11, no floating-point contraction, OpenMP)."""
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
-           "-o", _LIB_PATH + ".tmp", os.path.join(_HERE, "oracle.c"), "-lm"]
+           "-o", _LIB_PATH + ".tmp", os.path.join(_HERE, "oracle.c"),
+           os.path.join(_HERE, "oracle3d.c"), "-lm"]
     subprocess.check_call(cmd)
     os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
     return _LIB_PATH
@@ -178,3 +179,116 @@ def validate(tri: Triangulation, delaunay: bool = False) -> str:
 
 def num_threads() -> int:
     return int(_L().oracle_num_threads())
+
+
+# ---------------------------------------------------------------- the 3D walk (oracle3d.c)
+
+class _Tet(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64), ("xyz", ctypes.c_void_p), ("nt", ctypes.c_int64),
+                ("tet_v", ctypes.c_void_p), ("tet_nbr", ctypes.c_void_p),
+                ("tet_prim", ctypes.c_void_p), ("np", ctypes.c_int64), ("prims", ctypes.c_void_p)]
+
+
+def _L3():
+    lib = _L()
+    if not getattr(lib, "_tet_ready", False):
+        P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        lib.oracle3_orient.argtypes = [P, P, P, P]
+        lib.oracle3_orient.restype = I64
+        lib.oracle3_plucker.argtypes = [P, P, P, P]
+        lib.oracle3_plucker.restype = I64
+        lib.oracle3_pi.argtypes = [P, P, P, P, P]
+        lib.oracle3_pi.restype = I
+        lib.oracle3_walk.argtypes = [P, I64, P, P, P, I64, P, P, P, P, I]
+        lib.oracle3_brute.argtypes = [P, I64, P, P, P, P, P, P, I]
+        lib.oracle3_validate.argtypes = [P, ctypes.c_char_p, I]
+        lib.oracle3_locate.argtypes = [P, I64, P, P, P, I]
+        lib._tet_ready = True
+    return lib
+
+
+class TetMesh:
+    """A tetrahedralisation for the 3D checker (contiguous copies kept alive for C)."""
+
+    def __init__(self, xyz, tet_v, tet_nbr, tet_prim, prims):
+        self.xyz = _c(xyz, np.int32).reshape(-1, 3)
+        self.tet_v = _c(tet_v, np.int32).reshape(-1, 4)
+        self.tet_nbr = _c(tet_nbr, np.int32).reshape(-1, 4)
+        self.tet_prim = _c(tet_prim, np.int32).reshape(-1, 4)
+        self.prims = _c(prims, np.int32).reshape(-1, 3)
+        self.c = _Tet(self.xyz.shape[0], _p(self.xyz), self.tet_v.shape[0], _p(self.tet_v),
+                      _p(self.tet_nbr), _p(self.tet_prim), self.prims.shape[0], _p(self.prims))
+
+    @classmethod
+    def of(cls, scene):
+        return cls(scene.xyz, scene.tet_v, scene.tet_nbr, scene.tet_prim, scene.prims)
+
+
+def orient3(a, b, c, d) -> int:
+    """det[b - a; c - a; d - a] for integer grid points, exact."""
+    a, b, c, d = (_c(x, np.int32) for x in (a, b, c, d))
+    return int(_L3().oracle3_orient(_p(a), _p(b), _p(c), _p(d)))
+
+
+def plucker3(o, d, p, q) -> int:
+    """d . ((p - o) x (q - o)), exact."""
+    o, d, p, q = (_c(x, np.int32) for x in (o, d, p, q))
+    return int(_L3().oracle3_plucker(_p(o), _p(d), _p(p), _p(q)))
+
+
+def pi3(o, d, p, q):
+    """The walk's sign for the directed edge (p, q) after the symbolic move of the line; returns
+    (sign, degenerate)."""
+    o, d, p, q = (_c(x, np.int32) for x in (o, d, p, q))
+    dg = ctypes.c_int(0)
+    s = _L3().oracle3_pi(_p(o), _p(d), _p(p), _p(q), ctypes.byref(dg))
+    return int(s), bool(dg.value)
+
+
+def _outs3(n):
+    return np.empty(n, np.int32), np.empty(n, np.float64), np.empty(n, np.int32), np.empty(n, np.int32)
+
+
+def walk3(mesh: TetMesh, o, d, start, threads: int = 0, max_steps: int = 0):
+    """The 3D walk ray by ray. Returns (prim, t, steps, degenerate): prim >= 0 the primitive hit,
+    -1 out through a hull face that is not a primitive, -2 stopped at max_steps tetrahedra
+    (0: the tetrahedron count), -3 invalid ray (zero direction, start out of range or the origin
+    not strictly inside it)."""
+    o, d, start = _c(o, np.int32).reshape(-1, 3), _c(d, np.int32).reshape(-1, 3), _c(start, np.int32)
+    n = start.shape[0]
+    prim, t, steps, dg = _outs3(n)
+    _L3().oracle3_walk(ctypes.byref(mesh.c), n, _p(o), _p(d), _p(start), int(max_steps), _p(prim),
+                       _p(t), _p(steps), _p(dg), int(threads))
+    return prim, t, steps, dg
+
+
+def brute3(mesh: TetMesh, o, d, threads: int = 0):
+    """First primitive and crossing count by brute force over every face. Returns
+    (prim, t, steps, ambiguous): bit 0 of ambiguous marks a hit, bit 1 a count, that depends on how
+    ties are broken."""
+    o, d = _c(o, np.int32).reshape(-1, 3), _c(d, np.int32).reshape(-1, 3)
+    n = o.shape[0]
+    prim, t, steps, dg = _outs3(n)
+    st = _L3().oracle3_brute(ctypes.byref(mesh.c), n, _p(o), _p(d), _p(prim), _p(t), _p(steps),
+                             _p(dg), int(threads))
+    if st != 0:
+        raise MemoryError("oracle3_brute")
+    return prim, t, steps, dg
+
+
+def locate3(mesh: TetMesh, q, threads: int = 0):
+    """Brute-force point location. Returns (tet, status): 0 strictly inside, 1 on the boundary of
+    the first tetrahedron holding the point, -1 in none."""
+    q = _c(q, np.int32).reshape(-1, 3)
+    n = q.shape[0]
+    tt = np.empty(n, np.int32)
+    st = np.empty(n, np.int32)
+    _L3().oracle3_locate(ctypes.byref(mesh.c), n, _p(q), _p(tt), _p(st), int(threads))
+    return tt, st
+
+
+def validate3(mesh: TetMesh) -> str:
+    """'' if the tetrahedralisation passes every check, else the first failure."""
+    buf = ctypes.create_string_buffer(256)
+    r = _L3().oracle3_validate(ctypes.byref(mesh.c), buf, 256)
+    return "" if r == 0 else buf.value.decode()

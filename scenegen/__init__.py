@@ -481,3 +481,141 @@ def multi_sizes(name: str, seed: int = 0) -> tuple:
     segs = log_uniform_int(u[:, 0], *w["n_seg"])
     rays = log_uniform_int(u[:, 1], *w["rays"])
     return segs, rays
+
+
+# ---------------------------------------------------------------- 3D: tetrahedralisations
+#
+# Inputs of the 3D walk: vertices on the integer grid 0 <= x, y, z < 2^19, ray origins on the same
+# grid and integer directions with |components| <= 2^19, so that every orientation and Plücker
+# sign of the walk is an exact int64 computation. The tetrahedralisation is the Delaunay one of
+# seeded random grid points (scipy/Qhull), each tetrahedron positively oriented (checked exactly);
+# the scene's primitives are faces of it: every hull face and a seeded fraction of the interior
+# faces, so that the tetrahedralisation is a constrained one for them without a constrained
+# builder.
+
+GRID3 = 1 << 19
+
+
+@dataclass
+class TetScene:
+    xyz: np.ndarray       # (V,3) int32 grid coordinates
+    tet_v: np.ndarray     # (T,4) int32, orient3d(v0, v1, v2, v3) > 0
+    tet_nbr: np.ndarray   # (T,4) int32, the tetrahedron across face i (opposite v[i]); -1 hull
+    tet_prim: np.ndarray  # (T,4) int32, primitive of face i, -1 if not scene geometry
+    prims: np.ndarray     # (P,3) int32 vertex ids of each primitive triangle
+    name: str = ""
+
+    @property
+    def n_vertices(self):
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_tets(self):
+        return int(self.tet_v.shape[0])
+
+    @property
+    def n_prims(self):
+        return int(self.prims.shape[0])
+
+
+# the faces of a tetrahedron, opposite v[i], as seen from outside when v0..v3 is positive
+TET_FACES = ((1, 2, 3), (0, 3, 2), (0, 1, 3), (0, 2, 1))
+
+
+def orient3_int(a, b, c, d):
+    """det[b - a; c - a; d - a] over int64 rows (exact for grid coordinates)."""
+    a, b, c, d = (np.asarray(x, dtype=np.int64) for x in (a, b, c, d))
+    # contiguous columns: strided column views make the products several times slower
+    (u0, u1, u2), (v0, v1, v2), (w0, w1, w2) = (
+        [np.ascontiguousarray(x[..., k] - a[..., k]) for k in range(3)] for x in (b, c, d))
+    return u0 * (v1 * w2 - v2 * w1) - u1 * (v0 * w2 - v2 * w0) + u2 * (v0 * w1 - v1 * w0)
+
+
+def make_tet_scene(n_points: int, seed: int, frac_prims: float = 0.15, open_hull=False) -> TetScene:
+    """The Delaunay tetrahedralisation of n_points seeded grid points with every hull face and a
+    seeded fraction of the interior faces as primitives (open_hull: hull faces are not)."""
+    from scipy.spatial import Delaunay
+    for attempt in range(20):
+        rng = np.random.default_rng(np.random.SeedSequence([seed, TAG_SCENE, 3, attempt]))
+        pts = np.unique(rng.integers(0, GRID3, (n_points, 3)), axis=0)
+        rng.shuffle(pts)
+        dl = Delaunay(pts.astype(np.float64))
+        tv = dl.simplices.astype(np.int64)
+        nb = dl.neighbors.astype(np.int64)
+        o = orient3_int(*(pts[tv[:, i]].astype(np.int64) for i in range(4)))
+        if (o == 0).any():
+            continue  # a flat tetrahedron: draw the points again
+        neg = o < 0
+        tv[neg] = tv[neg][:, [1, 0, 2, 3]]
+        nb[neg] = nb[neg][:, [1, 0, 2, 3]]
+        break
+    else:
+        raise RuntimeError("no tetrahedralisation without flat tetrahedra")
+    T = tv.shape[0]
+    # faces named by (tet, i), each interior face once (from its lower tetrahedron), in row order;
+    # one uniform draw per interior face decides whether it is a primitive
+    t_idx, i_idx = np.nonzero((nb < 0) | (nb > np.arange(T)[:, None]))
+    n_idx = nb[t_idx, i_idx]
+    face_rng = np.random.default_rng(np.random.SeedSequence([seed, TAG_SCENE, 4]))
+    u = face_rng.random(t_idx.shape[0])
+    chosen = np.where(n_idx < 0, not open_hull, u < frac_prims)
+    t_c, i_c, n_c = t_idx[chosen], i_idx[chosen], n_idx[chosen]
+    k = np.arange(t_c.shape[0])
+    prim = -np.ones((T, 4), dtype=np.int64)
+    prim[t_c, i_c] = k
+    inner = n_c >= 0
+    j = np.argmax(nb[n_c[inner]] == t_c[inner][:, None], axis=1)
+    prim[n_c[inner], j] = k[inner]
+    faces = np.array(TET_FACES)
+    plist = np.stack([tv[t_c, faces[i_c, 0]], tv[t_c, faces[i_c, 1]], tv[t_c, faces[i_c, 2]]], 1)
+    return TetScene(np.ascontiguousarray(pts, dtype=np.int32), np.ascontiguousarray(tv, dtype=np.int32),
+                    np.ascontiguousarray(nb, dtype=np.int32), np.ascontiguousarray(prim, dtype=np.int32),
+                    np.ascontiguousarray(plist, dtype=np.int32).reshape(-1, 3),
+                    name=f"tets[{n_points}]" + ("+open" if open_hull else ""))
+
+
+@dataclass
+class Rays3:
+    o: np.ndarray       # (n,3) int32 grid points
+    d: np.ndarray       # (n,3) int32 nonzero
+    start: np.ndarray   # (n,) int32
+
+    @property
+    def n(self):
+        return int(self.start.shape[0])
+
+    def slice(self, a, b):
+        return Rays3(self.o[a:b], self.d[a:b], self.start[a:b])
+
+
+def sample_rays3(sc: TetScene, n: int, seed: int) -> Rays3:
+    """Rays with a start tetrahedron drawn by volume, an origin uniform inside it rounded to the
+    grid (drawn again until strictly inside, decided exactly), and an isotropic direction scaled
+    to 2^19 and rounded (never zero)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, TAG_RAYS, 3]))
+    P = sc.xyz.astype(np.int64)
+    vol = orient3_int(*(P[sc.tet_v[:, i]] for i in range(4))).astype(np.float64)
+    cdf = np.cumsum(vol) / vol.sum()
+    o = np.empty((n, 3), dtype=np.int64)
+    st = np.empty(n, dtype=np.int64)
+    todo = np.arange(n)
+    while todo.size:
+        k = todo.size
+        t = np.minimum(np.searchsorted(cdf, rng.random(k), side="right"), sc.n_tets - 1)
+        b = -np.log(rng.random((k, 4)))  # uniform barycentric coordinates
+        b /= b.sum(axis=1, keepdims=True)
+        V = P[sc.tet_v[t]]
+        q = np.rint(np.einsum("ki,kij->kj", b, V.astype(np.float64))).astype(np.int64)
+        inside = np.ones(k, dtype=bool)
+        for i in range(4):
+            f = TET_FACES[i]
+            inside &= orient3_int(V[:, f[0]], V[:, f[1]], V[:, f[2]], q) < 0
+        o[todo[inside]] = q[inside]
+        st[todo[inside]] = t[inside]
+        todo = todo[~inside]
+    g = rng.standard_normal((n, 3))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    d = np.rint(g * (GRID3 - 1)).astype(np.int64)
+    zero = (d == 0).all(axis=1)
+    d[zero] = [1, 0, 0]
+    return Rays3(o.astype(np.int32), d.astype(np.int32), st.astype(np.int32))
