@@ -14,6 +14,8 @@
  *              t = ((ax-ox)*nx + (ay-oy)*ny + (az-oz)*nz) / (dx*nx + dy*ny + dz*nz),
  *              n = (b - a) x (c - a), in IEEE binary64 in this order without fused operations,
  *   steps    = the number of tetrahedra visited, start and hit one included.
+ * A ray off the grid below, with a zero direction, a start out of range or an origin not strictly
+ * inside its start ends with code -3 and steps 0.
  *
  * Inputs live on an integer grid: vertex and origin coordinates in [0, 2^19), direction
  * components in [-2^19, 2^19], so every sign below is an exact int64 computation (a difference of
@@ -125,7 +127,10 @@ static void walk3_one(const oracle_tet_t *m, const int32_t *o, const int32_t *d,
   *t = INFINITY;
   *steps = 0;
   int dg = 0;
-  if (start < 0 || start >= m->nt || (d[0] == 0 && d[1] == 0 && d[2] == 0)) {
+  int on_grid = 1;
+  for (int k = 0; k < 3; ++k)
+    on_grid = on_grid && o[k] >= 0 && o[k] < (1 << 19) && d[k] >= -(1 << 19) && d[k] <= (1 << 19);
+  if (!on_grid || start < 0 || start >= m->nt || (d[0] == 0 && d[1] == 0 && d[2] == 0)) {
     *degen = 0;
     return;
   }

@@ -72,6 +72,58 @@ class Scene:
         self.free()
 
 
+class TetMesh:
+    """A 3D tetrahedralisation resident on the current device (include/ccsp_tet.h): integer grid
+    coordinates in [0, 2^19), positively oriented tetrahedra, primitives among their faces."""
+
+    def __init__(self, xyz, tet_v, tet_nbr, tet_prim, prims):
+        xyz, tv, tn, tp, pr = (_c(a, np.int32) for a in (xyz, tet_v, tet_nbr, tet_prim, prims))
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p).value
+        desc = B.TetMeshDesc(xyz.reshape(-1, 3).shape[0], p(xyz), tv.reshape(-1, 4).shape[0],
+                             p(tv), p(tn), p(tp), pr.reshape(-1, 3).shape[0], p(pr))
+        self.handle = None
+        self.handle = B.load_tetmesh(desc)
+        self.n_tets, self.device_bytes = B.tetmesh_info(self.handle)
+
+    @classmethod
+    def from_arrays(cls, scene):
+        """From any object with xyz, tet_v, tet_nbr, tet_prim and prims arrays."""
+        return cls(scene.xyz, scene.tet_v, scene.tet_nbr, scene.tet_prim, scene.prims)
+
+    def free(self):
+        if self.handle:
+            B.free_tetmesh(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+def trace3d(mesh: TetMesh, o, d, start, out: "Result | None" = None, step_limit: int = 0,
+            tune: "B.Tune3d | None" = None, stream=None):
+    """Walk rays through a tetrahedralisation: o, d (n, 3) int32 and start (n,) int32 CUDA
+    tensors. Returns a Result (hit_prim, hit_t, steps) in input order."""
+    import torch
+    n = start.shape[0]
+    for name, x, shape in (("o", o, (n, 3)), ("d", d, (n, 3)), ("start", start, (n,))):
+        if not x.is_cuda or x.dtype != torch.int32 or tuple(x.shape) != shape or not x.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous int32 CUDA tensor of shape {shape}")
+    res = _outputs(n, start.device, out)
+    B.trace_rays3d(mesh.handle, o.data_ptr(), d.data_ptr(), start.data_ptr(), n, int(step_limit),
+                   tune, res.hit_prim.data_ptr(), res.hit_t.data_ptr(), res.steps.data_ptr(),
+                   _stream(stream))
+    return res
+
+
 @dataclass
 class Result:
     hit_prim: "torch.Tensor"

@@ -52,7 +52,8 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
            "anneal_moves", "anneal_sweep", "anneal_propose", "anneal_schedule",
            "flip_anneal", "mesh_contract", "anneal_group",
-           "trace_rays_static", "mesh_subdivide")
+           "trace_rays_static", "mesh_subdivide",
+           "load_tetmesh", "free_tetmesh", "tetmesh_info", "trace_rays3d")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -192,6 +193,31 @@ _lib.mesh_contract.restype = _I
 _lib.anneal_group.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double,
                               ctypes.c_double, _P, _I64, _P, _P, _P, _P, _P, _P, _P]
 _lib.anneal_group.restype = _I
+
+
+# ---- include/ccsp_tet.h
+
+class TetMeshDesc(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("xyz", ctypes.c_void_p),
+                ("n_tets", ctypes.c_int64), ("tet_v", ctypes.c_void_p),
+                ("tet_nbr", ctypes.c_void_p), ("tet_prim", ctypes.c_void_p),
+                ("n_prims", ctypes.c_int64), ("prims", ctypes.c_void_p)]
+
+
+class Tune3d(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("rays_per_claim", ctypes.c_int32), ("refill_min", ctypes.c_int32)]
+
+
+_lib.load_tetmesh.argtypes = [ctypes.POINTER(TetMeshDesc), ctypes.POINTER(_P)]
+_lib.load_tetmesh.restype = _I
+_lib.free_tetmesh.argtypes = [_P]
+_lib.free_tetmesh.restype = _I
+_lib.tetmesh_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+_lib.tetmesh_info.restype = _I
+_lib.trace_rays3d.argtypes = [_P, _P, _P, _P, _I64, ctypes.c_int32, ctypes.POINTER(Tune3d),
+                              _P, _P, _P, _P]
+_lib.trace_rays3d.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -452,3 +478,27 @@ def gather_roofline(working_set_bytes: int, waves_per_cu: int = 16, steps_per_la
 def raw_call(name: str, *args):
     """Direct access to an exported symbol (for tests of argument handling)."""
     return getattr(_lib, name)(*args)
+
+
+def load_tetmesh(desc: TetMeshDesc) -> int:
+    h = _P()
+    _check(_lib.load_tetmesh(ctypes.byref(desc), ctypes.byref(h)))
+    return h.value
+
+
+def free_tetmesh(mesh: int) -> None:
+    _check(_lib.free_tetmesh(_P(mesh)))
+
+
+def tetmesh_info(mesh: int) -> tuple:
+    nt, nb = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.tetmesh_info(_P(mesh), ctypes.byref(nt), ctypes.byref(nb)))
+    return nt.value, nb.value
+
+
+def trace_rays3d(mesh: int, o: int, d: int, start: int, n: int, step_limit: int,
+                 tune: Tune3d | None, hit_prim: int, hit_t: int, steps: int,
+                 stream: int = 0) -> None:
+    _check(_lib.trace_rays3d(_P(mesh), _P(o), _P(d), _P(start), n, step_limit,
+                             ctypes.byref(tune) if tune is not None else None, _P(hit_prim),
+                             _P(hit_t), _P(steps), _P(stream)))

@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libccsp_walk.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
            for f in ("walk_kernels.hip", "bin.hip", "gather.hip", "locate.hip", "objective.hip", "flips.hip", "capi.cpp", "contract.cpp", "subdivide.cpp",
-                     "serve.cpp")]
+                     "serve.cpp", "tet3d.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
