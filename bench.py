@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large",
                     choices=["large", "grid", "tiny", "batch", "serve", "objective", "flips",
-                             "pipeline"],
+                             "pipeline", "tet3d"],
                     help="batch: the 256-scene workload in one graph-replayed, autotuned launch; "
                          "serve: the request server under Poisson arrivals; objective: the "
                          "low-weight objective on the subdivided large scene; flips: edge-flip "
@@ -85,6 +85,8 @@ def main():
                     help="leave out the objective leg (for profiler runs of the walk)")
     ap.add_argument("--no-multi", action="store_true",
                     help="leave out the batch and serving legs of the default run")
+    ap.add_argument("--no-tet3d", action="store_true",
+                    help="leave out the 3D tetrahedral walk leg of the default run")
     ap.add_argument("--multi-requests", type=int, default=3000,
                     help="requests per load level of the default run's serving leg")
     ap.add_argument("--tune", default="", help="wg,tile,waves_per_cu,refill_min")
@@ -122,6 +124,10 @@ def main():
         return
     if args.workload == "objective":
         print(json.dumps(objective_leg("large", args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "tet3d":
+        print(json.dumps(tet3d_leg(args.steps, args.warmup,
+                                   None if args.no_cpu else args.cpu_seconds / 2)), flush=True)
         return
     if args.workload == "pipeline":
         sc = (sg.make_scene("grid", seed=0) if args.scene == "grid"
@@ -270,6 +276,10 @@ def main():
         batch = batch_leg(3, 1, args.tune_cache)
         serve = serve_leg(args.multi_requests, args.slots)
 
+    tet3d = None
+    if args.workload == "large" and not args.no_tet3d:
+        tet3d = tet3d_leg(args.steps, args.warmup, None if args.no_cpu else args.cpu_seconds / 2)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_leg(sc, rays, args.cpu_seconds)
@@ -352,6 +362,7 @@ def main():
         "objective": objective,
         "triangulations": triangulations,
         "low_weight": low_weight,
+        "tet3d": tet3d,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -1057,6 +1068,116 @@ def pure_binary32_t_error(sc, o, d, res, torch, sample=1 << 20):
     rel = ((t32.double() - t64).abs() / t64.abs()).cpu().numpy()
     return {"p50": float(np.percentile(rel, 50)), "p99": float(np.percentile(rel, 99)),
             "max": float(rel.max()), "sample": int(rel.size)}
+
+
+TET3D_POINTS, TET3D_FRAC, TET3D_RAYS = 200_000, 0.05, 1 << 22
+
+
+def tet3d_leg(steps, warmup, cpu_seconds):
+    """The 3D walk (include/ccsp_tet.h): a Delaunay tetrahedralisation of 200,000 seeded grid
+    points with every hull face and 5% of the interior faces as primitives, 4M rays with a start
+    tetrahedron drawn by volume, an origin uniform in it and an isotropic direction. Whole traces
+    (binning and start records, then the walk) timed with events on the stream; stage times from
+    the library's own events; the walk's gather rate against the dependent-gather chase on a
+    buffer the size of the face slots."""
+    import numpy as np
+    import torch
+
+    import paper_2112_05570_amd as ccsp
+    from paper_2112_05570_amd import binding as B
+    import scenegen as sg
+
+    t0 = time.perf_counter()
+    sc = sg.make_tet_scene(TET3D_POINTS, seed=0, frac_prims=TET3D_FRAC)
+    r = sg.sample_rays3(sc, TET3D_RAYS, seed=1)
+    log(f"[bench] tet3d: {sc.n_tets} tetrahedra, {sc.n_prims} primitives, {r.n} rays "
+        f"(built in {time.perf_counter() - t0:.1f}s)")
+    dev = [torch.from_numpy(a).to("cuda:0") for a in (r.o, r.d, r.start)]
+    stream = torch.cuda.current_stream()
+    n = r.n
+    with ccsp.TetMesh.from_arrays(sc) as mesh:
+        res = ccsp.trace3d(mesh, *dev)
+
+        def timed(k, **kw):
+            for _ in range(warmup):
+                ccsp.trace3d(mesh, *dev, out=res, **kw)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(k):
+                ccsp.trace3d(mesh, *dev, out=res, **kw)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / k
+
+        ms = timed(steps)
+        ms_io = timed(max(1, steps // 2), input_order=True)
+        stages = []
+        for _ in range(max(3, steps // 2)):
+            ccsp.trace3d(mesh, *dev, out=res, timed=True)
+            stages.append(ccsp.trace3d_stage_times())
+        bin_ms, walk_ms = (float(np.mean([x[i] for x in stages])) for i in range(2))
+        steps_np = res.steps.cpu().numpy()
+        prim_np = res.hit_prim.cpu().numpy()
+        slot_bytes = 64 * sc.n_tets
+        chase = B.gather_roofline(slot_bytes, 16, 2048, stream.cuda_stream)
+    steps_total = int(steps_np.sum(dtype=np.int64))
+    # the walk's algorithmic bytes: the 64-byte start record, one 16-byte face slot per visited
+    # tetrahedron (its exit face), the 16 bytes of results
+    walk_bytes = 64 * n + 16 * steps_total + 16 * n
+    walk_gbs = walk_bytes / (walk_ms / 1e3) / 1e9
+    loads_s = steps_total / (walk_ms / 1e3)
+    out = {
+        "workload": f"tets: {TET3D_POINTS} seeded grid points (Delaunay), {sc.n_tets} tetrahedra, "
+                    f"hull + {int(TET3D_FRAC * 100)}% of interior faces as {sc.n_prims} primitives, "
+                    f"{n} rays (origin uniform in a volume-drawn start, isotropic direction), seed 0",
+        "rays": n, "tetrahedra": sc.n_tets, "primitives": sc.n_prims,
+        "value": n / ms * 1e3, "unit": "rays/s", "ms_per_trace": ms,
+        "ms_per_trace_input_order": ms_io,
+        "stages_ms": {"binning_and_start": bin_ms, "walk": walk_ms},
+        "mean_steps_per_ray": steps_total / n,
+        "p99_steps_per_ray": float(np.percentile(steps_np, 99)),
+        "steps_per_s": steps_total / ms * 1e3,
+        "rays_not_hit": int((prim_np < 0).sum()),
+        "dtype": "int32 coordinates, f64 filter + exact int64",
+        "roofline": {"bound": "hbm", "kernel": "walk3d", "kernel_ms": walk_ms,
+                     "achieved": walk_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": walk_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": walk_bytes,
+                     "bytes_model": "64 B/ray start record + 16 B per visited tetrahedron (its "
+                                    "exit slot) + 16 B/ray results (algorithmic)"},
+        "gather": {"slot_loads_per_s": loads_s, "chase_loads_per_s_slot_sized": chase,
+                   "slot_bytes": slot_bytes, "frac_of_chase": loads_s / chase},
+    }
+    if cpu_seconds:
+        out["cpu_baseline"] = tet3d_cpu_leg(sc, r, cpu_seconds)
+    return out
+
+
+def tet3d_cpu_leg(sc, r, budget_s):
+    """The 3D checker's walk, as it stands, on the host cores: a bounded prefix of the same rays."""
+    import numpy as np
+
+    import oracle
+
+    m3 = oracle.TetMesh.of(sc)
+    threads = oracle.num_threads()
+    m = 1 << 14
+    while True:
+        t = time.perf_counter()
+        oracle.walk3(m3, r.o[:m], r.d[:m], r.start[:m], threads)
+        dt = time.perf_counter() - t
+        if dt >= 1.0 or m >= r.n:
+            break
+        m = min(r.n, m * 4)
+    m = int(min(r.n, max(m, m * budget_s / dt)))
+    t = time.perf_counter()
+    _, _, s, _ = oracle.walk3(m3, r.o[:m], r.d[:m], r.start[:m], threads)
+    dt = time.perf_counter() - t
+    log(f"[bench] 3D checker walk: {m} rays on {threads} threads in {dt:.1f}s")
+    return {"value": m / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {m} of the same rays (exact int64 checker walk, OpenMP over rays)",
+            "steps_per_s": float(np.sum(s, dtype=np.int64)) / dt, "cpu": cpu_model()}
 
 
 def cpu_model():

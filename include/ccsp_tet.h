@@ -76,9 +76,11 @@ typedef struct {
  * the neighbour it names, whose fourth vertex lies strictly on the face's outer side, and every
  * primitive face named by both of its tetrahedra and made of its primitive's three vertices.
  * Returns CCSP_E_BAD_TRIANGULATION with the first failure in last_error(), CCSP_E_OOM if device
- * memory runs out. Device memory: 64 bytes per tetrahedron (four 16-byte face slots: neighbour and
- * entry face, the neighbour's fourth vertex, the vertex order across the face) plus 48 bytes per
- * tetrahedron for its four vertices (read in the start tetrahedron). */
+ * memory runs out. The library renumbers the tetrahedra internally along a Morton curve of their
+ * centroids (callers keep using their own ids). Device memory: 128 bytes per tetrahedron: four
+ * 16-byte face slots (the neighbour and its entry face, the neighbour's fourth vertex, the vertex
+ * order across the face) and 64 bytes for its four vertices and internal id (read in the start
+ * tetrahedron). */
 int load_tetmesh(const TetMeshDesc *desc, TetMesh **out);
 
 /* Free a loaded tetrahedralisation (synchronises the device first). NULL is a no-op. */
@@ -90,22 +92,39 @@ int tetmesh_info(const TetMesh *mesh, int64_t *n_tets, int64_t *device_bytes);
 /* Launch parameters of trace_rays3d; zero fields take the defaults. */
 typedef struct {
   int32_t wg_size;        /* threads per workgroup: 64..512, multiple of 64 (default 256) */
-  int32_t waves_per_cu;   /* persistent waves per compute unit, 1..64 (default 32) */
+  int32_t waves_per_cu;   /* persistent waves per compute unit, 1..64 (default 12) */
   int32_t rays_per_claim; /* rays a wave takes per global atomic, 64..65536, multiple of 64
-                             (default 256) */
+                             (default 256); the wave stages them 64 at a time in LDS */
   int32_t refill_min;     /* refill a wave once this many lanes are idle, 1..64 (default 8) */
+  int32_t bin_key;        /* binning key: 1 = the origin's cell of an 8x8x8 Morton-ordered grid,
+                             2 = that cell and the octant of the direction (default 1) */
 } Tune3d;
 
 /* Walk n rays through `mesh` (Sec. 1.4's per-tetrahedron decision, the 3D form of Sec. 5.1's
- * walk). o, d: 3*n int32 (device), start: n int32 (device), outputs hit_prim (n int32), hit_t
- * (n binary64), steps (n int32) on the device, all in input order; every ray is independent, so
- * the output arrays may not overlap the inputs. step_limit: 0 = the tetrahedron count, which the
- * walk never exceeds; else a walk that would enter one tetrahedron more ends with CCSP_RAY_GUARD.
- * tune may be NULL. Asynchronous on `stream` (hipStream_t, NULL = default stream); n = 0 is a
- * no-op. Device memory: one 8-byte counter per device, allocated on the first call. */
+ * walk). o, d: 3*n int32 (device), start: n int32 (device, the caller's tetrahedron ids), outputs
+ * hit_prim (n int32), hit_t (n binary64), steps (n int32) on the device, all in input order;
+ * every ray is independent, so the output arrays may not overlap the inputs.
+ * flags: 0 or CCSP_TRACE_INPUT_ORDER (walk the rays in input order instead of binning them by
+ * start tetrahedron first), optionally with CCSP_TRACE_TIMED (record stage events for
+ * trace3d_stage_times). Binning is a counting sort by the origin's cell of an 8x8x8 grid in
+ * Morton order (and the direction's octant, Tune3d.bin_key), so that the rays an XCD walks start
+ * close together and the rays a wave walks also head the same way; it also decides every ray's
+ * start tetrahedron (the precondition checks and the first exit face), so the walk proper starts
+ * at the first exit. Results are the same in either order.
+ * step_limit: 0 = the tetrahedron count, which the walk never exceeds; else a walk that would
+ * enter one tetrahedron more ends with CCSP_RAY_GUARD. tune may be NULL. Asynchronous on `stream`
+ * (hipStream_t, NULL = default stream); n = 0 is a no-op.
+ * Device memory: a ring of 128 groups of 8 tile counters per device (at most 128 calls in flight
+ * on one device at once), and ray scratch of 64 bytes per ray plus 16 KiB per 4096 rays, shared by the
+ * device's traces, grown (after a device synchronisation) when n exceeds every earlier call's;
+ * traces that bin on different streams of one device are ordered one after the other. */
 int trace_rays3d(const TetMesh *mesh, const int32_t *o, const int32_t *d, const int32_t *start,
-                 int64_t n, int32_t step_limit, const Tune3d *tune, int32_t *hit_prim,
-                 double *hit_t, int32_t *steps, void *stream);
+                 int64_t n, int32_t flags, int32_t step_limit, const Tune3d *tune,
+                 int32_t *hit_prim, double *hit_t, int32_t *steps, void *stream);
+
+/* Stage durations of the device's most recent trace_rays3d with CCSP_TRACE_TIMED: binning and
+ * the walk, in milliseconds (waits for that trace to finish). */
+int trace3d_stage_times(float *bin_ms, float *walk_ms);
 
 #ifdef __cplusplus
 }

@@ -108,18 +108,25 @@ class TetMesh:
         self.free()
 
 
+def trace3d_stage_times():
+    """(binning ms, walk ms) of the device's last timed trace3d."""
+    return B.trace3d_stage_times()
+
+
 def trace3d(mesh: TetMesh, o, d, start, out: "Result | None" = None, step_limit: int = 0,
-            tune: "B.Tune3d | None" = None, stream=None):
+            tune: "B.Tune3d | None" = None, stream=None, input_order=False, timed=False):
     """Walk rays through a tetrahedralisation: o, d (n, 3) int32 and start (n,) int32 CUDA
-    tensors. Returns a Result (hit_prim, hit_t, steps) in input order."""
+    tensors. Returns a Result (hit_prim, hit_t, steps) in input order. Rays are binned by start
+    tetrahedron first unless input_order; timed records stage events (trace3d_stage_times)."""
     import torch
     n = start.shape[0]
     for name, x, shape in (("o", o, (n, 3)), ("d", d, (n, 3)), ("start", start, (n,))):
         if not x.is_cuda or x.dtype != torch.int32 or tuple(x.shape) != shape or not x.is_contiguous():
             raise ValueError(f"{name} must be a contiguous int32 CUDA tensor of shape {shape}")
     res = _outputs(n, start.device, out)
-    B.trace_rays3d(mesh.handle, o.data_ptr(), d.data_ptr(), start.data_ptr(), n, int(step_limit),
-                   tune, res.hit_prim.data_ptr(), res.hit_t.data_ptr(), res.steps.data_ptr(),
+    flags = (B.CCSP_TRACE_INPUT_ORDER if input_order else 0) | (B.CCSP_TRACE_TIMED if timed else 0)
+    B.trace_rays3d(mesh.handle, o.data_ptr(), d.data_ptr(), start.data_ptr(), n, flags,
+                   int(step_limit), tune, res.hit_prim.data_ptr(), res.hit_t.data_ptr(), res.steps.data_ptr(),
                    _stream(stream))
     return res
 

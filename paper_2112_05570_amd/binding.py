@@ -53,7 +53,8 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "anneal_moves", "anneal_sweep", "anneal_propose", "anneal_schedule",
            "flip_anneal", "mesh_contract", "anneal_group",
            "trace_rays_static", "mesh_subdivide",
-           "load_tetmesh", "free_tetmesh", "tetmesh_info", "trace_rays3d")
+           "load_tetmesh", "free_tetmesh", "tetmesh_info", "trace_rays3d",
+           "trace3d_stage_times")
 
 
 class TriangulationDesc(ctypes.Structure):
@@ -206,7 +207,8 @@ class TetMeshDesc(ctypes.Structure):
 
 class Tune3d(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("rays_per_claim", ctypes.c_int32), ("refill_min", ctypes.c_int32)]
+                ("rays_per_claim", ctypes.c_int32), ("refill_min", ctypes.c_int32),
+                ("bin_key", ctypes.c_int32)]
 
 
 _lib.load_tetmesh.argtypes = [ctypes.POINTER(TetMeshDesc), ctypes.POINTER(_P)]
@@ -215,9 +217,11 @@ _lib.free_tetmesh.argtypes = [_P]
 _lib.free_tetmesh.restype = _I
 _lib.tetmesh_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
 _lib.tetmesh_info.restype = _I
-_lib.trace_rays3d.argtypes = [_P, _P, _P, _P, _I64, ctypes.c_int32, ctypes.POINTER(Tune3d),
-                              _P, _P, _P, _P]
+_lib.trace_rays3d.argtypes = [_P, _P, _P, _P, _I64, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.POINTER(Tune3d), _P, _P, _P, _P]
 _lib.trace_rays3d.restype = _I
+_lib.trace3d_stage_times.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+_lib.trace3d_stage_times.restype = _I
 
 
 class CcspError(RuntimeError):
@@ -496,9 +500,15 @@ def tetmesh_info(mesh: int) -> tuple:
     return nt.value, nb.value
 
 
-def trace_rays3d(mesh: int, o: int, d: int, start: int, n: int, step_limit: int,
+def trace_rays3d(mesh: int, o: int, d: int, start: int, n: int, flags: int, step_limit: int,
                  tune: Tune3d | None, hit_prim: int, hit_t: int, steps: int,
                  stream: int = 0) -> None:
-    _check(_lib.trace_rays3d(_P(mesh), _P(o), _P(d), _P(start), n, step_limit,
+    _check(_lib.trace_rays3d(_P(mesh), _P(o), _P(d), _P(start), n, flags, step_limit,
                              ctypes.byref(tune) if tune is not None else None, _P(hit_prim),
                              _P(hit_t), _P(steps), _P(stream)))
+
+
+def trace3d_stage_times() -> tuple:
+    b, w = ctypes.c_float(), ctypes.c_float()
+    _check(_lib.trace3d_stage_times(ctypes.byref(b), ctypes.byref(w)))
+    return b.value, w.value

@@ -2,7 +2,8 @@
 bit in hit_prim, hit_t and steps:
 
 * a 2,000-point tetrahedralisation with 15% of its interior faces as primitives, 20,000 rays,
-  under several launch shapes;
+  binned and in input order, under several launch shapes, and with a trace of another mesh on
+  another stream in between;
 * rays through vertices, edge midpoints, parallel to edges and along edge lines (every zero sign
   decided by the moved line on both sides);
 * an open hull (misses), the step guard, invalid rays (zero direction, off the grid, start out of
@@ -57,13 +58,28 @@ def test_small_scene_vs_checker(ccsp):
     ref = oracle.walk3(oracle.TetMesh.of(sc), r.o, r.d, r.start)[:3]
     print(f"{sc.n_tets} tetrahedra, mean steps {ref[2].mean():.1f}", flush=True)
     with ccsp.TetMesh.from_arrays(sc) as mesh:
-        _same(_run(ccsp, mesh, r.o, r.d, r.start), ref, "default launch")
-        for tune in ((64, 1, 64, 1), (512, 8, 1024, 64), (128, 64, 64, 32)):
+        _same(_run(ccsp, mesh, r.o, r.d, r.start), ref, "default launch (binned)")
+        _same(_run(ccsp, mesh, r.o, r.d, r.start, input_order=True), ref, "input order")
+        for tune in ((64, 1, 64, 1, 1), (512, 8, 1024, 64, 2), (128, 64, 128, 32, 1)):
             t = ccsp.binding.Tune3d(*tune)
             _same(_run(ccsp, mesh, r.o, r.d, r.start, tune=t), ref, f"launch {tune}")
+            _same(_run(ccsp, mesh, r.o, r.d, r.start, tune=t, input_order=True), ref,
+                  f"launch {tune}, input order")
         # a ragged tail: fewer rays than one claim, and one ray
         for n in (1, 97):
             _same(_run(ccsp, mesh, r.o[:n], r.d[:n], r.start[:n]), tuple(x[:n] for x in ref), f"n={n}")
+        # a second mesh traced in between on another stream, then this one again
+        s2 = torch.cuda.Stream()
+        with ccsp.TetMesh.from_arrays(sg.make_tet_scene(500, seed=9)) as other:
+            r2 = sg.sample_rays3(sg.make_tet_scene(500, seed=9), 3000, seed=3)
+            with torch.cuda.stream(s2):
+                t2 = [torch.from_numpy(a).to(DEV) for a in (r2.o, r2.d, r2.start)]
+                res2 = ccsp.trace3d(other, *t2, stream=s2)
+            _same(_run(ccsp, mesh, r.o, r.d, r.start), ref, "after another stream")
+            torch.cuda.synchronize()
+            ref2 = oracle.walk3(oracle.TetMesh.of(sg.make_tet_scene(500, seed=9)), r2.o, r2.d, r2.start)[:3]
+            _same((res2.hit_prim.cpu().numpy(), res2.hit_t.cpu().numpy(), res2.steps.cpu().numpy()),
+                  ref2, "other stream")
 
 
 def test_degenerate_rays_vs_checker(ccsp):
@@ -110,6 +126,9 @@ def test_bench_workload_vs_checker(ccsp):
     ref = oracle.walk3(oracle.TetMesh.of(sc), r.o[idx], r.d[idx], r.start[idx])[:3]
     with ccsp.TetMesh.from_arrays(sc) as mesh:
         got = _run(ccsp, mesh, r.o, r.d, r.start)
+        got_io = _run(ccsp, mesh, r.o, r.d, r.start, input_order=True)
     _same(tuple(x[idx] for x in got), ref, "bench workload")
+    for a, b, name in zip(got, got_io, ("prim", "t", "steps")):
+        assert np.array_equal(a, b), f"binned and input-order {name} differ"
     assert (got[0] >= 0).all()
     assert 10 < got[2].mean() < 40

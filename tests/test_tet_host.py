@@ -73,7 +73,7 @@ def test_trace3d_argument_errors():
     lib_call = B.raw_call
     out = np.zeros(4, np.int64)
     p = out.ctypes.data
-    assert lib_call("trace_rays3d", None, p, p, p, 1, 0, None, p, p, p, None) == B.CCSP_E_ARG
+    assert lib_call("trace_rays3d", None, p, p, p, 1, 0, 0, None, p, p, p, None) == B.CCSP_E_ARG
     assert "null mesh" in B.last_error()
     assert lib_call("tetmesh_info", None, None, None) == B.CCSP_E_ARG
     assert lib_call("free_tetmesh", None) == B.CCSP_OK
