@@ -94,7 +94,8 @@ typedef struct {
 } ObjectiveParams;
 
 /*
- * mesh_load: build the mesh's edges, adjacency and scratch on the current device. Fails with
+ * mesh_load (the triangulation with vertex kinds that the objective of Sec. 2.2 is defined on):
+ * build the mesh's edges, adjacency and scratch on the current device. Fails with
  * CCSP_E_BAD_TRIANGULATION when an id is out of range, a triangle repeats a vertex, a kind is
  * unknown, a CONSTRAINED vertex names no original edge, an edge lies in more than two triangles,
  * or two triangles run through their shared edge in the same direction. Synchronous.
@@ -105,8 +106,8 @@ int mesh_load(const MeshDesc *desc, MovableMesh **out);
 int mesh_info(const MovableMesh *mesh, int64_t *n_edges, int32_t *edge_v);
 
 /*
- * objective_eval: f and its parts at positions xy (DEVICE, 2 * n_vertices binary64, 16-byte
- * aligned). out (DEVICE, 4 binary64) receives f, w_contr, P_angle, P_len. If not NULL,
+ * objective_eval (Sec. 2.2.4, f assembled from Secs. 2.2.1-2.2.3): f and its parts at positions
+ * xy (DEVICE, 2 * n_vertices binary64, 16-byte aligned). out (DEVICE, 4 binary64) receives f, w_contr, P_angle, P_len. If not NULL,
  * contractible (DEVICE, n_edges bytes, 1 = contractible) and weight (DEVICE, n_edges binary64,
  * w(e)) receive the per-edge values. Sums are reduced in a fixed order: the result is
  * reproducible for a mesh. Every triangle is expected to be counter-clockwise at xy (not checked).
@@ -116,8 +117,8 @@ int objective_eval(MovableMesh *mesh, const double *xy, const ObjectiveParams *p
                    double *out, uint8_t *contractible, double *weight, void *stream);
 
 /*
- * objective_delta: for k proposed moves, vertex vid[i] (DEVICE int32) to q_xy[2i..2i+1] (DEVICE
- * binary64, 16-byte aligned), each against the positions xy as they are (the moves are independent
+ * objective_delta (Secs. 3.2.1-3.2.2, the change of f under single-vertex moves): for k proposed
+ * moves, vertex vid[i] (DEVICE int32) to q_xy[2i..2i+1] (DEVICE binary64, 16-byte aligned), each against the positions xy as they are (the moves are independent
  * alternatives, not applied): delta[i] = f(xy with the vertex moved) - f(xy) (DEVICE binary64),
  * the sum of the differences of every term of f that the move changes, and status[i] (DEVICE
  * int32, CCSP_MOVE_*). A constrained vertex's new position is taken as given (the caller projects
@@ -128,8 +129,9 @@ int objective_delta(MovableMesh *mesh, const double *xy, const ObjectiveParams *
                     int32_t *status, void *stream);
 
 /*
- * mesh_classes: a partition of the movable (non-ORIGINAL) vertices into classes whose members are
- * pairwise more than four edges apart. A move's change of f reads positions within four edges of
+ * mesh_classes (the sweeps' parallel form of the sequential chain of Sec. 3.1): a partition of the
+ * movable (non-ORIGINAL) vertices into classes whose members are pairwise more than four edges
+ * apart. A move's change of f reads positions within four edges of
  * its vertex only, so the moves of one class do not interact: evaluating them all against the same
  * positions and applying the accepted ones gives what applying them one after another would, in
  * any order. Greedy colouring over the mesh's internal order, computed on the first call and kept.
@@ -157,8 +159,8 @@ int anneal_moves(MovableMesh *mesh, double *xy, const ObjectiveParams *params, d
                  int32_t *status, void *stream);
 
 /*
- * anneal_sweep: one Metropolis step for every movable vertex, class by class in the order of
- * mesh_classes (classes computed on first use): the result is that of the sequential chain over
+ * anneal_sweep (Sec. 3.1 acceptance, Sec. 3.2.2 displacements): one Metropolis step for every
+ * movable vertex, class by class in the order of mesh_classes (classes computed on first use): the result is that of the sequential chain over
  * the vertices in the order mesh_classes lists them. Entry i of disp (DEVICE, 2 binary64 per
  * movable vertex, 16-byte aligned), u, delta and status (DEVICE, one per movable vertex) belongs to
  * the i-th vertex of that list; moves, acceptance, projection and status codes are those of
@@ -170,8 +172,8 @@ int anneal_sweep(MovableMesh *mesh, double *xy, const ObjectiveParams *params, d
                  const double *disp, const double *u, double *delta, int32_t *status, void *stream);
 
 /*
- * anneal_propose: one sweep as anneal_sweep (class by class, equal to the sequential chain in the
- * order of mesh_classes) with the proposals of Secs. 3.2.4-3.2.6 in place of displacements. The
+ * anneal_propose (Secs. 3.2.4-3.2.6: resampling, swap, contraction to a neighbour): one sweep as
+ * anneal_sweep (class by class, equal to the sequential chain in the order of mesh_classes) with the proposals of Secs. 3.2.4-3.2.6 in place of displacements. The
  * i-th movable vertex v (mesh_classes order) uses draws[4i..4i+3] = r0, r1, r2, r3 (DEVICE
  * binary64, 16-byte aligned; r0, r1, r2 in [0, 1), and for SWAP (r2, r3) a point of the closed unit
  * disk) and u[i]; positions are the current ones, left by the vertices before it.

@@ -71,7 +71,8 @@ typedef struct {
   const int32_t *prims;     /* 3*n_prims vertex ids */
 } TetMeshDesc;
 
-/* Validate and upload a tetrahedralisation (host arrays; synchronous). Checks, exactly: ids and
+/* load_tetmesh: validate and upload a tetrahedralisation whose faces carry the scene's triangles
+ * (the 3D constrained triangulation of Sec. 1.3; host arrays; synchronous). Checks, exactly: ids and
  * coordinates in range, every tetrahedron positively oriented, every interior face shared with
  * the neighbour it names, whose fourth vertex lies strictly on the face's outer side, and every
  * primitive face named by both of its tetrahedra and made of its primitive's three vertices.
@@ -83,10 +84,10 @@ typedef struct {
  * tetrahedron). */
 int load_tetmesh(const TetMeshDesc *desc, TetMesh **out);
 
-/* Free a loaded tetrahedralisation (synchronises the device first). NULL is a no-op. */
+/* free_tetmesh: free a loaded tetrahedralisation (synchronises the device first). NULL is a no-op. */
 int free_tetmesh(TetMesh *mesh);
 
-/* Device bytes held by a loaded tetrahedralisation. */
+/* tetmesh_info: tetrahedron count and device bytes of a loaded tetrahedralisation. */
 int tetmesh_info(const TetMesh *mesh, int64_t *n_tets, int64_t *device_bytes);
 
 /* Launch parameters of trace_rays3d; zero fields take the defaults. */
@@ -122,7 +123,7 @@ int trace_rays3d(const TetMesh *mesh, const int32_t *o, const int32_t *d, const 
                  int64_t n, int32_t flags, int32_t step_limit, const Tune3d *tune,
                  int32_t *hit_prim, double *hit_t, int32_t *steps, void *stream);
 
-/* Stage durations of the device's most recent trace_rays3d with CCSP_TRACE_TIMED: binning and
+/* trace3d_stage_times: stage durations of the device's most recent trace_rays3d with CCSP_TRACE_TIMED: binning and
  * the walk, in milliseconds (waits for that trace to finish). */
 int trace3d_stage_times(float *bin_ms, float *walk_ms);
 

@@ -118,7 +118,10 @@ typedef struct {
 } TuneParams;
 
 /*
- * load_triangulation: validate desc, pack it for the walk and copy it to the current device.
+ * load_triangulation: validate desc, pack it for the walk and copy it to the current device. The
+ * packed form holds, per triangle and edge, what one step of the walk of Sec. 5.1 reads: the
+ * neighbour, the edge it is entered through, the vertex the next decision needs and the
+ * primitive of a constrained edge (Sec. 5.1: a constrained exit edge ends the walk).
  * Validation (exact): vertex ids in range, every triangle strictly counter-clockwise, coordinates
  * finite with magnitude < 2^64, neighbours in range and symmetric with the shared edge reversed,
  * the same primitive on both sides of an edge, primitive ids in range, every constrained edge
@@ -129,7 +132,10 @@ typedef struct {
 int load_triangulation(const TriangulationDesc *desc, void *stream, Triangulation **out);
 
 /*
- * trace_rays: walk n rays through one triangulation. All array arguments are DEVICE pointers
+ * trace_rays: walk n rays through one triangulation (Sec. 5.1: from the start triangle, one exit
+ * decision per triangle, stopping at a constrained edge or the hull; Sec. 5.4: steps counts the
+ * triangles visited; the first triangle has three candidate exit edges and every later one two,
+ * Sec. 7.2's footnote). All array arguments are DEVICE pointers
  * owned by the caller: o_xy and d_xy hold n interleaved (x,y) binary64 pairs (16-byte aligned),
  * start_tri n triangle ids; the outputs hit_prim, hit_t (8-byte aligned) and steps receive n
  * values each. d must be nonzero and the origin strictly inside start_tri. The call is
@@ -145,7 +151,8 @@ int trace_rays(const Triangulation *tri, const double *o_xy, const double *d_xy,
                const int32_t *start_tri, int64_t n, int precision, int32_t *hit_prim,
                double *hit_t, int32_t *steps, void *stream);
 
-/* trace_rays with explicit tuning of the persistent launch (tune may be NULL). */
+/* trace_rays_tuned: trace_rays (the walk of Sec. 5.1) with explicit tuning of the persistent launch
+ * (tune may be NULL); results do not depend on the tuning. */
 int trace_rays_tuned(const Triangulation *tri, const double *o_xy, const double *d_xy,
                      const int32_t *start_tri, int64_t n, int precision, int32_t *hit_prim,
                      double *hit_t, int32_t *steps, const TuneParams *tune, void *stream);
@@ -182,8 +189,9 @@ typedef struct {
 } TraceItem;
 
 /*
- * trace_batch: walk the rays of n_items items (possibly different triangulations of uneven
- * sizes) in one persistent launch, then finish them in one more. `items` is a HOST array, read
+ * trace_batch: the walk of Sec. 5.1, as in trace_rays, for the rays of n_items items (possibly
+ * different triangulations of uneven sizes) in one persistent launch, then finish them in one
+ * more. `items` is a HOST array, read
  * during the call. Results equal those of one trace_rays per item; rays are walked in input order
  * (no binning). The item table goes to the device through library-owned rings of pinned and device
  * tables (allocated at the first call and when n_items exceeds every earlier call's), so batches
@@ -213,9 +221,11 @@ int autotune(const TraceItem *items, int32_t n_items, int precision, int32_t rep
              TuneParams *best, float *best_ms, void *stream);
 
 /* tune_cache_set: store launch parameters for a workload shape (as autotune would; for reloading
- * results saved earlier). tune_cache_get: 1 and *out if the shape has an entry, 0 if not. */
+ * results saved earlier). Launch parameters only: the walk (Sec. 5.1) and its results do not
+ * depend on them. */
 int tune_cache_set(int32_t n_items, int64_t total_rays, int64_t total_triangles, int precision,
                    const TuneParams *tune);
+/* tune_cache_get: 1 and *out if the shape has an entry, 0 if not. */
 int tune_cache_get(int32_t n_items, int64_t total_rays, int64_t total_triangles, int precision,
                    TuneParams *out);
 
