@@ -14,15 +14,15 @@ from test_oracle_predicates import _side_cases, side_exact
 pytestmark = pytest.mark.slow
 
 
-def test_side_sign_million_cases():
+def test_side_sign_many_cases():
     rng = np.random.default_rng(11)
-    cases = _side_cases(rng, 1_000_000)
+    cases = _side_cases(rng, 300_000)
     signs = {-1: 0, 0: 0, 1: 0}
     for o, d, v in cases:
         e = side_exact(o, d, v)
         signs[e] += 1
         assert oracle.side_sign(o, d, v) == e, (o, d, v)
-    assert min(signs.values()) > 10_000
+    assert min(signs.values()) > 3_000
 
 
 @pytest.mark.parametrize("name, n_edges_rays, n_prims_rays", [("grid", 24, 120), ("large", 3, 12)])
