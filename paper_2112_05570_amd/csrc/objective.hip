@@ -65,6 +65,11 @@ struct MeshDev {
   double* c;              // scratch: contraction weight, length, contractibility per edge
   double* len;
   uint8_t* contr;
+  // scratch per edge, set by edge_state for the call's positions: bit 0, the conditioning
+  // restriction holds (it reads only ORIGINAL positions and the original edges of CONSTRAINED
+  // vertices, which no move changes); bit 1, the flat-triangle restriction may apply (a
+  // topological test, see flat_candidate)
+  uint8_t* rule;
   double* partial;
 };
 
@@ -324,11 +329,45 @@ __device__ bool flat_ok(const MeshDev& m, const double2* __restrict__ xy, int a,
   return true;
 }
 
-// Contractibility of edge e = (a, b) (Sec. 2.2.2), with vertex mv at q.
-__device__ bool contractible_at(const MeshDev& m, const double2* __restrict__ xy, int e, int a,
-                                int b, double eps, int mv, double2 q) {
-  return direct_ok(m, a, b) && one_hop_ok(m, xy, e, m.edge_opp[e], eps, mv, q) &&
-         conditioning_ok(m, xy, a, b) && flat_ok(m, xy, a, b, eps, mv, q);
+// Whether flat_ok can fail for edge (a, b) at all: it joins a FREE F and a non-FREE C, and a
+// triangle of F without C has its other two vertices, one of them CONSTRAINED, on an original
+// edge through C. Kinds and topology only.
+__device__ bool flat_candidate(const MeshDev& m, int a, int b) {
+  const int ka = m.vk[a].x, kb = m.vk[b].x;
+  if ((ka == CCSP_VERTEX_FREE) == (kb == CCSP_VERTEX_FREE)) return false;
+  const int F = ka == CCSP_VERTEX_FREE ? a : b, C = ka == CCSP_VERTEX_FREE ? b : a;
+  for (int k = m.vtri_off[F], end = m.vtri_off[F + 1]; k < end; ++k) {
+    const int4 t = m.tri[m.vtri[k]];
+    if (t.x == C || t.y == C || t.z == C) continue;
+    const int X = t.x == F ? t.y : t.x;
+    const int Y = t.z == F ? t.y : t.z;
+    const bool cx = m.vk[X].x == CCSP_VERTEX_CONSTRAINED, cy = m.vk[Y].x == CCSP_VERTEX_CONSTRAINED;
+    if (!cx && !cy) continue;
+    const int L = m.vk[cx ? X : Y].y;
+    if (on_line(m, X, L) && on_line(m, Y, L) && on_line(m, C, L)) return true;
+  }
+  return false;
+}
+
+// The position-independent restrictions of edge (a, b) for edge_state's rule bits.
+__device__ __forceinline__ uint8_t rule_bits(const MeshDev& m, const double2* __restrict__ xy,
+                                             int a, int b) {
+  return (uint8_t)((conditioning_ok(m, xy, a, b) ? 1 : 0) | (flat_candidate(m, a, b) ? 2 : 0));
+}
+
+// Contractibility of edge e = (a, b) (Sec. 2.2.2), with vertex mv at q, given its rule bits.
+__device__ bool contractible_rules(const MeshDev& m, const double2* __restrict__ xy, int e, int a,
+                                   int b, double eps, int mv, double2 q, uint8_t rule) {
+  return direct_ok(m, a, b) && (rule & 1) && one_hop_ok(m, xy, e, m.edge_opp[e], eps, mv, q) &&
+         (!(rule & 2) || flat_ok(m, xy, a, b, eps, mv, q));
+}
+
+// Contractibility of edge e = (a, b), with vertex mv at q, from the rule bits of the call's
+// edge_state (valid for any movable vertex's position: no move changes what they read).
+__device__ __forceinline__ bool contractible_at(const MeshDev& m, const double2* __restrict__ xy,
+                                                int e, int a, int b, double eps, int mv,
+                                                double2 q) {
+  return contractible_rules(m, xy, e, a, b, eps, mv, q, m.rule[e]);
 }
 
 __device__ double block_sum(double v, double* sh) {
@@ -360,7 +399,9 @@ edge_state(MeshDev m, Par p, double* __restrict__ part) {
   for (int e = blockIdx.x * kThreads + threadIdx.x; e < m.ne; e += gridDim.x * kThreads) {
     const int2 ab = m.edge_v[e];
     const double len = dist(xy[ab.x], xy[ab.y]);
-    const bool ok = contractible_at(m, xy, e, ab.x, ab.y, p.eps, -1, make_double2(0, 0));
+    const uint8_t rule = rule_bits(m, xy, ab.x, ab.y);
+    m.rule[e] = rule;
+    const bool ok = contractible_rules(m, xy, e, ab.x, ab.y, p.eps, -1, make_double2(0, 0), rule);
     m.len[e] = len;
     m.contr[e] = ok ? 1 : 0;
     m.c[e] = c_of_len(ok, len, p.eps);
@@ -812,15 +853,32 @@ anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
 // The group of centre c is every movable vertex within distance d of it (a range query on a
 // uniform grid of the current positions, as the paper does), with no limit on its size. A sweep
 // runs in rounds. In a round every pending group finds its members and claims, by the lowest
-// centre index (atomicMin): the vertices within three edges of its members, and the grid cells
-// of its query disc and of its members' positions before and after the move. A group that holds
-// all its claims moves; the others wait for the next round. Two groups that move in one round
-// are therefore more than six edges apart (a move writes positions and edge scratch within one
-// edge of its members and reads within four), and neither moves a vertex into or out of the
-// other's disc: they commute, and the sweep equals the sequential chain over the centres in the
-// order (round, index).
+// priority (atomicMin; a group's priority is its centre index scrambled by a bijection, so that
+// groups whose indices run along a chain in space do not move one per round): the vertices within
+// two edges of its members (along paths that avoid hubs, see is_hub), and the grid cells of its
+// query disc and of its members' positions before and after the move. A group moves when it
+// holds its cells and no vertex within three edges of its members carries a lower priority; the
+// others wait for the next round. The pending group of lowest priority always moves. Two groups
+// that move in one round have members more than five edges apart: otherwise a vertex on a
+// shortest path between them lies within two edges of one and three of the other, and another
+// within three of the first and two of the second, so each would see the other's priority as
+// lower. A move writes positions and edge scratch within one edge of its members and reads within
+// four, and neither group moves a vertex into or out of the other's disc: the two commute, and the
+// sweep equals the sequential chain over the centres in the order (round, index).
 
 constexpr double kQueryWiden = 1.0 + 0x1p-40;  // query extents, widened against rounding
+
+// A group's claim priority: its index through the 32-bit finaliser of MurmurHash3 (Appleby), a
+// bijection of the 32-bit integers that leaves no order between neighbouring indices.
+__device__ __forceinline__ uint32_t group_priority(int i) {
+  uint32_t x = (uint32_t)i;
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
 
 struct VGrid {
   double x0, y0, inv;      // cell of p: floor((p - p0) * inv), clamped to the grid
@@ -864,17 +922,51 @@ __device__ __forceinline__ void for_members(const MeshDev& m, const VGrid& g, in
   });
 }
 
-// f(x) for every vertex within three edges of v (with repeats).
+// A hub: an ORIGINAL vertex with more than kHubDegree neighbours, such as a box corner whose fan
+// reaches hundreds of vertices. Its position never changes, and what a move reads or writes at a
+// hub's edges (their lengths and contraction states, the terms of the edges beside them) lies at
+// the moved vertex's own place in the fan, within two fan steps, which the fan's ring edges also
+// join. Claims therefore neither hold hubs nor pass through them: otherwise every group near a
+// corner would claim the corner's whole fan, and those groups would move one per round.
+constexpr int kHubDegree = 32;
+
+__device__ __forceinline__ bool is_hub(const MeshDev& m, int x) {
+  return m.adj_off[x + 1] - m.adj_off[x] > kHubDegree && m.vk[x].x == CCSP_VERTEX_ORIGINAL;
+}
+
+// f(x) for every vertex within two edges of the movable vertex v along paths that avoid hubs
+// (with repeats).
+template <class F>
+__device__ __forceinline__ void for_hops2(const MeshDev& m, int v, F&& f) {
+  f(v);
+  for (int a = m.adj_off[v], ae = m.adj_off[v + 1]; a < ae; ++a) {
+    const int w = m.adj[a].x;
+    if (is_hub(m, w)) continue;
+    f(w);
+    for (int b = m.adj_off[w], be = m.adj_off[w + 1]; b < be; ++b) {
+      const int x = m.adj[b].x;
+      if (!is_hub(m, x)) f(x);
+    }
+  }
+}
+
+// f(x) for every vertex within three edges of the movable vertex v along paths that avoid hubs
+// (with repeats).
 template <class F>
 __device__ __forceinline__ void for_hops3(const MeshDev& m, int v, F&& f) {
   f(v);
   for (int a = m.adj_off[v], ae = m.adj_off[v + 1]; a < ae; ++a) {
     const int w = m.adj[a].x;
+    if (is_hub(m, w)) continue;
     f(w);
     for (int b = m.adj_off[w], be = m.adj_off[w + 1]; b < be; ++b) {
       const int x = m.adj[b].x;
+      if (is_hub(m, x)) continue;
       f(x);
-      for (int e = m.adj_off[x], ee = m.adj_off[x + 1]; e < ee; ++e) f(m.adj[e].x);
+      for (int e = m.adj_off[x], ee = m.adj_off[x + 1]; e < ee; ++e) {
+        const int y = m.adj[e].x;
+        if (!is_hub(m, y)) f(y);
+      }
     }
   }
 }
@@ -946,8 +1038,8 @@ __global__ void __launch_bounds__(kThreads)
 group_claim(MeshDev m, VGrid g, Par p, double lambda, const int32_t* __restrict__ gcen,
             const double2* __restrict__ draws, const uint8_t* __restrict__ done, int n,
             const int32_t* __restrict__ off, int32_t* __restrict__ mem,
-            double2* __restrict__ disp, int32_t* __restrict__ own_v,
-            int32_t* __restrict__ own_c) {
+            double2* __restrict__ disp, uint32_t* __restrict__ own_v,
+            uint32_t* __restrict__ own_c) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n || done[i]) return;
   const int c = gcen[i];
@@ -983,24 +1075,26 @@ group_claim(MeshDev m, VGrid g, Par p, double lambda, const int32_t* __restrict_
   const double2 xi = draws[2 * i];
   const double2 D = make_double2(k * xi.x, k * xi.y);
   disp[i] = D;
-  auto claim_c = [&](int cell) { atomicMin(&own_c[cell], i); };
+  const uint32_t pri = group_priority(i);
+  auto claim_c = [&](int cell) { atomicMin(&own_c[cell], pri); };
   for_cells(g, m.xyi[c], d * kQueryWiden, claim_c);
   for (int j = 0; j < nm; ++j) {
     const int v = M[j];
     const double2 o = m.xyi[v], dv = member_disp(m, v, D);
     claim_c(cell_of(g, o));
     claim_c(cell_of(g, make_double2(o.x + dv.x, o.y + dv.y)));
-    for_hops3(m, v, [&](int x) { atomicMin(&own_v[x], i); });
+    for_hops2(m, v, [&](int x) { atomicMin(&own_v[x], pri); });
   }
 }
 
-// Whether group i holds every claim it made (no position changes during this pass).
+// Whether group i may move: it holds the cells it claimed and no vertex within three edges of its
+// members carries a lower priority (no position changes during this pass).
 __global__ void __launch_bounds__(kThreads)
 group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
             const double2* __restrict__ draws, const uint8_t* __restrict__ done, int n,
             const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
             const int32_t* __restrict__ mem, const double2* __restrict__ disp,
-            const int32_t* __restrict__ own_v, const int32_t* __restrict__ own_c,
+            const uint32_t* __restrict__ own_v, const uint32_t* __restrict__ own_c,
             uint8_t* __restrict__ won) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
@@ -1011,7 +1105,8 @@ group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
   const int c = gcen[i];
   const double d = (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps;
   bool ok = true;
-  auto held_c = [&](int cell) { ok = ok && own_c[cell] == i; };
+  const uint32_t pri = group_priority(i);
+  auto held_c = [&](int cell) { ok = ok && own_c[cell] == pri; };
   for_cells(g, m.xyi[c], d * kQueryWiden, held_c);
   const int* M = mem + off[i];
   const double2 D = disp[i];
@@ -1020,7 +1115,7 @@ group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
     const double2 o = m.xyi[v], dv = member_disp(m, v, D);
     held_c(cell_of(g, o));
     held_c(cell_of(g, make_double2(o.x + dv.x, o.y + dv.y)));
-    for_hops3(m, v, [&](int x) { ok = ok && own_v[x] == i; });
+    for_hops3(m, v, [&](int x) { ok = ok && own_v[x] >= pri; });
   }
   won[i] = ok ? 1 : 0;
 }
@@ -1458,7 +1553,7 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
   void* p_edge_v; void* p_nbr; void* p_opp; void* p_etri; void* p_tri; void* p_tedge;
   void* p_adj_off; void* p_adj; void* p_vtri_off; void* p_vtri; void* p_vk; void* p_prim;
   void* p_vold; void* p_vnew; void* p_eperm; void* p_xyi; void* p_hop_off; void* p_hop_v;
-  void* p_c; void* p_len; void* p_contr; void* p_part;
+  void* p_c; void* p_len; void* p_contr; void* p_rule; void* p_part;
   const Part parts[] = {
       {ev.data(), 8 * (size_t)E, &p_edge_v}, {enbr.data(), 16 * (size_t)E, &p_nbr},
       {eopp.data(), 8 * (size_t)E, &p_opp}, {etri.data(), 8 * (size_t)E, &p_etri},
@@ -1470,7 +1565,8 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
       {eperm.data(), 4 * (size_t)E, &p_eperm}, {nullptr, 16 * (size_t)V, &p_xyi},
       {hop_off.data(), 4 * (size_t)(E + 1), &p_hop_off}, {hop_v.data(), 4 * hop_v.size(), &p_hop_v},
       {nullptr, 8 * (size_t)E, &p_c}, {nullptr, 8 * (size_t)E, &p_len},
-      {nullptr, (size_t)E, &p_contr}, {nullptr, 8 * 3 * (size_t)ccsp::kMaxBlocks, &p_part}};
+      {nullptr, (size_t)E, &p_contr}, {nullptr, (size_t)E, &p_rule},
+      {nullptr, 8 * 3 * (size_t)ccsp::kMaxBlocks, &p_part}};
   size_t total = 0;
   for (const Part& pt : parts) total += (pt.bytes + 255) & ~size_t(255);
   he = hipMalloc(&m->mem, total);
@@ -1513,6 +1609,7 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
   d.c = (double*)p_c;
   d.len = (double*)p_len;
   d.contr = (uint8_t*)p_contr;
+  d.rule = (uint8_t*)p_rule;
   d.partial = (double*)p_part;
   m->edge_v = std::move(edge_can);
   *out = m;
@@ -1713,7 +1810,8 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   if (!(g.gy >= 1)) g.gy = 1;
   const int ncells = g.gx * g.gy;
   int32_t *gcen = nullptr, *cnt = nullptr, *off = nullptr, *start = nullptr, *cursor = nullptr;
-  int32_t *vert = nullptr, *own_v = nullptr, *own_c = nullptr, *mem = nullptr;
+  int32_t *vert = nullptr, *mem = nullptr;
+  uint32_t *own_v = nullptr, *own_c = nullptr;
   uint8_t *done = nullptr, *won = nullptr;
   double2* disp = nullptr;
   e = gs.get(&gcen, N);
@@ -1771,9 +1869,10 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
         return fail(CCSP_E_OOM, "anneal_group: member buffer allocation failed");
     }
     // claims, their check, and the moves of the groups holding all of theirs
-    hipLaunchKernelGGL(ccsp::fill_i32, dim3(vb), dim3(T), 0, s, own_v, (int64_t)d.nv, 0x7fffffff);
-    hipLaunchKernelGGL(ccsp::fill_i32, dim3((ncells + T - 1) / T), dim3(T), 0, s, own_c,
-                       (int64_t)ncells, 0x7fffffff);
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3(vb), dim3(T), 0, s, reinterpret_cast<int32_t*>(own_v),
+                       (int64_t)d.nv, -1);
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3((ncells + T - 1) / T), dim3(T), 0, s,
+                       reinterpret_cast<int32_t*>(own_c), (int64_t)ncells, -1);
     hipLaunchKernelGGL(ccsp::group_claim, dim3(gb), dim3(T), 0, s, d, g, p, lambda, gcen,
                        (const double2*)draws, done, N, off, mem, disp, own_v, own_c);
     hipLaunchKernelGGL(ccsp::group_check, dim3(gb), dim3(T), 0, s, d, g, p, gcen,

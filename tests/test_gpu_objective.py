@@ -693,6 +693,60 @@ def test_large_and_far_reaching_groups(ccsp):
                               centres=cen[keep])
 
 
+def _hub_mesh(n_ring=40, rings=3):
+    """An ORIGINAL hub at the origin whose fan is a ring of n_ring free vertices, further free
+    rings (each offset by half a step) and an ORIGINAL frame: the hub's degree is n_ring, above the
+    library's hub threshold. Delaunay (scipy), counter-clockwise."""
+    spatial = pytest.importorskip("scipy.spatial")
+    pts = [[0.0, 0.0]]
+    for r in range(rings):
+        rad = 1.0 + 0.6 * r
+        pts += [[rad * math.cos(2 * math.pi * (k + 0.5 * r) / n_ring),
+                 rad * math.sin(2 * math.pi * (k + 0.5 * r) / n_ring)] for k in range(n_ring)]
+    frame = [[4.0 * math.cos(2 * math.pi * k / 12), 4.0 * math.sin(2 * math.pi * k / 12)]
+             for k in range(12)]
+    xy = np.array(pts + frame)
+    n = xy.shape[0]
+    tri = spatial.Delaunay(xy).simplices.astype(np.int32)
+    a, b, c = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    cw = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]) < 0
+    tri[cw] = tri[cw][:, [0, 2, 1]]
+    kind = np.full(n, ob.FREE, dtype=np.int32)
+    kind[0] = ob.ORIGINAL
+    fr = list(range(n - 12, n))
+    kind[fr] = ob.ORIGINAL
+    line = np.zeros(n, dtype=np.int32)
+    prim_v = np.array([[fr[k], fr[(k + 1) % 12]] for k in range(12)], dtype=np.int32)
+    return xy, tri, kind, line, prim_v
+
+
+@pytest.mark.parametrize("eps,rep", [(0.04, 0), (0.04, 1), (0.12, 2)])
+def test_group_moves_around_a_hub(ccsp, eps, rep):
+    """Groups around an ORIGINAL vertex of degree 40: claims do not pass through such a hub, so
+    groups on different sides of its fan move in the same round, and the sweep still equals the
+    checker's sequential chain (positions bit for bit)."""
+    xy, tri, kind, line, prim_v = _hub_mesh()
+    assert int((tri == 0).any(axis=1).sum()) == 40  # the hub's fan
+    om = ob.Mesh(tri, kind, line, prim_v)
+    p = ob.Params(eps)
+    rng = np.random.default_rng(31 + rep)
+    with ccsp.MovableMesh(tri, kind, line, prim_v) as gm:
+        M = gm.movable.shape[0]
+        draws = np.zeros((M, 4))
+        draws[:, :2] = 0.3 * eps * rng.standard_normal((M, 2))
+        draws[:, 2] = rng.random(M)
+        u = rng.random(M)
+        st_r, size, rnd = _group_sweep_vs_chain(ccsp, gm, om, xy, p, 1e-3, 0.05, draws, u)
+        assert (st_r == ob.ACCEPTED).sum() > 10
+        # the hub's 40 fan vertices alone as centres: claims through the hub would make every two
+        # of them conflict (40 rounds); without, each conflicts with about a dozen fan neighbours
+        fan = np.arange(1, 41, dtype=np.int32)
+        k = np.searchsorted(gm.movable, fan)
+        _, _, rnd_f = _group_sweep_vs_chain(ccsp, gm, om, xy, p, 1e-3, 0.05, draws[k], u[k],
+                                            centres=fan)
+        assert rnd_f.max() + 1 < 35, rnd_f.max()
+
+
 @pytest.mark.parametrize("seed,eps", [(0, 0.3), (1, 1.0), (2, 2.0), (3, 0.3)])
 def test_conditioning_and_flat_rules_on_gpu(ccsp, seed, eps):
     """Sec. 2.2.2's conditioning and flat-triangle restrictions: on meshes where both fire (the
