@@ -1672,8 +1672,11 @@ int objective_delta(MovableMesh* mesh, const double* xy, const ObjectiveParams* 
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_delta: launch");
 }
 
-// Greedy colouring of the movable vertices over balls of `radius` edges: members of a class are
-// more than `radius` edges apart.
+// Greedy colouring of the movable vertices over balls of `radius` edges along paths that do not
+// pass through hubs (see is_hub: what a move reads or writes at a hub lies at the moved vertex's
+// own place in its fan, which the fan's ring edges join): members of a class are more than
+// `radius` edges apart along such paths. A box corner's fan would otherwise put all of its
+// hundreds of vertices in different classes.
 int build_classes(MovableMesh* mesh, int radius, std::vector<int64_t>& class_off,
                   std::vector<int32_t>& class_v, int32_t*& class_dev) {
   if (class_off.empty()) {
@@ -1696,14 +1699,18 @@ int build_classes(MovableMesh* mesh, int radius, std::vector<int64_t>& class_off
       size_t lo = 0;
       for (int r = 0; r < radius; ++r) {
         const size_t hi = ball.size();
-        for (size_t j = lo; j < hi; ++j)
-          for (int32_t k = adj_off[ball[j]]; k < adj_off[ball[j] + 1]; ++k) {
+        for (size_t j = lo; j < hi; ++j) {
+          const int32_t u = ball[j];
+          if (vk[2 * u] == CCSP_VERTEX_ORIGINAL && adj_off[u + 1] - adj_off[u] > ccsp::kHubDegree)
+            continue;  // a hub: in the ball, not passed through
+          for (int32_t k = adj_off[u]; k < adj_off[u + 1]; ++k) {
             const int32_t w = adj[2 * k];
             if (stamp[w] != (int32_t)v) {
               stamp[w] = (int32_t)v;
               ball.push_back(w);
             }
           }
+        }
         lo = hi;
       }
       used.assign(n + 1, 0);

@@ -209,11 +209,22 @@ def test_grid_eval_and_sampled_deltas(ccsp, grid):
         assert st[i] == ob.move_status(om, mesh.xy, int(v[i]), q[i])
 
 
+HUB_DEGREE = 32  # the library's hubs: ORIGINAL vertices of more neighbours than this
+
+
+def _is_hub(om, a):
+    return om.kind[a] == ob.ORIGINAL and om.nbr_off[a + 1] - om.nbr_off[a] > HUB_DEGREE
+
+
 def _ball(om, v, r):
+    """Vertices within r edges of v along paths that do not pass through hubs (a hub is in the
+    ball, but not gone through): the separation the library's classes and group claims keep."""
     seen, front = {v}, [v]
     for _ in range(r):
         nxt = []
         for a in front:
+            if _is_hub(om, a):
+                continue
             for w in om.nbr[om.nbr_off[a]:om.nbr_off[a + 1]].tolist():
                 if w not in seen:
                     seen.add(w)
@@ -745,6 +756,26 @@ def test_group_moves_around_a_hub(ccsp, eps, rep):
         _, _, rnd_f = _group_sweep_vs_chain(ccsp, gm, om, xy, p, 1e-3, 0.05, draws[k], u[k],
                                             centres=fan)
         assert rnd_f.max() + 1 < 35, rnd_f.max()
+        # single-vertex sweeps: classes separate the fan vertices along the ring, not through the
+        # hub (through it every two of the 40 would conflict), and a sweep equals the chain
+        cls = gm.classes()
+        assert len(cls) < 35, len(cls)
+        order = np.concatenate(cls)
+        for c in cls:
+            s_c = set(c.tolist())
+            for v in c.tolist():
+                assert not (_ball(om, v, 4) & s_c) - {v}
+        disp = 0.3 * eps * rng.standard_normal((order.shape[0], 2))
+        uu = rng.random(order.shape[0])
+        X = torch.from_numpy(xy.copy()).to(DEV)
+        d_s, st_s = gm.sweep(X, _params(ccsp, p), 1e-3, torch.from_numpy(disp).to(DEV),
+                             torch.from_numpy(uu).to(DEV))
+        xy_s, st_s = X.cpu().numpy(), st_s.cpu().numpy()
+    xy_ref, st_ref, _, margin = ob.metropolis_chain(om, xy, p, 1e-3, order, disp, uu)
+    valid = (st_ref == ob.ACCEPTED) | (st_ref == ob.REJECTED)
+    assert (margin[valid] > 1e-10).all(), "a decision lies within rounding of its threshold"
+    assert np.array_equal(st_s, st_ref) and np.array_equal(xy_s, xy_ref)
+    assert (st_ref == ob.ACCEPTED).sum() > 10
 
 
 @pytest.mark.parametrize("seed,eps", [(0, 0.3), (1, 1.0), (2, 2.0), (3, 0.3)])

@@ -111,7 +111,9 @@ def test_server_serve_workload_vs_checker(ccsp):
                 done += srv.poll(timeout_s=0.5)
                 assert time.monotonic() < deadline, "server did not finish"
             st = srv.stats()
-        assert all(status == 0 for _, status, *_ in done)
+        bad = [(ids[i], status) for i, status, *_ in done if status != 0]
+        assert not bad, (f"{len(bad)} requests failed: (request, status) {bad[:10]}; "
+                         f"sizes {[int(req_n[k]) for k, _ in bad[:10]]}; stats {st}")
         assert sorted(ids[i] for i, *_ in done) == list(range(N))
         assert st["max_items_per_launch"] > 1 and st["max_slots_busy"] >= 2
         # the checker walks each scene's sampled rays of all its requests in one call
