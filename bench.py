@@ -608,10 +608,12 @@ def pipeline_leg(sc, rays, stages=24, verbose=False, schedule=None):
 
 # Compulsory bytes of one objective evaluation (every array read once, scratch written and read
 # back once): per vertex 16 (caller's position) + 4 (its internal slot) + 16 + 16 (position in
-# internal order, written and read) + 8 (kind, line); per edge 8 (ends) + 8 (opposite vertices)
-# + 16 (neighbouring edges) + 4 (its 1-hop list offset) + 17 (length, c and contractibility
-# written) + 17 (read back); per triangle 16 (vertices).
-OBJ_BYTES_PER_VERTEX, OBJ_BYTES_PER_EDGE, OBJ_BYTES_PER_TRIANGLE = 60, 70, 16
+# internal order, written and read) + 8 (kind, line); per ORIGINAL vertex 16 (the position staged
+# by the previous call, compared to find out whether the rule bits still hold); per edge 8 (ends)
+# + 8 (opposite vertices) + 16 (neighbouring edges) + 4 (its 1-hop list offset) + 1 (rule bits)
+# + 17 (length, c and contractibility written) + 17 (read back); per triangle 16 (vertices).
+OBJ_BYTES_PER_VERTEX, OBJ_BYTES_PER_ORIGINAL, OBJ_BYTES_PER_EDGE, OBJ_BYTES_PER_TRIANGLE = (
+    60, 16, 71, 16)
 
 
 def objective_leg(scene_name, steps, warmup, moves=1 << 20):
@@ -779,8 +781,9 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
     end = gm.eval(XS, p_end).cpu().tolist()
     start_at_end_eps = gm.eval(xy, p_end).cpu().tolist()
     del xi, us
-    comp = (OBJ_BYTES_PER_VERTEX * mesh.n_vertices + OBJ_BYTES_PER_EDGE * gm.n_edges
-            + OBJ_BYTES_PER_TRIANGLE * mesh.n_triangles)
+    comp = (OBJ_BYTES_PER_VERTEX * mesh.n_vertices
+            + OBJ_BYTES_PER_ORIGINAL * int((mesh.kind == sg.ORIGINAL).sum())
+            + OBJ_BYTES_PER_EDGE * gm.n_edges + OBJ_BYTES_PER_TRIANGLE * mesh.n_triangles)
     achieved = comp / (ms_eval * 1e-3) / 1e9
     res = {
         "workload": f"{mesh.name}: {scene_name} CDT subdivided once, {mesh.n_vertices} vertices, "

@@ -28,8 +28,22 @@
  *   - both ends are ORIGINAL; or one end is ORIGINAL and the other CONSTRAINED to an original edge
  *     that does not end at it; or both are CONSTRAINED to different original edges; or
  *   - the 1-hop rule: a common neighbour H of its ends that is not one of its opposite vertices
- *     lies at distance >= eps from every opposite vertex (distances computed as |e| above).
- * The conditioning and flat-triangle restrictions of Sec. 2.2.2 are not applied.
+ *     lies at distance >= eps from every opposite vertex (distances computed as |e| above); or
+ *   - conditioning: its ends have different degrees of freedom (ORIGINAL 0, CONSTRAINED 1, FREE 2)
+ *     and some triangle of the end with more of them, h, that does not hold the other end l, with
+ *     l in h's place, is badly conditioned for good. That is decided from positions no move
+ *     changes: a triangle with a FREE vertex, or whose vertices all lie on one original edge,
+ *     never is; three ORIGINAL vertices are when near-collinear; two ORIGINAL o1, o2 and a
+ *     CONSTRAINED vertex on original edge (a, b) when (o1, o2, a), (o1, o2, b) and (o1, o2, mid)
+ *     all are, mid = ((a.x + b.x) * 0.5, (a.y + b.y) * 0.5); otherwise when the ends of every
+ *     CONSTRAINED vertex's original edge, and each ORIGINAL vertex, are near-collinear with the
+ *     ends (a, b) of the first CONSTRAINED vertex's original edge (in triangle order). (p, q, r)
+ *     is near-collinear when 16 * A / (P * P) < 0.01, A = 0.5 * |(q.x-p.x)*(r.y-p.y) -
+ *     (q.y-p.y)*(r.x-p.x)|, P = (|pq| + |qr|) + |rp|, or P = 0; or
+ *   - flat triangle: it joins a FREE F and a non-FREE C, and some triangle (F, X, Y) without C
+ *     has X, Y and C on one original edge L, one of X, Y CONSTRAINED; then every CONSTRAINED one T
+ *     of X, Y must reach C or an ORIGINAL end of L along L, through C and F's neighbours on L,
+ *     by edges shorter than eps, else the edge is not contractible.
  * Edges are numbered by (lower vertex id, higher vertex id); mesh_info returns them.
  *
  * Errors are the CCSP_* codes of ccsp_walk.h, with last_error() describing the failure.
@@ -122,7 +136,11 @@ int objective_eval(MovableMesh *mesh, const double *xy, const ObjectiveParams *p
  * alternatives, not applied): delta[i] = f(xy with the vertex moved) - f(xy) (DEVICE binary64),
  * the sum of the differences of every term of f that the move changes, and status[i] (DEVICE
  * int32, CCSP_MOVE_*). A constrained vertex's new position is taken as given (the caller projects
- * it on its original edge). Asynchronous on `stream`; overwrites the mesh's scratch.
+ * it on its original edge). Asynchronous on `stream`; overwrites the mesh's scratch. Batches of
+ * 4096 moves or more are evaluated in the order of their vertices (a radix sort of the move
+ * indices, results still in input order), in a device buffer the mesh keeps: 16 bytes per move
+ * plus the sort's temporaries, grown (after synchronising `stream`) when k exceeds every earlier
+ * batch's.
  */
 int objective_delta(MovableMesh *mesh, const double *xy, const ObjectiveParams *params,
                     const int32_t *vid, const double *q_xy, int64_t k, double *delta,

@@ -65,11 +65,13 @@ struct MeshDev {
   double* c;              // scratch: contraction weight, length, contractibility per edge
   double* len;
   uint8_t* contr;
-  // scratch per edge, set by edge_state for the call's positions: bit 0, the conditioning
-  // restriction holds (it reads only ORIGINAL positions and the original edges of CONSTRAINED
-  // vertices, which no move changes); bit 1, the flat-triangle restriction may apply (a
-  // topological test, see flat_candidate)
+  // per edge: bit 0, the conditioning restriction holds (it reads only ORIGINAL positions and
+  // the original edges of CONSTRAINED vertices, which no move changes); bit 1, the flat-triangle
+  // restriction may apply (a topological test, see flat_candidate). Kept across calls: edge_state
+  // recomputes them when *stale is set, which mesh_load does and permute_positions does when an
+  // ORIGINAL position differs, bit for bit, from the previous call's
   uint8_t* rule;
+  int32_t* stale;
   double* partial;
 };
 
@@ -382,11 +384,26 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// Caller positions into the mesh's internal vertex order.
+// Caller positions into the mesh's internal vertex order; an ORIGINAL position that differs from
+// the one staged by the previous call marks the rule bits stale.
 __global__ void __launch_bounds__(kThreads)
 permute_positions(MeshDev m, const double2* __restrict__ xy) {
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < m.nv; i += gridDim.x * kThreads)
-    m.xyi[i] = xy[m.vold[i]];
+  bool moved = false;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < m.nv; i += gridDim.x * kThreads) {
+    const double2 q = xy[m.vold[i]];
+    if (m.vk[i].x == CCSP_VERTEX_ORIGINAL) {
+      const double2 o = m.xyi[i];
+      moved = moved || __double_as_longlong(o.x) != __double_as_longlong(q.x) ||
+              __double_as_longlong(o.y) != __double_as_longlong(q.y);
+    }
+    m.xyi[i] = q;
+  }
+  if (moved) *m.stale = 1;
+}
+
+// After edge_state: the rule bits match the staged ORIGINAL positions.
+__global__ void rules_fresh(MeshDev m) {
+  if (threadIdx.x == 0) *m.stale = 0;
 }
 
 // Pass 1: length, contractibility and c of every edge; length-penalty partial sums. Each thread
@@ -395,12 +412,18 @@ __global__ void __launch_bounds__(kThreads)
 edge_state(MeshDev m, Par p, double* __restrict__ part) {
   __shared__ double sh[kThreads];
   const double2* __restrict__ xy = m.xyi;
+  const bool stale = *m.stale != 0;
   double s = 0.0;
   for (int e = blockIdx.x * kThreads + threadIdx.x; e < m.ne; e += gridDim.x * kThreads) {
     const int2 ab = m.edge_v[e];
     const double len = dist(xy[ab.x], xy[ab.y]);
-    const uint8_t rule = rule_bits(m, xy, ab.x, ab.y);
-    m.rule[e] = rule;
+    uint8_t rule;
+    if (stale) {
+      rule = rule_bits(m, xy, ab.x, ab.y);
+      m.rule[e] = rule;
+    } else {
+      rule = m.rule[e];
+    }
     const bool ok = contractible_rules(m, xy, e, ab.x, ab.y, p.eps, -1, make_double2(0, 0), rule);
     m.len[e] = len;
     m.contr[e] = ok ? 1 : 0;
@@ -469,6 +492,17 @@ finish_sums(const double* __restrict__ part, int n1, int n2, Par p, double* __re
 // ---- moves ----
 
 constexpr int kLdsNbrs = 16;  // neighbours of a moved vertex kept in LDS (Steiner vertices have ~6)
+constexpr int kCache = 8;     // entries of a move's cache of changed contraction weights
+
+// A thread's LDS columns for evaluating a move (stride kThreads): the moved vertex's neighbours,
+// and a direct-mapped cache, by edge id, of the contraction weight c an edge takes after the move
+// (each is read by up to four terms; computing it once per move keeps the neighbourhood gathers
+// of its contractibility from repeating).
+struct MoveLds {
+  int* nb;
+  int* ce;
+  double* cc;
+};
 
 struct MoveCtx {
   MeshDev m;
@@ -478,6 +512,8 @@ struct MoveCtx {
   double2 q;
   const int* nb;  // this thread's neighbours of v in LDS, stride kThreads, when deg <= kLdsNbrs
   int deg;
+  int* ce;        // the move's cache of changed c: edge ids (-1 empty) and values
+  double* cc;
 
   __device__ __forceinline__ bool adjacent(int x) const {
     if (deg > kLdsNbrs) return is_neighbour(m, v, x);
@@ -504,8 +540,14 @@ struct MoveCtx {
   }
   __device__ __forceinline__ double c(int e, bool moved) const {
     if (!moved || !in_c(e)) return m.c[e];
+    const int slot = (e & (kCache - 1)) * kThreads;
+    if (ce[slot] == e) return cc[slot];
     const int2 ab = m.edge_v[e];
-    return c_of_len(contractible_at(m, xy, e, ab.x, ab.y, p.eps, v, q), len(e, true), p.eps);
+    const double r =
+        c_of_len(contractible_at(m, xy, e, ab.x, ab.y, p.eps, v, q), len(e, true), p.eps);
+    ce[slot] = e;
+    cc[slot] = r;
+    return r;
   }
   __device__ __forceinline__ double term(int e, bool moved) const {
     double w = 1.0;
@@ -552,11 +594,12 @@ struct MoveCtx {
 
 // Change of f (through *df) of moving internal vertex v to q, against positions xy (internal
 // order) and the per-edge scratch of edge_state; with CHECK, CCSP_MOVE_FOLDS (and *df untouched)
-// when a triangle of v would not stay strictly counter-clockwise. nb is this thread's LDS column
-// for the vertex's neighbours.
+// when a triangle of v would not stay strictly counter-clockwise. lds holds this thread's LDS
+// columns.
 template <bool CHECK>
 __device__ __forceinline__ int move_change(const MeshDev& m, const double2* __restrict__ xy,
-                                           const Par& p, int v, double2 q, int* nb, double* df) {
+                                           const Par& p, int v, double2 q, MoveLds lds,
+                                           double* df) {
   double sa = 0.0;
   for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j) {
     const int4 t = m.tri[m.vtri[j]];
@@ -568,8 +611,10 @@ __device__ __forceinline__ int move_change(const MeshDev& m, const double2* __re
   }
   const int a0 = m.adj_off[v], deg = m.adj_off[v + 1] - a0;
   if (deg <= kLdsNbrs)
-    for (int j = 0; j < deg; ++j) nb[j * kThreads] = m.adj[a0 + j].x;
-  const MoveCtx ctx{m, xy, p, v, q, nb, deg};
+    for (int j = 0; j < deg; ++j) lds.nb[j * kThreads] = m.adj[a0 + j].x;
+#pragma unroll
+  for (int k = 0; k < kCache; ++k) lds.ce[k * kThreads] = -1;
+  const MoveCtx ctx{m, xy, p, v, q, lds.nb, deg, lds.ce, lds.cc};
   double se = 0.0, ss = 0.0;
   for (int j = a0, end = a0 + deg; j < end; ++j) {
     const int e = m.adj[j].y;
@@ -598,25 +643,45 @@ __device__ __forceinline__ int move_change(const MeshDev& m, const double2* __re
 }
 
 // Status and change of f (through *df, +inf unless valid) of moving the vertex of caller id cv
-// to q, against positions xy (internal order) and the per-edge scratch of edge_state. nb is this
-// thread's LDS column for the vertex's neighbours.
+// to q, against positions xy (internal order) and the per-edge scratch of edge_state. lds holds
+// this thread's LDS columns.
 __device__ __forceinline__ int evaluate_move(const MeshDev& m, const double2* __restrict__ xy,
-                                             const Par& p, int cv, double2 q, int* nb, double* df) {
+                                             const Par& p, int cv, double2 q, MoveLds lds,
+                                             double* df) {
   *df = __builtin_huge_val();
   if (cv < 0 || cv >= m.nv || !isfinite(q.x) || !isfinite(q.y)) return CCSP_MOVE_BAD;
   const int v = m.vnew[cv];
   if (m.vk[v].x == CCSP_VERTEX_ORIGINAL) return CCSP_MOVE_FIXED;
-  return move_change<true>(m, xy, p, v, q, nb, df);
+  return move_change<true>(m, xy, p, v, q, lds, df);
 }
 
+// Sort keys of a batch of moves: the moved vertex's internal id (nv for an id out of range), so
+// that evaluating the moves in key order lets neighbouring threads share the cache lines of
+// their neighbourhoods (internal ids follow a breadth-first order of the mesh).
 __global__ void __launch_bounds__(kThreads)
-move_delta(MeshDev m, Par p, const int32_t* __restrict__ vid, const double2* __restrict__ qv,
-           int64_t k, double* __restrict__ delta, int32_t* __restrict__ status) {
-  __shared__ int snb[kLdsNbrs * kThreads];
+move_keys(MeshDev m, const int32_t* __restrict__ vid, int64_t k, uint32_t* __restrict__ key,
+          uint32_t* __restrict__ idx) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= k) return;
+  const int cv = vid[i];
+  key[i] = (cv >= 0 && cv < m.nv) ? (uint32_t)m.vnew[cv] : (uint32_t)m.nv;
+  idx[i] = (uint32_t)i;
+}
+
+// objective_delta's moves; order (NULL: the identity) lists the move each thread evaluates.
+__global__ void __launch_bounds__(kThreads)
+move_delta(MeshDev m, Par p, const int32_t* __restrict__ vid, const double2* __restrict__ qv,
+           int64_t k, const uint32_t* __restrict__ order, double* __restrict__ delta,
+           int32_t* __restrict__ status) {
+  __shared__ int snb[kLdsNbrs * kThreads];
+  __shared__ int sce[kCache * kThreads];
+  __shared__ double scc[kCache * kThreads];
+  const MoveLds lds{snb + threadIdx.x, sce + threadIdx.x, scc + threadIdx.x};
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= k) return;
+  const int64_t i = order ? (int64_t)order[t] : t;
   double df;
-  status[i] = evaluate_move(m, m.xyi, p, vid[i], qv[i], snb + threadIdx.x, &df);
+  status[i] = evaluate_move(m, m.xyi, p, vid[i], qv[i], lds, &df);
   delta[i] = df;
 }
 
@@ -630,6 +695,9 @@ anneal_moves(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out,
              const double* __restrict__ u, int64_t k, double* __restrict__ delta,
              int32_t* __restrict__ status) {
   __shared__ int snb[kLdsNbrs * kThreads];
+  __shared__ int sce[kCache * kThreads];
+  __shared__ double scc[kCache * kThreads];
+  const MoveLds lds{snb + threadIdx.x, sce + threadIdx.x, scc + threadIdx.x};
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= k) return;
   const int cv = vid[i];
@@ -649,7 +717,7 @@ anneal_moves(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out,
     q = make_double2(o.x + d.x, o.y + d.y);
   }
   double df;
-  int st = evaluate_move(m, m.xyi, p, cv, q, snb + threadIdx.x, &df);
+  int st = evaluate_move(m, m.xyi, p, cv, q, lds, &df);
   if (st == CCSP_MOVE_OK) {
     if (df <= 0.0 || u[i] < exp(-df / temperature))
       xy_out[cv] = q;
@@ -773,6 +841,9 @@ anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
              double* __restrict__ delta, int32_t* __restrict__ status,
              unsigned long long* __restrict__ accepted) {
   __shared__ int snb[kLdsNbrs * kThreads];
+  __shared__ int sce[kCache * kThreads];
+  __shared__ double scc[kCache * kThreads];
+  const MoveLds lds{snb + threadIdx.x, sce + threadIdx.x, scc + threadIdx.x};
   const int i = blockIdx.x * kThreads + threadIdx.x;
   bool took = false;
   if (i < n) {
@@ -827,7 +898,7 @@ anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
     double df = __builtin_huge_val();
     int st = CCSP_MOVE_SKIPPED;
     if (!skip) {
-      st = evaluate_move(m, m.xyi, p, cv, q, snb + threadIdx.x, &df);
+      st = evaluate_move(m, m.xyi, p, cv, q, lds, &df);
       if (st == CCSP_MOVE_OK) {
         if (df <= 0.0 || u[i] < exp(-df / temperature)) {
           m.xyi[v] = q;
@@ -1134,6 +1205,9 @@ group_apply(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out, 
             int32_t* __restrict__ status, int32_t* __restrict__ members,
             int32_t* __restrict__ round, unsigned long long* __restrict__ applied) {
   __shared__ int snb[kLdsNbrs * kThreads];
+  __shared__ int sce[kCache * kThreads];
+  __shared__ double scc[kCache * kThreads];
+  const MoveLds lds{snb + threadIdx.x, sce + threadIdx.x, scc + threadIdx.x};
   const int i = blockIdx.x * kThreads + threadIdx.x;
   bool moved = false;
   if (i < n && won[i]) {
@@ -1147,7 +1221,7 @@ group_apply(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out, 
       const double2 o = m.xyi[v], dv = member_disp(m, v, D);
       const double2 q = make_double2(o.x + dv.x, o.y + dv.y);
       double dfj = 0.0;
-      move_change<false>(m, m.xyi, p, v, q, snb + threadIdx.x, &dfj);
+      move_change<false>(m, m.xyi, p, v, q, lds, &dfj);
       df += dfj;
       m.xyi[v] = q;
       refresh_scratch(m, p, v);
@@ -1239,6 +1313,8 @@ struct MovableMesh {
   std::vector<int32_t> class_v;    // caller ids, class by class
   int32_t* class_dev = nullptr;    // the same vertices, internal ids, on the device
   void* sched = nullptr;           // anneal_schedule: delta and status per movable vertex, counter
+  void* order_ws = nullptr;        // objective_delta: sort keys, move indices, sort temporaries
+  size_t order_bytes = 0;
 };
 
 namespace {
@@ -1270,6 +1346,16 @@ int grid_for(int64_t n) {
                                                      (n + ccsp::kThreads - 1) / ccsp::kThreads));
 }
 
+// Every call's first step: the caller's positions into internal order, then every edge's length,
+// contractibility and c (edge_state, length-penalty partial sums in d.partial[0..grid_for(ne))).
+void stage_edges(const ccsp::MeshDev& d, const ccsp::Par& p, const void* xy, hipStream_t s) {
+  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
+                     (const double2*)xy);
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
+                     d.partial);
+  hipLaunchKernelGGL(ccsp::rules_fresh, dim3(1), dim3(64), 0, s, d);
+}
+
 ccsp::Par to_par(const ObjectiveParams* p) {
   return ccsp::Par{p->eps, p->delta, p->eps0, p->mu_angle, p->mu_len, p->polish != 0};
 }
@@ -1279,6 +1365,53 @@ int check_device(const MovableMesh* m) {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != m->device) return fail(CCSP_E_ARG, "the mesh was loaded on another device");
+  return CCSP_OK;
+}
+
+// Batches of at least this many moves are evaluated in the order of their vertices' internal ids
+// (a breadth-first order of the mesh, so that close ids are close vertices), so that threads of a
+// wave share the cache lines of their neighbourhoods; a random batch of 2^20 moves on 8 million vertices otherwise fetches each
+// move's neighbourhood from memory on its own.
+constexpr int64_t kSortMoves = 4096;
+
+// Radix-sorts the move indices 0..k-1 by internal vertex id into the mesh's order workspace
+// (grown, after synchronising `s`, when k exceeds every earlier batch); *order receives them.
+int sort_moves(MovableMesh* mesh, const int32_t* vid, int64_t k, hipStream_t s,
+               const uint32_t** order) {
+  const ccsp::MeshDev& d = mesh->d;
+  int end_bit = 1;
+  while (end_bit < 32 && (int64_t(1) << end_bit) <= (int64_t)d.nv) ++end_bit;
+  size_t tmp = 0;
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint32_t*)nullptr,
+                                                    (uint32_t*)nullptr, (const uint32_t*)nullptr,
+                                                    (uint32_t*)nullptr, (int)k, 0, end_bit, s);
+  if (e != hipSuccess) return hip_fail(e, "objective_delta: sort size");
+  const size_t col = (4 * (size_t)k + 255) & ~size_t(255);
+  const size_t need = 4 * col + tmp;
+  if (need > mesh->order_bytes) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "objective_delta: synchronise");
+    if (mesh->order_ws) (void)hipFree(mesh->order_ws);
+    mesh->order_ws = nullptr;
+    mesh->order_bytes = 0;
+    if (hipMalloc(&mesh->order_ws, need) != hipSuccess) {
+      (void)hipGetLastError();
+      mesh->order_ws = nullptr;
+      return fail(CCSP_E_OOM, "objective_delta: device allocation failed");
+    }
+    mesh->order_bytes = need;
+  }
+  char* w = (char*)mesh->order_ws;
+  auto* key = (uint32_t*)w;
+  auto* key2 = (uint32_t*)(w + col);
+  auto* idx = (uint32_t*)(w + 2 * col);
+  auto* idx2 = (uint32_t*)(w + 3 * col);
+  hipLaunchKernelGGL(ccsp::move_keys, dim3((unsigned)((k + ccsp::kThreads - 1) / ccsp::kThreads)),
+                     dim3(ccsp::kThreads), 0, s, d, vid, k, key, idx);
+  e = hipcub::DeviceRadixSort::SortPairs(w + 4 * col, tmp, key, key2, idx, idx2, (int)k, 0,
+                                         end_bit, s);
+  if (e != hipSuccess) return hip_fail(e, "objective_delta: sort");
+  *order = idx2;
   return CCSP_OK;
 }
 
@@ -1553,7 +1686,8 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
   void* p_edge_v; void* p_nbr; void* p_opp; void* p_etri; void* p_tri; void* p_tedge;
   void* p_adj_off; void* p_adj; void* p_vtri_off; void* p_vtri; void* p_vk; void* p_prim;
   void* p_vold; void* p_vnew; void* p_eperm; void* p_xyi; void* p_hop_off; void* p_hop_v;
-  void* p_c; void* p_len; void* p_contr; void* p_rule; void* p_part;
+  void* p_c; void* p_len; void* p_contr; void* p_rule; void* p_stale; void* p_part;
+  const int32_t stale_at_load = 1;
   const Part parts[] = {
       {ev.data(), 8 * (size_t)E, &p_edge_v}, {enbr.data(), 16 * (size_t)E, &p_nbr},
       {eopp.data(), 8 * (size_t)E, &p_opp}, {etri.data(), 8 * (size_t)E, &p_etri},
@@ -1566,6 +1700,7 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
       {hop_off.data(), 4 * (size_t)(E + 1), &p_hop_off}, {hop_v.data(), 4 * hop_v.size(), &p_hop_v},
       {nullptr, 8 * (size_t)E, &p_c}, {nullptr, 8 * (size_t)E, &p_len},
       {nullptr, (size_t)E, &p_contr}, {nullptr, (size_t)E, &p_rule},
+      {&stale_at_load, sizeof(int32_t), &p_stale},
       {nullptr, 8 * 3 * (size_t)ccsp::kMaxBlocks, &p_part}};
   size_t total = 0;
   for (const Part& pt : parts) total += (pt.bytes + 255) & ~size_t(255);
@@ -1610,6 +1745,7 @@ int mesh_load(const MeshDesc* desc, MovableMesh** out) {
   d.len = (double*)p_len;
   d.contr = (uint8_t*)p_contr;
   d.rule = (uint8_t*)p_rule;
+  d.stale = (int32_t*)p_stale;
   d.partial = (double*)p_part;
   m->edge_v = std::move(edge_can);
   *out = m;
@@ -1634,9 +1770,7 @@ int objective_eval(MovableMesh* mesh, const double* xy, const ObjectiveParams* p
   const ccsp::Par p = to_par(params);
   hipStream_t s = (hipStream_t)stream;
   const int n1 = grid_for(d.ne), n2 = grid_for(std::max(d.ne, d.nt));
-  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
-                     (const double2*)xy);
-  hipLaunchKernelGGL(ccsp::edge_state, dim3(n1), dim3(ccsp::kThreads), 0, s, d, p, d.partial);
+  stage_edges(d, p, xy, s);
   hipLaunchKernelGGL(ccsp::terms_pass, dim3(n2), dim3(ccsp::kThreads), 0, s, d, p,
                      d.partial + n1, d.partial + n1 + n2, contractible, weight);
   hipLaunchKernelGGL(ccsp::finish_sums, dim3(1), dim3(ccsp::kThreads), 0, s, d.partial, n1, n2, p,
@@ -1661,13 +1795,14 @@ int objective_delta(MovableMesh* mesh, const double* xy, const ObjectiveParams* 
   const ccsp::MeshDev& d = mesh->d;
   const ccsp::Par p = to_par(params);
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
-                     (const double2*)xy);
-  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
-                     d.partial);
+  stage_edges(d, p, xy, s);
   const int64_t blocks = (k + ccsp::kThreads - 1) / ccsp::kThreads;
+  const uint32_t* order = nullptr;
+  if (k >= kSortMoves && k < (int64_t(1) << 31)) {
+    if (int r = sort_moves(mesh, vid, k, s, &order)) return r;
+  }
   hipLaunchKernelGGL(ccsp::move_delta, dim3((unsigned)blocks), dim3(ccsp::kThreads), 0, s, d, p,
-                     vid, (const double2*)q_xy, k, delta, status);
+                     vid, (const double2*)q_xy, k, order, delta, status);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_delta: launch");
 }
@@ -1789,9 +1924,7 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   const int N = (int)n;
   const int T = ccsp::kThreads;
   const unsigned gb = (unsigned)((N + T - 1) / T), vb = (unsigned)((d.nv + T - 1) / T);
-  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(T), 0, s, d,
-                     (const double2*)xy);
-  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(T), 0, s, d, p, d.partial);
+  stage_edges(d, p, xy, s);
   GroupScratch gs;
   double* box = nullptr;
   unsigned long long* applied = nullptr;
@@ -1917,10 +2050,7 @@ int anneal_moves(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   const ccsp::MeshDev& d = mesh->d;
   const ccsp::Par p = to_par(params);
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
-                     (const double2*)xy);
-  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
-                     d.partial);
+  stage_edges(d, p, xy, s);
   const int64_t blocks = (k + ccsp::kThreads - 1) / ccsp::kThreads;
   hipLaunchKernelGGL(ccsp::anneal_moves, dim3((unsigned)blocks), dim3(ccsp::kThreads), 0, s, d, p,
                      temperature, (double2*)xy, vid, (const double2*)disp, u, k, delta, status);
@@ -1944,10 +2074,7 @@ int anneal_sweep(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   const ccsp::MeshDev& d = mesh->d;
   const ccsp::Par p = to_par(params);
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
-                     (const double2*)xy);
-  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
-                     d.partial);
+  stage_edges(d, p, xy, s);
   const std::vector<int64_t>& off = mesh->class_off;
   for (size_t c = 0; c + 1 < off.size(); ++c) {
     const int n = (int)(off[c + 1] - off[c]);
@@ -1980,10 +2107,7 @@ int anneal_propose(MovableMesh* mesh, double* xy, const ObjectiveParams* params,
   const ccsp::MeshDev& d = mesh->d;
   const ccsp::Par p = to_par(params);
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s, d,
-                     (const double2*)xy);
-  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
-                     d.partial);
+  stage_edges(d, p, xy, s);
   const std::vector<int64_t>& off = mesh->class_off;
   for (size_t c = 0; c + 1 < off.size(); ++c) {
     const int n = (int)(off[c + 1] - off[c]);
@@ -2037,10 +2161,7 @@ int anneal_schedule(MovableMesh* mesh, double* xy, const ObjectiveParams* params
     ObjectiveParams pk = *params;
     pk.eps = eps[k];
     const ccsp::Par p = to_par(&pk);
-    hipLaunchKernelGGL(ccsp::permute_positions, dim3(grid_for(d.nv)), dim3(ccsp::kThreads), 0, s,
-                       d, (const double2*)xy);
-    hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(ccsp::kThreads), 0, s, d, p,
-                       d.partial);
+    stage_edges(d, p, xy, s);
     hipLaunchKernelGGL(ccsp::zero_counter, dim3(1), dim3(64), 0, s, counter);
     const double2* xk = (const double2*)xi + (size_t)k * M;
     const double* uk = u + (size_t)k * M;
@@ -2069,6 +2190,7 @@ int anneal_schedule(MovableMesh* mesh, double* xy, const ObjectiveParams* params
 void mesh_free(MovableMesh* mesh) {
   if (!mesh) return;
   if (mesh->sched) (void)hipFree(mesh->sched);
+  if (mesh->order_ws) (void)hipFree(mesh->order_ws);
   if (mesh->class_dev) (void)hipFree(mesh->class_dev);
   if (mesh->mem) (void)hipFree(mesh->mem);
   delete mesh;

@@ -151,6 +151,69 @@ def test_tiny_delta(ccsp, tiny, state, polish):
     assert (st[:n] == 1).sum() > 100 and (st[:n] == 0).sum() > 10
 
 
+def test_rules_follow_original_positions(ccsp, tiny):
+    """The conditioning restriction reads ORIGINAL positions only, so the library keeps its result
+    from call to call and recomputes it when an ORIGINAL position changes. One mesh evaluated at
+    positions whose ORIGINAL vertices change (a squash that makes triangles near-collinear), then
+    at positions where only movable vertices change, then back, equals the checker each time."""
+    mesh, om = tiny
+    p = ob.Params(0.03)
+    xy1 = mesh.xy
+    xy2 = mesh.xy.copy()
+    xy2[:, 1] *= 0.02
+    xy3 = xy2.copy()
+    movable = mesh.kind != sg.ORIGINAL
+    xy3[movable] = _clustered(mesh, om, p, 9)[movable]
+    xy3[:, 1][movable] *= 0.02
+    assert (ob.conditioning_contractible(om, xy1) != ob.conditioning_contractible(om, xy2)).sum() > 10
+    with ccsp.MovableMesh(om.tri_v, om.kind, om.line, om.prim_v) as gm:
+        for k, xy in enumerate((xy1, xy2, xy3, xy1, xy3)):
+            ref = ob.objective(om, xy, p)
+            out, con, w = gm.eval(torch.from_numpy(xy).to(DEV), _params(ccsp, p), per_edge=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(con.cpu().numpy().astype(bool), ref["contractible"]), k
+            assert np.array_equal(w.cpu().numpy(), ref["w"]), k
+
+
+def test_large_batches_equal_small_ones(ccsp, tiny):
+    """Batches of 4096 moves or more are evaluated in the order of their vertices (a sort inside
+    the call); every result equals the same move's result from batches below that size, and a
+    sample equals the checker. Bad ids sit among the sorted moves; a larger batch then a smaller
+    one run on the same mesh (the sort's scratch grows, then is reused)."""
+    mesh, om = tiny
+    p = ob.Params(0.03)
+    xy = _clustered(mesh, om, p, 5)
+    rng = np.random.default_rng(44)
+    parts = [sg.vertex_moves(mesh, 3000, 40 + j, (0.05, 0.3, 0.6)[j % 3]) for j in range(6)]
+    v = np.concatenate([a for a, _ in parts]).astype(np.int32)
+    q = np.concatenate([b for _, b in parts]).astype(np.float64)
+    bad = rng.choice(v.shape[0], 40, replace=False)
+    v[bad[:20]] = -1 - rng.integers(0, 5, 20)
+    v[bad[20:]] = mesh.n_vertices + rng.integers(0, 5, 20)
+    X = torch.from_numpy(xy).to(DEV)
+    with ccsp.MovableMesh(om.tri_v, om.kind, om.line, om.prim_v) as gm:
+        prm = _params(ccsp, p)
+
+        def run(vv, qq):
+            d, st = gm.delta(X, prm, torch.from_numpy(np.ascontiguousarray(vv)).to(DEV),
+                             torch.from_numpy(np.ascontiguousarray(qq)).to(DEV))
+            torch.cuda.synchronize()
+            return d.cpu().numpy(), st.cpu().numpy()
+
+        small = [run(v[i:i + 1000], q[i:i + 1000]) for i in range(0, v.shape[0], 1000)]
+        ds = np.concatenate([a for a, _ in small])
+        ss = np.concatenate([b for _, b in small])
+        for n in (v.shape[0], 4096, 9001):
+            d, st = run(v[:n], q[:n])
+            assert np.array_equal(st, ss[:n]), n
+            assert np.array_equal(d.view(np.int64), ds[:n].view(np.int64)), n
+    assert (ss[bad] == -2).all()
+    assert (ss == 1).sum() > 5000 and (ss == 0).sum() > 500
+    ok = np.nonzero(ss == 1)[0]
+    idx = np.concatenate([ok[:: ok.size // 6][:6], np.nonzero(ss == 0)[0][:2]])
+    _check_deltas(om, xy, p, v, q, ds, ss, "large batch", idx=idx)
+
+
 def test_move_back_is_exact_negative(ccsp, tiny):
     """Applying a move and proposing the way back gives exactly the opposite change, and the
     change agrees with two full evaluations."""
