@@ -231,9 +231,11 @@ int anneal_propose(MovableMesh *mesh, double *xy, const ObjectiveParams *params,
  *    anneal_moves. status[i] is CCSP_MOVE_OK, CCSP_MOVE_REJECTED or CCSP_MOVE_FOLDS and
  *    members[i] (DEVICE int32) the group's size.
  * The moves are made in rounds; round[i] (DEVICE int32) receives the round of centre i. Moves of
- * one round are independent (more than six edges apart, neither moving a vertex into or out of
- * the other's disc), so the result equals the sequential chain over the centres in the order of
- * increasing (round[i], i). xy (DEVICE) is updated in place. Allocates its scratch and
+ * one round are independent (more than five edges apart along paths that do not pass through an
+ * ORIGINAL vertex of more than 32 neighbours, neither moving a vertex into or out of the other's
+ * disc), so the result equals the sequential chain over the centres in the order of increasing
+ * (round[i], i). xy (DEVICE) is updated in place. Allocates its scratch (about 30 bytes per
+ * centre, 24 per member of the round's pending groups, 8 per vertex and 12 per grid cell) and
  * synchronises `stream` once per round; overwrites the mesh's scratch.
  */
 int anneal_group(MovableMesh *mesh, double *xy, const ObjectiveParams *params, double temperature,

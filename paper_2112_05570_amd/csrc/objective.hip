@@ -1103,53 +1103,115 @@ group_count(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
   cnt[i] = k;
 }
 
-// Members (the centre, then the others by increasing caller id) into mem[off[i]..], the move's
-// displacement, and the claims.
+// Position of vertex w in group (M, K, nm): 0 for the centre M[0], else its index in the members
+// M[1..nm) ordered by caller id K, or -1 when w is not a member.
+__device__ __forceinline__ int member_pos(const MeshDev& m, const int* __restrict__ M,
+                                          const int* __restrict__ K, int nm, int w) {
+  if (w == M[0]) return 0;
+  const int kw = m.vold[w];
+  int lo = 1, hi = nm;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int km = K[mid];
+    if (km == kw) return mid;
+    if (km < kw) lo = mid + 1; else hi = mid;
+  }
+  return -1;
+}
+
+// One wave per group (4 per workgroup). Members (the centre, then the others by increasing caller
+// id) into mem[off[i]..] with their caller ids in key[off[i]..], the move's displacement, and the
+// claims. Lane 0 collects the members of the range query; the lanes rank them by caller id
+// (distinct, so the order is unique), mark for each member which of its triangles hold no earlier
+// member, and make the claims; lane 0 adds the group's area in member order (the same sum as one
+// thread taking the members one after another).
 __global__ void __launch_bounds__(kThreads)
 group_claim(MeshDev m, VGrid g, Par p, double lambda, const int32_t* __restrict__ gcen,
             const double2* __restrict__ draws, const uint8_t* __restrict__ done, int n,
-            const int32_t* __restrict__ off, int32_t* __restrict__ mem,
-            double2* __restrict__ disp, uint32_t* __restrict__ own_v,
-            uint32_t* __restrict__ own_c) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n || done[i]) return;
-  const int c = gcen[i];
-  const double d = (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps;
-  int* M = mem + off[i];
-  int nm = 1;
-  M[0] = c;
-  for_members(m, g, c, d, [&](int w) {
-    const int cw = m.vold[w];
-    int j = nm++;
-    while (j > 1 && m.vold[M[j - 1]] > cw) {
-      M[j] = M[j - 1];
-      --j;
-    }
-    M[j] = w;
-  });
-  // area of the triangles holding any member, each at the first member (in order) holding it
-  double area = 0.0;
-  for (int j = 0; j < nm; ++j) {
-    const int v = M[j];
-    for (int k = m.vtri_off[v], end = m.vtri_off[v + 1]; k < end; ++k) {
-      const int tid = m.vtri[k];
-      const int4 tr = m.tri[tid];
-      bool earlier = false;
-      for (int l = 0; l < j; ++l) {
-        const int w = M[l];
-        earlier = earlier || tr.x == w || tr.y == w || tr.z == w;
+            const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
+            int32_t* __restrict__ mem, int32_t* __restrict__ key, int32_t* __restrict__ tmpm,
+            int32_t* __restrict__ tmpk, uint64_t* __restrict__ first, double2* __restrict__ disp,
+            uint32_t* __restrict__ own_v, uint32_t* __restrict__ own_c) {
+  const int i = (int)((blockIdx.x * (unsigned)kThreads + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const bool active = i < n && !done[i];
+  const int c = active ? gcen[i] : -1;
+  const int nm = active ? cnt[i] : 0;
+  const int o0 = active ? off[i] : 0;
+  int* M = mem + o0;
+  int* K = key + o0;
+  int* Mu = tmpm + o0;
+  int* Ku = tmpk + o0;
+  uint64_t* F = first + o0;
+  const double d = active ? (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps : 0.0;
+  if (active && lane == 0) {
+    int k = 1;
+    for_members(m, g, c, d, [&](int w) {
+      if (k < nm) {  // the same query as group_count's, so k stays below nm
+        Mu[k] = w;
+        Ku[k] = m.vold[w];
       }
-      if (!earlier) area = area + tri_area(m, tid);
-    }
+      ++k;
+    });
+    M[0] = c;
+    K[0] = m.vold[c];
   }
-  const double k = lambda * sqrt(area);
-  const double2 xi = draws[2 * i];
-  const double2 D = make_double2(k * xi.x, k * xi.y);
-  disp[i] = D;
+  __syncthreads();
+  for (int j = 1 + lane; j < nm; j += 64) {
+    const int kj = Ku[j];
+    int r = 1;
+    for (int l = 1; l < nm; ++l) r += Ku[l] < kj ? 1 : 0;
+    M[r] = Mu[j];
+    K[r] = kj;
+  }
+  __syncthreads();
+  // bit k of F[j]: triangle k of member j holds no member before j (k < 64; lane 0 decides the
+  // rest when it adds them up)
+  for (int j = lane; j < nm; j += 64) {
+    const int v = M[j];
+    uint64_t bits = 0;
+    for (int k = m.vtri_off[v], end = min(m.vtri_off[v + 1], m.vtri_off[v] + 64); k < end; ++k) {
+      const int4 tr = m.tri[m.vtri[k]];
+      const int px = member_pos(m, M, K, nm, tr.x), py = member_pos(m, M, K, nm, tr.y),
+                pz = member_pos(m, M, K, nm, tr.z);
+      const bool earlier = (px >= 0 && px < j) || (py >= 0 && py < j) || (pz >= 0 && pz < j);
+      if (!earlier) bits |= 1ull << (k - m.vtri_off[v]);
+    }
+    F[j] = bits;
+  }
+  __syncthreads();
+  if (active && lane == 0) {
+    // area of the triangles holding any member, each at the first member (in order) holding it
+    double area = 0.0;
+    for (int j = 0; j < nm; ++j) {
+      const int v = M[j];
+      const uint64_t bits = F[j];
+      const int k0 = m.vtri_off[v];
+      for (int k = k0, end = m.vtri_off[v + 1]; k < end; ++k) {
+        const int tid = m.vtri[k];
+        bool is_first;
+        if (k - k0 < 64) {
+          is_first = (bits >> (k - k0)) & 1;
+        } else {
+          const int4 tr = m.tri[tid];
+          const int px = member_pos(m, M, K, nm, tr.x), py = member_pos(m, M, K, nm, tr.y),
+                    pz = member_pos(m, M, K, nm, tr.z);
+          is_first = !((px >= 0 && px < j) || (py >= 0 && py < j) || (pz >= 0 && pz < j));
+        }
+        if (is_first) area = area + tri_area(m, tid);
+      }
+    }
+    const double k = lambda * sqrt(area);
+    const double2 xi = draws[2 * i];
+    disp[i] = make_double2(k * xi.x, k * xi.y);
+  }
+  __syncthreads();
+  if (!active) return;
+  const double2 D = disp[i];
   const uint32_t pri = group_priority(i);
   auto claim_c = [&](int cell) { atomicMin(&own_c[cell], pri); };
-  for_cells(g, m.xyi[c], d * kQueryWiden, claim_c);
-  for (int j = 0; j < nm; ++j) {
+  if (lane == 0) for_cells(g, m.xyi[c], d * kQueryWiden, claim_c);
+  for (int j = lane; j < nm; j += 64) {
     const int v = M[j];
     const double2 o = m.xyi[v], dv = member_disp(m, v, D);
     claim_c(cell_of(g, o));
@@ -1158,8 +1220,9 @@ group_claim(MeshDev m, VGrid g, Par p, double lambda, const int32_t* __restrict_
   }
 }
 
-// Whether group i may move: it holds the cells it claimed and no vertex within three edges of its
-// members carries a lower priority (no position changes during this pass).
+// One wave per group: whether group i may move, i.e. it holds the cells it claimed and no vertex
+// within three edges of its members carries a lower priority (no position changes during this
+// pass). The lanes take the members; the wave's vote decides.
 __global__ void __launch_bounds__(kThreads)
 group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
             const double2* __restrict__ draws, const uint8_t* __restrict__ done, int n,
@@ -1167,28 +1230,31 @@ group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
             const int32_t* __restrict__ mem, const double2* __restrict__ disp,
             const uint32_t* __restrict__ own_v, const uint32_t* __restrict__ own_c,
             uint8_t* __restrict__ won) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const int i = (int)((blockIdx.x * (unsigned)kThreads + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= n) return;
   if (done[i]) {
-    won[i] = 0;
+    if (lane == 0) won[i] = 0;
     return;
   }
-  const int c = gcen[i];
-  const double d = (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps;
   bool ok = true;
   const uint32_t pri = group_priority(i);
   auto held_c = [&](int cell) { ok = ok && own_c[cell] == pri; };
-  for_cells(g, m.xyi[c], d * kQueryWiden, held_c);
+  if (lane == 0) {
+    const double d = (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps;
+    for_cells(g, m.xyi[gcen[i]], d * kQueryWiden, held_c);
+  }
   const int* M = mem + off[i];
   const double2 D = disp[i];
-  for (int j = 0; j < cnt[i] && ok; ++j) {
+  for (int j = lane; j < cnt[i] && ok; j += 64) {
     const int v = M[j];
     const double2 o = m.xyi[v], dv = member_disp(m, v, D);
     held_c(cell_of(g, o));
     held_c(cell_of(g, make_double2(o.x + dv.x, o.y + dv.y)));
     for_hops3(m, v, [&](int x) { ok = ok && own_v[x] >= pri; });
   }
-  won[i] = ok ? 1 : 0;
+  const bool all = __ballot(!ok) == 0;
+  if (lane == 0) won[i] = all ? 1 : 0;
 }
 
 // The move of every group that holds its claims: its members moved one after another by D
@@ -1950,7 +2016,8 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   if (!(g.gy >= 1)) g.gy = 1;
   const int ncells = g.gx * g.gy;
   int32_t *gcen = nullptr, *cnt = nullptr, *off = nullptr, *start = nullptr, *cursor = nullptr;
-  int32_t *vert = nullptr, *mem = nullptr;
+  int32_t *vert = nullptr, *mem = nullptr, *key = nullptr, *tmpm = nullptr, *tmpk = nullptr;
+  uint64_t* first = nullptr;
   uint32_t *own_v = nullptr, *own_c = nullptr;
   uint8_t *done = nullptr, *won = nullptr;
   double2* disp = nullptr;
@@ -2005,7 +2072,9 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
     if (e != hipSuccess) return hip_fail(e, "anneal_group: member count");
     if ((size_t)total > mem_cap) {
       mem_cap = std::max<size_t>((size_t)total, 2 * mem_cap);
-      if (gs.get(&mem, mem_cap) != hipSuccess)
+      if (gs.get(&mem, mem_cap) != hipSuccess || gs.get(&key, mem_cap) != hipSuccess ||
+          gs.get(&tmpm, mem_cap) != hipSuccess || gs.get(&tmpk, mem_cap) != hipSuccess ||
+          gs.get(&first, mem_cap) != hipSuccess)
         return fail(CCSP_E_OOM, "anneal_group: member buffer allocation failed");
     }
     // claims, their check, and the moves of the groups holding all of theirs
@@ -2013,9 +2082,11 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
                        (int64_t)d.nv, -1);
     hipLaunchKernelGGL(ccsp::fill_i32, dim3((ncells + T - 1) / T), dim3(T), 0, s,
                        reinterpret_cast<int32_t*>(own_c), (int64_t)ncells, -1);
-    hipLaunchKernelGGL(ccsp::group_claim, dim3(gb), dim3(T), 0, s, d, g, p, lambda, gcen,
-                       (const double2*)draws, done, N, off, mem, disp, own_v, own_c);
-    hipLaunchKernelGGL(ccsp::group_check, dim3(gb), dim3(T), 0, s, d, g, p, gcen,
+    const unsigned wb = (unsigned)((N + T / 64 - 1) / (T / 64));  // one wave per group
+    hipLaunchKernelGGL(ccsp::group_claim, dim3(wb), dim3(T), 0, s, d, g, p, lambda, gcen,
+                       (const double2*)draws, done, N, off, cnt, mem, key, tmpm, tmpk, first, disp,
+                       own_v, own_c);
+    hipLaunchKernelGGL(ccsp::group_check, dim3(wb), dim3(T), 0, s, d, g, p, gcen,
                        (const double2*)draws, done, N, off, cnt, mem, disp, own_v, own_c, won);
     hipLaunchKernelGGL(ccsp::zero_counter, dim3(1), dim3(64), 0, s, applied);
     hipLaunchKernelGGL(ccsp::group_apply, dim3(gb), dim3(T), 0, s, d, p, temperature,
