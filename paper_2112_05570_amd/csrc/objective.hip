@@ -494,6 +494,17 @@ finish_sums(const double* __restrict__ part, int n1, int n2, Par p, double* __re
 constexpr int kLdsNbrs = 16;  // neighbours of a moved vertex kept in LDS (Steiner vertices have ~6)
 constexpr int kCache = 8;     // entries of a move's cache of changed contraction weights
 
+// The 32-bit finaliser of MurmurHash3 (Appleby): a bijection of the 32-bit integers that leaves no
+// order between neighbouring values.
+__device__ __forceinline__ uint32_t group_hash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
+
 // A thread's LDS columns for evaluating a move (stride kThreads): the moved vertex's neighbours,
 // and a direct-mapped cache, by edge id, of the contraction weight c an edge takes after the move
 // (each is read by up to four terms; computing it once per move keeps the neighbourhood gathers
@@ -504,21 +515,30 @@ struct MoveLds {
   double* cc;
 };
 
-struct MoveCtx {
+constexpr int kHash = 512;  // a wave's table of the changed c of one move (edge id -> c)
+
+// The context of one move's change of f. S is the stride of the LDS columns (a thread's own
+// columns in a workgroup of kThreads, or 1 for a wave's shared ones). Without WAVE, the changed c
+// of a C-edge is computed on first use into the thread's cache; with WAVE, the wave has computed
+// every C-edge's changed c beforehand into an open-addressing table (hkey, hval).
+template <int S, bool WAVE>
+struct MoveCtxT {
   MeshDev m;
   const double2* __restrict__ xy;
   Par p;
   int v;
   double2 q;
-  const int* nb;  // this thread's neighbours of v in LDS, stride kThreads, when deg <= kLdsNbrs
+  const int* nb;  // neighbours of v in LDS, stride S, when deg <= kLdsNbrs
   int deg;
   int* ce;        // the move's cache of changed c: edge ids (-1 empty) and values
   double* cc;
+  const int* hkey;      // WAVE: table keys (-1 empty) and values
+  const double* hval;
 
   __device__ __forceinline__ bool adjacent(int x) const {
     if (deg > kLdsNbrs) return is_neighbour(m, v, x);
     for (int j = 0; j < deg; ++j)
-      if (nb[j * kThreads] == x) return true;
+      if (nb[j * S] == x) return true;
     return false;
   }
   // The edges whose c may change when v moves: v's edges (lengths; the flat-triangle rule of
@@ -540,14 +560,21 @@ struct MoveCtx {
   }
   __device__ __forceinline__ double c(int e, bool moved) const {
     if (!moved || !in_c(e)) return m.c[e];
-    const int slot = (e & (kCache - 1)) * kThreads;
-    if (ce[slot] == e) return cc[slot];
-    const int2 ab = m.edge_v[e];
-    const double r =
-        c_of_len(contractible_at(m, xy, e, ab.x, ab.y, p.eps, v, q), len(e, true), p.eps);
-    ce[slot] = e;
-    cc[slot] = r;
-    return r;
+    if constexpr (WAVE) {
+      int h = (int)(group_hash((uint32_t)e) & (kHash - 1));
+      for (int k = 0; k < kHash; ++k, h = (h + 1) & (kHash - 1))
+        if (hkey[h] == e) return hval[h];
+      return __builtin_nan("");  // not reached: the table holds every C-edge
+    } else {
+      const int slot = (e & (kCache - 1)) * S;
+      if (ce[slot] == e) return cc[slot];
+      const int2 ab = m.edge_v[e];
+      const double r =
+          c_of_len(contractible_at(m, xy, e, ab.x, ab.y, p.eps, v, q), len(e, true), p.eps);
+      ce[slot] = e;
+      cc[slot] = r;
+      return r;
+    }
   }
   __device__ __forceinline__ double term(int e, bool moved) const {
     double w = 1.0;
@@ -596,7 +623,7 @@ struct MoveCtx {
 // order) and the per-edge scratch of edge_state; with CHECK, CCSP_MOVE_FOLDS (and *df untouched)
 // when a triangle of v would not stay strictly counter-clockwise. lds holds this thread's LDS
 // columns.
-template <bool CHECK>
+template <bool CHECK, int S = kThreads>
 __device__ __forceinline__ int move_change(const MeshDev& m, const double2* __restrict__ xy,
                                            const Par& p, int v, double2 q, MoveLds lds,
                                            double* df) {
@@ -611,10 +638,10 @@ __device__ __forceinline__ int move_change(const MeshDev& m, const double2* __re
   }
   const int a0 = m.adj_off[v], deg = m.adj_off[v + 1] - a0;
   if (deg <= kLdsNbrs)
-    for (int j = 0; j < deg; ++j) lds.nb[j * kThreads] = m.adj[a0 + j].x;
+    for (int j = 0; j < deg; ++j) lds.nb[j * S] = m.adj[a0 + j].x;
 #pragma unroll
-  for (int k = 0; k < kCache; ++k) lds.ce[k * kThreads] = -1;
-  const MoveCtx ctx{m, xy, p, v, q, lds.nb, deg, lds.ce, lds.cc};
+  for (int k = 0; k < kCache; ++k) lds.ce[k * S] = -1;
+  const MoveCtxT<S, false> ctx{m, xy, p, v, q, lds.nb, deg, lds.ce, lds.cc, nullptr, nullptr};
   double se = 0.0, ss = 0.0;
   for (int j = a0, end = a0 + deg; j < end; ++j) {
     const int e = m.adj[j].y;
@@ -732,15 +759,20 @@ anneal_moves(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out,
 // the scratch of the edges whose values depend on v's position, with the operations of
 // edge_state: length and c of its edges, contractibility and c of the edges joining two of its
 // neighbours (v may be an opposite or 1-hop vertex of those).
-__device__ __forceinline__ void refresh_scratch(const MeshDev& m, const Par& p, int v) {
+// Split in two (lengths, then the rest) for callers that refresh several vertices at once.
+__device__ __forceinline__ void refresh_lengths(const MeshDev& m, int v) {
   const double2* __restrict__ xy = m.xyi;
-  const int a0 = m.adj_off[v], a1 = m.adj_off[v + 1];
-  const double2 nq = make_double2(0, 0);
-  for (int j = a0; j < a1; ++j) {  // lengths first: the rules below read them
+  for (int j = m.adj_off[v], a1 = m.adj_off[v + 1]; j < a1; ++j) {
     const int e = m.adj[j].y;
     const int2 ab = m.edge_v[e];
     m.len[e] = dist(xy[ab.x], xy[ab.y]);
   }
+}
+
+__device__ __forceinline__ void refresh_rules(const MeshDev& m, const Par& p, int v) {
+  const double2* __restrict__ xy = m.xyi;
+  const int a0 = m.adj_off[v], a1 = m.adj_off[v + 1];
+  const double2 nq = make_double2(0, 0);
   for (int j = a0; j < a1; ++j) {
     const int e = m.adj[j].y;
     const int2 ab = m.edge_v[e];
@@ -769,6 +801,11 @@ __device__ __forceinline__ void refresh_scratch(const MeshDev& m, const Par& p, 
       m.c[e] = c_of_len(ok, m.len[e], p.eps);
     }
   }
+}
+
+__device__ __forceinline__ void refresh_scratch(const MeshDev& m, const Par& p, int v) {
+  refresh_lengths(m, v);  // first: the c below read the lengths
+  refresh_rules(m, p, v);
 }
 
 // Area of triangle t at the current positions, its vertices in the caller's order.
@@ -939,17 +976,9 @@ anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
 
 constexpr double kQueryWiden = 1.0 + 0x1p-40;  // query extents, widened against rounding
 
-// A group's claim priority: its index through the 32-bit finaliser of MurmurHash3 (Appleby), a
-// bijection of the 32-bit integers that leaves no order between neighbouring indices.
-__device__ __forceinline__ uint32_t group_priority(int i) {
-  uint32_t x = (uint32_t)i;
-  x ^= x >> 16;
-  x *= 0x85ebca6bu;
-  x ^= x >> 13;
-  x *= 0xc2b2ae35u;
-  x ^= x >> 16;
-  return x;
-}
+// A group's claim priority: its index through the 32-bit finaliser of MurmurHash3, so that
+// neighbouring indices carry unrelated priorities.
+__device__ __forceinline__ uint32_t group_priority(int i) { return group_hash((uint32_t)i); }
 
 struct VGrid {
   double x0, y0, inv;      // cell of p: floor((p - p0) * inv), clamped to the grid
@@ -1257,12 +1286,20 @@ group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
   if (lane == 0) won[i] = all ? 1 : 0;
 }
 
-// The move of every group that holds its claims: its members moved one after another by D
-// (projected when constrained), each with its change of f against the positions and scratch its
-// predecessors left, so that the changes add up to the change of f of the whole move; valid when
-// every triangle of every member is strictly counter-clockwise at the end; rejected or invalid
-// moves are undone from xy_out, which holds the positions before them.
-__global__ void __launch_bounds__(kThreads)
+constexpr int kSlots = 384;        // C-edges of one member move that a wave's tables hold
+constexpr int kApplyThreads = 64;  // group_apply: one wave per group
+
+// The move of every group that holds its claims, one wave (a workgroup) per group: its members
+// moved one after another by D (projected when constrained), each with its change of f against
+// the positions and scratch its predecessors left, so that the changes add up to the change of f
+// of the whole move; valid when every triangle of every member is strictly counter-clockwise at
+// the end; rejected or invalid moves are undone from xy_out, which holds the positions before
+// them. Per member the lanes list its C-edges (in move_change's order), compute each one's new c
+// into an LDS table, visit them (the same terms as move_change), and lane 0 adds the results in
+// that order, so the change of f is bit for bit move_change's; the C-edges' scratch is then
+// written as refresh_scratch would. A member with more than kLdsNbrs neighbours or kSlots
+// C-edges takes move_change and refresh_scratch on lane 0.
+__global__ void __launch_bounds__(kApplyThreads)
 group_apply(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out, int n,
             const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
             const int32_t* __restrict__ mem, const double2* __restrict__ disp,
@@ -1270,60 +1307,186 @@ group_apply(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out, 
             uint8_t* __restrict__ done, double* __restrict__ delta,
             int32_t* __restrict__ status, int32_t* __restrict__ members,
             int32_t* __restrict__ round, unsigned long long* __restrict__ applied) {
-  __shared__ int snb[kLdsNbrs * kThreads];
-  __shared__ int sce[kCache * kThreads];
-  __shared__ double scc[kCache * kThreads];
-  const MoveLds lds{snb + threadIdx.x, sce + threadIdx.x, scc + threadIdx.x};
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  bool moved = false;
-  if (i < n && won[i]) {
-    moved = true;
-    const int* M = mem + off[i];
-    const int nm = cnt[i];
-    const double2 D = disp[i];
-    double df = 0.0;
-    for (int j = 0; j < nm; ++j) {
-      const int v = M[j];
-      const double2 o = m.xyi[v], dv = member_disp(m, v, D);
-      const double2 q = make_double2(o.x + dv.x, o.y + dv.y);
+  __shared__ int wnb[kLdsNbrs];
+  __shared__ int slot_e[kSlots];
+  __shared__ double slot_c[kSlots];
+  __shared__ double slot_v[kSlots];
+  __shared__ uint8_t slot_ok[kSlots];
+  __shared__ double new_len[kLdsNbrs], short_d[kLdsNbrs], angle_d[kLdsNbrs];
+  __shared__ int free_n[kLdsNbrs], free_off[kLdsNbrs];
+  __shared__ int hkey[kHash];
+  __shared__ double hval[kHash];
+  __shared__ int fnb[kLdsNbrs], fce[kCache];
+  __shared__ double fcc[kCache];
+  __shared__ int n_slots;
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= n || !won[i]) return;
+  const int* M = mem + off[i];
+  const int nm = cnt[i];
+  const double2 D = disp[i];
+  double df = 0.0;  // lane 0's
+  for (int j = 0; j < nm; ++j) {
+    const int v = M[j];
+    const double2 o = m.xyi[v], dv = member_disp(m, v, D);
+    const double2 q = make_double2(o.x + dv.x, o.y + dv.y);
+    const int a0 = m.adj_off[v], deg = m.adj_off[v + 1] - a0;
+    const int t0 = m.vtri_off[v], nt = m.vtri_off[v + 1] - t0;
+    const int npair = deg * (deg - 1) / 2;
+    bool wide = deg > kLdsNbrs || nt > kLdsNbrs || deg + npair > kSlots;
+    if (!wide) {
+      if (lane < deg) {
+        const int2 a = m.adj[a0 + lane];
+        wnb[lane] = a.x;
+        slot_e[lane] = a.y;
+        const int2 ab = m.edge_v[a.y];
+        const double ln = dist(pos(m.xyi, ab.x, v, q), pos(m.xyi, ab.y, v, q));
+        new_len[lane] = ln;
+        short_d[lane] = short_term(ln, p.eps0) - short_term(m.len[a.y], p.eps0);
+      }
+      if (lane < nt) {
+        const int4 t = m.tri[m.vtri[t0 + lane]];
+        angle_d[lane] = triangle_angles(m.xyi, t, v, q, p.delta, p.polish) -
+                        triangle_angles(m.xyi, t, -1, q, p.delta, p.polish);
+      }
+      for (int h = lane; h < kHash; h += kApplyThreads) hkey[h] = -1;
+      __syncthreads();
+      // edges joining two neighbours, pairs (a, b), a < b, in row order; -1 where none
+      for (int pi = lane; pi < npair; pi += kApplyThreads) {
+        int a = 0, r = pi;
+        while (r >= deg - 1 - a) {
+          r -= deg - 1 - a;
+          ++a;
+        }
+        slot_e[deg + pi] = find_edge(m, wnb[a], wnb[a + 1 + r]);
+      }
+      // edges from a FREE neighbour F to a vertex that is not FREE, v or a neighbour of v
+      auto qualifies = [&](int C) {
+        if (C == v || m.vk[C].x == CCSP_VERTEX_FREE) return false;
+        for (int l = 0; l < deg; ++l)
+          if (wnb[l] == C) return false;
+        return true;
+      };
+      if (lane < deg) {
+        const int F = wnb[lane];
+        int k = 0;
+        if (m.vk[F].x == CCSP_VERTEX_FREE)
+          for (int r = m.adj_off[F], re = m.adj_off[F + 1]; r < re; ++r)
+            k += qualifies(m.adj[r].x) ? 1 : 0;
+        free_n[lane] = k;
+      }
+      __syncthreads();
+      if (lane == 0) {
+        int total = deg + npair;
+        for (int l = 0; l < deg; ++l) {
+          free_off[l] = total;
+          total += free_n[l];
+        }
+        n_slots = total <= kSlots ? total : -1;
+      }
+      __syncthreads();
+      const int ns = n_slots;
+      wide = ns < 0;
+      if (!wide) {
+        if (lane < deg && free_n[lane] > 0) {
+          const int F = wnb[lane];
+          int k = free_off[lane];
+          for (int r = m.adj_off[F], re = m.adj_off[F + 1]; r < re; ++r)
+            if (qualifies(m.adj[r].x)) slot_e[k++] = m.adj[r].y;
+        }
+        __syncthreads();
+        // the new c of every C-edge (each listed once), into the slots and the table
+        for (int sl = lane; sl < ns; sl += kApplyThreads) {
+          const int e = slot_e[sl];
+          if (e < 0) continue;
+          const int2 ab = m.edge_v[e];
+          const bool ok = contractible_at(m, m.xyi, e, ab.x, ab.y, p.eps, v, q);
+          const double c = c_of_len(ok, sl < deg ? new_len[sl] : m.len[e], p.eps);
+          slot_c[sl] = c;
+          slot_ok[sl] = ok ? 1 : 0;
+          int h = (int)(group_hash((uint32_t)e) & (kHash - 1));
+          while (atomicCAS(&hkey[h], -1, e) != -1) h = (h + 1) & (kHash - 1);
+          hval[h] = c;
+        }
+        __syncthreads();
+        const MoveCtxT<1, true> ctx{m, m.xyi, p, v, q, wnb, deg, nullptr, nullptr, hkey, hval};
+        for (int sl = lane; sl < ns; sl += kApplyThreads) {
+          const int e = slot_e[sl];
+          slot_v[sl] = e >= 0 ? ctx.visit(e) : 0.0;
+        }
+        __syncthreads();
+        if (lane == 0) {
+          double sa = 0.0, se = 0.0, ss = 0.0;
+          for (int t = 0; t < nt; ++t) sa += angle_d[t];
+          for (int k = 0; k < deg; ++k) {
+            se += slot_v[k];
+            ss += short_d[k];
+          }
+          for (int sl = deg; sl < ns; ++sl)
+            if (slot_e[sl] >= 0) se += slot_v[sl];
+          df += se + p.mu_angle * sa + p.mu_len * ss;
+          m.xyi[v] = q;
+        }
+        for (int sl = lane; sl < ns; sl += kApplyThreads) {
+          const int e = slot_e[sl];
+          if (e < 0) continue;
+          if (sl < deg) m.len[e] = new_len[sl];
+          m.contr[e] = slot_ok[sl];
+          m.c[e] = slot_c[sl];
+        }
+        __syncthreads();
+        continue;
+      }
+    }
+    if (lane == 0) {
       double dfj = 0.0;
-      move_change<false>(m, m.xyi, p, v, q, lds, &dfj);
+      move_change<false, 1>(m, m.xyi, p, v, q, MoveLds{fnb, fce, fcc}, &dfj);
       df += dfj;
       m.xyi[v] = q;
       refresh_scratch(m, p, v);
     }
-    bool ok = true;
-    for (int j = 0; j < nm && ok; ++j) {
-      const int v = M[j];
-      for (int k = m.vtri_off[v], end = m.vtri_off[v + 1]; k < end && ok; ++k) {
-        const int4 tr = m.tri[m.vtri[k]];
-        ok = orient_sign(m.xyi[tr.x], m.xyi[tr.y], m.xyi[tr.z]) > 0;
-      }
+    __syncthreads();
+  }
+  bool ok = true;
+  for (int j = lane; j < nm && ok; j += kApplyThreads) {
+    const int v = M[j];
+    for (int k = m.vtri_off[v], end = m.vtri_off[v + 1]; k < end && ok; ++k) {
+      const int4 tr = m.tri[m.vtri[k]];
+      ok = orient_sign(m.xyi[tr.x], m.xyi[tr.y], m.xyi[tr.z]) > 0;
     }
+  }
+  const bool valid = __ballot(!ok) == 0;
+  bool took = false;
+  if (lane == 0) {
     int st = CCSP_MOVE_FOLDS;
-    bool took = false;
-    if (ok) {
+    if (valid) {
       st = CCSP_MOVE_REJECTED;
       if (df <= 0.0 || u[i] < exp(-df / temperature)) {
         st = CCSP_MOVE_OK;
         took = true;
-        for (int j = 0; j < nm; ++j) xy_out[m.vold[M[j]]] = m.xyi[M[j]];
       }
     } else {
       df = __builtin_huge_val();
-    }
-    if (!took) {
-      for (int j = 0; j < nm; ++j) m.xyi[M[j]] = xy_out[m.vold[M[j]]];
-      for (int j = 0; j < nm; ++j) refresh_scratch(m, p, M[j]);
     }
     status[i] = st;
     delta[i] = df;
     members[i] = nm;
     round[i] = rnd;
     done[i] = 1;
+    atomicAdd(applied, 1ull);
   }
-  const int cnt_moved = __syncthreads_count(moved);
-  if (threadIdx.x == 0 && cnt_moved > 0) atomicAdd(applied, (unsigned long long)cnt_moved);
+  took = __ballot(took) != 0;
+  if (took) {
+    for (int j = lane; j < nm; j += kApplyThreads) xy_out[m.vold[M[j]]] = m.xyi[M[j]];
+    return;
+  }
+  // undo: every member back, then the scratch around them (lengths first; each edge's values
+  // depend on the positions and lengths alone, so the lanes' order does not matter)
+  for (int j = lane; j < nm; j += kApplyThreads) m.xyi[M[j]] = xy_out[m.vold[M[j]]];
+  __syncthreads();
+  for (int j = lane; j < nm; j += kApplyThreads) refresh_lengths(m, M[j]);
+  __syncthreads();
+  for (int j = lane; j < nm; j += kApplyThreads) refresh_rules(m, p, M[j]);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -2089,7 +2252,8 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
     hipLaunchKernelGGL(ccsp::group_check, dim3(wb), dim3(T), 0, s, d, g, p, gcen,
                        (const double2*)draws, done, N, off, cnt, mem, disp, own_v, own_c, won);
     hipLaunchKernelGGL(ccsp::zero_counter, dim3(1), dim3(64), 0, s, applied);
-    hipLaunchKernelGGL(ccsp::group_apply, dim3(gb), dim3(T), 0, s, d, p, temperature,
+    hipLaunchKernelGGL(ccsp::group_apply, dim3((unsigned)N), dim3(ccsp::kApplyThreads), 0, s, d, p,
+                       temperature,
                        (double2*)xy, N, off, cnt, mem, disp, u, won, rnd, done, delta, status,
                        members, round, applied);
     unsigned long long got = 0;

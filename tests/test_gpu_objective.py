@@ -841,6 +841,31 @@ def test_group_moves_around_a_hub(ccsp, eps, rep):
     assert (st_ref == ob.ACCEPTED).sum() > 10
 
 
+@pytest.mark.parametrize("eps,rep", [(0.04, 0), (0.3, 1)])
+def test_group_moves_with_a_free_vertex_of_high_degree(ccsp, eps, rep):
+    """The hub mesh with its centre made FREE: a movable vertex of 40 neighbours, more than the
+    LDS tables of the wave that applies a group hold, so that member's move is taken on one lane
+    while the others' are spread over the wave. Group sweeps (at eps = 0.3 the groups near the
+    centre hold it and much of its fan) equal the checker's sequential chain."""
+    xy, tri, kind, line, prim_v = _hub_mesh()
+    kind = kind.copy()
+    kind[0] = ob.FREE
+    om = ob.Mesh(tri, kind, line, prim_v)
+    p = ob.Params(eps)
+    rng = np.random.default_rng(71 + rep)
+    with ccsp.MovableMesh(tri, kind, line, prim_v) as gm:
+        M = gm.movable.shape[0]
+        assert gm.movable[0] == 0
+        draws = np.zeros((M, 4))
+        draws[:, :2] = 0.3 * eps * rng.standard_normal((M, 2))
+        draws[:, 2] = rng.random(M)
+        u = rng.random(M)
+        st_r, size, rnd = _group_sweep_vs_chain(ccsp, gm, om, xy, p, 1e-3, 0.05, draws, u)
+        assert (st_r == ob.ACCEPTED).sum() > 5
+        if eps > 0.2:
+            assert size.max() > 20
+
+
 @pytest.mark.parametrize("seed,eps", [(0, 0.3), (1, 1.0), (2, 2.0), (3, 0.3)])
 def test_conditioning_and_flat_rules_on_gpu(ccsp, seed, eps):
     """Sec. 2.2.2's conditioning and flat-triangle restrictions: on meshes where both fire (the
