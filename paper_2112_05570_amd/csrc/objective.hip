@@ -523,7 +523,7 @@ constexpr int kHash = 512;  // a wave's table of the changed c of one move (edge
 // every C-edge's changed c beforehand into an open-addressing table (hkey, hval).
 template <int S, bool WAVE>
 struct MoveCtxT {
-  MeshDev m;
+  const MeshDev& m;
   const double2* __restrict__ xy;
   Par p;
   int v;
@@ -865,95 +865,61 @@ __device__ __forceinline__ int neighbour_of_rank(const MeshDev& m, int v, int k)
   return m.adj[a1 - 1].x;  // not reached: caller ids are distinct
 }
 
-// One class of a sweep: Metropolis steps for its vertices (internal ids), which are pairwise more
-// than four edges apart, so that each thread's reads (within four edges of its vertex) and writes
-// (its position, and scratch of edges within one edge of it) never meet another thread's.
-// kind CCSP_PROPOSE_DISPLACE: the vertex moves by disp[i] (scaled by lambda * eta when lambda > 0);
-// the other kinds draw the new position from the vertex's neighbourhood with draws[2i], draws[2i+1]
-// (Secs. 3.2.4-3.2.6). Accepted moves are counted per block into *accepted when it is given.
-__global__ void __launch_bounds__(kThreads)
-anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
-             double2* __restrict__ xy_out, const int32_t* __restrict__ cls,
-             const double2* __restrict__ disp, const double* __restrict__ u, int n,
-             double* __restrict__ delta, int32_t* __restrict__ status,
-             unsigned long long* __restrict__ accepted) {
-  __shared__ int snb[kLdsNbrs * kThreads];
-  __shared__ int sce[kCache * kThreads];
-  __shared__ double scc[kCache * kThreads];
-  const MoveLds lds{snb + threadIdx.x, sce + threadIdx.x, scc + threadIdx.x};
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  bool took = false;
-  if (i < n) {
-    const int v = cls[i];
-    const int cv = m.vold[v];
-    const double2 o = m.xyi[v];
-    bool skip = false;
-    double2 d;
-    if (kind == CCSP_PROPOSE_DISPLACE) {
-      d = disp[i];
-      if (lambda > 0.0) {
-        // disp is a unit draw: scale by lambda * eta, eta the square root of the area of v's
-        // triangles (Sec. 3.2.2), summed in the caller's triangle order at the current positions
-        double area = 0.0;
-        for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j)
-          area += tri_area(m, m.vtri[j]);
-        const double k = lambda * sqrt(area);
-        d = make_double2(k * d.x, k * d.y);
+// The proposal of class member i (vertex v) of a sweep: its new position *q, or *skip when
+// the proposal does not apply to it (Secs. 3.2.2, 3.2.4-3.2.6, as documented for anneal_sweep and
+// anneal_propose).
+__device__ __forceinline__ void propose_move(const MeshDev& m, const Par& p, double lambda,
+                                             int kind, int v, int i,
+                                             const double2* __restrict__ disp, double2* q_out,
+                                             bool* skip_out) {
+  const double2 o = m.xyi[v];
+  bool skip = false;
+  double2 d;
+  if (kind == CCSP_PROPOSE_DISPLACE) {
+    d = disp[i];
+    if (lambda > 0.0) {
+      // disp is a unit draw: scale by lambda * eta, eta the square root of the area of v's
+      // triangles (Sec. 3.2.2), summed in the caller's triangle order at the current positions
+      double area = 0.0;
+      for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j)
+        area += tri_area(m, m.vtri[j]);
+      const double k = lambda * sqrt(area);
+      d = make_double2(k * d.x, k * d.y);
+    }
+  } else {
+    const double2 ra = disp[2 * i], rb = disp[2 * i + 1];
+    double2 target = o;
+    if (kind == CCSP_PROPOSE_SWAP) {
+      // Sec. 3.2.5: l uniform on [0.2 eps, 2 eps); only a vertex with an edge shorter than l
+      const double l = (0.2 + 1.8 * ra.x) * p.eps;
+      if (has_short_edge(m, v, l)) {
+        const int deg = m.adj_off[v + 1] - m.adj_off[v];
+        const int w = neighbour_of_rank(m, v, min((int)(ra.y * (double)deg), deg - 1));
+        const double2 pw = m.xyi[w];
+        target = make_double2(pw.x + l * rb.x, pw.y + l * rb.y);
+      } else {
+        skip = true;
       }
     } else {
-      const double2 ra = disp[2 * i], rb = disp[2 * i + 1];
-      double2 target = o;
-      if (kind == CCSP_PROPOSE_SWAP) {
-        // Sec. 3.2.5: l uniform on [0.2 eps, 2 eps); only a vertex with an edge shorter than l
-        const double l = (0.2 + 1.8 * ra.x) * p.eps;
-        if (has_short_edge(m, v, l)) {
-          const int deg = m.adj_off[v + 1] - m.adj_off[v];
-          const int w = neighbour_of_rank(m, v, min((int)(ra.y * (double)deg), deg - 1));
-          const double2 pw = m.xyi[w];
-          target = make_double2(pw.x + l * rb.x, pw.y + l * rb.y);
-        } else {
-          skip = true;
-        }
-      } else {
-        target = resample_star(m, v, ra.x, ra.y, rb.x);
-      }
-      d = make_double2(target.x - o.x, target.y - o.y);
+      target = resample_star(m, v, ra.x, ra.y, rb.x);
     }
-    const int2 kl = m.vk[v];
-    if (kl.x == CCSP_VERTEX_CONSTRAINED) {
-      const int2 ends = m.prim_v[kl.y];
-      const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
-      const double ex = b.x - a.x, ey = b.y - a.y;
-      const double s = (d.x * ex + d.y * ey) / (ex * ex + ey * ey);
-      d = make_double2(s * ex, s * ey);
-    }
-    const double2 q = make_double2(o.x + d.x, o.y + d.y);
-    // Sec. 3.2.6: only a change of the contracted state is tried, once
-    if (kind == CCSP_PROPOSE_CONTRACT &&
-        has_short_edge(m, v, p.eps) == has_short_edge_at(m, v, q, p.eps))
-      skip = true;
-    double df = __builtin_huge_val();
-    int st = CCSP_MOVE_SKIPPED;
-    if (!skip) {
-      st = evaluate_move(m, m.xyi, p, cv, q, lds, &df);
-      if (st == CCSP_MOVE_OK) {
-        if (df <= 0.0 || u[i] < exp(-df / temperature)) {
-          m.xyi[v] = q;
-          xy_out[cv] = q;
-          refresh_scratch(m, p, v);
-          took = true;
-        } else {
-          st = CCSP_MOVE_REJECTED;
-        }
-      }
-    }
-    status[i] = st;
-    delta[i] = df;
+    d = make_double2(target.x - o.x, target.y - o.y);
   }
-  if (accepted) {
-    const int c = __syncthreads_count(took);
-    if (threadIdx.x == 0 && c > 0) atomicAdd(accepted, (unsigned long long)c);
+  const int2 kl = m.vk[v];
+  if (kl.x == CCSP_VERTEX_CONSTRAINED) {
+    const int2 ends = m.prim_v[kl.y];
+    const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
+    const double ex = b.x - a.x, ey = b.y - a.y;
+    const double s = (d.x * ex + d.y * ey) / (ex * ex + ey * ey);
+    d = make_double2(s * ex, s * ey);
   }
+  const double2 q = make_double2(o.x + d.x, o.y + d.y);
+  // Sec. 3.2.6: only a change of the contracted state is tried, once
+  if (kind == CCSP_PROPOSE_CONTRACT &&
+      has_short_edge(m, v, p.eps) == has_short_edge_at(m, v, q, p.eps))
+    skip = true;
+  *q_out = q;
+  *skip_out = skip;
 }
 
 // ---- group moves (Sec. 3.2.3)
@@ -1286,20 +1252,193 @@ group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
   if (lane == 0) won[i] = all ? 1 : 0;
 }
 
-constexpr int kSlots = 384;        // C-edges of one member move that a wave's tables hold
-constexpr int kApplyThreads = 64;  // group_apply: one wave per group
+constexpr int kSlots = 384;    // C-edges of one move that a wave's tables hold
+constexpr int kWaveThreads = 64;  // kernels that spread one move over a wave (a workgroup)
+
+// A wave's LDS for one move (see wave_change).
+struct WaveLds {
+  int nb[kLdsNbrs];
+  int slot_e[kSlots];
+  double slot_c[kSlots];
+  double slot_v[kSlots];
+  uint8_t slot_ok[kSlots];
+  double new_len[kLdsNbrs], short_d[kLdsNbrs], angle_d[kLdsNbrs];
+  int free_n[kLdsNbrs], free_off[kLdsNbrs];
+  int hkey[kHash];
+  double hval[kHash];
+  int fnb[kLdsNbrs], fce[kCache];
+  double fcc[kCache];
+  int n_slots;
+};
+
+// The change of f of moving internal vertex v to q, spread over a wave: every lane of the
+// workgroup calls it with the same v and q. The lanes list v's C-edges in move_change's order (its
+// edges, the edges between pairs of its neighbours, one pair per lane, then the FREE neighbours'
+// edges, placed by a prefix sum of their counts), compute each one's new c into an LDS hash table,
+// visit them one per lane with move_change's code, and take the angle and length terms one per
+// lane; lane 0 adds the results in move_change's order, so its *df is bit for bit move_change's.
+// With CHECK, the result is CCSP_MOVE_FOLDS (on every lane, *df untouched) when a triangle of v
+// would not stay strictly counter-clockwise. A vertex with more than kLdsNbrs neighbours or
+// kSlots C-edges takes move_change on lane 0 (*wide set). wave_commit then applies the move.
+template <bool CHECK>
+__device__ __forceinline__ int wave_change(const MeshDev& m, const Par& p, int v, double2 q, WaveLds& w,
+                           int lane, double* df, bool* wide_out) {
+  const int a0 = m.adj_off[v], deg = m.adj_off[v + 1] - a0;
+  const int t0 = m.vtri_off[v], nt = m.vtri_off[v + 1] - t0;
+  const int npair = deg * (deg - 1) / 2;
+  bool wide = deg > kLdsNbrs || nt > kLdsNbrs || deg + npair > kSlots;
+  if (!wide) {
+    bool folds = false;
+    if (lane < deg) {
+      const int2 a = m.adj[a0 + lane];
+      w.nb[lane] = a.x;
+      w.slot_e[lane] = a.y;
+      const int2 ab = m.edge_v[a.y];
+      const double ln = dist(pos(m.xyi, ab.x, v, q), pos(m.xyi, ab.y, v, q));
+      w.new_len[lane] = ln;
+      w.short_d[lane] = short_term(ln, p.eps0) - short_term(m.len[a.y], p.eps0);
+    }
+    if (lane < nt) {
+      const int4 t = m.tri[m.vtri[t0 + lane]];
+      if (CHECK)
+        folds = orient_sign(pos(m.xyi, t.x, v, q), pos(m.xyi, t.y, v, q),
+                            pos(m.xyi, t.z, v, q)) <= 0;
+      w.angle_d[lane] = triangle_angles(m.xyi, t, v, q, p.delta, p.polish) -
+                        triangle_angles(m.xyi, t, -1, q, p.delta, p.polish);
+    }
+    for (int h = lane; h < kHash; h += kWaveThreads) w.hkey[h] = -1;
+    if (CHECK && __ballot(folds) != 0) {
+      *wide_out = false;
+      __syncthreads();
+      return CCSP_MOVE_FOLDS;
+    }
+    __syncthreads();
+    // edges joining two neighbours, pairs (a, b), a < b, in row order; -1 where none
+    for (int pi = lane; pi < npair; pi += kWaveThreads) {
+      int a = 0, r = pi;
+      while (r >= deg - 1 - a) {
+        r -= deg - 1 - a;
+        ++a;
+      }
+      w.slot_e[deg + pi] = find_edge(m, w.nb[a], w.nb[a + 1 + r]);
+    }
+    // edges from a FREE neighbour F to a vertex that is not FREE, v or a neighbour of v
+    auto qualifies = [&](int C) {
+      if (C == v || m.vk[C].x == CCSP_VERTEX_FREE) return false;
+      for (int l = 0; l < deg; ++l)
+        if (w.nb[l] == C) return false;
+      return true;
+    };
+    if (lane < deg) {
+      const int F = w.nb[lane];
+      int k = 0;
+      if (m.vk[F].x == CCSP_VERTEX_FREE)
+        for (int r = m.adj_off[F], re = m.adj_off[F + 1]; r < re; ++r)
+          k += qualifies(m.adj[r].x) ? 1 : 0;
+      w.free_n[lane] = k;
+    }
+    __syncthreads();
+    if (lane == 0) {
+      int total = deg + npair;
+      for (int l = 0; l < deg; ++l) {
+        w.free_off[l] = total;
+        total += w.free_n[l];
+      }
+      w.n_slots = total <= kSlots ? total : -1;
+    }
+    __syncthreads();
+    const int ns = w.n_slots;
+    wide = ns < 0;
+    if (!wide) {
+      if (lane < deg && w.free_n[lane] > 0) {
+        const int F = w.nb[lane];
+        int k = w.free_off[lane];
+        for (int r = m.adj_off[F], re = m.adj_off[F + 1]; r < re; ++r)
+          if (qualifies(m.adj[r].x)) w.slot_e[k++] = m.adj[r].y;
+      }
+      __syncthreads();
+      // the new c of every C-edge (each listed once), into the slots and the table
+      for (int sl = lane; sl < ns; sl += kWaveThreads) {
+        const int e = w.slot_e[sl];
+        if (e < 0) continue;
+        const int2 ab = m.edge_v[e];
+        const bool ok = contractible_at(m, m.xyi, e, ab.x, ab.y, p.eps, v, q);
+        const double c = c_of_len(ok, sl < deg ? w.new_len[sl] : m.len[e], p.eps);
+        w.slot_c[sl] = c;
+        w.slot_ok[sl] = ok ? 1 : 0;
+        int h = (int)(group_hash((uint32_t)e) & (kHash - 1));
+        while (atomicCAS(&w.hkey[h], -1, e) != -1) h = (h + 1) & (kHash - 1);
+        w.hval[h] = c;
+      }
+      __syncthreads();
+      const MoveCtxT<1, true> ctx{m, m.xyi, p, v, q, w.nb, deg, nullptr, nullptr, w.hkey, w.hval};
+      for (int sl = lane; sl < ns; sl += kWaveThreads) {
+        const int e = w.slot_e[sl];
+        w.slot_v[sl] = e >= 0 ? ctx.visit(e) : 0.0;
+      }
+      __syncthreads();
+      if (lane == 0) {
+        double sa = 0.0, se = 0.0, ss = 0.0;
+        for (int t = 0; t < nt; ++t) sa += w.angle_d[t];
+        for (int k = 0; k < deg; ++k) {
+          se += w.slot_v[k];
+          ss += w.short_d[k];
+        }
+        for (int sl = deg; sl < ns; ++sl)
+          if (w.slot_e[sl] >= 0) se += w.slot_v[sl];
+        *df = se + p.mu_angle * sa + p.mu_len * ss;
+      }
+      *wide_out = false;
+      return CCSP_MOVE_OK;
+    }
+  }
+  *wide_out = true;
+  int st = CCSP_MOVE_OK;
+  if (lane == 0) {
+    double dfj = 0.0;
+    st = move_change<CHECK, 1>(m, m.xyi, p, v, q, MoveLds{w.fnb, w.fce, w.fcc}, &dfj);
+    if (st == CCSP_MOVE_OK) *df = dfj;
+    w.n_slots = st;
+  }
+  __syncthreads();
+  st = w.n_slots;
+  __syncthreads();
+  return st;
+}
+
+// Applies the move of wave_change (status CCSP_MOVE_OK): v's new position and the scratch the
+// move changes, from the wave's tables as refresh_scratch would write it (on lane 0 with
+// refresh_scratch for a wide vertex). Every lane calls it; ends with the workgroup in step.
+__device__ __forceinline__ void wave_commit(const MeshDev& m, const Par& p, int v, double2 q, WaveLds& w,
+                            int lane, bool wide) {
+  if (wide) {
+    if (lane == 0) {
+      m.xyi[v] = q;
+      refresh_scratch(m, p, v);
+    }
+    __syncthreads();
+    return;
+  }
+  const int deg = m.adj_off[v + 1] - m.adj_off[v];
+  const int ns = w.n_slots;
+  if (lane == 0) m.xyi[v] = q;
+  for (int sl = lane; sl < ns; sl += kWaveThreads) {
+    const int e = w.slot_e[sl];
+    if (e < 0) continue;
+    if (sl < deg) m.len[e] = w.new_len[sl];
+    m.contr[e] = w.slot_ok[sl];
+    m.c[e] = w.slot_c[sl];
+  }
+  __syncthreads();
+}
 
 // The move of every group that holds its claims, one wave (a workgroup) per group: its members
 // moved one after another by D (projected when constrained), each with its change of f against
-// the positions and scratch its predecessors left, so that the changes add up to the change of f
-// of the whole move; valid when every triangle of every member is strictly counter-clockwise at
-// the end; rejected or invalid moves are undone from xy_out, which holds the positions before
-// them. Per member the lanes list its C-edges (in move_change's order), compute each one's new c
-// into an LDS table, visit them (the same terms as move_change), and lane 0 adds the results in
-// that order, so the change of f is bit for bit move_change's; the C-edges' scratch is then
-// written as refresh_scratch would. A member with more than kLdsNbrs neighbours or kSlots
-// C-edges takes move_change and refresh_scratch on lane 0.
-__global__ void __launch_bounds__(kApplyThreads)
+// the positions and scratch its predecessors left (wave_change), so that the changes add up to the
+// change of f of the whole move; valid when every triangle of every member is strictly
+// counter-clockwise at the end; rejected or invalid moves are undone from xy_out, which holds the
+// positions before them.
+__global__ void __launch_bounds__(kWaveThreads)
 group_apply(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out, int n,
             const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
             const int32_t* __restrict__ mem, const double2* __restrict__ disp,
@@ -1307,18 +1446,7 @@ group_apply(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out, 
             uint8_t* __restrict__ done, double* __restrict__ delta,
             int32_t* __restrict__ status, int32_t* __restrict__ members,
             int32_t* __restrict__ round, unsigned long long* __restrict__ applied) {
-  __shared__ int wnb[kLdsNbrs];
-  __shared__ int slot_e[kSlots];
-  __shared__ double slot_c[kSlots];
-  __shared__ double slot_v[kSlots];
-  __shared__ uint8_t slot_ok[kSlots];
-  __shared__ double new_len[kLdsNbrs], short_d[kLdsNbrs], angle_d[kLdsNbrs];
-  __shared__ int free_n[kLdsNbrs], free_off[kLdsNbrs];
-  __shared__ int hkey[kHash];
-  __shared__ double hval[kHash];
-  __shared__ int fnb[kLdsNbrs], fce[kCache];
-  __shared__ double fcc[kCache];
-  __shared__ int n_slots;
+  __shared__ WaveLds w;
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   if (i >= n || !won[i]) return;
@@ -1330,125 +1458,14 @@ group_apply(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out, 
     const int v = M[j];
     const double2 o = m.xyi[v], dv = member_disp(m, v, D);
     const double2 q = make_double2(o.x + dv.x, o.y + dv.y);
-    const int a0 = m.adj_off[v], deg = m.adj_off[v + 1] - a0;
-    const int t0 = m.vtri_off[v], nt = m.vtri_off[v + 1] - t0;
-    const int npair = deg * (deg - 1) / 2;
-    bool wide = deg > kLdsNbrs || nt > kLdsNbrs || deg + npair > kSlots;
-    if (!wide) {
-      if (lane < deg) {
-        const int2 a = m.adj[a0 + lane];
-        wnb[lane] = a.x;
-        slot_e[lane] = a.y;
-        const int2 ab = m.edge_v[a.y];
-        const double ln = dist(pos(m.xyi, ab.x, v, q), pos(m.xyi, ab.y, v, q));
-        new_len[lane] = ln;
-        short_d[lane] = short_term(ln, p.eps0) - short_term(m.len[a.y], p.eps0);
-      }
-      if (lane < nt) {
-        const int4 t = m.tri[m.vtri[t0 + lane]];
-        angle_d[lane] = triangle_angles(m.xyi, t, v, q, p.delta, p.polish) -
-                        triangle_angles(m.xyi, t, -1, q, p.delta, p.polish);
-      }
-      for (int h = lane; h < kHash; h += kApplyThreads) hkey[h] = -1;
-      __syncthreads();
-      // edges joining two neighbours, pairs (a, b), a < b, in row order; -1 where none
-      for (int pi = lane; pi < npair; pi += kApplyThreads) {
-        int a = 0, r = pi;
-        while (r >= deg - 1 - a) {
-          r -= deg - 1 - a;
-          ++a;
-        }
-        slot_e[deg + pi] = find_edge(m, wnb[a], wnb[a + 1 + r]);
-      }
-      // edges from a FREE neighbour F to a vertex that is not FREE, v or a neighbour of v
-      auto qualifies = [&](int C) {
-        if (C == v || m.vk[C].x == CCSP_VERTEX_FREE) return false;
-        for (int l = 0; l < deg; ++l)
-          if (wnb[l] == C) return false;
-        return true;
-      };
-      if (lane < deg) {
-        const int F = wnb[lane];
-        int k = 0;
-        if (m.vk[F].x == CCSP_VERTEX_FREE)
-          for (int r = m.adj_off[F], re = m.adj_off[F + 1]; r < re; ++r)
-            k += qualifies(m.adj[r].x) ? 1 : 0;
-        free_n[lane] = k;
-      }
-      __syncthreads();
-      if (lane == 0) {
-        int total = deg + npair;
-        for (int l = 0; l < deg; ++l) {
-          free_off[l] = total;
-          total += free_n[l];
-        }
-        n_slots = total <= kSlots ? total : -1;
-      }
-      __syncthreads();
-      const int ns = n_slots;
-      wide = ns < 0;
-      if (!wide) {
-        if (lane < deg && free_n[lane] > 0) {
-          const int F = wnb[lane];
-          int k = free_off[lane];
-          for (int r = m.adj_off[F], re = m.adj_off[F + 1]; r < re; ++r)
-            if (qualifies(m.adj[r].x)) slot_e[k++] = m.adj[r].y;
-        }
-        __syncthreads();
-        // the new c of every C-edge (each listed once), into the slots and the table
-        for (int sl = lane; sl < ns; sl += kApplyThreads) {
-          const int e = slot_e[sl];
-          if (e < 0) continue;
-          const int2 ab = m.edge_v[e];
-          const bool ok = contractible_at(m, m.xyi, e, ab.x, ab.y, p.eps, v, q);
-          const double c = c_of_len(ok, sl < deg ? new_len[sl] : m.len[e], p.eps);
-          slot_c[sl] = c;
-          slot_ok[sl] = ok ? 1 : 0;
-          int h = (int)(group_hash((uint32_t)e) & (kHash - 1));
-          while (atomicCAS(&hkey[h], -1, e) != -1) h = (h + 1) & (kHash - 1);
-          hval[h] = c;
-        }
-        __syncthreads();
-        const MoveCtxT<1, true> ctx{m, m.xyi, p, v, q, wnb, deg, nullptr, nullptr, hkey, hval};
-        for (int sl = lane; sl < ns; sl += kApplyThreads) {
-          const int e = slot_e[sl];
-          slot_v[sl] = e >= 0 ? ctx.visit(e) : 0.0;
-        }
-        __syncthreads();
-        if (lane == 0) {
-          double sa = 0.0, se = 0.0, ss = 0.0;
-          for (int t = 0; t < nt; ++t) sa += angle_d[t];
-          for (int k = 0; k < deg; ++k) {
-            se += slot_v[k];
-            ss += short_d[k];
-          }
-          for (int sl = deg; sl < ns; ++sl)
-            if (slot_e[sl] >= 0) se += slot_v[sl];
-          df += se + p.mu_angle * sa + p.mu_len * ss;
-          m.xyi[v] = q;
-        }
-        for (int sl = lane; sl < ns; sl += kApplyThreads) {
-          const int e = slot_e[sl];
-          if (e < 0) continue;
-          if (sl < deg) m.len[e] = new_len[sl];
-          m.contr[e] = slot_ok[sl];
-          m.c[e] = slot_c[sl];
-        }
-        __syncthreads();
-        continue;
-      }
-    }
-    if (lane == 0) {
-      double dfj = 0.0;
-      move_change<false, 1>(m, m.xyi, p, v, q, MoveLds{fnb, fce, fcc}, &dfj);
-      df += dfj;
-      m.xyi[v] = q;
-      refresh_scratch(m, p, v);
-    }
-    __syncthreads();
+    double dfj = 0.0;
+    bool wide = false;
+    wave_change<false>(m, p, v, q, w, lane, &dfj, &wide);
+    if (lane == 0) df += dfj;
+    wave_commit(m, p, v, q, w, lane, wide);
   }
   bool ok = true;
-  for (int j = lane; j < nm && ok; j += kApplyThreads) {
+  for (int j = lane; j < nm && ok; j += kWaveThreads) {
     const int v = M[j];
     for (int k = m.vtri_off[v], end = m.vtri_off[v + 1]; k < end && ok; ++k) {
       const int4 tr = m.tri[m.vtri[k]];
@@ -1477,16 +1494,70 @@ group_apply(MeshDev m, Par p, double temperature, double2* __restrict__ xy_out, 
   }
   took = __ballot(took) != 0;
   if (took) {
-    for (int j = lane; j < nm; j += kApplyThreads) xy_out[m.vold[M[j]]] = m.xyi[M[j]];
+    for (int j = lane; j < nm; j += kWaveThreads) xy_out[m.vold[M[j]]] = m.xyi[M[j]];
     return;
   }
   // undo: every member back, then the scratch around them (lengths first; each edge's values
   // depend on the positions and lengths alone, so the lanes' order does not matter)
-  for (int j = lane; j < nm; j += kApplyThreads) m.xyi[M[j]] = xy_out[m.vold[M[j]]];
+  for (int j = lane; j < nm; j += kWaveThreads) m.xyi[M[j]] = xy_out[m.vold[M[j]]];
   __syncthreads();
-  for (int j = lane; j < nm; j += kApplyThreads) refresh_lengths(m, M[j]);
+  for (int j = lane; j < nm; j += kWaveThreads) refresh_lengths(m, M[j]);
   __syncthreads();
-  for (int j = lane; j < nm; j += kApplyThreads) refresh_rules(m, p, M[j]);
+  for (int j = lane; j < nm; j += kWaveThreads) refresh_rules(m, p, M[j]);
+}
+
+// One class of a sweep: Metropolis steps for its vertices (internal ids), which are pairwise more
+// than four edges apart, so that each move's reads (within four edges of its vertex) and writes
+// (its position, and scratch of edges within one edge of it) never meet another's. One wave (a
+// 64-thread workgroup) per vertex: every lane makes the vertex's proposal alike (the same loads),
+// and wave_change spreads its change of f over the lanes (bit for bit move_change's).
+// kind CCSP_PROPOSE_DISPLACE: the vertex moves by disp[i] (scaled by lambda * eta when lambda > 0);
+// the other kinds draw the new position from the vertex's neighbourhood with draws[2i], draws[2i+1]
+// (Secs. 3.2.4-3.2.6). Accepted moves are counted into *accepted when it is given.
+__global__ void __launch_bounds__(kWaveThreads)
+anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
+                  double2* __restrict__ xy_out, const int32_t* __restrict__ cls,
+                  const double2* __restrict__ disp, const double* __restrict__ u, int n,
+                  double* __restrict__ delta, int32_t* __restrict__ status,
+                  unsigned long long* __restrict__ accepted) {
+  __shared__ WaveLds w;
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= n) return;
+  const int v = cls[i];
+  const int cv = m.vold[v];
+  double2 q;
+  bool skip;
+  propose_move(m, p, lambda, kind, v, i, disp, &q, &skip);
+  double df = __builtin_huge_val();
+  int st = CCSP_MOVE_SKIPPED;
+  bool took = false;
+  if (!skip) {
+    if (!isfinite(q.x) || !isfinite(q.y)) {
+      st = CCSP_MOVE_BAD;
+    } else if (m.vk[v].x == CCSP_VERTEX_ORIGINAL) {
+      st = CCSP_MOVE_FIXED;
+    } else {
+      double dfl = 0.0;
+      bool wide = false;
+      st = wave_change<true>(m, p, v, q, w, lane, &dfl, &wide);
+      if (st == CCSP_MOVE_OK) {
+        df = __shfl(dfl, 0);
+        if (df <= 0.0 || u[i] < exp(-df / temperature)) {
+          wave_commit(m, p, v, q, w, lane, wide);
+          took = true;
+        } else {
+          st = CCSP_MOVE_REJECTED;
+        }
+      }
+    }
+  }
+  if (lane == 0) {
+    if (took) xy_out[cv] = q;
+    status[i] = st;
+    delta[i] = df;
+    if (took && accepted) atomicAdd(accepted, 1ull);
+  }
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -2252,7 +2323,7 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
     hipLaunchKernelGGL(ccsp::group_check, dim3(wb), dim3(T), 0, s, d, g, p, gcen,
                        (const double2*)draws, done, N, off, cnt, mem, disp, own_v, own_c, won);
     hipLaunchKernelGGL(ccsp::zero_counter, dim3(1), dim3(64), 0, s, applied);
-    hipLaunchKernelGGL(ccsp::group_apply, dim3((unsigned)N), dim3(ccsp::kApplyThreads), 0, s, d, p,
+    hipLaunchKernelGGL(ccsp::group_apply, dim3((unsigned)N), dim3(ccsp::kWaveThreads), 0, s, d, p,
                        temperature,
                        (double2*)xy, N, off, cnt, mem, disp, u, won, rnd, done, delta, status,
                        members, round, applied);
@@ -2314,8 +2385,8 @@ int anneal_sweep(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   for (size_t c = 0; c + 1 < off.size(); ++c) {
     const int n = (int)(off[c + 1] - off[c]);
     if (n == 0) continue;
-    hipLaunchKernelGGL(ccsp::anneal_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
-                       dim3(ccsp::kThreads), 0, s, d, p, temperature, 0.0,
+    hipLaunchKernelGGL(ccsp::anneal_class, dim3((unsigned)n), dim3(ccsp::kWaveThreads), 0, s,
+                       d, p, temperature, 0.0,
                        (int)CCSP_PROPOSE_DISPLACE, (double2*)xy, mesh->class_dev + off[c],
                        (const double2*)disp + off[c], u + off[c], n, delta + off[c],
                        status + off[c], (unsigned long long*)nullptr);
@@ -2347,8 +2418,8 @@ int anneal_propose(MovableMesh* mesh, double* xy, const ObjectiveParams* params,
   for (size_t c = 0; c + 1 < off.size(); ++c) {
     const int n = (int)(off[c + 1] - off[c]);
     if (n == 0) continue;
-    hipLaunchKernelGGL(ccsp::anneal_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
-                       dim3(ccsp::kThreads), 0, s, d, p, temperature, 0.0, (int)kind,
+    hipLaunchKernelGGL(ccsp::anneal_class, dim3((unsigned)n), dim3(ccsp::kWaveThreads), 0, s,
+                       d, p, temperature, 0.0, (int)kind,
                        (double2*)xy, mesh->class_dev + off[c],
                        (const double2*)draws + 2 * off[c], u + off[c], n, delta + off[c],
                        status + off[c], (unsigned long long*)nullptr);
@@ -2403,8 +2474,8 @@ int anneal_schedule(MovableMesh* mesh, double* xy, const ObjectiveParams* params
     for (size_t c = 0; c + 1 < off.size(); ++c) {
       const int n = (int)(off[c + 1] - off[c]);
       if (n == 0) continue;
-      hipLaunchKernelGGL(ccsp::anneal_class, dim3((n + ccsp::kThreads - 1) / ccsp::kThreads),
-                         dim3(ccsp::kThreads), 0, s, d, p, temperature[k], lam,
+      hipLaunchKernelGGL(ccsp::anneal_class, dim3((unsigned)n), dim3(ccsp::kWaveThreads), 0,
+                         s, d, p, temperature[k], lam,
                          (int)CCSP_PROPOSE_DISPLACE, (double2*)xy, mesh->class_dev + off[c],
                          xk + off[c], uk + off[c], n, delta + off[c], status + off[c], counter);
     }
