@@ -515,12 +515,13 @@ struct MoveLds {
   double* cc;
 };
 
-constexpr int kHash = 512;  // a wave's table of the changed c of one move (edge id -> c)
+constexpr int kHash = 256;  // a wave's table of one move's C-edges (edge id -> slot)
 
 // The context of one move's change of f. S is the stride of the LDS columns (a thread's own
 // columns in a workgroup of kThreads, or 1 for a wave's shared ones). Without WAVE, the changed c
 // of a C-edge is computed on first use into the thread's cache; with WAVE, the wave has computed
-// every C-edge's changed c beforehand into an open-addressing table (hkey, hval).
+// every C-edge's changed c beforehand into its slot (hc), found through an open-addressing table
+// (hkey, hslot).
 template <int S, bool WAVE>
 struct MoveCtxT {
   const MeshDev& m;
@@ -532,8 +533,9 @@ struct MoveCtxT {
   int deg;
   int* ce;        // the move's cache of changed c: edge ids (-1 empty) and values
   double* cc;
-  const int* hkey;      // WAVE: table keys (-1 empty) and values
-  const double* hval;
+  const int* hkey;      // WAVE: table keys (-1 empty), their slots, and the slots' c
+  const uint16_t* hslot;
+  const double* hc;
 
   __device__ __forceinline__ bool adjacent(int x) const {
     if (deg > kLdsNbrs) return is_neighbour(m, v, x);
@@ -563,7 +565,7 @@ struct MoveCtxT {
     if constexpr (WAVE) {
       int h = (int)(group_hash((uint32_t)e) & (kHash - 1));
       for (int k = 0; k < kHash; ++k, h = (h + 1) & (kHash - 1))
-        if (hkey[h] == e) return hval[h];
+        if (hkey[h] == e) return hc[hslot[h]];
       return __builtin_nan("");  // not reached: the table holds every C-edge
     } else {
       const int slot = (e & (kCache - 1)) * S;
@@ -641,7 +643,8 @@ __device__ __forceinline__ int move_change(const MeshDev& m, const double2* __re
     for (int j = 0; j < deg; ++j) lds.nb[j * S] = m.adj[a0 + j].x;
 #pragma unroll
   for (int k = 0; k < kCache; ++k) lds.ce[k * S] = -1;
-  const MoveCtxT<S, false> ctx{m, xy, p, v, q, lds.nb, deg, lds.ce, lds.cc, nullptr, nullptr};
+  const MoveCtxT<S, false> ctx{m,      xy,     p,      v,      q,      lds.nb,
+                               deg,    lds.ce, lds.cc, nullptr, nullptr, nullptr};
   double se = 0.0, ss = 0.0;
   for (int j = a0, end = a0 + deg; j < end; ++j) {
     const int e = m.adj[j].y;
@@ -1252,7 +1255,7 @@ group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
   if (lane == 0) won[i] = all ? 1 : 0;
 }
 
-constexpr int kSlots = 384;    // C-edges of one move that a wave's tables hold
+constexpr int kSlots = 160;    // C-edges of one move that a wave's tables hold
 constexpr int kWaveThreads = 64;  // kernels that spread one move over a wave (a workgroup)
 
 // A wave's LDS for one move (see wave_change).
@@ -1265,7 +1268,7 @@ struct WaveLds {
   double new_len[kLdsNbrs], short_d[kLdsNbrs], angle_d[kLdsNbrs];
   int free_n[kLdsNbrs], free_off[kLdsNbrs];
   int hkey[kHash];
-  double hval[kHash];
+  uint16_t hslot[kHash];
   int fnb[kLdsNbrs], fce[kCache];
   double fcc[kCache];
   int n_slots;
@@ -1368,10 +1371,11 @@ __device__ __forceinline__ int wave_change(const MeshDev& m, const Par& p, int v
         w.slot_ok[sl] = ok ? 1 : 0;
         int h = (int)(group_hash((uint32_t)e) & (kHash - 1));
         while (atomicCAS(&w.hkey[h], -1, e) != -1) h = (h + 1) & (kHash - 1);
-        w.hval[h] = c;
+        w.hslot[h] = (uint16_t)sl;
       }
       __syncthreads();
-      const MoveCtxT<1, true> ctx{m, m.xyi, p, v, q, w.nb, deg, nullptr, nullptr, w.hkey, w.hval};
+      const MoveCtxT<1, true> ctx{m,       m.xyi,   p,      v,       q,        w.nb,
+                                  deg,     nullptr, nullptr, w.hkey, w.hslot, w.slot_c};
       for (int sl = lane; sl < ns; sl += kWaveThreads) {
         const int e = w.slot_e[sl];
         w.slot_v[sl] = e >= 0 ? ctx.visit(e) : 0.0;
