@@ -105,8 +105,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the walk shards by "
-                                   "replicating the scene and splitting rays (see DESIGN.md)",
+        print(json.dumps({"error": "bench.py runs on one GPU only; the walk would shard by "
+                                   "replicating the scene on every GPU and splitting the rays",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
