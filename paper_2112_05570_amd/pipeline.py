@@ -97,6 +97,10 @@ class Schedule:
     flip_rounds: int = 64
     outer_max: int = 12
     seed: int = 0
+    # group stages move the groups of a random share of the movable vertices: every vertex as a
+    # centre costs far more than a single-vertex sweep (groups of tens of members, in rounds), and
+    # Sec. 3.3.2 balances the perturbation types by the time they take
+    group_share: float = 1.0 / 32
 
 
 @dataclass
@@ -113,8 +117,8 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
     """Turn a subdivided triangulation into a low-weight one (Secs. 3.1-3.4):
     1. `stages` stages of annealing: each one displacement sweep with the adaptive step scale
        (Secs. 3.2, 3.2.2) and one sweep of resampling, contraction, swap or group moves in turn
-       (Secs. 3.2.3-3.2.6; group moves with the displacement's step scale), at the stage's
-       temperature and contraction length;
+       (Secs. 3.2.3-3.2.6; group moves with the displacement's step scale, centred at a random
+       `group_share` of the movable vertices), at the stage's temperature and contraction length;
     2. contraction of the edges shorter than the final length (Sec. 3.4.1);
     3. polishing sweeps without fuzzy contraction alternated with greedy flips (the weight as
        energy, T = 0) (Sec. 3.4.2);
@@ -157,6 +161,7 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
     X = torch.from_numpy(np.array(xy, dtype=np.float64)).to(dev)
     with MovableMesh(tri_v, kind, line, prim_v) as gm:
         m = gm.n_movable()
+        movable = torch.from_numpy(np.ascontiguousarray(gm.movable, dtype=np.int32)).to(dev)
         lam, acc = s.lambda0, []
         for k in range(s.stages):
             p = objective_params(epss[k], None, *mu)
@@ -166,13 +171,16 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
             lam = lam * min(2.0, max(0.5, 1.0 + (frac - s.target)))
             kind_k = ("resample", "contract", "swap", "group")[k % 4]
             if kind_k == "group":
-                r = proposal_draws(m, "group")
-                r[:, :2] = unit_draws(m)
-                _, st, _, _ = gm.group_sweep(X, p, temps[k], lam, r, uniforms(m))
+                n_c = max(1, int(m * s.group_share))
+                pick = torch.randperm(m, generator=gen, device=dev)[:n_c]
+                cen = movable[pick].contiguous()
+                r = proposal_draws(n_c, "group")
+                r[:, :2] = unit_draws(n_c)
+                _, st, _, _ = gm.group_sweep(X, p, temps[k], lam, r, uniforms(n_c), centres=cen)
             else:
                 _, st = gm.propose(X, p, temps[k], kind_k, proposal_draws(m, kind_k),
                                    uniforms(m))
-            acc.append([frac, int((st == 1).sum().item()) / m])
+            acc.append([frac, int((st == 1).sum().item()) / st.shape[0]])
             if verbose:
                 f = gm.eval(X, p).cpu().tolist()
                 print(f"[optimise] stage {k}: T {temps[k]:.3g} eps {epss[k]:.3g} "
