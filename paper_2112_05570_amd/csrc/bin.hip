@@ -21,6 +21,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "decide.hpp"
+#include "scan.hpp"
 #include "walk.hpp"
 
 namespace ccsp {
@@ -190,12 +191,7 @@ int bits_for(int64_t v) {  // smallest b with v < 2^b
 
 int n_chunks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
 
-size_t scan_temp_bytes(size_t items) {
-  size_t temp = 0;
-  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, temp, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                         (int)items);
-  return temp;
-}
+size_t scan_temp_bytes(size_t items) { return exclusive_scan_bytes((int64_t)items); }
 
 size_t sort_temp_bytes(int64_t n) {
   size_t temp = 0;
@@ -259,7 +255,6 @@ hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void
   p += align256(sizeof(uint32_t) * items);
   uint32_t* Hoff = reinterpret_cast<uint32_t*>(p);
   p += align256(sizeof(uint32_t) * items);
-  size_t temp_bytes = align256(scan_temp_bytes(items));
   BinGeom g;
   const double cells = (double)(1 << kGridBits);
   g.x0 = sc.box_x0;
@@ -269,7 +264,7 @@ hipError_t launch_bin_rays(const SceneDev& sc, const RaysDev& in, int kind, void
   hipLaunchKernelGGL(bucket_count, dim3(nch), dim3(kThreads), 0, stream, in.o, n, g, H, nch);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = hipcub::DeviceScan::ExclusiveSum(p, temp_bytes, H, Hoff, (int)items, stream);
+  e = launch_exclusive_scan(H, Hoff, (int64_t)items, reinterpret_cast<uint32_t*>(p), stream);
   if (e != hipSuccess) return e;
   if (stats)
     hipLaunchKernelGGL(bucket_scatter<true>, dim3(nch), dim3(kThreads), 0, stream, in.o, in.d,

@@ -1570,17 +1570,28 @@ fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
   if (i < n) a[i] = v;
 }
 
-// Bounding box of the positions (one workgroup; out: min x, min y, max x, max y).
+// Bounding box of the positions: each workgroup reduces a grid-stride share of the vertices into
+// part[4 * blockIdx.x ..] (min x, min y, max x, max y); with part == out and one workgroup over
+// nparts partial boxes instead (nparts > 0), the final box.
 __global__ void __launch_bounds__(kThreads)
-bbox_kernel(MeshDev m, double* __restrict__ out) {
+bbox_kernel(MeshDev m, const double* __restrict__ in, int nparts, double* __restrict__ out) {
   __shared__ double sh[4][kThreads];
   double a = __builtin_huge_val(), b = a, c = -a, e = -a;
-  for (int v = threadIdx.x; v < m.nv; v += kThreads) {
-    const double2 q = m.xyi[v];
-    a = fmin(a, q.x);
-    b = fmin(b, q.y);
-    c = fmax(c, q.x);
-    e = fmax(e, q.y);
+  if (nparts == 0) {
+    for (int v = blockIdx.x * kThreads + threadIdx.x; v < m.nv; v += gridDim.x * kThreads) {
+      const double2 q = m.xyi[v];
+      a = fmin(a, q.x);
+      b = fmin(b, q.y);
+      c = fmax(c, q.x);
+      e = fmax(e, q.y);
+    }
+  } else {
+    for (int k = threadIdx.x; k < nparts; k += kThreads) {
+      a = fmin(a, in[4 * k]);
+      b = fmin(b, in[4 * k + 1]);
+      c = fmax(c, in[4 * k + 2]);
+      e = fmax(e, in[4 * k + 3]);
+    }
   }
   sh[0][threadIdx.x] = a;
   sh[1][threadIdx.x] = b;
@@ -1596,7 +1607,7 @@ bbox_kernel(MeshDev m, double* __restrict__ out) {
     }
     __syncthreads();
   }
-  if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x < 4) out[4 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ void zero_counter(unsigned long long* __restrict__ c) {
@@ -2232,10 +2243,12 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   GroupScratch gs;
   double* box = nullptr;
   unsigned long long* applied = nullptr;
-  hipError_t e = gs.get(&box, 4);
+  const int nbox = grid_for(d.nv);  // workgroups of the bounding-box pass
+  hipError_t e = gs.get(&box, 4 * (size_t)nbox + 4);
   if (e == hipSuccess) e = gs.get(&applied, 1);
   if (e != hipSuccess) return fail(CCSP_E_OOM, "anneal_group: scratch allocation failed");
-  hipLaunchKernelGGL(ccsp::bbox_kernel, dim3(1), dim3(T), 0, s, d, box);
+  hipLaunchKernelGGL(ccsp::bbox_kernel, dim3(nbox), dim3(T), 0, s, d, nullptr, 0, box + 4);
+  hipLaunchKernelGGL(ccsp::bbox_kernel, dim3(1), dim3(T), 0, s, d, box + 4, nbox, box);
   double hb[4];
   e = hipMemcpyAsync(hb, box, sizeof hb, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -24,7 +24,6 @@
 // Compiled with -ffp-contract=off: the error bound and the hit distance assume every operation
 // is rounded separately.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <atomic>
@@ -38,6 +37,7 @@
 #include <vector>
 
 #include "ccsp_tet.h"
+#include "scan.hpp"
 
 namespace ccsp {
 void set_last_error(const char* msg);
@@ -548,8 +548,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 size_t bin_bytes(int64_t n, size_t* scan_tmp) {
   const int64_t nchunks = (n + kBinChunk - 1) / kBinChunk;
   const size_t cnt = (size_t)kMaxBuckets * (size_t)nchunks;
-  size_t tmp = 0;
-  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (uint32_t*)nullptr, (uint32_t*)nullptr, (int)cnt);
+  const size_t tmp = ccsp::exclusive_scan_bytes((int64_t)cnt);
   if (scan_tmp) *scan_tmp = tmp;
   return 2 * align256(cnt * sizeof(uint32_t)) + align256(tmp) + align256((size_t)n * sizeof(RayRec3));
 }
@@ -864,7 +863,8 @@ int trace_rays3d(const TetMesh* mesh, const int32_t* o, const int32_t* d, const 
     if (bin) {
       const int nbk = dirs ? kMaxBuckets : kCells;
       hipLaunchKernelGGL(bin_count, dim3(nchunks), dim3(kBinThreads), 0, st, o, d, n, dirs, nbk, H, nchunks);
-      e = hipcub::DeviceScan::ExclusiveSum(scan_tmp, tmp, H, Hoff, nbk * nchunks, st);
+      e = ccsp::launch_exclusive_scan(H, Hoff, (int64_t)nbk * nchunks,
+                                      static_cast<uint32_t*>(scan_tmp), st);
       if (e != hipSuccess) return hip_fail(e, "bucket scan");
       hipLaunchKernelGGL(bin_scatter, dim3(nchunks), dim3(kBinThreads), 0, st, mesh->first,
                          (int32_t)mesh->nt, io, dirs, nbk, Hoff, nchunks, recs);
