@@ -235,7 +235,8 @@ int anneal_propose(MovableMesh *mesh, double *xy, const ObjectiveParams *params,
  * ORIGINAL vertex of more than 32 neighbours, neither moving a vertex into or out of the other's
  * disc), so the result equals the sequential chain over the centres in the order of increasing
  * (round[i], i). xy (DEVICE) is updated in place. Allocates its scratch (about 30 bytes per
- * centre, 24 per member of the round's pending groups, 8 per vertex and 12 per grid cell) and
+ * centre, 24 per member of the round's pending groups, 8 per vertex, 8 per cell of the query
+ * grid and 4 per cell of the claims' grid, at most 64 MiB) and
  * synchronises `stream` once per round; overwrites the mesh's scratch.
  */
 int anneal_group(MovableMesh *mesh, double *xy, const ObjectiveParams *params, double temperature,

@@ -978,6 +978,18 @@ __device__ __forceinline__ void for_cells(const VGrid& g, double2 q, double r, F
     for (int cx = x0; cx <= x1; ++cx) f(cy * g.gx + cx);
 }
 
+// f(cell) for every cell meeting the square of half-side r around q, spread over a wave's lanes.
+template <class F>
+__device__ __forceinline__ void for_cells_lanes(const VGrid& g, double2 q, double r, int lane,
+                                                F&& f) {
+  const int x0 = clamp_cell((q.x - r - g.x0) * g.inv, g.gx);
+  const int x1 = clamp_cell((q.x + r - g.x0) * g.inv, g.gx);
+  const int y0 = clamp_cell((q.y - r - g.y0) * g.inv, g.gy);
+  const int y1 = clamp_cell((q.y + r - g.y0) * g.inv, g.gy);
+  const int w = x1 - x0 + 1, count = w * (y1 - y0 + 1);
+  for (int k = lane; k < count; k += 64) f((y0 + k / w) * g.gx + x0 + k % w);
+}
+
 // f(w) for every movable vertex w != c with dist(p_c, p_w) <= d (the distance as for edges).
 template <class F>
 __device__ __forceinline__ void for_members(const MeshDev& m, const VGrid& g, int c, double d,
@@ -1124,7 +1136,8 @@ __device__ __forceinline__ int member_pos(const MeshDev& m, const int* __restric
 // member, and make the claims; lane 0 adds the group's area in member order (the same sum as one
 // thread taking the members one after another).
 __global__ void __launch_bounds__(kThreads)
-group_claim(MeshDev m, VGrid g, Par p, double lambda, const int32_t* __restrict__ gcen,
+group_claim(MeshDev m, VGrid g, VGrid gc, Par p, double lambda,
+            const int32_t* __restrict__ gcen,
             const double2* __restrict__ draws, const uint8_t* __restrict__ done, int n,
             const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
             int32_t* __restrict__ mem, int32_t* __restrict__ key, int32_t* __restrict__ tmpm,
@@ -1208,12 +1221,12 @@ group_claim(MeshDev m, VGrid g, Par p, double lambda, const int32_t* __restrict_
   const double2 D = disp[i];
   const uint32_t pri = group_priority(i);
   auto claim_c = [&](int cell) { atomicMin(&own_c[cell], pri); };
-  if (lane == 0) for_cells(g, m.xyi[c], d * kQueryWiden, claim_c);
+  for_cells_lanes(gc, m.xyi[c], d * kQueryWiden, lane, claim_c);
   for (int j = lane; j < nm; j += 64) {
     const int v = M[j];
     const double2 o = m.xyi[v], dv = member_disp(m, v, D);
-    claim_c(cell_of(g, o));
-    claim_c(cell_of(g, make_double2(o.x + dv.x, o.y + dv.y)));
+    claim_c(cell_of(gc, o));
+    claim_c(cell_of(gc, make_double2(o.x + dv.x, o.y + dv.y)));
     for_hops2(m, v, [&](int x) { atomicMin(&own_v[x], pri); });
   }
 }
@@ -1222,7 +1235,7 @@ group_claim(MeshDev m, VGrid g, Par p, double lambda, const int32_t* __restrict_
 // within three edges of its members carries a lower priority (no position changes during this
 // pass). The lanes take the members; the wave's vote decides.
 __global__ void __launch_bounds__(kThreads)
-group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
+group_check(MeshDev m, VGrid gc, Par p, const int32_t* __restrict__ gcen,
             const double2* __restrict__ draws, const uint8_t* __restrict__ done, int n,
             const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
             const int32_t* __restrict__ mem, const double2* __restrict__ disp,
@@ -1238,17 +1251,15 @@ group_check(MeshDev m, VGrid g, Par p, const int32_t* __restrict__ gcen,
   bool ok = true;
   const uint32_t pri = group_priority(i);
   auto held_c = [&](int cell) { ok = ok && own_c[cell] == pri; };
-  if (lane == 0) {
-    const double d = (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps;
-    for_cells(g, m.xyi[gcen[i]], d * kQueryWiden, held_c);
-  }
+  const double d = (0.5 + 4.5 * draws[2 * i + 1].x) * p.eps;
+  for_cells_lanes(gc, m.xyi[gcen[i]], d * kQueryWiden, lane, held_c);
   const int* M = mem + off[i];
   const double2 D = disp[i];
   for (int j = lane; j < cnt[i] && ok; j += 64) {
     const int v = M[j];
     const double2 o = m.xyi[v], dv = member_disp(m, v, D);
-    held_c(cell_of(g, o));
-    held_c(cell_of(g, make_double2(o.x + dv.x, o.y + dv.y)));
+    held_c(cell_of(gc, o));
+    held_c(cell_of(gc, make_double2(o.x + dv.x, o.y + dv.y)));
     for_hops3(m, v, [&](int x) { ok = ok && own_v[x] >= pri; });
   }
   const bool all = __ballot(!ok) == 0;
@@ -2266,6 +2277,15 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   if (!(g.gx >= 1)) g.gx = 1;
   if (!(g.gy >= 1)) g.gy = 1;
   const int ncells = g.gx * g.gy;
+  // the claims' grid: cells a quarter of the query grid's side, at most 4096 per side (groups
+  // whose discs only share a coarse cell then do not conflict)
+  ccsp::VGrid gc = g;
+  gc.inv = 4.0 * g.inv;
+  gc.gx = (int)std::min(4096.0, std::max(1.0, std::floor((hb[2] - gc.x0) * gc.inv) + 1.0));
+  gc.gy = (int)std::min(4096.0, std::max(1.0, std::floor((hb[3] - gc.y0) * gc.inv) + 1.0));
+  if (!(gc.gx >= 1)) gc.gx = 1;
+  if (!(gc.gy >= 1)) gc.gy = 1;
+  const int nclaim = gc.gx * gc.gy;
   int32_t *gcen = nullptr, *cnt = nullptr, *off = nullptr, *start = nullptr, *cursor = nullptr;
   int32_t *vert = nullptr, *mem = nullptr, *key = nullptr, *tmpm = nullptr, *tmpk = nullptr;
   uint64_t* first = nullptr;
@@ -2279,7 +2299,7 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
   if (e == hipSuccess) e = gs.get(&cursor, (size_t)ncells + 1);
   if (e == hipSuccess) e = gs.get(&vert, d.nv);
   if (e == hipSuccess) e = gs.get(&own_v, d.nv);
-  if (e == hipSuccess) e = gs.get(&own_c, ncells);
+  if (e == hipSuccess) e = gs.get(&own_c, nclaim);
   if (e == hipSuccess) e = gs.get(&done, N);
   if (e == hipSuccess) e = gs.get(&won, N);
   if (e == hipSuccess) e = gs.get(&disp, N);
@@ -2331,13 +2351,13 @@ int anneal_group(MovableMesh* mesh, double* xy, const ObjectiveParams* params, d
     // claims, their check, and the moves of the groups holding all of theirs
     hipLaunchKernelGGL(ccsp::fill_i32, dim3(vb), dim3(T), 0, s, reinterpret_cast<int32_t*>(own_v),
                        (int64_t)d.nv, -1);
-    hipLaunchKernelGGL(ccsp::fill_i32, dim3((ncells + T - 1) / T), dim3(T), 0, s,
-                       reinterpret_cast<int32_t*>(own_c), (int64_t)ncells, -1);
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3((nclaim + T - 1) / T), dim3(T), 0, s,
+                       reinterpret_cast<int32_t*>(own_c), (int64_t)nclaim, -1);
     const unsigned wb = (unsigned)((N + T / 64 - 1) / (T / 64));  // one wave per group
-    hipLaunchKernelGGL(ccsp::group_claim, dim3(wb), dim3(T), 0, s, d, g, p, lambda, gcen,
+    hipLaunchKernelGGL(ccsp::group_claim, dim3(wb), dim3(T), 0, s, d, g, gc, p, lambda, gcen,
                        (const double2*)draws, done, N, off, cnt, mem, key, tmpm, tmpk, first, disp,
                        own_v, own_c);
-    hipLaunchKernelGGL(ccsp::group_check, dim3(wb), dim3(T), 0, s, d, g, p, gcen,
+    hipLaunchKernelGGL(ccsp::group_check, dim3(wb), dim3(T), 0, s, d, gc, p, gcen,
                        (const double2*)draws, done, N, off, cnt, mem, disp, own_v, own_c, won);
     hipLaunchKernelGGL(ccsp::zero_counter, dim3(1), dim3(64), 0, s, applied);
     hipLaunchKernelGGL(ccsp::group_apply, dim3((unsigned)N), dim3(ccsp::kWaveThreads), 0, s, d, p,
