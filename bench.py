@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--scene", default="grid",
                     help="pipeline: 'grid', or 'lines:N' for N random segments drawn as in the "
                          "large scene")
+    ap.add_argument("--pipeline-rounds", type=int, default=1,
+                    help="pipeline: rounds of subdivision and optimisation (2 = the iterated "
+                         "strategy with one intermediate subdivision)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the checker leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-objective", action="store_true",
@@ -133,7 +136,8 @@ def main():
         sc = (sg.make_scene("grid", seed=0) if args.scene == "grid"
               else sg.make_scene("large", seed=0, n_seg=int(args.scene.split(":")[1])))
         rays = sg.sample_rays(sc, args.rays or (1 << 20), seed=0)
-        print(json.dumps(pipeline_leg(sc, rays, verbose=True)), flush=True)
+        print(json.dumps(pipeline_leg(sc, rays, verbose=True, rounds=args.pipeline_rounds)),
+              flush=True)
         return
     if args.workload == "flips":
         sc = sg.make_scene("grid", seed=0)
@@ -514,14 +518,16 @@ def grid_triangulations(sc, rays, scene, o, d, st, out, steps):
     return res
 
 
-def pipeline_leg(sc, rays, stages=24, verbose=False, schedule=None):
+def pipeline_leg(sc, rays, stages=24, verbose=False, schedule=None, rounds=1):
     """The paper's low-weight pipeline on a scene (``paper_2112_05570_amd.pipeline.optimise``:
     annealing with every single-vertex proposal, contraction, polishing and greedy flips, raised
     contraction lengths) from its CDT subdivided once (Sec. 3.5.2), then the CDT and the result
     walked by the same rays (origins located in the result by the library's point location).
     Returns weights, counts, times and the walk comparison: steps per ray, trace time, the share
     of rays hitting the same original primitive, and the largest relative difference of t (the
-    result's constrained edges are sub-segments of the primitives, collinear to rounding)."""
+    result's constrained edges are sub-segments of the primitives, collinear to rounding). With
+    rounds > 1, the iterated strategy of Sec. 3.5.3 (``pipeline.optimise_iterated``) from the CDT,
+    reporting the lightest round and each round's weight."""
     import numpy as np
     import torch
 
@@ -533,8 +539,13 @@ def pipeline_leg(sc, rays, stages=24, verbose=False, schedule=None):
     t0 = time.perf_counter()
     mesh = subdivided(sc)
     t_sub = time.perf_counter() - t0
-    r = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, size,
-                    schedule or pl.Schedule(stages=stages), verbose=verbose)
+    if rounds > 1:
+        xy0, tv0, kd0, ln0, pv0 = sg.movable_input(sc)
+        r = pl.optimise_iterated(tv0, kd0, ln0, pv0, xy0, size,
+                                 schedule or pl.Schedule(stages=stages), rounds, verbose=verbose)
+    else:
+        r = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, size,
+                        schedule or pl.Schedule(stages=stages), verbose=verbose)
     res = {"subdivided": {"vertices": mesh.n_vertices, "triangles": mesh.n_triangles,
                           "weight": r.log["weight_start"], "subdivide_s": t_sub},
            "stages": stages, "anneal_s": r.log["anneal_s"],
@@ -544,6 +555,12 @@ def pipeline_leg(sc, rays, stages=24, verbose=False, schedule=None):
            "final": {"vertices": int(r.xy.shape[0]), "triangles": int(r.tri_v.shape[0]),
                      "steiner_vertices": int((r.kind != 0).sum()), "weight": r.log["weight_final"]},
            "total_s": time.perf_counter() - t0}
+    if rounds > 1:
+        res["rounds"] = [{"subdivided_vertices": g["subdivided_vertices"],
+                          "vertices": g["vertices"], "weight": g["weight_final"],
+                          "anneal_s": g["anneal_s"], "contract_polish_s": g["contract_polish_s"]}
+                         for g in r.log["rounds"]]
+        res["rounds_stopped"] = r.log["stopped"]
     nbr, prim, prims, sub_to_orig = pl.walk_arrays(r.tri_v, r.kind, r.line, mesh.prim_v, r.xy)
     dev = torch.device("cuda:0")
     o = torch.from_numpy(rays.o).to(dev)

@@ -10,11 +10,11 @@ counter-clockwise triangles, vertex kinds (0 original, 1 constrained to original
 from __future__ import annotations
 
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-from . import MovableMesh, contract, flip_anneal, objective_params
+from . import MovableMesh, contract, flip_anneal, objective_params, subdivide
 
 ORIGINAL, CONSTRAINED, FREE = 0, 1, 2
 
@@ -246,4 +246,43 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
     log["contract_polish"] = hist
     log["weight_final"] = best_w
     best.log = log
+    return best
+
+
+def optimise_iterated(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = None,
+                      rounds: int = 2, verbose=False) -> Result:
+    """The iterated strategy of Sec. 3.5.3: `rounds` times, subdivide the current triangulation
+    (Sec. 3.5.2; the first round starts from the given one, normally the CDT, whose vertices are
+    all ORIGINAL, so that there is nothing to move without it) and run `optimise` on the result.
+    Round k uses the schedule's seed + k. Returns the lightest of the rounds' results (keeping the
+    lightest, as the contraction rounds of Sec. 3.4.2 do: a later round starts from a subdivision,
+    which is heavier, and need not end lighter), with each round's log in log["rounds"]. When a
+    later round's subdivision is not valid (a sub-triangle not strictly counter-clockwise after
+    rounding), the strategy stops there and log["stopped"] says why."""
+    from .binding import CcspError
+
+    s = schedule or Schedule()
+    prim_v = np.ascontiguousarray(prim_v, dtype=np.int32).reshape(-1, 2)
+    tv, kd, ln, pos = tri_v, kind, line, np.asarray(xy, dtype=np.float64)
+    best, logs, stopped = None, [], None
+    for k in range(rounds):
+        try:
+            tv2, kd2, ln2, pv2, pos2 = subdivide(tv, kd, ln, prim_v, pos)
+        except CcspError as err:
+            # an optimised triangulation can hold slivers (vertices on one original edge up to
+            # rounding) whose midpoints round across an edge; the strategy then ends here
+            if best is None:
+                raise
+            stopped = f"round {k}: {err}"
+            break
+        r = optimise(tv2, kd2, ln2, pv2, pos2, size, replace(s, seed=s.seed + k), verbose)
+        logs.append(dict(r.log, subdivided_vertices=int(pos2.shape[0]),
+                         vertices=int(r.xy.shape[0])))
+        if verbose:
+            print(f"[optimise] round {k}: {pos2.shape[0]} vertices subdivided, weight "
+                  f"{r.log['weight_final']:.1f}", flush=True)
+        if best is None or r.log["weight_final"] < best.log["weight_final"]:
+            best = r
+        tv, kd, ln, pos = r.tri_v, r.kind, r.line, r.xy
+    best.log = dict(best.log, rounds=logs, stopped=stopped)
     return best

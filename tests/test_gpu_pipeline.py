@@ -141,3 +141,41 @@ def test_other_scenes_and_seeds(ccsp, name, kw, seed):
     mapped = np.where(g[0] >= 0, s2o[np.maximum(g[0], 0)], g[0])
     _assert_chains(prims, s2o, mesh.prim_v, mesh.xy)
     assert np.array_equal(mapped, cdt[0]), np.nonzero(mapped != cdt[0])[0][:5]
+
+
+def test_iterated_strategy(ccsp):
+    """Sec. 3.5.3's iterated strategy, two rounds of subdivision and optimisation on the tiny
+    scene: the second round starts from the first result subdivided (so it has more vertices than
+    that result), the returned triangulation is the lighter round's and is valid, keeps the original
+    vertices, and the GPU walk on it equals the checker's on a sample of located rays."""
+    from paper_2112_05570_amd import pipeline as pl
+    sc = sg.make_scene("tiny")
+    xy, tv, kd, ln, pv = sg.movable_input(sc)
+    size = sc.box[1] - sc.box[0]
+    sched = pl.Schedule(stages=6, t0_rel=1e-3, t1_rel=1e-5, e0_rel=2e-2, e1_rel=2e-3,
+                        outer_max=2, flip_rounds=16, seed=11)
+    r = pl.optimise_iterated(tv, kd, ln, pv, xy, size, sched, rounds=2)
+    logs = r.log["rounds"]
+    assert len(logs) == 2
+    w = [g["weight_final"] for g in logs]
+    assert r.log["weight_final"] == min(w)
+    assert logs[1]["subdivided_vertices"] > logs[0]["vertices"]
+    nbr, prim, prims, s2o = pl.walk_arrays(r.tri_v, r.kind, r.line, pv, r.xy)
+    tri = oracle.Triangulation(r.xy, r.tri_v, nbr, prim, prims)
+    assert oracle.validate(tri) == ""
+    assert (r.kind == 0).sum() == sc.n_vertices and np.array_equal(r.xy[r.kind == 0], sc.xy)
+    assert r.log["weight_final"] == pl.weight(r.tri_v, r.xy)
+    rays = sg.sample_rays(sc, 4096, seed=13)
+    with ccsp.Scene(r.xy, r.tri_v, nbr, prim, prims) as s_opt:
+        o = torch.from_numpy(rays.o).to(DEV)
+        d = torch.from_numpy(rays.d).to(DEV)
+        st, stat = ccsp.locate(s_opt, o)
+        keep = torch.nonzero(stat == 0).squeeze(1)
+        got = ccsp.trace(s_opt, o[keep].contiguous(), d[keep].contiguous(),
+                         st[keep].contiguous(), precision="fp64")
+        torch.cuda.synchronize()
+        g = [x.cpu().numpy() for x in (got.hit_prim, got.hit_t, got.steps)]
+    k = keep.cpu().numpy()
+    assert k.shape[0] > 4000
+    ref = oracle.walk(tri, rays.o[k], rays.d[k], st.cpu().numpy()[k])
+    assert all(np.array_equal(a, b) for a, b in zip(g, ref))
