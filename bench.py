@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--pipeline-rounds", type=int, default=1,
                     help="pipeline: rounds of subdivision and optimisation (2 = the iterated "
                          "strategy with one intermediate subdivision)")
+    ap.add_argument("--balance-sweeps", type=int, default=0,
+                    help="pipeline: sweeps per stage with perturbation types drawn for equal time "
+                         "(0: a displacement sweep and the next proposal type in turn)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the checker leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-objective", action="store_true",
@@ -136,8 +139,10 @@ def main():
         sc = (sg.make_scene("grid", seed=0) if args.scene == "grid"
               else sg.make_scene("large", seed=0, n_seg=int(args.scene.split(":")[1])))
         rays = sg.sample_rays(sc, args.rays or (1 << 20), seed=0)
-        print(json.dumps(pipeline_leg(sc, rays, verbose=True, rounds=args.pipeline_rounds)),
-              flush=True)
+        from paper_2112_05570_amd import pipeline as pl
+        sched = pl.Schedule(balance_sweeps=args.balance_sweeps)
+        print(json.dumps(pipeline_leg(sc, rays, verbose=True, schedule=sched,
+                                      rounds=args.pipeline_rounds)), flush=True)
         return
     if args.workload == "flips":
         sc = sg.make_scene("grid", seed=0)
@@ -555,6 +560,8 @@ def pipeline_leg(sc, rays, stages=24, verbose=False, schedule=None, rounds=1):
            "final": {"vertices": int(r.xy.shape[0]), "triangles": int(r.tri_v.shape[0]),
                      "steiner_vertices": int((r.kind != 0).sum()), "weight": r.log["weight_final"]},
            "total_s": time.perf_counter() - t0}
+    if "balance" in r.log:
+        res["balance"] = r.log["balance"]
     if rounds > 1:
         res["rounds"] = [{"subdivided_vertices": g["subdivided_vertices"],
                           "vertices": g["vertices"], "weight": g["weight_final"],

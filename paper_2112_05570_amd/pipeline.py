@@ -101,6 +101,11 @@ class Schedule:
     # centre costs far more than a single-vertex sweep (groups of tens of members, in rounds), and
     # Sec. 3.3.2 balances the perturbation types by the time they take
     group_share: float = 1.0 / 32
+    # > 0: each stage runs this many sweeps whose types (displacement, resampling, contraction,
+    # swap, group) are drawn with probability inversely proportional to each type's last measured
+    # time, so that every type receives about equal time (Sec. 3.3.2); results then depend on the
+    # timings. 0: one displacement sweep and one sweep of the next proposal type in turn
+    balance_sweeps: int = 0
 
 
 @dataclass
@@ -163,13 +168,22 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
         m = gm.n_movable()
         movable = torch.from_numpy(np.ascontiguousarray(gm.movable, dtype=np.int32)).to(dev)
         lam, acc = s.lambda0, []
-        for k in range(s.stages):
+        kinds = ("displace", "resample", "contract", "swap", "group")
+        spent = {kd_: 0.0 for kd_ in kinds}
+        last = {kd_: 0.0 for kd_ in kinds}
+        counts = {kd_: 0 for kd_ in kinds}
+        pick_rng = np.random.default_rng(s.seed)
+
+        def run(kind_k, k):
+            """One sweep of a perturbation type at stage k; returns the accepted share."""
+            nonlocal lam
             p = objective_params(epss[k], None, *mu)
-            _, a = gm.schedule(X, p, [temps[k]], [epss[k]], lam, unit_draws(m)[None],
-                               uniforms(1, m), target=s.target)
-            frac = int(a[0]) / m
-            lam = lam * min(2.0, max(0.5, 1.0 + (frac - s.target)))
-            kind_k = ("resample", "contract", "swap", "group")[k % 4]
+            if kind_k == "displace":
+                _, a = gm.schedule(X, p, [temps[k]], [epss[k]], lam, unit_draws(m)[None],
+                                   uniforms(1, m), target=s.target)
+                frac = int(a[0]) / m
+                lam = lam * min(2.0, max(0.5, 1.0 + (frac - s.target)))
+                return frac
             if kind_k == "group":
                 n_c = max(1, int(m * s.group_share))
                 pick = torch.randperm(m, generator=gen, device=dev)[:n_c]
@@ -180,14 +194,47 @@ def optimise(tri_v, kind, line, prim_v, xy, size, schedule: Schedule | None = No
             else:
                 _, st = gm.propose(X, p, temps[k], kind_k, proposal_draws(m, kind_k),
                                    uniforms(m))
-            acc.append([frac, int((st == 1).sum().item()) / st.shape[0]])
+            return int((st == 1).sum().item()) / st.shape[0]
+
+        def timed_run(kind_k, k):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = run(kind_k, k)
+            torch.cuda.synchronize()
+            last[kind_k] = time.perf_counter() - t
+            spent[kind_k] += last[kind_k]
+            counts[kind_k] += 1
+            return r
+
+        for k in range(s.stages):
+            if s.balance_sweeps > 0:
+                shares = []
+                for j in range(s.balance_sweeps):
+                    # every type once first, so that each has a measured time
+                    untimed = [kd_ for kd_ in kinds if counts[kd_] == 0]
+                    if untimed:
+                        kind_k = untimed[0]
+                    else:
+                        w = np.array([1.0 / max(last[kd_], 1e-6) for kd_ in kinds])
+                        kind_k = kinds[int(pick_rng.choice(len(kinds), p=w / w.sum()))]
+                    shares.append((kind_k, timed_run(kind_k, k)))
+                frac = np.mean([sh for kd_, sh in shares if kd_ == "displace"] or [0.0])
+                acc.append([float(frac), shares])
+            else:
+                frac = run("displace", k)
+                kind_k = ("resample", "contract", "swap", "group")[k % 4]
+                acc.append([frac, run(kind_k, k)])
             if verbose:
-                f = gm.eval(X, p).cpu().tolist()
+                f = gm.eval(X, objective_params(epss[k], None, *mu)).cpu().tolist()
+                what = (f"{kind_k} {acc[-1][1]:.3f}" if s.balance_sweeps == 0 else
+                        " ".join(f"{kd_}:{sh:.3f}" for kd_, sh in acc[-1][1]))
                 print(f"[optimise] stage {k}: T {temps[k]:.3g} eps {epss[k]:.3g} "
-                      f"accepted {frac:.2f} / {kind_k} {acc[-1][1]:.3f}, f {f[0]:.1f}", flush=True)
+                      f"accepted {frac:.2f} / {what}, f {f[0]:.1f}", flush=True)
     xy_opt = X.cpu().numpy()
     log["anneal_s"] = time.perf_counter() - t0
     log["acceptance"] = acc
+    if s.balance_sweeps > 0:
+        log["balance"] = {"sweeps": counts, "seconds": spent}
     log["weight_annealed"] = weight(tri_v, xy_opt)
 
     pol = objective_params(epss[-1], None, *mu, polish=True)

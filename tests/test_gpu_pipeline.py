@@ -179,3 +179,23 @@ def test_iterated_strategy(ccsp):
     assert k.shape[0] > 4000
     ref = oracle.walk(tri, rays.o[k], rays.d[k], st.cpu().numpy()[k])
     assert all(np.array_equal(a, b) for a, b in zip(g, ref))
+
+
+def test_time_balanced_perturbations(ccsp):
+    """Sec. 3.3.2's choice of perturbation types by equal computation time: every type runs
+    (each first once, to be timed), the stages run the asked number of sweeps, and the result is
+    a valid triangulation, lighter than the subdivided input, that keeps the original vertices."""
+    from paper_2112_05570_amd import pipeline as pl
+    sc = sg.make_scene("tiny")
+    mesh = helpers.subdivided(sc)
+    size = sc.box[1] - sc.box[0]
+    sched = pl.Schedule(stages=4, t0_rel=1e-3, t1_rel=1e-5, e0_rel=2e-2, e1_rel=2e-3,
+                        outer_max=2, flip_rounds=16, seed=5, balance_sweeps=6)
+    r = pl.optimise(mesh.tri_v, mesh.kind, mesh.line, mesh.prim_v, mesh.xy, size, sched)
+    bal = r.log["balance"]
+    assert sum(bal["sweeps"].values()) == 4 * 6
+    assert all(c >= 1 for c in bal["sweeps"].values())
+    nbr, prim, prims, s2o = pl.walk_arrays(r.tri_v, r.kind, r.line, mesh.prim_v, r.xy)
+    assert oracle.validate(oracle.Triangulation(r.xy, r.tri_v, nbr, prim, prims)) == ""
+    assert (r.kind == 0).sum() == sc.n_vertices and np.array_equal(r.xy[r.kind == 0], sc.xy)
+    assert r.log["weight_final"] < r.log["weight_start"]
