@@ -650,6 +650,45 @@ def metropolis_chain(m: Mesh, xy, p: Params, temperature, vid, disp, u):
     return xy, st, df, margin
 
 
+def joint_move(m: Mesh, xy, p: Params, temperature, lam, vid, xi, u):
+    """The second variant of Sec. 3.2.2: the distinct movable vertices vid move together, vertex
+    vid[i] by (lam * sqrt(star area of vid[i])) * xi[i] at the positions before the move,
+    projected for constrained vertices; one Metropolis decision (Sec. 3.1) with u on the change of
+    f, taken as the sum over edges and triangles of every term's new minus old value. Returns
+    (status, delta, bound, positions after, margin): status ACCEPTED, REJECTED, FOLDED (a triangle
+    of a moved vertex not strictly counter-clockwise) or BAD (an id out of range, original or
+    repeated, or a draw not finite); bound is the reordering bound of delta's sums; margin as in
+    metropolis_chain."""
+    xy = np.array(xy, dtype=np.float64)
+    vid = [int(v) for v in vid]
+    xi = np.asarray(xi, dtype=np.float64).reshape(-1, 2)
+    if (len(set(vid)) != len(vid) or not np.isfinite(xi).all()
+            or any(not (0 <= v < m.nv) or m.kind[v] == ORIGINAL for v in vid)):
+        return BAD, np.inf, 0.0, xy, np.inf
+    new = xy.copy()
+    for i, v in enumerate(vid):
+        k = lam * np.sqrt(star_area(m, xy, v))
+        new[v] = xy[v] + project(m, xy, v, np.array([k * xi[i, 0], k * xi[i, 1]]))
+    moved = np.zeros(m.nv, dtype=bool)
+    moved[vid] = True
+    for t in np.nonzero(moved[m.tri_v].any(axis=1))[0]:
+        a, b, c = (new[k] for k in m.tri_v[t])
+        if orient(a, b, c) <= 0:
+            return FOLDED, np.inf, 0.0, xy, np.inf
+    t0, t1 = terms(m, xy, p), terms(m, new, p)
+    de, da, dl = t1["edge"] - t0["edge"], t1["angle"] - t0["angle"], t1["short"] - t0["short"]
+    d = de.sum() + p.mu_angle * da.sum() + p.mu_len * dl.sum()
+    u53 = 2.0 ** -53
+    bound = 2 * (de.size + da.size) * u53 * (np.abs(de).sum() + p.mu_angle * np.abs(da).sum()
+                                            + p.mu_len * np.abs(dl).sum()) + 4 * u53 * abs(d)
+    with np.errstate(divide="ignore", over="ignore"):
+        accept = d <= 0.0 or u < np.exp(-np.float64(d) / np.float64(temperature))
+        margin = abs(d + temperature * np.log(u)) if u > 0 else np.inf
+    if accept:
+        return ACCEPTED, d, bound, new, margin
+    return REJECTED, d, bound, xy, margin
+
+
 def star_area(m: Mesh, xy, v):
     """Area of the triangles of vertex v, summed in increasing triangle id, each as
     0.5 * ((b - a) x (c - a)) on its vertices in their stored order."""
