@@ -782,6 +782,23 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
                           "mean_group_size": float(gmem.double().mean().item()),
                           "f_after": gm.eval(XP, p).cpu().tolist()[0]}
     del XP
+    # joint moves (the second variant of Sec. 3.2.2): 2% of the movable vertices at once, one
+    # Metropolis decision per move on the sum of every term's change
+    n_j, jsteps = max(1, n_mov // 50), 8
+    jrng = np.random.default_rng(9)
+    XP = X.clone()
+    jst = []
+    t_j = time.perf_counter()
+    for _ in range(jsteps):
+        jv = torch.from_numpy(gm.movable[jrng.choice(n_mov, n_j, replace=False)]).to(xy.device)
+        jx = torch.from_numpy(jrng.standard_normal((n_j, 2))).to(xy.device)
+        jst.append(gm.joint(XP, p, temperature, 0.01, jv, jx, float(jrng.random()))[1])
+    ms_j = (time.perf_counter() - t_j) * 1e3 / jsteps
+    log(f"[bench] objective: joint move of {n_j} vertices {ms_j:.2f} ms")
+    proposals["joint"] = {"vertices": n_j, "ms_per_move": ms_j, "steps": jsteps,
+                          "accepted": jst.count(1), "rejected": jst.count(2),
+                          "folded": jst.count(0)}
+    del XP
 
     # an annealing schedule (Secs. 3.2, 3.3.1): temperature and contraction length lowered together
     # by a factor of 10 over the sweeps, step scale adapted toward 23% acceptance

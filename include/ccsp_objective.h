@@ -160,6 +160,30 @@ int objective_delta(MovableMesh *mesh, const double *xy, const ObjectiveParams *
 int mesh_classes(MovableMesh *mesh, int32_t *n_classes, int64_t *class_off, int32_t *class_v);
 
 /*
+ * anneal_joint (the second variant of Sec. 3.2.2, which perturbs a fixed fraction of the movable
+ * vertices in one go): one Metropolis step (Sec. 3.1) for one move of the k >= 1 distinct movable
+ * vertices vid[0..k) (DEVICE int32, caller ids) together. Vertex vid[i] moves by
+ * lambda * eta_i * xi[2i..2i+1] (xi DEVICE binary64, 16-byte aligned, unit draws; eta_i the
+ * square root of the area of vid[i]'s triangles at the positions before the move, summed in the
+ * caller's triangle order, as in anneal_schedule), projected on its original edge when
+ * CONSTRAINED (as in anneal_moves). The move is valid when every triangle of every moved vertex
+ * is strictly counter-clockwise afterwards. Its change of f is the sum over edges and triangles
+ * of every term's new value minus its old one (each term as in objective_eval; a term the move
+ * does not reach gives exactly 0), added per part in a fixed order and combined as f is. It is
+ * accepted when valid and delta <= 0 or u < exp(-delta / temperature); xy (DEVICE) is then updated
+ * in place. *delta_out (HOST) receives the change (+inf unless valid) and *status_out (HOST)
+ * CCSP_MOVE_OK, CCSP_MOVE_REJECTED, CCSP_MOVE_FOLDS, or CCSP_MOVE_BAD when an id is out of range,
+ * ORIGINAL or repeated, or a draw is not finite (nothing moves then). Synchronises `stream` once;
+ * overwrites the mesh's scratch. Device memory kept by the mesh: 16 bytes per edge, 8 per
+ * triangle, 4 per vertex and 16 per moved vertex (grown, after synchronising `stream`, when k
+ * exceeds every earlier call's).
+ */
+int anneal_joint(MovableMesh *mesh, double *xy, const ObjectiveParams *params,
+                 double temperature, double lambda, const int32_t *vid, int64_t k,
+                 const double *xi, double u, double *delta_out, int32_t *status_out,
+                 void *stream);
+
+/*
  * anneal_moves: one Metropolis step (Sec. 3.1) for each of k single-vertex moves (Sec. 3.2.2), for
  * moves that do not interact (the vertices of one class of mesh_classes; for other sets, every
  * move is still evaluated against the positions before the call). Move i displaces vertex vid[i]

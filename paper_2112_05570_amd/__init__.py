@@ -422,6 +422,20 @@ class MovableMesh:
                        _stream(stream))
         return d, st
 
+    def joint(self, xy, params, temperature, lam, vid, xi, u, stream=None):
+        """One Metropolis step for one move of the distinct movable vertices vid (caller ids,
+        int32 CUDA tensor) together, by lam * eta_i * xi[i] (xi (k,2) float64 CUDA unit draws; see
+        ``anneal_joint``), u a float in [0, 1). xy is updated in place when the move is accepted.
+        Returns (delta, status) as Python numbers. Synchronous."""
+        import torch
+        k = vid.shape[0]
+        if (not vid.is_cuda or vid.dtype != torch.int32 or not vid.is_contiguous()
+                or tuple(xi.shape) != (k, 2) or xi.dtype != torch.float64
+                or not xi.is_contiguous() or not xi.is_cuda):
+            raise ValueError("vid int32 (k,), xi float64 (k,2): contiguous CUDA tensors")
+        return B.anneal_joint(self.handle, self._xy(xy), params, float(temperature), float(lam),
+                              vid.data_ptr(), k, xi.data_ptr(), float(u), _stream(stream))
+
     def sweep(self, xy, params, temperature, disp, u, stream=None):
         """One Metropolis step for every movable vertex, class by class (see ``anneal_sweep``):
         disp (M,2) and u (M,) float64 CUDA tensors in the order of ``classes()``. xy is updated in

@@ -50,7 +50,7 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
            "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
-           "anneal_moves", "anneal_sweep", "anneal_propose", "anneal_schedule",
+           "anneal_moves", "anneal_joint", "anneal_sweep", "anneal_propose", "anneal_schedule",
            "flip_anneal", "mesh_contract", "anneal_group",
            "trace_rays_static", "mesh_subdivide",
            "load_tetmesh", "free_tetmesh", "tetmesh_info", "trace_rays3d",
@@ -176,6 +176,9 @@ _lib.mesh_classes.restype = _I
 _lib.anneal_moves.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double, _P, _P, _P,
                               _I64, _P, _P, _P]
 _lib.anneal_moves.restype = _I
+_lib.anneal_joint.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double,
+                              ctypes.c_double, _P, _I64, _P, ctypes.c_double, _P, _P, _P]
+_lib.anneal_joint.restype = _I
 _lib.anneal_sweep.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double, _P, _P, _P,
                               _P, _P]
 _lib.anneal_sweep.restype = _I
@@ -376,6 +379,16 @@ def anneal_moves(mesh: int, xy: int, params: ObjectiveParams, temperature: float
                  disp: int, u: int, k: int, delta: int, status: int, stream: int = 0) -> None:
     _check(_lib.anneal_moves(_P(mesh), _P(xy), ctypes.byref(params), temperature, _P(vid), _P(disp),
                              _P(u), k, _P(delta), _P(status), _P(stream)))
+
+
+def anneal_joint(mesh: int, xy: int, params: ObjectiveParams, temperature: float, lam: float,
+                 vid: int, k: int, xi: int, u: float, stream: int = 0) -> tuple:
+    """Returns (delta, status) of the joint move (host values)."""
+    delta = ctypes.c_double()
+    status = ctypes.c_int32()
+    _check(_lib.anneal_joint(_P(mesh), _P(xy), ctypes.byref(params), temperature, lam, _P(vid), k,
+                             _P(xi), u, ctypes.byref(delta), ctypes.byref(status), _P(stream)))
+    return delta.value, status.value
 
 
 def anneal_sweep(mesh: int, xy: int, params: ObjectiveParams, temperature: float, disp: int,

@@ -1575,6 +1575,140 @@ anneal_class(MeshDev m, Par p, double temperature, double lambda, int kind,
   }
 }
 
+// ---- joint moves of many vertices with one decision (the second variant of Sec. 3.2.2)
+
+// Flags of a joint move (bits of *flags).
+constexpr int kJointBad = 1;    // an id out of range, not movable, repeated, or a draw not finite
+constexpr int kJointFolds = 2;  // a triangle of a moved vertex not strictly counter-clockwise
+
+// Every term of f at the staged positions and edge scratch: te[e] = w(e) |e| (as terms_pass),
+// ts[e] the length penalty of e, ta[t] the angle penalty of t.
+__global__ void __launch_bounds__(kThreads)
+joint_terms(MeshDev m, Par p, double* __restrict__ te, double* __restrict__ ts,
+            double* __restrict__ ta) {
+  const int n = m.ne > m.nt ? m.ne : m.nt;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    if (i < m.ne) {
+      const double w = p.polish ? 1.0 : weight_from(m.c, m.edge_nbr[i]);
+      te[i] = w * m.len[i];
+      ts[i] = short_term(m.len[i], p.eps0);
+    }
+    if (i < m.nt) ta[i] = triangle_angles(m.xyi, m.tri[i], -1, make_double2(0, 0), p.delta, p.polish);
+  }
+}
+
+// New position of every vertex of the joint move, from the positions before it: vid[i] (caller
+// id) moves by lambda * eta * xi[i], eta the square root of the area of its triangles (summed in
+// the caller's triangle order), projected on its original edge when constrained. mark holds the
+// epoch of the last joint move that named each vertex, which finds repeats.
+__global__ void __launch_bounds__(kThreads)
+joint_prepare(MeshDev m, double lambda, const int32_t* __restrict__ vid,
+              const double2* __restrict__ xi, int64_t k, uint32_t epoch,
+              uint32_t* __restrict__ mark, double2* __restrict__ qnew, int* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= k) return;
+  const int cv = vid[i];
+  const double2 x = xi[i];
+  if (cv < 0 || cv >= m.nv || !isfinite(x.x) || !isfinite(x.y)) {
+    atomicOr(flags, kJointBad);
+    return;
+  }
+  const int v = m.vnew[cv];
+  if (m.vk[v].x == CCSP_VERTEX_ORIGINAL || atomicExch(&mark[v], epoch) == epoch) {
+    atomicOr(flags, kJointBad);
+    return;
+  }
+  double area = 0.0;
+  for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j)
+    area += tri_area(m, m.vtri[j]);
+  const double kk = lambda * sqrt(area);
+  double2 d = make_double2(kk * x.x, kk * x.y);
+  const int2 kl = m.vk[v];
+  if (kl.x == CCSP_VERTEX_CONSTRAINED) {
+    const int2 ends = m.prim_v[kl.y];
+    const double2 a = m.xyi[ends.x], b = m.xyi[ends.y];
+    const double ex = b.x - a.x, ey = b.y - a.y;
+    const double s = (d.x * ex + d.y * ey) / (ex * ex + ey * ey);
+    d = make_double2(s * ex, s * ey);
+  }
+  const double2 o = m.xyi[v];
+  qnew[i] = make_double2(o.x + d.x, o.y + d.y);
+}
+
+// The joint move's positions into the staged ones (unless a flag is set).
+__global__ void __launch_bounds__(kThreads)
+joint_apply(MeshDev m, const int32_t* __restrict__ vid, const double2* __restrict__ qnew,
+            int64_t k, const int* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= k || *flags != 0) return;
+  m.xyi[m.vnew[vid[i]]] = qnew[i];
+}
+
+// Validity after the joint move: every triangle of every moved vertex strictly counter-clockwise.
+__global__ void __launch_bounds__(kThreads)
+joint_check(MeshDev m, const int32_t* __restrict__ vid, int64_t k, int* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= k || (*flags & kJointBad) != 0) return;
+  const int v = m.vnew[vid[i]];
+  for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j) {
+    const int4 t = m.tri[m.vtri[j]];
+    if (orient_sign(m.xyi[t.x], m.xyi[t.y], m.xyi[t.z]) <= 0) {
+      atomicOr(flags, kJointFolds);
+      return;
+    }
+  }
+}
+
+// Per-workgroup sums (fixed stride per thread) of every term's new minus stored old value:
+// part[b] edges' w |e|, part[nb + b] angle penalties, part[2 nb + b] length penalties.
+__global__ void __launch_bounds__(kThreads)
+joint_diff(MeshDev m, Par p, const double* __restrict__ te, const double* __restrict__ ts,
+           const double* __restrict__ ta, double* __restrict__ part) {
+  __shared__ double sh[kThreads];
+  const int n = m.ne > m.nt ? m.ne : m.nt;
+  double se = 0.0, sa = 0.0, sl = 0.0;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    if (i < m.ne) {
+      const double w = p.polish ? 1.0 : weight_from(m.c, m.edge_nbr[i]);
+      se += w * m.len[i] - te[i];
+      sl += short_term(m.len[i], p.eps0) - ts[i];
+    }
+    if (i < m.nt)
+      sa += triangle_angles(m.xyi, m.tri[i], -1, make_double2(0, 0), p.delta, p.polish) - ta[i];
+  }
+  se = block_sum(se, sh);
+  sa = block_sum(sa, sh);
+  sl = block_sum(sl, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = se;
+    part[gridDim.x + blockIdx.x] = sa;
+    part[2 * gridDim.x + blockIdx.x] = sl;
+  }
+}
+
+// out[0] = the change of f, out[1..3] = those of w_contr, P_angle and P_len (one workgroup).
+__global__ void __launch_bounds__(kThreads)
+joint_finish(const double* __restrict__ part, int nb, Par p, double* __restrict__ out) {
+  __shared__ double sh[kThreads];
+  const double dw = sum_fixed(part, nb, sh);
+  const double da = sum_fixed(part + nb, nb, sh);
+  const double dl = sum_fixed(part + 2 * nb, nb, sh);
+  if (threadIdx.x == 0) {
+    out[0] = dw + p.mu_angle * da + p.mu_len * dl;
+    out[1] = dw;
+    out[2] = da;
+    out[3] = dl;
+  }
+}
+
+// An accepted joint move's positions into the caller's array.
+__global__ void __launch_bounds__(kThreads)
+joint_commit(const int32_t* __restrict__ vid, const double2* __restrict__ qnew, int64_t k,
+             double2* __restrict__ xy_out) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < k) xy_out[vid[i]] = qnew[i];
+}
+
 __global__ void __launch_bounds__(kThreads)
 fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -1641,6 +1775,9 @@ struct MovableMesh {
   void* sched = nullptr;           // anneal_schedule: delta and status per movable vertex, counter
   void* order_ws = nullptr;        // objective_delta: sort keys, move indices, sort temporaries
   size_t order_bytes = 0;
+  void* joint_ws = nullptr;        // anneal_joint: stored terms, marks, sums, new positions
+  size_t joint_bytes = 0;
+  uint32_t joint_epoch = 0;
 };
 
 namespace {
@@ -2105,6 +2242,98 @@ int objective_eval(MovableMesh* mesh, const double* xy, const ObjectiveParams* p
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_eval: launch");
 }
 
+int anneal_joint(MovableMesh* mesh, double* xy, const ObjectiveParams* params,
+                 double temperature, double lambda, const int32_t* vid, int64_t k,
+                 const double* xi, double u, double* delta_out, int32_t* status_out,
+                 void* stream) {
+  if (!mesh || !xy || !delta_out || !status_out || (k > 0 && (!vid || !xi)))
+    return fail(CCSP_E_ARG, "anneal_joint: null argument");
+  if (k < 1 || k >= (int64_t(1) << 31)) return fail(CCSP_E_ARG, "anneal_joint: bad vertex count");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)xi & 15) != 0 || ((uintptr_t)vid & 3) != 0)
+    return fail(CCSP_E_ARG, "anneal_joint: misaligned buffer");
+  if (!check_params(params)) return fail(CCSP_E_ARG, "anneal_joint: invalid parameters");
+  if (!(temperature >= 0) || !std::isfinite(temperature))
+    return fail(CCSP_E_ARG, "anneal_joint: temperature must be finite and >= 0");
+  if (!(lambda >= 0) || !std::isfinite(lambda))
+    return fail(CCSP_E_ARG, "anneal_joint: lambda must be finite and >= 0");
+  if (int r = check_device(mesh)) return r;
+  const ccsp::MeshDev& d = mesh->d;
+  const ccsp::Par p = to_par(params);
+  hipStream_t s = (hipStream_t)stream;
+  const int T = ccsp::kThreads;
+  const int nb = grid_for(std::max(d.ne, d.nt));
+  // workspace: te, ts (E doubles), ta (T doubles), marks (V), sums, out, flags, then new positions
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t o_ts = al(8 * (size_t)d.ne), o_ta = o_ts + al(8 * (size_t)d.ne);
+  const size_t o_mark = o_ta + al(8 * (size_t)d.nt), o_part = o_mark + al(4 * (size_t)d.nv);
+  const size_t o_out = o_part + al(8 * 3 * (size_t)ccsp::kMaxBlocks), o_flags = o_out + 256;
+  const size_t o_q = o_flags + 256, need = o_q + al(16 * (size_t)k);
+  hipError_t e;
+  if (need > mesh->joint_bytes) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "anneal_joint: synchronise");
+    if (mesh->joint_ws) (void)hipFree(mesh->joint_ws);
+    mesh->joint_ws = nullptr;
+    mesh->joint_bytes = 0;
+    if (hipMalloc(&mesh->joint_ws, need) != hipSuccess) {
+      (void)hipGetLastError();
+      mesh->joint_ws = nullptr;
+      return fail(CCSP_E_OOM, "anneal_joint: device allocation failed");
+    }
+    mesh->joint_bytes = need;
+    mesh->joint_epoch = 0;
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3((unsigned)((d.nv + T - 1) / T)), dim3(T), 0, s,
+                       (int32_t*)((char*)mesh->joint_ws + o_mark), (int64_t)d.nv, 0);
+  }
+  char* w = (char*)mesh->joint_ws;
+  double *te = (double*)w, *ts = (double*)(w + o_ts), *ta = (double*)(w + o_ta);
+  auto* mark = (uint32_t*)(w + o_mark);
+  auto* part = (double*)(w + o_part);
+  auto* out = (double*)(w + o_out);
+  auto* flags = (int*)(w + o_flags);
+  auto* qnew = (double2*)(w + o_q);
+  if (++mesh->joint_epoch == 0) {  // marks hold epochs: after a wrap, clear them
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3((unsigned)((d.nv + T - 1) / T)), dim3(T), 0, s,
+                       (int32_t*)mark, (int64_t)d.nv, 0);
+    mesh->joint_epoch = 1;
+  }
+  const unsigned kb = (unsigned)((k + T - 1) / T);
+  stage_edges(d, p, xy, s);
+  hipLaunchKernelGGL(ccsp::fill_i32, dim3(1), dim3(T), 0, s, (int32_t*)flags, (int64_t)1, 0);
+  hipLaunchKernelGGL(ccsp::joint_terms, dim3(nb), dim3(T), 0, s, d, p, te, ts, ta);
+  hipLaunchKernelGGL(ccsp::joint_prepare, dim3(kb), dim3(T), 0, s, d, lambda, vid,
+                     (const double2*)xi, k, mesh->joint_epoch, mark, qnew, flags);
+  hipLaunchKernelGGL(ccsp::joint_apply, dim3(kb), dim3(T), 0, s, d, vid, qnew, k, flags);
+  hipLaunchKernelGGL(ccsp::joint_check, dim3(kb), dim3(T), 0, s, d, vid, k, flags);
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(T), 0, s, d, p, d.partial);
+  hipLaunchKernelGGL(ccsp::joint_diff, dim3(nb), dim3(T), 0, s, d, p, te, ts, ta, part);
+  hipLaunchKernelGGL(ccsp::joint_finish, dim3(1), dim3(T), 0, s, part, nb, p, out);
+  double hout[4];
+  int hflags = 0;
+  e = hipMemcpyAsync(hout, out, sizeof hout, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "anneal_joint");
+  *delta_out = __builtin_huge_val();
+  if (hflags & ccsp::kJointBad) {
+    *status_out = CCSP_MOVE_BAD;
+  } else if (hflags & ccsp::kJointFolds) {
+    *status_out = CCSP_MOVE_FOLDS;
+  } else {
+    const double df = hout[0];
+    *delta_out = df;
+    if (df <= 0.0 || u < std::exp(-df / temperature)) {
+      *status_out = CCSP_MOVE_OK;
+      hipLaunchKernelGGL(ccsp::joint_commit, dim3(kb), dim3(T), 0, s, vid, qnew, k,
+                         (double2*)xy);
+    } else {
+      *status_out = CCSP_MOVE_REJECTED;
+    }
+  }
+  e = hipGetLastError();
+  return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_joint: launch");
+}
+
 int objective_delta(MovableMesh* mesh, const double* xy, const ObjectiveParams* params,
                     const int32_t* vid, const double* q_xy, int64_t k, double* delta,
                     int32_t* status, void* stream) {
@@ -2534,6 +2763,7 @@ void mesh_free(MovableMesh* mesh) {
   if (!mesh) return;
   if (mesh->sched) (void)hipFree(mesh->sched);
   if (mesh->order_ws) (void)hipFree(mesh->order_ws);
+  if (mesh->joint_ws) (void)hipFree(mesh->joint_ws);
   if (mesh->class_dev) (void)hipFree(mesh->class_dev);
   if (mesh->mem) (void)hipFree(mesh->mem);
   delete mesh;

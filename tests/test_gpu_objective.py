@@ -151,6 +151,51 @@ def test_tiny_delta(ccsp, tiny, state, polish):
     assert (st[:n] == 1).sum() > 100 and (st[:n] == 0).sum() > 10
 
 
+@pytest.mark.parametrize("state", ["subdivided", "clustered"])
+def test_joint_moves_equal_checker(ccsp, tiny, state):
+    """The second variant of Sec. 3.2.2 (anneal_joint): a random 5% of the movable vertices moved
+    together, one decision. Status equal to the checker's joint_move, the change of f within the
+    reordering bound of its sums, positions after each step bit for bit; a chain of steps at two
+    temperatures and step scales (some accepted, some rejected, some folded), then invalid
+    inputs (a repeated, an original and an out-of-range id) that leave the positions alone."""
+    mesh, om = tiny
+    p = ob.Params(0.03)
+    xy = mesh.xy.copy() if state == "subdivided" else _clustered(mesh, om, p, 8)
+    rng = np.random.default_rng(61)
+    movable = np.nonzero(mesh.kind != sg.ORIGINAL)[0]
+    k = max(2, movable.shape[0] // 20)
+    seen = set()
+    with ccsp.MovableMesh(om.tri_v, om.kind, om.line, om.prim_v) as gm:
+        prm = _params(ccsp, p)
+        X = torch.from_numpy(xy.copy()).to(DEV)
+        for step in range(24):
+            lam, temp = ((0.05, 1e-3), (0.3, 1e-4), (0.01, 0.0))[step % 3]
+            vids = rng.choice(movable, k, replace=False).astype(np.int32)
+            xi = rng.standard_normal((k, 2))
+            uu = float(rng.random())
+            d, st = gm.joint(X, prm, temp, lam, torch.from_numpy(vids).to(DEV),
+                             torch.from_numpy(xi).to(DEV), uu)
+            rs, rd, bound, xy_new, margin = ob.joint_move(om, xy, p, temp, lam, vids, xi, uu)
+            assert margin > 1e-10, "a decision lies within rounding of its threshold"
+            assert st == rs, (step, st, rs)
+            if rs in (ob.ACCEPTED, ob.REJECTED):
+                assert abs(d - rd) <= bound, (step, d, rd, bound)
+            else:
+                assert d == math.inf
+            xy = xy_new
+            assert np.array_equal(X.cpu().numpy(), xy), step
+            seen.add(rs)
+        assert seen >= {ob.ACCEPTED, ob.REJECTED, ob.FOLDED}, seen
+        orig = int(np.nonzero(mesh.kind == sg.ORIGINAL)[0][0])
+        good = movable[:3].astype(np.int32)
+        for bad in ([good[0], good[1], good[0]], [good[0], orig, good[1]],
+                    [good[0], good[1], mesh.n_vertices]):
+            d, st = gm.joint(X, prm, 1e-3, 0.05, torch.tensor(bad, dtype=torch.int32, device=DEV),
+                             torch.full((3, 2), 0.1, dtype=torch.float64, device=DEV), 0.5)
+            assert st == -2 and d == math.inf
+        assert np.array_equal(X.cpu().numpy(), xy)
+
+
 def test_rules_follow_original_positions(ccsp, tiny):
     """The conditioning restriction reads ORIGINAL positions only, so the library keeps its result
     from call to call and recomputes it when an ORIGINAL position changes. One mesh evaluated at
