@@ -783,7 +783,8 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
                           "f_after": gm.eval(XP, p).cpu().tolist()[0]}
     del XP
     # joint moves (the second variant of Sec. 3.2.2): 2% of the movable vertices at once, one
-    # Metropolis decision per move on the sum of every term's change
+    # Metropolis decision per move on the sum of every term's change; the step scale is far
+    # below the single moves' (a joint move folds when any of its vertices does)
     n_j, jsteps = max(1, n_mov // 50), 8
     jrng = np.random.default_rng(9)
     XP = X.clone()
@@ -792,7 +793,7 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
     for _ in range(jsteps):
         jv = torch.from_numpy(gm.movable[jrng.choice(n_mov, n_j, replace=False)]).to(xy.device)
         jx = torch.from_numpy(jrng.standard_normal((n_j, 2))).to(xy.device)
-        jst.append(gm.joint(XP, p, temperature, 0.01, jv, jx, float(jrng.random()))[1])
+        jst.append(gm.joint(XP, p, temperature, 1e-3, jv, jx, float(jrng.random()))[1])
     ms_j = (time.perf_counter() - t_j) * 1e3 / jsteps
     log(f"[bench] objective: joint move of {n_j} vertices {ms_j:.2f} ms")
     proposals["joint"] = {"vertices": n_j, "ms_per_move": ms_j, "steps": jsteps,
