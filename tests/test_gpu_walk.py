@@ -407,18 +407,22 @@ def test_server_alone_vs_mix(ccsp, tiny_scene, tiny_rays, grid_pair):
         n = int(np.exp(rng.uniform(np.log(1), np.log(60_000))))
         if k % 17 == 0:
             n = 0
+        if 1 <= k <= 3:
+            # three requests of 3.4 MB each, submitted back to back, do not fit the 8 MiB pool
+            # together: the third waits for memory unless the first has already finished
+            s, n = 1, 60_000
         off = int(rng.integers(0, pools[s].n - n + 1))
         reqs.append((s, off, n))
+    # outputs allocated before any submission, so that requests arrive back to back
+    outs = [ccsp.Result(torch.empty(n, dtype=torch.int32).pin_memory(),
+                        torch.empty(n, dtype=torch.float64).pin_memory(),
+                        torch.empty(n, dtype=torch.int32).pin_memory()) for _, _, n in reqs]
     try:
         with ccsp.Server(precision="fp32", slots=3, max_items=8, memory_bytes=8 << 20) as srv:
-            outs, ids, done = [], {}, []
+            ids, done = {}, []
             for k, (s, off, n) in enumerate(reqs):
                 o, d, st = (x[off:off + n] for x in host[s])
-                out = ccsp.Result(torch.empty(n, dtype=torch.int32).pin_memory(),
-                                  torch.empty(n, dtype=torch.float64).pin_memory(),
-                                  torch.empty(n, dtype=torch.int32).pin_memory())
-                outs.append(out)
-                ids[srv.submit(scenes[s], o, d, st, out)] = k
+                ids[srv.submit(scenes[s], o, d, st, outs[k])] = k
                 if k % 10 == 9:
                     done += srv.poll()
             deadline = 60.0
