@@ -793,7 +793,7 @@ def objective_leg(scene_name, steps, warmup, moves=1 << 20):
     for _ in range(jsteps):
         jv = torch.from_numpy(gm.movable[jrng.choice(n_mov, n_j, replace=False)]).to(xy.device)
         jx = torch.from_numpy(jrng.standard_normal((n_j, 2))).to(xy.device)
-        jst.append(gm.joint(XP, p, temperature, 1e-3, jv, jx, float(jrng.random()))[1])
+        jst.append(gm.joint(XP, p, temperature, 1e-5, jv, jx, float(jrng.random()))[1])
     ms_j = (time.perf_counter() - t_j) * 1e3 / jsteps
     log(f"[bench] objective: joint move of {n_j} vertices {ms_j:.2f} ms")
     proposals["joint"] = {"vertices": n_j, "ms_per_move": ms_j, "steps": jsteps,
