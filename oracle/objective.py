@@ -669,6 +669,12 @@ def joint_move(m: Mesh, xy, p: Params, temperature, lam, vid, xi, u):
     for i, v in enumerate(vid):
         k = lam * np.sqrt(star_area(m, xy, v))
         new[v] = xy[v] + project(m, xy, v, np.array([k * xi[i, 0], k * xi[i, 1]]))
+    return _joint_decide(m, xy, new, vid, p, temperature, u)
+
+
+def _joint_decide(m: Mesh, xy, new, vid, p: Params, temperature, u):
+    """Validity, change of f and Metropolis decision of a joint move from xy to new, which differ
+    at the vertices vid (see joint_move)."""
     moved = np.zeros(m.nv, dtype=bool)
     moved[vid] = True
     for t in np.nonzero(moved[m.tri_v].any(axis=1))[0]:
@@ -687,6 +693,32 @@ def joint_move(m: Mesh, xy, p: Params, temperature, lam, vid, xi, u):
     if accept:
         return ACCEPTED, d, bound, new, margin
     return REJECTED, d, bound, xy, margin
+
+
+def joint_groups(m: Mesh, xy, p: Params, temperature, lam, centres, xi, rd, u):
+    """The second variant of Sec. 3.2.3: the groups of several centres (group_members with
+    d = (0.5 + 4.5 rd[i]) eps, at the positions before the move) move together, each by
+    (lam * sqrt(group area)) * xi[i] projected per member, a vertex held by several groups with
+    the displacement of the first of them in centre order (the paper leaves overlaps open); one
+    decision as in joint_move. BAD when a centre is out of range or original, or a draw is not
+    finite. Returns what joint_move returns."""
+    xy = np.array(xy, dtype=np.float64)
+    xi = np.asarray(xi, dtype=np.float64).reshape(-1, 2)
+    rd = np.asarray(rd, dtype=np.float64)
+    cs = [int(c) for c in centres]
+    if (not np.isfinite(xi).all() or not np.isfinite(rd).all()
+            or any(not (0 <= c < m.nv) or m.kind[c] == ORIGINAL for c in cs)):
+        return BAD, np.inf, 0.0, xy, np.inf
+    new, owned = xy.copy(), {}
+    for i, c in enumerate(cs):
+        members = group_members(m, xy, c, (0.5 + 4.5 * rd[i]) * p.eps)
+        k = lam * math.sqrt(group_area(m, xy, members))
+        D = np.array([k * xi[i, 0], k * xi[i, 1]])
+        for v in members:
+            if v not in owned:
+                owned[v] = i
+                new[v] = xy[v] + project(m, xy, v, D)
+    return _joint_decide(m, xy, new, sorted(owned), p, temperature, u)
 
 
 def star_area(m: Mesh, xy, v):

@@ -129,3 +129,73 @@ def test_invalid_inputs_and_folds(tiny):
         assert st == ob.BAD and d == math.inf and np.array_equal(new, mesh.xy)
     st, d, _, new, _ = ob.joint_move(om, mesh.xy, p, 1e-3, 50.0, free, x, 0.5)
     assert st == ob.FOLDED and d == math.inf and np.array_equal(new, mesh.xy)
+
+
+def test_one_group_is_the_group_move(tiny):
+    """Joint groups with one centre are that centre's group move (group_chain's single step):
+    same status, positions and change of f."""
+    mesh, om = tiny
+    p = ob.Params(0.05)
+    rng = np.random.default_rng(8)
+    movable = np.nonzero(mesh.kind != sg.ORIGINAL)[0]
+    seen = set()
+    for c in rng.choice(movable, 25, replace=False):
+        xi = 0.3 * rng.standard_normal((1, 2))
+        rd = rng.random(1)
+        u = rng.random(1)
+        xy_c, st_c, df_c, _, size = ob.group_chain(om, mesh.xy, p, 1e-3, 0.05, [int(c)], xi, rd, u)
+        st, d, b, new, _ = ob.joint_groups(om, mesh.xy, p, 1e-3, 0.05, [int(c)], xi, rd, u[0])
+        assert st == st_c[0]
+        assert np.array_equal(new, xy_c)
+        if st in (ob.ACCEPTED, ob.REJECTED):
+            assert d == df_c[0]
+        seen.add(int(st))
+        seen.add(-int(size[0] > 1))
+    assert {ob.ACCEPTED, ob.REJECTED, -1} <= seen
+
+
+def test_far_apart_groups_add_up_and_overlaps_take_the_first(tiny):
+    """Groups far apart change f by the sum of their single moves; a vertex in two groups moves
+    with the first group's displacement."""
+    mesh, om = tiny
+    p = ob.Params(0.02)
+    rng = np.random.default_rng(9)
+    added = 0
+    for trial in range(6):
+        cs = _far_apart(om, rng, 3, hops=12)
+        xi = 0.2 * rng.standard_normal((3, 2))
+        rd = np.zeros(3)  # d = eps / 2: small groups
+        singles = [ob.group_chain(om, mesh.xy, p, 0.0, 0.05, [c], xi[i:i + 1], rd[i:i + 1],
+                                  [0.5]) for i, c in enumerate(cs)]
+        st, d, b, new, _ = ob.joint_groups(om, mesh.xy, p, 0.0, 0.05, cs, xi, rd, 0.5)
+        if any(sg_[1][0] == ob.FOLDED for sg_ in singles):
+            assert st == ob.FOLDED
+            continue
+        total = sum(sg_[2][0] for sg_ in singles)
+        assert abs(d - total) <= b + 1e-9 * sum(abs(sg_[2][0]) for sg_ in singles) + 1e-300
+        added += 1
+    assert added >= 3
+    # overlapping groups: a centre and its neighbour, both with a large d
+    free = [int(v) for v in np.nonzero(mesh.kind == sg.FREE)[0]]
+    c0 = free[0]
+    c1 = int(next(w for w in om.nbr[om.nbr_off[c0]:om.nbr_off[c0 + 1]] if mesh.kind[w] == sg.FREE))
+    xi = np.array([[1e-3, 0.0], [0.0, 1e-3]])
+    rd = np.ones(2)
+    st, d, b, new, _ = ob.joint_groups(om, mesh.xy, p, 1e9, 0.05, [c0, c1], xi, rd, 0.0)
+    m0 = ob.group_members(om, mesh.xy, c0, 5.0 * p.eps)
+    k0 = 0.05 * math.sqrt(ob.group_area(om, mesh.xy, m0))
+    assert st == ob.ACCEPTED and c1 in m0
+    want = mesh.xy[c1] + ob.project(om, mesh.xy, c1, np.array([k0 * 1e-3, 0.0]))
+    assert np.array_equal(new[c1], want)
+
+
+def test_joint_groups_bad_inputs(tiny):
+    mesh, om = tiny
+    p = ob.Params(0.05)
+    free = [int(v) for v in np.nonzero(mesh.kind == sg.FREE)[0][:2]]
+    orig = int(np.nonzero(mesh.kind == sg.ORIGINAL)[0][0])
+    xi = np.full((2, 2), 0.1)
+    for cs, x, rd in (([free[0], orig], xi, np.zeros(2)), ([free[0], mesh.n_vertices], xi, np.zeros(2)),
+                      (free, np.array([[0.1, np.inf], [0.1, 0.1]]), np.zeros(2))):
+        st, d, _, new, _ = ob.joint_groups(om, mesh.xy, p, 1e-3, 0.05, cs, x, rd, 0.5)
+        assert st == ob.BAD and d == math.inf and np.array_equal(new, mesh.xy)
