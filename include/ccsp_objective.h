@@ -184,6 +184,23 @@ int anneal_joint(MovableMesh *mesh, double *xy, const ObjectiveParams *params,
                  void *stream);
 
 /*
+ * anneal_joint_groups (the second variant of Sec. 3.2.3, which perturbs a fixed set of groups in
+ * one go): one Metropolis step for the group moves of n >= 1 centres (DEVICE int32 caller ids)
+ * made together. Centre i's group (as in anneal_group, at the positions before the move: d from
+ * draws[4i+2], members within d) moves by (lambda * sqrt(group area)) * (draws[4i], draws[4i+1])
+ * (draws DEVICE binary64, 16-byte aligned), projected per CONSTRAINED member; a vertex in several
+ * groups moves with the displacement of the first of them in centre order (the paper does not say;
+ * this is a reading). Validity, change of f, decision, outputs and the update of xy are those of
+ * anneal_joint; CCSP_MOVE_BAD when a centre is out of range or ORIGINAL. Synchronises `stream`
+ * three times; allocates its group scratch for the call (as anneal_group) and keeps anneal_joint's
+ * workspace; overwrites the mesh's scratch.
+ */
+int anneal_joint_groups(MovableMesh *mesh, double *xy, const ObjectiveParams *params,
+                        double temperature, double lambda, const int32_t *centres, int64_t n,
+                        const double *draws, double u, double *delta_out, int32_t *status_out,
+                        void *stream);
+
+/*
  * anneal_moves: one Metropolis step (Sec. 3.1) for each of k single-vertex moves (Sec. 3.2.2), for
  * moves that do not interact (the vertices of one class of mesh_classes; for other sets, every
  * move is still evaluated against the positions before the call). Move i displaces vertex vid[i]

@@ -436,6 +436,21 @@ class MovableMesh:
         return B.anneal_joint(self.handle, self._xy(xy), params, float(temperature), float(lam),
                               vid.data_ptr(), k, xi.data_ptr(), float(u), _stream(stream))
 
+    def joint_groups(self, xy, params, temperature, lam, centres, draws, u, stream=None):
+        """One Metropolis step for the group moves of the centres (caller ids, int32 CUDA tensor)
+        made together (see ``anneal_joint_groups``): draws (n,4) float64 CUDA (xi.x, xi.y, r,
+        unused), u a float in [0, 1). xy is updated in place when the move is accepted. Returns
+        (delta, status) as Python numbers. Synchronous."""
+        import torch
+        n = centres.shape[0]
+        if (not centres.is_cuda or centres.dtype != torch.int32 or not centres.is_contiguous()
+                or tuple(draws.shape) != (n, 4) or draws.dtype != torch.float64
+                or not draws.is_contiguous() or not draws.is_cuda):
+            raise ValueError("centres int32 (n,), draws float64 (n,4): contiguous CUDA tensors")
+        return B.anneal_joint_groups(self.handle, self._xy(xy), params, float(temperature),
+                                     float(lam), centres.data_ptr(), n, draws.data_ptr(),
+                                     float(u), _stream(stream))
+
     def sweep(self, xy, params, temperature, disp, u, stream=None):
         """One Metropolis step for every movable vertex, class by class (see ``anneal_sweep``):
         disp (M,2) and u (M,) float64 CUDA tensors in the order of ``classes()``. xy is updated in

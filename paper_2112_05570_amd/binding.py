@@ -50,7 +50,7 @@ EXPORTS = ("load_triangulation", "trace_rays", "trace_rays_tuned", "trace_batch"
            "tune_cache_set", "tune_cache_get", "server_create", "server_submit", "server_poll",
            "server_stats", "server_destroy", "locate_points", "trace_bounces", "mesh_load",
            "mesh_info", "objective_eval", "objective_delta", "mesh_free", "mesh_classes",
-           "anneal_moves", "anneal_joint", "anneal_sweep", "anneal_propose", "anneal_schedule",
+           "anneal_moves", "anneal_joint", "anneal_joint_groups", "anneal_sweep", "anneal_propose", "anneal_schedule",
            "flip_anneal", "mesh_contract", "anneal_group",
            "trace_rays_static", "mesh_subdivide",
            "load_tetmesh", "free_tetmesh", "tetmesh_info", "trace_rays3d",
@@ -179,6 +179,9 @@ _lib.anneal_moves.restype = _I
 _lib.anneal_joint.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double,
                               ctypes.c_double, _P, _I64, _P, ctypes.c_double, _P, _P, _P]
 _lib.anneal_joint.restype = _I
+_lib.anneal_joint_groups.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double,
+                                     ctypes.c_double, _P, _I64, _P, ctypes.c_double, _P, _P, _P]
+_lib.anneal_joint_groups.restype = _I
 _lib.anneal_sweep.argtypes = [_P, _P, ctypes.POINTER(ObjectiveParams), ctypes.c_double, _P, _P, _P,
                               _P, _P]
 _lib.anneal_sweep.restype = _I
@@ -388,6 +391,18 @@ def anneal_joint(mesh: int, xy: int, params: ObjectiveParams, temperature: float
     status = ctypes.c_int32()
     _check(_lib.anneal_joint(_P(mesh), _P(xy), ctypes.byref(params), temperature, lam, _P(vid), k,
                              _P(xi), u, ctypes.byref(delta), ctypes.byref(status), _P(stream)))
+    return delta.value, status.value
+
+
+def anneal_joint_groups(mesh: int, xy: int, params: ObjectiveParams, temperature: float,
+                        lam: float, centres: int, n: int, draws: int, u: float,
+                        stream: int = 0) -> tuple:
+    """Returns (delta, status) of the joint group move (host values)."""
+    delta = ctypes.c_double()
+    status = ctypes.c_int32()
+    _check(_lib.anneal_joint_groups(_P(mesh), _P(xy), ctypes.byref(params), temperature, lam,
+                                    _P(centres), n, _P(draws), u, ctypes.byref(delta),
+                                    ctypes.byref(status), _P(stream)))
     return delta.value, status.value
 
 

@@ -32,6 +32,7 @@
 
 #include "ccsp_objective.h"
 #include "exact.hpp"
+#include "scan.hpp"
 #include "walk.hpp"
 
 struct MovableMesh;
@@ -1217,7 +1218,7 @@ group_claim(MeshDev m, VGrid g, VGrid gc, Par p, double lambda,
     disp[i] = make_double2(k * xi.x, k * xi.y);
   }
   __syncthreads();
-  if (!active) return;
+  if (!active || own_v == nullptr) return;  // no claims: the joint group moves
   const double2 D = disp[i];
   const uint32_t pri = group_priority(i);
   auto claim_c = [&](int cell) { atomicMin(&own_c[cell], pri); };
@@ -1707,6 +1708,73 @@ joint_commit(const int32_t* __restrict__ vid, const double2* __restrict__ qnew, 
              double2* __restrict__ xy_out) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i < k) xy_out[vid[i]] = qnew[i];
+}
+
+// ---- the joint move of several groups (the second variant of Sec. 3.2.3): every member moves
+// with the displacement of the first group, in centre order, that holds it; one decision.
+
+// owner[v] = the lowest index of the groups holding v (one wave per group).
+__global__ void __launch_bounds__(kThreads)
+jgroup_owner(const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
+             const int32_t* __restrict__ mem, int n, int32_t* __restrict__ owner) {
+  const int i = (int)((blockIdx.x * (unsigned)kThreads + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int* M = mem + off[i];
+  for (int j = lane; j < cnt[i]; j += 64) atomicMin(&owner[M[j]], i);
+}
+
+// Member slot off[i] + j of group i: its vertex (internal id) and new position when the group owns
+// it, else -1 (one wave per group).
+__global__ void __launch_bounds__(kThreads)
+jgroup_prepare(MeshDev m, const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
+               const int32_t* __restrict__ mem, const double2* __restrict__ disp,
+               const int32_t* __restrict__ owner, int n, int32_t* __restrict__ vint,
+               double2* __restrict__ qlist) {
+  const int i = (int)((blockIdx.x * (unsigned)kThreads + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int* M = mem + off[i];
+  const double2 D = disp[i];
+  for (int j = lane; j < cnt[i]; j += 64) {
+    const int v = M[j];
+    const int slot = off[i] + j;
+    if (owner[v] == i) {
+      const double2 o = m.xyi[v], dv = member_disp(m, v, D);
+      vint[slot] = v;
+      qlist[slot] = make_double2(o.x + dv.x, o.y + dv.y);
+    } else {
+      vint[slot] = -1;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+jgroup_apply(MeshDev m, const int32_t* __restrict__ vint, const double2* __restrict__ qlist,
+             int64_t k) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < k && vint[i] >= 0) m.xyi[vint[i]] = qlist[i];
+}
+
+__global__ void __launch_bounds__(kThreads)
+jgroup_check(MeshDev m, const int32_t* __restrict__ vint, int64_t k, int* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= k || vint[i] < 0) return;
+  const int v = vint[i];
+  for (int j = m.vtri_off[v], end = m.vtri_off[v + 1]; j < end; ++j) {
+    const int4 t = m.tri[m.vtri[j]];
+    if (orient_sign(m.xyi[t.x], m.xyi[t.y], m.xyi[t.z]) <= 0) {
+      atomicOr(flags, kJointFolds);
+      return;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+jgroup_commit(MeshDev m, const int32_t* __restrict__ vint, const double2* __restrict__ qlist,
+              int64_t k, double2* __restrict__ xy_out) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < k && vint[i] >= 0) xy_out[m.vold[vint[i]]] = qlist[i];
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -2242,6 +2310,60 @@ int objective_eval(MovableMesh* mesh, const double* xy, const ObjectiveParams* p
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_eval: launch");
 }
 
+}  // extern "C"
+
+namespace {
+
+// The joint moves' device workspace, kept by the mesh: the terms before the move (te, ts per
+// edge, ta per triangle), the vertex marks, the partial sums, the result and the flags, then k
+// new positions. Grown (after synchronising s) when k exceeds every earlier call's.
+struct JointBuf {
+  double *te, *ts, *ta, *part, *out;
+  uint32_t* mark;
+  int* flags;
+  double2* q;
+};
+
+int joint_buffers(MovableMesh* mesh, int64_t k, hipStream_t s, JointBuf* jb) {
+  const ccsp::MeshDev& d = mesh->d;
+  const int T = ccsp::kThreads;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t o_ts = al(8 * (size_t)d.ne), o_ta = o_ts + al(8 * (size_t)d.ne);
+  const size_t o_mark = o_ta + al(8 * (size_t)d.nt), o_part = o_mark + al(4 * (size_t)d.nv);
+  const size_t o_out = o_part + al(8 * 3 * (size_t)ccsp::kMaxBlocks), o_flags = o_out + 256;
+  const size_t o_q = o_flags + 256, need = o_q + al(16 * (size_t)k);
+  if (need > mesh->joint_bytes) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "joint moves: synchronise");
+    if (mesh->joint_ws) (void)hipFree(mesh->joint_ws);
+    mesh->joint_ws = nullptr;
+    mesh->joint_bytes = 0;
+    if (hipMalloc(&mesh->joint_ws, need) != hipSuccess) {
+      (void)hipGetLastError();
+      mesh->joint_ws = nullptr;
+      return fail(CCSP_E_OOM, "joint moves: device allocation failed");
+    }
+    mesh->joint_bytes = need;
+    mesh->joint_epoch = 0;
+    hipLaunchKernelGGL(ccsp::fill_i32, dim3((unsigned)((d.nv + T - 1) / T)), dim3(T), 0, s,
+                       (int32_t*)((char*)mesh->joint_ws + o_mark), (int64_t)d.nv, 0);
+  }
+  char* w = (char*)mesh->joint_ws;
+  jb->te = (double*)w;
+  jb->ts = (double*)(w + o_ts);
+  jb->ta = (double*)(w + o_ta);
+  jb->mark = (uint32_t*)(w + o_mark);
+  jb->part = (double*)(w + o_part);
+  jb->out = (double*)(w + o_out);
+  jb->flags = (int*)(w + o_flags);
+  jb->q = (double2*)(w + o_q);
+  return CCSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int anneal_joint(MovableMesh* mesh, double* xy, const ObjectiveParams* params,
                  double temperature, double lambda, const int32_t* vid, int64_t k,
                  const double* xi, double u, double* delta_out, int32_t* status_out,
@@ -2262,41 +2384,18 @@ int anneal_joint(MovableMesh* mesh, double* xy, const ObjectiveParams* params,
   hipStream_t s = (hipStream_t)stream;
   const int T = ccsp::kThreads;
   const int nb = grid_for(std::max(d.ne, d.nt));
-  // workspace: te, ts (E doubles), ta (T doubles), marks (V), sums, out, flags, then new positions
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t o_ts = al(8 * (size_t)d.ne), o_ta = o_ts + al(8 * (size_t)d.ne);
-  const size_t o_mark = o_ta + al(8 * (size_t)d.nt), o_part = o_mark + al(4 * (size_t)d.nv);
-  const size_t o_out = o_part + al(8 * 3 * (size_t)ccsp::kMaxBlocks), o_flags = o_out + 256;
-  const size_t o_q = o_flags + 256, need = o_q + al(16 * (size_t)k);
-  hipError_t e;
-  if (need > mesh->joint_bytes) {
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "anneal_joint: synchronise");
-    if (mesh->joint_ws) (void)hipFree(mesh->joint_ws);
-    mesh->joint_ws = nullptr;
-    mesh->joint_bytes = 0;
-    if (hipMalloc(&mesh->joint_ws, need) != hipSuccess) {
-      (void)hipGetLastError();
-      mesh->joint_ws = nullptr;
-      return fail(CCSP_E_OOM, "anneal_joint: device allocation failed");
-    }
-    mesh->joint_bytes = need;
-    mesh->joint_epoch = 0;
-    hipLaunchKernelGGL(ccsp::fill_i32, dim3((unsigned)((d.nv + T - 1) / T)), dim3(T), 0, s,
-                       (int32_t*)((char*)mesh->joint_ws + o_mark), (int64_t)d.nv, 0);
-  }
-  char* w = (char*)mesh->joint_ws;
-  double *te = (double*)w, *ts = (double*)(w + o_ts), *ta = (double*)(w + o_ta);
-  auto* mark = (uint32_t*)(w + o_mark);
-  auto* part = (double*)(w + o_part);
-  auto* out = (double*)(w + o_out);
-  auto* flags = (int*)(w + o_flags);
-  auto* qnew = (double2*)(w + o_q);
+  JointBuf jb;
+  if (int r = joint_buffers(mesh, k, s, &jb)) return r;
+  double *te = jb.te, *ts = jb.ts, *ta = jb.ta, *part = jb.part, *out = jb.out;
+  uint32_t* mark = jb.mark;
+  int* flags = jb.flags;
+  auto* qnew = jb.q;
   if (++mesh->joint_epoch == 0) {  // marks hold epochs: after a wrap, clear them
     hipLaunchKernelGGL(ccsp::fill_i32, dim3((unsigned)((d.nv + T - 1) / T)), dim3(T), 0, s,
                        (int32_t*)mark, (int64_t)d.nv, 0);
     mesh->joint_epoch = 1;
   }
+  hipError_t e;
   const unsigned kb = (unsigned)((k + T - 1) / T);
   stage_edges(d, p, xy, s);
   hipLaunchKernelGGL(ccsp::fill_i32, dim3(1), dim3(T), 0, s, (int32_t*)flags, (int64_t)1, 0);
@@ -2332,6 +2431,173 @@ int anneal_joint(MovableMesh* mesh, double* xy, const ObjectiveParams* params,
   }
   e = hipGetLastError();
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_joint: launch");
+}
+
+int anneal_joint_groups(MovableMesh* mesh, double* xy, const ObjectiveParams* params,
+                        double temperature, double lambda, const int32_t* centres, int64_t n,
+                        const double* draws, double u, double* delta_out, int32_t* status_out,
+                        void* stream) {
+  if (!mesh || !xy || !delta_out || !status_out || (n > 0 && (!centres || !draws)))
+    return fail(CCSP_E_ARG, "anneal_joint_groups: null argument");
+  if (n < 1 || n >= (int64_t(1) << 26))
+    return fail(CCSP_E_ARG, "anneal_joint_groups: bad centre count");
+  if (((uintptr_t)xy & 15) != 0 || ((uintptr_t)draws & 15) != 0 || ((uintptr_t)centres & 3) != 0)
+    return fail(CCSP_E_ARG, "anneal_joint_groups: misaligned buffer");
+  if (!check_params(params)) return fail(CCSP_E_ARG, "anneal_joint_groups: invalid parameters");
+  if (!(temperature >= 0) || !std::isfinite(temperature))
+    return fail(CCSP_E_ARG, "anneal_joint_groups: temperature must be finite and >= 0");
+  if (!(lambda >= 0) || !std::isfinite(lambda))
+    return fail(CCSP_E_ARG, "anneal_joint_groups: lambda must be finite and >= 0");
+  if (int r = check_device(mesh)) return r;
+  const ccsp::MeshDev& d = mesh->d;
+  const ccsp::Par p = to_par(params);
+  hipStream_t s = (hipStream_t)stream;
+  const int T = ccsp::kThreads;
+  const int N = (int)n;
+  const int nb = grid_for(std::max(d.ne, d.nt));
+  JointBuf jb;
+  if (int r = joint_buffers(mesh, 1, s, &jb)) return r;
+  stage_edges(d, p, xy, s);
+  hipLaunchKernelGGL(ccsp::joint_terms, dim3(nb), dim3(T), 0, s, d, p, jb.te, jb.ts, jb.ta);
+  // the query grid of the positions (as for anneal_group)
+  GroupScratch gs;
+  const int nbox = grid_for(d.nv);
+  double* box = nullptr;
+  hipError_t e = gs.get(&box, 4 * (size_t)nbox + 4);
+  if (e != hipSuccess) return fail(CCSP_E_OOM, "anneal_joint_groups: scratch allocation failed");
+  hipLaunchKernelGGL(ccsp::bbox_kernel, dim3(nbox), dim3(T), 0, s, d, nullptr, 0, box + 4);
+  hipLaunchKernelGGL(ccsp::bbox_kernel, dim3(1), dim3(T), 0, s, d, box + 4, nbox, box);
+  double hb[4];
+  e = hipMemcpyAsync(hb, box, sizeof hb, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "anneal_joint_groups: bounding box");
+  const double ext = std::max(hb[2] - hb[0], hb[3] - hb[1]);
+  double h = std::max(5.0 * p.eps, ext / 1024.0);
+  if (!(h > 0) || !std::isfinite(h)) h = 1.0;
+  ccsp::VGrid g{};
+  g.x0 = std::isfinite(hb[0]) ? hb[0] : 0.0;
+  g.y0 = std::isfinite(hb[1]) ? hb[1] : 0.0;
+  g.inv = 1.0 / h;
+  g.gx = (int)std::min(1024.0, std::max(1.0, std::floor((hb[2] - g.x0) * g.inv) + 1.0));
+  g.gy = (int)std::min(1024.0, std::max(1.0, std::floor((hb[3] - g.y0) * g.inv) + 1.0));
+  if (!(g.gx >= 1)) g.gx = 1;
+  if (!(g.gy >= 1)) g.gy = 1;
+  const int ncells = g.gx * g.gy;
+  int32_t *gcen = nullptr, *cnt = nullptr, *off = nullptr, *start = nullptr, *cursor = nullptr;
+  int32_t *vert = nullptr, *rnd = nullptr, *st = nullptr, *mem_n = nullptr;
+  uint32_t* sums = nullptr;
+  uint8_t* done = nullptr;
+  double* dl = nullptr;
+  double2* disp = nullptr;
+  e = gs.get(&gcen, N);
+  if (e == hipSuccess) e = gs.get(&cnt, (size_t)N + 1);
+  if (e == hipSuccess) e = gs.get(&off, (size_t)N + 1);
+  if (e == hipSuccess) e = gs.get(&start, (size_t)ncells + 1);
+  if (e == hipSuccess) e = gs.get(&cursor, (size_t)ncells + 1);
+  if (e == hipSuccess) e = gs.get(&vert, d.nv);
+  if (e == hipSuccess) e = gs.get(&done, N);
+  if (e == hipSuccess) e = gs.get(&disp, N);
+  if (e == hipSuccess) e = gs.get(&rnd, N);
+  if (e == hipSuccess) e = gs.get(&st, N);
+  if (e == hipSuccess) e = gs.get(&mem_n, N);
+  if (e == hipSuccess) e = gs.get(&dl, N);
+  if (e == hipSuccess)
+    e = gs.get(&sums, ccsp::exclusive_scan_bytes(std::max<int64_t>(N, ncells) + 1) / 4);
+  if (e != hipSuccess) return fail(CCSP_E_OOM, "anneal_joint_groups: scratch allocation failed");
+  g.start = start;
+  g.vert = vert;
+  hipLaunchKernelGGL(ccsp::fill_i32, dim3((ncells + T) / T), dim3(T), 0, s, cursor,
+                     (int64_t)ncells + 1, 0);
+  hipLaunchKernelGGL(ccsp::vgrid_count, dim3((d.nv + T - 1) / T), dim3(T), 0, s, d, g, cursor);
+  e = ccsp::launch_exclusive_scan((const uint32_t*)cursor, (uint32_t*)start, ncells + 1, sums, s);
+  if (e != hipSuccess) return hip_fail(e, "anneal_joint_groups: grid scan");
+  hipLaunchKernelGGL(ccsp::fill_i32, dim3((ncells + T) / T), dim3(T), 0, s, cursor,
+                     (int64_t)ncells + 1, 0);
+  hipLaunchKernelGGL(ccsp::vgrid_fill, dim3((d.nv + T - 1) / T), dim3(T), 0, s, d, g, cursor,
+                     vert);
+  // centres; a centre that is not a movable vertex makes the whole move BAD
+  const unsigned gb = (unsigned)((N + T - 1) / T);
+  hipLaunchKernelGGL(ccsp::group_setup, dim3(gb), dim3(T), 0, s, d, centres, N, gcen, done, dl,
+                     st, mem_n, rnd);
+  std::vector<uint8_t> hd(N);
+  e = hipMemcpyAsync(hd.data(), done, N, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "anneal_joint_groups: setup");
+  *delta_out = __builtin_huge_val();
+  for (uint8_t x : hd)
+    if (x) {
+      *status_out = CCSP_MOVE_BAD;
+      return CCSP_OK;
+    }
+  // the groups, their members, areas and displacements at the positions before the move
+  hipLaunchKernelGGL(ccsp::fill_i32, dim3((N + T) / T), dim3(T), 0, s, cnt, (int64_t)N + 1, 0);
+  hipLaunchKernelGGL(ccsp::group_count, dim3(gb), dim3(T), 0, s, d, g, p, gcen,
+                     (const double2*)draws, done, N, cnt);
+  e = ccsp::launch_exclusive_scan((const uint32_t*)cnt, (uint32_t*)off, N + 1, sums, s);
+  if (e != hipSuccess) return hip_fail(e, "anneal_joint_groups: member scan");
+  int32_t total = 0;
+  e = hipMemcpyAsync(&total, off + N, sizeof total, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "anneal_joint_groups: member count");
+  int32_t *mem = nullptr, *key = nullptr, *tmpm = nullptr, *tmpk = nullptr, *owner = nullptr;
+  int32_t* vint = nullptr;
+  uint64_t* first = nullptr;
+  double2* qlist = nullptr;
+  e = gs.get(&mem, (size_t)total);
+  if (e == hipSuccess) e = gs.get(&key, (size_t)total);
+  if (e == hipSuccess) e = gs.get(&tmpm, (size_t)total);
+  if (e == hipSuccess) e = gs.get(&tmpk, (size_t)total);
+  if (e == hipSuccess) e = gs.get(&first, (size_t)total);
+  if (e == hipSuccess) e = gs.get(&vint, (size_t)total);
+  if (e == hipSuccess) e = gs.get(&qlist, (size_t)total);
+  if (e == hipSuccess) e = gs.get(&owner, d.nv);
+  if (e != hipSuccess) return fail(CCSP_E_OOM, "anneal_joint_groups: member buffer allocation failed");
+  const unsigned wb = (unsigned)((N + T / 64 - 1) / (T / 64));  // one wave per group
+  hipLaunchKernelGGL(ccsp::group_claim, dim3(wb), dim3(T), 0, s, d, g, g, p, lambda, gcen,
+                     (const double2*)draws, done, N, off, cnt, mem, key, tmpm, tmpk, first, disp,
+                     (uint32_t*)nullptr, (uint32_t*)nullptr);
+  hipLaunchKernelGGL(ccsp::fill_i32, dim3((d.nv + T - 1) / T), dim3(T), 0, s, owner,
+                     (int64_t)d.nv, INT32_MAX);
+  hipLaunchKernelGGL(ccsp::jgroup_owner, dim3(wb), dim3(T), 0, s, off, cnt, mem, N, owner);
+  hipLaunchKernelGGL(ccsp::jgroup_prepare, dim3(wb), dim3(T), 0, s, d, off, cnt, mem, disp,
+                     owner, N, vint, qlist);
+  // the move, its validity and its change of f
+  const unsigned kb = (unsigned)((total + T - 1) / T);
+  hipLaunchKernelGGL(ccsp::fill_i32, dim3(1), dim3(T), 0, s, (int32_t*)jb.flags, (int64_t)1, 0);
+  if (total > 0) {
+    hipLaunchKernelGGL(ccsp::jgroup_apply, dim3(kb), dim3(T), 0, s, d, vint, qlist,
+                       (int64_t)total);
+    hipLaunchKernelGGL(ccsp::jgroup_check, dim3(kb), dim3(T), 0, s, d, vint, (int64_t)total,
+                       jb.flags);
+  }
+  hipLaunchKernelGGL(ccsp::edge_state, dim3(grid_for(d.ne)), dim3(T), 0, s, d, p, d.partial);
+  hipLaunchKernelGGL(ccsp::joint_diff, dim3(nb), dim3(T), 0, s, d, p, jb.te, jb.ts, jb.ta,
+                     jb.part);
+  hipLaunchKernelGGL(ccsp::joint_finish, dim3(1), dim3(T), 0, s, jb.part, nb, p, jb.out);
+  double hout[4];
+  int hflags = 0;
+  e = hipMemcpyAsync(hout, jb.out, sizeof hout, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflags, jb.flags, sizeof hflags, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "anneal_joint_groups");
+  if (hflags & ccsp::kJointFolds) {
+    *status_out = CCSP_MOVE_FOLDS;
+  } else {
+    const double df = hout[0];
+    *delta_out = df;
+    if (df <= 0.0 || u < std::exp(-df / temperature)) {
+      *status_out = CCSP_MOVE_OK;
+      if (total > 0)
+        hipLaunchKernelGGL(ccsp::jgroup_commit, dim3(kb), dim3(T), 0, s, d, vint, qlist,
+                           (int64_t)total, (double2*)xy);
+      e = hipStreamSynchronize(s);  // the group scratch is freed on return
+      if (e != hipSuccess) return hip_fail(e, "anneal_joint_groups: commit");
+    } else {
+      *status_out = CCSP_MOVE_REJECTED;
+    }
+  }
+  e = hipGetLastError();
+  return e == hipSuccess ? CCSP_OK : hip_fail(e, "anneal_joint_groups: launch");
 }
 
 int objective_delta(MovableMesh* mesh, const double* xy, const ObjectiveParams* params,

@@ -196,6 +196,52 @@ def test_joint_moves_equal_checker(ccsp, tiny, state):
         assert np.array_equal(X.cpu().numpy(), xy)
 
 
+@pytest.mark.parametrize("eps", [0.03, 0.08])
+def test_joint_group_moves_equal_checker(ccsp, tiny, eps):
+    """The second variant of Sec. 3.2.3 (anneal_joint_groups): a few random centres' groups moved
+    together, one decision, overlapping groups taking the first group's displacement. Status equal
+    to the checker's joint_groups, the change of f within the reordering bound, positions after
+    each step bit for bit, over a chain of steps; then a centre that is ORIGINAL (BAD, nothing
+    moves)."""
+    mesh, om = tiny
+    p = ob.Params(eps)
+    xy = mesh.xy.copy()
+    rng = np.random.default_rng(71)
+    movable = np.nonzero(mesh.kind != sg.ORIGINAL)[0]
+    seen = set()
+    with ccsp.MovableMesh(om.tri_v, om.kind, om.line, om.prim_v) as gm:
+        prm = _params(ccsp, p)
+        X = torch.from_numpy(xy.copy()).to(DEV)
+        for step in range(20):
+            lam, temp = ((0.005, 1e-3), (0.02, 1e-4), (0.002, 0.0), (0.005, 1e9))[step % 4]
+            n = int(rng.integers(1, 6))
+            cs = rng.choice(movable, n).astype(np.int32)  # repeats allowed
+            draws = np.zeros((n, 4))
+            draws[:, :2] = rng.standard_normal((n, 2))
+            draws[:, 2] = rng.random(n)
+            uu = float(rng.random()) if temp < 1e9 else 0.0
+            d, st = gm.joint_groups(X, prm, temp, lam, torch.from_numpy(cs).to(DEV),
+                                    torch.from_numpy(draws).to(DEV), uu)
+            rs, rd, bound, xy_new, margin = ob.joint_groups(om, xy, p, temp, lam, cs,
+                                                            draws[:, :2], draws[:, 2], uu)
+            assert margin > 1e-10, "a decision lies within rounding of its threshold"
+            assert st == rs, (step, st, rs)
+            if rs in (ob.ACCEPTED, ob.REJECTED):
+                assert abs(d - rd) <= bound, (step, d, rd, bound)
+            else:
+                assert d == math.inf
+            xy = xy_new
+            assert np.array_equal(X.cpu().numpy(), xy), step
+            seen.add(rs)
+        assert seen >= {ob.ACCEPTED, ob.REJECTED, ob.FOLDED}, seen
+        orig = int(np.nonzero(mesh.kind == sg.ORIGINAL)[0][0])
+        cs = torch.tensor([int(movable[0]), orig], dtype=torch.int32, device=DEV)
+        d, st = gm.joint_groups(X, prm, 1e-3, 0.05, cs,
+                                torch.full((2, 4), 0.1, dtype=torch.float64, device=DEV), 0.5)
+        assert st == -2 and d == math.inf
+        assert np.array_equal(X.cpu().numpy(), xy)
+
+
 def test_rules_follow_original_positions(ccsp, tiny):
     """The conditioning restriction reads ORIGINAL positions only, so the library keeps its result
     from call to call and recomputes it when an ORIGINAL position changes. One mesh evaluated at
