@@ -1777,6 +1777,38 @@ jgroup_commit(MeshDev m, const int32_t* __restrict__ vint, const double2* __rest
   if (i < k && vint[i] >= 0) xy_out[m.vold[vint[i]]] = qlist[i];
 }
 
+// objective_delta's moves with one wave (a 64-thread workgroup) per move: wave_change gives the
+// change of f bit for bit as move_change. order (NULL: the identity) lists the move each
+// workgroup evaluates.
+__global__ void __launch_bounds__(kWaveThreads)
+move_delta_wave(MeshDev m, Par p, const int32_t* __restrict__ vid, const double2* __restrict__ qv,
+                int64_t k, const uint32_t* __restrict__ order, double* __restrict__ delta,
+                int32_t* __restrict__ status) {
+  __shared__ WaveLds w;
+  const int64_t t = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (t >= k) return;
+  const int64_t i = order ? (int64_t)order[t] : t;
+  const int cv = vid[i];
+  const double2 q = qv[i];
+  int st;
+  double df = __builtin_huge_val();
+  if (cv < 0 || cv >= m.nv || !isfinite(q.x) || !isfinite(q.y)) {
+    st = CCSP_MOVE_BAD;
+  } else if (m.vk[m.vnew[cv]].x == CCSP_VERTEX_ORIGINAL) {
+    st = CCSP_MOVE_FIXED;
+  } else {
+    double dfl = 0.0;
+    bool wide = false;
+    st = wave_change<true>(m, p, m.vnew[cv], q, w, lane, &dfl, &wide);
+    if (st == CCSP_MOVE_OK) df = dfl;
+  }
+  if (lane == 0) {
+    status[i] = st;
+    delta[i] = df;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads)
 fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -2622,8 +2654,12 @@ int objective_delta(MovableMesh* mesh, const double* xy, const ObjectiveParams* 
   if (k >= kSortMoves && k < (int64_t(1) << 31)) {
     if (int r = sort_moves(mesh, vid, k, s, &order)) return r;
   }
-  hipLaunchKernelGGL(ccsp::move_delta, dim3((unsigned)blocks), dim3(ccsp::kThreads), 0, s, d, p,
-                     vid, (const double2*)q_xy, k, order, delta, status);
+  if (k < (int64_t(1) << 31))
+    hipLaunchKernelGGL(ccsp::move_delta_wave, dim3((unsigned)k), dim3(ccsp::kWaveThreads), 0, s,
+                       d, p, vid, (const double2*)q_xy, k, order, delta, status);
+  else
+    hipLaunchKernelGGL(ccsp::move_delta, dim3((unsigned)blocks), dim3(ccsp::kThreads), 0, s, d, p,
+                       vid, (const double2*)q_xy, k, order, delta, status);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CCSP_OK : hip_fail(e, "objective_delta: launch");
 }
